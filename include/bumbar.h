@@ -1,0 +1,228 @@
+/*
+ * bumbar.h -- C ABI of the MI355X (gfx950) BU-MBAR solver library (libbumbar.so).
+ *
+ * Problem (Muller, Alesiani, Christiansen, "BU-MBAR: a hybrid solution
+ * strategy for the MBAR equations", Section 2): K thermodynamic states, N
+ * samples pooled from all states, N_k of them drawn in state k (sum N_k = N),
+ * and the reduced energy u_kn of every sample n evaluated in every state k
+ * (the paper's beta_k E_n, generalised to any reduced energy). The solver
+ * returns the free energies f_k (gauge f_0 = 0) that solve the MBAR equations
+ *     f_i = -log sum_n exp(-u_in) / sum_k N_k exp(f_k - u_kn),
+ * the limit of infinitesimal bin width of the binned WHAM iteration, Eq. (1),
+ * and optionally the weights W_nk = exp(f_k - u_kn) / sum_j N_j exp(f_j - u_jn).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers on the context's device unless a
+ *    parameter says "host". The caller allocates and owns all of them; the
+ *    library never frees caller memory and never keeps a pointer past the
+ *    call.
+ *  - u_kn is K x N row-major (state-major: sample index n contiguous),
+ *    element type given by a BUMBAR_F64 / BUMBAR_F32 code. Rows may be
+ *    padded: ld >= N is the row stride in elements where a call takes one.
+ *  - N_k is int64 on the device; states with N_k = 0 are allowed (they are
+ *    excluded from the denominators and their f_k is filled from the
+ *    MBAR formula).
+ *  - u_kn = +inf is allowed (sample impossible in that state); NaN or -inf
+ *    make the call fail with BUMBAR_EINVAL.
+ *  - Work is issued on the context's HIP stream. Calls that return host
+ *    scalars or statistics synchronise that stream before returning; the
+ *    others return once their work is queued unless noted.
+ *  - No call throws; each returns a status code and stores a message
+ *    retrievable with bumbar_last_error().
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef BUMBAR_H
+#define BUMBAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define BUMBAR_OK 0
+#define BUMBAR_EINVAL (-1)   /* bad shape, dtype, sum N_k != N, non-finite input, tol <= 0 */
+#define BUMBAR_ENOMEM (-2)   /* workspace too small or host allocation failed             */
+#define BUMBAR_EDEVICE (-3)  /* a HIP runtime call failed                                 */
+#define BUMBAR_ENOTCONV (-4) /* iteration cap reached; the best f is still written        */
+#define BUMBAR_ETOOBIG (-5)  /* request larger than the server's memory budget            */
+#define BUMBAR_EBUSY (-6)    /* server has no free slot / ticket not finished              */
+
+/* ---- codes ------------------------------------------------------------ */
+#define BUMBAR_F64 0
+#define BUMBAR_F32 1
+
+#define BUMBAR_PREC_FP64 0  /* every sweep in FP64                                       */
+#define BUMBAR_PREC_MIXED 1 /* FP32 sweeps, FP64 accumulation/solve, FP64 refinement     */
+
+#define BUMBAR_FINISH_NEWTON 0
+#define BUMBAR_FINISH_SCI 1
+
+#define BUMBAR_MODEL_NONE 0     /* bin representative = mean of the bin's u_kn           */
+#define BUMBAR_MODEL_LINEAR 1   /* u_k(x) = c_k + sum_j a_kj x_j                         */
+#define BUMBAR_MODEL_HARMONIC 2 /* u_k(x) = c_k + sum_j kappa_kj / 2 (x_j - x0_kj)^2     */
+
+typedef struct bumbar_ctx bumbar_ctx;
+
+/* One phase-2 check of Algorithm 1 (Section 2). */
+typedef struct {
+  int64_t n;      /* nominal bin target n0 * inc^t before the decision   */
+  int64_t P;      /* nonempty bins at n                                  */
+  int64_t P_next; /* nonempty bins at n * inc                            */
+  double s_n;     /* relative step, Eq. (2), at n                        */
+  double s_next;  /* relative step, Eq. (2), at n * inc                  */
+  int refine;     /* 1 if n was multiplied by inc (Eq. (3) test)         */
+  int stop;       /* 1 if the binned stage ended after this check        */
+} bumbar_check;
+
+typedef struct {
+  double tol;          /* finisher stops when max_k |applied delta f_k| < tol (kT). Default 1e-10 */
+  int precision;       /* BUMBAR_PREC_*                                                  */
+  int binning;         /* 1: Algorithm 1 on the coordinates xi, then the finisher;
+                          0: plain unbinned SCI then the finisher                        */
+  int64_t n0;          /* initial nonempty-bin target (paper: 100)                       */
+  double eps;          /* phase-1 stop on the relative step, Eq. (2) (paper: 1e-3)        */
+  int64_t inc;         /* refinement factor (paper: 10)                                  */
+  int n_intermediate;  /* SCI steps between refinement checks (paper: 20)                */
+  int finisher;        /* BUMBAR_FINISH_NEWTON or BUMBAR_FINISH_SCI                       */
+  int64_t max_iter;    /* cap on SCI steps of all stages (default 1e6)                   */
+  int max_newton;      /* cap on finisher Newton steps (default 100)                     */
+  double sci_switch;   /* plain mode: unbinned SCI until max |delta f| < sci_switch      */
+  int replay_phase1;   /* schedule replay: phase-1 steps (used if replay_refine != NULL)  */
+  const int* replay_refine; /* host; schedule replay: refine flag of each phase-2 check  */
+  int n_replay;        /* number of entries in replay_refine                              */
+  int profile;         /* 1: time every unbinned sweep kernel with HIP events (stats)      */
+} bumbar_options;
+
+typedef struct {
+  int64_t phase1_iters;     /* binned SCI steps in phase 1                              */
+  int64_t phase2_iters;     /* binned SCI steps after phase 1 (incl. probes)            */
+  int64_t n_checks;         /* phase-2 checks performed                                 */
+  int64_t finisher_steps;   /* finisher steps (Newton or SCI)                           */
+  int64_t sci_fallbacks;    /* Newton steps replaced by an SCI step                      */
+  int64_t unbinned_sweeps;  /* full K x N sweeps                                        */
+  int64_t robust_sweeps;    /* sweeps redone on the two-pass underflow-safe path         */
+  int64_t hessians;         /* K x K Hessian contractions                               */
+  double final_step;        /* last applied max |delta f| (kT)                           */
+  double grad_norm;         /* Euclidean norm of the MBAR gradient at the result         */
+  double time_binning_ms;   /* histogram / width search                                 */
+  double time_binned_ms;    /* binned SCI stages                                        */
+  double time_final_ms;     /* unbinned finisher                                        */
+  double sweep_kernel_ms;   /* profile = 1: summed duration of the unbinned sweep kernels */
+  int64_t sweep_kernel_launches; /* profile = 1: number of timed sweep kernel launches   */
+  bumbar_check* checks;     /* host, caller-owned, may be NULL: schedule of phase 2     */
+  int checks_capacity;      /* entries available in checks                              */
+} bumbar_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+int bumbar_create(bumbar_ctx** out, int device, void* hip_stream);
+void bumbar_destroy(bumbar_ctx* ctx);
+/* Message of the last failed call on ctx (never NULL; "" if none). */
+const char* bumbar_last_error(const bumbar_ctx* ctx);
+/* Library version string. */
+const char* bumbar_version(void);
+
+/* Defaults: the paper's settings n0 = 100, eps = 1e-3, inc = 10,
+ * n_intermediate = 20 (Section 2, after Algorithm 1), tol = 1e-10,
+ * Newton finisher, FP64, binning off. */
+void bumbar_default_options(bumbar_options* opt);
+
+/* ---- workspace -------------------------------------------------------- */
+
+/* Bytes of device workspace bumbar_solve needs for a K x N problem with
+ * d-dimensional binning coordinates (d = 0 if no binning). */
+int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
+                           const bumbar_options* opt, size_t* bytes);
+
+/* ---- solve ------------------------------------------------------------ */
+
+/*
+ * Solve the MBAR equations.
+ *  u_kn     K x N (row stride N), dtype u_dtype. With precision MIXED, an
+ *           FP64 u_kn is packed to FP32 internally (in the workspace).
+ *  N_k      K int64.
+ *  xi       N x d float64 binning coordinates (row-major), d in {1, 2};
+ *           required when opt->binning = 1, else may be NULL.
+ *  model    BUMBAR_MODEL_*; coef is K x (1 + 2d) float64 (layout in the
+ *           model codes above), or NULL for BUMBAR_MODEL_NONE. With a model
+ *           the bin representative is the model at the bin centre; without,
+ *           the mean of u_kn over the bin's samples.
+ *  f_init   K float64 starting point, or NULL for f = 0 (Algorithm 1 starts
+ *           from 0; f_init is used only when binning = 0).
+ *  f_k      K float64 output (gauge f_0 = 0).
+ *  W_nk     N x K float64 output (sample-major) or NULL.
+ *  log_D_n  N float64 output, ln sum_k N_k exp(f_k - u_kn), or NULL.
+ *  stats    host, may be NULL.
+ * Synchronises the stream. Returns BUMBAR_ENOTCONV (with f_k written) if
+ * max_iter or max_newton is reached.
+ */
+int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                 const int64_t* N_k, const double* xi, int d, int model, const double* coef,
+                 const double* f_init, const bumbar_options* opt, void* workspace,
+                 size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
+                 bumbar_stats* stats);
+
+/* ---- single steps (the kernels of the solve, exposed for testing) ------ */
+
+/*
+ * One unbinned self-consistent iteration (Eq. (1) with one sample per bin):
+ *   ln D_n   = ln sum_{k: N_k>0} N_k exp(f_k - u_kn)
+ *   f_new_i  = -ln sum_n exp(-u_in - ln D_n),  then f_new -= f_new_0
+ *   S_i      = sum_n N_i exp(f_i - u_in - ln D_n) (= N_i sum_n W_ni)
+ * u_kn K x N with row stride ld >= N. f (K), outputs f_new (K), log_D_n (N,
+ * may be NULL), S (K, may be NULL). sweep_stats (host, may be NULL) receives
+ * {max_i |f_new_i - f_i|, relative step Eq. (2), sum_n ln D_n - sum_k N_k f_k,
+ * Euclidean norm of S - N over sampled states}. The workspace must hold
+ * bumbar_query_workspace(ctx, K, N, 0, NULL) bytes. Synchronises iff
+ * sweep_stats != NULL.
+ */
+int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
+                 const int64_t* N_k, const double* f, void* workspace, size_t ws_bytes,
+                 double* f_new, double* log_D_n, double* S, double* sweep_stats);
+
+/*
+ * Hessian of the MBAR objective F(f) = sum_n ln D_n - sum_k N_k f_k at f:
+ *   H_ij = delta_ij S_i - sum_n P_ni P_nj,  P_ni = N_i exp(f_i - u_in - ln D_n)
+ * (the W W^T contraction; zero rows/columns for N_k = 0). log_D_n must be
+ * ln D_n at f (e.g. from bumbar_sweep) and S the matching S. H is K x K
+ * float64 row-major. Uses FP64 MFMA.
+ */
+int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                   int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
+                   const double* S, void* workspace, size_t ws_bytes, double* H);
+
+/* W_nk = exp(f_k - u_kn - ln D_n), N x K float64 (sample-major). */
+int bumbar_weights(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
+                   const double* f, const double* log_D_n, double* W_nk);
+
+/*
+ * Binning for a target of n nonempty bins (Section 2, after Eq. (1)):
+ * quantise xi (N x d float64) per dimension onto 32-bit integers anchored at
+ * the minimum, find the width m (in quanta) by integer bisection for
+ * max{m : g(m) >= n}, and build the histogram over the nonempty bins in
+ * ascending cell order. Outputs (device, caller-sized for the worst case
+ * N): cells (uint64, P entries), H (int64 counts, P entries), sample_bin
+ * (int32, N entries, may be NULL); host outputs m_out, P_out. Synchronises.
+ */
+int bumbar_bin(bumbar_ctx* ctx, const double* xi, int64_t N, int d, int64_t n_target,
+               void* workspace, size_t ws_bytes, uint64_t* m_out, int64_t* P_out,
+               uint64_t* cells, int64_t* H, int32_t* sample_bin);
+
+/*
+ * Per-sample probabilities at a target state, Eqs. (5)-(6) (Section 3):
+ *   p_n = exp(-u_target_n - ln D_n) / sum_m exp(-u_target_m - ln D_m).
+ * u_target (N) and log_D_n (N) in, p (N) out. Synchronises.
+ */
+int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const double* log_D_n,
+                    void* workspace, size_t ws_bytes, double* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BUMBAR_H */

@@ -1,0 +1,299 @@
+"""MI355X (gfx950) BU-MBAR solver: Python binding of libbumbar.so.
+
+The binding only marshals arguments. PyTorch supplies device memory and the
+HIP stream: pass CUDA (HIP) tensors, results come back as tensors on the same
+device. Every step of the solve runs in the HIP kernels of libbumbar.
+
+    import torch, paper_2609_03541_amd as bm
+    f, info = bm.solve(u_kn, N_k, xi=xi, model=bm.MODEL_HARMONIC, coef=coef, binning=True)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _capi
+from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,  # noqa: F401
+                    FINISH_NEWTON, FINISH_SCI, MODEL_HARMONIC, MODEL_LINEAR, MODEL_NONE, OK,
+                    PREC_FP64, PREC_MIXED)
+
+__all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight",
+           "BumbarError", "default_options"]
+
+
+class BumbarError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bumbar error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device=None, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libbumbar needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = _capi.load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = st
+        h = C.c_void_p()
+        rc = self.lib.bumbar_create(C.byref(h), dev, C.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise BumbarError(rc, "bumbar_create failed")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bumbar_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self.lib.bumbar_last_error(self.h).decode()
+
+    def check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise BumbarError(rc, self.error())
+        return rc
+
+    def workspace(self, nbytes):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def query_workspace(self, K, N, d=0, opts=None):
+        nb = C.c_size_t()
+        o = C.byref(opts) if opts is not None else None
+        self.check(self.lib.bumbar_query_workspace(self.h, K, N, d, o, C.byref(nb)))
+        return nb.value
+
+
+_default_ctx = {}
+
+
+def context(device=None):
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream)
+    if key not in _default_ctx:
+        _default_ctx[key] = Context(dev)
+    return _default_ctx[key]
+
+
+def default_options(**kw):
+    o = _capi.Options()
+    _capi.load().bumbar_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _keep(ctx, *tensors):
+    """Hold the temporaries of an asynchronous call until the stream passes this point.
+
+    The library queues kernels and returns; a tensor created only to pass a
+    pointer must not go back to the caching allocator before those kernels
+    run. record_stream ties the block to the context's stream.
+    """
+    for t in tensors:
+        if t is not None:
+            t.record_stream(ctx.stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, device):
+    torch = _torch()
+    if t is None:
+        return None
+    if not torch.is_tensor(t):
+        t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+def _dtype_code(u):
+    torch = _torch()
+    if u.dtype == torch.float64:
+        return F64
+    if u.dtype == torch.float32:
+        return F32
+    raise TypeError("u_kn must be float64 or float32")
+
+
+def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None,
+          want_weights=False, want_logD=False, ctx=None, checks_capacity=256, **options):
+    """Solve the MBAR equations for u (K x N) and counts Nk (K).
+
+    ``binning`` defaults to True when coordinates ``xi`` (N x d) are given.
+    Keyword options are the fields of ``bumbar_options`` (tol, precision,
+    n0, eps, inc, n_intermediate, finisher, max_iter, max_newton, sci_switch).
+    ``replay=(phase1_steps, [refine flags])`` replays a phase-2 schedule.
+    Returns (f, info): f is a float64 tensor on the device; info holds the
+    statistics, the phase-2 schedule and optional W (N x K) and ln D (N).
+    """
+    torch = _torch()
+    ctx = ctx or context()
+    dev = torch.device(f"cuda:{ctx.device}")
+    if not (torch.is_tensor(u) and u.is_cuda):
+        u = torch.as_tensor(u)
+    u = u.to(dev).contiguous()
+    K, N = u.shape
+    Nk_t = _dev(Nk, torch.int64, dev)
+    d = 0
+    xi_t = None
+    if xi is not None:
+        xi_t = _dev(xi, torch.float64, dev)
+        if xi_t.dim() == 1:
+            xi_t = xi_t[:, None].contiguous()
+        d = xi_t.shape[1]
+    if binning is None:
+        binning = xi is not None
+    replay = options.pop("replay", None)
+    opts = default_options(binning=int(bool(binning)), **options)
+    keep = None
+    if replay is not None:
+        arr = (C.c_int * max(1, len(replay[1])))(*[int(x) for x in replay[1]])
+        keep = arr
+        opts.replay_phase1 = int(replay[0])
+        opts.replay_refine = C.cast(arr, C.POINTER(C.c_int))
+        opts.n_replay = len(replay[1])
+    coef_t = _dev(coef, torch.float64, dev) if coef is not None else None
+    f_init_t = _dev(f_init, torch.float64, dev) if f_init is not None else None
+    nbytes = ctx.query_workspace(K, N, d if binning else 0, opts)
+    ws = ctx.workspace(nbytes)
+    f = torch.empty(K, dtype=torch.float64, device=dev)
+    W = torch.empty((N, K), dtype=torch.float64, device=dev) if want_weights else None
+    lD = torch.empty(N, dtype=torch.float64, device=dev) if want_logD else None
+    st = _capi.Stats()
+    chk = (_capi.Check * max(1, checks_capacity))()
+    st.checks = C.cast(chk, C.POINTER(_capi.Check))
+    st.checks_capacity = checks_capacity
+    rc = ctx.lib.bumbar_solve(ctx.h, _ptr(u), _dtype_code(u), K, N, _ptr(Nk_t), _ptr(xi_t), d,
+                              int(model), _ptr(coef_t), _ptr(f_init_t), C.byref(opts),
+                              _ptr(ws), ws.numel(), _ptr(f), _ptr(W), _ptr(lD), C.byref(st))
+    del keep
+    _keep(ctx, Nk_t, xi_t, coef_t, f_init_t, u)
+    ctx.check(rc, allow=(ENOTCONV,))
+    info = {name: getattr(st, name) for name, _ in _capi.Stats._fields_
+            if name not in ("checks", "checks_capacity")}
+    info["status"] = rc
+    n = min(int(st.n_checks), checks_capacity)
+    info["checks"] = [dict(n=c.n, P=c.P, P_next=c.P_next, s_n=c.s_n, s_next=c.s_next,
+                           refine=c.refine, stop=c.stop) for c in chk[:n]]
+    if W is not None:
+        info["W"] = W
+    if lD is not None:
+        info["logD"] = lD
+    return f, info
+
+
+def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True):
+    """One unbinned SCI step (Eq. (1), one sample per bin). Returns f_new, ln D, S, stats."""
+    torch = _torch()
+    ctx = ctx or context()
+    dev = u.device
+    K, N = u.shape[0], u.shape[1]
+    ld = u.stride(0) if ld is None else ld
+    Nk_t = _dev(Nk, torch.int64, dev)
+    f_t = _dev(f, torch.float64, dev)
+    ws = ctx.workspace(ctx.query_workspace(K, N, 0))
+    f_new = torch.empty(K, dtype=torch.float64, device=dev)
+    lD = torch.empty(N, dtype=torch.float64, device=dev)
+    S = torch.empty(K, dtype=torch.float64, device=dev)
+    stats = (C.c_double * 4)() if with_stats else None
+    rc = ctx.lib.bumbar_sweep(ctx.h, _ptr(u), _dtype_code(u), K, N, ld, _ptr(Nk_t), _ptr(f_t),
+                              _ptr(ws), ws.numel(), _ptr(f_new), _ptr(lD), _ptr(S),
+                              C.cast(stats, C.POINTER(C.c_double)) if stats else None)
+    ctx.check(rc)
+    _keep(ctx, Nk_t, f_t)
+    st = None
+    if stats is not None:
+        st = dict(max_df=stats[0], rel_step=stats[1], objective=stats[2], grad_norm=stats[3])
+    return f_new, lD, S, st
+
+
+def hessian(u, Nk, f, logD, S, ctx=None):
+    """K x K Hessian of the MBAR objective at f (FP64 MFMA)."""
+    torch = _torch()
+    ctx = ctx or context()
+    dev = u.device
+    K, N = u.shape
+    ws = ctx.workspace(ctx.query_workspace(K, N, 0))
+    H = torch.empty((K, K), dtype=torch.float64, device=dev)
+    # keep every marshalled tensor alive until the queued kernels have run
+    Nk_t = _dev(Nk, torch.int64, dev)
+    f_t = _dev(f, torch.float64, dev)
+    rc = ctx.lib.bumbar_hessian(ctx.h, _ptr(u), _dtype_code(u), K, N, u.stride(0), _ptr(Nk_t),
+                                _ptr(f_t), _ptr(logD), _ptr(S), _ptr(ws), ws.numel(), _ptr(H))
+    ctx.check(rc)
+    _keep(ctx, Nk_t, f_t)
+    return H
+
+
+def weights(u, f, logD, ctx=None):
+    """W_nk = exp(f_k - u_kn - ln D_n), N x K."""
+    torch = _torch()
+    ctx = ctx or context()
+    K, N = u.shape
+    W = torch.empty((N, K), dtype=torch.float64, device=u.device)
+    f_t = _dev(f, torch.float64, u.device)
+    rc = ctx.lib.bumbar_weights(ctx.h, _ptr(u), _dtype_code(u), K, N, u.stride(0), _ptr(f_t),
+                                _ptr(logD), _ptr(W))
+    ctx.check(rc)
+    _keep(ctx, f_t)
+    return W
+
+
+def bin_coordinates(xi, n_target, ctx=None):
+    """Width search and histogram for a target of n nonempty bins.
+
+    Returns (m, cells (P, uint64 as int64 tensor), H (P), sample_bin (N)).
+    """
+    torch = _torch()
+    ctx = ctx or context()
+    dev = torch.device(f"cuda:{ctx.device}")
+    xi_t = _dev(xi, torch.float64, dev)
+    if xi_t.dim() == 1:
+        xi_t = xi_t[:, None].contiguous()
+    N, d = xi_t.shape
+    ws = ctx.workspace(ctx.query_workspace(1, N, d))
+    cells = torch.empty(N, dtype=torch.int64, device=dev)
+    H = torch.empty(N, dtype=torch.int64, device=dev)
+    sb = torch.empty(N, dtype=torch.int32, device=dev)
+    m = C.c_uint64()
+    P = C.c_int64()
+    rc = ctx.lib.bumbar_bin(ctx.h, _ptr(xi_t), N, d, int(n_target), _ptr(ws), ws.numel(),
+                            C.byref(m), C.byref(P), _ptr(cells), _ptr(H), _ptr(sb))
+    ctx.check(rc)
+    return m.value, cells[:P.value], H[:P.value], sb
+
+
+def reweight(u_target, logD, ctx=None):
+    """Per-sample probabilities at a target state (Eqs. (5)-(6))."""
+    torch = _torch()
+    ctx = ctx or context()
+    N = u_target.numel()
+    ws = ctx.workspace(8 * (2 * 1024 + 2))
+    p = torch.empty(N, dtype=torch.float64, device=u_target.device)
+    rc = ctx.lib.bumbar_reweight(ctx.h, _ptr(u_target), N, _ptr(logD), _ptr(ws), ws.numel(),
+                                 _ptr(p))
+    ctx.check(rc)
+    return p

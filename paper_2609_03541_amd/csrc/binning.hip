@@ -1,0 +1,407 @@
+// Binning on the GPU (Section 2, text after Eq. (1)): quantisation of the
+// sampled coordinates, the nonempty-bin count g(m) for a width of m quanta,
+// the histogram over the nonempty bins and the bin representatives.
+//
+// Everything after quantisation is integer arithmetic, so the bins, counts
+// and the width found by the bisection are bit-identical to any correct
+// implementation of the same definitions. g(m) is computed from sorted keys
+// (distinct values are the run starts of a sorted sequence): in 1-D the
+// quantised coordinates are sorted once, because q -> q / m is monotone, so
+// every probe is a single pass over N integers; in 2-D the row-major cell id
+// is not monotone in (q_y, q_x) for all m, so each probe sorts the cell ids
+// (radix sort restricted to the bits the ids can occupy). The histogram
+// takes the run starts and run lengths of the same sorted sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "bumbar_impl.h"
+#include "solver_internal.h"
+
+namespace bumbar {
+
+constexpr int kBT = 256;
+constexpr int kRedBlocks = 1024;
+
+// ---- min / max per dimension --------------------------------------------
+__global__ void __launch_bounds__(kBT)
+    minmax_partial_kernel(const double* __restrict__ xi, int64_t N, int d,
+                          double* __restrict__ part) {
+  __shared__ double smin[kBT], smax[kBT];
+  for (int j = 0; j < d; ++j) {
+    double a = INFINITY, b = -INFINITY;
+    for (int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * kBT) {
+      const double v = xi[n * d + j];
+      a = fmin(a, v);
+      b = fmax(b, v);
+      if (v != v) {
+        a = -INFINITY;  // poison: reported as non-finite
+        b = INFINITY;
+      }
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kBT / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      part[(blockIdx.x * 2 + 0) * 2 + j] = smin[0];
+      part[(blockIdx.x * 2 + 1) * 2 + j] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void minmax_final_kernel(int nparts, int d, const double* __restrict__ part,
+                                    double* __restrict__ mm) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int j = 0; j < d; ++j) {
+      double a = INFINITY, b = -INFINITY;
+      for (int p = 0; p < nparts; ++p) {
+        a = fmin(a, part[(p * 2 + 0) * 2 + j]);
+        b = fmax(b, part[(p * 2 + 1) * 2 + j]);
+      }
+      mm[2 * j] = a;
+      mm[2 * j + 1] = b;
+    }
+  }
+}
+
+hipError_t launch_minmax(hipStream_t s, const double* xi, int64_t N, int d, double* mm,
+                         int64_t* scratch) {
+  double* part = reinterpret_cast<double*>(scratch);
+  int nb = (int)std::min<int64_t>(kRedBlocks, (N + kBT - 1) / kBT);
+  hipLaunchKernelGGL(minmax_partial_kernel, dim3(nb), dim3(kBT), 0, s, xi, N, d, part);
+  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(64), 0, s, nb, d, part, mm);
+  return hipGetLastError();
+}
+
+// ---- quantisation ---------------------------------------------------------
+// lo = min, scale = (2^32 - 1) / (max - min) (0 if max = min),
+// q = min(floor((x - lo) * scale), 2^32 - 1); separate IEEE subtract and
+// multiply (no contraction is possible for (x - lo) * scale).
+__global__ void quantize_params_kernel(int d, const double* __restrict__ mm, double* lo,
+                                       double* scale, unsigned* bad) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    unsigned b = 0;
+    for (int j = 0; j < d; ++j) {
+      const double a = mm[2 * j], c = mm[2 * j + 1];
+      if (!(a > -INFINITY && c < INFINITY)) b = 1;
+      lo[j] = a;
+      scale[j] = (c > a) ? 4294967295.0 / (c - a) : 0.0;
+    }
+    *bad = b;
+  }
+}
+
+__global__ void __launch_bounds__(kBT)
+    quantize_kernel(const double* __restrict__ xi, int64_t N, int d,
+                    const double* __restrict__ lo, const double* __restrict__ scale,
+                    uint32_t* __restrict__ q) {
+  const int64_t e = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (e >= N * d) return;
+  const int j = (int)(e % d);
+  const double diff = __dsub_rn(xi[e], lo[j]);
+  double fl = floor(__dmul_rn(diff, scale[j]));
+  if (fl > 4294967295.0) fl = 4294967295.0;
+  if (!(fl >= 0.0)) fl = 0.0;
+  q[e] = (uint32_t)fl;
+}
+
+hipError_t launch_quantize(hipStream_t s, const double* xi, int64_t N, int d, const double* mm,
+                           double* lo, double* scale, uint32_t* q, unsigned* bad) {
+  hipLaunchKernelGGL(quantize_params_kernel, dim3(1), dim3(64), 0, s, d, mm, lo, scale, bad);
+  const int64_t tot = N * d;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)((tot + kBT - 1) / kBT)), dim3(kBT), 0, s, xi,
+                     N, d, lo, scale, q);
+  return hipGetLastError();
+}
+
+// ---- sorting ----------------------------------------------------------------
+__global__ void iota_kernel(uint32_t* p, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) p[i] = (uint32_t)i;
+}
+
+size_t sort_temp_bytes(int64_t N) {
+  size_t a = 0, b = 0;
+  (void)rocprim::radix_sort_pairs((void*)nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
+  (void)rocprim::radix_sort_pairs((void*)nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
+  size_t c = 0;
+  (void)rocprim::inclusive_scan((void*)nullptr, c, (const int32_t*)nullptr, (int32_t*)nullptr,
+                          (size_t)N, rocprim::plus<int32_t>());
+  return std::max(std::max(a, b), c) + 1024;
+}
+
+hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t* iota,
+                          uint32_t* q_sorted, uint32_t* perm, void* tmp, size_t tmp_bytes) {
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, iota,
+                     N);
+  size_t bytes = tmp_bytes;
+  return rocprim::radix_sort_pairs(tmp, bytes, q, q_sorted, (const uint32_t*)iota, perm, (size_t)N,
+                                   0, 32, s);
+}
+
+// ---- distinct counting -----------------------------------------------------
+// counts[1 + b] = number of run starts in block b's range; counts[0] = total.
+__global__ void __launch_bounds__(kBT)
+    count_runs_1d_kernel(const uint32_t* __restrict__ qs, int64_t N, uint64_t m,
+                         int64_t* __restrict__ counts) {
+  __shared__ int64_t sh[kBT];
+  int64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBT) {
+    const uint64_t a = (uint64_t)qs[i] / m;
+    c += (i == 0) ? 1 : (a != (uint64_t)qs[i - 1] / m);
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[1 + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kBT)
+    count_runs_keys_kernel(const uint64_t* __restrict__ ks, int64_t N,
+                           int64_t* __restrict__ counts) {
+  __shared__ int64_t sh[kBT];
+  int64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBT)
+    c += (i == 0) ? 1 : (ks[i] != ks[i - 1]);
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[1 + blockIdx.x] = sh[0];
+}
+
+__global__ void sum_counts_kernel(int nb, int64_t* counts) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t t = 0;
+    for (int b = 0; b < nb; ++b) t += counts[1 + b];
+    counts[0] = t;
+  }
+}
+
+static int red_blocks(int64_t N) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (N + kBT - 1) / kBT));
+}
+
+hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, uint64_t m,
+                           int64_t* counts) {
+  const int nb = red_blocks(N);
+  hipLaunchKernelGGL(count_runs_1d_kernel, dim3(nb), dim3(kBT), 0, s, q_sorted, N, m, counts);
+  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(64), 0, s, nb, counts);
+  return hipGetLastError();
+}
+
+// 2-D row-major cell id with the first coordinate fastest:
+//   c = q0 / m + (q1 / m) * (floor((2^32 - 1) / m) + 1)
+__device__ __forceinline__ uint64_t cell2(uint32_t q0, uint32_t q1, uint64_t m) {
+  const uint64_t stride = 4294967295ull / m + 1ull;
+  return (uint64_t)q0 / m + ((uint64_t)q1 / m) * stride;
+}
+
+__global__ void cells_kernel(const uint32_t* __restrict__ q, int64_t N, int d, uint64_t m,
+                             uint64_t* __restrict__ keys) {
+  const int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (n >= N) return;
+  keys[n] = (d == 1) ? (uint64_t)q[n] / m : cell2(q[2 * n], q[2 * n + 1], m);
+}
+
+static unsigned key_bits(int d, uint64_t m) {
+  // the largest possible cell id for this m, then its bit length
+  uint64_t maxc;
+  if (d == 1) {
+    maxc = 4294967295ull / m;
+  } else {
+    const uint64_t stride = 4294967295ull / m + 1ull;
+    maxc = (4294967295ull / m) + (4294967295ull / m) * stride;
+  }
+  unsigned b = 1;
+  while (b < 64 && (maxc >> b) != 0) ++b;
+  return b;
+}
+
+hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
+                           uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
+                           int64_t* counts) {
+  hipLaunchKernelGGL(cells_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q, N, 2,
+                     m, keys);
+  size_t bytes = tmp_bytes;
+  hipError_t e = rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, keys_sorted,
+                                          (size_t)N, 0, key_bits(2, m), s);
+  if (e != hipSuccess) return e;
+  const int nb = red_blocks(N);
+  hipLaunchKernelGGL(count_runs_keys_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, counts);
+  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(64), 0, s, nb, counts);
+  return hipGetLastError();
+}
+
+// ---- histogram ----------------------------------------------------------------
+__global__ void keys_from_sorted_1d_kernel(const uint32_t* __restrict__ qs, int64_t N, uint64_t m,
+                                           uint64_t* __restrict__ ks) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) ks[i] = (uint64_t)qs[i] / m;
+}
+
+__global__ void copy_u32_kernel(const uint32_t* __restrict__ a, int64_t N, uint32_t* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) b[i] = a[i];
+}
+
+__global__ void run_flags_kernel(const uint64_t* __restrict__ ks, int64_t N,
+                                 int32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) flags[i] = (i == 0) ? 1 : (ks[i] != ks[i - 1]);
+}
+
+// bin_of_pos holds the inclusive scan of the run flags on entry.
+__global__ void run_starts_kernel(const uint64_t* __restrict__ ks, int64_t N,
+                                  int32_t* __restrict__ bin_of_pos, int64_t* __restrict__ start,
+                                  uint64_t* __restrict__ cells, int64_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i >= N) return;
+  const int32_t b = bin_of_pos[i] - 1;
+  const bool first = (i == 0) || (ks[i] != ks[i - 1]);
+  if (first) {
+    start[b] = i;
+    cells[b] = ks[i];
+  }
+  if (i == N - 1) {
+    start[b + 1] = N;
+    counts[0] = (int64_t)b + 1;
+  }
+  bin_of_pos[i] = b;
+}
+
+hipError_t launch_histogram(hipStream_t s, const uint32_t* q, int64_t N, int d, uint64_t m,
+                            const uint32_t* q1_sorted, const uint32_t* perm1, uint32_t* iota,
+                            uint64_t* keys, uint64_t* keys_sorted, uint32_t* perm,
+                            int32_t* bin_of_pos, int64_t* start, uint64_t* cells, void* tmp,
+                            size_t tmp_bytes, int64_t* counts) {
+  const unsigned nb = (unsigned)((N + kBT - 1) / kBT);
+  hipError_t e;
+  if (d == 1) {
+    hipLaunchKernelGGL(keys_from_sorted_1d_kernel, dim3(nb), dim3(kBT), 0, s, q1_sorted, N, m,
+                       keys_sorted);
+    hipLaunchKernelGGL(copy_u32_kernel, dim3(nb), dim3(kBT), 0, s, perm1, N, perm);
+  } else {
+    hipLaunchKernelGGL(cells_kernel, dim3(nb), dim3(kBT), 0, s, q, N, 2, m, keys);
+    hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(kBT), 0, s, iota, N);
+    size_t bytes = tmp_bytes;
+    e = rocprim::radix_sort_pairs(tmp, bytes, (const uint64_t*)keys, keys_sorted,
+                                  (const uint32_t*)iota, perm, (size_t)N, 0, key_bits(2, m), s);
+    if (e != hipSuccess) return e;
+  }
+  // run flags -> inclusive scan -> bin index per sorted position
+  int32_t* flags = reinterpret_cast<int32_t*>(keys);  // keys no longer needed
+  hipLaunchKernelGGL(run_flags_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, flags);
+  size_t bytes = tmp_bytes;
+  e = rocprim::inclusive_scan(tmp, bytes, (const int32_t*)flags, bin_of_pos, (size_t)N,
+                              rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(run_starts_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, bin_of_pos,
+                     start, cells, counts);
+  return hipGetLastError();
+}
+
+// ---- representatives ------------------------------------------------------------
+// CENTRE (model): ubar_kp = u_k(centre of bin p), centre_j = lo_j + (c_j + 1/2) m / scale_j.
+// MEAN (no model): ubar_kp = mean of u_kn over the bin's samples (sorted order,
+// which is ascending sample index within a bin because the sort is stable).
+__global__ void __launch_bounds__(kBT)
+    represent_kernel(int K, int64_t N, int d, int model, const double* __restrict__ coef,
+                     const double* __restrict__ lo, const double* __restrict__ scale, uint64_t m,
+                     int64_t P, const uint64_t* __restrict__ cells,
+                     const int64_t* __restrict__ start, const uint32_t* __restrict__ perm,
+                     const double* __restrict__ u, double* __restrict__ ubar,
+                     double* __restrict__ h) {
+  const int64_t e = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (e >= (int64_t)K * P) return;
+  const int k = (int)(e / P);
+  const int64_t p = e % P;
+  const int64_t s0 = start[p], s1 = start[p + 1];
+  if (k == 0) h[p] = (double)(s1 - s0);
+  double v;
+  if (model == BUMBAR_MODEL_NONE) {
+    double acc = 0.0;
+    for (int64_t i = s0; i < s1; ++i) acc += u[(int64_t)k * N + perm[i]];
+    v = acc / (double)(s1 - s0);
+  } else {
+    double x[2];
+    uint64_t cc[2];
+    if (d == 1) {
+      cc[0] = cells[p];
+    } else {
+      const uint64_t stride = 4294967295ull / m + 1ull;
+      cc[0] = cells[p] % stride;
+      cc[1] = cells[p] / stride;
+    }
+    for (int j = 0; j < d; ++j)
+      x[j] = scale[j] > 0.0 ? lo[j] + ((double)cc[j] + 0.5) * (double)m / scale[j] : lo[j];
+    const double* ck = coef + (int64_t)k * (1 + 2 * d);
+    v = ck[0];
+    for (int j = 0; j < d; ++j) {
+      if (model == BUMBAR_MODEL_LINEAR) {
+        v += ck[1 + j] * x[j];
+      } else {
+        const double dx = x[j] - ck[2 + 2 * j];
+        v += 0.5 * ck[1 + 2 * j] * dx * dx;
+      }
+    }
+  }
+  ubar[(int64_t)k * P + p] = v;
+}
+
+hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, const double* coef,
+                            const double* lo, const double* scale, uint64_t m, int64_t P,
+                            const uint64_t* cells, const int64_t* start, const uint32_t* perm,
+                            const double* u, double* ubar, double* h) {
+  const int64_t tot = (int64_t)K * P;
+  hipLaunchKernelGGL(represent_kernel, dim3((unsigned)((tot + kBT - 1) / kBT)), dim3(kBT), 0, s, K,
+                     N, d, model, coef, lo, scale, m, P, cells, start, perm, u, ubar, h);
+  return hipGetLastError();
+}
+
+__global__ void sample_bin_kernel(int64_t N, const uint32_t* __restrict__ perm,
+                                  const int32_t* __restrict__ bin_of_pos,
+                                  int32_t* __restrict__ sample_bin) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) sample_bin[perm[i]] = bin_of_pos[i];
+}
+
+hipError_t launch_sample_bin(hipStream_t s, int64_t N, const uint32_t* perm,
+                             const int32_t* bin_of_pos, int32_t* sample_bin) {
+  hipLaunchKernelGGL(sample_bin_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, N,
+                     perm, bin_of_pos, sample_bin);
+  return hipGetLastError();
+}
+
+__global__ void counts_from_start_kernel(int64_t P, const int64_t* __restrict__ start,
+                                         int64_t* __restrict__ H) {
+  const int64_t p = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (p < P) H[p] = start[p + 1] - start[p];
+}
+
+hipError_t launch_counts_from_start(hipStream_t s, int64_t P, const int64_t* start, int64_t* H) {
+  hipLaunchKernelGGL(counts_from_start_kernel, dim3((unsigned)((P + kBT - 1) / kBT)), dim3(kBT), 0,
+                     s, P, start, H);
+  return hipGetLastError();
+}
+
+}  // namespace bumbar

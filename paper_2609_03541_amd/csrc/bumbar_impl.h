@@ -1,0 +1,124 @@
+// Internal declarations of libbumbar (not installed; the public ABI is include/bumbar.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "bumbar.h"
+
+namespace bumbar {
+
+// Scalars produced by the sweep finaliser (device memory, read back on demand).
+struct SweepScalars {
+  double max_df;    // max_k |f_new_k - f_k|
+  double rel_step;  // Eq. (2), gauge state excluded
+  double objective; // sum_n h_n ln D_n - sum_k N_k f_k
+  double grad_norm; // || S - N ||_2 over sampled states
+  double min_S;     // min over sampled states of S_k
+  unsigned flags;   // bit 0: column denominator underflow / non-finite;
+                    // bit 1: state sum underflow / non-finite (robust path needed)
+  unsigned pad;
+};
+
+enum : unsigned { FLAG_COL = 1u, FLAG_STATE = 2u, FLAG_NAN = 4u };
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, which is how bumbar_query_workspace sizes the same sequence.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  bool overflow = false;
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = count * sizeof(T);
+    size_t start = (off + 255) & ~size_t(255);
+    off = start + bytes;
+    if (base == nullptr) return nullptr;
+    if (off > cap) {
+      overflow = true;
+      return nullptr;
+    }
+    return reinterpret_cast<T*>(base + start);
+  }
+};
+
+// ---- sweep kernels (sweep.hip) ------------------------------------------
+
+// Per-problem constants staged on the device for the sweeps.
+struct SweepConsts {
+  const double* cst;  // K: ln N'_k + f_k (N'_k = N_k if N_k > 0 else 1)
+  const double* gk;   // K: 1 if N_k > 0 else 0
+};
+
+int sweep_max_grid(int num_cus);                // upper bound for workspace sizing
+int robust_chunks(int64_t N);                   // column chunks of the robust pass
+
+// Fast single-pass sweep. Writes per-block partial state sums (grid x K),
+// per-block objective partials and flags. h (per-column multiplicity) may be
+// null; logD may be null. Returns 0 or a hipError_t value.
+// The grid (persistent, occupancy-sized) is returned in *grid_out.
+hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                             const double* cst, const double* gk, const double* h, double* logD,
+                             double* part, double* part_obj, unsigned* part_flags, int num_cus,
+                             int* grid_out);
+bool sweep_fast_supported(int K);
+
+// Robust two-pass sweep: exact column max, then per-state online log-sum-exp.
+hipError_t launch_sweep_robust(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                               const double* cst, const double* gk, const double* h,
+                               double* logD, double* partM, double* partS, double* part_obj,
+                               unsigned* part_flags, int chunks);
+
+// Finaliser. mode 0: partials are S' sums (fast path); mode 1: (M, S) pairs.
+hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, const double* part,
+                                 const double* partS, const double* part_obj,
+                                 const unsigned* part_flags, const double* f, const double* lnNp,
+                                 const int64_t* Nk, double* f_new, double* lnS, double* S_out,
+                                 SweepScalars* out);
+
+// cst_k = ln N'_k + f_k, gk, lnNp from N_k and f.
+hipError_t launch_prepare_consts(hipStream_t s, int K, const int64_t* Nk, const double* f,
+                                 double* cst, double* gk, double* lnNp);
+
+// Small vector kernels.
+hipError_t launch_axpy_to(hipStream_t s, int K, const double* f, double alpha, const double* d,
+                          double* out);  // out = f + alpha d
+hipError_t launch_fill_unsampled_gauge(hipStream_t s, int K, const int64_t* Nk, double* f,
+                                       const double* lnS);
+hipError_t launch_max_abs_diff(hipStream_t s, int K, const double* a, const double* b,
+                               double* out);
+hipError_t launch_weights(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                          const double* f, const double* logD, double* W);
+hipError_t launch_reweight(hipStream_t s, int64_t N, const double* ut, const double* logD,
+                           double* part, int nparts, double* p);
+hipError_t launch_check_finite_f(hipStream_t s, int K, const double* f, unsigned* flag);
+
+// ---- Hessian and linear algebra (hessian.hip, linalg.hip) ----------------
+size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out);
+hipError_t launch_hessian(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                          const double* cst, const double* gk, const double* logD,
+                          const double* S, double* partials, int chunks, double* H);
+// Newton direction on the reduced system (drop the first sampled state and
+// the unsampled ones). A: workspace K*K doubles, idx: K ints. ok: device int.
+hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, const double* H,
+                                   const double* S, double* A, int* idx, double* d, int* ok);
+
+}  // namespace bumbar
+
+struct bumbar_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  std::string err;
+  void* pinned = nullptr;  // small pinned host buffer for scalar readbacks
+  // optional timing of the unbinned sweep kernel (HIP events on ctx->stream)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+};

@@ -1,0 +1,179 @@
+// Hessian of the MBAR objective on FP64 matrix cores (gfx950 MFMA).
+//
+// F(f) = sum_n ln D_n - sum_k N_k f_k has gradient g_i = S_i - N_i and Hessian
+//   H_ij = delta_ij S_i - sum_n P_in P_jn,   P_in = N_i W_ni = g_i exp(c_i - u_in - ln D_n)
+// with c_i = ln N'_i + f_i (Section 2: derivative-based strategies; the Newton
+// finisher on unbinned data). The contraction G = P P^T over the N samples is
+// the only dense-matrix work of the method and runs on v_mfma_f64_16x16x4.
+//
+// Layout: the K x K output is cut into 64 x 64 blocks; only blocks with
+// bi <= bj are computed (symmetry). A workgroup (4 waves) owns one block and
+// one contiguous chunk of samples; per step of 16 samples it reads the two
+// 64-row slabs of u (coalesced along n), forms P in registers (one exp per
+// element), stages it in LDS, and each wave accumulates a 32 x 32 quarter of
+// the block as 2 x 2 MFMA tiles. Partial blocks are summed over chunks in a
+// fixed order by a second kernel, so the result is deterministic.
+#include <cmath>
+
+#include "bumbar_impl.h"
+#include "devmath.h"
+
+namespace bumbar {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int HB = 64;   // output block edge
+constexpr int HS = 16;   // samples per step
+constexpr int HP = HS + 1;  // padded LDS row (doubles)
+
+// Block index b in [0, nb*(nb+1)/2) -> (bi, bj) with bi <= bj, row-major over bi.
+__device__ __forceinline__ void block_coords(int b, int nb, int& bi, int& bj) {
+  int i = 0;
+  int rem = b;
+  while (rem >= nb - i) {
+    rem -= nb - i;
+    ++i;
+  }
+  bi = i;
+  bj = i + rem;
+}
+
+__global__ void __launch_bounds__(256)
+    hessian_partial_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+                           const double* __restrict__ cst, const double* __restrict__ gk,
+                           const double* __restrict__ logD, int nb, int chunks,
+                           int64_t chunk_len, double* __restrict__ partials) {
+  __shared__ double Pi[HB][HP];
+  __shared__ double Pj[HB][HP];
+  const int blk = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  int bi, bj;
+  block_coords(blk, nb, bi, bj);
+  const bool diag = (bi == bj);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+
+  // loader mapping: row r = tid / 4, samples (tid % 4) * 4 .. + 3
+  const int lr = tid >> 2;
+  const int ls = (tid & 3) * 4;
+  const int ki = bi * HB + lr;
+  const int kj = bj * HB + lr;
+  const double ci = (ki < K) ? cst[ki] : 0.0;
+  const double cj = (kj < K) ? cst[kj] : 0.0;
+  const bool si = (ki < K) && gk[ki] != 0.0;
+  const bool sj = (kj < K) && gk[kj] != 0.0;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  const int64_t n_begin = (int64_t)chunk * chunk_len;
+  int64_t n_end = n_begin + chunk_len;
+  if (n_end > N) n_end = N;
+
+  for (int64_t n0 = n_begin; n0 < n_end; n0 += HS) {
+    // form P for the two slabs
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t n = n0 + ls + q;
+      const bool ok = n < n_end;
+      const double lD = ok ? logD[n] : 0.0;
+      double vi = 0.0;
+      if (si && ok) vi = exp_nonpos(ci - u[(int64_t)ki * ld + n] - lD);
+      Pi[lr][ls + q] = vi;
+      if (!diag) {
+        double vj = 0.0;
+        if (sj && ok) vj = exp_nonpos(cj - u[(int64_t)kj * ld + n] - lD);
+        Pj[lr][ls + q] = vj;
+      }
+    }
+    __syncthreads();
+    const double(*Bsrc)[HP] = diag ? Pi : Pj;
+#pragma unroll
+    for (int s = 0; s < HS / 4; ++s) {
+      const int col = s * 4 + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Pi[wi * 32 + a * 16 + (lane & 15)][col];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bsrc[wj * 32 + b * 16 + (lane & 15)][col];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // write the partial block: in the 16 x 16 FP64 accumulator, lane l holds
+  // element v (0..3) at row l/16 + 4 v, column l % 16 of each tile
+  double* out = partials + (int64_t)blockIdx.x * HB * HB;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wi * 32 + a * 16 + (lane >> 4) + 4 * v;
+        const int c = wj * 32 + b * 16 + (lane & 15);
+        out[r * HB + c] = acc[a][b][v];
+      }
+}
+
+// H_ij = delta_ij S_i - sum_chunks G_ij, written to both triangles.
+__global__ void __launch_bounds__(256)
+    hessian_reduce_kernel(int K, int nb, int chunks, const double* __restrict__ partials,
+                          const double* __restrict__ S, const double* __restrict__ gk,
+                          double* __restrict__ H) {
+  const int blk = blockIdx.y;
+  int bi, bj;
+  block_coords(blk, nb, bi, bj);
+  const int e = blockIdx.x * 256 + threadIdx.x;  // element in the 64 x 64 block
+  if (e >= HB * HB) return;
+  const int r = e / HB, c = e % HB;
+  const int i = bi * HB + r, j = bj * HB + c;
+  if (i >= K || j >= K) return;
+  if (bi == bj && j < i) return;  // lower half of a diagonal block: mirror of the upper
+  double g = 0.0;
+  const double* p = partials + ((int64_t)blk * chunks) * HB * HB + e;
+  for (int q = 0; q < chunks; ++q) g += p[(int64_t)q * HB * HB];
+  double v = -g;
+  if (i == j) v += (gk[i] != 0.0) ? S[i] : 0.0;
+  if (gk[i] == 0.0 || gk[j] == 0.0) v = 0.0;
+  H[(int64_t)i * K + j] = v;
+  H[(int64_t)j * K + i] = v;
+}
+
+static int hess_nb(int K) { return (K + HB - 1) / HB; }
+
+size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
+  const int nb = hess_nb(K);
+  const int nblk = nb * (nb + 1) / 2;
+  // aim for about 4 workgroups per CU, each chunk at least 256 samples
+  int chunks = (4 * num_cus + nblk - 1) / nblk;
+  const int64_t max_chunks = (N + 255) / 256;
+  if (chunks > max_chunks) chunks = (int)max_chunks;
+  if (chunks < 1) chunks = 1;
+  if (chunks_out) *chunks_out = chunks;
+  return (size_t)nblk * chunks * HB * HB;
+}
+
+hipError_t launch_hessian(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                          const double* cst, const double* gk, const double* logD,
+                          const double* S, double* partials, int chunks, double* H) {
+  const int nb = hess_nb(K);
+  const int nblk = nb * (nb + 1) / 2;
+  int64_t chunk_len = (N + chunks - 1) / chunks;
+  chunk_len = (chunk_len + HS - 1) / HS * HS;
+  hipLaunchKernelGGL(hessian_partial_kernel, dim3(nblk * chunks), dim3(256), 0, s, u, ld, K, N,
+                     cst, gk, logD, nb, chunks, chunk_len, partials);
+  hipLaunchKernelGGL(hessian_reduce_kernel, dim3(HB * HB / 256, nblk), dim3(256), 0, s, K, nb,
+                     chunks, partials, S, gk, H);
+  return hipGetLastError();
+}
+
+}  // namespace bumbar

@@ -1,0 +1,542 @@
+// Host side of libbumbar: the C ABI of include/bumbar.h, the unbinned sweep
+// driver (fast path with robust fallback) and the Newton finisher.
+//
+// The binned stage (Algorithm 1) lives in algo.cpp; both use the helpers
+// declared in solver_internal.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "bumbar_impl.h"
+#include "solver_internal.h"
+
+using namespace bumbar;
+
+namespace bumbar {
+
+int fail(bumbar_ctx* ctx, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return code;
+}
+
+int hip_fail(bumbar_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, BUMBAR_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Device buffers of one unbinned problem, carved from the workspace.
+void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
+  K = K_;
+  N = N_;
+  cst = ar.take<double>(K);
+  gk = ar.take<double>(K);
+  lnNp = ar.take<double>(K);
+  f = ar.take<double>(K);
+  f_new = ar.take<double>(K);
+  f_trial = ar.take<double>(K);
+  dir = ar.take<double>(K);
+  lnS = ar.take<double>(K);
+  S = ar.take<double>(K);
+  lnS_t = ar.take<double>(K);
+  S_t = ar.take<double>(K);
+  logD = ar.take<double>(N);
+  logD_t = ar.take<double>(N);
+  const int g = sweep_max_grid(num_cus);
+  const int ch = robust_chunks(N);
+  nparts_cap = std::max(g, ch);
+  part = ar.take<double>((size_t)nparts_cap * K);
+  partS = ar.take<double>((size_t)ch * K);
+  part_obj = ar.take<double>(nparts_cap);
+  part_flags = ar.take<unsigned>(nparts_cap);
+  scal = ar.take<SweepScalars>(2);
+  misc = ar.take<double>(8);
+  ok = ar.take<int>(4);
+  idx = ar.take<int>(K);
+  A = ar.take<double>((size_t)K * K + K);
+  H = ar.take<double>((size_t)K * K);
+  hess_parts = ar.take<double>(hessian_partial_count(K, N, num_cus, &hess_chunks));
+}
+
+// Event pairs for timing sweep kernels; at most 4096 launches per solve are timed.
+std::pair<hipEvent_t, hipEvent_t>* next_event_pair(bumbar_ctx* ctx) {
+  if (ctx->events_used >= 4096) return nullptr;
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return nullptr;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return nullptr;
+    }
+    ctx->events.emplace_back(a, b);
+  }
+  return &ctx->events[ctx->events_used++];
+}
+
+// Sum of the timed intervals (the stream must have been synchronised).
+static double collect_event_ms(bumbar_ctx* ctx, int64_t* count) {
+  double tot = 0.0;
+  for (size_t i = 0; i < ctx->events_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second) == hipSuccess)
+      tot += ms;
+  }
+  *count = (int64_t)ctx->events_used;
+  ctx->events_used = 0;
+  return tot;
+}
+
+int read_scalars(bumbar_ctx* ctx, const SweepScalars* dev, SweepScalars* host) {
+  hipError_t e = hipMemcpyAsync(ctx->pinned, dev, sizeof(SweepScalars), hipMemcpyDeviceToHost,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "scalar readback");
+  std::memcpy(host, ctx->pinned, sizeof(SweepScalars));
+  return BUMBAR_OK;
+}
+
+int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "readback");
+  return BUMBAR_OK;
+}
+
+// One sweep (unbinned when h == nullptr, binned with multiplicities h
+// otherwise) of the K x N matrix u at f. Outputs: f_out (gauged SCI step),
+// logD_out, lnS_out, S_out and the scalars (read back to *sc when sc != null).
+int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
+             const double* h, const int64_t* Nk, const double* f, double* f_out,
+             double* logD_out, double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
+             SweepCounters* cnt) {
+  hipStream_t s = ctx->stream;
+  const int K = B.K;
+  hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
+  if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
+  bool robust = force_robust || !sweep_fast_supported(K);
+  if (!robust) {
+    int grid = 0;
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (ctx->profiling && h == nullptr) ev = next_event_pair(ctx);
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_fast(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.part_obj,
+                          B.part_flags, ctx->num_cus, &grid);
+    if (ev) (void)hipEventRecord(ev->second, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sweep_fast");
+    e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f,
+                              B.lnNp, Nk, f_out, lnS_out, S_out, B.scal);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
+    if (cnt) cnt->fast++;
+    if (sc == nullptr) return BUMBAR_OK;
+    int rc = read_scalars(ctx, B.scal, sc);
+    if (rc) return rc;
+    if ((sc->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) return BUMBAR_OK;
+    robust = true;
+  }
+  const int ch = robust_chunks(N);
+  e = launch_sweep_robust(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.partS, B.part_obj,
+                          B.part_flags, ch);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_robust");
+  e = launch_sweep_finalize(s, 1, K, ch, B.part, B.partS, B.part_obj, B.part_flags, f, B.lnNp, Nk,
+                            f_out, lnS_out, S_out, B.scal);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
+  if (cnt) cnt->robust++;
+  SweepScalars tmp;
+  SweepScalars* out = sc ? sc : &tmp;
+  int rc = read_scalars(ctx, B.scal, out);
+  if (rc) return rc;
+  if (out->flags & FLAG_NAN)
+    return fail(ctx, BUMBAR_EINVAL, "non-finite reduced energies (NaN or -inf in u_kn)");
+  return BUMBAR_OK;
+}
+
+// Newton finisher on unbinned data (see the oracle's reading): full Newton
+// step on the reduced system, trial steps alpha = 1, 1/2, ..., 2^-10 accepted
+// when they lower ||S - N||_2; otherwise one SCI step. Stops when the applied
+// max |delta f| < tol. f (device, K) is updated in place.
+int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
+                  const int64_t* Nk, double tol, int max_steps, bumbar_stats* st,
+                  SweepCounters* cnt, double* final_step, double* final_gnorm) {
+  hipStream_t s = ctx->stream;
+  const int K = B.K;
+  const int64_t N = B.N;
+  SweepScalars sc{};
+  // fill unsampled states and gauge at the start (as the oracle does)
+  int rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
+                    cnt);
+  if (rc) return rc;
+  hipError_t e = launch_fill_unsampled_gauge(s, K, Nk, B.f, B.lnS);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fill_unsampled");
+  int steps = 0, fallbacks = 0;
+  double last = INFINITY;
+  rc = BUMBAR_ENOTCONV;
+  while (steps < max_steps) {
+    rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
+                  cnt);
+    if (rc) return rc;
+    const double gn = sc.grad_norm;
+    if (final_gnorm) *final_gnorm = gn;
+    e = launch_hessian(s, u, ld, K, N, B.cst, B.gk, B.logD, B.S, B.hess_parts, B.hess_chunks, B.H);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
+    if (st) st->hessians++;
+    e = launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
+    if (e != hipSuccess) return hip_fail(ctx, e, "newton_direction");
+    int ok = 0;
+    rc = read_bytes(ctx, B.ok, &ok, sizeof(int));
+    if (rc) return rc;
+    bool accepted = false;
+    SweepScalars st2{};
+    if (ok) {
+      double alpha = 1.0;
+      for (int t = 0; t <= 10; ++t, alpha *= 0.5) {
+        e = launch_axpy_to(s, K, B.f, alpha, B.dir, B.f_trial);
+        if (e != hipSuccess) return hip_fail(ctx, e, "axpy");
+        rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
+                      &st2, false, cnt);
+        if (rc) return rc;
+        if (st2.grad_norm < gn) {
+          accepted = true;
+          break;
+        }
+      }
+    }
+    if (!accepted) {
+      // SCI step: f_trial = SCI(f) (gauged), from a sweep at f
+      rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_trial, B.logD_t, B.lnS_t, B.S_t,
+                    nullptr, false, cnt);
+      if (rc) return rc;
+      rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
+                    &st2, false, cnt);
+      if (rc) return rc;
+      ++fallbacks;
+    }
+    e = launch_fill_unsampled_gauge(s, K, Nk, B.f_trial, B.lnS_t);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fill_unsampled");
+    e = launch_max_abs_diff(s, K, B.f_trial, B.f, B.misc);
+    if (e != hipSuccess) return hip_fail(ctx, e, "max_abs_diff");
+    e = hipMemcpyAsync(B.f, B.f_trial, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
+    rc = read_bytes(ctx, B.misc, &last, sizeof(double));
+    if (rc) return rc;
+    ++steps;
+    if (last < tol) {
+      rc = BUMBAR_OK;
+      break;
+    }
+    rc = BUMBAR_ENOTCONV;
+  }
+  if (st) {
+    st->finisher_steps += steps;
+    st->sci_fallbacks += fallbacks;
+  }
+  if (final_step) *final_step = last;
+  return rc;
+}
+
+// Plain self-consistent iteration on unbinned data until the step is below
+// `until` (or the cap); f updated in place.
+int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld, const int64_t* Nk,
+              double until, int64_t max_steps, int64_t* steps_out, SweepCounters* cnt,
+              double* last_step) {
+  SweepScalars sc{};
+  int64_t it = 0;
+  int rc = BUMBAR_ENOTCONV;
+  while (it < max_steps) {
+    rc = sweep_at(ctx, B, u, ld, B.N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
+                  cnt);
+    if (rc) return rc;
+    hipError_t e =
+        hipMemcpyAsync(B.f, B.f_new, sizeof(double) * B.K, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
+    ++it;
+    if (last_step) *last_step = sc.max_df;
+    if (sc.max_df < until) {
+      rc = BUMBAR_OK;
+      break;
+    }
+    rc = BUMBAR_ENOTCONV;
+  }
+  if (steps_out) *steps_out = it;
+  return rc;
+}
+
+}  // namespace bumbar
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* bumbar_version(void) { return "bumbar-gfx950 0.1"; }
+
+int bumbar_create(bumbar_ctx** out, int device, void* hip_stream) {
+  if (!out) return BUMBAR_EINVAL;
+  *out = nullptr;
+  bumbar_ctx* c = new (std::nothrow) bumbar_ctx();
+  if (!c) return BUMBAR_ENOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, device);
+    if (e == hipSuccess) c->num_cus = p.multiProcessorCount;
+  }
+  if (e == hipSuccess) e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return BUMBAR_EDEVICE;
+  }
+  *out = c;
+  return BUMBAR_OK;
+}
+
+void bumbar_destroy(bumbar_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& p : ctx->events) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* bumbar_last_error(const bumbar_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void bumbar_default_options(bumbar_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-10;
+  o->precision = BUMBAR_PREC_FP64;
+  o->binning = 0;
+  o->n0 = 100;
+  o->eps = 1e-3;
+  o->inc = 10;
+  o->n_intermediate = 20;
+  o->finisher = BUMBAR_FINISH_NEWTON;
+  o->max_iter = 1000000;
+  o->max_newton = 100;
+  o->sci_switch = 1e-3;
+  o->replay_phase1 = 0;
+  o->replay_refine = nullptr;
+  o->n_replay = 0;
+  o->profile = 0;
+}
+
+int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
+                           const bumbar_options* opt, size_t* bytes) {
+  if (!ctx || !bytes || K <= 0 || N <= 0 || d < 0 || d > 2) return BUMBAR_EINVAL;
+  Arena ar;
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  if (d > 0 && (opt == nullptr || opt->binning)) binned_carve_size(ar, K, N, d, ctx->num_cus);
+  *bytes = ar.off + 256;
+  return BUMBAR_OK;
+}
+
+static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
+                        int64_t ld) {
+  if (!ctx) return BUMBAR_EINVAL;
+  ctx->err.clear();
+  if (!u) return fail(ctx, BUMBAR_EINVAL, "u_kn is NULL");
+  if (K <= 0 || N <= 0) return fail(ctx, BUMBAR_EINVAL, "K and N must be positive");
+  if (ld < N) return fail(ctx, BUMBAR_EINVAL, "row stride ld < N");
+  if (u_dtype != BUMBAR_F64)
+    return fail(ctx, BUMBAR_EINVAL, "only FP64 u_kn is supported by this entry point");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BUMBAR_EDEVICE, "hipSetDevice");
+  return BUMBAR_OK;
+}
+
+int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
+                 const int64_t* N_k, const double* f, void* workspace, size_t ws_bytes,
+                 double* f_new, double* log_D_n, double* S, double* sweep_stats) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (!N_k || !f || !f_new || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes)", ws_bytes);
+  double* logD = log_D_n ? log_D_n : B.logD;
+  double* Sv = S ? S : B.S;
+  SweepScalars sc{};
+  // Without stats the call stays asynchronous on the fast path; the fallback
+  // decision then needs the flags, so read them back anyway.
+  rc = sweep_at(ctx, B, reinterpret_cast<const double*>(u_kn), ld, N, nullptr, N_k, f, f_new,
+                logD, B.lnS, Sv, sweep_stats ? &sc : nullptr, false, nullptr);
+  if (rc) return rc;
+  if (sweep_stats) {
+    sweep_stats[0] = sc.max_df;
+    sweep_stats[1] = sc.rel_step;
+    sweep_stats[2] = sc.objective;
+    sweep_stats[3] = sc.grad_norm;
+  }
+  return BUMBAR_OK;
+}
+
+int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                   int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
+                   const double* S, void* workspace, size_t ws_bytes, double* H) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (!N_k || !f || !log_D_n || !S || !H || !workspace)
+    return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
+  hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
+  if (e == hipSuccess)
+    e = launch_hessian(ctx->stream, reinterpret_cast<const double*>(u_kn), ld, K, N, B.cst, B.gk,
+                       log_D_n, S, B.hess_parts, B.hess_chunks, H);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
+  return BUMBAR_OK;
+}
+
+int bumbar_weights(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
+                   const double* f, const double* log_D_n, double* W_nk) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (!f || !log_D_n || !W_nk) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  hipError_t e = launch_weights(ctx->stream, reinterpret_cast<const double*>(u_kn), ld, K, N, f,
+                                log_D_n, W_nk);
+  if (e != hipSuccess) return hip_fail(ctx, e, "weights");
+  return BUMBAR_OK;
+}
+
+int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const double* log_D_n,
+                    void* workspace, size_t ws_bytes, double* p) {
+  if (!ctx) return BUMBAR_EINVAL;
+  ctx->err.clear();
+  if (!u_target || !log_D_n || !p || !workspace || N <= 0)
+    return fail(ctx, BUMBAR_EINVAL, "bad argument");
+  const int nparts = 1024;
+  if (ws_bytes < sizeof(double) * (2 * nparts + 2))
+    return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
+  hipError_t e = launch_reweight(ctx->stream, N, u_target, log_D_n,
+                                 reinterpret_cast<double*>(workspace), nparts, p);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reweight");
+  return BUMBAR_OK;
+}
+
+int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                 const int64_t* N_k, const double* xi, int d, int model, const double* coef,
+                 const double* f_init, const bumbar_options* opt_in, void* workspace,
+                 size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
+                 bumbar_stats* stats) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, N);
+  if (rc) return rc;
+  bumbar_options opt;
+  if (opt_in)
+    opt = *opt_in;
+  else
+    bumbar_default_options(&opt);
+  if (!N_k || !f_k || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  if (!(opt.tol > 0.0)) return fail(ctx, BUMBAR_EINVAL, "tol must be > 0");
+  if (opt.binning && (!xi || d < 1 || d > 2))
+    return fail(ctx, BUMBAR_EINVAL, "binning needs coordinates xi with d in {1, 2}");
+  if (opt.binning && (opt.n0 < 2 || opt.inc < 2 || opt.n_intermediate < 0 || !(opt.eps > 0.0)))
+    return fail(ctx, BUMBAR_EINVAL, "invalid binning settings");
+  if (model != BUMBAR_MODEL_NONE && model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC)
+    return fail(ctx, BUMBAR_EINVAL, "unknown model code");
+  if (model != BUMBAR_MODEL_NONE && !coef) return fail(ctx, BUMBAR_EINVAL, "model needs coef");
+  // counts: host copy for validation
+  std::vector<int64_t> nk(K);
+  rc = read_bytes(ctx, N_k, nk.data(), sizeof(int64_t) * K);
+  if (rc) return rc;
+  int64_t tot = 0;
+  for (int k = 0; k < K; ++k) {
+    if (nk[k] < 0) return fail(ctx, BUMBAR_EINVAL, "negative N_k");
+    tot += nk[k];
+  }
+  if (tot != N) return fail(ctx, BUMBAR_EINVAL, "sum of N_k (%lld) != N (%lld)", (long long)tot,
+                            (long long)N);
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  BinnedBufs BB;
+  if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus);
+  if (ar.overflow)
+    return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
+  bumbar_stats local{};
+  bumbar_stats* st = stats ? stats : &local;
+  bumbar_check* chk = st->checks;
+  int chk_cap = st->checks_capacity;
+  std::memset(st, 0, sizeof(*st));
+  st->checks = chk;
+  st->checks_capacity = chk_cap;
+  hipStream_t s = ctx->stream;
+  const double* u = reinterpret_cast<const double*>(u_kn);
+  SweepCounters cnt;
+  hipError_t e;
+  ctx->profiling = opt.profile != 0;
+  ctx->events_used = 0;
+  if (f_init && !opt.binning)
+    e = hipMemcpyAsync(B.f, f_init, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+  else
+    e = hipMemsetAsync(B.f, 0, sizeof(double) * K, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "init f");
+
+  int stage_rc = BUMBAR_OK;
+  if (opt.binning) {
+    stage_rc = binned_stage(ctx, B, BB, u, N_k, nk.data(), xi, d, model, coef, opt, st, &cnt);
+    if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
+  } else if (opt.finisher == BUMBAR_FINISH_NEWTON) {
+    const double t0 = now_ms();
+    int64_t it = 0;
+    double last = 0;
+    stage_rc = sci_until(ctx, B, u, N, N_k, opt.sci_switch, opt.max_iter, &it, &cnt, &last);
+    if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
+    st->phase1_iters = it;
+    st->time_binned_ms = now_ms() - t0;
+  }
+  const double t1 = now_ms();
+  int fin_rc = BUMBAR_OK;
+  if (stage_rc == BUMBAR_OK) {
+    if (opt.finisher == BUMBAR_FINISH_NEWTON) {
+      fin_rc = newton_finish(ctx, B, u, N, N_k, opt.tol, opt.max_newton, st, &cnt,
+                             &st->final_step, &st->grad_norm);
+    } else {
+      int64_t it = 0;
+      const int64_t left = std::max<int64_t>(0, opt.max_iter - st->phase1_iters - st->phase2_iters);
+      fin_rc = sci_until(ctx, B, u, N, N_k, opt.tol, left, &it, &cnt, &st->final_step);
+      st->finisher_steps = it;
+    }
+    if (fin_rc != BUMBAR_OK && fin_rc != BUMBAR_ENOTCONV) return fin_rc;
+  }
+  st->time_final_ms = now_ms() - t1;
+  // outputs: ln D at the final f, weights, f
+  SweepScalars sc{};
+  rc = sweep_at(ctx, B, u, N, N, nullptr, N_k, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, &cnt);
+  if (rc) return rc;
+  st->grad_norm = sc.grad_norm;
+  e = hipMemcpyAsync(f_k, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && log_D_n)
+    e = hipMemcpyAsync(log_D_n, B.logD, sizeof(double) * N, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && W_nk) e = launch_weights(s, u, N, K, N, B.f, B.logD, W_nk);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "outputs");
+  st->unbinned_sweeps = cnt.fast + cnt.robust;
+  st->robust_sweeps = cnt.robust;
+  if (ctx->profiling) st->sweep_kernel_ms = collect_event_ms(ctx, &st->sweep_kernel_launches);
+  ctx->profiling = false;
+  if (stage_rc == BUMBAR_ENOTCONV || fin_rc == BUMBAR_ENOTCONV)
+    return fail(ctx, BUMBAR_ENOTCONV, "iteration cap reached before convergence");
+  return BUMBAR_OK;
+}
+
+}  // extern "C"

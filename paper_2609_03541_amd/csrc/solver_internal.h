@@ -1,0 +1,129 @@
+// Host-side helpers shared by solver.cpp (unbinned sweeps, Newton finisher,
+// C ABI) and algo.cpp (binning and Algorithm 1).
+#pragma once
+
+#include <cstdarg>
+#include <cstdint>
+
+#include "bumbar_impl.h"
+
+namespace bumbar {
+
+int fail(bumbar_ctx* ctx, int code, const char* fmt, ...);
+int hip_fail(bumbar_ctx* ctx, hipError_t e, const char* where);
+double now_ms();
+int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes);
+std::pair<hipEvent_t, hipEvent_t>* next_event_pair(bumbar_ctx* ctx);
+
+struct SweepCounters {
+  int64_t fast = 0;
+  int64_t robust = 0;
+};
+
+// Device buffers for sweeps and the Newton finisher of one K x N problem.
+struct UnbinnedBufs {
+  int K = 0;
+  int64_t N = 0;
+  double *cst = nullptr, *gk = nullptr, *lnNp = nullptr;
+  double *f = nullptr, *f_new = nullptr, *f_trial = nullptr, *dir = nullptr;
+  double *lnS = nullptr, *S = nullptr, *lnS_t = nullptr, *S_t = nullptr;
+  double *logD = nullptr, *logD_t = nullptr;
+  int nparts_cap = 0;
+  double *part = nullptr, *partS = nullptr, *part_obj = nullptr;
+  unsigned* part_flags = nullptr;
+  SweepScalars* scal = nullptr;
+  double* misc = nullptr;
+  int* ok = nullptr;
+  int* idx = nullptr;
+  double *A = nullptr, *H = nullptr, *hess_parts = nullptr;
+  int hess_chunks = 1;
+  void carve(Arena& ar, int K, int64_t N, int num_cus);
+};
+
+int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
+             const double* h, const int64_t* Nk, const double* f, double* f_out,
+             double* logD_out, double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
+             SweepCounters* cnt);
+
+int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
+                  const int64_t* Nk, double tol, int max_steps, bumbar_stats* st,
+                  SweepCounters* cnt, double* final_step, double* final_gnorm);
+
+int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld, const int64_t* Nk,
+              double until, int64_t max_steps, int64_t* steps_out, SweepCounters* cnt,
+              double* last_step);
+
+// ---- binning ---------------------------------------------------------------
+
+struct Level {
+  int64_t n = 0;   // nominal target
+  uint64_t m = 0;  // width in quanta
+  int64_t P = 0;   // nonempty bins
+  double* ubar = nullptr;  // K x P (row stride P)
+  double* h = nullptr;     // P multiplicities (as double)
+};
+
+struct BinnedBufs {
+  int d = 0;
+  int64_t N = 0;
+  uint32_t* q = nullptr;         // N x d quantised coordinates
+  double* lo = nullptr;          // d
+  double* scale = nullptr;       // d
+  double* mm = nullptr;          // 2 d min / max
+  uint64_t* keys = nullptr;      // N cell ids (unsorted)
+  uint64_t* keys_sorted = nullptr;
+  uint32_t* iota = nullptr;      // N: 0..N-1
+  uint32_t* perm = nullptr;      // N: sample index of each sorted position
+  uint32_t* q1_sorted = nullptr; // 1-D: sorted q (sorted once)
+  uint32_t* perm1 = nullptr;     // 1-D: permutation of the one-time sort
+  int32_t* bin_of_pos = nullptr; // N: bin index of each sorted position
+  int64_t* start = nullptr;      // N + 1: first sorted position of each bin
+  uint64_t* cells = nullptr;     // N: cell id of each bin
+  int64_t* counts = nullptr;     // reduction scratch
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  double* ubar[2] = {nullptr, nullptr};  // K x N each (worst case P = N)
+  double* h[2] = {nullptr, nullptr};     // N each
+  double* logD_lvl = nullptr;            // N
+  double *f_n = nullptr, *f_x = nullptr; // K
+  void carve(Arena& ar, int K, int64_t N, int d, int num_cus);
+};
+
+void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus);
+
+int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double* u,
+                 const int64_t* Nk_dev, const int64_t* Nk_host, const double* xi, int d,
+                 int model, const double* coef, const bumbar_options& opt, bumbar_stats* st,
+                 SweepCounters* cnt);
+
+// Binning primitives (binning.hip).
+size_t sort_temp_bytes(int64_t N);
+hipError_t launch_minmax(hipStream_t s, const double* xi, int64_t N, int d, double* mm,
+                         int64_t* scratch);
+hipError_t launch_quantize(hipStream_t s, const double* xi, int64_t N, int d, const double* mm,
+                           double* lo, double* scale, uint32_t* q, unsigned* bad);
+hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t* iota,
+                          uint32_t* q_sorted, uint32_t* perm, void* tmp, size_t tmp_bytes);
+// g(m) for 1-D sorted coordinates or 2-D (sorts the cell ids of this m); result
+// in counts[0] after the call.
+hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, uint64_t m,
+                           int64_t* counts);
+hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
+                           uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
+                           int64_t* counts);
+// Histogram at width m: bins in ascending cell order. On return counts[0] = P
+// (device); cells, start (P + 1 entries), bin_of_pos, perm filled.
+hipError_t launch_histogram(hipStream_t s, const uint32_t* q, int64_t N, int d, uint64_t m,
+                            const uint32_t* q1_sorted, const uint32_t* perm1, uint32_t* iota,
+                            uint64_t* keys, uint64_t* keys_sorted, uint32_t* perm,
+                            int32_t* bin_of_pos, int64_t* start, uint64_t* cells, void* tmp,
+                            size_t tmp_bytes, int64_t* counts);
+hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, const double* coef,
+                            const double* lo, const double* scale, uint64_t m, int64_t P,
+                            const uint64_t* cells, const int64_t* start, const uint32_t* perm,
+                            const double* u, double* ubar, double* h);
+hipError_t launch_sample_bin(hipStream_t s, int64_t N, const uint32_t* perm,
+                             const int32_t* bin_of_pos, int32_t* sample_bin);
+hipError_t launch_counts_from_start(hipStream_t s, int64_t P, const int64_t* start, int64_t* H);
+
+}  // namespace bumbar

@@ -1,0 +1,867 @@
+// Sweep kernels of the MBAR self-consistent iteration on gfx950.
+//
+// One sweep evaluates, for the current free energies f (Section 2, Eq. (1) in
+// its unbinned limit, or binned with per-column multiplicities h_p):
+//   ln D_n  = ln sum_{k: N_k>0} N_k exp(f_k - u_kn)
+//   S_i     = sum_n h_n N_i exp(f_i - u_in - ln D_n)          (h_n = 1 unbinned)
+//   f_new_i = ln N'_i + f_i - ln S_i                            (then gauge f_0 = 0)
+// which is f_new_i = -ln sum_n h_n exp(-u_in - ln D_n).
+//
+// Fast path (sweep_fast): a persistent workgroup owns a K x TN column tile per
+// iteration, held in registers. With a_kn = c_k - u_kn (c_k = ln N'_k + f_k):
+//   pass 1: m_n = max_k a_kn                   (exact column shift)
+//   pass 2: e_kn = exp(a_kn - m_n), D'_n = sum_k g_k e_kn
+//   pass 3: acc_k += e_kn * h_n / D'_n         (per-thread, per-state accumulator)
+// so u_kn is read from HBM once and each element costs one exponential. The
+// per-state accumulators are reduced across lanes and written once per
+// workgroup; the finaliser adds the workgroup partials in a fixed order, so a
+// sweep is deterministic (no floating-point atomics anywhere).
+//
+// The shift m_n makes every e_kn <= 1 (no overflow). A state whose every
+// weight is below the double range (a far-off starting f) would make S_i
+// underflow; the finaliser flags that and the host reruns the sweep on the
+// robust two-pass path, which keeps an exact per-state log-sum-exp.
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "bumbar_impl.h"
+#include "devmath.h"
+
+namespace bumbar {
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, 64); }
+
+// ---------------------------------------------------------------------------
+// Fast single-pass sweep.
+//   NW   waves per workgroup         LPR  lanes along a row segment
+//   CPL  columns per lane            ROWS rows (states) per thread
+// Thread t: column lane lc = t % LPR, row group rg = t / LPR; it owns rows
+// k = rg + RG * j (j < ROWS) and columns col0 .. col0 + CPL - 1 of each tile.
+// Rows past K read row K - 1 (always in bounds) and are masked by c_k = -inf,
+// so the main loop has no per-row branches; the last, partial column tile
+// takes a separate guarded path.
+// ---------------------------------------------------------------------------
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <int NW, int LPR, int CPL, int ROWS>
+struct SweepTile {
+  static constexpr int NT = NW * 64;
+  static constexpr int RG = NT / LPR;
+  static constexpr int TN = LPR * CPL;
+};
+
+// Load this thread's ROWS x CPL elements of column tile t. Padding rows
+// (j >= rows_here) re-read the thread's last valid row (c_k = -inf masks
+// them); in the TAIL tile columns past N re-read column N - 1 (their weight is
+// zeroed). The row offsets are opaque to the compiler so every load is
+// unconditional: no branch and no reuse of another row's value, hence no wait
+// on an earlier load before the next is issued.
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool TAIL>
+__device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const double* __restrict__ rowp,
+                                          int64_t rstride, int rows_here, int64_t t, int64_t N,
+                                          int lc) {
+  constexpr int TN = SweepTile<NW, LPR, CPL, ROWS>::TN;
+  const int64_t col0 = t * TN + (int64_t)lc * CPL;
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    int64_t roff = (int64_t)(j < rows_here ? j : (rows_here > 0 ? rows_here - 1 : 0)) * rstride;
+    asm volatile("" : "+v"(roff));
+    const double* p = rowp + roff + t * TN;
+    if constexpr (!TAIL && VEC && CPL == 2) {
+      const d2v v = *reinterpret_cast<const d2v*>(p);
+      a[j][0] = v.x;
+      a[j][1] = v.y;
+    } else if constexpr (!TAIL) {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) a[j][i] = p[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        const int64_t off = (col0 + i < N) ? (int64_t)i : (N - 1 - col0);
+        a[j][i] = p[off];
+      }
+    }
+  }
+}
+
+// The three passes over a loaded tile (see the file comment).
+template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED>
+__device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, int64_t N, int lc,
+                                             int rg, int wave, int rgw,
+                                             const double* __restrict__ c_sh, unsigned smask,
+                                             const double* __restrict__ h,
+                                             double* __restrict__ logD,
+                                             double (*red1)[LPR * CPL], double (*red2)[LPR * CPL],
+                                             double* acc, double& obj, unsigned& bad) {
+  using TL = SweepTile<NW, LPR, CPL, ROWS>;
+  constexpr int RG = TL::RG;
+  constexpr int TN = TL::TN;
+  const int64_t col0 = t * TN + (int64_t)lc * CPL;
+  // opaque copies: re-read c_k from LDS each tile rather than pin ROWS
+  // registers to it
+  int rgo = rg;
+  unsigned sm = smask;
+  asm volatile("" : "+v"(rgo), "+v"(sm));
+  // ---- pass 1: a = c - u and the column maximum ----
+  double cm[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) cm[i] = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    const double c = c_sh[rgo + RG * j];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      a[j][i] = c - a[j][i];
+      cm[i] = fmax(cm[i], a[j][i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) {
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1) cm[i] = fmax(cm[i], __shfl_xor(cm[i], off, 64));
+    if (rgw == 0) red1[wave][lc * CPL + i] = cm[i];
+  }
+  __syncthreads();
+  double m[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) {
+    double v = red1[0][lc * CPL + i];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v = fmax(v, red1[w][lc * CPL + i]);
+    m[i] = (v == -INFINITY) ? 0.0 : v;
+  }
+  // ---- pass 2: e = exp(a - m) and the column sum over sampled states ----
+  double ds[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) ds[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      a[j][i] = exp_nonpos(a[j][i] - m[i]);
+      if constexpr (MASKED) {
+        ds[i] = ((sm >> j) & 1u) ? ds[i] + a[j][i] : ds[i];
+      } else {
+        ds[i] += a[j][i];
+      }
+    }
+    // keep the exponentials of one row together: bounds register pressure
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) {
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1) ds[i] += __shfl_xor(ds[i], off, 64);
+    if (rgw == 0) red2[wave][lc * CPL + i] = ds[i];
+  }
+  __syncthreads();
+  double w[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) {
+    double D = red2[0][lc * CPL + i];
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) D += red2[wv][lc * CPL + i];
+    const int64_t n = col0 + i;
+    const bool valid = !TAIL || n < N;
+    const double hn = (h != nullptr && valid) ? h[n] : 1.0;
+    w[i] = valid ? hn / D : 0.0;
+    if (valid) {
+      if (!(D >= 1e-300 && D <= 1e300)) bad |= FLAG_COL;
+      if (rg == 0) {
+        const double l = m[i] + log(D);
+        if (logD != nullptr) logD[n] = l;
+        obj = __builtin_fma(hn, l, obj);
+      }
+    }
+  }
+  // ---- pass 3: per-state accumulation of e * h / D' ----
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) acc[j] = __builtin_fma(a[j][i], w[i], acc[j]);
+}
+
+// Tile loop over the full tiles of this block; with PF the next tile's loads
+// are issued into a second register buffer before the current tile is
+// processed (software prefetch), so HBM traffic overlaps the arithmetic.
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF>
+__device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64_t rstride,
+                                          int rows_here, int64_t nfull, int64_t N, int lc, int rg,
+                                          int wave, int rgw, const double* __restrict__ c_sh,
+                                          unsigned smask, const double* __restrict__ h,
+                                          double* __restrict__ logD, double (*red1)[LPR * CPL],
+                                          double (*red2)[LPR * CPL], double* acc, double& obj,
+                                          unsigned& bad) {
+  const int64_t G = gridDim.x;
+  int64_t t = blockIdx.x;
+  if constexpr (!PF) {
+    for (; t < nfull; t += G) {
+      double a[ROWS][CPL];
+      tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+                                                      logD, red1, red2, acc, obj, bad);
+    }
+  } else {
+    double a[ROWS][CPL], b[ROWS][CPL];
+    if (t < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
+    while (t < nfull) {
+      const int64_t t1 = t + G;
+      if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(b, base, rstride, rows_here, t1, N, lc);
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+                                                      logD, red1, red2, acc, obj, bad);
+      if (t1 >= nfull) break;
+      const int64_t t2 = t1 + G;
+      if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t2, N, lc);
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
+                                                      logD, red1, red2, acc, obj, bad);
+      t = t2;
+    }
+  }
+}
+
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF>
+__global__ void __launch_bounds__(NW * 64)
+    sweep_fast_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+                      int64_t ntiles, const double* __restrict__ cst,
+                      const double* __restrict__ gk, const double* __restrict__ h,
+                      double* __restrict__ logD, double* __restrict__ part,
+                      double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+  using TL = SweepTile<NW, LPR, CPL, ROWS>;
+  constexpr int NT = TL::NT;
+  constexpr int RG = TL::RG;
+  constexpr int TN = TL::TN;
+  __shared__ double red1[NW][TN];
+  __shared__ double red2[NW][TN];
+  __shared__ double c_sh[ROWS * RG];
+  __shared__ unsigned fl;
+
+  const int tid = threadIdx.x;
+  const int lc = tid % LPR;
+  const int rg = tid / LPR;
+  const int wave = tid >> 6;
+  const int rgw = (tid & 63) / LPR;
+
+  // per-state constants: c_k in LDS (-inf for padding rows), sampled flags as a
+  // bitmask (used only when some state has N_k = 0)
+  for (int k = tid; k < ROWS * RG; k += NT) c_sh[k] = (k < K) ? cst[k] : -INFINITY;
+  if (tid == 0) fl = 0u;
+  unsigned smask = 0u;
+  double acc[ROWS];
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    const int k = rg + RG * j;
+    if (k < K && gk[k] != 0.0) smask |= 1u << j;
+    acc[j] = 0.0;
+  }
+  // Pointer to this thread's first row (row 0 for a thread with no valid
+  // row); its rows are RG apart. rows_here counts its rows below K.
+  const int rows_here = (rg < K) ? (K - 1 - rg) / RG + 1 : 0;
+  const double* base = u + (int64_t)((rg < K) ? rg : 0) * ld + (int64_t)lc * CPL;
+  const int64_t rstride = (int64_t)RG * ld;
+  // any state with N_k = 0 among this block's rows? (uniform over the block)
+  const unsigned valid_bits = (rows_here >= 32) ? 0xffffffffu : ((1u << rows_here) - 1u);
+  const bool masked = __syncthreads_or(smask != valid_bits) != 0;
+
+  double obj = 0.0;
+  unsigned bad = 0;
+  const int64_t nfull = N / TN;
+  if (!masked)
+    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF>(base, rstride, rows_here, nfull, N, lc, rg, wave,
+                                                  rgw, c_sh, smask, h, logD, red1, red2, acc, obj,
+                                                  bad);
+  else
+    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false>(base, rstride, rows_here, nfull, N, lc, rg,
+                                                    wave, rgw, c_sh, smask, h, logD, red1, red2,
+                                                    acc, obj, bad);
+  if (nfull < ntiles && blockIdx.x == (unsigned)(nfull % gridDim.x)) {
+    double a[ROWS][CPL];
+    tile_load<NW, LPR, CPL, ROWS, VEC, true>(a, base, rstride, rows_here, nfull, N, lc);
+    tile_compute<NW, LPR, CPL, ROWS, true, true>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
+                                                 logD, red1, red2, acc, obj, bad);
+  }
+
+  // Reduce each state's accumulator over the LPR lanes of its row group
+  // (contiguous lanes; xor butterfly, identical result in every lane).
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, 64);
+    const int k = rg + RG * j;
+    if (lc == 0 && k < K) part[(int64_t)blockIdx.x * K + k] = v;
+  }
+  // objective partial: only row group 0 (lanes 0..LPR-1 of wave 0) holds it
+  double o = obj;
+#pragma unroll
+  for (int off = 1; off < LPR; off <<= 1) o += __shfl_xor(o, off, 64);
+  if (tid == 0) part_obj[blockIdx.x] = o;
+  // flags: OR over the block in shared memory, then one plain store
+  if (bad) atomicOr(&fl, bad);
+  __syncthreads();
+  if (tid == 0) part_flags[blockIdx.x] = fl;
+}
+
+// Launch configuration table: (NW, LPR, CPL, ROWS, PF) by number of states.
+struct FastCfg {
+  int kmax, nw, lpr, cpl, rows, pf;
+};
+static const FastCfg kCfgs[] = {
+    {8, 4, 64, 2, 2, 1},    {16, 4, 64, 2, 4, 1},   {32, 4, 64, 2, 8, 1},
+    {64, 4, 32, 2, 8, 1},   {104, 4, 32, 2, 13, 1}, {128, 4, 32, 2, 16, 0},
+    {256, 8, 32, 2, 16, 0},
+};
+// Extra instantiations reachable through BUMBAR_SWEEP_CFG="nw,lpr,cpl,rows,pf"
+// (launch-shape tuning; results do not depend on the shape beyond rounding).
+static const FastCfg kTune[] = {
+    {0, 4, 32, 2, 13, 0}, {0, 8, 32, 2, 7, 1}, {0, 8, 32, 2, 7, 0}, {0, 8, 64, 2, 13, 0},
+    {0, 4, 64, 2, 8, 0},  {0, 8, 16, 2, 4, 1},
+};
+
+static const FastCfg* pick_cfg(int K) {
+  static FastCfg forced{};
+  static int forced_state = -1;
+  if (forced_state < 0) {
+    forced_state = 0;
+    if (const char* e = getenv("BUMBAR_SWEEP_CFG")) {
+      FastCfg c{};
+      if (sscanf(e, "%d,%d,%d,%d,%d", &c.nw, &c.lpr, &c.cpl, &c.rows, &c.pf) == 5) {
+        for (const auto& t : kTune)
+          if (t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows && t.pf == c.pf)
+            forced_state = 1;
+        for (const auto& t : kCfgs)
+          if (t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows && t.pf == c.pf)
+            forced_state = 1;
+        if (forced_state) forced = c;
+      }
+    }
+  }
+  if (forced_state == 1) {
+    forced.kmax = (forced.nw * 64 / forced.lpr) * forced.rows;
+    return K <= forced.kmax ? &forced : nullptr;
+  }
+  for (const auto& c : kCfgs)
+    if (K <= c.kmax) return &c;
+  return nullptr;
+}
+
+bool sweep_fast_supported(int K) { return pick_cfg(K) != nullptr; }
+
+int sweep_max_grid(int num_cus) { return num_cus * 8; }
+
+template <int NW, int LPR, int CPL, int ROWS, int PF>
+static hipError_t launch_cfg(hipStream_t s, bool vec, const double* u, int64_t ld, int K,
+                             int64_t N, const double* cst, const double* gk, const double* h,
+                             double* logD, double* part, double* part_obj, unsigned* pf,
+                             int num_cus, int* grid_out) {
+  constexpr int TN = LPR * CPL;
+  const int64_t ntiles = (N + TN - 1) / TN;
+  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0>;
+  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0>;
+  // resident workgroups per CU of this instantiation (queried once)
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kv, NW * 64, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    per_cu = nb;
+  }
+  int64_t g = (int64_t)num_cus * per_cu;
+  if (g > ntiles) g = ntiles;
+  if (g > sweep_max_grid(num_cus)) g = sweep_max_grid(num_cus);
+  if (g < 1) g = 1;
+  *grid_out = (int)g;
+  if (vec)
+    hipLaunchKernelGGL(kv, dim3((unsigned)g), dim3(NW * 64), 0, s, u, ld, K, N, ntiles, cst, gk, h,
+                       logD, part, part_obj, pf);
+  else
+    hipLaunchKernelGGL(ks, dim3((unsigned)g), dim3(NW * 64), 0, s, u, ld, K, N, ntiles, cst, gk, h,
+                       logD, part, part_obj, pf);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                             const double* cst, const double* gk, const double* h, double* logD,
+                             double* part, double* part_obj, unsigned* part_flags, int num_cus,
+                             int* grid_out) {
+  const FastCfg* c = pick_cfg(K);
+  if (!c) return hipErrorInvalidValue;
+  const bool vec = ((reinterpret_cast<uintptr_t>(u) & 15) == 0) && ((ld & 1) == 0);
+#define BUMBAR_CFG(a, b, cc, d, e)                                                             \
+  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e)                 \
+    return launch_cfg<a, b, cc, d, e>(s, vec, u, ld, K, N, cst, gk, h, logD, part, part_obj,   \
+                                      part_flags, num_cus, grid_out);
+  BUMBAR_CFG(4, 64, 2, 2, 1)
+  BUMBAR_CFG(4, 64, 2, 4, 1)
+  BUMBAR_CFG(4, 64, 2, 8, 1)
+  BUMBAR_CFG(4, 32, 2, 8, 1)
+  BUMBAR_CFG(4, 32, 2, 13, 1)
+  BUMBAR_CFG(4, 32, 2, 16, 0)
+  BUMBAR_CFG(8, 32, 2, 16, 0)
+  BUMBAR_CFG(4, 32, 2, 13, 0)
+  BUMBAR_CFG(8, 32, 2, 7, 1)
+  BUMBAR_CFG(8, 32, 2, 7, 0)
+  BUMBAR_CFG(8, 64, 2, 13, 0)
+  BUMBAR_CFG(4, 64, 2, 8, 0)
+  BUMBAR_CFG(8, 16, 2, 4, 1)
+#undef BUMBAR_CFG
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Robust two-pass sweep (any K; underflow-safe for arbitrarily poor f).
+// ---------------------------------------------------------------------------
+
+// Pass A: exact ln D_n per column (thread per column, coalesced along n).
+__global__ void __launch_bounds__(256)
+    robust_logD_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+                       const double* __restrict__ cst, const double* __restrict__ gk,
+                       double* __restrict__ logD, unsigned* __restrict__ bad_out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned bad = 0;
+  if (n < N) {
+    double m = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+      const double a = cst[k] - u[(int64_t)k * ld + n];
+      if (gk[k] != 0.0) m = fmax(m, a);
+      if (a != a || a == INFINITY) bad |= FLAG_NAN;
+    }
+    double D = 0.0;
+    if (m > -INFINITY && m < INFINITY) {
+      for (int k = 0; k < K; ++k)
+        if (gk[k] != 0.0) D += exp_nonpos(cst[k] - u[(int64_t)k * ld + n] - m);
+      logD[n] = m + log(D);
+    } else {
+      logD[n] = m;
+      bad |= FLAG_COL;
+    }
+  }
+  if (bad) atomicOr(bad_out, bad);
+}
+
+// Pass B: per-state online log-sum-exp of t_kn = ln h_n - u_kn - ln D_n over a
+// chunk of columns; writes (M, S) with sum_{n in chunk} exp(t_kn) = S e^M, and
+// the chunk's objective partial sum_n h_n ln D_n.
+constexpr int kRobustThreads = 256;
+constexpr int kRobustPerThread = 16;
+constexpr int64_t kRobustChunk = (int64_t)kRobustThreads * kRobustPerThread;
+
+int robust_chunks(int64_t N) { return (int)((N + kRobustChunk - 1) / kRobustChunk); }
+
+__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
+  if (m2 == -INFINITY) return;
+  if (m == -INFINITY) {
+    m = m2;
+    s = s2;
+    return;
+  }
+  if (m2 > m) {
+    s = s * exp_nonpos(m - m2) + s2;
+    m = m2;
+  } else {
+    s = s + s2 * exp_nonpos(m2 - m);
+  }
+}
+
+__global__ void __launch_bounds__(kRobustThreads)
+    robust_state_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+                        const double* __restrict__ h, const double* __restrict__ logD,
+                        double* __restrict__ partM, double* __restrict__ partS,
+                        double* __restrict__ part_obj) {
+  __shared__ double sm[kRobustThreads];
+  __shared__ double ss[kRobustThreads];
+  const int64_t base = (int64_t)blockIdx.x * kRobustChunk;
+  const int tid = threadIdx.x;
+  double lD[kRobustPerThread], lh[kRobustPerThread];
+  double obj = 0.0;
+#pragma unroll
+  for (int i = 0; i < kRobustPerThread; ++i) {
+    const int64_t n = base + tid + (int64_t)i * kRobustThreads;
+    if (n < N) {
+      lD[i] = logD[n];
+      const double hn = h ? h[n] : 1.0;
+      lh[i] = log(hn);
+      obj += hn * lD[i];
+    } else {
+      lD[i] = INFINITY;
+      lh[i] = -INFINITY;
+    }
+  }
+  for (int k = 0; k < K; ++k) {
+    double m = -INFINITY, s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRobustPerThread; ++i) {
+      const int64_t n = base + tid + (int64_t)i * kRobustThreads;
+      if (n < N) {
+        const double t = lh[i] - u[(int64_t)k * ld + n] - lD[i];
+        lse_merge(m, s, t, 1.0);
+      }
+    }
+    sm[tid] = m;
+    ss[tid] = s;
+    __syncthreads();
+    for (int w = kRobustThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        double m1 = sm[tid], s1 = ss[tid];
+        lse_merge(m1, s1, sm[tid + w], ss[tid + w]);
+        sm[tid] = m1;
+        ss[tid] = s1;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      partM[(int64_t)blockIdx.x * K + k] = sm[0];
+      partS[(int64_t)blockIdx.x * K + k] = ss[0];
+    }
+    __syncthreads();
+  }
+  sm[tid] = obj;
+  __syncthreads();
+  for (int w = kRobustThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) part_obj[blockIdx.x] = sm[0];
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_sweep_robust(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                               const double* cst, const double* gk, const double* h,
+                               double* logD, double* partM, double* partS, double* part_obj,
+                               unsigned* part_flags, int chunks) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((chunks + 255) / 256), dim3(256), 0, s, part_flags,
+                     chunks);
+  const int64_t nb = (N + 255) / 256;
+  hipLaunchKernelGGL(robust_logD_kernel, dim3((unsigned)nb), dim3(256), 0, s, u, ld, K, N, cst,
+                     gk, logD, part_flags);
+  hipLaunchKernelGGL(robust_state_kernel, dim3(chunks), dim3(kRobustThreads), 0, s, u, ld, K, N,
+                     h, logD, partM, partS, part_obj);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Finaliser: merges the workgroup partials in a fixed order (one thread per
+// state) and computes f_new, ln S, the gradient norm, Eq. (2) and flags.
+// ---------------------------------------------------------------------------
+constexpr int kFinThreads = 1024;
+
+__device__ __forceinline__ double block_reduce_max(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] = fmax(sh[tid], sh[tid + w]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_reduce_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+    sweep_finalize_kernel(int mode, int K, int nparts, const double* __restrict__ part,
+                          const double* __restrict__ partS, const double* __restrict__ part_obj,
+                          const unsigned* __restrict__ part_flags, const double* __restrict__ f,
+                          const double* __restrict__ lnNp, const int64_t* __restrict__ Nk,
+                          double* __restrict__ f_new, double* __restrict__ lnS_out,
+                          double* __restrict__ S_out, SweepScalars* __restrict__ out) {
+  __shared__ double sh[kFinThreads];
+  __shared__ double f0s;
+  __shared__ unsigned flags_sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) flags_sh = 0u;
+  __syncthreads();
+  unsigned fl = 0u;
+  for (int i = tid; i < nparts; i += kFinThreads) fl |= part_flags[i];
+  double gsq = 0.0, minS = INFINITY;
+  // Fast-path partials: T lanes per state (T a power of two, consecutive
+  // lanes of one wave) each add every T-th partial, then a fixed xor
+  // butterfly combines them, so the order of additions never changes.
+  int T = 1;
+  if (mode == 0)
+    while (T < 64 && 2 * T * K <= kFinThreads) T *= 2;
+  const int kstride = kFinThreads / T;
+  const int kfirst = tid / T, lane_c = tid % T;
+  for (int k0 = 0; k0 < K; k0 += kstride) {
+    const int k = k0 + kfirst;
+    double Sp = 0.0;
+    if (mode == 0 && k < K)
+      for (int p = lane_c; p < nparts; p += T) Sp += part[(int64_t)p * K + k];
+    if (mode == 0)
+      for (int off = 1; off < T; off <<= 1) Sp += __shfl_xor(Sp, off, 64);
+    if (k >= K || lane_c != 0) continue;
+    double lnS, fn, S;
+    if (mode == 0) {
+      S = Sp;
+      lnS = log(S);
+      fn = lnNp[k] + f[k] - lnS;
+      if (!(S >= 1e-290 && S <= 1e290)) fl |= FLAG_STATE;
+    } else {
+      double M = -INFINITY, Ssum = 0.0;
+      for (int p = 0; p < nparts; ++p) lse_merge(M, Ssum, part[(int64_t)p * K + k],
+                                                 partS[(int64_t)p * K + k]);
+      const double lse = M + log(Ssum);  // ln sum_n h_n exp(-u_kn - ln D_n)
+      fn = -lse;
+      lnS = lnNp[k] + f[k] + lse;
+      S = exp(lnS);
+      if (!(lse > -INFINITY && lse < INFINITY)) fl |= FLAG_STATE;
+    }
+    if (lnS_out) lnS_out[k] = lnS;
+    if (S_out) S_out[k] = S;
+    f_new[k] = fn;
+    if (Nk[k] > 0) {
+      const double g = S - (double)Nk[k];
+      gsq += g * g;
+      minS = fmin(minS, S);
+    }
+    if (fn != fn) fl |= FLAG_NAN;
+  }
+  if (fl) atomicOr(&flags_sh, fl);
+  __syncthreads();
+  if (tid == 0) f0s = f_new[0];
+  __syncthreads();
+  const double f0 = f0s;
+  double mdf = 0.0, rs = 0.0, nf = 0.0;
+  for (int k = tid; k < K; k += kFinThreads) {
+    const double fn = f_new[k] - f0;
+    f_new[k] = fn;
+    double df = fabs(fn - f[k]);
+    if (df != df) df = INFINITY;
+    mdf = fmax(mdf, df);
+    if (k >= 1) {
+      double r;
+      if (f[k] != 0.0)
+        r = fabs(fn / f[k] - 1.0);
+      else
+        r = (fn == 0.0) ? 0.0 : INFINITY;
+      if (r != r) r = INFINITY;
+      rs = fmax(rs, r);
+    }
+    nf = __builtin_fma(-(double)Nk[k], f[k], nf);
+  }
+  mdf = block_reduce_max(mdf, sh);
+  rs = block_reduce_max(rs, sh);
+  gsq = block_reduce_sum(gsq, sh);
+  minS = -block_reduce_max(-minS, sh);
+  nf = block_reduce_sum(nf, sh);
+  double ob = 0.0;
+  for (int p = tid; p < nparts; p += kFinThreads) ob += part_obj[p];
+  ob = block_reduce_sum(ob, sh);
+  if (tid == 0) {
+    out->max_df = mdf;
+    out->rel_step = rs;
+    out->objective = ob + nf;
+    out->grad_norm = sqrt(gsq);
+    out->min_S = minS;
+    out->flags = flags_sh;
+    out->pad = 0u;
+  }
+}
+
+hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, const double* part,
+                                 const double* partS, const double* part_obj,
+                                 const unsigned* part_flags, const double* f, const double* lnNp,
+                                 const int64_t* Nk, double* f_new, double* lnS, double* S_out,
+                                 SweepScalars* out) {
+  hipLaunchKernelGGL(sweep_finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, mode, K, nparts,
+                     part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels.
+// ---------------------------------------------------------------------------
+__global__ void prepare_consts_kernel(int K, const int64_t* __restrict__ Nk,
+                                      const double* __restrict__ f, double* __restrict__ cst,
+                                      double* __restrict__ gk, double* __restrict__ lnNp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) {
+    const double l = Nk[k] > 0 ? log((double)Nk[k]) : 0.0;
+    lnNp[k] = l;
+    cst[k] = l + f[k];
+    gk[k] = Nk[k] > 0 ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_prepare_consts(hipStream_t s, int K, const int64_t* Nk, const double* f,
+                                 double* cst, double* gk, double* lnNp) {
+  hipLaunchKernelGGL(prepare_consts_kernel, dim3((K + 255) / 256), dim3(256), 0, s, K, Nk, f, cst,
+                     gk, lnNp);
+  return hipGetLastError();
+}
+
+__global__ void axpy_to_kernel(int K, const double* f, double alpha, const double* d, double* o) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) o[k] = __builtin_fma(alpha, d[k], f[k]);
+}
+
+hipError_t launch_axpy_to(hipStream_t s, int K, const double* f, double alpha, const double* d,
+                          double* out) {
+  hipLaunchKernelGGL(axpy_to_kernel, dim3((K + 255) / 256), dim3(256), 0, s, K, f, alpha, d, out);
+  return hipGetLastError();
+}
+
+// Unsampled states: f_k <- f_k - ln S_k (= -ln sum_n exp(-u_kn - ln D_n), since
+// ln N'_k = 0 for them), then the gauge f <- f - f_0. One block.
+__global__ void __launch_bounds__(1024)
+    fill_unsampled_gauge_kernel(int K, const int64_t* __restrict__ Nk, double* __restrict__ f,
+                                const double* __restrict__ lnS) {
+  __shared__ double f0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    if (Nk[k] <= 0) f[k] = f[k] - lnS[k];
+  __syncthreads();
+  if (threadIdx.x == 0) f0 = f[0];
+  __syncthreads();
+  const double g = f0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) f[k] -= g;
+}
+
+hipError_t launch_fill_unsampled_gauge(hipStream_t s, int K, const int64_t* Nk, double* f,
+                                       const double* lnS) {
+  hipLaunchKernelGGL(fill_unsampled_gauge_kernel, dim3(1), dim3(1024), 0, s, K, Nk, f, lnS);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(1024)
+    max_abs_diff_kernel(int K, const double* a, const double* b, double* out) {
+  __shared__ double sh[1024];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < K; k += 1024) {
+    double d = fabs(a[k] - b[k]);
+    if (d != d) d = INFINITY;
+    m = fmax(m, d);
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+hipError_t launch_max_abs_diff(hipStream_t s, int K, const double* a, const double* b,
+                               double* out) {
+  hipLaunchKernelGGL(max_abs_diff_kernel, dim3(1), dim3(1024), 0, s, K, a, b, out);
+  return hipGetLastError();
+}
+
+// W_nk = exp(f_k - u_kn - ln D_n), N x K output; 32 x 32 tiles transposed
+// through shared memory so both the read of u (along n) and the write of W
+// (along k) are coalesced.
+__global__ void __launch_bounds__(256)
+    weights_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+                   const double* __restrict__ f, const double* __restrict__ logD,
+                   double* __restrict__ W) {
+  __shared__ double tile[32][33];
+  const int64_t n0 = (int64_t)blockIdx.x * 32;
+  const int k0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r;
+    const int64_t n = n0 + tx;
+    double v = 0.0;
+    if (k < K && n < N) {
+      const double x = f[k] - u[(int64_t)k * ld + n] - logD[n];
+      v = exp(x);
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t n = n0 + r;
+    const int k = k0 + tx;
+    if (k < K && n < N) W[n * K + k] = tile[tx][r];
+  }
+}
+
+hipError_t launch_weights(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                          const double* f, const double* logD, double* W) {
+  dim3 grid((unsigned)((N + 31) / 32), (unsigned)((K + 31) / 32));
+  hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, s, u, ld, K, N, f, logD, W);
+  return hipGetLastError();
+}
+
+// Reweighting (Eqs. (5)-(6)): p_n = exp(t_n - M) / sum_m exp(t_m - M),
+// t_n = -u_target_n - ln D_n. Three launches: block maxima, one block
+// merging (M, S) in a fixed order, then the normalised write.
+__global__ void __launch_bounds__(256)
+    rw_partial_kernel(int64_t N, const double* __restrict__ ut, const double* __restrict__ logD,
+                      double* __restrict__ part) {
+  __shared__ double sm[256], ss[256];
+  double m = -INFINITY, s = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < N; n += (int64_t)gridDim.x * 256)
+    lse_merge(m, s, -ut[n] - logD[n], 1.0);
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      double m1 = sm[threadIdx.x], s1 = ss[threadIdx.x];
+      lse_merge(m1, s1, sm[threadIdx.x + w], ss[threadIdx.x + w]);
+      sm[threadIdx.x] = m1;
+      ss[threadIdx.x] = s1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sm[0];
+    part[2 * blockIdx.x + 1] = ss[0];
+  }
+}
+
+__global__ void rw_merge_kernel(int nparts, double* part) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double m = -INFINITY, s = 0.0;
+    for (int p = 0; p < nparts; ++p) lse_merge(m, s, part[2 * p], part[2 * p + 1]);
+    part[2 * nparts] = m + log(s);
+  }
+}
+
+__global__ void rw_write_kernel(int64_t N, const double* __restrict__ ut,
+                                const double* __restrict__ logD, const double* __restrict__ lse,
+                                double* __restrict__ p) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < N) p[n] = exp(-ut[n] - logD[n] - *lse);
+}
+
+hipError_t launch_reweight(hipStream_t s, int64_t N, const double* ut, const double* logD,
+                           double* part, int nparts, double* p) {
+  hipLaunchKernelGGL(rw_partial_kernel, dim3(nparts), dim3(256), 0, s, N, ut, logD, part);
+  hipLaunchKernelGGL(rw_merge_kernel, dim3(1), dim3(64), 0, s, nparts, part);
+  hipLaunchKernelGGL(rw_write_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, ut,
+                     logD, part + 2 * nparts, p);
+  return hipGetLastError();
+}
+
+__global__ void check_finite_kernel(int K, const double* f, unsigned* flag) {
+  unsigned bad = 0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    if (!(f[k] > -INFINITY && f[k] < INFINITY)) bad = 1;
+  if (bad) atomicOr(flag, 1u);
+}
+
+hipError_t launch_check_finite_f(hipStream_t s, int K, const double* f, unsigned* flag) {
+  hipLaunchKernelGGL(check_finite_kernel, dim3(1), dim3(256), 0, s, K, f, flag);
+  return hipGetLastError();
+}
+
+}  // namespace bumbar

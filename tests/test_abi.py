@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every symbol include/bumbar.h declares.
+
+No compute call is made (these run without a GPU).
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "bumbar.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bumbar_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_03541_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        pytest.fail("libbumbar.so is not built (run __graft_entry__.build())")
+    return _capi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_2609_03541_amd import _capi
+    assert set(declared_functions()) == set(_capi.SIGNATURES)
+
+
+def test_default_options_are_the_papers_settings(lib):
+    from paper_2609_03541_amd import _capi
+    o = _capi.Options()
+    lib.bumbar_default_options(C.byref(o))
+    # n0 = 100, eps = 1e-3, inc = 10, N_intermediate = 20 (Section 2, after Algorithm 1)
+    assert (o.n0, o.eps, o.inc, o.n_intermediate) == (100, 1e-3, 10, 20)
+    assert o.tol > 0 and o.finisher == _capi.FINISH_NEWTON
+
+
+def test_version_and_null_context(lib):
+    assert lib.bumbar_version().decode().startswith("bumbar")
+    assert lib.bumbar_last_error(None) == b""
+    assert lib.bumbar_create(None, 0, None) == -1
+    nb = C.c_size_t()
+    assert lib.bumbar_query_workspace(None, 4, 10, 0, None, C.byref(nb)) == -1
+
+
+def test_struct_layouts_match_header():
+    # field order of the ctypes mirrors follows the header text
+    from paper_2609_03541_amd import _capi
+    text = open(os.path.join(ROOT, "include", "bumbar.h")).read()
+    for struct, cls in [("bumbar_options", _capi.Options), ("bumbar_stats", _capi.Stats),
+                        ("bumbar_check", _capi.Check)]:
+        m = re.search(r"typedef struct \{((?:(?!typedef).)*?)\}\s*" + struct + ";", text,
+                      flags=re.S)
+        body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
+        fields = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*;", body)
+        assert fields == [f for f, _ in cls._fields_], struct

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances: FP64 single steps agree to 1e-12 (absolute, kT) or 1e-12
+relative; full solves to 1e-9 kT (the FP64 target); bins, counts, widths and
+bin maps are integers and must be identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    import paper_2609_03541_amd as bm
+    return bm
+
+
+def dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def random_problem(K, N, seed, unsampled=()):
+    g = np.random.default_rng(seed)
+    Nk = np.zeros(K, dtype=np.int64)
+    sampled = [k for k in range(K) if k not in unsampled]
+    base = N // len(sampled)
+    for k in sampled:
+        Nk[k] = base
+    Nk[sampled[0]] += N - Nk.sum()
+    centres = g.uniform(-2, 2, K)
+    kappa = g.uniform(0.5, 4, K)
+    owner = np.repeat(np.arange(K), Nk)
+    x = g.normal(centres[owner], 1 / np.sqrt(kappa[owner]))
+    u = 0.5 * kappa[:, None] * (x[None, :] - centres[:, None]) ** 2
+    return u, Nk, x
+
+
+SHAPES = [(1, 37), (2, 129), (3, 1000), (8, 8000), (13, 515), (64, 3001), (65, 2047),
+          (100, 12345), (128, 4097), (200, 2500), (256, 1111), (300, 1500), (1000, 700)]
+
+
+@pytest.mark.parametrize("K,N", SHAPES)
+def test_single_sweep_matches_oracle(bm, K, N):
+    say(f"sweep parity K={K} N={N}")
+    u, Nk, _ = random_problem(K, N, seed=K * 7 + N)
+    g = np.random.default_rng(1)
+    f = np.concatenate([[0.0], g.normal(0, 0.3, K - 1)])
+    fn_ref, lD_ref = oracle.sci_step(u, Nk, f, return_logD=True)
+    fn, lD, S, st = bm.sweep(dev(u), Nk, f)
+    fn, lD, S = fn.cpu().numpy(), lD.cpu().numpy(), S.cpu().numpy()
+    assert np.max(np.abs(lD - lD_ref)) < 1e-12 * max(1.0, np.abs(lD_ref).max())
+    assert np.max(np.abs(fn - fn_ref)) < 1e-12
+    # S_i = N_i sum_n W_ni and the gradient norm
+    W = oracle.weights(u, Nk, f)
+    S_ref = Nk * W.sum(axis=0)
+    samp = Nk > 0
+    assert np.max(np.abs(S[samp] - S_ref[samp]) / S_ref[samp]) < 1e-12
+    F_ref, g_ref = oracle.objective_gradient(u, Nk, f)
+    assert abs(st["objective"] - F_ref) < 1e-10 * max(1.0, abs(F_ref))
+    assert abs(st["grad_norm"] - np.linalg.norm(g_ref)) < 1e-9 * max(1.0, np.linalg.norm(g_ref))
+    assert st["max_df"] == pytest.approx(np.max(np.abs(fn_ref - f)), rel=1e-9, abs=1e-13)
+
+
+def test_sweep_with_padded_rows_and_unsampled_state(bm):
+    import torch
+    K, N = 6, 1001
+    u, Nk, _ = random_problem(K, N, seed=3, unsampled=(2,))
+    f = np.array([0.0, 0.4, 1.0, -0.3, 0.2, 0.1])
+    fn_ref = oracle.sci_step(u, Nk, f)
+    ld = 1040
+    buf = torch.full((K, ld), float("nan"), dtype=torch.float64, device="cuda")
+    buf[:, :N] = dev(u)
+    fn, lD, S, st = bm.sweep(buf, Nk, f, ld=ld) if False else bm.sweep(buf[:, :N], Nk, f, ld=ld)
+    assert np.max(np.abs(fn.cpu().numpy() - fn_ref)) < 1e-12
+
+
+def test_robust_path_far_from_solution(bm):
+    # a starting point 900 kT off makes some state sums underflow in double:
+    # the fast path must flag it and the robust path give the oracle's step
+    u, Nk, _ = random_problem(5, 2000, seed=4)
+    f = np.array([0.0, 900.0, -5.0, 3.0, 0.0])
+    fn_ref = oracle.sci_step(u, Nk, f)
+    fn, lD, S, st = bm.sweep(dev(u), Nk, f)
+    assert np.max(np.abs(fn.cpu().numpy() - fn_ref)) < 1e-9
+
+
+@pytest.mark.parametrize("K,N", [(3, 500), (8, 4000), (64, 999), (100, 3000), (130, 777)])
+def test_hessian_matches_oracle(bm, K, N):
+    say(f"hessian parity K={K} N={N}")
+    u, Nk, _ = random_problem(K, N, seed=K + N)
+    f = np.concatenate([[0.0], np.random.default_rng(2).normal(0, 0.2, K - 1)])
+    H_ref = oracle.hessian(u, Nk, f)
+    ud = dev(u)
+    fn, lD, S, _ = bm.sweep(ud, Nk, f)
+    H = bm.hessian(ud, Nk, f, lD, S).cpu().numpy()
+    scale = np.abs(H_ref).max()
+    assert np.max(np.abs(H - H_ref)) < 1e-12 * scale
+
+
+def test_weights_match_oracle(bm):
+    u, Nk, _ = random_problem(7, 1234, seed=9, unsampled=(3,))
+    f = np.array([0.0, 0.1, 0.5, 2.0, -0.2, 0.3, 0.0])
+    W_ref = oracle.weights(u, Nk, f)
+    ud = dev(u)
+    _, lD, _, _ = bm.sweep(ud, Nk, f)
+    W = bm.weights(ud, f, lD).cpu().numpy()
+    assert np.max(np.abs(W - W_ref)) < 1e-13
+
+
+@pytest.mark.parametrize("cfg", ["harmonic", "double_well", "unsampled"])
+def test_plain_solve_matches_oracle(bm, cfg):
+    say(f"plain solve parity {cfg}")
+    if cfg == "harmonic":
+        p = synth.harmonic_1d(K=8, Nk=1000, seed=0)
+        u, Nk = p["u"], p["Nk"]
+    elif cfg == "double_well":
+        p = synth.double_well(K=40, Nk=500, seed=2)
+        u, Nk = p["u"], p["Nk"]
+    else:
+        u, Nk, _ = random_problem(9, 3000, seed=5, unsampled=(0, 4))
+    f_ref, info_ref = oracle.solve_mbar(u, Nk)
+    f, info = bm.solve(dev(u), Nk, tol=1e-12)
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+    assert info["grad_norm"] < 1e-6
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_binning_bit_exact(bm, d):
+    g = np.random.default_rng(30 + d)
+    N = 20011
+    xi = g.normal(0, 1, size=(N, d))
+    xi[:300] = xi[300:600]  # duplicate points
+    xi[600:700, 0] = xi[700, 0]  # ties along one axis
+    q, lo, sc = oracle.quantize(xi)
+    for n in [2, 100, 1000, 10000, 30000]:
+        say(f"binning d={d} n={n}")
+        m_ref, g_ref, _ = oracle.width_search(q, n)
+        cells_ref, H_ref, sb_ref = oracle.histogram(q, m_ref)
+        m, cells, H, sb = bm.bin_coordinates(xi, n)
+        assert m == m_ref
+        assert np.array_equal(cells.cpu().numpy().view(np.uint64), cells_ref)
+        assert np.array_equal(H.cpu().numpy(), H_ref)
+        assert np.array_equal(sb.cpu().numpy(), sb_ref)
+
+
+def test_bumbar_solve_matches_oracle_1d(bm):
+    p = synth.double_well(K=30, Nk=700, seed=5)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    fo, info_o = oracle.bumbar(p["u"], p["Nk"], p["xi"], p["model_type"], p["coef"], tol=1e-11)
+    f, info = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       tol=1e-11)
+    assert info["status"] == 0
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+    say("schedule gpu", info["phase1_iters"], [c["refine"] for c in info["checks"]],
+        "oracle", info_o["phase1"], [c["refine"] for c in info_o["checks"]])
+    # replaying the oracle's schedule gives the oracle's binned trajectory
+    flags = [c["refine"] for c in info_o["checks"]]
+    f2, info2 = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                         tol=1e-11, replay=(info_o["phase1"], flags))
+    gc = info2["checks"]
+    oc = info_o["checks"]
+    assert [c["P"] for c in gc] == [c["P"] for c in oc]
+    assert [c["P_next"] for c in gc] == [c["P_next"] for c in oc]
+    for a, b in zip(gc, oc):
+        assert abs(a["s_n"] - b["s_n"]) <= 1e-9 * abs(b["s_n"]) + 1e-15
+        assert abs(a["s_next"] - b["s_next"]) <= 1e-9 * abs(b["s_next"]) + 1e-15
+
+
+def test_bumbar_solve_mean_representatives_2d(bm):
+    p = synth.ladder_2d(K=12, Nk=300, seed=1)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=bm.MODEL_NONE, tol=1e-11)
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+    f2, info2 = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                         tol=1e-11)
+    assert np.max(np.abs(f2.cpu().numpy() - f_ref)) < 1e-9
+
+
+def test_reweight_matches_oracle(bm):
+    p = synth.harmonic_1d(K=4, Nk=300, seed=6)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    lD_ref = oracle.log_denominator(p["u"], p["Nk"], f_ref)
+    f, info = bm.solve(dev(p["u"]), p["Nk"], tol=1e-12, want_logD=True)
+    ut = 0.5 * 2.0 * (p["xi"][:, 0] - 0.3) ** 2
+    pr = bm.reweight(dev(ut), info["logD"]).cpu().numpy()
+    assert np.max(np.abs(pr - oracle.reweight(ut, lD_ref))) < 1e-12 * max(1, pr.max())
+
+
+def test_deterministic_repeat(bm):
+    u, Nk, _ = random_problem(100, 50000, seed=11)
+    f = np.zeros(100)
+    a = bm.sweep(dev(u), Nk, f)[0].cpu().numpy()
+    b = bm.sweep(dev(u), Nk, f)[0].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_invalid_inputs_raise(bm):
+    u, Nk, _ = random_problem(4, 100, seed=1)
+    with pytest.raises(bm.BumbarError):
+        bm.solve(dev(u), Nk + 1)  # sum N_k != N
+    bad = u.copy()
+    bad[1, 5] = np.nan
+    with pytest.raises(bm.BumbarError):
+        bm.solve(dev(bad), Nk)
