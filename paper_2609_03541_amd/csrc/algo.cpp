@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <utility>
+#include <vector>
 
 #include "bumbar_impl.h"
 #include "solver_internal.h"
@@ -175,27 +176,72 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   if (rc) return rc;
   t_bin += now_ms() - t0;
 
-  // three K-vectors rotate as the current f, SCI(f, n) and SCI(f, n * inc)
-  double* slot[3] = {B.f, BB.f_n, BB.f_x};
-  int ia = 0;
-  SweepScalars sc{};
+  // The current f lives in BB.f_n. Steps are queued in batches whose iterates
+  // go to B.f_hist and whose scalars go to B.scal_hist; one readback per
+  // batch. The decisions use exactly the per-step values, so the trajectory
+  // is the same as with a readback after every step; a flagged step (far-off
+  // f, see the sweep) is redone on the robust path before anything else.
+  hipError_t e = hipMemcpyAsync(BB.f_n, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
+  const bool fast = sweep_fast_supported(K);
+  std::vector<SweepScalars> hs(kHistSteps);
+  auto fh = [&](int i) { return B.f_hist + (size_t)i * K; };
+  auto set_current = [&](const double* src) -> int {
+    hipError_t e2 = hipMemcpyAsync(BB.f_n, src, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+    return e2 == hipSuccess ? BUMBAR_OK : hip_fail(ctx, e2, "copy f");
+  };
+  auto read_hist = [&](int T) -> int {
+    return read_bytes(ctx, B.scal_hist, hs.data(), sizeof(SweepScalars) * T);
+  };
+  auto flagged = [&](const SweepScalars& x) {
+    return (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
+  };
+  // one step on the robust-capable path, result in fh(slot)
+  auto safe_step = [&](const Level& L, const double* fin, int slot, SweepScalars* sc) -> int {
+    return sweep_at(ctx, B, L.ubar, L.P, L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl, B.lnS_t,
+                    B.S_t, sc, false, nullptr);
+  };
   int64_t it1 = 0, it2 = 0, nchk = 0;
   int result = BUMBAR_OK;
-  // phase 1
-  for (;;) {
+  // ---- phase 1: iterate at n0 until the relative step is below eps ----
+  for (bool done = false; !done;) {
     if (it1 + it2 >= opt.max_iter) {
       result = BUMBAR_ENOTCONV;
       break;
     }
-    const int ib = (ia + 1) % 3;
-    rc = binned_sci(ctx, B, BB, cur, Nk_dev, slot[ia], slot[ib], &sc, cnt);
+    int64_t T = std::min<int64_t>(kHistSteps, opt.max_iter - it1 - it2);
+    if (opt.replay_refine) T = std::min<int64_t>(T, std::max<int64_t>(1, opt.replay_phase1 - it1));
+    int nvalid = 0;  // leading steps that are usable
+    if (fast) {
+      for (int i = 0; i < T; ++i) {
+        rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev, i == 0 ? BB.f_n : fh(i - 1),
+                         fh(i), BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + i);
+        if (rc) return rc;
+      }
+      rc = read_hist((int)T);
+      if (rc) return rc;
+      while (nvalid < T && !flagged(hs[nvalid])) ++nvalid;
+    }
+    if (nvalid == 0) {  // first step flagged (or no fast path): one robust-capable step
+      rc = safe_step(cur, BB.f_n, 0, &hs[0]);
+      if (rc) return rc;
+      nvalid = 1;
+    }
+    int used = nvalid;
+    for (int i = 0; i < nvalid; ++i) {
+      const int64_t n_it = it1 + i + 1;
+      const bool stop = opt.replay_refine ? (n_it >= opt.replay_phase1) : (hs[i].rel_step < opt.eps);
+      if (stop) {
+        used = i + 1;
+        done = true;
+        break;
+      }
+    }
+    it1 += used;
+    rc = set_current(fh(used - 1));
     if (rc) return rc;
-    ia = ib;
-    ++it1;
-    const bool done = opt.replay_refine ? (it1 >= opt.replay_phase1) : (sc.rel_step < opt.eps);
-    if (done) break;
   }
-  // phase 2
+  // ---- phase 2 ----
   if (result == BUMBAR_OK) {
     n = n * opt.inc;
     t0 = now_ms();
@@ -204,24 +250,77 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     rc = build_level(ctx, BB, K, n * opt.inc, model, coef, u, 1 - cur_slot, &nxt);
     if (rc) return rc;
     t_bin += now_ms() - t0;
+    const int nint = opt.n_intermediate;
     for (;;) {
-      if (it1 + it2 + opt.n_intermediate + 2 > opt.max_iter) {
+      if (it1 + it2 + nint + 2 > opt.max_iter) {
         result = BUMBAR_ENOTCONV;
         break;
       }
-      for (int i = 0; i < opt.n_intermediate; ++i) {
-        const int ib = (ia + 1) % 3;
-        rc = binned_sci(ctx, B, BB, cur, Nk_dev, slot[ia], slot[ib], &sc, cnt);
+      // intermediate steps, in batches that leave room for the two probes
+      int done_int = 0;
+      bool fallback = false;
+      while (!fallback && nint - done_int > kHistSteps - 2) {
+        const int T = kHistSteps - 2;
+        for (int i = 0; i < T && fast; ++i) {
+          rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev,
+                           i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
+                           B.scal_hist + i);
+          if (rc) return rc;
+        }
+        if (!fast) {
+          fallback = true;
+          break;
+        }
+        rc = read_hist(T);
         if (rc) return rc;
-        ia = ib;
+        for (int i = 0; i < T; ++i) fallback = fallback || flagged(hs[i]);
+        if (fallback) break;
+        rc = set_current(fh(T - 1));
+        if (rc) return rc;
+        done_int += T;
       }
-      const int in = (ia + 1) % 3, ix = (ia + 2) % 3;
       SweepScalars sn{}, sx{};
-      rc = binned_sci(ctx, B, BB, cur, Nk_dev, slot[ia], slot[in], &sn, cnt);
-      if (rc) return rc;
-      rc = binned_sci(ctx, B, BB, nxt, Nk_dev, slot[ia], slot[ix], &sx, cnt);
-      if (rc) return rc;
-      it2 += opt.n_intermediate + 2;
+      int in = 0, ix = 0;
+      if (!fallback && fast) {
+        const int T = nint - done_int;
+        for (int i = 0; i < T; ++i) {
+          rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev,
+                           i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
+                           B.scal_hist + i);
+          if (rc) return rc;
+        }
+        const double* fin = T == 0 ? BB.f_n : fh(T - 1);
+        in = T;
+        ix = T + 1;
+        rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev, fin, fh(in), BB.logD_lvl,
+                         B.lnS_t, B.S_t, B.scal_hist + in);
+        if (rc) return rc;
+        rc = sweep_queue(ctx, B, nxt.ubar, nxt.P, nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
+                         B.lnS_t, B.S_t, B.scal_hist + ix);
+        if (rc) return rc;
+        rc = read_hist(T + 2);
+        if (rc) return rc;
+        for (int i = 0; i < T + 2; ++i) fallback = fallback || flagged(hs[i]);
+        sn = hs[in];
+        sx = hs[ix];
+      }
+      if (fallback || !fast) {
+        // redo the remaining intermediate steps and both probes one by one from
+        // the current f (robust path where a step needs it)
+        for (int i = done_int; i < nint; ++i) {
+          rc = safe_step(cur, BB.f_n, 0, nullptr);
+          if (rc) return rc;
+          rc = set_current(fh(0));
+          if (rc) return rc;
+        }
+        in = 0;
+        ix = 1;
+        rc = safe_step(cur, BB.f_n, in, &sn);
+        if (rc) return rc;
+        rc = safe_step(nxt, BB.f_n, ix, &sx);
+        if (rc) return rc;
+      }
+      it2 += nint + 2;
       int refine;
       if (opt.replay_refine)
         refine = (nchk < opt.n_replay) ? (opt.replay_refine[nchk] != 0) : 0;
@@ -235,7 +334,8 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       rec.s_n = sn.rel_step;
       rec.s_next = sx.rel_step;
       rec.refine = refine;
-      ia = refine ? ix : in;
+      rc = set_current(refine ? fh(ix) : fh(in));
+      if (rc) return rc;
       if (refine) {
         n = n * opt.inc;
         if (2 * opt.inc * n > N) stop = 1;
@@ -255,10 +355,8 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       }
     }
   }
-  if (slot[ia] != B.f) {
-    hipError_t e = hipMemcpyAsync(B.f, slot[ia], sizeof(double) * K, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
-  }
+  e = hipMemcpyAsync(B.f, BB.f_n, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
   st->phase1_iters = it1;
   st->phase2_iters = it2;
   st->n_checks = nchk;

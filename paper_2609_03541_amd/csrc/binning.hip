@@ -61,18 +61,31 @@ __global__ void __launch_bounds__(kBT)
   }
 }
 
-__global__ void minmax_final_kernel(int nparts, int d, const double* __restrict__ part,
-                                    double* __restrict__ mm) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    for (int j = 0; j < d; ++j) {
-      double a = INFINITY, b = -INFINITY;
-      for (int p = 0; p < nparts; ++p) {
-        a = fmin(a, part[(p * 2 + 0) * 2 + j]);
-        b = fmax(b, part[(p * 2 + 1) * 2 + j]);
-      }
-      mm[2 * j] = a;
-      mm[2 * j + 1] = b;
+__global__ void __launch_bounds__(kBT)
+    minmax_final_kernel(int nparts, int d, const double* __restrict__ part,
+                        double* __restrict__ mm) {
+  __shared__ double smin[kBT], smax[kBT];
+  for (int j = 0; j < d; ++j) {
+    double a = INFINITY, b = -INFINITY;
+    for (int p = threadIdx.x; p < nparts; p += kBT) {
+      a = fmin(a, part[(p * 2 + 0) * 2 + j]);
+      b = fmax(b, part[(p * 2 + 1) * 2 + j]);
     }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kBT / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      mm[2 * j] = smin[0];
+      mm[2 * j + 1] = smax[0];
+    }
+    __syncthreads();
   }
 }
 
@@ -81,7 +94,7 @@ hipError_t launch_minmax(hipStream_t s, const double* xi, int64_t N, int d, doub
   double* part = reinterpret_cast<double*>(scratch);
   int nb = (int)std::min<int64_t>(kRedBlocks, (N + kBT - 1) / kBT);
   hipLaunchKernelGGL(minmax_partial_kernel, dim3(nb), dim3(kBT), 0, s, xi, N, d, part);
-  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(64), 0, s, nb, d, part, mm);
+  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(kBT), 0, s, nb, d, part, mm);
   return hipGetLastError();
 }
 
@@ -189,12 +202,18 @@ __global__ void __launch_bounds__(kBT)
   if (threadIdx.x == 0) counts[1 + blockIdx.x] = sh[0];
 }
 
-__global__ void sum_counts_kernel(int nb, int64_t* counts) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t t = 0;
-    for (int b = 0; b < nb; ++b) t += counts[1 + b];
-    counts[0] = t;
+// counts[0] = sum of the nb block counts (integer, so the order is irrelevant).
+__global__ void __launch_bounds__(kBT) sum_counts_kernel(int nb, int64_t* counts) {
+  __shared__ int64_t sh[kBT];
+  int64_t t = 0;
+  for (int b = threadIdx.x; b < nb; b += kBT) t += counts[1 + b];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) counts[0] = sh[0];
 }
 
 static int red_blocks(int64_t N) {
@@ -205,7 +224,7 @@ hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, u
                            int64_t* counts) {
   const int nb = red_blocks(N);
   hipLaunchKernelGGL(count_runs_1d_kernel, dim3(nb), dim3(kBT), 0, s, q_sorted, N, m, counts);
-  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(64), 0, s, nb, counts);
+  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(kBT), 0, s, nb, counts);
   return hipGetLastError();
 }
 
@@ -248,7 +267,7 @@ hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t
   if (e != hipSuccess) return e;
   const int nb = red_blocks(N);
   hipLaunchKernelGGL(count_runs_keys_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, counts);
-  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(64), 0, s, nb, counts);
+  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(kBT), 0, s, nb, counts);
   return hipGetLastError();
 }
 

@@ -63,10 +63,12 @@ void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
   part_obj = ar.take<double>(nparts_cap);
   part_flags = ar.take<unsigned>(nparts_cap);
   scal = ar.take<SweepScalars>(2);
+  scal_hist = ar.take<SweepScalars>(kHistSteps);
+  f_hist = ar.take<double>((size_t)kHistSteps * K);
   misc = ar.take<double>(8);
   ok = ar.take<int>(4);
   idx = ar.take<int>(K);
-  A = ar.take<double>((size_t)K * K + K);
+  A = ar.take<double>((size_t)K * K + 3 * (size_t)K);
   H = ar.take<double>((size_t)K * K);
   hess_parts = ar.take<double>(hessian_partial_count(K, N, num_cus, &hess_chunks));
 }
@@ -160,6 +162,26 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld
   if (rc) return rc;
   if (out->flags & FLAG_NAN)
     return fail(ctx, BUMBAR_EINVAL, "non-finite reduced energies (NaN or -inf in u_kn)");
+  return BUMBAR_OK;
+}
+
+// Queue one fast-path sweep without any readback; its scalars go to
+// dev_scal (device). Flags must be checked by the caller after reading the
+// scalars back. Requires sweep_fast_supported(K).
+int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
+                const double* h, const int64_t* Nk, const double* f, double* f_out,
+                double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal) {
+  hipStream_t s = ctx->stream;
+  const int K = B.K;
+  hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
+  if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
+  int grid = 0;
+  e = launch_sweep_fast(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.part_obj, B.part_flags,
+                        ctx->num_cus, &grid);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_fast");
+  e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f, B.lnNp,
+                            Nk, f_out, lnS_out, S_out, dev_scal);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
   return BUMBAR_OK;
 }
 

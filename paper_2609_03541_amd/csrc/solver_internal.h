@@ -15,6 +15,9 @@ double now_ms();
 int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes);
 std::pair<hipEvent_t, hipEvent_t>* next_event_pair(bumbar_ctx* ctx);
 
+// Binned SCI steps queued between two host readbacks.
+constexpr int kHistSteps = 32;
+
 struct SweepCounters {
   int64_t fast = 0;
   int64_t robust = 0;
@@ -32,6 +35,8 @@ struct UnbinnedBufs {
   double *part = nullptr, *partS = nullptr, *part_obj = nullptr;
   unsigned* part_flags = nullptr;
   SweepScalars* scal = nullptr;
+  SweepScalars* scal_hist = nullptr;  // kHistSteps per-step scalars (binned batches)
+  double* f_hist = nullptr;           // kHistSteps x K iterates (binned batches)
   double* misc = nullptr;
   int* ok = nullptr;
   int* idx = nullptr;
@@ -44,6 +49,10 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld
              const double* h, const int64_t* Nk, const double* f, double* f_out,
              double* logD_out, double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
              SweepCounters* cnt);
+
+int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
+                const double* h, const int64_t* Nk, const double* f, double* f_out,
+                double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal);
 
 int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
                   const int64_t* Nk, double tol, int max_steps, bumbar_stats* st,

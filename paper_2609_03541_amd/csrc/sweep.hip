@@ -87,7 +87,7 @@ __device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const double* 
 }
 
 // The three passes over a loaded tile (see the file comment).
-template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED>
+template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED, int SG>
 __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, int64_t N, int lc,
                                              int rg, int wave, int rgw,
                                              const double* __restrict__ c_sh, unsigned smask,
@@ -105,7 +105,7 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
   unsigned sm = smask;
   asm volatile("" : "+v"(rgo), "+v"(sm));
   // ---- pass 1: a = c - u and the column maximum ----
-  double cm[CPL];
+  double cm[CPL], chk = 0.0;
 #pragma unroll
   for (int i = 0; i < CPL; ++i) cm[i] = -INFINITY;
 #pragma unroll
@@ -115,8 +115,10 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
     for (int i = 0; i < CPL; ++i) {
       a[j][i] = c - a[j][i];
       cm[i] = fmax(cm[i], a[j][i]);
+      chk += a[j][i];  // NaN if any u is NaN (or -inf): the max would drop it
     }
   }
+  if (chk != chk) bad |= FLAG_NAN;
 #pragma unroll
   for (int i = 0; i < CPL; ++i) {
 #pragma unroll
@@ -147,8 +149,12 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
         ds[i] += a[j][i];
       }
     }
-    // keep the exponentials of one row together: bounds register pressure
-    __builtin_amdgcn_sched_barrier(0);
+    // schedule the exponentials in groups of SG rows (0: no grouping); a
+    // group boundary bounds register pressure at the cost of fewer
+    // independent chains in flight
+    if constexpr (SG > 0) {
+      if ((j + 1) % SG == 0) __builtin_amdgcn_sched_barrier(0);
+    }
   }
 #pragma unroll
   for (int i = 0; i < CPL; ++i) {
@@ -166,27 +172,45 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
     const int64_t n = col0 + i;
     const bool valid = !TAIL || n < N;
     const double hn = (h != nullptr && valid) ? h[n] : 1.0;
-    w[i] = valid ? hn / D : 0.0;
-    if (valid) {
-      if (!(D >= 1e-300 && D <= 1e300)) bad |= FLAG_COL;
-      if (rg == 0) {
-        const double l = m[i] + log(D);
-        if (logD != nullptr) logD[n] = l;
-        obj = __builtin_fma(hn, l, obj);
-      }
-    }
+    w[i] = valid ? hn * rcp_nr(D) : 0.0;
+    if (valid && !(D >= 1e-300 && D <= 1e300)) bad |= FLAG_COL;
   }
   // ---- pass 3: per-state accumulation of e * h / D' ----
 #pragma unroll
   for (int j = 0; j < ROWS; ++j)
 #pragma unroll
     for (int i = 0; i < CPL; ++i) acc[j] = __builtin_fma(a[j][i], w[i], acc[j]);
+  // the tile values are dead from here on: do the logarithms now
+  __builtin_amdgcn_sched_barrier(0);
+  // ln D_n and the objective (red1 / red2 stay valid until the next tile's
+  // first barrier): wave v handles columns [v * CW, (v + 1) * CW),
+  // one lane each, so every wave evaluates one logarithm per tile.
+  {
+    constexpr int CW = TN / NW;
+    const int lane = threadIdx.x & 63;
+    if (lane < CW) {
+      const int col = wave * CW + lane;
+      double mv = red1[0][col], Dv = red2[0][col];
+#pragma unroll
+      for (int wv = 1; wv < NW; ++wv) {
+        mv = fmax(mv, red1[wv][col]);
+        Dv += red2[wv][col];
+      }
+      if (mv == -INFINITY) mv = 0.0;
+      const int64_t n = t * TN + col;
+      if (!TAIL || n < N) {
+        const double l = mv + log_ge1(Dv);
+        if (logD != nullptr) logD[n] = l;
+        obj = __builtin_fma(h != nullptr ? h[n] : 1.0, l, obj);
+      }
+    }
+  }
 }
 
 // Tile loop over the full tiles of this block; with PF the next tile's loads
 // are issued into a second register buffer before the current tile is
 // processed (software prefetch), so HBM traffic overlaps the arithmetic.
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF>
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG>
 __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64_t rstride,
                                           int rows_here, int64_t nfull, int64_t N, int lc, int rg,
                                           int wave, int rgw, const double* __restrict__ c_sh,
@@ -200,7 +224,7 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
     for (; t < nfull; t += G) {
       double a[ROWS][CPL];
       tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1, red2, acc, obj, bad);
     }
   } else {
@@ -209,19 +233,19 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
     while (t < nfull) {
       const int64_t t1 = t + G;
       if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(b, base, rstride, rows_here, t1, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1, red2, acc, obj, bad);
       if (t1 >= nfull) break;
       const int64_t t2 = t1 + G;
       if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t2, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1, red2, acc, obj, bad);
       t = t2;
     }
   }
 }
 
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF>
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF, int SG>
 __global__ void __launch_bounds__(NW * 64)
     sweep_fast_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
                       int64_t ntiles, const double* __restrict__ cst,
@@ -268,17 +292,17 @@ __global__ void __launch_bounds__(NW * 64)
   unsigned bad = 0;
   const int64_t nfull = N / TN;
   if (!masked)
-    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF>(base, rstride, rows_here, nfull, N, lc, rg, wave,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG>(base, rstride, rows_here, nfull, N, lc, rg, wave,
                                                   rgw, c_sh, smask, h, logD, red1, red2, acc, obj,
                                                   bad);
   else
-    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false>(base, rstride, rows_here, nfull, N, lc, rg,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1>(base, rstride, rows_here, nfull, N, lc, rg,
                                                     wave, rgw, c_sh, smask, h, logD, red1, red2,
                                                     acc, obj, bad);
   if (nfull < ntiles && blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     double a[ROWS][CPL];
     tile_load<NW, LPR, CPL, ROWS, VEC, true>(a, base, rstride, rows_here, nfull, N, lc);
-    tile_compute<NW, LPR, CPL, ROWS, true, true>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
+    tile_compute<NW, LPR, CPL, ROWS, true, true, 1>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                  logD, red1, red2, acc, obj, bad);
   }
 
@@ -290,13 +314,20 @@ __global__ void __launch_bounds__(NW * 64)
 #pragma unroll
     for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, 64);
     const int k = rg + RG * j;
-    if (lc == 0 && k < K) part[(int64_t)blockIdx.x * K + k] = v;
+    if (lc == 0 && k < K) part[(int64_t)k * gridDim.x + blockIdx.x] = v;  // state-major
   }
-  // objective partial: only row group 0 (lanes 0..LPR-1 of wave 0) holds it
+  // objective partial: sum over the block (wave butterflies, then waves in order)
   double o = obj;
 #pragma unroll
-  for (int off = 1; off < LPR; off <<= 1) o += __shfl_xor(o, off, 64);
-  if (tid == 0) part_obj[blockIdx.x] = o;
+  for (int off = 1; off < 64; off <<= 1) o += __shfl_xor(o, off, 64);
+  __syncthreads();  // red1 is free again
+  if ((tid & 63) == 0) red1[0][wave] = o;
+  __syncthreads();
+  if (tid == 0) {
+    double ob = red1[0][0];
+    for (int wv = 1; wv < NW; ++wv) ob += red1[0][wv];
+    part_obj[blockIdx.x] = ob;
+  }
   // flags: OR over the block in shared memory, then one plain store
   if (bad) atomicOr(&fl, bad);
   __syncthreads();
@@ -305,18 +336,18 @@ __global__ void __launch_bounds__(NW * 64)
 
 // Launch configuration table: (NW, LPR, CPL, ROWS, PF) by number of states.
 struct FastCfg {
-  int kmax, nw, lpr, cpl, rows, pf;
+  int kmax, nw, lpr, cpl, rows, pf, sg;
 };
 static const FastCfg kCfgs[] = {
-    {8, 4, 64, 2, 2, 1},    {16, 4, 64, 2, 4, 1},   {32, 4, 64, 2, 8, 1},
-    {64, 4, 32, 2, 8, 1},   {104, 4, 32, 2, 13, 1}, {128, 4, 32, 2, 16, 0},
-    {256, 8, 32, 2, 16, 0},
+    {8, 4, 64, 2, 2, 1, 1},    {16, 4, 64, 2, 4, 1, 1},   {32, 4, 64, 2, 8, 1, 1},
+    {64, 4, 32, 2, 8, 1, 1},   {104, 4, 32, 2, 13, 0, 0}, {128, 4, 32, 2, 16, 0, 1},
+    {256, 8, 32, 2, 16, 0, 1},
 };
-// Extra instantiations reachable through BUMBAR_SWEEP_CFG="nw,lpr,cpl,rows,pf"
+// Extra instantiations reachable through BUMBAR_SWEEP_CFG="nw,lpr,cpl,rows,pf,sg"
 // (launch-shape tuning; results do not depend on the shape beyond rounding).
 static const FastCfg kTune[] = {
-    {0, 4, 32, 2, 13, 0}, {0, 8, 32, 2, 7, 1}, {0, 8, 32, 2, 7, 0}, {0, 8, 64, 2, 13, 0},
-    {0, 4, 64, 2, 8, 0},  {0, 8, 16, 2, 4, 1},
+    {0, 4, 32, 2, 13, 1, 0}, {0, 4, 32, 2, 13, 1, 2}, {0, 4, 32, 2, 13, 1, 1},
+    {0, 8, 32, 2, 7, 1, 0},  {0, 8, 32, 2, 7, 0, 0},  {0, 4, 64, 2, 8, 1, 0},
 };
 
 static const FastCfg* pick_cfg(int K) {
@@ -326,13 +357,15 @@ static const FastCfg* pick_cfg(int K) {
     forced_state = 0;
     if (const char* e = getenv("BUMBAR_SWEEP_CFG")) {
       FastCfg c{};
-      if (sscanf(e, "%d,%d,%d,%d,%d", &c.nw, &c.lpr, &c.cpl, &c.rows, &c.pf) == 5) {
+      if (sscanf(e, "%d,%d,%d,%d,%d,%d", &c.nw, &c.lpr, &c.cpl, &c.rows, &c.pf, &c.sg) == 6) {
+        auto same = [&](const FastCfg& t) {
+          return t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows &&
+                 t.pf == c.pf && t.sg == c.sg;
+        };
         for (const auto& t : kTune)
-          if (t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows && t.pf == c.pf)
-            forced_state = 1;
+          if (same(t)) forced_state = 1;
         for (const auto& t : kCfgs)
-          if (t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows && t.pf == c.pf)
-            forced_state = 1;
+          if (same(t)) forced_state = 1;
         if (forced_state) forced = c;
       }
     }
@@ -350,15 +383,15 @@ bool sweep_fast_supported(int K) { return pick_cfg(K) != nullptr; }
 
 int sweep_max_grid(int num_cus) { return num_cus * 8; }
 
-template <int NW, int LPR, int CPL, int ROWS, int PF>
+template <int NW, int LPR, int CPL, int ROWS, int PF, int SG>
 static hipError_t launch_cfg(hipStream_t s, bool vec, const double* u, int64_t ld, int K,
                              int64_t N, const double* cst, const double* gk, const double* h,
                              double* logD, double* part, double* part_obj, unsigned* pf,
                              int num_cus, int* grid_out) {
   constexpr int TN = LPR * CPL;
   const int64_t ntiles = (N + TN - 1) / TN;
-  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0>;
-  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0>;
+  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG>;
+  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG>;
   // resident workgroups per CU of this instantiation (queried once)
   static int per_cu = 0;
   if (per_cu == 0) {
@@ -388,23 +421,23 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
   const FastCfg* c = pick_cfg(K);
   if (!c) return hipErrorInvalidValue;
   const bool vec = ((reinterpret_cast<uintptr_t>(u) & 15) == 0) && ((ld & 1) == 0);
-#define BUMBAR_CFG(a, b, cc, d, e)                                                             \
-  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e)                 \
-    return launch_cfg<a, b, cc, d, e>(s, vec, u, ld, K, N, cst, gk, h, logD, part, part_obj,   \
-                                      part_flags, num_cus, grid_out);
-  BUMBAR_CFG(4, 64, 2, 2, 1)
-  BUMBAR_CFG(4, 64, 2, 4, 1)
-  BUMBAR_CFG(4, 64, 2, 8, 1)
-  BUMBAR_CFG(4, 32, 2, 8, 1)
-  BUMBAR_CFG(4, 32, 2, 13, 1)
-  BUMBAR_CFG(4, 32, 2, 16, 0)
-  BUMBAR_CFG(8, 32, 2, 16, 0)
-  BUMBAR_CFG(4, 32, 2, 13, 0)
-  BUMBAR_CFG(8, 32, 2, 7, 1)
-  BUMBAR_CFG(8, 32, 2, 7, 0)
-  BUMBAR_CFG(8, 64, 2, 13, 0)
-  BUMBAR_CFG(4, 64, 2, 8, 0)
-  BUMBAR_CFG(8, 16, 2, 4, 1)
+#define BUMBAR_CFG(a, b, cc, d, e, f)                                                          \
+  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e && c->sg == f)   \
+    return launch_cfg<a, b, cc, d, e, f>(s, vec, u, ld, K, N, cst, gk, h, logD, part, part_obj, \
+                                         part_flags, num_cus, grid_out);
+  BUMBAR_CFG(4, 64, 2, 2, 1, 1)
+  BUMBAR_CFG(4, 64, 2, 4, 1, 1)
+  BUMBAR_CFG(4, 64, 2, 8, 1, 1)
+  BUMBAR_CFG(4, 32, 2, 8, 1, 1)
+  BUMBAR_CFG(4, 32, 2, 13, 0, 0)
+  BUMBAR_CFG(4, 32, 2, 16, 0, 1)
+  BUMBAR_CFG(8, 32, 2, 16, 0, 1)
+  BUMBAR_CFG(4, 32, 2, 13, 1, 0)
+  BUMBAR_CFG(4, 32, 2, 13, 1, 2)
+  BUMBAR_CFG(4, 32, 2, 13, 1, 1)
+  BUMBAR_CFG(8, 32, 2, 7, 1, 0)
+  BUMBAR_CFG(8, 32, 2, 7, 0, 0)
+  BUMBAR_CFG(4, 64, 2, 8, 1, 0)
 #undef BUMBAR_CFG
   return hipErrorInvalidValue;
 }
@@ -545,66 +578,90 @@ hipError_t launch_sweep_robust(hipStream_t s, const double* u, int64_t ld, int K
 }
 
 // ---------------------------------------------------------------------------
-// Finaliser: merges the workgroup partials in a fixed order (one thread per
-// state) and computes f_new, ln S, the gradient norm, Eq. (2) and flags.
+// Finaliser: merges the workgroup partials in a fixed order and computes
+// f_new, ln S, S, the gradient norm, Eq. (2) and flags. One workgroup of FT
+// threads (256 for small problems, 1024 otherwise); the six scalar results
+// are reduced together (wave butterflies, then the waves in order).
 // ---------------------------------------------------------------------------
-constexpr int kFinThreads = 1024;
+struct Red6 {
+  double mdf, rs, gsq, minS, nf, ob;
+};
 
-__device__ __forceinline__ double block_reduce_max(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) sh[tid] = fmax(sh[tid], sh[tid + w]);
-    __syncthreads();
+template <int FT>
+__device__ __forceinline__ Red6 block_reduce6(Red6 v, double (*sh)[6]) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    v.mdf = fmax(v.mdf, __shfl_xor(v.mdf, off, 64));
+    v.rs = fmax(v.rs, __shfl_xor(v.rs, off, 64));
+    v.gsq += __shfl_xor(v.gsq, off, 64);
+    v.minS = fmin(v.minS, __shfl_xor(v.minS, off, 64));
+    v.nf += __shfl_xor(v.nf, off, 64);
+    v.ob += __shfl_xor(v.ob, off, 64);
   }
-  const double r = sh[0];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w][0] = v.mdf;
+    sh[w][1] = v.rs;
+    sh[w][2] = v.gsq;
+    sh[w][3] = v.minS;
+    sh[w][4] = v.nf;
+    sh[w][5] = v.ob;
+  }
   __syncthreads();
+  Red6 r{sh[0][0], sh[0][1], sh[0][2], sh[0][3], sh[0][4], sh[0][5]};
+  for (int q = 1; q < FT / 64; ++q) {
+    r.mdf = fmax(r.mdf, sh[q][0]);
+    r.rs = fmax(r.rs, sh[q][1]);
+    r.gsq += sh[q][2];
+    r.minS = fmin(r.minS, sh[q][3]);
+    r.nf += sh[q][4];
+    r.ob += sh[q][5];
+  }
   return r;
 }
 
-__device__ __forceinline__ double block_reduce_sum(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) sh[tid] += sh[tid + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-__global__ void __launch_bounds__(kFinThreads)
+template <int FT>
+__global__ void __launch_bounds__(FT)
     sweep_finalize_kernel(int mode, int K, int nparts, const double* __restrict__ part,
                           const double* __restrict__ partS, const double* __restrict__ part_obj,
                           const unsigned* __restrict__ part_flags, const double* __restrict__ f,
                           const double* __restrict__ lnNp, const int64_t* __restrict__ Nk,
                           double* __restrict__ f_new, double* __restrict__ lnS_out,
                           double* __restrict__ S_out, SweepScalars* __restrict__ out) {
-  __shared__ double sh[kFinThreads];
+  __shared__ double sh[FT / 64][6];
   __shared__ double f0s;
   __shared__ unsigned flags_sh;
   const int tid = threadIdx.x;
   if (tid == 0) flags_sh = 0u;
-  __syncthreads();
   unsigned fl = 0u;
-  for (int i = tid; i < nparts; i += kFinThreads) fl |= part_flags[i];
-  double gsq = 0.0, minS = INFINITY;
+  for (int i = tid; i < nparts; i += FT) fl |= part_flags[i];
+  Red6 v{0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
+  for (int p = tid; p < nparts; p += FT) v.ob += part_obj[p];
   // Fast-path partials: T lanes per state (T a power of two, consecutive
   // lanes of one wave) each add every T-th partial, then a fixed xor
   // butterfly combines them, so the order of additions never changes.
   int T = 1;
   if (mode == 0)
-    while (T < 64 && 2 * T * K <= kFinThreads) T *= 2;
-  const int kstride = kFinThreads / T;
+    while (T < 64 && 2 * T * K <= FT) T *= 2;
+  const int kstride = FT / T;
   const int kfirst = tid / T, lane_c = tid % T;
   for (int k0 = 0; k0 < K; k0 += kstride) {
     const int k = k0 + kfirst;
     double Sp = 0.0;
-    if (mode == 0 && k < K)
-      for (int p = lane_c; p < nparts; p += T) Sp += part[(int64_t)p * K + k];
+    if (mode == 0 && k < K) {
+      // fast-path partials are state-major: part[k * nparts + p]
+      const double* pk = part + (int64_t)k * nparts;
+      int p = lane_c;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (; p + 3 * T < nparts; p += 4 * T) {
+        s0 += pk[p];
+        s1 += pk[p + T];
+        s2 += pk[p + 2 * T];
+        s3 += pk[p + 3 * T];
+      }
+      for (; p < nparts; p += T) s0 += pk[p];
+      Sp = (s0 + s1) + (s2 + s3);
+    }
     if (mode == 0)
       for (int off = 1; off < T; off <<= 1) Sp += __shfl_xor(Sp, off, 64);
     if (k >= K || lane_c != 0) continue;
@@ -629,23 +686,22 @@ __global__ void __launch_bounds__(kFinThreads)
     f_new[k] = fn;
     if (Nk[k] > 0) {
       const double g = S - (double)Nk[k];
-      gsq += g * g;
-      minS = fmin(minS, S);
+      v.gsq += g * g;
+      v.minS = fmin(v.minS, S);
     }
     if (fn != fn) fl |= FLAG_NAN;
   }
+  __syncthreads();  // flags_sh initialised; f_new complete
   if (fl) atomicOr(&flags_sh, fl);
-  __syncthreads();
   if (tid == 0) f0s = f_new[0];
   __syncthreads();
   const double f0 = f0s;
-  double mdf = 0.0, rs = 0.0, nf = 0.0;
-  for (int k = tid; k < K; k += kFinThreads) {
+  for (int k = tid; k < K; k += FT) {
     const double fn = f_new[k] - f0;
     f_new[k] = fn;
     double df = fabs(fn - f[k]);
     if (df != df) df = INFINITY;
-    mdf = fmax(mdf, df);
+    v.mdf = fmax(v.mdf, df);
     if (k >= 1) {
       double r;
       if (f[k] != 0.0)
@@ -653,24 +709,17 @@ __global__ void __launch_bounds__(kFinThreads)
       else
         r = (fn == 0.0) ? 0.0 : INFINITY;
       if (r != r) r = INFINITY;
-      rs = fmax(rs, r);
+      v.rs = fmax(v.rs, r);
     }
-    nf = __builtin_fma(-(double)Nk[k], f[k], nf);
+    v.nf = __builtin_fma(-(double)Nk[k], f[k], v.nf);
   }
-  mdf = block_reduce_max(mdf, sh);
-  rs = block_reduce_max(rs, sh);
-  gsq = block_reduce_sum(gsq, sh);
-  minS = -block_reduce_max(-minS, sh);
-  nf = block_reduce_sum(nf, sh);
-  double ob = 0.0;
-  for (int p = tid; p < nparts; p += kFinThreads) ob += part_obj[p];
-  ob = block_reduce_sum(ob, sh);
+  const Red6 r = block_reduce6<FT>(v, sh);
   if (tid == 0) {
-    out->max_df = mdf;
-    out->rel_step = rs;
-    out->objective = ob + nf;
-    out->grad_norm = sqrt(gsq);
-    out->min_S = minS;
+    out->max_df = r.mdf;
+    out->rel_step = r.rs;
+    out->objective = r.ob + r.nf;
+    out->grad_norm = sqrt(r.gsq);
+    out->min_S = r.minS;
     out->flags = flags_sh;
     out->pad = 0u;
   }
@@ -681,8 +730,12 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
                                  SweepScalars* out) {
-  hipLaunchKernelGGL(sweep_finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, mode, K, nparts,
-                     part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
+  if (K <= 256 && nparts <= 4096)
+    hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts, part,
+                       partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
+  else
+    hipLaunchKernelGGL(sweep_finalize_kernel<1024>, dim3(1), dim3(1024), 0, s, mode, K, nparts,
+                       part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
   return hipGetLastError();
 }
 
