@@ -94,6 +94,8 @@ typedef struct {
   const int* replay_refine; /* host; schedule replay: refine flag of each phase-2 check  */
   int n_replay;        /* number of entries in replay_refine                              */
   int profile;         /* 1: time every unbinned sweep kernel with HIP events (stats)      */
+  double mixed_tol;    /* PREC_MIXED: Newton on the FP32 matrix until max |delta f| <
+                          mixed_tol, then FP64 refinement to tol (default 1e-6)          */
 } bumbar_options;
 
 typedef struct {
@@ -105,6 +107,7 @@ typedef struct {
   int64_t unbinned_sweeps;  /* full K x N sweeps                                        */
   int64_t robust_sweeps;    /* sweeps redone on the two-pass underflow-safe path         */
   int64_t hessians;         /* K x K Hessian contractions                               */
+  int64_t mixed_steps;      /* finisher steps taken on the FP32 packed matrix            */
   double final_step;        /* last applied max |delta f| (kT)                           */
   double grad_norm;         /* Euclidean norm of the MBAR gradient at the result         */
   double time_binning_ms;   /* histogram / width search                                 */

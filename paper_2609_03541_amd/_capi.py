@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("n_intermediate", C.c_int), ("finisher", C.c_int), ("max_iter", C.c_int64),
                 ("max_newton", C.c_int), ("sci_switch", C.c_double),
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
-                ("n_replay", C.c_int), ("profile", C.c_int)]
+                ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -51,6 +51,7 @@ class Stats(C.Structure):
                 ("n_checks", C.c_int64), ("finisher_steps", C.c_int64),
                 ("sci_fallbacks", C.c_int64), ("unbinned_sweeps", C.c_int64),
                 ("robust_sweeps", C.c_int64), ("hessians", C.c_int64),
+                ("mixed_steps", C.c_int64),
                 ("final_step", C.c_double), ("grad_norm", C.c_double),
                 ("time_binning_ms", C.c_double), ("time_binned_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("sweep_kernel_ms", C.c_double),

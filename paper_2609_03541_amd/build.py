@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbumbar.so")
-SOURCES = ["sweep.hip", "hessian.hip", "linalg.hip", "binning.hip", "solver.cpp", "algo.cpp"]
+SOURCES = ["sweep.hip", "sweep_wide.hip", "sweep32.hip", "hessian.hip", "linalg.hip", "binning.hip",
+           "solver.cpp", "algo.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -147,11 +147,19 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
   return BUMBAR_OK;
 }
 
+static Mat level_mat(const Level& L) {
+  Mat M;
+  M.u = L.ubar;
+  M.kind = 0;
+  M.ld = L.P;
+  return M;
+}
+
 static int binned_sci(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const Level& L,
                       const int64_t* Nk, const double* f, double* f_out, SweepScalars* sc,
                       SweepCounters* cnt) {
   (void)cnt;  // binned sweeps are counted by the stage's iteration counters
-  return sweep_at(ctx, B, L.ubar, L.P, L.P, L.h, Nk, f, f_out, BB.logD_lvl, B.lnS_t, B.S_t, sc,
+  return sweep_at(ctx, B, level_mat(L), L.P, L.h, Nk, f, f_out, BB.logD_lvl, B.lnS_t, B.S_t, sc,
                   false, nullptr);
 }
 
@@ -198,7 +206,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   };
   // one step on the robust-capable path, result in fh(slot)
   auto safe_step = [&](const Level& L, const double* fin, int slot, SweepScalars* sc) -> int {
-    return sweep_at(ctx, B, L.ubar, L.P, L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl, B.lnS_t,
+    return sweep_at(ctx, B, level_mat(L), L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl, B.lnS_t,
                     B.S_t, sc, false, nullptr);
   };
   int64_t it1 = 0, it2 = 0, nchk = 0;
@@ -214,7 +222,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     int nvalid = 0;  // leading steps that are usable
     if (fast) {
       for (int i = 0; i < T; ++i) {
-        rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev, i == 0 ? BB.f_n : fh(i - 1),
+        rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, i == 0 ? BB.f_n : fh(i - 1),
                          fh(i), BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + i);
         if (rc) return rc;
       }
@@ -262,7 +270,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       while (!fallback && nint - done_int > kHistSteps - 2) {
         const int T = kHistSteps - 2;
         for (int i = 0; i < T && fast; ++i) {
-          rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev,
+          rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                            i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
                            B.scal_hist + i);
           if (rc) return rc;
@@ -284,7 +292,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       if (!fallback && fast) {
         const int T = nint - done_int;
         for (int i = 0; i < T; ++i) {
-          rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev,
+          rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                            i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
                            B.scal_hist + i);
           if (rc) return rc;
@@ -292,10 +300,10 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         const double* fin = T == 0 ? BB.f_n : fh(T - 1);
         in = T;
         ix = T + 1;
-        rc = sweep_queue(ctx, B, cur.ubar, cur.P, cur.P, cur.h, Nk_dev, fin, fh(in), BB.logD_lvl,
+        rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, fin, fh(in), BB.logD_lvl,
                          B.lnS_t, B.S_t, B.scal_hist + in);
         if (rc) return rc;
-        rc = sweep_queue(ctx, B, nxt.ubar, nxt.P, nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
+        rc = sweep_queue(ctx, B, level_mat(nxt), nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
                          B.lnS_t, B.S_t, B.scal_hist + ix);
         if (rc) return rc;
         rc = read_hist(T + 2);

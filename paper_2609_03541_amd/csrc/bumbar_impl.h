@@ -70,7 +70,8 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
 bool sweep_fast_supported(int K);
 
 // Robust two-pass sweep: exact column max, then per-state online log-sum-exp.
-hipError_t launch_sweep_robust(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+// u is FP64, or FP32 when f32 (widened on load).
+hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                                const double* cst, const double* gk, const double* h,
                                double* logD, double* partM, double* partS, double* part_obj,
                                unsigned* part_flags, int chunks);
@@ -93,7 +94,7 @@ hipError_t launch_fill_unsampled_gauge(hipStream_t s, int K, const int64_t* Nk, 
                                        const double* lnS);
 hipError_t launch_max_abs_diff(hipStream_t s, int K, const double* a, const double* b,
                                double* out);
-hipError_t launch_weights(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+hipError_t launch_weights(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                           const double* f, const double* logD, double* W);
 hipError_t launch_reweight(hipStream_t s, int64_t N, const double* ut, const double* logD,
                            double* part, int nparts, double* p);
@@ -101,9 +102,27 @@ hipError_t launch_check_finite_f(hipStream_t s, int K, const double* f, unsigned
 
 // ---- Hessian and linear algebra (hessian.hip, linalg.hip) ----------------
 size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out);
-hipError_t launch_hessian(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+// utype 0: FP64 u; 1: FP32 u (widened); 2: packed mixed-precision matrix
+// (cst = d_k, m0 = per-column shift).
+hipError_t launch_hessian(hipStream_t s, const void* u, int utype, int64_t ld, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
-                          const double* S, double* partials, int chunks, double* H);
+                          const double* m0, const double* S, double* partials, int chunks,
+                          double* H);
+// Two-pass FP64 sweep for any K (FP64 or FP32 u); grid returned in *grid_out.
+int wide_grid(int64_t N, int num_cus);
+hipError_t launch_sweep_wide(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
+                             const double* cst, const double* gk, const double* h, double* logD,
+                             double* part, double* part_obj, unsigned* part_flags, int num_cus,
+                             int* grid_out);
+// Mixed precision (sweep32.hip).
+bool sweep32_supported(int K);
+hipError_t launch_pack_f32(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+                           const double* c0, float* r, int64_t ldr, double* m0);
+hipError_t launch_delta(hipStream_t s, int K, const double* f, const double* f0, double* d);
+hipError_t launch_sweep32(hipStream_t s, const float* r, int64_t ld, int K, int64_t N,
+                          const double* dk, const double* gk, const double* m0, double* logD,
+                          double* part, double* part_obj, unsigned* part_flags, int num_cus,
+                          int* grid_out);
 // Newton direction on the reduced system (drop the first sampled state and
 // the unsampled ones). A: workspace K*K doubles, idx: K ints. ok: device int.
 hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, const double* H,

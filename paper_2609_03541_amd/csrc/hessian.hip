@@ -38,11 +38,16 @@ __device__ __forceinline__ void block_coords(int b, int nb, int& bi, int& bj) {
   bj = i + rem;
 }
 
+// TI = double: x = c_k - u_kn - ln D_n. TI = float (packed mixed-precision
+// matrix r_kn = c0_k - u_kn - m0_n): x = d_k + r_kn - (ln D_n - m0_n) with
+// d_k = c_k - c0_k passed as cst and NEG_U set.
+template <typename TI, bool NEG_U>
 __global__ void __launch_bounds__(256)
-    hessian_partial_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    hessian_partial_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                            const double* __restrict__ cst, const double* __restrict__ gk,
-                           const double* __restrict__ logD, int nb, int chunks,
-                           int64_t chunk_len, double* __restrict__ partials) {
+                           const double* __restrict__ logD, const double* __restrict__ m0,
+                           int nb, int chunks, int64_t chunk_len,
+                           double* __restrict__ partials) {
   __shared__ double Pi[HB][HP];
   __shared__ double Pj[HB][HP];
   const int blk = blockIdx.x / chunks;
@@ -81,13 +86,19 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < 4; ++q) {
       const int64_t n = n0 + ls + q;
       const bool ok = n < n_end;
-      const double lD = ok ? logD[n] : 0.0;
+      const double lD = ok ? (NEG_U ? logD[n] - m0[n] : logD[n]) : 0.0;
       double vi = 0.0;
-      if (si && ok) vi = exp_nonpos(ci - u[(int64_t)ki * ld + n] - lD);
+      if (si && ok) {
+        const double x = (double)u[(int64_t)ki * ld + n];
+        vi = exp_nonpos(ci - (NEG_U ? -x : x) - lD);
+      }
       Pi[lr][ls + q] = vi;
       if (!diag) {
         double vj = 0.0;
-        if (sj && ok) vj = exp_nonpos(cj - u[(int64_t)kj * ld + n] - lD);
+        if (sj && ok) {
+          const double x = (double)u[(int64_t)kj * ld + n];
+          vj = exp_nonpos(cj - (NEG_U ? -x : x) - lD);
+        }
         Pj[lr][ls + q] = vj;
       }
     }
@@ -162,15 +173,27 @@ size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
   return (size_t)nblk * chunks * HB * HB;
 }
 
-hipError_t launch_hessian(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+hipError_t launch_hessian(hipStream_t s, const void* u, int utype, int64_t ld, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
-                          const double* S, double* partials, int chunks, double* H) {
+                          const double* m0, const double* S, double* partials, int chunks,
+                          double* H) {
   const int nb = hess_nb(K);
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
-  hipLaunchKernelGGL(hessian_partial_kernel, dim3(nblk * chunks), dim3(256), 0, s, u, ld, K, N,
-                     cst, gk, logD, nb, chunks, chunk_len, partials);
+  const dim3 g(nblk * chunks);
+  if (utype == 0)
+    hipLaunchKernelGGL((hessian_partial_kernel<double, false>), g, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
+                       chunk_len, partials);
+  else if (utype == 1)
+    hipLaunchKernelGGL((hessian_partial_kernel<float, false>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
+                       chunk_len, partials);
+  else
+    hipLaunchKernelGGL((hessian_partial_kernel<float, true>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
+                       chunk_len, partials);
   hipLaunchKernelGGL(hessian_reduce_kernel, dim3(HB * HB / 256, nblk), dim3(256), 0, s, K, nb,
                      chunks, partials, S, gk, H);
   return hipGetLastError();

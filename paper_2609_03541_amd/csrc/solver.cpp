@@ -71,6 +71,7 @@ void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
   A = ar.take<double>((size_t)K * K + 3 * (size_t)K);
   H = ar.take<double>((size_t)K * K);
   hess_parts = ar.take<double>(hessian_partial_count(K, N, num_cus, &hess_chunks));
+  dk = ar.take<double>(K);
 }
 
 // Event pairs for timing sweep kernels; at most 4096 launches per solve are timed.
@@ -118,46 +119,84 @@ int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
 }
 
 // One sweep (unbinned when h == nullptr, binned with multiplicities h
-// otherwise) of the K x N matrix u at f. Outputs: f_out (gauged SCI step),
+// otherwise) of the matrix M at f. Outputs: f_out (gauged SCI step),
 // logD_out, lnS_out, S_out and the scalars (read back to *sc when sc != null).
-int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
-             const double* h, const int64_t* Nk, const double* f, double* f_out,
-             double* logD_out, double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
-             SweepCounters* cnt) {
+// Kernel choice: FP64 u with K <= 256 -> register-tiled single pass; other
+// FP64 / FP32 u -> two-pass FP64; packed matrix -> FP32 single pass. A
+// flagged FP64 sweep is redone on the robust path.
+static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N,
+                       const double* h, const int64_t* Nk, const double* f, double* f_out,
+                       double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal,
+                       bool timed) {
   hipStream_t s = ctx->stream;
   const int K = B.K;
   hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
   if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
-  bool robust = force_robust || !sweep_fast_supported(K);
-  if (!robust) {
-    int grid = 0;
-    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (ctx->profiling && h == nullptr) ev = next_event_pair(ctx);
+  int grid = 0;
+  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+  if (timed && ctx->profiling && h == nullptr) ev = next_event_pair(ctx);
+  if (M.kind == 2) {
+    e = launch_delta(s, K, f, M.f0, B.dk);
+    if (e != hipSuccess) return hip_fail(ctx, e, "delta");
     if (ev) (void)hipEventRecord(ev->first, s);
-    e = launch_sweep_fast(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.part_obj,
-                          B.part_flags, ctx->num_cus, &grid);
-    if (ev) (void)hipEventRecord(ev->second, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "sweep_fast");
-    e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f,
-                              B.lnNp, Nk, f_out, lnS_out, S_out, B.scal);
-    if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
-    if (cnt) cnt->fast++;
-    if (sc == nullptr) return BUMBAR_OK;
-    int rc = read_scalars(ctx, B.scal, sc);
-    if (rc) return rc;
-    if ((sc->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) return BUMBAR_OK;
-    robust = true;
+    e = launch_sweep32(s, reinterpret_cast<const float*>(M.u), M.ld, K, N, B.dk, B.gk, M.m0,
+                       logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
+  } else if (M.kind == 0 && sweep_fast_supported(K)) {
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_fast(s, reinterpret_cast<const double*>(M.u), M.ld, K, N, B.cst, B.gk, h,
+                          logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
+  } else {
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_wide(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
+                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
   }
+  if (ev) (void)hipEventRecord(ev->second, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep");
+  e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f, B.lnNp,
+                            Nk, f_out, lnS_out, S_out, dev_scal);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
+  return BUMBAR_OK;
+}
+
+int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
+                const int64_t* Nk, const double* f, double* f_out, double* logD_out,
+                double* lnS_out, double* S_out, SweepScalars* dev_scal) {
+  return queue_sweep(ctx, B, M, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, dev_scal, false);
+}
+
+int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
+             const int64_t* Nk, const double* f, double* f_out, double* logD_out,
+             double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
+             SweepCounters* cnt) {
+  hipStream_t s = ctx->stream;
+  const int K = B.K;
+  SweepScalars tmp;
+  SweepScalars* out = sc ? sc : &tmp;
+  if (!force_robust || M.kind == 2) {
+    int rc = queue_sweep(ctx, B, M, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, B.scal, true);
+    if (rc) return rc;
+    if (cnt) cnt->fast++;
+    if (sc == nullptr && M.kind != 2) {
+      // callers without scalars still need the flags for the fallback decision
+      rc = read_scalars(ctx, B.scal, out);
+      if (rc) return rc;
+    } else {
+      rc = read_scalars(ctx, B.scal, out);
+      if (rc) return rc;
+    }
+    if (M.kind == 2) return BUMBAR_OK;  // flags are the caller's signal to leave FP32
+    if ((out->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) return BUMBAR_OK;
+  }
+  hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
+  if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
   const int ch = robust_chunks(N);
-  e = launch_sweep_robust(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.partS, B.part_obj,
-                          B.part_flags, ch);
+  e = launch_sweep_robust(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
+                          B.partS, B.part_obj, B.part_flags, ch);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep_robust");
   e = launch_sweep_finalize(s, 1, K, ch, B.part, B.partS, B.part_obj, B.part_flags, f, B.lnNp, Nk,
                             f_out, lnS_out, S_out, B.scal);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
   if (cnt) cnt->robust++;
-  SweepScalars tmp;
-  SweepScalars* out = sc ? sc : &tmp;
   int rc = read_scalars(ctx, B.scal, out);
   if (rc) return rc;
   if (out->flags & FLAG_NAN)
@@ -165,53 +204,55 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld
   return BUMBAR_OK;
 }
 
-// Queue one fast-path sweep without any readback; its scalars go to
-// dev_scal (device). Flags must be checked by the caller after reading the
-// scalars back. Requires sweep_fast_supported(K).
-int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
-                const double* h, const int64_t* Nk, const double* f, double* f_out,
-                double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal) {
+static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const double* f) {
+  // B.cst / B.gk hold the constants of the last sweep at f; the packed matrix
+  // needs d = f - f0 instead of c.
   hipStream_t s = ctx->stream;
-  const int K = B.K;
-  hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
-  if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
-  int grid = 0;
-  e = launch_sweep_fast(s, u, ld, K, N, B.cst, B.gk, h, logD_out, B.part, B.part_obj, B.part_flags,
-                        ctx->num_cus, &grid);
-  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_fast");
-  e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f, B.lnNp,
-                            Nk, f_out, lnS_out, S_out, dev_scal);
-  if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
-  return BUMBAR_OK;
+  if (M.kind == 2) {
+    hipError_t e = launch_delta(s, B.K, f, M.f0, B.dk);
+    if (e != hipSuccess) return e;
+    return launch_hessian(s, M.u, 2, M.ld, B.K, B.N, B.dk, B.gk, B.logD, M.m0, B.S, B.hess_parts,
+                          B.hess_chunks, B.H);
+  }
+  return launch_hessian(s, M.u, M.kind, M.ld, B.K, B.N, B.cst, B.gk, B.logD, nullptr, B.S,
+                        B.hess_parts, B.hess_chunks, B.H);
 }
 
 // Newton finisher on unbinned data (see the oracle's reading): full Newton
 // step on the reduced system, trial steps alpha = 1, 1/2, ..., 2^-10 accepted
 // when they lower ||S - N||_2; otherwise one SCI step. Stops when the applied
-// max |delta f| < tol. f (device, K) is updated in place.
-int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
-                  const int64_t* Nk, double tol, int max_steps, bumbar_stats* st,
-                  SweepCounters* cnt, double* final_step, double* final_gnorm) {
+// max |delta f| < tol. f (device, K) is updated in place. With the packed
+// matrix, a flagged sweep ends the loop early with BUMBAR_ENOTCONV (the
+// caller continues in FP64).
+int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double tol,
+                  int max_steps, bumbar_stats* st, SweepCounters* cnt, double* final_step,
+                  double* final_gnorm) {
   hipStream_t s = ctx->stream;
   const int K = B.K;
   const int64_t N = B.N;
   SweepScalars sc{};
+  auto bad32 = [&](const SweepScalars& x) {
+    return M.kind == 2 && (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
+  };
   // fill unsampled states and gauge at the start (as the oracle does)
-  int rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
-                    cnt);
+  int rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, cnt);
   if (rc) return rc;
+  if (bad32(sc)) return BUMBAR_ENOTCONV;
   hipError_t e = launch_fill_unsampled_gauge(s, K, Nk, B.f, B.lnS);
   if (e != hipSuccess) return hip_fail(ctx, e, "fill_unsampled");
   int steps = 0, fallbacks = 0;
   double last = INFINITY;
   rc = BUMBAR_ENOTCONV;
   while (steps < max_steps) {
-    rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
-                  cnt);
+    rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, cnt);
     if (rc) return rc;
+    if (bad32(sc)) {
+      rc = BUMBAR_ENOTCONV;
+      break;
+    }
     const double gn = sc.grad_norm;
     if (final_gnorm) *final_gnorm = gn;
-    e = launch_hessian(s, u, ld, K, N, B.cst, B.gk, B.logD, B.S, B.hess_parts, B.hess_chunks, B.H);
+    e = queue_hessian(ctx, B, M, B.f);
     if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
     if (st) st->hessians++;
     e = launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
@@ -226,23 +267,32 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
       for (int t = 0; t <= 10; ++t, alpha *= 0.5) {
         e = launch_axpy_to(s, K, B.f, alpha, B.dir, B.f_trial);
         if (e != hipSuccess) return hip_fail(ctx, e, "axpy");
-        rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
+        rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
                       &st2, false, cnt);
         if (rc) return rc;
+        if (bad32(st2)) break;
         if (st2.grad_norm < gn) {
           accepted = true;
           break;
         }
       }
+      if (bad32(st2)) {
+        rc = BUMBAR_ENOTCONV;
+        break;
+      }
     }
     if (!accepted) {
       // SCI step: f_trial = SCI(f) (gauged), from a sweep at f
-      rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f, B.f_trial, B.logD_t, B.lnS_t, B.S_t,
-                    nullptr, false, cnt);
+      rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_trial, B.logD_t, B.lnS_t, B.S_t, nullptr,
+                    false, cnt);
       if (rc) return rc;
-      rc = sweep_at(ctx, B, u, ld, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
-                    &st2, false, cnt);
+      rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t, &st2,
+                    false, cnt);
       if (rc) return rc;
+      if (bad32(st2)) {
+        rc = BUMBAR_ENOTCONV;
+        break;
+      }
       ++fallbacks;
     }
     e = launch_fill_unsampled_gauge(s, K, Nk, B.f_trial, B.lnS_t);
@@ -270,15 +320,13 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
 
 // Plain self-consistent iteration on unbinned data until the step is below
 // `until` (or the cap); f updated in place.
-int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld, const int64_t* Nk,
-              double until, int64_t max_steps, int64_t* steps_out, SweepCounters* cnt,
-              double* last_step) {
+int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double until,
+              int64_t max_steps, int64_t* steps_out, SweepCounters* cnt, double* last_step) {
   SweepScalars sc{};
   int64_t it = 0;
   int rc = BUMBAR_ENOTCONV;
   while (it < max_steps) {
-    rc = sweep_at(ctx, B, u, ld, B.N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false,
-                  cnt);
+    rc = sweep_at(ctx, B, M, B.N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, cnt);
     if (rc) return rc;
     hipError_t e =
         hipMemcpyAsync(B.f, B.f_new, sizeof(double) * B.K, hipMemcpyDeviceToDevice, ctx->stream);
@@ -356,17 +404,7 @@ void bumbar_default_options(bumbar_options* o) {
   o->replay_refine = nullptr;
   o->n_replay = 0;
   o->profile = 0;
-}
-
-int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
-                           const bumbar_options* opt, size_t* bytes) {
-  if (!ctx || !bytes || K <= 0 || N <= 0 || d < 0 || d > 2) return BUMBAR_EINVAL;
-  Arena ar;
-  UnbinnedBufs B;
-  B.carve(ar, K, N, ctx->num_cus);
-  if (d > 0 && (opt == nullptr || opt->binning)) binned_carve_size(ar, K, N, d, ctx->num_cus);
-  *bytes = ar.off + 256;
-  return BUMBAR_OK;
+  o->mixed_tol = 1e-6;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
@@ -376,10 +414,18 @@ static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int6
   if (!u) return fail(ctx, BUMBAR_EINVAL, "u_kn is NULL");
   if (K <= 0 || N <= 0) return fail(ctx, BUMBAR_EINVAL, "K and N must be positive");
   if (ld < N) return fail(ctx, BUMBAR_EINVAL, "row stride ld < N");
-  if (u_dtype != BUMBAR_F64)
-    return fail(ctx, BUMBAR_EINVAL, "only FP64 u_kn is supported by this entry point");
+  if (u_dtype != BUMBAR_F64 && u_dtype != BUMBAR_F32)
+    return fail(ctx, BUMBAR_EINVAL, "u_dtype must be BUMBAR_F64 or BUMBAR_F32");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BUMBAR_EDEVICE, "hipSetDevice");
   return BUMBAR_OK;
+}
+
+static Mat input_mat(const void* u, int u_dtype, int64_t ld) {
+  Mat M;
+  M.u = u;
+  M.kind = (u_dtype == BUMBAR_F32) ? 1 : 0;
+  M.ld = ld;
+  return M;
 }
 
 int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
@@ -395,10 +441,13 @@ int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   double* logD = log_D_n ? log_D_n : B.logD;
   double* Sv = S ? S : B.S;
   SweepScalars sc{};
-  // Without stats the call stays asynchronous on the fast path; the fallback
-  // decision then needs the flags, so read them back anyway.
-  rc = sweep_at(ctx, B, reinterpret_cast<const double*>(u_kn), ld, N, nullptr, N_k, f, f_new,
-                logD, B.lnS, Sv, sweep_stats ? &sc : nullptr, false, nullptr);
+  const Mat M = input_mat(u_kn, u_dtype, ld);
+  if (sweep_stats == nullptr && M.kind == 0 && sweep_fast_supported(K)) {
+    // asynchronous: queue the sweep without reading anything back (the caller
+    // accepts that a far-off f is not rerun on the robust path)
+    return sweep_queue(ctx, B, M, N, nullptr, N_k, f, f_new, logD, B.lnS, Sv, B.scal);
+  }
+  rc = sweep_at(ctx, B, M, N, nullptr, N_k, f, f_new, logD, B.lnS, Sv, &sc, false, nullptr);
   if (rc) return rc;
   if (sweep_stats) {
     sweep_stats[0] = sc.max_df;
@@ -422,8 +471,8 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
   hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
   if (e == hipSuccess)
-    e = launch_hessian(ctx->stream, reinterpret_cast<const double*>(u_kn), ld, K, N, B.cst, B.gk,
-                       log_D_n, S, B.hess_parts, B.hess_chunks, H);
+    e = launch_hessian(ctx->stream, u_kn, u_dtype == BUMBAR_F32 ? 1 : 0, ld, K, N, B.cst, B.gk,
+                       log_D_n, nullptr, S, B.hess_parts, B.hess_chunks, H);
   if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
   return BUMBAR_OK;
 }
@@ -433,8 +482,8 @@ int bumbar_weights(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
   if (rc) return rc;
   if (!f || !log_D_n || !W_nk) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
-  hipError_t e = launch_weights(ctx->stream, reinterpret_cast<const double*>(u_kn), ld, K, N, f,
-                                log_D_n, W_nk);
+  hipError_t e = launch_weights(ctx->stream, u_kn, u_dtype == BUMBAR_F32, ld, K, N, f, log_D_n,
+                                W_nk);
   if (e != hipSuccess) return hip_fail(ctx, e, "weights");
   return BUMBAR_OK;
 }
@@ -452,6 +501,38 @@ int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const do
                                  reinterpret_cast<double*>(workspace), nparts, p);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "reweight");
+  return BUMBAR_OK;
+}
+
+// Extra device buffers of the mixed-precision finisher.
+struct MixedBufs {
+  float* r = nullptr;     // K x N packed matrix
+  double* m0 = nullptr;   // N
+  double* f0 = nullptr;   // K
+  void carve(Arena& ar, int K, int64_t N) {
+    r = ar.take<float>((size_t)K * (size_t)N);
+    m0 = ar.take<double>(N);
+    f0 = ar.take<double>(K);
+  }
+};
+
+static bool mixed_enabled(const bumbar_options& opt, int u_dtype, int K) {
+  return opt.precision == BUMBAR_PREC_MIXED && u_dtype == BUMBAR_F64 && sweep32_supported(K) &&
+         opt.finisher == BUMBAR_FINISH_NEWTON;
+}
+
+int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
+                           const bumbar_options* opt, size_t* bytes) {
+  if (!ctx || !bytes || K <= 0 || N <= 0 || d < 0 || d > 2) return BUMBAR_EINVAL;
+  Arena ar;
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  if (d > 0 && (opt == nullptr || opt->binning)) binned_carve_size(ar, K, N, d, ctx->num_cus);
+  if (opt && opt->precision == BUMBAR_PREC_MIXED && sweep32_supported(K)) {
+    MixedBufs X;
+    X.carve(ar, K, N);
+  }
+  *bytes = ar.off + 256;
   return BUMBAR_OK;
 }
 
@@ -476,6 +557,8 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (model != BUMBAR_MODEL_NONE && model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC)
     return fail(ctx, BUMBAR_EINVAL, "unknown model code");
   if (model != BUMBAR_MODEL_NONE && !coef) return fail(ctx, BUMBAR_EINVAL, "model needs coef");
+  if (opt.binning && model == BUMBAR_MODEL_NONE && u_dtype != BUMBAR_F64)
+    return fail(ctx, BUMBAR_EINVAL, "mean bin representatives need FP64 u_kn (or give a model)");
   // counts: host copy for validation
   std::vector<int64_t> nk(K);
   rc = read_bytes(ctx, N_k, nk.data(), sizeof(int64_t) * K);
@@ -487,11 +570,14 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   }
   if (tot != N) return fail(ctx, BUMBAR_EINVAL, "sum of N_k (%lld) != N (%lld)", (long long)tot,
                             (long long)N);
+  const bool mixed = mixed_enabled(opt, u_dtype, K);
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
   BinnedBufs BB;
   if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus);
+  MixedBufs X;
+  if (mixed) X.carve(ar, K, N);
   if (ar.overflow)
     return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
   bumbar_stats local{};
@@ -502,7 +588,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->checks = chk;
   st->checks_capacity = chk_cap;
   hipStream_t s = ctx->stream;
-  const double* u = reinterpret_cast<const double*>(u_kn);
+  const Mat M = input_mat(u_kn, u_dtype, N);
   SweepCounters cnt;
   hipError_t e;
   ctx->profiling = opt.profile != 0;
@@ -515,13 +601,14 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
 
   int stage_rc = BUMBAR_OK;
   if (opt.binning) {
-    stage_rc = binned_stage(ctx, B, BB, u, N_k, nk.data(), xi, d, model, coef, opt, st, &cnt);
+    stage_rc = binned_stage(ctx, B, BB, reinterpret_cast<const double*>(u_kn), N_k, nk.data(), xi,
+                            d, model, coef, opt, st, &cnt);
     if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
   } else if (opt.finisher == BUMBAR_FINISH_NEWTON) {
     const double t0 = now_ms();
     int64_t it = 0;
     double last = 0;
-    stage_rc = sci_until(ctx, B, u, N, N_k, opt.sci_switch, opt.max_iter, &it, &cnt, &last);
+    stage_rc = sci_until(ctx, B, M, N_k, opt.sci_switch, opt.max_iter, &it, &cnt, &last);
     if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
     st->phase1_iters = it;
     st->time_binned_ms = now_ms() - t0;
@@ -530,12 +617,34 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   int fin_rc = BUMBAR_OK;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
-      fin_rc = newton_finish(ctx, B, u, N, N_k, opt.tol, opt.max_newton, st, &cnt,
-                             &st->final_step, &st->grad_norm);
+      if (mixed) {
+        // pack at the current f, Newton on the FP32 matrix to mixed_tol, then
+        // FP64 refinement on u to tol
+        e = launch_prepare_consts(s, K, N_k, B.f, B.cst, B.gk, B.lnNp);
+        if (e == hipSuccess) e = launch_pack_f32(s, reinterpret_cast<const double*>(u_kn), N, K,
+                                                 N, B.cst, X.r, N, X.m0);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(X.f0, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pack");
+        Mat R;
+        R.u = X.r;
+        R.kind = 2;
+        R.ld = N;
+        R.m0 = X.m0;
+        R.f0 = X.f0;
+        const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
+        const int64_t before = st->finisher_steps;
+        int mrc = newton_finish(ctx, B, R, N_k, mtol, opt.max_newton, st, &cnt, &st->final_step,
+                                &st->grad_norm);
+        if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
+        st->mixed_steps = st->finisher_steps - before;
+      }
+      fin_rc = newton_finish(ctx, B, M, N_k, opt.tol, opt.max_newton, st, &cnt, &st->final_step,
+                             &st->grad_norm);
     } else {
       int64_t it = 0;
       const int64_t left = std::max<int64_t>(0, opt.max_iter - st->phase1_iters - st->phase2_iters);
-      fin_rc = sci_until(ctx, B, u, N, N_k, opt.tol, left, &it, &cnt, &st->final_step);
+      fin_rc = sci_until(ctx, B, M, N_k, opt.tol, left, &it, &cnt, &st->final_step);
       st->finisher_steps = it;
     }
     if (fin_rc != BUMBAR_OK && fin_rc != BUMBAR_ENOTCONV) return fin_rc;
@@ -543,13 +652,14 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->time_final_ms = now_ms() - t1;
   // outputs: ln D at the final f, weights, f
   SweepScalars sc{};
-  rc = sweep_at(ctx, B, u, N, N, nullptr, N_k, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, &cnt);
+  rc = sweep_at(ctx, B, M, N, nullptr, N_k, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, &cnt);
   if (rc) return rc;
   st->grad_norm = sc.grad_norm;
   e = hipMemcpyAsync(f_k, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && log_D_n)
     e = hipMemcpyAsync(log_D_n, B.logD, sizeof(double) * N, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && W_nk) e = launch_weights(s, u, N, K, N, B.f, B.logD, W_nk);
+  if (e == hipSuccess && W_nk)
+    e = launch_weights(s, u_kn, u_dtype == BUMBAR_F32, N, K, N, B.f, B.logD, W_nk);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "outputs");
   st->unbinned_sweeps = cnt.fast + cnt.robust;

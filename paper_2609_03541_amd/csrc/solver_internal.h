@@ -23,6 +23,17 @@ struct SweepCounters {
   int64_t robust = 0;
 };
 
+// The matrix a sweep reads: FP64 u, FP32 u (widened to FP64 arithmetic), or
+// the packed mixed-precision matrix r_kn = fp32(c0_k - u_kn - m0_n) taken at
+// the reference point f0 (FP32 arithmetic inside the sweep).
+struct Mat {
+  const void* u = nullptr;
+  int kind = 0;  // 0: FP64, 1: FP32, 2: packed mixed precision
+  int64_t ld = 0;
+  const double* m0 = nullptr;  // kind 2: per-column shift (N)
+  const double* f0 = nullptr;  // kind 2: reference point (K)
+};
+
 // Device buffers for sweeps and the Newton finisher of one K x N problem.
 struct UnbinnedBufs {
   int K = 0;
@@ -41,26 +52,28 @@ struct UnbinnedBufs {
   int* ok = nullptr;
   int* idx = nullptr;
   double *A = nullptr, *H = nullptr, *hess_parts = nullptr;
+  double* dk = nullptr;  // f - f0 for the packed matrix
   int hess_chunks = 1;
   void carve(Arena& ar, int K, int64_t N, int num_cus);
 };
 
-int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
-             const double* h, const int64_t* Nk, const double* f, double* f_out,
-             double* logD_out, double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
+// One sweep of M at f. With a packed matrix a flagged sweep (weights outside
+// the FP32 range) is reported through sc->flags and not redone.
+int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
+             const int64_t* Nk, const double* f, double* f_out, double* logD_out,
+             double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
              SweepCounters* cnt);
 
-int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const double* u, int64_t ld, int64_t N,
-                const double* h, const int64_t* Nk, const double* f, double* f_out,
-                double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal);
+int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
+                const int64_t* Nk, const double* f, double* f_out, double* logD_out,
+                double* lnS_out, double* S_out, SweepScalars* dev_scal);
 
-int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld,
-                  const int64_t* Nk, double tol, int max_steps, bumbar_stats* st,
-                  SweepCounters* cnt, double* final_step, double* final_gnorm);
+int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double tol,
+                  int max_steps, bumbar_stats* st, SweepCounters* cnt, double* final_step,
+                  double* final_gnorm);
 
-int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const double* u, int64_t ld, const int64_t* Nk,
-              double until, int64_t max_steps, int64_t* steps_out, SweepCounters* cnt,
-              double* last_step);
+int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double until,
+              int64_t max_steps, int64_t* steps_out, SweepCounters* cnt, double* last_step);
 
 // ---- binning ---------------------------------------------------------------
 

@@ -447,8 +447,9 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
 // ---------------------------------------------------------------------------
 
 // Pass A: exact ln D_n per column (thread per column, coalesced along n).
+template <typename TI>
 __global__ void __launch_bounds__(256)
-    robust_logD_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    robust_logD_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                        const double* __restrict__ cst, const double* __restrict__ gk,
                        double* __restrict__ logD, unsigned* __restrict__ bad_out) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,14 +457,14 @@ __global__ void __launch_bounds__(256)
   if (n < N) {
     double m = -INFINITY;
     for (int k = 0; k < K; ++k) {
-      const double a = cst[k] - u[(int64_t)k * ld + n];
+      const double a = cst[k] - (double)u[(int64_t)k * ld + n];
       if (gk[k] != 0.0) m = fmax(m, a);
       if (a != a || a == INFINITY) bad |= FLAG_NAN;
     }
     double D = 0.0;
     if (m > -INFINITY && m < INFINITY) {
       for (int k = 0; k < K; ++k)
-        if (gk[k] != 0.0) D += exp_nonpos(cst[k] - u[(int64_t)k * ld + n] - m);
+        if (gk[k] != 0.0) D += exp_nonpos(cst[k] - (double)u[(int64_t)k * ld + n] - m);
       logD[n] = m + log(D);
     } else {
       logD[n] = m;
@@ -497,8 +498,9 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
   }
 }
 
+template <typename TI>
 __global__ void __launch_bounds__(kRobustThreads)
-    robust_state_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    robust_state_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                         const double* __restrict__ h, const double* __restrict__ logD,
                         double* __restrict__ partM, double* __restrict__ partS,
                         double* __restrict__ part_obj) {
@@ -527,7 +529,7 @@ __global__ void __launch_bounds__(kRobustThreads)
     for (int i = 0; i < kRobustPerThread; ++i) {
       const int64_t n = base + tid + (int64_t)i * kRobustThreads;
       if (n < N) {
-        const double t = lh[i] - u[(int64_t)k * ld + n] - lD[i];
+        const double t = lh[i] - (double)u[(int64_t)k * ld + n] - lD[i];
         lse_merge(m, s, t, 1.0);
       }
     }
@@ -563,18 +565,30 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_sweep_robust(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
-                               const double* cst, const double* gk, const double* h,
-                               double* logD, double* partM, double* partS, double* part_obj,
-                               unsigned* part_flags, int chunks) {
+template <typename TI>
+static hipError_t launch_robust_t(hipStream_t s, const TI* u, int64_t ld, int K, int64_t N,
+                                  const double* cst, const double* gk, const double* h,
+                                  double* logD, double* partM, double* partS, double* part_obj,
+                                  unsigned* part_flags, int chunks) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3((chunks + 255) / 256), dim3(256), 0, s, part_flags,
                      chunks);
   const int64_t nb = (N + 255) / 256;
-  hipLaunchKernelGGL(robust_logD_kernel, dim3((unsigned)nb), dim3(256), 0, s, u, ld, K, N, cst,
+  hipLaunchKernelGGL(robust_logD_kernel<TI>, dim3((unsigned)nb), dim3(256), 0, s, u, ld, K, N, cst,
                      gk, logD, part_flags);
-  hipLaunchKernelGGL(robust_state_kernel, dim3(chunks), dim3(kRobustThreads), 0, s, u, ld, K, N,
-                     h, logD, partM, partS, part_obj);
+  hipLaunchKernelGGL(robust_state_kernel<TI>, dim3(chunks), dim3(kRobustThreads), 0, s, u, ld, K,
+                     N, h, logD, partM, partS, part_obj);
   return hipGetLastError();
+}
+
+hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
+                               const double* cst, const double* gk, const double* h,
+                               double* logD, double* partM, double* partS, double* part_obj,
+                               unsigned* part_flags, int chunks) {
+  if (f32)
+    return launch_robust_t<float>(s, reinterpret_cast<const float*>(u), ld, K, N, cst, gk, h, logD,
+                                  partM, partS, part_obj, part_flags, chunks);
+  return launch_robust_t<double>(s, reinterpret_cast<const double*>(u), ld, K, N, cst, gk, h, logD,
+                                 partM, partS, part_obj, part_flags, chunks);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,8 +834,9 @@ hipError_t launch_max_abs_diff(hipStream_t s, int K, const double* a, const doub
 // W_nk = exp(f_k - u_kn - ln D_n), N x K output; 32 x 32 tiles transposed
 // through shared memory so both the read of u (along n) and the write of W
 // (along k) are coalesced.
+template <typename TI>
 __global__ void __launch_bounds__(256)
-    weights_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    weights_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                    const double* __restrict__ f, const double* __restrict__ logD,
                    double* __restrict__ W) {
   __shared__ double tile[32][33];
@@ -833,7 +848,7 @@ __global__ void __launch_bounds__(256)
     const int64_t n = n0 + tx;
     double v = 0.0;
     if (k < K && n < N) {
-      const double x = f[k] - u[(int64_t)k * ld + n] - logD[n];
+      const double x = f[k] - (double)u[(int64_t)k * ld + n] - logD[n];
       v = exp(x);
     }
     tile[r][tx] = v;
@@ -846,10 +861,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-hipError_t launch_weights(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+hipError_t launch_weights(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                           const double* f, const double* logD, double* W) {
   dim3 grid((unsigned)((N + 31) / 32), (unsigned)((K + 31) / 32));
-  hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, s, u, ld, K, N, f, logD, W);
+  if (f32)
+    hipLaunchKernelGGL(weights_kernel<float>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(u), ld, K, N, f, logD, W);
+  else
+    hipLaunchKernelGGL(weights_kernel<double>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(u), ld, K, N, f, logD, W);
   return hipGetLastError();
 }
 

@@ -218,3 +218,59 @@ def test_invalid_inputs_raise(bm):
     bad[1, 5] = np.nan
     with pytest.raises(bm.BumbarError):
         bm.solve(dev(bad), Nk)
+
+
+@pytest.mark.parametrize("K,N", [(5, 999), (100, 3001), (300, 2000)])
+def test_fp32_input_sweep_matches_oracle_on_widened_values(bm, K, N):
+    # FP32 u is widened to FP64 on load: the exact reference is the oracle on
+    # the float-rounded values
+    import torch
+    u, Nk, _ = random_problem(K, N, seed=K + 3 * N)
+    u32 = u.astype(np.float32)
+    f = np.concatenate([[0.0], np.random.default_rng(3).normal(0, 0.2, K - 1)])
+    fn_ref, lD_ref = oracle.sci_step(u32.astype(np.float64), Nk, f, return_logD=True)
+    fn, lD, S, st = bm.sweep(torch.as_tensor(u32).cuda(), Nk, f)
+    assert np.max(np.abs(fn.cpu().numpy() - fn_ref)) < 1e-12
+    assert np.max(np.abs(lD.cpu().numpy() - lD_ref)) < 1e-12 * max(1.0, np.abs(lD_ref).max())
+
+
+@pytest.mark.parametrize("cfg", ["harmonic", "double_well", "ladder"])
+def test_mixed_precision_solve_matches_fp64_oracle(bm, cfg):
+    say(f"mixed precision solve {cfg}")
+    if cfg == "harmonic":
+        p = synth.harmonic_1d(K=8, Nk=1500, seed=2)
+    elif cfg == "double_well":
+        p = synth.double_well(K=50, Nk=400, seed=7)
+    else:
+        p = synth.ladder_2d(K=120, Nk=60, seed=3)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       precision=bm.PREC_MIXED, tol=1e-11)
+    err = np.max(np.abs(f.cpu().numpy() - f_ref))
+    say(f"  mixed steps {info['mixed_steps']} fp64 steps {info['finisher_steps'] - info['mixed_steps']}"
+        f" err {err:.2e}")
+    assert info["mixed_steps"] >= 1
+    assert err < 1e-9
+
+
+def test_mixed_precision_fp32_stage_accuracy(bm):
+    # stopping right after the FP32 stage (loose tol) already lands within
+    # 1e-4 kT; the refinement is what reaches the FP64 tolerance
+    p = synth.double_well(K=40, Nk=500, seed=8)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       precision=bm.PREC_MIXED, tol=1e-3, mixed_tol=1e-3)
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-3
+
+
+def test_hessian_fp32_input(bm):
+    import torch
+    K, N = 70, 2000
+    u, Nk, _ = random_problem(K, N, seed=21)
+    u32 = u.astype(np.float32)
+    f = np.concatenate([[0.0], np.random.default_rng(5).normal(0, 0.2, K - 1)])
+    H_ref = oracle.hessian(u32.astype(np.float64), Nk, f)
+    ud = torch.as_tensor(u32).cuda()
+    fn, lD, S, _ = bm.sweep(ud, Nk, f)
+    H = bm.hessian(ud, Nk, f, lD, S).cpu().numpy()
+    assert np.max(np.abs(H - H_ref)) < 1e-12 * np.abs(H_ref).max()
