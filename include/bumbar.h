@@ -224,6 +224,76 @@ int bumbar_bin(bumbar_ctx* ctx, const double* xi, int64_t N, int d, int64_t n_ta
 int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const double* log_D_n,
                     void* workspace, size_t ws_bytes, double* p);
 
+/* ---- batched serving ---------------------------------------------------
+ *
+ * A server keeps up to max_active MBAR problems resident on one device and
+ * solves them concurrently (one HIP stream and context per active slot, so
+ * the kernels of different problems overlap on the GPU); new requests are
+ * admitted in arrival order as soon as a slot is free and the problem's
+ * device footprint (its u_kn, inputs and solver workspace) fits in the
+ * server's memory arena, which is reserved once at creation. Each problem is
+ * solved by exactly the kernels and launch shapes of bumbar_solve, so its
+ * result is bitwise the same alone and in the mix.
+ */
+typedef struct bumbar_server bumbar_server;
+
+typedef struct {
+  int device;               /* HIP device                                              */
+  size_t hbm_budget_bytes;  /* device memory reserved for resident requests            */
+  int max_active;           /* problems solved concurrently (>= 1)                     */
+} bumbar_server_options;
+
+typedef struct {
+  int K;
+  int64_t N;
+  const double* u_kn;   /* host K x N FP64, or NULL: u_kn = model(xi) is built on the device */
+  const int64_t* N_k;   /* host, K entries                                               */
+  const double* xi;     /* host N x d coordinates (binning and/or model), or NULL        */
+  int d;                /* coordinate dimension (0 if xi is NULL)                         */
+  int model;            /* BUMBAR_MODEL_*                                                */
+  const double* coef;   /* host K x (1 + 2d) model coefficients, or NULL                  */
+  bumbar_options opt;   /* solve options                                                 */
+} bumbar_request;
+
+#define BUMBAR_TICKET_QUEUED 0
+#define BUMBAR_TICKET_RUNNING 1
+#define BUMBAR_TICKET_DONE 2
+#define BUMBAR_TICKET_FAILED 3
+
+/* Reserve the memory arena and start max_active worker slots. */
+int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out);
+/* Queue a request. The host arrays it points to must stay valid until the
+ * ticket is DONE or FAILED. BUMBAR_ETOOBIG if its footprint exceeds the
+ * whole arena. */
+int bumbar_server_submit(bumbar_server* srv, const bumbar_request* req, uint64_t* ticket);
+/* State of a ticket (BUMBAR_TICKET_*); EINVAL for an unknown ticket. */
+int bumbar_server_poll(bumbar_server* srv, uint64_t ticket, int* state);
+/* Block until the ticket is DONE or FAILED. */
+int bumbar_server_wait(bumbar_server* srv, uint64_t ticket);
+/* Result of a finished ticket: f_k (host, K entries, or NULL), statistics
+ * (host, may be NULL; its checks array is not filled), latency from
+ * submission to completion in ms, and the solve's status code. The ticket
+ * is released: a second call (or a poll) returns EINVAL. EBUSY if the ticket
+ * has not finished (it is then kept). */
+int bumbar_server_result(bumbar_server* srv, uint64_t ticket, double* f_k_host,
+                         bumbar_stats* stats, double* latency_ms, int* status);
+/* Counters: completed requests, largest number of problems on the device
+ * at once, largest arena use in bytes. */
+int bumbar_server_counters(bumbar_server* srv, int64_t* completed, int64_t* peak_active,
+                           size_t* peak_bytes);
+/* Let running requests finish, fail the ones still queued (status
+ * BUMBAR_EBUSY), stop the slots and release the arena. */
+void bumbar_server_destroy(bumbar_server* srv);
+
+/* u_kn = model_k(xi_n) on the device (K x N, row stride N): the reduced
+ * energies of the LINEAR / HARMONIC models (layout of coef as in
+ * bumbar_solve) for N coordinates xi (N x d, d in {1, 2}); every pointer is
+ * device memory owned by the caller. Any potential common to all states is
+ * left out, since it cancels in Eq. (1). Stream-ordered on the context's
+ * stream (does not synchronise); EINVAL for a bad argument. */
+int bumbar_model_energies(bumbar_ctx* ctx, int K, int64_t N, int d, int model,
+                          const double* coef, const double* xi, double* u_kn);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,
                     PREC_FP64, PREC_MIXED)
 
 __all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight",
+           "model_energies", "Server",
            "BumbarError", "default_options"]
 
 
@@ -297,3 +298,139 @@ def reweight(u_target, logD, ctx=None):
                                  _ptr(p))
     ctx.check(rc)
     return p
+
+
+def model_energies(xi, coef, model, K, ctx=None):
+    """u_kn = model_k(xi_n) (K x N, FP64) built on the device from coordinates xi (N x d)."""
+    torch = _torch()
+    ctx = ctx or context()
+    dev = torch.device(f"cuda:{ctx.device}")
+    xi_t = _dev(xi, torch.float64, dev)
+    if xi_t.dim() == 1:
+        xi_t = xi_t[:, None].contiguous()
+    N, d = xi_t.shape
+    coef_t = _dev(coef, torch.float64, dev)
+    u = torch.empty((K, N), dtype=torch.float64, device=dev)
+    rc = ctx.lib.bumbar_model_energies(ctx.h, int(K), int(N), int(d), int(model), _ptr(coef_t),
+                                       _ptr(xi_t), _ptr(u))
+    _keep(ctx, xi_t, coef_t)
+    ctx.check(rc)
+    return u
+
+
+class Server:
+    """Continuous batching of independent solves on one device.
+
+    ``submit`` takes host (numpy) arrays and returns a ticket; the server
+    admits requests in arrival order whenever a slot is free and the problem
+    fits in the device arena of ``hbm_budget_bytes`` reserved at creation.
+    The arrays are held here until the ticket's result has been read.
+    """
+
+    def __init__(self, hbm_budget_bytes, max_active=4, device=None):
+        import numpy  # noqa: F401  (requests are host arrays)
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libbumbar needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = _capi.load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        o = _capi.ServerOptions(dev, int(hbm_budget_bytes), int(max_active))
+        h = C.c_void_p()
+        rc = self.lib.bumbar_server_create(C.byref(o), C.byref(h))
+        if rc != 0:
+            raise BumbarError(rc, "bumbar_server_create failed")
+        self.h = h
+        self._held = {}
+
+    def submit(self, Nk, u=None, xi=None, model=MODEL_NONE, coef=None, K=None, binning=None,
+               **options):
+        """Queue one problem. Give u (K x N float64), or xi + model + coef (u built on device)."""
+        import numpy as np
+        if "replay" in options:
+            raise ValueError("replayed schedules are not supported by the server")
+        if u is None and (xi is None or coef is None or model == MODEL_NONE):
+            raise ValueError("give u, or xi with a model and its coefficients")
+        arrs = {}
+        if u is not None:
+            arrs["u"] = np.ascontiguousarray(u, dtype=np.float64)
+            K, N = arrs["u"].shape
+        arrs["Nk"] = np.ascontiguousarray(Nk, dtype=np.int64)
+        K = int(K if K is not None else arrs["Nk"].shape[0])
+        d = 0
+        if xi is not None:
+            x = np.ascontiguousarray(xi, dtype=np.float64)
+            if x.ndim == 1:
+                x = x[:, None]
+            arrs["xi"] = x
+            N, d = x.shape
+        if coef is not None:
+            arrs["coef"] = np.ascontiguousarray(coef, dtype=np.float64)
+        if binning is None:
+            binning = xi is not None
+        req = _capi.Request()
+        req.K, req.N, req.d, req.model = K, int(N), int(d), int(model)
+
+        def p(name):
+            a = arrs.get(name)
+            return C.c_void_p(a.ctypes.data) if a is not None else None
+
+        req.u_kn, req.N_k, req.xi, req.coef = p("u"), p("Nk"), p("xi"), p("coef")
+        req.opt = default_options(binning=int(bool(binning)), **options)
+        t = C.c_uint64()
+        rc = self.lib.bumbar_server_submit(self.h, C.byref(req), C.byref(t))
+        if rc != 0:
+            raise BumbarError(rc, "bumbar_server_submit failed")
+        self._held[t.value] = (arrs, K)
+        return t.value
+
+    def poll(self, ticket):
+        s = C.c_int()
+        rc = self.lib.bumbar_server_poll(self.h, C.c_uint64(ticket), C.byref(s))
+        if rc != 0:
+            raise BumbarError(rc, "unknown ticket")
+        return s.value
+
+    def wait(self, ticket):
+        rc = self.lib.bumbar_server_wait(self.h, C.c_uint64(ticket))
+        if rc != 0:
+            raise BumbarError(rc, "unknown ticket")
+
+    def result(self, ticket, wait=True):
+        """(f as numpy float64, info) of a finished ticket; waits for it by default.
+
+        The ticket is released once its result has been read."""
+        import numpy as np
+        if wait:
+            self.wait(ticket)
+        _, K = self._held[ticket]
+        f = np.empty(K, dtype=np.float64)
+        st = _capi.Stats()
+        lat = C.c_double()
+        status = C.c_int()
+        rc = self.lib.bumbar_server_result(self.h, C.c_uint64(ticket), C.c_void_p(f.ctypes.data),
+                                           C.byref(st), C.byref(lat), C.byref(status))
+        if rc != 0:
+            raise BumbarError(rc, "result not available")
+        info = {name: getattr(st, name) for name, _ in _capi.Stats._fields_
+                if name not in ("checks", "checks_capacity")}
+        info["latency_ms"] = lat.value
+        info["status"] = status.value
+        del self._held[ticket]
+        return f, info
+
+    def counters(self):
+        c, a, b = C.c_int64(), C.c_int64(), C.c_size_t()
+        self.lib.bumbar_server_counters(self.h, C.byref(c), C.byref(a), C.byref(b))
+        return dict(completed=c.value, peak_active=a.value, peak_bytes=b.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bumbar_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

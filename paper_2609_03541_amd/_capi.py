@@ -29,6 +29,10 @@ FINISH_SCI = 1
 MODEL_NONE = 0
 MODEL_LINEAR = 1
 MODEL_HARMONIC = 2
+TICKET_QUEUED = 0
+TICKET_RUNNING = 1
+TICKET_DONE = 2
+TICKET_FAILED = 3
 
 
 class Check(C.Structure):
@@ -59,6 +63,16 @@ class Stats(C.Structure):
                 ("checks_capacity", C.c_int)]
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int)]
+
+
+class Request(C.Structure):
+    _fields_ = [("K", C.c_int), ("N", C.c_int64), ("u_kn", C.c_void_p), ("N_k", C.c_void_p),
+                ("xi", C.c_void_p), ("d", C.c_int), ("model", C.c_int), ("coef", C.c_void_p),
+                ("opt", Options)]
+
+
 # name -> (restype, argtypes); the full exported surface of include/bumbar.h
 vp, dp, i64p, u64p, i32p = (C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                             C.POINTER(C.c_uint64), C.POINTER(C.c_int32))
@@ -81,6 +95,15 @@ SIGNATURES = {
     "bumbar_bin": (C.c_int, [vp, vp, C.c_int64, C.c_int, C.c_int64, vp, C.c_size_t, u64p, i64p,
                              vp, vp, vp]),
     "bumbar_reweight": (C.c_int, [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
+    "bumbar_model_energies": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, vp]),
+    "bumbar_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(C.c_void_p)]),
+    "bumbar_server_submit": (C.c_int, [vp, C.POINTER(Request), u64p]),
+    "bumbar_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int)]),
+    "bumbar_server_wait": (C.c_int, [vp, C.c_uint64]),
+    "bumbar_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(Stats), dp,
+                                       C.POINTER(C.c_int)]),
+    "bumbar_server_counters": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_size_t)]),
+    "bumbar_server_destroy": (None, [vp]),
 }
 
 _lib = None

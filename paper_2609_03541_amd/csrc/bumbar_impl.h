@@ -127,6 +127,9 @@ hipError_t launch_sweep32(hipStream_t s, const float* r, int64_t ld, int K, int6
 // the unsampled ones). A: workspace K*K doubles, idx: K ints. ok: device int.
 hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, const double* H,
                                    const double* S, double* A, int* idx, double* d, int* ok);
+// u_kn = model_k(xi_n), K x N FP64 with row stride N; d in {1, 2}.
+hipError_t launch_model_energies(hipStream_t s, int K, int64_t N, int d, int model,
+                                 const double* coef, const double* xi, double* u);
 
 }  // namespace bumbar
 

@@ -104,14 +104,15 @@ hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, cons
   const int mmax = K - 1;
   if (mmax <= kLdsMaxM) {
     const size_t lds = sizeof(double) * ((size_t)mmax * mmax + 3 * mmax + 1);
-    static size_t attr = 0;  // raise the dynamic LDS limit when a larger size is needed
-    if (lds > attr) {
+    // raise the dynamic LDS limit once to the largest size this kernel uses
+    static const bool attr = [] {
+      const size_t mx = sizeof(double) * ((size_t)kLdsMaxM * kLdsMaxM + 3 * kLdsMaxM + 1);
       if (hipFuncSetAttribute(reinterpret_cast<const void*>(&newton_direction_kernel<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-        (void)hipGetLastError();  // clear; the launch below reports a real failure
-      }
-      attr = lds;
-    }
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx) != hipSuccess)
+        (void)hipGetLastError();  // clear; a launch that still fails reports it
+      return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL(newton_direction_kernel<true>, dim3(1), dim3(kLT), lds, s, K, Nk, H, S, A,
                        idx, d, ok);
   } else {

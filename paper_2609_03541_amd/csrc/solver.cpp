@@ -504,6 +504,18 @@ int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const do
   return BUMBAR_OK;
 }
 
+int bumbar_model_energies(bumbar_ctx* ctx, int K, int64_t N, int d, int model,
+                          const double* coef, const double* xi, double* u_kn) {
+  if (!ctx) return BUMBAR_EINVAL;
+  ctx->err.clear();
+  if (K <= 0 || N <= 0 || (d != 1 && d != 2) || !coef || !xi || !u_kn ||
+      (model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC))
+    return fail(ctx, BUMBAR_EINVAL, "bad argument");
+  const hipError_t e = launch_model_energies(ctx->stream, K, N, d, model, coef, xi, u_kn);
+  if (e != hipSuccess) return hip_fail(ctx, e, "model energies");
+  return BUMBAR_OK;
+}
+
 // Extra device buffers of the mixed-precision finisher.
 struct MixedBufs {
   float* r = nullptr;     // K x N packed matrix

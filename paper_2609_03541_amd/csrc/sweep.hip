@@ -350,11 +350,11 @@ static const FastCfg kTune[] = {
     {0, 8, 32, 2, 7, 1, 0},  {0, 8, 32, 2, 7, 0, 0},  {0, 4, 64, 2, 8, 1, 0},
 };
 
-static const FastCfg* pick_cfg(int K) {
-  static FastCfg forced{};
-  static int forced_state = -1;
-  if (forced_state < 0) {
-    forced_state = 0;
+static FastCfg read_forced_cfg(int* state) {
+  FastCfg forced{};
+  *state = 0;
+  {
+    int& forced_state = *state;
     if (const char* e = getenv("BUMBAR_SWEEP_CFG")) {
       FastCfg c{};
       if (sscanf(e, "%d,%d,%d,%d,%d,%d", &c.nw, &c.lpr, &c.cpl, &c.rows, &c.pf, &c.sg) == 6) {
@@ -366,14 +366,20 @@ static const FastCfg* pick_cfg(int K) {
           if (same(t)) forced_state = 1;
         for (const auto& t : kCfgs)
           if (same(t)) forced_state = 1;
-        if (forced_state) forced = c;
+        if (*state) {
+          forced = c;
+          forced.kmax = (c.nw * 64 / c.lpr) * c.rows;
+        }
       }
     }
   }
-  if (forced_state == 1) {
-    forced.kmax = (forced.nw * 64 / forced.lpr) * forced.rows;
-    return K <= forced.kmax ? &forced : nullptr;
-  }
+  return forced;
+}
+
+static const FastCfg* pick_cfg(int K) {
+  static int forced_state = 0;
+  static FastCfg forced = read_forced_cfg(&forced_state);  // thread-safe one-time init
+  if (forced_state == 1) return K <= forced.kmax ? &forced : nullptr;
   for (const auto& c : kCfgs)
     if (K <= c.kmax) return &c;
   return nullptr;
@@ -392,14 +398,13 @@ static hipError_t launch_cfg(hipStream_t s, bool vec, const double* u, int64_t l
   const int64_t ntiles = (N + TN - 1) / TN;
   auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG>;
   auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG>;
-  // resident workgroups per CU of this instantiation (queried once)
-  static int per_cu = 0;
-  if (per_cu == 0) {
+  // resident workgroups per CU of this instantiation (queried once, thread-safe)
+  static const int per_cu = [&] {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kv, NW * 64, 0) != hipSuccess || nb < 1)
       nb = 1;
-    per_cu = nb;
-  }
+    return nb;
+  }();
   int64_t g = (int64_t)num_cus * per_cu;
   if (g > ntiles) g = ntiles;
   if (g > sweep_max_grid(num_cus)) g = sweep_max_grid(num_cus);

@@ -242,15 +242,14 @@ static hipError_t launch32_t(hipStream_t s, const float* r, int64_t ld, int K, i
                              double* part, double* part_obj, unsigned* pf, int num_cus,
                              int* grid_out) {
   const int64_t ntiles = (N + 63) / 64;
-  static int per_cu = 0;
-  if (per_cu == 0) {
+  static const int per_cu = [] {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep32_kernel<NW, ROWS>, NW * 64, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
-    per_cu = nb;
-  }
+    return nb;
+  }();
   int64_t g = (int64_t)num_cus * per_cu;
   if (g > ntiles) g = ntiles;
   if (g > sweep_max_grid(num_cus)) g = sweep_max_grid(num_cus);

@@ -157,13 +157,15 @@ static hipError_t launch_wide_t(hipStream_t s, const TI* u, int64_t ld, int K, i
   const int G = wide_grid(N, num_cus);
   *grid_out = G;
   const size_t lds = sizeof(double) * (size_t)K;
-  static size_t attr = 0;
-  if (lds > 48 * 1024 && lds > attr) {
+  // allow up to 144 KB of dynamic LDS (K <= 18432 states) once
+  static const bool attr = [] {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&wide_colpass_kernel<TI>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024) != hipSuccess)
       (void)hipGetLastError();
-    attr = lds;
-  }
+    return true;
+  }();
+  (void)attr;
+  if (lds > 144 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(wide_colpass_kernel<TI>, dim3(G), dim3(kWA), lds, s, u, ld, K, N, cst, gk, h,
                      logD, part_obj, part_flags);
   dim3 gb(G, (K + kWBStates - 1) / kWBStates);

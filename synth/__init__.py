@@ -61,7 +61,8 @@ def _problem(u, Nk, xi, model_type, coef, **meta):
     return out
 
 
-def harmonic_1d(K=8, Nk=1000, seed=0, kappa_range=(0.5, 4.0), x_range=(-2.0, 2.0)):
+def harmonic_1d(K=8, Nk=1000, seed=0, kappa_range=(0.5, 4.0), x_range=(-2.0, 2.0),
+                materialize=True):
     """K 1-D harmonic wells u_k(x) = kappa_k (x - x_k)^2 / 2 at beta = 1.
 
     kappa_k ~ U[0.5, 4] (all K drawn first), then x_k ~ U[-2, 2]; state k
@@ -74,7 +75,7 @@ def harmonic_1d(K=8, Nk=1000, seed=0, kappa_range=(0.5, 4.0), x_range=(-2.0, 2.0
     counts = np.full(K, Nk, dtype=np.int64) if np.isscalar(Nk) else np.asarray(Nk, np.int64)
     xs = [g.normal(x0[k], 1.0 / math.sqrt(kappa[k]), int(counts[k])) for k in range(K)]
     x = np.concatenate(xs) if len(xs) else np.zeros(0)
-    u = _harmonic_u(x, kappa, x0)
+    u = _harmonic_u(x, kappa, x0) if materialize else None
     coef = np.zeros((K, 3))
     coef[:, 1] = kappa
     coef[:, 2] = x0
@@ -218,7 +219,7 @@ def muller_brown_grid(G=40, Nk=5000, kappa=20.0, seed=4, burn=1000, thin=5, sigm
     return prob
 
 
-def double_well_iid(K, Nk, kappa, seed, span=(-1.5, 1.5), grid=8192):
+def double_well_iid(K, Nk, kappa, seed, span=(-1.5, 1.5), grid=8192, materialize=True):
     """Independent draws from each biased double-well window by inverse CDF on a grid.
 
     Used for the serving stream, where running hundreds of Metropolis chains
@@ -238,7 +239,9 @@ def double_well_iid(K, Nk, kappa, seed, span=(-1.5, 1.5), grid=8192):
         idx = np.searchsorted(cdf, r)
         parts.append(xs[np.minimum(idx, grid - 1)] + (g.random(int(Nk[k])) - 0.5) * dxg)
     x = np.concatenate(parts)
-    u = double_well_potential(x)[None, :] + _harmonic_u(x, np.full(K, kappa), xc)
+    u = None
+    if materialize:
+        u = double_well_potential(x)[None, :] + _harmonic_u(x, np.full(K, kappa), xc)
     coef = np.zeros((K, 3))
     coef[:, 1] = kappa
     coef[:, 2] = xc
@@ -274,12 +277,14 @@ def serving_stream(n_problems=512, seed=3, K_range=(4, 256), Nk_range=(100, 2000
     return out
 
 
-def materialize_problem(spec):
+def materialize_problem(spec, materialize=True):
+    """Build a stream problem; ``materialize=False`` leaves u to the model (u = None)."""
     if spec["kind"] == "harmonic":
-        return harmonic_1d(K=spec["K"], Nk=spec["Nk"], seed=spec["seed"])
+        return harmonic_1d(K=spec["K"], Nk=spec["Nk"], seed=spec["seed"],
+                           materialize=materialize)
     K = spec["K"]
     kappa = 50.0 * ((K - 1) / 99.0) ** 2
-    return double_well_iid(K, spec["Nk"], kappa, spec["seed"])
+    return double_well_iid(K, spec["Nk"], kappa, spec["seed"], materialize=materialize)
 
 
 def config(i, seed=None, scale=1.0):

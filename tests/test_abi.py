@@ -47,11 +47,23 @@ def test_default_options_are_the_papers_settings(lib):
 
 
 def test_version_and_null_context(lib):
+    from paper_2609_03541_amd import _capi
     assert lib.bumbar_version().decode().startswith("bumbar")
     assert lib.bumbar_last_error(None) == b""
     assert lib.bumbar_create(None, 0, None) == -1
     nb = C.c_size_t()
     assert lib.bumbar_query_workspace(None, 4, 10, 0, None, C.byref(nb)) == -1
+    assert lib.bumbar_model_energies(None, 4, 10, 1, 2, None, None, None) == -1
+    srv = C.c_void_p()
+    assert lib.bumbar_server_create(None, C.byref(srv)) == -1
+    bad = _capi.ServerOptions(0, 1 << 20, 0)  # max_active < 1 is rejected before any HIP call
+    assert lib.bumbar_server_create(C.byref(bad), C.byref(srv)) == -1
+    t = C.c_uint64()
+    assert lib.bumbar_server_submit(None, None, C.byref(t)) == -1
+    assert lib.bumbar_server_poll(None, 1, None) == -1
+    assert lib.bumbar_server_wait(None, 1) == -1
+    assert lib.bumbar_server_counters(None, None, None, None) == -1
+    lib.bumbar_server_destroy(None)
 
 
 def test_struct_layouts_match_header():
@@ -59,7 +71,9 @@ def test_struct_layouts_match_header():
     from paper_2609_03541_amd import _capi
     text = open(os.path.join(ROOT, "include", "bumbar.h")).read()
     for struct, cls in [("bumbar_options", _capi.Options), ("bumbar_stats", _capi.Stats),
-                        ("bumbar_check", _capi.Check)]:
+                        ("bumbar_check", _capi.Check),
+                        ("bumbar_server_options", _capi.ServerOptions),
+                        ("bumbar_request", _capi.Request)]:
         m = re.search(r"typedef struct \{((?:(?!typedef).)*?)\}\s*" + struct + ";", text,
                       flags=re.S)
         body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
