@@ -142,12 +142,23 @@ void bumbar_default_options(bumbar_options* opt);
 int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
                            const bumbar_options* opt, size_t* bytes);
 
+/* Bytes of device workspace bumbar_solve needs when u_kn is NULL (energies
+ * from the model, d-dimensional coordinates, d in {1, 2}). */
+int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
+                                 const bumbar_options* opt, size_t* bytes);
+
 /* ---- solve ------------------------------------------------------------ */
 
 /*
  * Solve the MBAR equations.
  *  u_kn     K x N (row stride N), dtype u_dtype. With precision MIXED, an
  *           FP64 u_kn is packed to FP32 internally (in the workspace).
+ *           NULL: the energies are the model's (HARMONIC or LINEAR, coef
+ *           and xi required, d in {1, 2}), evaluated inside the kernels at
+ *           every use and never stored; size the workspace with
+ *           bumbar_query_workspace_model. With precision MIXED the Newton
+ *           stage then runs on FP32 model sweeps (FP32 coordinates) before
+ *           the FP64 refinement.
  *  N_k      K int64.
  *  xi       N x d float64 binning coordinates (row-major), d in {1, 2};
  *           required when opt->binning = 1, else may be NULL.
@@ -199,6 +210,25 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
                    int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
                    const double* S, void* workspace, size_t ws_bytes, double* H);
 
+/*
+ * The same single sweep and Hessian with u_kn taken from the model (the
+ * on-the-fly kinds of bumbar_solve with u_kn = NULL): coef K x (1 + 2d),
+ * xi N x d float64 (device). precision BUMBAR_PREC_FP64 evaluates the model
+ * and the exponentials in FP64; BUMBAR_PREC_MIXED in FP32 (coordinates
+ * rounded to FP32, log2-domain expanded quadratic, hardware exp2) with FP64
+ * partial sums. Workspace: bumbar_query_workspace_model(ctx, K, N, d, NULL).
+ * Both synchronise; an FP32 sweep whose sums leave the FP32 range returns
+ * BUMBAR_EINVAL.
+ */
+int bumbar_sweep_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
+                       const double* xi, int precision, const int64_t* N_k, const double* f,
+                       void* workspace, size_t ws_bytes, double* f_new, double* log_D_n,
+                       double* S, double* sweep_stats);
+int bumbar_hessian_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
+                         const double* xi, int precision, const int64_t* N_k, const double* f,
+                         const double* log_D_n, const double* S, void* workspace,
+                         size_t ws_bytes, double* H);
+
 /* W_nk = exp(f_k - u_kn - ln D_n), N x K float64 (sample-major). */
 int bumbar_weights(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
                    const double* f, const double* log_D_n, double* W_nk);
@@ -246,7 +276,7 @@ typedef struct {
 typedef struct {
   int K;
   int64_t N;
-  const double* u_kn;   /* host K x N FP64, or NULL: u_kn = model(xi) is built on the device */
+  const double* u_kn;   /* host K x N FP64, or NULL: energies from the model (in-kernel)  */
   const int64_t* N_k;   /* host, K entries                                               */
   const double* xi;     /* host N x d coordinates (binning and/or model), or NULL        */
   int d;                /* coordinate dimension (0 if xi is NULL)                         */

@@ -17,7 +17,7 @@ from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,
                     PREC_FP64, PREC_MIXED)
 
 __all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight",
-           "model_energies", "Server",
+           "model_energies", "sweep_model", "hessian_model", "Server",
            "BumbarError", "default_options"]
 
 
@@ -143,6 +143,8 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
           want_weights=False, want_logD=False, ctx=None, checks_capacity=256, **options):
     """Solve the MBAR equations for u (K x N) and counts Nk (K).
 
+    ``u = None`` takes the energies from the model (``xi``, ``model``,
+    ``coef`` required): they are evaluated inside the kernels, never stored.
     ``binning`` defaults to True when coordinates ``xi`` (N x d) are given.
     Keyword options are the fields of ``bumbar_options`` (tol, precision,
     n0, eps, inc, n_intermediate, finisher, max_iter, max_newton, sci_switch).
@@ -153,10 +155,11 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     torch = _torch()
     ctx = ctx or context()
     dev = torch.device(f"cuda:{ctx.device}")
-    if not (torch.is_tensor(u) and u.is_cuda):
-        u = torch.as_tensor(u)
-    u = u.to(dev).contiguous()
-    K, N = u.shape
+    if u is not None:
+        if not (torch.is_tensor(u) and u.is_cuda):
+            u = torch.as_tensor(u)
+        u = u.to(dev).contiguous()
+        K, N = u.shape
     Nk_t = _dev(Nk, torch.int64, dev)
     d = 0
     xi_t = None
@@ -165,6 +168,11 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
         if xi_t.dim() == 1:
             xi_t = xi_t[:, None].contiguous()
         d = xi_t.shape[1]
+    if u is None:
+        # energies from the model, evaluated inside the kernels
+        if xi_t is None or coef is None or model == MODEL_NONE:
+            raise ValueError("u = None needs xi, a model and its coefficients")
+        K, N = Nk_t.numel(), xi_t.shape[0]
     if binning is None:
         binning = xi is not None
     replay = options.pop("replay", None)
@@ -178,7 +186,13 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
         opts.n_replay = len(replay[1])
     coef_t = _dev(coef, torch.float64, dev) if coef is not None else None
     f_init_t = _dev(f_init, torch.float64, dev) if f_init is not None else None
-    nbytes = ctx.query_workspace(K, N, d if binning else 0, opts)
+    if u is None:
+        nb = C.c_size_t()
+        ctx.check(ctx.lib.bumbar_query_workspace_model(ctx.h, K, N, d, C.byref(opts),
+                                                       C.byref(nb)))
+        nbytes = nb.value
+    else:
+        nbytes = ctx.query_workspace(K, N, d if binning else 0, opts)
     ws = ctx.workspace(nbytes)
     f = torch.empty(K, dtype=torch.float64, device=dev)
     W = torch.empty((N, K), dtype=torch.float64, device=dev) if want_weights else None
@@ -187,7 +201,7 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     chk = (_capi.Check * max(1, checks_capacity))()
     st.checks = C.cast(chk, C.POINTER(_capi.Check))
     st.checks_capacity = checks_capacity
-    rc = ctx.lib.bumbar_solve(ctx.h, _ptr(u), _dtype_code(u), K, N, _ptr(Nk_t), _ptr(xi_t), d,
+    rc = ctx.lib.bumbar_solve(ctx.h, _ptr(u), _dtype_code(u) if u is not None else F64, K, N, _ptr(Nk_t), _ptr(xi_t), d,
                               int(model), _ptr(coef_t), _ptr(f_init_t), C.byref(opts),
                               _ptr(ws), ws.numel(), _ptr(f), _ptr(W), _ptr(lD), C.byref(st))
     del keep
@@ -298,6 +312,69 @@ def reweight(u_target, logD, ctx=None):
                                  _ptr(p))
     ctx.check(rc)
     return p
+
+
+def _model_args(xi, coef, ctx):
+    torch = _torch()
+    dev = torch.device(f"cuda:{ctx.device}")
+    xi_t = _dev(xi, torch.float64, dev)
+    if xi_t.dim() == 1:
+        xi_t = xi_t[:, None].contiguous()
+    return xi_t, _dev(coef, torch.float64, dev)
+
+
+def _model_ws(ctx, K, N, d):
+    nb = C.c_size_t()
+    ctx.check(ctx.lib.bumbar_query_workspace_model(ctx.h, K, N, d, None, C.byref(nb)))
+    return ctx.workspace(nb.value)
+
+
+def sweep_model(xi, coef, model, Nk, f, precision=PREC_FP64, ctx=None):
+    """One unbinned SCI step with u from the model (FP64, or FP32 with precision=PREC_MIXED).
+
+    Returns f_new, ln D, S and the scalars (max_df, rel_step, objective, grad_norm)."""
+    torch = _torch()
+    ctx = ctx or context()
+    xi_t, coef_t = _model_args(xi, coef, ctx)
+    N, d = xi_t.shape
+    dev = xi_t.device
+    Nk_t = _dev(Nk, torch.int64, dev)
+    K = Nk_t.numel()
+    f_t = _dev(f, torch.float64, dev)
+    ws = _model_ws(ctx, K, N, d)
+    f_new = torch.empty(K, dtype=torch.float64, device=dev)
+    lD = torch.empty(N, dtype=torch.float64, device=dev)
+    S = torch.empty(K, dtype=torch.float64, device=dev)
+    stats = (C.c_double * 4)()
+    rc = ctx.lib.bumbar_sweep_model(ctx.h, K, N, d, int(model), _ptr(coef_t), _ptr(xi_t),
+                                    int(precision), _ptr(Nk_t), _ptr(f_t), _ptr(ws), ws.numel(),
+                                    _ptr(f_new), _ptr(lD), _ptr(S), stats)
+    _keep(ctx, xi_t, coef_t, Nk_t, f_t)
+    ctx.check(rc)
+    return f_new, lD, S, dict(max_df=stats[0], rel_step=stats[1], objective=stats[2],
+                              grad_norm=stats[3])
+
+
+def hessian_model(xi, coef, model, Nk, f, logD, S, precision=PREC_FP64, ctx=None):
+    """K x K Hessian of the MBAR objective with u from the model."""
+    torch = _torch()
+    ctx = ctx or context()
+    xi_t, coef_t = _model_args(xi, coef, ctx)
+    N, d = xi_t.shape
+    dev = xi_t.device
+    Nk_t = _dev(Nk, torch.int64, dev)
+    K = Nk_t.numel()
+    f_t = _dev(f, torch.float64, dev)
+    lD_t = _dev(logD, torch.float64, dev)
+    S_t = _dev(S, torch.float64, dev)
+    ws = _model_ws(ctx, K, N, d)
+    H = torch.empty((K, K), dtype=torch.float64, device=dev)
+    rc = ctx.lib.bumbar_hessian_model(ctx.h, K, N, d, int(model), _ptr(coef_t), _ptr(xi_t),
+                                      int(precision), _ptr(Nk_t), _ptr(f_t), _ptr(lD_t),
+                                      _ptr(S_t), _ptr(ws), ws.numel(), _ptr(H))
+    _keep(ctx, xi_t, coef_t, Nk_t, f_t, lD_t, S_t)
+    ctx.check(rc)
+    return H
 
 
 def model_energies(xi, coef, model, K, ctx=None):

@@ -95,6 +95,12 @@ SIGNATURES = {
     "bumbar_bin": (C.c_int, [vp, vp, C.c_int64, C.c_int, C.c_int64, vp, C.c_size_t, u64p, i64p,
                              vp, vp, vp]),
     "bumbar_reweight": (C.c_int, [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
+    "bumbar_query_workspace_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int,
+                                               C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    "bumbar_sweep_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, C.c_int, vp,
+                                     vp, vp, C.c_size_t, vp, vp, vp, dp]),
+    "bumbar_hessian_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, C.c_int,
+                                       vp, vp, vp, vp, vp, C.c_size_t, vp]),
     "bumbar_model_energies": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, vp]),
     "bumbar_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(C.c_void_p)]),
     "bumbar_server_submit": (C.c_int, [vp, C.POINTER(Request), u64p]),

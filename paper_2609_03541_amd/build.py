@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbumbar.so")
-SOURCES = ["sweep.hip", "sweep_wide.hip", "sweep32.hip", "hessian.hip", "linalg.hip", "binning.hip",
+SOURCES = ["sweep.hip", "sweep_wide.hip", "sweep32.hip", "sweep_otf.hip", "hessian.hip", "linalg.hip", "binning.hip",
            "model.hip", "solver.cpp", "algo.cpp", "server.cpp"]
 
 FLAGS = [

@@ -102,12 +102,43 @@ hipError_t launch_check_finite_f(hipStream_t s, int K, const double* f, unsigned
 
 // ---- Hessian and linear algebra (hessian.hip, linalg.hip) ----------------
 size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out);
-// utype 0: FP64 u; 1: FP32 u (widened); 2: packed mixed-precision matrix
-// (cst = d_k, m0 = per-column shift).
-hipError_t launch_hessian(hipStream_t s, const void* u, int utype, int64_t ld, int K, int64_t N,
+// Reduced energies from the bias model, evaluated inside the kernels.
+struct OtfModel {
+  const double* xi = nullptr;    // N x d FP64 coordinates
+  const float* xf = nullptr;     // N x d FP32 coordinates (FP32 kernels)
+  const double* coef = nullptr;  // K x (1 + 2d) model coefficients
+  int d = 0;
+  int model = 0;                 // BUMBAR_MODEL_LINEAR or BUMBAR_MODEL_HARMONIC
+  float* cf32 = nullptr;         // K x (2 + 2d) per-sweep FP32 coefficients
+  double* cf64 = nullptr;        // K x (2 + 2d) per-sweep FP64 coefficients
+};
+size_t otf_coef_floats(int K, int d);  // entries of cf32 (and of cf64)
+int otf_grid(int64_t N, int num_cus);
+hipError_t launch_pack_coords(hipStream_t s, int64_t n, const double* xi, float* xf);
+// Two-pass sweep with u from the model (FP32 or FP64 arithmetic); also
+// rebuilds the per-sweep coefficients from cst / gk. Partials state-major.
+hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
+                            const double* cst, const double* gk, double* logD, double* part,
+                            double* part_obj, unsigned* part_flags, int num_cus, int* grid_out);
+// Rebuilds only the per-sweep coefficients (cf32 or cf64) from cst / gk.
+hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, const double* cst,
+                            const double* gk);
+hipError_t launch_weights_otf(hipStream_t s, const OtfModel& m, int K, int64_t N, const double* f,
+                              const double* logD, double* W);
+
+// What the Hessian reads: kind 0 FP64 u; 1 FP32 u (widened); 2 packed
+// mixed-precision matrix (cst = d_k, m0 = per-column shift); 3 model in FP32
+// (otf.cf32 current); 4 model in FP64 (otf.cf64 current).
+struct HessSource {
+  int kind = 0;
+  const void* u = nullptr;
+  int64_t ld = 0;
+  const double* m0 = nullptr;
+  OtfModel otf;
+};
+hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
-                          const double* m0, const double* S, double* partials, int chunks,
-                          double* H);
+                          const double* S, double* partials, int chunks, double* H);
 // Two-pass FP64 sweep for any K (FP64 or FP32 u); grid returned in *grid_out.
 int wide_grid(int64_t N, int num_cus);
 hipError_t launch_sweep_wide(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,

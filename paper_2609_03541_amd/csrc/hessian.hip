@@ -38,16 +38,118 @@ __device__ __forceinline__ void block_coords(int b, int nb, int& bi, int& bj) {
   bj = i + rem;
 }
 
-// TI = double: x = c_k - u_kn - ln D_n. TI = float (packed mixed-precision
-// matrix r_kn = c0_k - u_kn - m0_n): x = d_k + r_kn - (ln D_n - m0_n) with
-// d_k = c_k - c0_k passed as cst and NEG_U set.
-template <typename TI, bool NEG_U>
+// Sources of P_kn = g_k exp(c_k - u_kn - ln D_n) for one row k and one
+// sample n: row(k, c) captures what is fixed along the row, col(n) what is
+// fixed along the column, and p(row, n, col) the element.
+
+// Stored FP64 or FP32 u: x = c_k - u_kn - ln D_n.
+template <typename TI>
+struct SrcMat {
+  const TI* u;
+  int64_t ld;
+  struct Row {
+    const TI* p;
+    double c;
+  };
+  __device__ Row row(int k, double c) const { return {u + (int64_t)k * ld, c}; }
+  __device__ double col(int64_t n, const double* logD) const { return logD[n]; }
+  __device__ double p(const Row& r, int64_t n, double lD) const {
+    return exp_nonpos(r.c - (double)r.p[n] - lD);
+  }
+};
+
+// Packed mixed-precision matrix r_kn = c0_k - u_kn - m0_n: x = d_k + r_kn -
+// (ln D_n - m0_n) with d_k = c_k - c0_k passed as the row constant.
+struct SrcPacked {
+  const float* r;
+  int64_t ld;
+  const double* m0;
+  struct Row {
+    const float* p;
+    double c;
+  };
+  __device__ Row row(int k, double c) const { return {r + (int64_t)k * ld, c}; }
+  __device__ double col(int64_t n, const double* logD) const { return logD[n] - m0[n]; }
+  __device__ double p(const Row& rw, int64_t n, double lD) const {
+    return exp_nonpos(rw.c + (double)rw.p[n] - lD);
+  }
+};
+
+// Energies from the bias model in FP64 (direct form), coordinates xi (N x D);
+// c64 holds [E_col | E_st | H | X0] as built for the on-the-fly sweeps.
+template <int D, int MODEL>
+struct SrcModel64 {
+  const double* xi;
+  const double* c64;
+  int K;
+  struct Row {
+    double e, h[D], x0[D];
+  };
+  __device__ Row row(int k, double) const {
+    Row r;
+    r.e = c64[K + k];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      r.h[j] = c64[2 * K + (int64_t)j * K + k];
+      r.x0[j] = c64[2 * K + (int64_t)(D + j) * K + k];
+    }
+    return r;
+  }
+  __device__ double col(int64_t n, const double* logD) const { return logD[n]; }
+  __device__ double p(const Row& r, int64_t n, double lD) const {
+    double q = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double x = xi[n * D + j];
+      if (MODEL == BUMBAR_MODEL_HARMONIC) {
+        const double dx = x - r.x0[j];
+        q = __builtin_fma(r.h[j] * dx, dx, q);
+      } else {
+        q = __builtin_fma(r.h[j], x, q);
+      }
+    }
+    return exp_nonpos(r.e - lD - q);
+  }
+};
+
+// Energies from the bias model in FP32 (expanded form in log2 units, as in
+// the FP32 on-the-fly sweeps); cf holds [A_col | A_st | B | C].
+template <int D>
+struct SrcModel32 {
+  const float* xf;
+  const float* cf;
+  int K;
+  struct Row {
+    float a, b[D], c[D];
+  };
+  __device__ Row row(int k, double) const {
+    Row r;
+    r.a = cf[K + k];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      r.b[j] = cf[2 * K + (int64_t)j * K + k];
+      r.c[j] = cf[2 * K + (int64_t)(D + j) * K + k];
+    }
+    return r;
+  }
+  __device__ double col(int64_t n, const double* logD) const { return -1.4426950408889634 * logD[n]; }
+  __device__ double p(const Row& r, int64_t n, double e) const {
+    float v = r.a + (float)e;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float x = xf[n * D + j];
+      v = __builtin_fmaf(r.b[j], x, v);
+      v = __builtin_fmaf(r.c[j], x * x, v);
+    }
+    return (double)__builtin_amdgcn_exp2f(v);
+  }
+};
+
+template <class Src>
 __global__ void __launch_bounds__(256)
-    hessian_partial_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
-                           const double* __restrict__ cst, const double* __restrict__ gk,
-                           const double* __restrict__ logD, const double* __restrict__ m0,
-                           int nb, int chunks, int64_t chunk_len,
-                           double* __restrict__ partials) {
+    hessian_partial_kernel(Src src, int K, int64_t N, const double* __restrict__ cst,
+                           const double* __restrict__ gk, const double* __restrict__ logD,
+                           int nb, int chunks, int64_t chunk_len, double* __restrict__ partials) {
   __shared__ double Pi[HB][HP];
   __shared__ double Pj[HB][HP];
   const int blk = blockIdx.x / chunks;
@@ -65,10 +167,10 @@ __global__ void __launch_bounds__(256)
   const int ls = (tid & 3) * 4;
   const int ki = bi * HB + lr;
   const int kj = bj * HB + lr;
-  const double ci = (ki < K) ? cst[ki] : 0.0;
-  const double cj = (kj < K) ? cst[kj] : 0.0;
   const bool si = (ki < K) && gk[ki] != 0.0;
   const bool sj = (kj < K) && gk[kj] != 0.0;
+  const typename Src::Row ri = src.row(si ? ki : 0, si ? cst[ki] : 0.0);
+  const typename Src::Row rj = src.row(sj ? kj : 0, sj ? cst[kj] : 0.0);
 
   d4 acc[2][2];
 #pragma unroll
@@ -86,21 +188,9 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < 4; ++q) {
       const int64_t n = n0 + ls + q;
       const bool ok = n < n_end;
-      const double lD = ok ? (NEG_U ? logD[n] - m0[n] : logD[n]) : 0.0;
-      double vi = 0.0;
-      if (si && ok) {
-        const double x = (double)u[(int64_t)ki * ld + n];
-        vi = exp_nonpos(ci - (NEG_U ? -x : x) - lD);
-      }
-      Pi[lr][ls + q] = vi;
-      if (!diag) {
-        double vj = 0.0;
-        if (sj && ok) {
-          const double x = (double)u[(int64_t)kj * ld + n];
-          vj = exp_nonpos(cj - (NEG_U ? -x : x) - lD);
-        }
-        Pj[lr][ls + q] = vj;
-      }
+      const double lD = ok ? src.col(n, logD) : 0.0;
+      Pi[lr][ls + q] = (si && ok) ? src.p(ri, n, lD) : 0.0;
+      if (!diag) Pj[lr][ls + q] = (sj && ok) ? src.p(rj, n, lD) : 0.0;
     }
     __syncthreads();
     const double(*Bsrc)[HP] = diag ? Pi : Pj;
@@ -173,27 +263,60 @@ size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
   return (size_t)nblk * chunks * HB * HB;
 }
 
-hipError_t launch_hessian(hipStream_t s, const void* u, int utype, int64_t ld, int K, int64_t N,
+template <class Src>
+static void launch_partial(hipStream_t s, const Src& src, int K, int64_t N, const double* cst,
+                           const double* gk, const double* logD, int nb, int chunks,
+                           int64_t chunk_len, double* partials) {
+  const int nblk = nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(hessian_partial_kernel<Src>, dim3(nblk * chunks), dim3(256), 0, s, src, K, N,
+                     cst, gk, logD, nb, chunks, chunk_len, partials);
+}
+
+hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
-                          const double* m0, const double* S, double* partials, int chunks,
-                          double* H) {
+                          const double* S, double* partials, int chunks, double* H) {
   const int nb = hess_nb(K);
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
-  const dim3 g(nblk * chunks);
-  if (utype == 0)
-    hipLaunchKernelGGL((hessian_partial_kernel<double, false>), g, dim3(256), 0, s,
-                       reinterpret_cast<const double*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
+  switch (hs.kind) {
+    case 0:
+      launch_partial(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
+                     gk, logD, nb, chunks, chunk_len, partials);
+      break;
+    case 1:
+      launch_partial(s, SrcMat<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst, gk,
+                     logD, nb, chunks, chunk_len, partials);
+      break;
+    case 2:
+      launch_partial(s, SrcPacked{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N, cst,
+                     gk, logD, nb, chunks, chunk_len, partials);
+      break;
+    case 3:
+      if (hs.otf.d == 1)
+        launch_partial(s, SrcModel32<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
                        chunk_len, partials);
-  else if (utype == 1)
-    hipLaunchKernelGGL((hessian_partial_kernel<float, false>), g, dim3(256), 0, s,
-                       reinterpret_cast<const float*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
+      else
+        launch_partial(s, SrcModel32<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
                        chunk_len, partials);
-  else
-    hipLaunchKernelGGL((hessian_partial_kernel<float, true>), g, dim3(256), 0, s,
-                       reinterpret_cast<const float*>(u), ld, K, N, cst, gk, logD, m0, nb, chunks,
-                       chunk_len, partials);
+      break;
+    default:
+      if (hs.otf.model == BUMBAR_MODEL_HARMONIC) {
+        if (hs.otf.d == 1)
+          launch_partial(s, SrcModel64<1, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+                         cst, gk, logD, nb, chunks, chunk_len, partials);
+        else
+          launch_partial(s, SrcModel64<2, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+                         cst, gk, logD, nb, chunks, chunk_len, partials);
+      } else {
+        if (hs.otf.d == 1)
+          launch_partial(s, SrcModel64<1, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+                         cst, gk, logD, nb, chunks, chunk_len, partials);
+        else
+          launch_partial(s, SrcModel64<2, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+                         cst, gk, logD, nb, chunks, chunk_len, partials);
+      }
+  }
   hipLaunchKernelGGL(hessian_reduce_kernel, dim3(HB * HB / 256, nblk), dim3(256), 0, s, K, nb,
                      chunks, partials, S, gk, H);
   return hipGetLastError();

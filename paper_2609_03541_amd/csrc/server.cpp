@@ -3,8 +3,9 @@
 //
 // Memory: one arena of hbm_budget_bytes is reserved at creation and handed
 // out first-fit (256-byte aligned) to admitted requests; a request's
-// footprint is its resident u_kn plus inputs plus the workspace bumbar_solve
-// asks for. Admission is strictly in arrival order: a free slot takes the
+// footprint is its resident u_kn (if it carries one; a model request keeps
+// only its coordinates, the energies being evaluated inside the kernels)
+// plus inputs plus the workspace bumbar_solve asks for. Admission is strictly in arrival order: a free slot takes the
 // oldest queued request as soon as its footprint fits, so a large request is
 // not overtaken indefinitely. Each slot owns a HIP stream (default priority)
 // and a library context; slots run in their own host threads, so the
@@ -118,11 +119,15 @@ namespace {
 
 size_t footprint_of(bumbar_server* srv, const bumbar_request& r, size_t* ws_out) {
   size_t ws = 0;
-  const int dq = (r.opt.binning && r.xi) ? r.d : 0;
-  bumbar_query_workspace(srv->sizing_ctx, r.K, r.N, dq, &r.opt, &ws);
+  if (r.u_kn) {
+    const int dq = (r.opt.binning && r.xi) ? r.d : 0;
+    bumbar_query_workspace(srv->sizing_ctx, r.K, r.N, dq, &r.opt, &ws);
+  } else {
+    bumbar_query_workspace_model(srv->sizing_ctx, r.K, r.N, r.d, &r.opt, &ws);
+  }
   *ws_out = ws;
   size_t b = 0;
-  b += align_up(sizeof(double) * (size_t)r.K * (size_t)r.N);  // u_kn
+  if (r.u_kn) b += align_up(sizeof(double) * (size_t)r.K * (size_t)r.N);  // resident u_kn
   if (r.xi) b += align_up(sizeof(double) * (size_t)r.N * (size_t)r.d);
   b += align_up(sizeof(int64_t) * (size_t)r.K);
   if (r.coef) b += align_up(sizeof(double) * (size_t)r.K * (size_t)(1 + 2 * r.d));
@@ -139,7 +144,8 @@ void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
     p += align_up(bytes);
     return q;
   };
-  double* u = reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.K * (size_t)r.N));
+  double* u =
+      r.u_kn ? reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.K * (size_t)r.N)) : nullptr;
   double* xi = r.xi ? reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.N * r.d)) : nullptr;
   int64_t* nk = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (size_t)r.K));
   double* coef =
@@ -163,14 +169,9 @@ void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
     job.status = BUMBAR_EDEVICE;
     return;
   }
-  if (!r.u_kn) {
-    const int rc = bumbar_model_energies(ctx, r.K, r.N, r.d, r.model, coef, xi, u);
-    if (rc) {
-      job.status = rc;
-      return;
-    }
-  }
-  const int dq = (r.opt.binning && r.xi) ? r.d : 0;
+  // a request without u_kn is solved with the energies evaluated from the
+  // model inside the kernels (u_kn = NULL in bumbar_solve)
+  const int dq = r.xi ? r.d : 0;
   job.stats.checks = nullptr;
   job.stats.checks_capacity = 0;
   job.status = bumbar_solve(ctx, u, BUMBAR_F64, r.K, r.N, nk, dq ? xi : nullptr, dq, r.model,

@@ -49,6 +49,7 @@ void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
   f_new = ar.take<double>(K);
   f_trial = ar.take<double>(K);
   dir = ar.take<double>(K);
+  f_sweep = ar.take<double>(K);
   lnS = ar.take<double>(K);
   S = ar.take<double>(K);
   lnS_t = ar.take<double>(K);
@@ -141,6 +142,11 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep32(s, reinterpret_cast<const float*>(M.u), M.ld, K, N, B.dk, B.gk, M.m0,
                        logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
+  } else if (M.kind >= 3) {
+    if (h != nullptr) return fail(ctx, BUMBAR_EINVAL, "on-the-fly sweeps are unbinned");
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, logD_out, B.part, B.part_obj,
+                         B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind == 0 && sweep_fast_supported(K)) {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_fast(s, reinterpret_cast<const double*>(M.u), M.ld, K, N, B.cst, B.gk, h,
@@ -172,20 +178,23 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
   const int K = B.K;
   SweepScalars tmp;
   SweepScalars* out = sc ? sc : &tmp;
-  if (!force_robust || M.kind == 2) {
+  if (!force_robust || M.kind >= 2) {
     int rc = queue_sweep(ctx, B, M, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, B.scal, true);
     if (rc) return rc;
     if (cnt) cnt->fast++;
-    if (sc == nullptr && M.kind != 2) {
-      // callers without scalars still need the flags for the fallback decision
-      rc = read_scalars(ctx, B.scal, out);
-      if (rc) return rc;
-    } else {
-      rc = read_scalars(ctx, B.scal, out);
-      if (rc) return rc;
-    }
-    if (M.kind == 2) return BUMBAR_OK;  // flags are the caller's signal to leave FP32
+    // callers without scalars still need the flags for the fallback decision
+    rc = read_scalars(ctx, B.scal, out);
+    if (rc) return rc;
+    // FP32 kinds: flags are the caller's signal to leave FP32
+    if (M.kind == 2 || M.kind == 3) return BUMBAR_OK;
     if ((out->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) return BUMBAR_OK;
+    if (M.kind == 4) {
+      // the model sweep keeps exact maxima per sample; there is no separate
+      // robust pass for it
+      if (out->flags & FLAG_NAN) return fail(ctx, BUMBAR_EINVAL, "non-finite coordinates");
+      return fail(ctx, BUMBAR_EINVAL,
+                  "state or sample sums out of the FP64 range in the on-the-fly sweep");
+    }
   }
   hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
   if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
@@ -205,25 +214,44 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
 }
 
 static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const double* f) {
-  // B.cst / B.gk hold the constants of the last sweep at f; the packed matrix
-  // needs d = f - f0 instead of c.
+  // B.cst / B.gk hold the constants at f; the packed matrix needs d = f - f0
+  // instead of c, and the model kinds their coefficients rebuilt at f.
   hipStream_t s = ctx->stream;
+  HessSource hs;
+  hs.kind = M.kind;
+  hs.u = M.u;
+  hs.ld = M.ld;
+  hs.otf = M.otf;
+  const double* cst = B.cst;
+  hipError_t e = hipSuccess;
   if (M.kind == 2) {
-    hipError_t e = launch_delta(s, B.K, f, M.f0, B.dk);
-    if (e != hipSuccess) return e;
-    return launch_hessian(s, M.u, 2, M.ld, B.K, B.N, B.dk, B.gk, B.logD, M.m0, B.S, B.hess_parts,
-                          B.hess_chunks, B.H);
+    e = launch_delta(s, B.K, f, M.f0, B.dk);
+    hs.m0 = M.m0;
+    cst = B.dk;
+  } else if (M.kind >= 3) {
+    e = launch_otf_coefs(s, M.otf, M.kind == 3, B.K, B.cst, B.gk);
   }
-  return launch_hessian(s, M.u, M.kind, M.ld, B.K, B.N, B.cst, B.gk, B.logD, nullptr, B.S,
-                        B.hess_parts, B.hess_chunks, B.H);
+  if (e != hipSuccess) return e;
+  return launch_hessian(s, hs, B.K, B.N, cst, B.gk, B.logD, B.S, B.hess_parts, B.hess_chunks,
+                        B.H);
 }
 
-// Newton finisher on unbinned data (see the oracle's reading): full Newton
-// step on the reduced system, trial steps alpha = 1, 1/2, ..., 2^-10 accepted
-// when they lower ||S - N||_2; otherwise one SCI step. Stops when the applied
-// max |delta f| < tol. f (device, K) is updated in place. With the packed
-// matrix, a flagged sweep ends the loop early with BUMBAR_ENOTCONV (the
-// caller continues in FP64).
+// Newton finisher on unbinned data (Section 2, derivative-based strategies).
+// Each step solves the reduced Newton system and tries alpha = 1, 1/2, ...,
+// 2^-10, accepting the first trial that lowers ||S - N||_2; if none does, one
+// SCI step is taken. Stops when the applied max |delta f| < tol. f (device,
+// K) is updated in place.
+//
+// Work per step: the sweep at the accepted trial point doubles as the sweep
+// at the new iterate (its ln D, S and constants are kept), and the Hessian is
+// reused (a chord step) while the steps it gives keep halving the gradient
+// norm; a stale Hessian that fails that test is rebuilt at the current f
+// before any smaller trial is tried. Only the gradient, the line-search test
+// and the stopping test need the matrix of M, so the fixed point reached is
+// the one of M whatever Hessian produced the steps. B.H_valid carries a
+// Hessian across calls (the FP64 refinement after the packed stage starts
+// from the packed stage's Hessian). With the packed matrix, a flagged sweep
+// ends the loop early with BUMBAR_ENOTCONV (the caller continues in FP64).
 int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double tol,
                   int max_steps, bumbar_stats* st, SweepCounters* cnt, double* final_step,
                   double* final_gnorm) {
@@ -234,35 +262,56 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
   auto bad32 = [&](const SweepScalars& x) {
     return M.kind == 2 && (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
   };
-  // fill unsampled states and gauge at the start (as the oracle does)
+  // the sweep at the starting point; unsampled states filled and the gauge
+  // fixed afterwards (neither changes S of sampled states, ln D - c or the
+  // gradient norm, so the sweep stays the sweep at f)
   int rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, cnt);
   if (rc) return rc;
   if (bad32(sc)) return BUMBAR_ENOTCONV;
-  hipError_t e = launch_fill_unsampled_gauge(s, K, Nk, B.f, B.lnS);
+  // B.cst and B.logD must describe the same point when the Hessian is built
+  // from them: the trial sweeps overwrite B.cst, and the gauge shift moves f
+  // after its sweep, so the constants are rebuilt at the swept point f_sweep.
+  hipError_t e = hipMemcpyAsync(B.f_sweep, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_fill_unsampled_gauge(s, K, Nk, B.f, B.lnS);
   if (e != hipSuccess) return hip_fail(ctx, e, "fill_unsampled");
+  auto build_hessian = [&]() -> int {
+    hipError_t e2 = launch_prepare_consts(s, K, Nk, B.f_sweep, B.cst, B.gk, B.lnNp);
+    if (e2 == hipSuccess) e2 = queue_hessian(ctx, B, M, B.f_sweep);
+    if (e2 != hipSuccess) return hip_fail(ctx, e2, "hessian");
+    if (st) st->hessians++;
+    B.H_valid = true;
+    return BUMBAR_OK;
+  };
+  auto direction = [&](int* ok) -> int {
+    hipError_t e2 = launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
+    if (e2 != hipSuccess) return hip_fail(ctx, e2, "newton_direction");
+    return read_bytes(ctx, B.ok, ok, sizeof(int));
+  };
   int steps = 0, fallbacks = 0;
   double last = INFINITY;
   rc = BUMBAR_ENOTCONV;
   while (steps < max_steps) {
-    rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, cnt);
-    if (rc) return rc;
-    if (bad32(sc)) {
-      rc = BUMBAR_ENOTCONV;
-      break;
-    }
     const double gn = sc.grad_norm;
     if (final_gnorm) *final_gnorm = gn;
-    e = queue_hessian(ctx, B, M, B.f);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
-    if (st) st->hessians++;
-    e = launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
-    if (e != hipSuccess) return hip_fail(ctx, e, "newton_direction");
-    int ok = 0;
-    rc = read_bytes(ctx, B.ok, &ok, sizeof(int));
-    if (rc) return rc;
-    bool accepted = false;
+    bool fresh = false;
+    if (!B.H_valid) {
+      rc = build_hessian();
+      if (rc) return rc;
+      fresh = true;
+    }
+    bool accepted = false, flagged = false;
     SweepScalars st2{};
-    if (ok) {
+    for (;;) {
+      int ok = 0;
+      rc = direction(&ok);
+      if (rc) return rc;
+      if (!ok && !fresh) {
+        rc = build_hessian();
+        if (rc) return rc;
+        fresh = true;
+        continue;
+      }
+      if (!ok) break;
       double alpha = 1.0;
       for (int t = 0; t <= 10; ++t, alpha *= 0.5) {
         e = launch_axpy_to(s, K, B.f, alpha, B.dir, B.f_trial);
@@ -270,19 +319,29 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
         rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
                       &st2, false, cnt);
         if (rc) return rc;
-        if (bad32(st2)) break;
-        if (st2.grad_norm < gn) {
+        if (bad32(st2)) {
+          flagged = true;
+          break;
+        }
+        // a stale Hessian must at least halve the gradient norm at alpha = 1
+        if (fresh ? st2.grad_norm < gn : st2.grad_norm < 0.5 * gn) {
           accepted = true;
           break;
         }
+        if (!fresh) break;
       }
-      if (bad32(st2)) {
-        rc = BUMBAR_ENOTCONV;
-        break;
-      }
+      if (accepted || flagged || fresh) break;
+      rc = build_hessian();
+      if (rc) return rc;
+      fresh = true;
+    }
+    if (flagged) {
+      rc = BUMBAR_ENOTCONV;
+      break;
     }
     if (!accepted) {
-      // SCI step: f_trial = SCI(f) (gauged), from a sweep at f
+      // SCI step from the sweep at f: f_trial = SCI(f) (gauged), then the
+      // sweep at f_trial
       rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f, B.f_trial, B.logD_t, B.lnS_t, B.S_t, nullptr,
                     false, cnt);
       if (rc) return rc;
@@ -295,15 +354,21 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
       }
       ++fallbacks;
     }
-    e = launch_fill_unsampled_gauge(s, K, Nk, B.f_trial, B.lnS_t);
+    e = hipMemcpyAsync(B.f_sweep, B.f_trial, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_fill_unsampled_gauge(s, K, Nk, B.f_trial, B.lnS_t);
     if (e != hipSuccess) return hip_fail(ctx, e, "fill_unsampled");
     e = launch_max_abs_diff(s, K, B.f_trial, B.f, B.misc);
     if (e != hipSuccess) return hip_fail(ctx, e, "max_abs_diff");
-    e = hipMemcpyAsync(B.f, B.f_trial, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
+    // the trial point becomes the iterate, its sweep the sweep at f
+    std::swap(B.f, B.f_trial);
+    std::swap(B.logD, B.logD_t);
+    std::swap(B.lnS, B.lnS_t);
+    std::swap(B.S, B.S_t);
+    sc = st2;
     rc = read_bytes(ctx, B.misc, &last, sizeof(double));
     if (rc) return rc;
     ++steps;
+    if (final_gnorm) *final_gnorm = sc.grad_norm;
     if (last < tol) {
       rc = BUMBAR_OK;
       break;
@@ -470,9 +535,89 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   B.carve(ar, K, N, ctx->num_cus);
   if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
   hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
+  HessSource hs;
+  hs.kind = u_dtype == BUMBAR_F32 ? 1 : 0;
+  hs.u = u_kn;
+  hs.ld = ld;
   if (e == hipSuccess)
-    e = launch_hessian(ctx->stream, u_kn, u_dtype == BUMBAR_F32 ? 1 : 0, ld, K, N, B.cst, B.gk,
-                       log_D_n, nullptr, S, B.hess_parts, B.hess_chunks, H);
+    e = launch_hessian(ctx->stream, hs, K, N, B.cst, B.gk, log_D_n, S, B.hess_parts,
+                       B.hess_chunks, H);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
+  return BUMBAR_OK;
+}
+
+// Model problem of K states over N coordinates: the on-the-fly kinds.
+static int model_setup(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
+                       const double* xi, int precision, void* workspace, size_t ws_bytes,
+                       UnbinnedBufs* B, Mat* M) {
+  int rc = check_common(ctx, coef, BUMBAR_F64, K, N, N);
+  if (rc) return rc;
+  if ((model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC) || !xi || d < 1 || d > 2)
+    return fail(ctx, BUMBAR_EINVAL, "needs a LINEAR or HARMONIC model and xi with d in {1, 2}");
+  if (precision != BUMBAR_PREC_FP64 && precision != BUMBAR_PREC_MIXED)
+    return fail(ctx, BUMBAR_EINVAL, "unknown precision");
+  if (!workspace) return fail(ctx, BUMBAR_EINVAL, "NULL workspace");
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  B->carve(ar, K, N, ctx->num_cus);
+  OtfBufs O;
+  O.carve(ar, K, N, d);
+  if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes)", ws_bytes);
+  M->kind = precision == BUMBAR_PREC_MIXED ? 3 : 4;
+  M->otf.xi = xi;
+  M->otf.xf = O.xf;
+  M->otf.coef = coef;
+  M->otf.d = d;
+  M->otf.model = model;
+  M->otf.cf32 = O.cf32;
+  M->otf.cf64 = O.cf64;
+  if (M->kind == 3) {
+    const hipError_t e = launch_pack_coords(ctx->stream, N * d, xi, O.xf);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pack coordinates");
+  }
+  return BUMBAR_OK;
+}
+
+int bumbar_sweep_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
+                       const double* xi, int precision, const int64_t* N_k, const double* f,
+                       void* workspace, size_t ws_bytes, double* f_new, double* log_D_n,
+                       double* S, double* sweep_stats) {
+  UnbinnedBufs B;
+  Mat M;
+  int rc = model_setup(ctx, K, N, d, model, coef, xi, precision, workspace, ws_bytes, &B, &M);
+  if (rc) return rc;
+  if (!N_k || !f || !f_new) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  SweepScalars sc{};
+  rc = sweep_at(ctx, B, M, N, nullptr, N_k, f, f_new, log_D_n ? log_D_n : B.logD, B.lnS,
+                S ? S : B.S, &sc, false, nullptr);
+  if (rc) return rc;
+  if (M.kind == 3 && (sc.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)))
+    return fail(ctx, BUMBAR_EINVAL, "sums out of the FP32 range in the FP32 model sweep");
+  if (sweep_stats) {
+    sweep_stats[0] = sc.max_df;
+    sweep_stats[1] = sc.rel_step;
+    sweep_stats[2] = sc.objective;
+    sweep_stats[3] = sc.grad_norm;
+  }
+  return BUMBAR_OK;
+}
+
+int bumbar_hessian_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
+                         const double* xi, int precision, const int64_t* N_k, const double* f,
+                         const double* log_D_n, const double* S, void* workspace,
+                         size_t ws_bytes, double* H) {
+  UnbinnedBufs B;
+  Mat M;
+  int rc = model_setup(ctx, K, N, d, model, coef, xi, precision, workspace, ws_bytes, &B, &M);
+  if (rc) return rc;
+  if (!N_k || !f || !log_D_n || !S || !H) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
+  HessSource hs;
+  hs.kind = M.kind;
+  hs.otf = M.otf;
+  if (e == hipSuccess) e = launch_otf_coefs(ctx->stream, M.otf, M.kind == 3, K, B.cst, B.gk);
+  if (e == hipSuccess)
+    e = launch_hessian(ctx->stream, hs, K, N, B.cst, B.gk, log_D_n, S, B.hess_parts,
+                       B.hess_chunks, H);
   if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
   return BUMBAR_OK;
 }
@@ -548,12 +693,28 @@ int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
   return BUMBAR_OK;
 }
 
+int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
+                                 const bumbar_options* opt, size_t* bytes) {
+  if (!ctx || !bytes || K <= 0 || N <= 0 || d < 1 || d > 2) return BUMBAR_EINVAL;
+  Arena ar;
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus);
+  OtfBufs O;
+  O.carve(ar, K, N, d);
+  *bytes = ar.off + 256;
+  return BUMBAR_OK;
+}
+
 int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
                  const int64_t* N_k, const double* xi, int d, int model, const double* coef,
                  const double* f_init, const bumbar_options* opt_in, void* workspace,
                  size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
                  bumbar_stats* stats) {
-  int rc = check_common(ctx, u_kn, u_dtype, K, N, N);
+  // u_kn == NULL: the energies come from the model, evaluated in the kernels
+  const bool otf = (u_kn == nullptr);
+  int rc = otf ? check_common(ctx, coef, BUMBAR_F64, K, N, N) : check_common(ctx, u_kn, u_dtype, K,
+                                                                             N, N);
   if (rc) return rc;
   bumbar_options opt;
   if (opt_in)
@@ -561,6 +722,8 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   else
     bumbar_default_options(&opt);
   if (!N_k || !f_k || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  if (otf && (model == BUMBAR_MODEL_NONE || !xi || d < 1 || d > 2))
+    return fail(ctx, BUMBAR_EINVAL, "u_kn = NULL needs a model, its coefficients and xi (d in {1, 2})");
   if (!(opt.tol > 0.0)) return fail(ctx, BUMBAR_EINVAL, "tol must be > 0");
   if (opt.binning && (!xi || d < 1 || d > 2))
     return fail(ctx, BUMBAR_EINVAL, "binning needs coordinates xi with d in {1, 2}");
@@ -582,14 +745,19 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   }
   if (tot != N) return fail(ctx, BUMBAR_EINVAL, "sum of N_k (%lld) != N (%lld)", (long long)tot,
                             (long long)N);
-  const bool mixed = mixed_enabled(opt, u_dtype, K);
+  const bool mixed = otf ? (opt.precision == BUMBAR_PREC_MIXED &&
+                            opt.finisher == BUMBAR_FINISH_NEWTON)
+                         : mixed_enabled(opt, u_dtype, K);
+  // carve order mirrors bumbar_query_workspace / bumbar_query_workspace_model
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
   BinnedBufs BB;
   if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus);
   MixedBufs X;
-  if (mixed) X.carve(ar, K, N);
+  if (mixed && !otf) X.carve(ar, K, N);
+  OtfBufs O;
+  if (otf) O.carve(ar, K, N, d);
   if (ar.overflow)
     return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
   bumbar_stats local{};
@@ -600,9 +768,23 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->checks = chk;
   st->checks_capacity = chk_cap;
   hipStream_t s = ctx->stream;
-  const Mat M = input_mat(u_kn, u_dtype, N);
-  SweepCounters cnt;
+  Mat M = input_mat(u_kn, u_dtype, N);
   hipError_t e;
+  if (otf) {
+    M.kind = 4;
+    M.otf.xi = xi;
+    M.otf.xf = O.xf;
+    M.otf.coef = coef;
+    M.otf.d = d;
+    M.otf.model = model;
+    M.otf.cf32 = O.cf32;
+    M.otf.cf64 = O.cf64;
+    if (mixed) {
+      e = launch_pack_coords(s, N * d, xi, O.xf);
+      if (e != hipSuccess) return hip_fail(ctx, e, "pack coordinates");
+    }
+  }
+  SweepCounters cnt;
   ctx->profiling = opt.profile != 0;
   ctx->events_used = 0;
   if (f_init && !opt.binning)
@@ -627,9 +809,20 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   }
   const double t1 = now_ms();
   int fin_rc = BUMBAR_OK;
+  int64_t steps64 = 0;  // Newton steps on M itself (after any packed stage)
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
-      if (mixed) {
+      if (mixed && otf) {
+        // Newton on the FP32 model sweeps to mixed_tol, then FP64 refinement
+        Mat R = M;
+        R.kind = 3;
+        const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
+        const int64_t before = st->finisher_steps;
+        int mrc = newton_finish(ctx, B, R, N_k, mtol, opt.max_newton, st, &cnt, &st->final_step,
+                                &st->grad_norm);
+        if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
+        st->mixed_steps = st->finisher_steps - before;
+      } else if (mixed) {
         // pack at the current f, Newton on the FP32 matrix to mixed_tol, then
         // FP64 refinement on u to tol
         e = launch_prepare_consts(s, K, N_k, B.f, B.cst, B.gk, B.lnNp);
@@ -651,8 +844,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
         if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
         st->mixed_steps = st->finisher_steps - before;
       }
+      const int64_t before64 = st->finisher_steps;
       fin_rc = newton_finish(ctx, B, M, N_k, opt.tol, opt.max_newton, st, &cnt, &st->final_step,
                              &st->grad_norm);
+      steps64 = st->finisher_steps - before64;
     } else {
       int64_t it = 0;
       const int64_t left = std::max<int64_t>(0, opt.max_iter - st->phase1_iters - st->phase2_iters);
@@ -662,16 +857,23 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     if (fin_rc != BUMBAR_OK && fin_rc != BUMBAR_ENOTCONV) return fin_rc;
   }
   st->time_final_ms = now_ms() - t1;
-  // outputs: ln D at the final f, weights, f
-  SweepScalars sc{};
-  rc = sweep_at(ctx, B, M, N, nullptr, N_k, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, &cnt);
-  if (rc) return rc;
-  st->grad_norm = sc.grad_norm;
+  // outputs: ln D at the final f, weights, f. After Newton steps the last
+  // sweep was at the final f up to the gauge shift (which leaves the
+  // gradient unchanged), so a new sweep is needed only for ln D and W.
+  const bool newton_done = stage_rc == BUMBAR_OK && opt.finisher == BUMBAR_FINISH_NEWTON &&
+                           steps64 > 0;
+  if (!newton_done || log_D_n || W_nk) {
+    SweepScalars sc{};
+    rc = sweep_at(ctx, B, M, N, nullptr, N_k, B.f, B.f_new, B.logD, B.lnS, B.S, &sc, false, &cnt);
+    if (rc) return rc;
+    st->grad_norm = sc.grad_norm;
+  }
   e = hipMemcpyAsync(f_k, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && log_D_n)
     e = hipMemcpyAsync(log_D_n, B.logD, sizeof(double) * N, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && W_nk)
-    e = launch_weights(s, u_kn, u_dtype == BUMBAR_F32, N, K, N, B.f, B.logD, W_nk);
+    e = otf ? launch_weights_otf(s, M.otf, K, N, B.f, B.logD, W_nk)
+            : launch_weights(s, u_kn, u_dtype == BUMBAR_F32, N, K, N, B.f, B.logD, W_nk);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "outputs");
   st->unbinned_sweeps = cnt.fast + cnt.robust;

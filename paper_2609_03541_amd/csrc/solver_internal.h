@@ -23,15 +23,30 @@ struct SweepCounters {
   int64_t robust = 0;
 };
 
-// The matrix a sweep reads: FP64 u, FP32 u (widened to FP64 arithmetic), or
-// the packed mixed-precision matrix r_kn = fp32(c0_k - u_kn - m0_n) taken at
-// the reference point f0 (FP32 arithmetic inside the sweep).
+// The matrix a sweep reads: FP64 u, FP32 u (widened to FP64 arithmetic), the
+// packed mixed-precision matrix r_kn = fp32(c0_k - u_kn - m0_n) taken at the
+// reference point f0 (FP32 arithmetic inside the sweep), or u from the bias
+// model evaluated inside the kernels (FP32 or FP64 arithmetic).
 struct Mat {
   const void* u = nullptr;
-  int kind = 0;  // 0: FP64, 1: FP32, 2: packed mixed precision
+  int kind = 0;  // 0: FP64, 1: FP32, 2: packed, 3: model FP32, 4: model FP64
   int64_t ld = 0;
   const double* m0 = nullptr;  // kind 2: per-column shift (N)
   const double* f0 = nullptr;  // kind 2: reference point (K)
+  OtfModel otf;                // kinds 3 and 4
+};
+
+// Coordinates in FP32 and the per-sweep model coefficients of the
+// on-the-fly kinds (carved whenever coordinates are given).
+struct OtfBufs {
+  float* xf = nullptr;
+  float* cf32 = nullptr;
+  double* cf64 = nullptr;
+  void carve(Arena& ar, int K, int64_t N, int d) {
+    xf = ar.take<float>((size_t)N * d);
+    cf32 = ar.take<float>(otf_coef_floats(K, d));
+    cf64 = ar.take<double>(otf_coef_floats(K, d));
+  }
 };
 
 // Device buffers for sweeps and the Newton finisher of one K x N problem.
@@ -40,6 +55,7 @@ struct UnbinnedBufs {
   int64_t N = 0;
   double *cst = nullptr, *gk = nullptr, *lnNp = nullptr;
   double *f = nullptr, *f_new = nullptr, *f_trial = nullptr, *dir = nullptr;
+  double* f_sweep = nullptr;  // the point of the sweep whose ln D the Hessian uses
   double *lnS = nullptr, *S = nullptr, *lnS_t = nullptr, *S_t = nullptr;
   double *logD = nullptr, *logD_t = nullptr;
   int nparts_cap = 0;
@@ -54,6 +70,7 @@ struct UnbinnedBufs {
   double *A = nullptr, *H = nullptr, *hess_parts = nullptr;
   double* dk = nullptr;  // f - f0 for the packed matrix
   int hess_chunks = 1;
+  bool H_valid = false;  // H holds a Hessian usable for chord steps
   void carve(Arena& ar, int K, int64_t N, int num_cus);
 };
 

@@ -1,0 +1,566 @@
+// Sweeps with the reduced energies computed on the fly from the bias model
+// (Section 2: the energies of umbrella windows are known functions of the
+// sampled coordinate; any potential common to all states cancels in Eq. (1)
+// and is left out). u_kn is never stored: each kernel reads the N x d
+// coordinates and the K model coefficients and evaluates
+//   HARMONIC  u_k(x) = a_k + sum_j kappa_kj / 2 (x_j - x0_kj)^2
+//   LINEAR    u_k(x) = a_k + sum_j b_kj x_j
+// per element, so the sweep is bound by arithmetic (exponentials), not HBM.
+//
+// Two passes, as for large K with a stored matrix: a column pass (exact
+// log-sum-exp over sampled states per sample, online max in chunks of 8
+// states with the state coefficients staged in LDS tiles) and a state pass
+// (each thread accumulates 8 or 16 states over a strided set of samples;
+// per-block partials are written state-major for the common finaliser).
+//
+// FP64 kernels evaluate u in the direct form above from FP64 coordinates and
+// use the FP64 exponential. FP32 kernels (mixed precision) use the expanded
+// quadratic form t = A_k + sum_j (B_kj x_j + C_kj x_j^2) in log2 units with
+// the hardware exp2, from FP32 coordinates; A, B, C are rebuilt in FP64 for
+// every sweep and rounded once.
+#include <cmath>
+
+#include "bumbar_impl.h"
+#include "devmath.h"
+
+namespace bumbar {
+
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr int kOT = 256;        // threads per block (both passes)
+constexpr int kOTile = 512;     // states per LDS tile in the column pass
+constexpr int kOStates = 64;    // states per state-pass block (4 row groups)
+
+int otf_grid(int64_t N, int num_cus) {
+  int64_t g = (N + 2 * kOT - 1) / (2 * kOT);
+  const int64_t cap = (int64_t)num_cus * 4;
+  if (g > cap) g = cap;
+  if (g > sweep_max_grid(num_cus)) g = sweep_max_grid(num_cus);
+  return (int)(g < 1 ? 1 : g);
+}
+
+// ---- coefficient preparation ------------------------------------------------
+
+// FP32 coefficients in log2 units: cf = [A_col K | A_st K | B K*d | C K*d] with
+// A_st = log2e (c_k - w0_k), A_col = A_st for sampled states and -inf
+// otherwise, B = -log2e w1, C = -log2e w2, where u_k = w0 + sum (w1 x + w2 x^2).
+__global__ void otf32_coef_kernel(int K, int d, int model, const double* __restrict__ coef,
+                                  const double* __restrict__ cst, const double* __restrict__ gk,
+                                  float* __restrict__ cf) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double* ck = coef + (int64_t)k * (1 + 2 * d);
+  double w0 = ck[0];
+  for (int j = 0; j < d; ++j) {
+    double w1, w2;
+    if (model == BUMBAR_MODEL_HARMONIC) {
+      const double h = 0.5 * ck[1 + 2 * j], x0 = ck[2 + 2 * j];
+      w0 += h * x0 * x0;
+      w1 = -2.0 * h * x0;
+      w2 = h;
+    } else {
+      w1 = ck[1 + j];
+      w2 = 0.0;
+    }
+    cf[2 * K + (int64_t)j * K + k] = (float)(-kLog2e * w1);
+    cf[2 * K + (int64_t)(d + j) * K + k] = (float)(-kLog2e * w2);
+  }
+  const float a = (float)(kLog2e * (cst[k] - w0));
+  cf[K + k] = a;
+  cf[k] = gk[k] != 0.0 ? a : -INFINITY;
+}
+
+// FP64 coefficients: c64 = [E_col K | E_st K | H K*d | X0 K*d] with
+// E_st = c_k - a_k, E_col = E_st for sampled states and -inf otherwise (the
+// column pass skips unsampled states); for HARMONIC, H = kappa / 2 and X0 =
+// the centre; for LINEAR, H = b and X0 = 0 (the kernels branch on the model
+// at compile time).
+__global__ void otf64_coef_kernel(int K, int d, int model, const double* __restrict__ coef,
+                                  const double* __restrict__ cst, const double* __restrict__ gk,
+                                  double* __restrict__ c64) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double* ck = coef + (int64_t)k * (1 + 2 * d);
+  for (int j = 0; j < d; ++j) {
+    if (model == BUMBAR_MODEL_HARMONIC) {
+      c64[2 * K + (int64_t)j * K + k] = 0.5 * ck[1 + 2 * j];
+      c64[2 * K + (int64_t)(d + j) * K + k] = ck[2 + 2 * j];
+    } else {
+      c64[2 * K + (int64_t)j * K + k] = ck[1 + j];
+      c64[2 * K + (int64_t)(d + j) * K + k] = 0.0;
+    }
+  }
+  const double e = cst[k] - ck[0];
+  c64[K + k] = e;
+  c64[k] = gk[k] != 0.0 ? e : -INFINITY;
+}
+
+__global__ void pack_coords_kernel(int64_t n, const double* __restrict__ xi, float* __restrict__ xf) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) xf[i] = (float)xi[i];
+}
+
+// ---- model evaluation ---------------------------------------------------------
+
+// sum_j H_j (x_j - X0_j)^2 (HARMONIC) or sum_j H_j x_j (LINEAR), FP64.
+template <int D, int MODEL>
+__device__ __forceinline__ double model_rest(const double* h, const double* x0, const double* x) {
+  double q = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (MODEL == BUMBAR_MODEL_HARMONIC) {
+      const double dx = x[j] - x0[j];
+      q = __builtin_fma(h[j] * dx, dx, q);
+    } else {
+      q = __builtin_fma(h[j], x[j], q);
+    }
+  }
+  return q;
+}
+
+// ---- FP32 passes ----------------------------------------------------------------
+
+template <int D>
+__global__ void __launch_bounds__(kOT)
+    otf32_colpass_kernel(int K, int64_t N, const float* __restrict__ xf,
+                         const float* __restrict__ cf, double* __restrict__ logD,
+                         double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+  __shared__ float sA[kOTile];
+  __shared__ float sB[D][kOTile];
+  __shared__ float sC[D][kOTile];
+  __shared__ double wred[kOT / 64];
+  __shared__ unsigned fl;
+  if (threadIdx.x == 0) fl = 0u;
+  double obj = 0.0;
+  unsigned bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kOT * 2;
+  // every thread of the block runs the same number of column iterations (the
+  // LDS tiles are shared), with out-of-range columns masked
+  const int64_t n_iter = (N + stride - 1) / stride;
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t n0 = it * stride + ((int64_t)blockIdx.x * kOT + threadIdx.x) * 2;
+    const bool ok0 = n0 < N, ok1 = n0 + 1 < N;
+    float x0[D], x1[D], q0[D], q1[D];
+    float chk = 0.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x0[j] = ok0 ? xf[n0 * D + j] : 0.f;
+      x1[j] = ok1 ? xf[(n0 + 1) * D + j] : x0[j];
+      q0[j] = x0[j] * x0[j];
+      q1[j] = x1[j] * x1[j];
+      chk += x0[j] + x1[j];
+    }
+    if (chk != chk) bad |= FLAG_NAN;
+    float m0 = -1e30f, m1 = -1e30f, s0 = 0.f, s1 = 0.f;
+    for (int t0 = 0; t0 < K; t0 += kOTile) {
+      const int tl = min(kOTile, K - t0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < tl; i += kOT) {
+        sA[i] = cf[t0 + i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          sB[j][i] = cf[2 * K + (int64_t)j * K + t0 + i];
+          sC[j][i] = cf[2 * K + (int64_t)(D + j) * K + t0 + i];
+        }
+      }
+      __syncthreads();
+      for (int c0 = 0; c0 < tl; c0 += 8) {
+        float a0[8], a1[8];
+        float cm0 = -INFINITY, cm1 = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = c0 + q;
+          const bool in = i < tl;
+          const int ii = in ? i : 0;
+          float v0 = in ? sA[ii] : -INFINITY;
+          float v1 = v0;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            v0 = __builtin_fmaf(sB[j][ii], x0[j], v0);
+            v0 = __builtin_fmaf(sC[j][ii], q0[j], v0);
+            v1 = __builtin_fmaf(sB[j][ii], x1[j], v1);
+            v1 = __builtin_fmaf(sC[j][ii], q1[j], v1);
+          }
+          a0[q] = v0;
+          a1[q] = v1;
+          cm0 = fmaxf(cm0, v0);
+          cm1 = fmaxf(cm1, v1);
+        }
+        if (cm0 > m0) {
+          s0 *= __builtin_amdgcn_exp2f(m0 - cm0);
+          m0 = cm0;
+        }
+        if (cm1 > m1) {
+          s1 *= __builtin_amdgcn_exp2f(m1 - cm1);
+          m1 = cm1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          s0 += __builtin_amdgcn_exp2f(a0[q] - m0);
+          s1 += __builtin_amdgcn_exp2f(a1[q] - m1);
+        }
+      }
+    }
+    if (ok0) {
+      if (!(m0 > -1e30f && s0 > 0.f && s0 < INFINITY)) bad |= FLAG_COL;
+      const double l0 = ((double)m0 + (double)__builtin_amdgcn_logf(s0)) * kLn2;
+      logD[n0] = l0;
+      obj += l0;
+    }
+    if (ok1) {
+      if (!(m1 > -1e30f && s1 > 0.f && s1 < INFINITY)) bad |= FLAG_COL;
+      const double l1 = ((double)m1 + (double)__builtin_amdgcn_logf(s1)) * kLn2;
+      logD[n0 + 1] = l1;
+      obj += l1;
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) obj += __shfl_xor(obj, off, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = obj;
+  if (bad) atomicOr(&fl, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = wred[0];
+    for (int w = 1; w < kOT / 64; ++w) o += wred[w];
+    part_obj[blockIdx.x] = o;
+    part_flags[blockIdx.x] = fl;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kOT)
+    otf32_statepass_kernel(int K, int64_t N, const float* __restrict__ xf,
+                           const float* __restrict__ cf, const double* __restrict__ logD,
+                           double* __restrict__ part) {
+  constexpr int R = kOStates / 4;  // states per thread
+  const int lc = threadIdx.x & 63;
+  const int rg = threadIdx.x >> 6;
+  const int kbase = blockIdx.y * kOStates + rg;
+  float A[R], B[D][R], C[D][R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = kbase + 4 * r;
+    const bool in = k < K;
+    A[r] = in ? cf[K + k] : -INFINITY;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      B[j][r] = in ? cf[2 * K + (int64_t)j * K + k] : 0.f;
+      C[j][r] = in ? cf[2 * K + (int64_t)(D + j) * K + k] : 0.f;
+    }
+    acc[r] = 0.f;
+  }
+  const int64_t stride = (int64_t)gridDim.x * 128;
+  for (int64_t n0 = (int64_t)blockIdx.x * 128 + lc * 2; n0 < N; n0 += stride) {
+    const bool two = n0 + 1 < N;
+    float x0[D], x1[D], q0[D], q1[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x0[j] = xf[n0 * D + j];
+      x1[j] = two ? xf[(n0 + 1) * D + j] : x0[j];
+      q0[j] = x0[j] * x0[j];
+      q1[j] = x1[j] * x1[j];
+    }
+    const float e0 = (float)(-kLog2e * logD[n0]);
+    // a missing second column contributes exp2(-inf) = 0
+    const float e1 = two ? (float)(-kLog2e * logD[n0 + 1]) : -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float v0 = A[r] + e0, v1 = A[r] + e1;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        v0 = __builtin_fmaf(B[j][r], x0[j], v0);
+        v0 = __builtin_fmaf(C[j][r], q0[j], v0);
+        v1 = __builtin_fmaf(B[j][r], x1[j], v1);
+        v1 = __builtin_fmaf(C[j][r], q1[j], v1);
+      }
+      acc[r] += __builtin_amdgcn_exp2f(v0) + __builtin_amdgcn_exp2f(v1);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = (double)acc[r];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    const int k = kbase + 4 * r;
+    if (lc == 0 && k < K) part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// ---- FP64 passes ----------------------------------------------------------------
+
+template <int D, int MODEL>
+__global__ void __launch_bounds__(kOT)
+    otf64_colpass_kernel(int K, int64_t N, const double* __restrict__ xi,
+                         const double* __restrict__ c64, double* __restrict__ logD,
+                         double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+  constexpr int T = kOTile / 2;  // FP64 tile: half the states of the FP32 tile
+  __shared__ double sE[T];
+  __shared__ double sH[D][T];
+  __shared__ double sX[D][T];
+  __shared__ double wred[kOT / 64];
+  __shared__ unsigned fl;
+  if (threadIdx.x == 0) fl = 0u;
+  double obj = 0.0;
+  unsigned bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kOT * 2;
+  const int64_t n_iter = (N + stride - 1) / stride;
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t n0 = it * stride + ((int64_t)blockIdx.x * kOT + threadIdx.x) * 2;
+    const bool ok0 = n0 < N, ok1 = n0 + 1 < N;
+    double x0[D], x1[D];
+    double chk = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x0[j] = ok0 ? xi[n0 * D + j] : 0.0;
+      x1[j] = ok1 ? xi[(n0 + 1) * D + j] : x0[j];
+      chk += x0[j] + x1[j];
+    }
+    if (chk != chk) bad |= FLAG_NAN;
+    double m0 = -INFINITY, m1 = -INFINITY, s0 = 0.0, s1 = 0.0;
+    for (int t0 = 0; t0 < K; t0 += T) {
+      const int tl = min(T, K - t0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < tl; i += kOT) {
+        sE[i] = c64[t0 + i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          sH[j][i] = c64[2 * K + (int64_t)j * K + t0 + i];
+          sX[j][i] = c64[2 * K + (int64_t)(D + j) * K + t0 + i];
+        }
+      }
+      __syncthreads();
+      for (int c0 = 0; c0 < tl; c0 += 8) {
+        double a0[8], a1[8];
+        double cm0 = -INFINITY, cm1 = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = c0 + q;
+          const bool in = i < tl;
+          const int ii = in ? i : 0;
+          double h[D], xc[D];
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            h[j] = sH[j][ii];
+            xc[j] = sX[j][ii];
+          }
+          const double e = in ? sE[ii] : -INFINITY;
+          a0[q] = e - model_rest<D, MODEL>(h, xc, x0);
+          a1[q] = e - model_rest<D, MODEL>(h, xc, x1);
+          cm0 = fmax(cm0, a0[q]);
+          cm1 = fmax(cm1, a1[q]);
+        }
+        if (cm0 > m0) {
+          s0 *= exp_nonpos(m0 - cm0);
+          m0 = cm0;
+        }
+        if (cm1 > m1) {
+          s1 *= exp_nonpos(m1 - cm1);
+          m1 = cm1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          s0 += exp_nonpos(a0[q] - m0);
+          s1 += exp_nonpos(a1[q] - m1);
+        }
+      }
+    }
+    if (ok0) {
+      if (!(m0 > -INFINITY && m0 < INFINITY)) bad |= FLAG_COL;
+      const double l0 = m0 + log(s0);
+      logD[n0] = l0;
+      obj += l0;
+    }
+    if (ok1) {
+      if (!(m1 > -INFINITY && m1 < INFINITY)) bad |= FLAG_COL;
+      const double l1 = m1 + log(s1);
+      logD[n0 + 1] = l1;
+      obj += l1;
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) obj += __shfl_xor(obj, off, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = obj;
+  if (bad) atomicOr(&fl, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = wred[0];
+    for (int w = 1; w < kOT / 64; ++w) o += wred[w];
+    part_obj[blockIdx.x] = o;
+    part_flags[blockIdx.x] = fl;
+  }
+}
+
+template <int D, int MODEL>
+__global__ void __launch_bounds__(kOT)
+    otf64_statepass_kernel(int K, int64_t N, const double* __restrict__ xi,
+                           const double* __restrict__ c64, const double* __restrict__ logD,
+                           double* __restrict__ part) {
+  constexpr int R = kOStates / 8;  // 8 states per thread; two row-group passes per block
+  const int lc = threadIdx.x & 63;
+  const int rg = threadIdx.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * 128;
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    const int kbase = blockIdx.y * kOStates + half * (kOStates / 2) + rg;
+    double E[R], H[D][R], X[D][R], acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = kbase + 4 * r;
+      const bool in = k < K;
+      E[r] = in ? c64[K + k] : -INFINITY;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        H[j][r] = in ? c64[2 * K + (int64_t)j * K + k] : 0.0;
+        X[j][r] = in ? c64[2 * K + (int64_t)(D + j) * K + k] : 0.0;
+      }
+      acc[r] = 0.0;
+    }
+    for (int64_t n0 = (int64_t)blockIdx.x * 128 + lc * 2; n0 < N; n0 += stride) {
+      const bool two = n0 + 1 < N;
+      double x0[D], x1[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        x0[j] = xi[n0 * D + j];
+        x1[j] = two ? xi[(n0 + 1) * D + j] : x0[j];
+      }
+      const double l0 = logD[n0];
+      const double l1 = two ? logD[n0 + 1] : INFINITY;  // exp(-inf) = 0 for a missing column
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double h[D], xc[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          h[j] = H[j][r];
+          xc[j] = X[j][r];
+        }
+        acc[r] += exp_nonpos(E[r] - l0 - model_rest<D, MODEL>(h, xc, x0));
+        acc[r] += exp_nonpos(E[r] - l1 - model_rest<D, MODEL>(h, xc, x1));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double v = acc[r];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+      const int k = kbase + 4 * r;
+      if (lc == 0 && k < K) part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+    }
+  }
+}
+
+// W_nk = exp(f_k - u_kn - ln D_n), N x K sample-major, FP64 model.
+template <int D, int MODEL>
+__global__ void otf64_weights_kernel(int K, int64_t N, const double* __restrict__ xi,
+                                     const double* __restrict__ coef,
+                                     const double* __restrict__ f,
+                                     const double* __restrict__ logD, double* __restrict__ W) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)K * N) return;
+  const int64_t n = e / K;
+  const int k = (int)(e % K);
+  const double* ck = coef + (int64_t)k * (1 + 2 * D);
+  double h[D], xc[D], x[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    x[j] = xi[n * D + j];
+    if (MODEL == BUMBAR_MODEL_HARMONIC) {
+      h[j] = 0.5 * ck[1 + 2 * j];
+      xc[j] = ck[2 + 2 * j];
+    } else {
+      h[j] = ck[1 + j];
+      xc[j] = 0.0;
+    }
+  }
+  W[e] = exp_nonpos(f[k] - ck[0] - model_rest<D, MODEL>(h, xc, x) - logD[n]);
+}
+
+// ---- launchers ------------------------------------------------------------------
+
+size_t otf_coef_floats(int K, int d) { return (size_t)K * (2 + 2 * d); }
+
+hipError_t launch_pack_coords(hipStream_t s, int64_t n, const double* xi, float* xf) {
+  hipLaunchKernelGGL(pack_coords_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xi,
+                     xf);
+  return hipGetLastError();
+}
+
+hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, const double* cst,
+                            const double* gk) {
+  const dim3 cg((K + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(otf32_coef_kernel, cg, dim3(256), 0, s, K, m.d, m.model, m.coef, cst, gk,
+                       m.cf32);
+  else
+    hipLaunchKernelGGL(otf64_coef_kernel, cg, dim3(256), 0, s, K, m.d, m.model, m.coef, cst, gk,
+                       m.cf64);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
+                            const double* cst, const double* gk, double* logD, double* part,
+                            double* part_obj, unsigned* part_flags, int num_cus, int* grid_out) {
+  if (m.d != 1 && m.d != 2) return hipErrorInvalidValue;
+  const int G = otf_grid(N, num_cus);
+  *grid_out = G;
+  const dim3 sg(G, (K + kOStates - 1) / kOStates);
+  hipError_t e = launch_otf_coefs(s, m, fp32, K, cst, gk);
+  if (e != hipSuccess) return e;
+  if (fp32) {
+    if (m.d == 1) {
+      hipLaunchKernelGGL(otf32_colpass_kernel<1>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,
+                         logD, part_obj, part_flags);
+      hipLaunchKernelGGL(otf32_statepass_kernel<1>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, logD,
+                         part);
+    } else {
+      hipLaunchKernelGGL(otf32_colpass_kernel<2>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,
+                         logD, part_obj, part_flags);
+      hipLaunchKernelGGL(otf32_statepass_kernel<2>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, logD,
+                         part);
+    }
+    return hipGetLastError();
+  }
+#define OTF64_PASSES(D_, M_)                                                                      \
+  hipLaunchKernelGGL((otf64_colpass_kernel<D_, M_>), dim3(G), dim3(kOT), 0, s, K, N, m.xi, m.cf64, \
+                     logD, part_obj, part_flags);                                                 \
+  hipLaunchKernelGGL((otf64_statepass_kernel<D_, M_>), sg, dim3(kOT), 0, s, K, N, m.xi, m.cf64,   \
+                     logD, part)
+  if (m.model == BUMBAR_MODEL_HARMONIC) {
+    if (m.d == 1) {
+      OTF64_PASSES(1, BUMBAR_MODEL_HARMONIC);
+    } else {
+      OTF64_PASSES(2, BUMBAR_MODEL_HARMONIC);
+    }
+  } else {
+    if (m.d == 1) {
+      OTF64_PASSES(1, BUMBAR_MODEL_LINEAR);
+    } else {
+      OTF64_PASSES(2, BUMBAR_MODEL_LINEAR);
+    }
+  }
+#undef OTF64_PASSES
+  return hipGetLastError();
+}
+
+hipError_t launch_weights_otf(hipStream_t s, const OtfModel& m, int K, int64_t N, const double* f,
+                              const double* logD, double* W) {
+  const int64_t tot = (int64_t)K * N;
+  const dim3 g((unsigned)((tot + 255) / 256));
+  if (m.model == BUMBAR_MODEL_HARMONIC) {
+    if (m.d == 1)
+      hipLaunchKernelGGL((otf64_weights_kernel<1, BUMBAR_MODEL_HARMONIC>), g, dim3(256), 0, s, K,
+                         N, m.xi, m.coef, f, logD, W);
+    else
+      hipLaunchKernelGGL((otf64_weights_kernel<2, BUMBAR_MODEL_HARMONIC>), g, dim3(256), 0, s, K,
+                         N, m.xi, m.coef, f, logD, W);
+  } else {
+    if (m.d == 1)
+      hipLaunchKernelGGL((otf64_weights_kernel<1, BUMBAR_MODEL_LINEAR>), g, dim3(256), 0, s, K, N,
+                         m.xi, m.coef, f, logD, W);
+    else
+      hipLaunchKernelGGL((otf64_weights_kernel<2, BUMBAR_MODEL_LINEAR>), g, dim3(256), 0, s, K, N,
+                         m.xi, m.coef, f, logD, W);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bumbar
