@@ -23,8 +23,20 @@ footprint) is compared with the plain FP64 solver taking the same stream one
 problem at a time. Value: solves/s of the served run; p50/p99 latency from
 arrival to result; the largest |f - f_FP64| over all problems in kT.
 
+With --workload ladder: the temperature/alchemical ladder, K = 1000 states,
+N_k = 2000 (N = 2e6), u_kn = beta_k E_n + lambda_k V_n stored as a 16 GB FP64
+matrix (built on the device from E, V); plain MBAR (no binning) solved in
+FP64 and in mixed precision (FP32 packed sweeps, FP64 refinement).
+
+With --workload mb2d: the 2-D umbrella grid on the Muller-Brown surface,
+K = 40 x 40 = 1600 windows (kappa = 20), N_k = 5000 (N = 8e6), FP32 (x, y)
+samples; u_kn is never stored: every sweep evaluates the harmonic biases
+inside the kernel. Mixed-precision BU-MBAR (binned stage on bin centres,
+FP32 model sweeps in the Newton stage, FP64 refinement).
+
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
        python bench.py --workload stream [--n-problems 512] [--rate 100]
+       python bench.py --workload ladder|mb2d [--steps 2]
 """
 from __future__ import annotations
 
@@ -55,7 +67,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["double_well", "stream"], default="double_well")
+    ap.add_argument("--workload", choices=["double_well", "stream", "ladder", "mb2d"],
+                    default="double_well")
     ap.add_argument("--n-problems", type=int, default=512)
     ap.add_argument("--rate", type=float, default=100.0, help="stream arrivals per second")
     ap.add_argument("--max-active", type=int, default=8)
@@ -81,6 +94,10 @@ def main():
         sys.exit(1)
     if args.workload == "stream":
         return run_stream(args, bm, stream)
+    if args.workload == "ladder":
+        return run_ladder(args, bm, synth)
+    if args.workload == "mb2d":
+        return run_mb2d(args, bm, synth)
     dev = torch.device("cuda:0")
     t = time.time()
     p = synth.double_well(K=100, Nk=10000, seed=1)
@@ -179,6 +196,143 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def _timed_solves(bm, args, label, solve):
+    """Warm-up and timed solves; returns (last f, infos, ms per solve)."""
+    import torch
+    for i in range(args.warmup):
+        f, info = solve(False)
+        log(f"{label} warmup {i}: status={info['status']} p1={info['phase1_iters']} "
+            f"p2={info['phase2_iters']} newton={info['finisher_steps']} "
+            f"mixed={info['mixed_steps']} hess={info['hessians']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        f, info = solve(True)
+        infos.append(info)
+        log(f"{label} step {i}: status={info['status']} binning={info['time_binning_ms']:.1f}ms "
+            f"binned={info['time_binned_ms']:.1f}ms final={info['time_final_ms']:.1f}ms "
+            f"sweeps={info['unbinned_sweeps']} newton={info['finisher_steps']} "
+            f"hess={info['hessians']} sweep_ms={info['sweep_kernel_ms']:.2f}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    return f, infos, ms
+
+
+def _avg_sweep_s(infos):
+    ms = sum(i["sweep_kernel_ms"] for i in infos)
+    n = sum(i["sweep_kernel_launches"] for i in infos)
+    return ms / max(1, n) / 1e3, n
+
+
+def _base_line(args, value, unit, ms, dtype, config):
+    return {
+        "metric": "sweep K*N elem/s + time-to-solve at 1e-6 kT; batched solves/s, p50/p99",
+        "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic", "config": config,
+    }
+
+
+def run_ladder(args, bm, synth):
+    import torch
+    t = time.time()
+    p = synth.ladder_2d(K=1000, Nk=2000, seed=2, materialize=False)
+    K, N = p["K"], p["N"]
+    xi = torch.tensor(p["xi"], device="cuda")
+    coef = torch.tensor(p["coef"], device="cuda")
+    u = bm.model_energies(xi, coef, bm.MODEL_LINEAR, K)  # stored K x N FP64 (16 GB)
+    Nk = torch.tensor(p["Nk"], device="cuda")
+    torch.cuda.synchronize()
+    log(f"ladder generated in {time.time() - t:.1f}s: K={K} N={N}, u {u.numel() * 8 / 1e9:.1f} GB")
+    ctx = bm.context()
+    res = {}
+    for name, prec in (("f64", bm.PREC_FP64), ("mixed", bm.PREC_MIXED)):
+        f, infos, ms = _timed_solves(
+            bm, args, name,
+            lambda prof, prec=prec: bm.solve(u, Nk, tol=args.tol, precision=prec,
+                                             profile=int(prof), ctx=ctx))
+        sw, n = _avg_sweep_s(infos)
+        res[name] = dict(f=f.cpu().numpy(), ms=ms, sweep_s=sw, launches=n, info=infos[-1])
+    diff = float(np.max(np.abs(res["mixed"]["f"] - res["f64"]["f"])))
+    # single-sweep rates of the two stored-matrix sweeps at the solution
+    f0 = torch.tensor(res["f64"]["f"], device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bm.sweep(u, Nk, f0, ctx=ctx, with_stats=False)
+    e0.record(ctx.stream)
+    for _ in range(5):
+        bm.sweep(u, Nk, f0, ctx=ctx, with_stats=False)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    f64_sweep_s = e0.elapsed_time(e1) / 5e3
+    elems = K * N
+    achieved = 8.0 * elems / f64_sweep_s / 1e9
+    out = _base_line(args, elems / f64_sweep_s, "elem/s", res["f64"]["ms"], "f64", {
+        "workload": "ladder u_kn = beta_k E_n + lambda_k V_n, K=1000, N=2e6 (N_k=2000), "
+                    "u_kn 1000x2e6 FP64 stored, plain MBAR (SCI to 1e-3 then Newton)",
+        "K": K, "N": N, "tol_kT": args.tol})
+    out.update({
+        "time_to_solve_s": {"f64": res["f64"]["ms"] / 1e3, "mixed": res["mixed"]["ms"] / 1e3},
+        "sweep_kernel_us_in_solve": {k: v["sweep_s"] * 1e6 for k, v in res.items()},
+        "max_abs_diff_mixed_vs_f64_kT": diff,
+        "grad_norm": res["f64"]["info"]["grad_norm"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": None,
+    })
+    print(json.dumps(out), flush=True)
+
+
+def run_mb2d(args, bm, synth):
+    import torch
+    t = time.time()
+    p = synth.muller_brown_grid(G=40, Nk=5000, seed=4)
+    K, N = p["K"], p["N"]
+    xi = torch.tensor(p["xi"], device="cuda")
+    coef = torch.tensor(p["coef"], device="cuda")
+    Nk = torch.tensor(p["Nk"], device="cuda")
+    torch.cuda.synchronize()
+    log(f"muller-brown grid generated in {time.time() - t:.1f}s: K={K} N={N}")
+    ctx = bm.context()
+    f, infos, ms = _timed_solves(
+        bm, args, "mixed",
+        lambda prof: bm.solve(None, Nk, xi=xi, model=bm.MODEL_HARMONIC, coef=coef, tol=args.tol,
+                              precision=bm.PREC_MIXED, profile=int(prof), ctx=ctx))
+    # single model sweeps at the solution, FP32 and FP64
+    rates = {}
+    for name, prec in (("f32", bm.PREC_MIXED), ("f64", bm.PREC_FP64)):
+        bm.sweep_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, precision=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn, lD, S, st = bm.sweep_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, precision=prec,
+                                           ctx=ctx)
+        torch.cuda.synchronize()
+        rates[name] = (time.perf_counter() - t0) / reps
+        if name == "f64":
+            residual = st["max_df"]
+            gnorm = st["grad_norm"]
+    elems = K * N
+    # two exponentials per element (column pass and state pass)
+    exp_rate = 2.0 * elems / rates["f32"] / 1e9
+    exp_peak = 256 * 16 * 2.4  # Gexp/s: 16 transcendental lanes per CU per clock
+    out = _base_line(args, elems / rates["f32"], "elem/s", ms, "f32+f64", {
+        "workload": "2-D umbrella grid on the Muller-Brown surface, K=1600 windows (kappa=20), "
+                    "N=8e6 (N_k=5000) FP32 (x,y); u_kn evaluated in-kernel, mixed-precision "
+                    "BU-MBAR", "K": K, "N": N, "tol_kT": args.tol})
+    out.update({
+        "time_to_solve_s": ms / 1e3,
+        "sweep_s": rates,
+        "fp64_sci_residual_kT": residual,
+        "grad_norm": gnorm,
+        "roofline": {"bound": "alu", "achieved": exp_rate, "peak": exp_peak, "unit": "Gexp/s",
+                     "frac": exp_rate / exp_peak, "traffic": None},
+        "cpu_baseline": None,
+    })
     print(json.dumps(out), flush=True)
 
 

@@ -23,8 +23,9 @@ namespace bumbar {
 
 constexpr int kCountSlots = 8192;
 
-void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus) {
+void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool otf_mode) {
   (void)num_cus;
+  otf = otf_mode;
   d = d_;
   N = N_;
   q = ar.take<uint32_t>((size_t)N * d);
@@ -44,7 +45,10 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus) {
   sort_tmp_bytes = sort_temp_bytes(N);
   sort_tmp = ar.take<char>(sort_tmp_bytes);
   for (int i = 0; i < 2; ++i) {
-    ubar[i] = ar.take<double>((size_t)K * N);
+    if (otf)
+      cen[i] = ar.take<double>((size_t)N * d);
+    else
+      ubar[i] = ar.take<double>((size_t)K * N);
     h[i] = ar.take<double>(N);
   }
   logD_lvl = ar.take<double>(N);
@@ -52,9 +56,9 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus) {
   f_x = ar.take<double>(K);
 }
 
-void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus) {
+void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode) {
   BinnedBufs b;
-  b.carve(ar, K, N, d, num_cus);
+  b.carve(ar, K, N, d, num_cus, otf_mode);
 }
 
 static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
@@ -136,18 +140,32 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
   if (rc) return rc;
   if (P != g) return fail(ctx, BUMBAR_EDEVICE, "histogram size %lld != g(m) %lld", (long long)P,
                           (long long)g);
-  hipError_t e = launch_represent(ctx->stream, K, BB.N, BB.d, model, coef, BB.lo, BB.scale, m, P,
-                                  BB.cells, BB.start, BB.perm, u, BB.ubar[slot], BB.h[slot]);
+  hipError_t e;
+  if (BB.otf)
+    e = launch_centres(ctx->stream, BB.d, BB.lo, BB.scale, m, P, BB.cells, BB.start,
+                       BB.cen[slot], BB.h[slot]);
+  else
+    e = launch_represent(ctx->stream, K, BB.N, BB.d, model, coef, BB.lo, BB.scale, m, P,
+                         BB.cells, BB.start, BB.perm, u, BB.ubar[slot], BB.h[slot]);
   if (e != hipSuccess) return hip_fail(ctx, e, "represent");
   L->n = n;
   L->m = m;
   L->P = P;
-  L->ubar = BB.ubar[slot];
+  L->ubar = BB.otf ? nullptr : BB.ubar[slot];
+  L->cen = BB.otf ? BB.cen[slot] : nullptr;
   L->h = BB.h[slot];
   return BUMBAR_OK;
 }
 
-static Mat level_mat(const Level& L) {
+// The matrix of a level: stored representatives, or the model evaluated at
+// the bin centres (FP64) when the stage runs on the fly.
+static Mat level_mat_of(const Level& L, const Mat* otf_base) {
+  if (otf_base) {
+    Mat M = *otf_base;
+    M.kind = 4;
+    M.otf.xi = L.cen;
+    return M;
+  }
   Mat M;
   M.u = L.ubar;
   M.kind = 0;
@@ -155,18 +173,11 @@ static Mat level_mat(const Level& L) {
   return M;
 }
 
-static int binned_sci(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const Level& L,
-                      const int64_t* Nk, const double* f, double* f_out, SweepScalars* sc,
-                      SweepCounters* cnt) {
-  (void)cnt;  // binned sweeps are counted by the stage's iteration counters
-  return sweep_at(ctx, B, level_mat(L), L.P, L.h, Nk, f, f_out, BB.logD_lvl, B.lnS_t, B.S_t, sc,
-                  false, nullptr);
-}
-
 int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double* u,
                  const int64_t* Nk_dev, const int64_t* Nk_host, const double* xi, int d,
                  int model, const double* coef, const bumbar_options& opt, bumbar_stats* st,
-                 SweepCounters* cnt) {
+                 SweepCounters* cnt, const Mat* otf_base) {
+  auto level_mat = [otf_base](const Level& L) { return level_mat_of(L, otf_base); };
   (void)Nk_host;
   hipStream_t s = ctx->stream;
   const int K = B.K;
@@ -191,7 +202,9 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   // f, see the sweep) is redone on the robust path before anything else.
   hipError_t e = hipMemcpyAsync(BB.f_n, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
-  const bool fast = sweep_fast_supported(K);
+  // batched steps need a kernel that never needs the robust rerun in the
+  // common case: the register-tiled FP64 sweep, or the model sweep
+  const bool fast = otf_base != nullptr || sweep_fast_supported(K);
   std::vector<SweepScalars> hs(kHistSteps);
   auto fh = [&](int i) { return B.f_hist + (size_t)i * K; };
   auto set_current = [&](const double* src) -> int {
@@ -386,7 +399,7 @@ extern "C" int bumbar_bin(bumbar_ctx* ctx, const double* xi, int64_t N, int d, i
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BUMBAR_EDEVICE, "hipSetDevice");
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
   BinnedBufs BB;
-  BB.carve(ar, 1, N, d, ctx->num_cus);
+  BB.carve(ar, 1, N, d, ctx->num_cus, false);
   if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
   int rc = quantize_all(ctx, BB, xi);
   if (rc) return rc;

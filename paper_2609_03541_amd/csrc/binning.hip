@@ -397,6 +397,39 @@ hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, c
   return hipGetLastError();
 }
 
+// Bin centres (P x d) and multiplicities of the current histogram: the
+// coordinates at which the bias model gives the bin representative (the
+// same centre as in represent_kernel), for sweeps that evaluate the model
+// inside the kernel instead of storing K x P representatives.
+__global__ void centres_kernel(int d, const double* __restrict__ lo,
+                               const double* __restrict__ scale, uint64_t m, int64_t P,
+                               const uint64_t* __restrict__ cells,
+                               const int64_t* __restrict__ start, double* __restrict__ cen,
+                               double* __restrict__ h) {
+  const int64_t p = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (p >= P) return;
+  h[p] = (double)(start[p + 1] - start[p]);
+  uint64_t cc[2];
+  if (d == 1) {
+    cc[0] = cells[p];
+    cc[1] = 0;
+  } else {
+    const uint64_t stride = 4294967295ull / m + 1ull;
+    cc[0] = cells[p] % stride;
+    cc[1] = cells[p] / stride;
+  }
+  for (int j = 0; j < d; ++j)
+    cen[p * d + j] = scale[j] > 0.0 ? lo[j] + ((double)cc[j] + 0.5) * (double)m / scale[j] : lo[j];
+}
+
+hipError_t launch_centres(hipStream_t s, int d, const double* lo, const double* scale, uint64_t m,
+                          int64_t P, const uint64_t* cells, const int64_t* start, double* cen,
+                          double* h) {
+  hipLaunchKernelGGL(centres_kernel, dim3((unsigned)((P + kBT - 1) / kBT)), dim3(kBT), 0, s, d, lo,
+                     scale, m, P, cells, start, cen, h);
+  return hipGetLastError();
+}
+
 __global__ void sample_bin_kernel(int64_t N, const uint32_t* __restrict__ perm,
                                   const int32_t* __restrict__ bin_of_pos,
                                   int32_t* __restrict__ sample_bin) {

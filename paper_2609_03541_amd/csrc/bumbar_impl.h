@@ -115,10 +115,12 @@ struct OtfModel {
 size_t otf_coef_floats(int K, int d);  // entries of cf32 (and of cf64)
 int otf_grid(int64_t N, int num_cus);
 hipError_t launch_pack_coords(hipStream_t s, int64_t n, const double* xi, float* xf);
-// Two-pass sweep with u from the model (FP32 or FP64 arithmetic); also
-// rebuilds the per-sweep coefficients from cst / gk. Partials state-major.
+// Two-pass sweep with u from the model (FP32 or FP64 arithmetic) at the N
+// points of m.xi / m.xf with multiplicities h (NULL: 1); also rebuilds the
+// per-sweep coefficients from cst / gk. Partials state-major.
 hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
-                            const double* cst, const double* gk, double* logD, double* part,
+                            const double* cst, const double* gk, const double* h, double* logD,
+                            double* part,
                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out);
 // Rebuilds only the per-sweep coefficients (cf32 or cf64) from cst / gk.
 hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, const double* cst,
@@ -158,6 +160,13 @@ hipError_t launch_sweep32(hipStream_t s, const float* r, int64_t ld, int K, int6
 // the unsampled ones). A: workspace K*K doubles, idx: K ints. ok: device int.
 hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, const double* H,
                                    const double* S, double* A, int* idx, double* d, int* ok);
+// Largest reduced size the single-workgroup LDS solve takes.
+int newton_lds_max_m();
+// Blocked Cholesky solve of the same reduced system for any m; idx (m
+// entries, the kept states) must be on the device; A holds m*m + m doubles.
+hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
+                                           const double* H, const double* S, double* A,
+                                           const int* idx, double* d, int* ok);
 // u_kn = model_k(xi_n), K x N FP64 with row stride N; d in {1, 2}.
 hipError_t launch_model_energies(hipStream_t s, int K, int64_t N, int d, int model,
                                  const double* coef, const double* xi, double* u);

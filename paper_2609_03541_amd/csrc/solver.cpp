@@ -143,10 +143,9 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
     e = launch_sweep32(s, reinterpret_cast<const float*>(M.u), M.ld, K, N, B.dk, B.gk, M.m0,
                        logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind >= 3) {
-    if (h != nullptr) return fail(ctx, BUMBAR_EINVAL, "on-the-fly sweeps are unbinned");
     if (ev) (void)hipEventRecord(ev->first, s);
-    e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, logD_out, B.part, B.part_obj,
-                         B.part_flags, ctx->num_cus, &grid);
+    e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, h, logD_out, B.part,
+                         B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind == 0 && sweep_fast_supported(K)) {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_fast(s, reinterpret_cast<const double*>(M.u), M.ld, K, N, B.cst, B.gk, h,
@@ -259,8 +258,9 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
   const int K = B.K;
   const int64_t N = B.N;
   SweepScalars sc{};
+  const bool fp32 = M.kind == 2 || M.kind == 3;
   auto bad32 = [&](const SweepScalars& x) {
-    return M.kind == 2 && (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
+    return fp32 && (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
   };
   // the sweep at the starting point; unsampled states filled and the gauge
   // fixed afterwards (neither changes S of sampled states, ln D - c or the
@@ -283,7 +283,10 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
     return BUMBAR_OK;
   };
   auto direction = [&](int* ok) -> int {
-    hipError_t e2 = launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
+    hipError_t e2 = (B.m_red > newton_lds_max_m())
+                        ? launch_newton_direction_blocked(s, K, B.m_red, Nk, B.H, B.S, B.A, B.idx,
+                                                          B.dir, B.ok)
+                        : launch_newton_direction(s, K, Nk, B.H, B.S, B.A, B.idx, B.dir, B.ok);
     if (e2 != hipSuccess) return hip_fail(ctx, e2, "newton_direction");
     return read_bytes(ctx, B.ok, ok, sizeof(int));
   };
@@ -313,7 +316,10 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
       }
       if (!ok) break;
       double alpha = 1.0;
-      for (int t = 0; t <= 10; ++t, alpha *= 0.5) {
+      // FP32 kinds take full steps only: below the FP32 resolution the
+      // gradient norm stops falling and the FP64 refinement takes over
+      const int max_t = fp32 ? 0 : 10;
+      for (int t = 0; t <= max_t; ++t, alpha *= 0.5) {
         e = launch_axpy_to(s, K, B.f, alpha, B.dir, B.f_trial);
         if (e != hipSuccess) return hip_fail(ctx, e, "axpy");
         rc = sweep_at(ctx, B, M, N, nullptr, Nk, B.f_trial, B.f_new, B.logD_t, B.lnS_t, B.S_t,
@@ -330,12 +336,14 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
         }
         if (!fresh) break;
       }
-      if (accepted || flagged || fresh) break;
+      // a stale Hessian that fails is rebuilt, except in the FP32 kinds: there
+      // the failure means the FP32 noise floor, and the FP64 stage takes over
+      if (accepted || flagged || fresh || fp32) break;
       rc = build_hessian();
       if (rc) return rc;
       fresh = true;
     }
-    if (flagged) {
+    if (flagged || (fp32 && !accepted)) {
       rc = BUMBAR_ENOTCONV;
       break;
     }
@@ -684,7 +692,8 @@ int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
   Arena ar;
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
-  if (d > 0 && (opt == nullptr || opt->binning)) binned_carve_size(ar, K, N, d, ctx->num_cus);
+  if (d > 0 && (opt == nullptr || opt->binning))
+    binned_carve_size(ar, K, N, d, ctx->num_cus, false);
   if (opt && opt->precision == BUMBAR_PREC_MIXED && sweep32_supported(K)) {
     MixedBufs X;
     X.carve(ar, K, N);
@@ -699,7 +708,7 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
   Arena ar;
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
-  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus);
+  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus, true);
   OtfBufs O;
   O.carve(ar, K, N, d);
   *bytes = ar.off + 256;
@@ -753,7 +762,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
   BinnedBufs BB;
-  if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus);
+  if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus, otf);
   MixedBufs X;
   if (mixed && !otf) X.carve(ar, K, N);
   OtfBufs O;
@@ -787,6 +796,19 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   SweepCounters cnt;
   ctx->profiling = opt.profile != 0;
   ctx->events_used = 0;
+  // kept states of the reduced Newton system (all sampled states but the
+  // first), uploaded once for the blocked solve of large systems
+  std::vector<int> kept;
+  for (int k = 0, first = 1; k < K; ++k)
+    if (nk[k] > 0) {
+      if (!first) kept.push_back(k);
+      first = 0;
+    }
+  if ((int)kept.size() > newton_lds_max_m()) {
+    e = hipMemcpyAsync(B.idx, kept.data(), sizeof(int) * kept.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload idx");
+    B.m_red = (int)kept.size();
+  }
   if (f_init && !opt.binning)
     e = hipMemcpyAsync(B.f, f_init, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
   else
@@ -796,7 +818,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   int stage_rc = BUMBAR_OK;
   if (opt.binning) {
     stage_rc = binned_stage(ctx, B, BB, reinterpret_cast<const double*>(u_kn), N_k, nk.data(), xi,
-                            d, model, coef, opt, st, &cnt);
+                            d, model, coef, opt, st, &cnt, otf ? &M : nullptr);
     if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
   } else if (opt.finisher == BUMBAR_FINISH_NEWTON) {
     const double t0 = now_ms();

@@ -71,6 +71,7 @@ struct UnbinnedBufs {
   double* dk = nullptr;  // f - f0 for the packed matrix
   int hess_chunks = 1;
   bool H_valid = false;  // H holds a Hessian usable for chord steps
+  int m_red = -1;        // reduced Newton size when idx was uploaded by the host, else -1
   void carve(Arena& ar, int K, int64_t N, int num_cus);
 };
 
@@ -98,7 +99,8 @@ struct Level {
   int64_t n = 0;   // nominal target
   uint64_t m = 0;  // width in quanta
   int64_t P = 0;   // nonempty bins
-  double* ubar = nullptr;  // K x P (row stride P)
+  double* ubar = nullptr;  // K x P (row stride P); stored representatives
+  double* cen = nullptr;   // P x d bin centres; representatives from the model
   double* h = nullptr;     // P multiplicities (as double)
 };
 
@@ -121,19 +123,23 @@ struct BinnedBufs {
   int64_t* counts = nullptr;     // reduction scratch
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
-  double* ubar[2] = {nullptr, nullptr};  // K x N each (worst case P = N)
+  bool otf = false;                      // representatives from the model in the kernels
+  double* ubar[2] = {nullptr, nullptr};  // K x N each (worst case P = N); stored mode
+  double* cen[2] = {nullptr, nullptr};   // N x d each (worst case P = N); otf mode
   double* h[2] = {nullptr, nullptr};     // N each
   double* logD_lvl = nullptr;            // N
   double *f_n = nullptr, *f_x = nullptr; // K
-  void carve(Arena& ar, int K, int64_t N, int d, int num_cus);
+  void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode);
 };
 
-void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus);
+void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode);
 
+// otf_base: nullptr for stored representatives, else the FP64 model matrix
+// (kind 4) whose coordinates the stage replaces by the bin centres.
 int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double* u,
                  const int64_t* Nk_dev, const int64_t* Nk_host, const double* xi, int d,
                  int model, const double* coef, const bumbar_options& opt, bumbar_stats* st,
-                 SweepCounters* cnt);
+                 SweepCounters* cnt, const Mat* otf_base);
 
 // Binning primitives (binning.hip).
 size_t sort_temp_bytes(int64_t N);
@@ -161,6 +167,9 @@ hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, c
                             const double* lo, const double* scale, uint64_t m, int64_t P,
                             const uint64_t* cells, const int64_t* start, const uint32_t* perm,
                             const double* u, double* ubar, double* h);
+hipError_t launch_centres(hipStream_t s, int d, const double* lo, const double* scale, uint64_t m,
+                          int64_t P, const uint64_t* cells, const int64_t* start, double* cen,
+                          double* h);
 hipError_t launch_sample_bin(hipStream_t s, int64_t N, const uint32_t* perm,
                              const int32_t* bin_of_pos, int32_t* sample_bin);
 hipError_t launch_counts_from_start(hipStream_t s, int64_t P, const int64_t* start, int64_t* H);

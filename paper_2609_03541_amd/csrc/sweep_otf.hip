@@ -123,7 +123,8 @@ __device__ __forceinline__ double model_rest(const double* h, const double* x0, 
 template <int D>
 __global__ void __launch_bounds__(kOT)
     otf32_colpass_kernel(int K, int64_t N, const float* __restrict__ xf,
-                         const float* __restrict__ cf, double* __restrict__ logD,
+                         const float* __restrict__ cf, const double* __restrict__ h,
+                         double* __restrict__ logD,
                          double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
   __shared__ float sA[kOTile];
   __shared__ float sB[D][kOTile];
@@ -205,13 +206,13 @@ __global__ void __launch_bounds__(kOT)
       if (!(m0 > -1e30f && s0 > 0.f && s0 < INFINITY)) bad |= FLAG_COL;
       const double l0 = ((double)m0 + (double)__builtin_amdgcn_logf(s0)) * kLn2;
       logD[n0] = l0;
-      obj += l0;
+      obj = __builtin_fma(h ? h[n0] : 1.0, l0, obj);
     }
     if (ok1) {
       if (!(m1 > -1e30f && s1 > 0.f && s1 < INFINITY)) bad |= FLAG_COL;
       const double l1 = ((double)m1 + (double)__builtin_amdgcn_logf(s1)) * kLn2;
       logD[n0 + 1] = l1;
-      obj += l1;
+      obj = __builtin_fma(h ? h[n0 + 1] : 1.0, l1, obj);
     }
   }
 #pragma unroll
@@ -230,8 +231,8 @@ __global__ void __launch_bounds__(kOT)
 template <int D>
 __global__ void __launch_bounds__(kOT)
     otf32_statepass_kernel(int K, int64_t N, const float* __restrict__ xf,
-                           const float* __restrict__ cf, const double* __restrict__ logD,
-                           double* __restrict__ part) {
+                           const float* __restrict__ cf, const double* __restrict__ h,
+                           const double* __restrict__ logD, double* __restrict__ part) {
   constexpr int R = kOStates / 4;  // states per thread
   const int lc = threadIdx.x & 63;
   const int rg = threadIdx.x >> 6;
@@ -263,6 +264,9 @@ __global__ void __launch_bounds__(kOT)
     const float e0 = (float)(-kLog2e * logD[n0]);
     // a missing second column contributes exp2(-inf) = 0
     const float e1 = two ? (float)(-kLog2e * logD[n0 + 1]) : -INFINITY;
+    // bin multiplicities (exact in FP32 below 2^24 samples per bin)
+    const float h0 = h ? (float)h[n0] : 1.f;
+    const float h1 = h && two ? (float)h[n0 + 1] : 1.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       float v0 = A[r] + e0, v1 = A[r] + e1;
@@ -273,7 +277,8 @@ __global__ void __launch_bounds__(kOT)
         v1 = __builtin_fmaf(B[j][r], x1[j], v1);
         v1 = __builtin_fmaf(C[j][r], q1[j], v1);
       }
-      acc[r] += __builtin_amdgcn_exp2f(v0) + __builtin_amdgcn_exp2f(v1);
+      acc[r] = __builtin_fmaf(h0, __builtin_amdgcn_exp2f(v0), acc[r]);
+      acc[r] = __builtin_fmaf(h1, __builtin_amdgcn_exp2f(v1), acc[r]);
     }
   }
 #pragma unroll
@@ -291,7 +296,8 @@ __global__ void __launch_bounds__(kOT)
 template <int D, int MODEL>
 __global__ void __launch_bounds__(kOT)
     otf64_colpass_kernel(int K, int64_t N, const double* __restrict__ xi,
-                         const double* __restrict__ c64, double* __restrict__ logD,
+                         const double* __restrict__ c64, const double* __restrict__ h,
+                         double* __restrict__ logD,
                          double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
   constexpr int T = kOTile / 2;  // FP64 tile: half the states of the FP32 tile
   __shared__ double sE[T];
@@ -337,15 +343,15 @@ __global__ void __launch_bounds__(kOT)
           const int i = c0 + q;
           const bool in = i < tl;
           const int ii = in ? i : 0;
-          double h[D], xc[D];
+          double hc[D], xc[D];
 #pragma unroll
           for (int j = 0; j < D; ++j) {
-            h[j] = sH[j][ii];
+            hc[j] = sH[j][ii];
             xc[j] = sX[j][ii];
           }
           const double e = in ? sE[ii] : -INFINITY;
-          a0[q] = e - model_rest<D, MODEL>(h, xc, x0);
-          a1[q] = e - model_rest<D, MODEL>(h, xc, x1);
+          a0[q] = e - model_rest<D, MODEL>(hc, xc, x0);
+          a1[q] = e - model_rest<D, MODEL>(hc, xc, x1);
           cm0 = fmax(cm0, a0[q]);
           cm1 = fmax(cm1, a1[q]);
         }
@@ -368,13 +374,13 @@ __global__ void __launch_bounds__(kOT)
       if (!(m0 > -INFINITY && m0 < INFINITY)) bad |= FLAG_COL;
       const double l0 = m0 + log(s0);
       logD[n0] = l0;
-      obj += l0;
+      obj = __builtin_fma(h ? h[n0] : 1.0, l0, obj);
     }
     if (ok1) {
       if (!(m1 > -INFINITY && m1 < INFINITY)) bad |= FLAG_COL;
       const double l1 = m1 + log(s1);
       logD[n0 + 1] = l1;
-      obj += l1;
+      obj = __builtin_fma(h ? h[n0 + 1] : 1.0, l1, obj);
     }
   }
 #pragma unroll
@@ -393,8 +399,8 @@ __global__ void __launch_bounds__(kOT)
 template <int D, int MODEL>
 __global__ void __launch_bounds__(kOT)
     otf64_statepass_kernel(int K, int64_t N, const double* __restrict__ xi,
-                           const double* __restrict__ c64, const double* __restrict__ logD,
-                           double* __restrict__ part) {
+                           const double* __restrict__ c64, const double* __restrict__ h,
+                           const double* __restrict__ logD, double* __restrict__ part) {
   constexpr int R = kOStates / 8;  // 8 states per thread; two row-group passes per block
   const int lc = threadIdx.x & 63;
   const int rg = threadIdx.x >> 6;
@@ -425,16 +431,20 @@ __global__ void __launch_bounds__(kOT)
       }
       const double l0 = logD[n0];
       const double l1 = two ? logD[n0 + 1] : INFINITY;  // exp(-inf) = 0 for a missing column
+      const double w0 = h ? h[n0] : 1.0;
+      const double w1 = h && two ? h[n0 + 1] : 1.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double h[D], xc[D];
+        double hc[D], xc[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-          h[j] = H[j][r];
+          hc[j] = H[j][r];
           xc[j] = X[j][r];
         }
-        acc[r] += exp_nonpos(E[r] - l0 - model_rest<D, MODEL>(h, xc, x0));
-        acc[r] += exp_nonpos(E[r] - l1 - model_rest<D, MODEL>(h, xc, x1));
+        acc[r] = __builtin_fma(w0, exp_nonpos(E[r] - l0 - model_rest<D, MODEL>(hc, xc, x0)),
+                               acc[r]);
+        acc[r] = __builtin_fma(w1, exp_nonpos(E[r] - l1 - model_rest<D, MODEL>(hc, xc, x1)),
+                               acc[r]);
       }
     }
 #pragma unroll
@@ -497,7 +507,8 @@ hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, 
 }
 
 hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
-                            const double* cst, const double* gk, double* logD, double* part,
+                            const double* cst, const double* gk, const double* h, double* logD,
+                            double* part,
                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out) {
   if (m.d != 1 && m.d != 2) return hipErrorInvalidValue;
   const int G = otf_grid(N, num_cus);
@@ -508,22 +519,22 @@ hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, 
   if (fp32) {
     if (m.d == 1) {
       hipLaunchKernelGGL(otf32_colpass_kernel<1>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,
-                         logD, part_obj, part_flags);
-      hipLaunchKernelGGL(otf32_statepass_kernel<1>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, logD,
-                         part);
+                         h, logD, part_obj, part_flags);
+      hipLaunchKernelGGL(otf32_statepass_kernel<1>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, h,
+                         logD, part);
     } else {
       hipLaunchKernelGGL(otf32_colpass_kernel<2>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,
-                         logD, part_obj, part_flags);
-      hipLaunchKernelGGL(otf32_statepass_kernel<2>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, logD,
-                         part);
+                         h, logD, part_obj, part_flags);
+      hipLaunchKernelGGL(otf32_statepass_kernel<2>, sg, dim3(kOT), 0, s, K, N, m.xf, m.cf32, h,
+                         logD, part);
     }
     return hipGetLastError();
   }
 #define OTF64_PASSES(D_, M_)                                                                      \
   hipLaunchKernelGGL((otf64_colpass_kernel<D_, M_>), dim3(G), dim3(kOT), 0, s, K, N, m.xi, m.cf64, \
-                     logD, part_obj, part_flags);                                                 \
+                     h, logD, part_obj, part_flags);                                              \
   hipLaunchKernelGGL((otf64_statepass_kernel<D_, M_>), sg, dim3(kOT), 0, s, K, N, m.xi, m.cf64,   \
-                     logD, part)
+                     h, logD, part)
   if (m.model == BUMBAR_MODEL_HARMONIC) {
     if (m.d == 1) {
       OTF64_PASSES(1, BUMBAR_MODEL_HARMONIC);
