@@ -225,6 +225,138 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// ---- K <= 256: one workgroup per chunk of samples covers every state -------
+//
+// Per step of 16 samples the workgroup forms P for all K_pad = 16 ceil(K/16)
+// rows once (one exponential per element, rows of 16 samples read as four
+// 32-byte runs) into LDS, then its waves accumulate the upper-triangle 16 x 16
+// tiles of G = P P^T, tile t going to wave t % NW (TPW tiles per wave, FP64
+// accumulators in registers). Each chunk writes its K_pad x K_pad partial
+// (upper tiles) for the fixed-order reduction.
+constexpr int kSmallMaxK = 256;
+
+template <class Src, int NW, int TPW>
+__global__ void __launch_bounds__(NW * 64)
+    hessian_small_kernel(Src src, int K, int Kp, int64_t N, const double* __restrict__ cst,
+                         const double* __restrict__ gk, const double* __restrict__ logD,
+                         int64_t chunk_len, double* __restrict__ partials) {
+  constexpr int NT = NW * 64;
+  constexpr int RPP = NT / 4;  // rows per loader pass
+  __shared__ double P[kSmallMaxK][HP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int T = Kp / 16;
+  const int ntiles = T * (T + 1) / 2;
+  // tiles of this wave: t = wave + j NW -> (ti, tj), ti <= tj, row-major
+  int ti[TPW], tj[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    int t = wave + j * NW, a = 0;
+    if (t >= ntiles) t = -1;
+    if (t >= 0)
+      while (t >= T - a) {
+        t -= T - a;
+        ++a;
+      }
+    ti[j] = t >= 0 ? a : -1;
+    tj[j] = t >= 0 ? a + t : -1;
+  }
+  // loader rows of this thread: r = tid / 4 + pass * RPP
+  const int lr = tid >> 2;
+  const int ls = (tid & 3) * 4;
+  constexpr int MAXP = kSmallMaxK / RPP;
+  typename Src::Row rows[MAXP];
+  bool live[MAXP];
+#pragma unroll
+  for (int q = 0; q < MAXP; ++q) {
+    const int k = lr + q * RPP;
+    live[q] = k < K && gk[k] != 0.0;
+    rows[q] = src.row(live[q] ? k : 0, live[q] ? cst[k] : 0.0);
+  }
+  d4 acc[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  const int64_t n_begin = (int64_t)blockIdx.x * chunk_len;
+  int64_t n_end = n_begin + chunk_len;
+  if (n_end > N) n_end = N;
+  for (int64_t n0 = n_begin; n0 < n_end; n0 += HS) {
+    double col[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int64_t n = n0 + ls + w;
+      col[w] = n < n_end ? src.col(n, logD) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+      const int r = lr + q * RPP;
+      if (r < Kp) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int64_t n = n0 + ls + w;
+          P[r][ls + w] = (live[q] && n < n_end) ? src.p(rows[q], n, col[w]) : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sidx = 0; sidx < HS / 4; ++sidx) {
+      const int c = sidx * 4 + (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        if (ti[j] < 0) continue;  // uniform per wave
+        const double av = P[ti[j] * 16 + (lane & 15)][c];
+        const double bv = P[tj[j] * 16 + (lane & 15)][c];
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane l holds element v at row l/16 + 4 v, column l % 16 of each tile
+  double* out = partials + (int64_t)blockIdx.x * Kp * Kp;
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    if (ti[j] < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = ti[j] * 16 + (lane >> 4) + 4 * v;
+      const int c = tj[j] * 16 + (lane & 15);
+      out[(int64_t)r * Kp + c] = acc[j][v];
+    }
+  }
+}
+
+// H_ij = delta_ij S_i - sum_chunks G_ij for i <= j (upper tiles), mirrored.
+__global__ void __launch_bounds__(256)
+    hessian_small_reduce_kernel(int K, int Kp, int chunks, const double* __restrict__ partials,
+                                const double* __restrict__ S, const double* __restrict__ gk,
+                                double* __restrict__ H) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)K * K) return;
+  const int i = (int)(e / K), j = (int)(e % K);
+  if (j < i) return;
+  // the partial holds the upper tiles: (i, j) lies in tile (i/16, j/16) with
+  // i/16 <= j/16 since i <= j
+  double g = 0.0;
+  const double* p = partials + (int64_t)i * Kp + j;
+  for (int q = 0; q < chunks; ++q) g += p[(int64_t)q * Kp * Kp];
+  double v = -g;
+  if (i == j) v += (gk[i] != 0.0) ? S[i] : 0.0;
+  if (gk[i] == 0.0 || gk[j] == 0.0) v = 0.0;
+  H[(int64_t)i * K + j] = v;
+  H[(int64_t)j * K + i] = v;
+}
+
+static int small_kp(int K) { return (K + 15) / 16 * 16; }
+
+static int small_chunks(int64_t N, int num_cus) {
+  int64_t g = 2 * (int64_t)num_cus;
+  const int64_t by_n = (N + 255) / 256;  // at least 256 samples per chunk
+  if (g > by_n) g = by_n;
+  return (int)(g < 1 ? 1 : g);
+}
+
 // H_ij = delta_ij S_i - sum_chunks G_ij, written to both triangles.
 __global__ void __launch_bounds__(256)
     hessian_reduce_kernel(int K, int nb, int chunks, const double* __restrict__ partials,
@@ -252,6 +384,12 @@ __global__ void __launch_bounds__(256)
 static int hess_nb(int K) { return (K + HB - 1) / HB; }
 
 size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
+  if (K <= kSmallMaxK) {
+    const int ch = small_chunks(N, num_cus);
+    if (chunks_out) *chunks_out = ch;
+    const size_t kp = (size_t)small_kp(K);
+    return (size_t)ch * kp * kp;
+  }
   const int nb = hess_nb(K);
   const int nblk = nb * (nb + 1) / 2;
   // aim for about 4 workgroups per CU, each chunk at least 256 samples
@@ -272,6 +410,32 @@ static void launch_partial(hipStream_t s, const Src& src, int K, int64_t N, cons
                      cst, gk, logD, nb, chunks, chunk_len, partials);
 }
 
+template <class Src>
+static void launch_small(hipStream_t s, const Src& src, int K, int64_t N, const double* cst,
+                         const double* gk, const double* logD, int chunks, double* partials) {
+  const int Kp = small_kp(K);
+  int64_t chunk_len = (N + chunks - 1) / chunks;
+  chunk_len = (chunk_len + HS - 1) / HS * HS;
+  const int T = Kp / 16, nt = T * (T + 1) / 2;
+  // 4 waves up to 36 tiles (K <= 128), else 8 waves (up to 136 tiles)
+  if (nt <= 4 * 9)
+    hipLaunchKernelGGL((hessian_small_kernel<Src, 4, 9>), dim3(chunks), dim3(256), 0, s, src, K, Kp,
+                       N, cst, gk, logD, chunk_len, partials);
+  else
+    hipLaunchKernelGGL((hessian_small_kernel<Src, 8, 17>), dim3(chunks), dim3(512), 0, s, src, K,
+                       Kp, N, cst, gk, logD, chunk_len, partials);
+}
+
+template <class Src>
+static void launch_any(hipStream_t s, const Src& src, int K, int64_t N, const double* cst,
+                       const double* gk, const double* logD, int nb, int chunks,
+                       int64_t chunk_len, double* partials) {
+  if (K <= kSmallMaxK)
+    launch_small(s, src, K, N, cst, gk, logD, chunks, partials);
+  else
+    launch_partial(s, src, K, N, cst, gk, logD, nb, chunks, chunk_len, partials);
+}
+
 hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
                           const double* S, double* partials, int chunks, double* H) {
@@ -281,44 +445,48 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   chunk_len = (chunk_len + HS - 1) / HS * HS;
   switch (hs.kind) {
     case 0:
-      launch_partial(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
+      launch_any(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
                      gk, logD, nb, chunks, chunk_len, partials);
       break;
     case 1:
-      launch_partial(s, SrcMat<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst, gk,
+      launch_any(s, SrcMat<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst, gk,
                      logD, nb, chunks, chunk_len, partials);
       break;
     case 2:
-      launch_partial(s, SrcPacked{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N, cst,
+      launch_any(s, SrcPacked{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N, cst,
                      gk, logD, nb, chunks, chunk_len, partials);
       break;
     case 3:
       if (hs.otf.d == 1)
-        launch_partial(s, SrcModel32<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
+        launch_any(s, SrcModel32<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
                        chunk_len, partials);
       else
-        launch_partial(s, SrcModel32<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
+        launch_any(s, SrcModel32<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb, chunks,
                        chunk_len, partials);
       break;
     default:
       if (hs.otf.model == BUMBAR_MODEL_HARMONIC) {
         if (hs.otf.d == 1)
-          launch_partial(s, SrcModel64<1, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+          launch_any(s, SrcModel64<1, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
                          cst, gk, logD, nb, chunks, chunk_len, partials);
         else
-          launch_partial(s, SrcModel64<2, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+          launch_any(s, SrcModel64<2, BUMBAR_MODEL_HARMONIC>{hs.otf.xi, hs.otf.cf64, K}, K, N,
                          cst, gk, logD, nb, chunks, chunk_len, partials);
       } else {
         if (hs.otf.d == 1)
-          launch_partial(s, SrcModel64<1, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+          launch_any(s, SrcModel64<1, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
                          cst, gk, logD, nb, chunks, chunk_len, partials);
         else
-          launch_partial(s, SrcModel64<2, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
+          launch_any(s, SrcModel64<2, BUMBAR_MODEL_LINEAR>{hs.otf.xi, hs.otf.cf64, K}, K, N,
                          cst, gk, logD, nb, chunks, chunk_len, partials);
       }
   }
-  hipLaunchKernelGGL(hessian_reduce_kernel, dim3(HB * HB / 256, nblk), dim3(256), 0, s, K, nb,
-                     chunks, partials, S, gk, H);
+  if (K <= kSmallMaxK)
+    hipLaunchKernelGGL(hessian_small_reduce_kernel, dim3((unsigned)(((int64_t)K * K + 255) / 256)),
+                       dim3(256), 0, s, K, small_kp(K), chunks, partials, S, gk, H);
+  else
+    hipLaunchKernelGGL(hessian_reduce_kernel, dim3(HB * HB / 256, nblk), dim3(256), 0, s, K, nb,
+                       chunks, partials, S, gk, H);
   return hipGetLastError();
 }
 

@@ -100,7 +100,8 @@ def test_robust_path_far_from_solution(bm):
     assert np.max(np.abs(fn.cpu().numpy() - fn_ref)) < 1e-9
 
 
-@pytest.mark.parametrize("K,N", [(3, 500), (8, 4000), (64, 999), (100, 3000), (130, 777)])
+@pytest.mark.parametrize("K,N", [(3, 500), (8, 4000), (64, 999), (100, 3000), (130, 777),
+                                 (200, 1500), (256, 1001), (257, 600)])
 def test_hessian_matches_oracle(bm, K, N):
     say(f"hessian parity K={K} N={N}")
     u, Nk, _ = random_problem(K, N, seed=K + N)
