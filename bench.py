@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--skip-sequential", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -118,6 +120,14 @@ def main():
         f, info = one_solve(False)
         log(f"warmup {i}: phase1={info['phase1_iters']} phase2={info['phase2_iters']} "
             f"checks={info['n_checks']} newton={info['finisher_steps']}")
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written
+        xc = torch.empty(2**27, dtype=torch.float64, device=dev)
+        yc = torch.empty_like(xc)
+        yc.copy_(xc)
+        torch.cuda.synchronize()
+        del xc, yc
+        log("copy calibration: 1 GiB device copy done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sweep_ms, launches = 0.0, 0
@@ -170,6 +180,7 @@ def main():
                          f"u_kn ({per:.2f} s each)"}
 
     achieved = 8.0 * elems / avg_sweep_s / 1e9 if launches else None
+    traffic = _counter_traffic("sweep_fast_double_well_K100_N1e6")
     out = {
         "metric": "sweep K*N elem/s + time-to-solve at 1e-6 kT; batched solves/s, p50/p99",
         "value": value,
@@ -193,10 +204,32 @@ def main():
         "oracle_sci_residual_kT": residual,
         "grad_norm": infos[-1]["grad_norm"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _counter_traffic(name):
+    """HBM bytes per launch of a kernel from its committed counter summary.
+
+    The summary (profiles/<name>_traffic.json) records FETCH_SIZE and
+    WRITE_SIZE per dispatch scaled by a plain copy kernel, and the hash of the
+    kernel source it was taken with; a changed source gives None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + "_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        src = os.path.join(ROOT, rec["source"])
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if digest != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def _timed_solves(bm, args, label, solve):
@@ -253,8 +286,9 @@ def run_ladder(args, bm, synth):
     for name, prec in (("f64", bm.PREC_FP64), ("mixed", bm.PREC_MIXED)):
         f, infos, ms = _timed_solves(
             bm, args, name,
-            lambda prof, prec=prec: bm.solve(u, Nk, tol=args.tol, precision=prec,
-                                             profile=int(prof), ctx=ctx))
+            lambda prof, prec=prec: bm.solve(u, Nk, xi=xi, model=bm.MODEL_LINEAR, coef=coef,
+                                             tol=args.tol, precision=prec, profile=int(prof),
+                                             ctx=ctx))
         sw, n = _avg_sweep_s(infos)
         res[name] = dict(f=f.cpu().numpy(), ms=ms, sweep_s=sw, launches=n, info=infos[-1])
     diff = float(np.max(np.abs(res["mixed"]["f"] - res["f64"]["f"])))
@@ -272,7 +306,7 @@ def run_ladder(args, bm, synth):
     achieved = 8.0 * elems / f64_sweep_s / 1e9
     out = _base_line(args, elems / f64_sweep_s, "elem/s", res["f64"]["ms"], "f64", {
         "workload": "ladder u_kn = beta_k E_n + lambda_k V_n, K=1000, N=2e6 (N_k=2000), "
-                    "u_kn 1000x2e6 FP64 stored, plain MBAR (SCI to 1e-3 then Newton)",
+                    "u_kn 1000x2e6 FP64 stored, BU-MBAR on (E, V) bins + Newton",
         "K": K, "N": N, "tol_kT": args.tol})
     out.update({
         "time_to_solve_s": {"f64": res["f64"]["ms"] / 1e3, "mixed": res["mixed"]["ms"] / 1e3},

@@ -64,6 +64,16 @@ extern "C" {
 #define BUMBAR_MODEL_LINEAR 1   /* u_k(x) = c_k + sum_j a_kj x_j                         */
 #define BUMBAR_MODEL_HARMONIC 2 /* u_k(x) = c_k + sum_j kappa_kj / 2 (x_j - x0_kj)^2     */
 
+/* Bin representatives of Eq. (1) (bumbar_options.represent). CENTRE: the
+ * model at the bin centre, evaluated inside the binned sweeps (needs a
+ * model; the workspace holds only the P x d centres). MEAN: the mean of u_kn
+ * over the bin's samples (needs an FP64 u_kn; the workspace holds K x P
+ * representatives, P <= N). AUTO: CENTRE when a model is given, else MEAN;
+ * the workspace is sized for both. */
+#define BUMBAR_REPRESENT_AUTO 0
+#define BUMBAR_REPRESENT_CENTRE 1
+#define BUMBAR_REPRESENT_MEAN 2
+
 typedef struct bumbar_ctx bumbar_ctx;
 
 /* One phase-2 check of Algorithm 1 (Section 2). */
@@ -96,6 +106,7 @@ typedef struct {
   int profile;         /* 1: time every unbinned sweep kernel with HIP events (stats)      */
   double mixed_tol;    /* PREC_MIXED: Newton on the FP32 matrix until max |delta f| <
                           mixed_tol, then FP64 refinement to tol (default 1e-6)          */
+  int represent;       /* bin representatives (BUMBAR_REPRESENT_*); default AUTO         */
 } bumbar_options;
 
 typedef struct {

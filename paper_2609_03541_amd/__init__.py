@@ -14,7 +14,7 @@ import ctypes as C
 from . import _capi
 from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,  # noqa: F401
                     FINISH_NEWTON, FINISH_SCI, MODEL_HARMONIC, MODEL_LINEAR, MODEL_NONE, OK,
-                    PREC_FP64, PREC_MIXED)
+                    PREC_FP64, PREC_MIXED, REPRESENT_AUTO, REPRESENT_CENTRE, REPRESENT_MEAN)
 
 __all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight",
            "model_energies", "sweep_model", "hessian_model", "Server",
@@ -176,6 +176,8 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     if binning is None:
         binning = xi is not None
     replay = options.pop("replay", None)
+    options.setdefault("represent", _capi.REPRESENT_CENTRE if model != MODEL_NONE
+                       else _capi.REPRESENT_MEAN)
     opts = default_options(binning=int(bool(binning)), **options)
     keep = None
     if replay is not None:
@@ -452,6 +454,8 @@ class Server:
             return C.c_void_p(a.ctypes.data) if a is not None else None
 
         req.u_kn, req.N_k, req.xi, req.coef = p("u"), p("Nk"), p("xi"), p("coef")
+        options.setdefault("represent", _capi.REPRESENT_CENTRE if model != MODEL_NONE
+                           else _capi.REPRESENT_MEAN)
         req.opt = default_options(binning=int(bool(binning)), **options)
         t = C.c_uint64()
         rc = self.lib.bumbar_server_submit(self.h, C.byref(req), C.byref(t))

@@ -29,6 +29,9 @@ FINISH_SCI = 1
 MODEL_NONE = 0
 MODEL_LINEAR = 1
 MODEL_HARMONIC = 2
+REPRESENT_AUTO = 0
+REPRESENT_CENTRE = 1
+REPRESENT_MEAN = 2
 TICKET_QUEUED = 0
 TICKET_RUNNING = 1
 TICKET_DONE = 2
@@ -47,7 +50,8 @@ class Options(C.Structure):
                 ("n_intermediate", C.c_int), ("finisher", C.c_int), ("max_iter", C.c_int64),
                 ("max_newton", C.c_int), ("sci_switch", C.c_double),
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
-                ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double)]
+                ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
+                ("represent", C.c_int)]
 
 
 class Stats(C.Structure):

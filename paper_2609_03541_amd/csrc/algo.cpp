@@ -23,9 +23,10 @@ namespace bumbar {
 
 constexpr int kCountSlots = 8192;
 
-void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool otf_mode) {
+void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,
+                       bool cen_bufs) {
   (void)num_cus;
-  otf = otf_mode;
+  otf = cen_bufs && !ubar_bufs;
   d = d_;
   N = N_;
   q = ar.take<uint32_t>((size_t)N * d);
@@ -45,10 +46,8 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool o
   sort_tmp_bytes = sort_temp_bytes(N);
   sort_tmp = ar.take<char>(sort_tmp_bytes);
   for (int i = 0; i < 2; ++i) {
-    if (otf)
-      cen[i] = ar.take<double>((size_t)N * d);
-    else
-      ubar[i] = ar.take<double>((size_t)K * N);
+    if (cen_bufs) cen[i] = ar.take<double>((size_t)N * d);
+    if (ubar_bufs) ubar[i] = ar.take<double>((size_t)K * N);
     h[i] = ar.take<double>(N);
   }
   logD_lvl = ar.take<double>(N);
@@ -56,9 +55,10 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool o
   f_x = ar.take<double>(K);
 }
 
-void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode) {
+void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
+                       bool cen_bufs) {
   BinnedBufs b;
-  b.carve(ar, K, N, d, num_cus, otf_mode);
+  b.carve(ar, K, N, d, num_cus, ubar_bufs, cen_bufs);
 }
 
 static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
@@ -202,8 +202,8 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   // f, see the sweep) is redone on the robust path before anything else.
   hipError_t e = hipMemcpyAsync(BB.f_n, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "copy f");
-  // batched steps need a kernel that never needs the robust rerun in the
-  // common case: the register-tiled FP64 sweep, or the model sweep
+  // batched steps need a kernel that flags the rare steps that need the
+  // robust rerun: the register-tiled FP64 sweep, or the model sweep
   const bool fast = otf_base != nullptr || sweep_fast_supported(K);
   std::vector<SweepScalars> hs(kHistSteps);
   auto fh = [&](int i) { return B.f_hist + (size_t)i * K; };
@@ -399,7 +399,7 @@ extern "C" int bumbar_bin(bumbar_ctx* ctx, const double* xi, int64_t N, int d, i
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BUMBAR_EDEVICE, "hipSetDevice");
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
   BinnedBufs BB;
-  BB.carve(ar, 1, N, d, ctx->num_cus, false);
+  BB.carve(ar, 1, N, d, ctx->num_cus, false, false);
   if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
   int rc = quantize_all(ctx, BB, xi);
   if (rc) return rc;

@@ -123,8 +123,9 @@ int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
 // otherwise) of the matrix M at f. Outputs: f_out (gauged SCI step),
 // logD_out, lnS_out, S_out and the scalars (read back to *sc when sc != null).
 // Kernel choice: FP64 u with K <= 256 -> register-tiled single pass; other
-// FP64 / FP32 u -> two-pass FP64; packed matrix -> FP32 single pass. A
-// flagged FP64 sweep is redone on the robust path.
+// FP64 / FP32 u -> two-pass FP64; packed matrix -> FP32 single pass; model
+// kinds -> on-the-fly passes. A flagged FP64 sweep is redone on the robust
+// path.
 static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N,
                        const double* h, const int64_t* Nk, const double* f, double* f_out,
                        double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal,
@@ -478,6 +479,7 @@ void bumbar_default_options(bumbar_options* o) {
   o->n_replay = 0;
   o->profile = 0;
   o->mixed_tol = 1e-6;
+  o->represent = BUMBAR_REPRESENT_AUTO;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
@@ -686,17 +688,35 @@ static bool mixed_enabled(const bumbar_options& opt, int u_dtype, int K) {
          opt.finisher == BUMBAR_FINISH_NEWTON;
 }
 
+// With a stored u_kn, bin representatives are materialised (K x P, one
+// represent pass per level) whenever the register-tiled sweep takes K: its
+// binned steps are one launch each. For larger K, bin-centre representatives
+// are evaluated inside the two-pass model sweep instead, which needs only the
+// P x d centres. MEAN always materialises.
+static bool stored_ubar_bufs(int rep, int K) {
+  return rep != BUMBAR_REPRESENT_CENTRE || sweep_fast_supported(K);
+}
+static bool centre_bufs(int rep, int K) {
+  return rep != BUMBAR_REPRESENT_MEAN && !sweep_fast_supported(K);
+}
+
 int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
                            const bumbar_options* opt, size_t* bytes) {
   if (!ctx || !bytes || K <= 0 || N <= 0 || d < 0 || d > 2) return BUMBAR_EINVAL;
   Arena ar;
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
-  if (d > 0 && (opt == nullptr || opt->binning))
-    binned_carve_size(ar, K, N, d, ctx->num_cus, false);
+  const int rep = opt ? opt->represent : BUMBAR_REPRESENT_AUTO;
+  const bool binned = d > 0 && (opt == nullptr || opt->binning);
+  if (binned)
+    binned_carve_size(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(rep, K), centre_bufs(rep, K));
   if (opt && opt->precision == BUMBAR_PREC_MIXED && sweep32_supported(K)) {
     MixedBufs X;
     X.carve(ar, K, N);
+  }
+  if (binned && centre_bufs(rep, K)) {
+    OtfBufs O;
+    O.carve(ar, K, N, d);
   }
   *bytes = ar.off + 256;
   return BUMBAR_OK;
@@ -708,7 +728,7 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
   Arena ar;
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
-  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus, true);
+  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus, false, true);
   OtfBufs O;
   O.carve(ar, K, N, d);
   *bytes = ar.off + 256;
@@ -741,7 +761,15 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (model != BUMBAR_MODEL_NONE && model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC)
     return fail(ctx, BUMBAR_EINVAL, "unknown model code");
   if (model != BUMBAR_MODEL_NONE && !coef) return fail(ctx, BUMBAR_EINVAL, "model needs coef");
-  if (opt.binning && model == BUMBAR_MODEL_NONE && u_dtype != BUMBAR_F64)
+  if (opt.represent < BUMBAR_REPRESENT_AUTO || opt.represent > BUMBAR_REPRESENT_MEAN)
+    return fail(ctx, BUMBAR_EINVAL, "unknown bin representative");
+  const int rep = opt.represent != BUMBAR_REPRESENT_AUTO
+                      ? opt.represent
+                      : (model != BUMBAR_MODEL_NONE ? BUMBAR_REPRESENT_CENTRE
+                                                    : BUMBAR_REPRESENT_MEAN);
+  if (opt.binning && rep == BUMBAR_REPRESENT_CENTRE && model == BUMBAR_MODEL_NONE)
+    return fail(ctx, BUMBAR_EINVAL, "bin-centre representatives need a model");
+  if (opt.binning && rep == BUMBAR_REPRESENT_MEAN && (otf || u_dtype != BUMBAR_F64))
     return fail(ctx, BUMBAR_EINVAL, "mean bin representatives need FP64 u_kn (or give a model)");
   // counts: host copy for validation
   std::vector<int64_t> nk(K);
@@ -762,11 +790,18 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
   BinnedBufs BB;
-  if (opt.binning) BB.carve(ar, K, N, d, ctx->num_cus, otf);
+  if (opt.binning) {
+    if (otf)
+      BB.carve(ar, K, N, d, ctx->num_cus, false, true);
+    else
+      BB.carve(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(opt.represent, K),
+               centre_bufs(opt.represent, K));
+    BB.otf = rep == BUMBAR_REPRESENT_CENTRE && (otf || !sweep_fast_supported(K));
+  }
   MixedBufs X;
   if (mixed && !otf) X.carve(ar, K, N);
   OtfBufs O;
-  if (otf) O.carve(ar, K, N, d);
+  if (otf || (opt.binning && centre_bufs(opt.represent, K))) O.carve(ar, K, N, d);
   if (ar.overflow)
     return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
   bumbar_stats local{};
@@ -817,8 +852,20 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
 
   int stage_rc = BUMBAR_OK;
   if (opt.binning) {
+    // bin-centre representatives: the FP64 model evaluated in the binned sweeps
+    Mat Mc;
+    Mc.kind = 4;
+    Mc.otf.xi = xi;
+    Mc.otf.xf = O.xf;
+    Mc.otf.coef = coef;
+    Mc.otf.d = d;
+    Mc.otf.model = model;
+    Mc.otf.cf32 = O.cf32;
+    Mc.otf.cf64 = O.cf64;
+    // MEAN ignores a given model: the representatives are the bin means of u
+    const int rep_model = rep == BUMBAR_REPRESENT_MEAN ? BUMBAR_MODEL_NONE : model;
     stage_rc = binned_stage(ctx, B, BB, reinterpret_cast<const double*>(u_kn), N_k, nk.data(), xi,
-                            d, model, coef, opt, st, &cnt, otf ? &M : nullptr);
+                            d, rep_model, coef, opt, st, &cnt, BB.otf ? &Mc : nullptr);
     if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
   } else if (opt.finisher == BUMBAR_FINISH_NEWTON) {
     const double t0 = now_ms();

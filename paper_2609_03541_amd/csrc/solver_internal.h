@@ -129,10 +129,13 @@ struct BinnedBufs {
   double* h[2] = {nullptr, nullptr};     // N each
   double* logD_lvl = nullptr;            // N
   double *f_n = nullptr, *f_x = nullptr; // K
-  void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode);
+  // ubar_bufs: K x N representative buffers (MEAN); cen_bufs: N x d centres
+  // (CENTRE). otf is set by the caller to the representative in use.
+  void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs, bool cen_bufs);
 };
 
-void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool otf_mode);
+void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
+                       bool cen_bufs);
 
 // otf_base: nullptr for stored representatives, else the FP64 model matrix
 // (kind 4) whose coordinates the stage replaces by the bin centres.

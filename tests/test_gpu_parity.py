@@ -206,6 +206,25 @@ def test_bumbar_solve_mean_representatives_2d(bm):
     assert np.max(np.abs(f2.cpu().numpy() - f_ref)) < 1e-9
 
 
+def test_representative_choices(bm):
+    # AUTO with a model is CENTRE (bitwise); MEAN with a model given uses the
+    # bin means; all reach the unbinned solution
+    p = synth.harmonic_1d(K=10, Nk=400, seed=12)
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    kw = dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11)
+    fa, _ = bm.solve(dev(p["u"]), p["Nk"], represent=bm.REPRESENT_AUTO, **kw)
+    fc, _ = bm.solve(dev(p["u"]), p["Nk"], represent=bm.REPRESENT_CENTRE, **kw)
+    fm, _ = bm.solve(dev(p["u"]), p["Nk"], represent=bm.REPRESENT_MEAN, **kw)
+    assert np.array_equal(fa.cpu().numpy(), fc.cpu().numpy())
+    # MEAN with the model given is MEAN without it (the model is not used)
+    fm0, _ = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], tol=1e-11)
+    assert np.array_equal(fm.cpu().numpy(), fm0.cpu().numpy())
+    for f in (fc, fm):
+        assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+    with pytest.raises(bm.BumbarError):
+        bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], represent=bm.REPRESENT_CENTRE, tol=1e-11)
+
+
 def test_reweight_matches_oracle(bm):
     p = synth.harmonic_1d(K=4, Nk=300, seed=6)
     f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])

@@ -115,7 +115,9 @@ def test_model_request_solved_on_the_fly(bm):
 
 def footprint_bound(bm, K, N, d, binning):
     ctx = bm.context()
-    ws = ctx.query_workspace(K, N, d if binning else 0, bm.default_options(binning=int(binning)))
+    # the same options the server's request carries (bin-centre representatives)
+    opts = bm.default_options(binning=int(binning), represent=bm.REPRESENT_CENTRE)
+    ws = ctx.query_workspace(K, N, d if binning else 0, opts)
     parts = [8 * K * N, 8 * N * d, 8 * K, 8 * K * (1 + 2 * d), 8 * K, ws]
     return sum(-(-b // 256) * 256 for b in parts)
 
