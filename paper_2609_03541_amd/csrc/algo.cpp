@@ -91,9 +91,86 @@ static int nonempty(bumbar_ctx* ctx, BinnedBufs& BB, uint64_t m, int64_t* g) {
   return read_bytes(ctx, BB.counts, g, sizeof(int64_t));
 }
 
+// 1-D: the same bisection, with the midpoints of the next kLevels levels of
+// the bisection tree evaluated in one pass and the path then walked on the
+// host, so each round costs one readback instead of one per probe.
+constexpr int kLevels = 6;  // 63 midpoints per round (+ m = 1 in the first)
+
+static void subtree_mids(uint64_t lo, uint64_t hi, int depth, std::vector<uint64_t>* out) {
+  if (depth == 0 || hi - lo <= 1) return;
+  const uint64_t mid = lo + (hi - lo) / 2;
+  out->push_back(mid);
+  subtree_mids(mid, hi, depth - 1, out);
+  subtree_mids(lo, mid, depth - 1, out);
+}
+
+static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_out,
+                           int64_t* g_out) {
+  hipStream_t s = ctx->stream;
+  uint64_t* dev_ms = reinterpret_cast<uint64_t*>(BB.counts + kCountSlots / 2);
+  unsigned long long* dev_g = reinterpret_cast<unsigned long long*>(BB.counts + 8);
+  std::vector<uint64_t> ms;
+  std::vector<unsigned long long> gs;
+  std::vector<uint64_t> pairs;
+  auto eval = [&]() -> int {
+    pairs.clear();
+    for (uint64_t m : ms) {
+      pairs.push_back(m);
+      pairs.push_back(width_magic(m));
+    }
+    hipError_t e = hipMemcpyAsync(dev_ms, pairs.data(), sizeof(uint64_t) * pairs.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_count_1d_multi(s, BB.q1_sorted, BB.N, dev_ms, (int)ms.size(), dev_g);
+    if (e != hipSuccess) return hip_fail(ctx, e, "count");
+    gs.resize(ms.size());
+    return read_bytes(ctx, dev_g, gs.data(), sizeof(unsigned long long) * ms.size());
+  };
+  uint64_t lo = 1, hi = 4294967296ull;
+  ms.push_back(1);
+  subtree_mids(lo, hi, kLevels, &ms);
+  int rc = eval();
+  if (rc) return rc;
+  const int64_t g1 = (int64_t)gs[0];
+  if (g1 < n) {
+    *m_out = 1;
+    *g_out = g1;
+    return BUMBAR_OK;
+  }
+  int64_t glo = g1;
+  for (;;) {
+    // walk the evaluated part of the tree exactly as the bisection would
+    auto find = [&](uint64_t m) -> int64_t {
+      for (size_t i = 0; i < ms.size(); ++i)
+        if (ms[i] == m) return (int64_t)gs[i];
+      return -1;
+    };
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      const int64_t gm = find(mid);
+      if (gm < 0) break;  // outside this round's subtree
+      if (gm >= n) {
+        lo = mid;
+        glo = gm;
+      } else {
+        hi = mid;
+      }
+    }
+    if (hi - lo <= 1) break;
+    ms.clear();
+    subtree_mids(lo, hi, kLevels, &ms);
+    rc = eval();
+    if (rc) return rc;
+  }
+  *m_out = lo;
+  *g_out = glo;
+  return BUMBAR_OK;
+}
+
 // w*(n) = max{m : g(m) >= n} by the integer bisection of the oracle.
 static int width_search(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_out,
                         int64_t* g_out) {
+  if (BB.d == 1) return width_search_1d(ctx, BB, n, m_out, g_out);
   int64_t g1 = 0;
   int rc = nonempty(ctx, BB, 1, &g1);
   if (rc) return rc;
@@ -235,8 +312,9 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     int nvalid = 0;  // leading steps that are usable
     if (fast) {
       for (int i = 0; i < T; ++i) {
+        // each step's finaliser leaves the constants of the next step in B.cst
         rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, i == 0 ? BB.f_n : fh(i - 1),
-                         fh(i), BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + i);
+                         fh(i), BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + i, i > 0, B.cst);
         if (rc) return rc;
       }
       rc = read_hist((int)T);
@@ -285,7 +363,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         for (int i = 0; i < T && fast; ++i) {
           rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                            i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
-                           B.scal_hist + i);
+                           B.scal_hist + i, i > 0, B.cst);
           if (rc) return rc;
         }
         if (!fast) {
@@ -307,17 +385,19 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         for (int i = 0; i < T; ++i) {
           rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                            i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
-                           B.scal_hist + i);
+                           B.scal_hist + i, i > 0, B.cst);
           if (rc) return rc;
         }
         const double* fin = T == 0 ? BB.f_n : fh(T - 1);
         in = T;
         ix = T + 1;
+        // both probes start from fin: the first reuses the constants the last
+        // intermediate step left (if any), the second those of the first
         rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, fin, fh(in), BB.logD_lvl,
-                         B.lnS_t, B.S_t, B.scal_hist + in);
+                         B.lnS_t, B.S_t, B.scal_hist + in, T > 0, nullptr);
         if (rc) return rc;
         rc = sweep_queue(ctx, B, level_mat(nxt), nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
-                         B.lnS_t, B.S_t, B.scal_hist + ix);
+                         B.lnS_t, B.S_t, B.scal_hist + ix, true, nullptr);
         if (rc) return rc;
         rc = read_hist(T + 2);
         if (rc) return rc;

@@ -216,6 +216,85 @@ __global__ void __launch_bounds__(kBT) sum_counts_kernel(int nb, int64_t* counts
   if (threadIdx.x == 0) counts[0] = sh[0];
 }
 
+// g(m) for up to kMaxProbes widths in one pass over the sorted coordinates:
+// counts[j] = number of distinct floor(q / m_j) (run starts, integer atomics,
+// so the totals do not depend on the order of the additions).
+//
+// The divisions use a multiplier per width: for 2 <= m < 2^32 and q < 2^32,
+// floor(q / m) = floor(q * M / 2^64) exactly with M = ceil(2^64 / m) (the
+// error q (M m - 2^64) / (m 2^64) stays below 2^-32 < 1/m, so it never
+// crosses an integer); m = 1 gives q, and m >= 2^32 gives 0.
+constexpr int kMaxProbes = 64;
+
+__device__ __forceinline__ uint32_t div_by_magic(uint32_t q, uint64_t m, uint64_t magic) {
+  if (m == 1) return q;
+  if (m > 0xffffffffull) return 0u;
+  const uint32_t lo = (uint32_t)magic, hi = (uint32_t)(magic >> 32);
+  const uint64_t t = (uint64_t)q * hi + __umulhi(q, lo);
+  return (uint32_t)(t >> 32);
+}
+
+constexpr int kProbeBlocks = 256;  // workgroups of the multi-probe count
+constexpr int kProbeElems = 16;    // max sorted coordinates per thread per pass
+
+// Each thread holds a run of consecutive sorted coordinates in registers and,
+// probe by probe, counts the positions where floor(q / m) changes (one
+// division per element per probe, compared with the previous element's).
+// Per-block totals are added with one integer atomic per probe and block.
+__global__ void __launch_bounds__(kBT)
+    count_runs_1d_multi_kernel(const uint32_t* __restrict__ qs, int64_t N,
+                               const uint64_t* __restrict__ ms, int M,
+                               unsigned long long* __restrict__ counts) {
+  __shared__ uint64_t sm[kMaxProbes], smag[kMaxProbes];
+  __shared__ unsigned sred[kBT / 64][kMaxProbes];
+  for (int j = threadIdx.x; j < M; j += kBT) {
+    sm[j] = ms[2 * j];
+    smag[j] = ms[2 * j + 1];
+  }
+  for (int i = threadIdx.x; i < (kBT / 64) * kMaxProbes; i += kBT) (&sred[0][0])[i] = 0u;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nthreads = (int64_t)gridDim.x * kBT;
+  const int64_t per = (N + nthreads - 1) / nthreads;
+  const int64_t tid = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  const int64_t first = tid * per;
+  const int64_t last = std::min<int64_t>(N, first + per);
+  // the chunk loop has the same trip count in every lane (shuffles inside)
+  for (int64_t off = 0; off < per; off += kProbeElems) {
+    const int64_t base = first + off;
+    const int cnt = base < last ? (int)std::min<int64_t>(kProbeElems, last - base) : 0;
+    uint32_t v[kProbeElems];
+#pragma unroll
+    for (int e = 0; e < kProbeElems; ++e) v[e] = e < cnt ? qs[base + e] : 0u;
+    const uint32_t prev = (cnt > 0 && base > 0) ? qs[base - 1] : 0u;
+    for (int j = 0; j < M; ++j) {
+      const uint64_t m = sm[j], mg = smag[j];
+      uint32_t dp = div_by_magic(prev, m, mg);
+      unsigned cj = 0;
+#pragma unroll
+      for (int e = 0; e < kProbeElems; ++e) {
+        const uint32_t d = div_by_magic(v[e], m, mg);
+        cj += (e < cnt && (base + e == 0 || d != dp)) ? 1u : 0u;
+        dp = d;
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) cj += __shfl_xor(cj, o, 64);
+      if (lane == 0) sred[wave][j] += cj;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < M; j += kBT) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBT / 64; ++w) t += sred[w][j];
+    if (t) atomicAdd(&counts[j], t);
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
 static int red_blocks(int64_t N) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (N + kBT - 1) / kBT));
 }
@@ -225,6 +304,21 @@ hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, u
   const int nb = red_blocks(N);
   hipLaunchKernelGGL(count_runs_1d_kernel, dim3(nb), dim3(kBT), 0, s, q_sorted, N, m, counts);
   hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(kBT), 0, s, nb, counts);
+  return hipGetLastError();
+}
+
+uint64_t width_magic(uint64_t m) {
+  if (m < 2 || m > 0xffffffffull) return 0;
+  return ~0ull / m + 1ull;  // ceil(2^64 / m)
+}
+
+hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
+                                 const uint64_t* ms, int M, unsigned long long* counts) {
+  if (M < 1 || M > kMaxProbes) return hipErrorInvalidValue;
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(kProbeBlocks, (N + kBT - 1) / kBT));
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kMaxProbes), 0, s, counts, M);
+  hipLaunchKernelGGL(count_runs_1d_multi_kernel, dim3((unsigned)nb), dim3(kBT), 0, s, q_sorted, N,
+                     ms, M, counts);
   return hipGetLastError();
 }
 

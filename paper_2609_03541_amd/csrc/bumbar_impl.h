@@ -81,7 +81,7 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
                                  const double* partS, const double* part_obj,
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
-                                 SweepScalars* out);
+                                 SweepScalars* out, double* cst_next = nullptr);
 
 // cst_k = ln N'_k + f_k, gk, lnNp from N_k and f.
 hipError_t launch_prepare_consts(hipStream_t s, int K, const int64_t* Nk, const double* f,

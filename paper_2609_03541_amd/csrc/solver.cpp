@@ -129,10 +129,11 @@ int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
 static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N,
                        const double* h, const int64_t* Nk, const double* f, double* f_out,
                        double* logD_out, double* lnS_out, double* S_out, SweepScalars* dev_scal,
-                       bool timed) {
+                       bool timed, bool consts_ready = false, double* cst_next = nullptr) {
   hipStream_t s = ctx->stream;
   const int K = B.K;
-  hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
+  hipError_t e = hipSuccess;
+  if (!consts_ready) e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
   if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
   int grid = 0;
   std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
@@ -159,15 +160,17 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
   if (ev) (void)hipEventRecord(ev->second, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep");
   e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f, B.lnNp,
-                            Nk, f_out, lnS_out, S_out, dev_scal);
+                            Nk, f_out, lnS_out, S_out, dev_scal, cst_next);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
   return BUMBAR_OK;
 }
 
 int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
                 const int64_t* Nk, const double* f, double* f_out, double* logD_out,
-                double* lnS_out, double* S_out, SweepScalars* dev_scal) {
-  return queue_sweep(ctx, B, M, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, dev_scal, false);
+                double* lnS_out, double* S_out, SweepScalars* dev_scal, bool consts_ready,
+                double* cst_next) {
+  return queue_sweep(ctx, B, M, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, dev_scal, false,
+                     consts_ready, cst_next);
 }
 
 int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,

@@ -82,9 +82,14 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
              double* lnS_out, double* S_out, SweepScalars* sc, bool force_robust,
              SweepCounters* cnt);
 
+// Queues one sweep without reading anything back. consts_ready: B.cst / B.gk
+// / B.lnNp already hold the constants at f (skip their rebuild); cst_next:
+// where the finaliser writes the constants at f_out for a following step
+// (may be B.cst itself), or nullptr.
 int sweep_queue(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, const double* h,
                 const int64_t* Nk, const double* f, double* f_out, double* logD_out,
-                double* lnS_out, double* S_out, SweepScalars* dev_scal);
+                double* lnS_out, double* S_out, SweepScalars* dev_scal,
+                bool consts_ready = false, double* cst_next = nullptr);
 
 int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double tol,
                   int max_steps, bumbar_stats* st, SweepCounters* cnt, double* final_step,
@@ -156,6 +161,11 @@ hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t*
 // in counts[0] after the call.
 hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, uint64_t m,
                            int64_t* counts);
+// g(m_j) for M <= 64 widths over sorted 1-D coordinates; ms (device) holds
+// the pairs (m_j, width_magic(m_j)); counts (M, device) are zeroed by the call.
+uint64_t width_magic(uint64_t m);
+hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
+                                 const uint64_t* ms, int M, unsigned long long* counts);
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts);

@@ -646,7 +646,8 @@ __global__ void __launch_bounds__(FT)
                           const unsigned* __restrict__ part_flags, const double* __restrict__ f,
                           const double* __restrict__ lnNp, const int64_t* __restrict__ Nk,
                           double* __restrict__ f_new, double* __restrict__ lnS_out,
-                          double* __restrict__ S_out, SweepScalars* __restrict__ out) {
+                          double* __restrict__ S_out, SweepScalars* __restrict__ out,
+                          double* __restrict__ cst_next) {
   __shared__ double sh[FT / 64][6];
   __shared__ double f0s;
   __shared__ unsigned flags_sh;
@@ -718,6 +719,8 @@ __global__ void __launch_bounds__(FT)
   for (int k = tid; k < K; k += FT) {
     const double fn = f_new[k] - f0;
     f_new[k] = fn;
+    // the constants of a sweep at f_new (what prepare_consts would write)
+    if (cst_next) cst_next[k] = lnNp[k] + fn;
     double df = fabs(fn - f[k]);
     if (df != df) df = INFINITY;
     v.mdf = fmax(v.mdf, df);
@@ -748,13 +751,16 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
                                  const double* partS, const double* part_obj,
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
-                                 SweepScalars* out) {
-  if (K <= 256 && nparts <= 4096)
+                                 SweepScalars* out, double* cst_next) {
+  // few partials: one wave-sized block; many: 1024 threads so that several
+  // lanes share each state's partials
+  if (K <= 256 && nparts <= 16)
     hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts, part,
-                       partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
+                       partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out, cst_next);
   else
     hipLaunchKernelGGL(sweep_finalize_kernel<1024>, dim3(1), dim3(1024), 0, s, mode, K, nparts,
-                       part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out);
+                       part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out,
+                       cst_next);
   return hipGetLastError();
 }
 
