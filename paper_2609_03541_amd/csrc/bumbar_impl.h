@@ -130,9 +130,11 @@ hipError_t launch_weights_otf(hipStream_t s, const OtfModel& m, int K, int64_t N
 
 // What the Hessian reads: kind 0 FP64 u; 1 FP32 u (widened); 2 packed
 // mixed-precision matrix (cst = d_k, m0 = per-column shift); 3 model in FP32
-// (otf.cf32 current); 4 model in FP64 (otf.cf64 current).
+// (otf.cf32 current); 4 model in FP64 (otf.cf64 current). Kinds 2 and 3 with
+// K > 256 run on FP16 matrix cores (FP32 accumulation within a chunk).
 struct HessSource {
   int kind = 0;
+  int num_cus = 256;  // sizes the sample chunks of the FP16-core path
   const void* u = nullptr;
   int64_t ld = 0;
   const double* m0 = nullptr;

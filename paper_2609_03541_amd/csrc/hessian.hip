@@ -357,6 +357,183 @@ static int small_chunks(int64_t N, int num_cus) {
   return (int)(g < 1 ? 1 : g);
 }
 
+// ---- mixed precision, K > 256: FP16 matrix cores ----------------------------
+//
+// The Hessian only shapes the Newton steps (the fixed point is set by the
+// FP64 gradient), so in mixed precision P is formed in FP32 (exp2) and
+// rounded to FP16 (P_kn lies in [0, 1]: sum_k P_kn = 1), and G = P P^T runs on
+// v_mfma_f32_16x16x32_f16 with FP32 accumulation inside a sample chunk and
+// FP64 across chunks. Output blocks are 256 x 256 (bi <= bj), so P is
+// recomputed ceil(K / 256) times instead of ceil(K / 64). Per step of 32
+// samples a workgroup (8 waves) writes the two 256 x 32 slabs of P to LDS;
+// wave w owns tile rows 2w and 2w + 1 of the block (32 tiles of 16 x 16).
+// Operand layout (checked on the hardware): A lane l holds row l % 16,
+// k = 8 (l / 16) .. + 7; B lane l holds column l % 16, the same k; the
+// accumulator lane l holds rows 4 (l / 16) + i, column l % 16.
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int XB = 256;      // output block edge
+constexpr int XS = 32;       // samples per step (one MFMA k-extent)
+constexpr int XP = XS + 8;   // padded LDS row (halves): rows 80 bytes apart
+
+// Packed matrix in FP32: P = exp(d_k + r_kn - (ln D_n - m0_n)).
+struct SrcPacked32 {
+  const float* r;
+  int64_t ld;
+  const double* m0;
+  struct Row {
+    const float* p;
+    float d;
+  };
+  __device__ Row row(int k, double c) const {
+    return {r + (int64_t)k * ld, (float)(1.4426950408889634 * c)};
+  }
+  __device__ float col(int64_t n, const double* logD) const {
+    return (float)(1.4426950408889634 * (logD[n] - m0[n]));
+  }
+  __device__ float p(const Row& rw, int64_t n, float c) const {
+    return __builtin_amdgcn_exp2f(__builtin_fmaf(rw.p[n], 1.44269504f, rw.d - c));
+  }
+};
+
+// Model in FP32 (the log2-domain coefficients of the FP32 model sweeps).
+template <int D>
+struct SrcModel32f {
+  const float* xf;
+  const float* cf;
+  int K;
+  struct Row {
+    float a, b[D], c[D];
+  };
+  __device__ Row row(int k, double) const {
+    Row rw;
+    rw.a = cf[K + k];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      rw.b[j] = cf[2 * K + (int64_t)j * K + k];
+      rw.c[j] = cf[2 * K + (int64_t)(D + j) * K + k];
+    }
+    return rw;
+  }
+  __device__ float col(int64_t n, const double* logD) const {
+    return (float)(-1.4426950408889634 * logD[n]);
+  }
+  __device__ float p(const Row& rw, int64_t n, float e) const {
+    float v = rw.a + e;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float x = xf[n * D + j];
+      v = __builtin_fmaf(rw.b[j], x, v);
+      v = __builtin_fmaf(rw.c[j], x * x, v);
+    }
+    return __builtin_amdgcn_exp2f(v);
+  }
+};
+
+template <class Src>
+__global__ void __launch_bounds__(512)
+    hessian_h16_kernel(Src src, int K, int64_t N, const double* __restrict__ cst,
+                       const double* __restrict__ gk, const double* __restrict__ logD, int nb,
+                       int chunks, int64_t chunk_len, float* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) _Float16 Pi[XB][XP];
+  __shared__ __attribute__((aligned(16))) _Float16 Pj[XB][XP];
+  const int blk = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  int bi, bj;
+  block_coords(blk, nb, bi, bj);
+  const bool diag = (bi == bj);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  // loader: row lr of both slabs, samples ls .. ls + 15
+  const int lr = tid >> 1;
+  const int ls = (tid & 1) * 16;
+  const int ki = bi * XB + lr, kj = bj * XB + lr;
+  const bool si = ki < K && gk[ki] != 0.0;
+  const bool sj = kj < K && gk[kj] != 0.0;
+  const typename Src::Row ri = src.row(si ? ki : 0, si ? cst[ki] : 0.0);
+  const typename Src::Row rj = src.row(sj ? kj : 0, sj ? cst[kj] : 0.0);
+  f4v acc[2][16];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
+  const int64_t n_begin = (int64_t)chunk * chunk_len;
+  const int64_t n_end = n_begin + chunk_len < N ? n_begin + chunk_len : N;
+  for (int64_t n0 = n_begin; n0 < n_end; n0 += XS) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t n = n0 + ls + q;
+      const bool ok = n < n_end;
+      const float cn = ok ? src.col(n, logD) : 0.f;
+      Pi[lr][ls + q] = (_Float16)((si && ok) ? src.p(ri, n, cn) : 0.f);
+      if (!diag) Pj[lr][ls + q] = (_Float16)((sj && ok) ? src.p(rj, n, cn) : 0.f);
+    }
+    __syncthreads();
+    const _Float16(*Bsrc)[XP] = diag ? Pi : Pj;
+    const int kq = (lane >> 4) * 8;
+    h8v av[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+      av[a] = *reinterpret_cast<const h8v*>(&Pi[(2 * wave + a) * 16 + (lane & 15)][kq]);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const h8v bv = *reinterpret_cast<const h8v*>(&Bsrc[b * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* out = partials + (int64_t)blockIdx.x * XB * XB;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = (2 * wave + a) * 16 + (lane >> 4) * 4 + v;
+        const int c = b * 16 + (lane & 15);
+        out[r * XB + c] = acc[a][b][v];
+      }
+}
+
+// H_ij = delta_ij S_i - sum_chunks G_ij (FP64 sum in a fixed order), both triangles.
+__global__ void __launch_bounds__(256)
+    hessian_h16_reduce_kernel(int K, int nb, int chunks, const float* __restrict__ partials,
+                              const double* __restrict__ S, const double* __restrict__ gk,
+                              double* __restrict__ H) {
+  const int blk = blockIdx.y;
+  int bi, bj;
+  block_coords(blk, nb, bi, bj);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= XB * XB) return;
+  const int r = e / XB, c = e % XB;
+  const int i = bi * XB + r, j = bj * XB + c;
+  if (i >= K || j >= K) return;
+  if (bi == bj && j < i) return;
+  double g = 0.0;
+  const float* p = partials + ((int64_t)blk * chunks) * XB * XB + e;
+  for (int q = 0; q < chunks; ++q) g += (double)p[(int64_t)q * XB * XB];
+  double v = -g;
+  if (i == j) v += (gk[i] != 0.0) ? S[i] : 0.0;
+  if (gk[i] == 0.0 || gk[j] == 0.0) v = 0.0;
+  H[(int64_t)i * K + j] = v;
+  H[(int64_t)j * K + i] = v;
+}
+
+static int h16_nb(int K) { return (K + XB - 1) / XB; }
+
+static int h16_chunks(int K, int64_t N, int num_cus) {
+  const int nb = h16_nb(K);
+  const int nblk = nb * (nb + 1) / 2;
+  int64_t ch = (2 * (int64_t)num_cus + nblk - 1) / nblk;
+  const int64_t by_n = (N + 1023) / 1024;
+  if (ch > by_n) ch = by_n;
+  return (int)(ch < 1 ? 1 : ch);
+}
+
 // H_ij = delta_ij S_i - sum_chunks G_ij, written to both triangles.
 __global__ void __launch_bounds__(256)
     hessian_reduce_kernel(int K, int nb, int chunks, const double* __restrict__ partials,
@@ -398,7 +575,11 @@ size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
   if (chunks > max_chunks) chunks = (int)max_chunks;
   if (chunks < 1) chunks = 1;
   if (chunks_out) *chunks_out = chunks;
-  return (size_t)nblk * chunks * HB * HB;
+  // room for the FP16-core path of the mixed-precision sources as well
+  const int nb16 = h16_nb(K);
+  const size_t h16 = (size_t)(nb16 * (nb16 + 1) / 2) * h16_chunks(K, N, num_cus) * XB * XB;
+  const size_t fp64 = (size_t)nblk * chunks * HB * HB;
+  return fp64 > (h16 + 1) / 2 ? fp64 : (h16 + 1) / 2;
 }
 
 template <class Src>
@@ -443,6 +624,30 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
+  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3)) {
+    const int nb16 = h16_nb(K);
+    const int nblk16 = nb16 * (nb16 + 1) / 2;
+    const int ch16 = h16_chunks(K, N, hs.num_cus);
+    int64_t len16 = (N + ch16 - 1) / ch16;
+    len16 = (len16 + XS - 1) / XS * XS;
+    float* p16 = reinterpret_cast<float*>(partials);
+    const dim3 g16(nblk16 * ch16);
+    if (hs.kind == 2)
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcPacked32>, g16, dim3(512), 0, s,
+                         SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
+                         cst, gk, logD, nb16, ch16, len16, p16);
+    else if (hs.otf.d == 1)
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<1>>, g16, dim3(512), 0, s,
+                         SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb16,
+                         ch16, len16, p16);
+    else
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<2>>, g16, dim3(512), 0, s,
+                         SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb16,
+                         ch16, len16, p16);
+    hipLaunchKernelGGL(hessian_h16_reduce_kernel, dim3(XB * XB / 256, nblk16), dim3(256), 0, s, K,
+                       nb16, ch16, p16, S, gk, H);
+    return hipGetLastError();
+  }
   switch (hs.kind) {
     case 0:
       launch_any(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,

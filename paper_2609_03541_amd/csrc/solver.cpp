@@ -222,6 +222,7 @@ static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, 
   hipStream_t s = ctx->stream;
   HessSource hs;
   hs.kind = M.kind;
+  hs.num_cus = ctx->num_cus;
   hs.u = M.u;
   hs.ld = M.ld;
   hs.otf = M.otf;
@@ -626,6 +627,7 @@ int bumbar_hessian_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, co
   hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
   HessSource hs;
   hs.kind = M.kind;
+  hs.num_cus = ctx->num_cus;
   hs.otf = M.otf;
   if (e == hipSuccess) e = launch_otf_coefs(ctx->stream, M.otf, M.kind == 3, K, B.cst, B.gk);
   if (e == hipSuccess)
