@@ -222,8 +222,11 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     return f, info
 
 
-def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True):
-    """One unbinned SCI step (Eq. (1), one sample per bin). Returns f_new, ln D, S, stats."""
+def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True, want_logD=True):
+    """One unbinned SCI step (Eq. (1), one sample per bin). Returns f_new, ln D, S, stats.
+
+    With ``want_logD=False`` no ln D is written (the form the SCI iteration
+    uses) and None is returned in its place."""
     torch = _torch()
     ctx = ctx or context()
     dev = u.device
@@ -233,11 +236,12 @@ def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True):
     f_t = _dev(f, torch.float64, dev)
     ws = ctx.workspace(ctx.query_workspace(K, N, 0))
     f_new = torch.empty(K, dtype=torch.float64, device=dev)
-    lD = torch.empty(N, dtype=torch.float64, device=dev)
+    lD = torch.empty(N, dtype=torch.float64, device=dev) if want_logD else None
     S = torch.empty(K, dtype=torch.float64, device=dev)
     stats = (C.c_double * 4)() if with_stats else None
     rc = ctx.lib.bumbar_sweep(ctx.h, _ptr(u), _dtype_code(u), K, N, ld, _ptr(Nk_t), _ptr(f_t),
-                              _ptr(ws), ws.numel(), _ptr(f_new), _ptr(lD), _ptr(S),
+                              _ptr(ws), ws.numel(), _ptr(f_new),
+                              _ptr(lD), _ptr(S),
                               C.cast(stats, C.POINTER(C.c_double)) if stats else None)
     ctx.check(rc)
     _keep(ctx, Nk_t, f_t)

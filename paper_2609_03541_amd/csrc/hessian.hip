@@ -360,24 +360,54 @@ static int small_chunks(int64_t N, int num_cus) {
 // ---- mixed precision, K > 256: FP16 matrix cores ----------------------------
 //
 // The Hessian only shapes the Newton steps (the fixed point is set by the
-// FP64 gradient), so in mixed precision P is formed in FP32 (exp2) and
-// rounded to FP16 (P_kn lies in [0, 1]: sum_k P_kn = 1), and G = P P^T runs on
-// v_mfma_f32_16x16x32_f16 with FP32 accumulation inside a sample chunk and
-// FP64 across chunks. Output blocks are 256 x 256 (bi <= bj), so P is
-// recomputed ceil(K / 256) times instead of ceil(K / 64). Per step of 32
-// samples a workgroup (8 waves) writes the two 256 x 32 slabs of P to LDS;
-// wave w owns tile rows 2w and 2w + 1 of the block (32 tiles of 16 x 16).
+// FP64 gradient), so in mixed precision P is formed in FP32 (exp2 of an
+// exponent in log2 units) and rounded to FP16 (P_kn lies in [0, 1]:
+// sum_k P_kn = 1), and G = P P^T runs on v_mfma_f32_16x16x32_f16 with FP32
+// accumulation inside a sample chunk and FP64 across chunks.
+//
+// A workgroup (8 waves) owns one 256 x 256 output block (bi <= bj) and one
+// sample chunk. Per step of 32 samples it forms the two 256 x 32 slabs of P
+// (rows of block bi and of block bj) in LDS:
+//  * fill: lane l of wave w computes one row of one slab (w / 4 selects the
+//    slab, 64 (w % 4) + l the row) over the step's samples, which are the
+//    same for the whole wave, so the per-sample values (column constant,
+//    coordinates) are wave-uniform scalar loads and each element costs a few
+//    FMAs and one exp2; on a diagonal block the two wave halves split the
+//    samples of the one slab instead;
+//  * product: wave w accumulates the 64 x 128 output tile (rows 64 (w % 4),
+//    columns 128 (w / 4)) as 4 x 8 MFMA tiles.
+// The slabs are double-buffered: the fill of step s + 1 (VALU) is issued
+// between the matrix instructions of step s, one barrier per step.
 // Operand layout (checked on the hardware): A lane l holds row l % 16,
 // k = 8 (l / 16) .. + 7; B lane l holds column l % 16, the same k; the
 // accumulator lane l holds rows 4 (l / 16) + i, column l % 16.
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f4a __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr int XB = 256;      // output block edge
 constexpr int XS = 32;       // samples per step (one MFMA k-extent)
 constexpr int XP = XS + 8;   // padded LDS row (halves): rows 80 bytes apart
+constexpr double kLog2eH = 1.4426950408889634;
 
-// Packed matrix in FP32: P = exp(d_k + r_kn - (ln D_n - m0_n)).
+// Per-sample column constant in log2 units, once per Hessian:
+//   packed FP32 matrix  c_n = log2(e) (ln D_n - m0_n)
+//   FP32 model          c_n = -log2(e) ln D_n       (m0 == nullptr)
+__global__ void __launch_bounds__(256)
+    h16_colv_kernel(int64_t N, const double* __restrict__ logD, const double* __restrict__ m0,
+                    float* __restrict__ colv) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  colv[n] = m0 ? (float)(kLog2eH * (logD[n] - m0[n])) : (float)(-kLog2eH * logD[n]);
+}
+
+// Sources of the exponents t_kn (log2 units) of 16 consecutive samples n ..
+// n + 15 of one row: full() when all 16 lie in the chunk (the per-sample
+// values are contiguous wave-uniform runs, read in batches of 8 by scalar
+// loads), tail() otherwise (indices clamped to the chunk's last sample; the
+// caller zeroes those values).
+
+// Packed FP32 matrix: t_kn = log2(e) r_kn + d_k - c_n.
 struct SrcPacked32 {
   const float* r;
   int64_t ld;
@@ -386,18 +416,44 @@ struct SrcPacked32 {
     const float* p;
     float d;
   };
-  __device__ Row row(int k, double c) const {
-    return {r + (int64_t)k * ld, (float)(1.4426950408889634 * c)};
+  __device__ Row row(int k, double dk) const {
+    return {r + (int64_t)k * ld, (float)(kLog2eH * dk)};
   }
-  __device__ float col(int64_t n, const double* logD) const {
-    return (float)(1.4426950408889634 * (logD[n] - m0[n]));
+  __device__ void full(const Row& rw, int64_t n, bool vec, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+    float x[16];
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < 16; q += 4) {
+        const f4v v = *reinterpret_cast<const f4v*>(rw.p + n + q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[q + i] = v[i];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = rw.p[n + q];
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h += 8) {
+      float cv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cv[q] = colv[n + h + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[h + q] = __builtin_fmaf(x[h + q], 1.44269504f, rw.d - cv[q]);
+    }
   }
-  __device__ float p(const Row& rw, int64_t n, float c) const {
-    return __builtin_amdgcn_exp2f(__builtin_fmaf(rw.p[n], 1.44269504f, rw.d - c));
+  __device__ void tail(const Row& rw, int64_t n, int64_t last, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t m = n + q < last ? n + q : last;
+      t[q] = __builtin_fmaf(rw.p[m], 1.44269504f, rw.d - colv[m]);
+    }
   }
 };
 
-// Model in FP32 (the log2-domain coefficients of the FP32 model sweeps).
+// FP32 model (the log2-domain coefficients of the FP32 model sweeps):
+// t_kn = A_k + e_n + sum_j x_nj (B_jk + C_jk x_nj), e_n = -log2(e) ln D_n.
 template <int D>
 struct SrcModel32f {
   const float* xf;
@@ -416,85 +472,155 @@ struct SrcModel32f {
     }
     return rw;
   }
-  __device__ float col(int64_t n, const double* logD) const {
-    return (float)(-1.4426950408889634 * logD[n]);
-  }
-  __device__ float p(const Row& rw, int64_t n, float e) const {
+  __device__ float eval(const Row& rw, float e, const float* x) const {
     float v = rw.a + e;
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const float x = xf[n * D + j];
-      v = __builtin_fmaf(rw.b[j], x, v);
-      v = __builtin_fmaf(rw.c[j], x * x, v);
+    for (int j = 0; j < D; ++j) v = __builtin_fmaf(__builtin_fmaf(rw.c[j], x[j], rw.b[j]), x[j], v);
+    return v;
+  }
+  __device__ void full(const Row& rw, int64_t n, bool, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+#pragma unroll
+    for (int h = 0; h < 16; h += 8) {
+      float cv[8], x[8 * D];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cv[q] = colv[n + h + q];
+#pragma unroll
+      for (int i = 0; i < 8 * D; ++i) x[i] = xf[(n + h) * D + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[h + q] = eval(rw, cv[q], &x[q * D]);
     }
-    return __builtin_amdgcn_exp2f(v);
+  }
+  __device__ void tail(const Row& rw, int64_t n, int64_t last, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t m = n + q < last ? n + q : last;
+      float x[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[j] = xf[m * D + j];
+      t[q] = eval(rw, colv[m], x);
+    }
   }
 };
+
+// 16 FP16 values of P for one row: exp2 of the exponents, zero for an
+// unsampled row or samples past the chunk end.
+template <class Src>
+__device__ __forceinline__ void fill16(const Src& src, const typename Src::Row& rw, bool on,
+                                       int64_t n, int64_t n_end, bool vec,
+                                       const float* __restrict__ colv, h8v& lo, h8v& hi) {
+  float t[16];
+  if (n + 16 <= n_end) {
+    src.full(rw, n, vec, colv, t);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const _Float16 h = (_Float16)(on ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
+      if (q < 8)
+        lo[q] = h;
+      else
+        hi[q - 8] = h;
+    }
+  } else {
+    src.tail(rw, n, n_end - 1, colv, t);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const bool ok = on && n + q < n_end;
+      const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
+      if (q < 8)
+        lo[q] = h;
+      else
+        hi[q - 8] = h;
+    }
+  }
+}
+
+template <class Src>
+__device__ __forceinline__ void h16_fill(const Src& src, const typename Src::Row& rw, bool on,
+                                         bool diag, int64_t n, int64_t n_end, bool vec,
+                                         const float* __restrict__ colv, h8v& v0, h8v& v1,
+                                         h8v& v2, h8v& v3) {
+  fill16(src, rw, on, n, n_end, vec, colv, v0, v1);
+  if (!diag) fill16(src, rw, on, n + 16, n_end, vec, colv, v2, v3);
+}
+
+__device__ __forceinline__ void h16_store(_Float16* row, bool diag, const h8v& v0, const h8v& v1,
+                                          const h8v& v2, const h8v& v3) {
+  *reinterpret_cast<h8v*>(row) = v0;
+  *reinterpret_cast<h8v*>(row + 8) = v1;
+  if (!diag) {
+    *reinterpret_cast<h8v*>(row + 16) = v2;
+    *reinterpret_cast<h8v*>(row + 24) = v3;
+  }
+}
 
 template <class Src>
 __global__ void __launch_bounds__(512)
     hessian_h16_kernel(Src src, int K, int64_t N, const double* __restrict__ cst,
-                       const double* __restrict__ gk, const double* __restrict__ logD, int nb,
-                       int chunks, int64_t chunk_len, float* __restrict__ partials) {
-  __shared__ __attribute__((aligned(16))) _Float16 Pi[XB][XP];
-  __shared__ __attribute__((aligned(16))) _Float16 Pj[XB][XP];
+                       const double* __restrict__ gk, const float* __restrict__ colv, int nb,
+                       int chunks, int64_t chunk_len, bool vec, float* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) _Float16 P[2][2][XB][XP];  // [buffer][slab][row][sample]
   const int blk = blockIdx.x / chunks;
   const int chunk = blockIdx.x % chunks;
   int bi, bj;
   block_coords(blk, nb, bi, bj);
   const bool diag = (bi == bj);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  // loader: row lr of both slabs, samples ls .. ls + 15
-  const int lr = tid >> 1;
-  const int ls = (tid & 1) * 16;
-  const int ki = bi * XB + lr, kj = bj * XB + lr;
-  const bool si = ki < K && gk[ki] != 0.0;
-  const bool sj = kj < K && gk[kj] != 0.0;
-  const typename Src::Row ri = src.row(si ? ki : 0, si ? cst[ki] : 0.0);
-  const typename Src::Row rj = src.row(sj ? kj : 0, sj ? cst[kj] : 0.0);
-  f4v acc[2][16];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // fill role
+  const int slab = diag ? 0 : (wave >> 2);
+  const int frow = (wave & 3) * 64 + lane;
+  const int s0 = diag ? (wave >> 2) * 16 : 0;
+  const int k = (slab ? bj : bi) * XB + frow;
+  const bool on = k < K && gk[k] != 0.0;
+  const typename Src::Row rw = src.row(on ? k : 0, on ? cst[k] : 0.0);
+  // product role: output rows 64 wr + 16 a, columns 128 wc + 16 b
+  const int wr = wave & 3, wc = wave >> 2;
+  const int kq = (lane >> 4) * 8;
+  f4v acc[4][8];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 16; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 8; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
+
   const int64_t n_begin = (int64_t)chunk * chunk_len;
   const int64_t n_end = n_begin + chunk_len < N ? n_begin + chunk_len : N;
+  h8v v0, v1, v2, v3;
+  if (n_begin < n_end) {
+    h16_fill(src, rw, on, diag, n_begin + s0, n_end, vec, colv, v0, v1, v2, v3);
+    h16_store(&P[0][slab][frow][s0], diag, v0, v1, v2, v3);
+  }
+  __syncthreads();
+  int cur = 0;
   for (int64_t n0 = n_begin; n0 < n_end; n0 += XS) {
+    const bool more = n0 + XS < n_end;
+    if (more) h16_fill(src, rw, on, diag, n0 + XS + s0, n_end, vec, colv, v0, v1, v2, v3);
+    const _Float16(*Pa)[XP] = P[cur][0];
+    const _Float16(*Pb)[XP] = P[cur][diag ? 0 : 1];
+    h8v av[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t n = n0 + ls + q;
-      const bool ok = n < n_end;
-      const float cn = ok ? src.col(n, logD) : 0.f;
-      Pi[lr][ls + q] = (_Float16)((si && ok) ? src.p(ri, n, cn) : 0.f);
-      if (!diag) Pj[lr][ls + q] = (_Float16)((sj && ok) ? src.p(rj, n, cn) : 0.f);
-    }
-    __syncthreads();
-    const _Float16(*Bsrc)[XP] = diag ? Pi : Pj;
-    const int kq = (lane >> 4) * 8;
-    h8v av[2];
+    for (int a = 0; a < 4; ++a)
+      av[a] = *reinterpret_cast<const h8v*>(&Pa[wr * 64 + a * 16 + (lane & 15)][kq]);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-      av[a] = *reinterpret_cast<const h8v*>(&Pi[(2 * wave + a) * 16 + (lane & 15)][kq]);
+    for (int b = 0; b < 8; ++b) {
+      const h8v bv = *reinterpret_cast<const h8v*>(&Pb[wc * 128 + b * 16 + (lane & 15)][kq]);
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      const h8v bv = *reinterpret_cast<const h8v*>(&Bsrc[b * 16 + (lane & 15)][kq]);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
     }
+    if (more) h16_store(&P[cur ^ 1][slab][frow][s0], diag, v0, v1, v2, v3);
     __syncthreads();
+    cur ^= 1;
   }
   float* out = partials + (int64_t)blockIdx.x * XB * XB;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
+    for (int b = 0; b < 8; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = (2 * wave + a) * 16 + (lane >> 4) * 4 + v;
-        const int c = b * 16 + (lane & 15);
+        const int r = wr * 64 + a * 16 + (lane >> 4) * 4 + v;
+        const int c = wc * 128 + b * 16 + (lane & 15);
         out[r * XB + c] = acc[a][b][v];
       }
 }
@@ -526,10 +652,25 @@ __global__ void __launch_bounds__(256)
 static int h16_nb(int K) { return (K + XB - 1) / XB; }
 
 static int h16_chunks(int K, int64_t N, int num_cus) {
+  // one workgroup per CU at a time: pick the chunk count in [2, 8] rounds of
+  // the grid whose last round is fullest (ties: fewer chunks), each chunk at
+  // least 1024 samples
   const int nb = h16_nb(K);
   const int nblk = nb * (nb + 1) / 2;
-  int64_t ch = (2 * (int64_t)num_cus + nblk - 1) / nblk;
   const int64_t by_n = (N + 1023) / 1024;
+  const int lo = (2 * num_cus + nblk - 1) / nblk, hi = (8 * num_cus + nblk - 1) / nblk;
+  int best = lo;
+  double best_eff = 0.0;
+  for (int ch = lo; ch <= hi; ++ch) {
+    const int64_t wgs = (int64_t)nblk * ch;
+    const int64_t rounds = (wgs + num_cus - 1) / num_cus;
+    const double eff = (double)wgs / (double)(rounds * num_cus);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = ch;
+    }
+  }
+  int64_t ch = best;
   if (ch > by_n) ch = by_n;
   return (int)(ch < 1 ? 1 : ch);
 }
@@ -577,7 +718,9 @@ size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
   if (chunks_out) *chunks_out = chunks;
   // room for the FP16-core path of the mixed-precision sources as well
   const int nb16 = h16_nb(K);
-  const size_t h16 = (size_t)(nb16 * (nb16 + 1) / 2) * h16_chunks(K, N, num_cus) * XB * XB;
+  // (FP32 partial blocks, then the N per-sample column constants)
+  const size_t h16 =
+      (size_t)(nb16 * (nb16 + 1) / 2) * h16_chunks(K, N, num_cus) * XB * XB + (size_t)N + 64;
   const size_t fp64 = (size_t)nblk * chunks * HB * HB;
   return fp64 > (h16 + 1) / 2 ? fp64 : (h16 + 1) / 2;
 }
@@ -631,19 +774,24 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
     int64_t len16 = (N + ch16 - 1) / ch16;
     len16 = (len16 + XS - 1) / XS * XS;
     float* p16 = reinterpret_cast<float*>(partials);
+    float* colv = p16 + (size_t)nblk16 * ch16 * XB * XB;
     const dim3 g16(nblk16 * ch16);
-    if (hs.kind == 2)
+    hipLaunchKernelGGL(h16_colv_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N,
+                       logD, hs.kind == 2 ? hs.m0 : nullptr, colv);
+    if (hs.kind == 2) {
+      const bool vec = ((hs.ld & 3) == 0) && ((reinterpret_cast<uintptr_t>(hs.u) & 15) == 0);
       hipLaunchKernelGGL(hessian_h16_kernel<SrcPacked32>, g16, dim3(512), 0, s,
                          SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
-                         cst, gk, logD, nb16, ch16, len16, p16);
-    else if (hs.otf.d == 1)
+                         cst, gk, colv, nb16, ch16, len16, vec, p16);
+    } else if (hs.otf.d == 1) {
       hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<1>>, g16, dim3(512), 0, s,
-                         SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb16,
-                         ch16, len16, p16);
-    else
+                         SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
+                         ch16, len16, false, p16);
+    } else {
       hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<2>>, g16, dim3(512), 0, s,
-                         SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, logD, nb16,
-                         ch16, len16, p16);
+                         SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
+                         ch16, len16, false, p16);
+    }
     hipLaunchKernelGGL(hessian_h16_reduce_kernel, dim3(XB * XB / 256, nblk16), dim3(256), 0, s, K,
                        nb16, ch16, p16, S, gk, H);
     return hipGetLastError();

@@ -86,7 +86,11 @@ __device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const double* 
   }
 }
 
-// The three passes over a loaded tile (see the file comment).
+// The three passes over a loaded tile (see the file comment). red1 / red2
+// are read by every wave in the ln D step at the end, so a caller that runs
+// tiles back to back without a barrier between them alternates two copies of
+// them (a wave may start the next tile's pass 1 while another is still
+// reading this tile's).
 template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED, int SG>
 __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, int64_t N, int lc,
                                              int rg, int wave, int rgw,
@@ -182,8 +186,7 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
     for (int i = 0; i < CPL; ++i) acc[j] = __builtin_fma(a[j][i], w[i], acc[j]);
   // the tile values are dead from here on: do the logarithms now
   __builtin_amdgcn_sched_barrier(0);
-  // ln D_n and the objective (red1 / red2 stay valid until the next tile's
-  // first barrier): wave v handles columns [v * CW, (v + 1) * CW),
+  // ln D_n and the objective: wave v handles columns [v * CW, (v + 1) * CW),
   // one lane each, so every wave evaluates one logarithm per tile.
   {
     constexpr int CW = TN / NW;
@@ -210,14 +213,16 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
 // Tile loop over the full tiles of this block; with PF the next tile's loads
 // are issued into a second register buffer before the current tile is
 // processed (software prefetch), so HBM traffic overlaps the arithmetic.
+// Successive tiles use alternating copies (par) of the reduction buffers.
 template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG>
 __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64_t rstride,
                                           int rows_here, int64_t nfull, int64_t N, int lc, int rg,
                                           int wave, int rgw, const double* __restrict__ c_sh,
                                           unsigned smask, const double* __restrict__ h,
-                                          double* __restrict__ logD, double (*red1)[LPR * CPL],
-                                          double (*red2)[LPR * CPL], double* acc, double& obj,
-                                          unsigned& bad) {
+                                          double* __restrict__ logD,
+                                          double (*red1)[NW][LPR * CPL],
+                                          double (*red2)[NW][LPR * CPL], int& par, double* acc,
+                                          double& obj, unsigned& bad) {
   const int64_t G = gridDim.x;
   int64_t t = blockIdx.x;
   if constexpr (!PF) {
@@ -225,7 +230,8 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
       double a[ROWS][CPL];
       tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
-                                                      logD, red1, red2, acc, obj, bad);
+                                                      logD, red1[par], red2[par], acc, obj, bad);
+      par ^= 1;
     }
   } else {
     double a[ROWS][CPL], b[ROWS][CPL];
@@ -234,12 +240,14 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
       const int64_t t1 = t + G;
       if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(b, base, rstride, rows_here, t1, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
-                                                      logD, red1, red2, acc, obj, bad);
+                                                      logD, red1[par], red2[par], acc, obj, bad);
+      par ^= 1;
       if (t1 >= nfull) break;
       const int64_t t2 = t1 + G;
       if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t2, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
-                                                      logD, red1, red2, acc, obj, bad);
+                                                      logD, red1[par], red2[par], acc, obj, bad);
+      par ^= 1;
       t = t2;
     }
   }
@@ -256,8 +264,8 @@ __global__ void __launch_bounds__(NW * 64)
   constexpr int NT = TL::NT;
   constexpr int RG = TL::RG;
   constexpr int TN = TL::TN;
-  __shared__ double red1[NW][TN];
-  __shared__ double red2[NW][TN];
+  __shared__ double red1[2][NW][TN];
+  __shared__ double red2[2][NW][TN];
   __shared__ double c_sh[ROWS * RG];
   __shared__ unsigned fl;
 
@@ -290,20 +298,21 @@ __global__ void __launch_bounds__(NW * 64)
 
   double obj = 0.0;
   unsigned bad = 0;
+  int par = 0;
   const int64_t nfull = N / TN;
   if (!masked)
     tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG>(base, rstride, rows_here, nfull, N, lc, rg, wave,
-                                                  rgw, c_sh, smask, h, logD, red1, red2, acc, obj,
-                                                  bad);
+                                                  rgw, c_sh, smask, h, logD, red1, red2, par, acc,
+                                                  obj, bad);
   else
     tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1>(base, rstride, rows_here, nfull, N, lc, rg,
                                                     wave, rgw, c_sh, smask, h, logD, red1, red2,
-                                                    acc, obj, bad);
+                                                    par, acc, obj, bad);
   if (nfull < ntiles && blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     double a[ROWS][CPL];
     tile_load<NW, LPR, CPL, ROWS, VEC, true>(a, base, rstride, rows_here, nfull, N, lc);
     tile_compute<NW, LPR, CPL, ROWS, true, true, 1>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
-                                                 logD, red1, red2, acc, obj, bad);
+                                                 logD, red1[par], red2[par], acc, obj, bad);
   }
 
   // Reduce each state's accumulator over the LPR lanes of its row group
@@ -321,11 +330,11 @@ __global__ void __launch_bounds__(NW * 64)
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) o += __shfl_xor(o, off, 64);
   __syncthreads();  // red1 is free again
-  if ((tid & 63) == 0) red1[0][wave] = o;
+  if ((tid & 63) == 0) red1[0][0][wave] = o;
   __syncthreads();
   if (tid == 0) {
-    double ob = red1[0][0];
-    for (int wv = 1; wv < NW; ++wv) ob += red1[0][wv];
+    double ob = red1[0][0][0];
+    for (int wv = 1; wv < NW; ++wv) ob += red1[0][0][wv];
     part_obj[blockIdx.x] = ob;
   }
   // flags: OR over the block in shared memory, then one plain store

@@ -73,8 +73,11 @@ __global__ void __launch_bounds__(NW * 64)
   constexpr int LPR = 16, CPL = 4, TN = LPR * CPL;
   constexpr int NT = NW * 64;
   constexpr int RG = NT / LPR;
-  __shared__ float red1[NW][TN];
-  __shared__ float red2[NW][TN];
+  // two copies of the reduction buffers, alternating by tile: every wave reads
+  // all of them in the ln D step, and a wave may reach the next tile's pass 1
+  // before another has finished that step
+  __shared__ float red1b[2][NW][TN];
+  __shared__ float red2b[2][NW][TN];
   __shared__ float d_sh[ROWS * RG];
   __shared__ double wred[NW];
   __shared__ unsigned fl;
@@ -101,7 +104,10 @@ __global__ void __launch_bounds__(NW * 64)
   const bool vec = ((reinterpret_cast<uintptr_t>(r) & 15) == 0) && ((ld & 3) == 0);
   double obj = 0.0;
   unsigned bad = 0;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  int par = 0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x, par ^= 1) {
+    float(*red1)[TN] = red1b[par];
+    float(*red2)[TN] = red2b[par];
     const int64_t col0 = t * TN + (int64_t)lc * CPL;
     const bool full = (t + 1) * TN <= N;
     float a[ROWS][CPL];
