@@ -391,7 +391,7 @@ def _serve(bm, probs, arrivals, max_active, budget, opts):
         res = []
         for i, t in enumerate(tickets):
             res.append(srv.result(t))
-            if (i + 1) % 64 == 0:
+            if (i + 1) % 16 == 0:
                 log(f"  {i + 1}/{len(tickets)} results")
         wall = time.perf_counter() - t0
         return res, wall, srv.counters()

@@ -24,7 +24,7 @@ namespace bumbar {
 constexpr int kCountSlots = 8192;
 
 void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,
-                       bool cen_bufs) {
+                       bool cen_bufs, bool cen_f32) {
   (void)num_cus;
   otf = cen_bufs && !ubar_bufs;
   d = d_;
@@ -47,6 +47,7 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
   sort_tmp = ar.take<char>(sort_tmp_bytes);
   for (int i = 0; i < 2; ++i) {
     if (cen_bufs) cen[i] = ar.take<double>((size_t)N * d);
+    if (cen_bufs && cen_f32) cenf[i] = ar.take<float>((size_t)N * d);
     if (ubar_bufs) ubar[i] = ar.take<double>((size_t)K * N);
     h[i] = ar.take<double>(N);
   }
@@ -56,9 +57,9 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
 }
 
 void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
-                       bool cen_bufs) {
+                       bool cen_bufs, bool cen_f32) {
   BinnedBufs b;
-  b.carve(ar, K, N, d, num_cus, ubar_bufs, cen_bufs);
+  b.carve(ar, K, N, d, num_cus, ubar_bufs, cen_bufs, cen_f32);
 }
 
 static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
@@ -224,23 +225,28 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
   else
     e = launch_represent(ctx->stream, K, BB.N, BB.d, model, coef, BB.lo, BB.scale, m, P,
                          BB.cells, BB.start, BB.perm, u, BB.ubar[slot], BB.h[slot]);
+  if (e == hipSuccess && BB.otf && BB.cenf[slot])
+    e = launch_pack_coords(ctx->stream, P * BB.d, BB.cen[slot], BB.cenf[slot]);
   if (e != hipSuccess) return hip_fail(ctx, e, "represent");
   L->n = n;
   L->m = m;
   L->P = P;
   L->ubar = BB.otf ? nullptr : BB.ubar[slot];
   L->cen = BB.otf ? BB.cen[slot] : nullptr;
+  L->cenf = BB.otf ? BB.cenf[slot] : nullptr;
   L->h = BB.h[slot];
   return BUMBAR_OK;
 }
 
 // The matrix of a level: stored representatives, or the model evaluated at
-// the bin centres (FP64) when the stage runs on the fly.
-static Mat level_mat_of(const Level& L, const Mat* otf_base) {
+// the bin centres when the stage runs on the fly (FP32 when the level has
+// FP32 centres and fp32 is asked for, else FP64).
+static Mat level_mat_of(const Level& L, const Mat* otf_base, bool fp32) {
   if (otf_base) {
     Mat M = *otf_base;
-    M.kind = 4;
+    M.kind = (fp32 && L.cenf) ? 3 : 4;
     M.otf.xi = L.cen;
+    M.otf.xf = L.cenf;
     return M;
   }
   Mat M;
@@ -253,8 +259,13 @@ static Mat level_mat_of(const Level& L, const Mat* otf_base) {
 int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double* u,
                  const int64_t* Nk_dev, const int64_t* Nk_host, const double* xi, int d,
                  int model, const double* coef, const bumbar_options& opt, bumbar_stats* st,
-                 SweepCounters* cnt, const Mat* otf_base) {
-  auto level_mat = [otf_base](const Level& L) { return level_mat_of(L, otf_base); };
+                 SweepCounters* cnt, const Mat* otf_base, bool fp32_steps) {
+  // batched steps: FP32 centres when asked for (and present); the
+  // one-at-a-time fallback steps: FP64
+  auto level_mat = [otf_base, fp32_steps](const Level& L) {
+    return level_mat_of(L, otf_base, fp32_steps);
+  };
+  auto level_mat64 = [otf_base](const Level& L) { return level_mat_of(L, otf_base, false); };
   (void)Nk_host;
   hipStream_t s = ctx->stream;
   const int K = B.K;
@@ -296,8 +307,8 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   };
   // one step on the robust-capable path, result in fh(slot)
   auto safe_step = [&](const Level& L, const double* fin, int slot, SweepScalars* sc) -> int {
-    return sweep_at(ctx, B, level_mat(L), L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl, B.lnS_t,
-                    B.S_t, sc, false, nullptr);
+    return sweep_at(ctx, B, level_mat64(L), L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl,
+                    B.lnS_t, B.S_t, sc, false, nullptr);
   };
   int64_t it1 = 0, it2 = 0, nchk = 0;
   int result = BUMBAR_OK;

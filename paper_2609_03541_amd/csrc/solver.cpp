@@ -733,7 +733,9 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
   Arena ar;
   UnbinnedBufs B;
   B.carve(ar, K, N, ctx->num_cus);
-  if (opt == nullptr || opt->binning) binned_carve_size(ar, K, N, d, ctx->num_cus, false, true);
+  if (opt == nullptr || opt->binning)
+    binned_carve_size(ar, K, N, d, ctx->num_cus, false, true,
+                      opt && opt->precision == BUMBAR_PREC_MIXED && K > 256);
   OtfBufs O;
   O.carve(ar, K, N, d);
   *bytes = ar.off + 256;
@@ -796,8 +798,9 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   B.carve(ar, K, N, ctx->num_cus);
   BinnedBufs BB;
   if (opt.binning) {
+    // on the fly in mixed precision: FP32 centres for the binned steps
     if (otf)
-      BB.carve(ar, K, N, d, ctx->num_cus, false, true);
+      BB.carve(ar, K, N, d, ctx->num_cus, false, true, mixed && K > 256);
     else
       BB.carve(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(opt.represent, K),
                centre_bufs(opt.represent, K));
@@ -869,8 +872,31 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     Mc.otf.cf64 = O.cf64;
     // MEAN ignores a given model: the representatives are the bin means of u
     const int rep_model = rep == BUMBAR_REPRESENT_MEAN ? BUMBAR_MODEL_NONE : model;
-    stage_rc = binned_stage(ctx, B, BB, reinterpret_cast<const double*>(u_kn), N_k, nk.data(), xi,
-                            d, rep_model, coef, opt, st, &cnt, BB.otf ? &Mc : nullptr);
+    // On the fly in mixed precision with K > 256 (where a binned step is a
+    // compute-bound model sweep over K x P, not a few launches) the binned
+    // steps first run on the FP32 model sweep. That stage only provides the
+    // Newton start, but FP32 rounding of large energies can keep its
+    // relative-step tests from passing: if it has not converged within
+    // kFp32BinnedSteps steps it is rerun in FP64 from the start. For smaller K
+    // the FP32 noise costs more iterations than it saves per step.
+    constexpr int64_t kFp32BinnedSteps = 4000;
+    const bool try32 = otf && mixed && K > 256 && BB.cenf[0] != nullptr;
+    if (try32) {
+      bumbar_options o32 = opt;
+      o32.max_iter = std::min<int64_t>(opt.max_iter, kFp32BinnedSteps);
+      stage_rc = binned_stage(ctx, B, BB, nullptr, N_k, nk.data(), xi, d, rep_model, coef, o32, st,
+                              &cnt, &Mc, true);
+      if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
+      if (stage_rc == BUMBAR_ENOTCONV && o32.max_iter < opt.max_iter) {
+        e = hipMemsetAsync(B.f, 0, sizeof(double) * K, s);  // the binned stage starts at f = 0
+        if (e != hipSuccess) return hip_fail(ctx, e, "init f");
+        stage_rc = binned_stage(ctx, B, BB, nullptr, N_k, nk.data(), xi, d, rep_model, coef, opt,
+                                st, &cnt, &Mc, false);
+      }
+    } else {
+      stage_rc = binned_stage(ctx, B, BB, reinterpret_cast<const double*>(u_kn), N_k, nk.data(),
+                              xi, d, rep_model, coef, opt, st, &cnt, BB.otf ? &Mc : nullptr);
+    }
     if (stage_rc != BUMBAR_OK && stage_rc != BUMBAR_ENOTCONV) return stage_rc;
   } else if (opt.finisher == BUMBAR_FINISH_NEWTON) {
     const double t0 = now_ms();

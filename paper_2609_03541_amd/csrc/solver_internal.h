@@ -106,6 +106,7 @@ struct Level {
   int64_t P = 0;   // nonempty bins
   double* ubar = nullptr;  // K x P (row stride P); stored representatives
   double* cen = nullptr;   // P x d bin centres; representatives from the model
+  float* cenf = nullptr;   // the same centres in FP32 (mixed precision), or null
   double* h = nullptr;     // P multiplicities (as double)
 };
 
@@ -131,23 +132,28 @@ struct BinnedBufs {
   bool otf = false;                      // representatives from the model in the kernels
   double* ubar[2] = {nullptr, nullptr};  // K x N each (worst case P = N); stored mode
   double* cen[2] = {nullptr, nullptr};   // N x d each (worst case P = N); otf mode
+  float* cenf[2] = {nullptr, nullptr};   // FP32 copies of cen (mixed precision)
   double* h[2] = {nullptr, nullptr};     // N each
   double* logD_lvl = nullptr;            // N
   double *f_n = nullptr, *f_x = nullptr; // K
   // ubar_bufs: K x N representative buffers (MEAN); cen_bufs: N x d centres
-  // (CENTRE). otf is set by the caller to the representative in use.
-  void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs, bool cen_bufs);
+  // (CENTRE), cen_f32 also their FP32 copies. otf is set by the caller to the
+  // representative in use.
+  void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs, bool cen_bufs,
+             bool cen_f32 = false);
 };
 
 void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
-                       bool cen_bufs);
+                       bool cen_bufs, bool cen_f32 = false);
 
 // otf_base: nullptr for stored representatives, else the FP64 model matrix
-// (kind 4) whose coordinates the stage replaces by the bin centres.
+// (kind 4) whose coordinates the stage replaces by the bin centres. With
+// fp32_steps and FP32 centres (BinnedBufs::cenf) the batched steps run the
+// FP32 model sweep and only steps that need a fallback run in FP64.
 int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double* u,
                  const int64_t* Nk_dev, const int64_t* Nk_host, const double* xi, int d,
                  int model, const double* coef, const bumbar_options& opt, bumbar_stats* st,
-                 SweepCounters* cnt, const Mat* otf_base);
+                 SweepCounters* cnt, const Mat* otf_base, bool fp32_steps = false);
 
 // Binning primitives (binning.hip).
 size_t sort_temp_bytes(int64_t N);

@@ -144,6 +144,19 @@ def test_solve_on_the_fly_matches_oracle(bm, name, binning, precision):
         say("  mixed steps", info["mixed_steps"], "newton", info["finisher_steps"])
 
 
+def test_mixed_on_the_fly_large_energies(bm):
+    # K > 256 on the fly in mixed precision: the binned steps start on the
+    # FP32 model sweep (falling back to FP64 if FP32 rounding of these large
+    # ladder energies stalls its step tests); the result is the FP64 one
+    p = synth.ladder_2d(K=300, Nk=40, seed=6)
+    say(f"mixed on-the-fly ladder: K={p['K']} N={p['N']}")
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(None, p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       precision=1, tol=1e-11)
+    assert info["status"] == 0
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+
+
 def test_on_the_fly_equals_stored_solve(bm):
     # the same problem with u stored and u from the model reaches the same f
     p = aniso_2d(K=25, Nk=200, seed=8)
