@@ -164,8 +164,10 @@ hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, cons
                                    const double* S, double* A, int* idx, double* d, int* ok);
 // Largest reduced size the single-workgroup LDS solve takes.
 int newton_lds_max_m();
-// Blocked Cholesky solve of the same reduced system for any m; idx (m
-// entries, the kept states) must be on the device; A holds m*m + m doubles.
+// Blocked Cholesky solve of the same reduced system for any 0 < m < K; idx
+// (m entries, the kept states) must be on the device; A holds
+// newton_ws_doubles(K) doubles.
+size_t newton_ws_doubles(int K);
 hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
                                            const double* H, const double* S, double* A,
                                            const int* idx, double* d, int* ok);

@@ -129,17 +129,29 @@ hipError_t launch_newton_direction(hipStream_t s, int K, const int64_t* Nk, cons
 
 // ---------------------------------------------------------------------------
 // Reduced systems larger than the LDS kernel holds (m > 136): a blocked
-// right-looking Cholesky factorisation A = L L^T in place (lower triangle,
-// 64 x 64 blocks) followed by blocked forward and backward substitution. Per
-// block column p: the diagonal block is factored by one workgroup in LDS,
-// the blocks below it are solved against L_pp^T (one workgroup per block
-// row), and every trailing block (i, j), p < j <= i, loses L_ip L_jp^T (one
-// workgroup per block, 4 x 4 outputs per thread). A pivot that is not
-// positive clears *ok, as in the LDS kernel.
+// right-looking Cholesky factorisation A = L L^T (64 x 64 blocks) with the
+// forward substitution L y = b folded in, then a backward substitution
+// L^T x = y. Each diagonal block L_pp is factored in LDS together with its
+// inverse, so that the blocks below it, L_ip = A_ip L_pp^{-T}, and the piece
+// y_p = L_pp^{-1} b_p are products rather than serial substitutions.
+//
+// Per block column p one launch (chol_step_kernel) covers every trailing block
+// (i, j), p < j <= i: it forms L_ip and L_jp from the untouched A_ip, A_jp and
+// subtracts L_ip L_jp^T from A_ij; the diagonal blocks (i, i) also store
+// L_ip^T in the upper block (p, i) (the lower one is still read by other
+// workgroups of the launch) and take b_i -= L_ip y_p; the workgroup of block
+// (p+1, p+1), whose update is the last that block receives, factors it
+// straight away for the next launch. Storage after the factorisation: the
+// diagonal blocks hold L_pp below and L_pp^T above the diagonal, the upper
+// off-diagonal blocks hold L^T (copied to the lower ones before the backward
+// substitution), and the inverses L_pp^{-1} sit in a separate array. A pivot
+// that is not positive clears *ok, as in the LDS kernel; the launches after
+// it return at once.
 namespace bumbar {
 
 constexpr int CB = 64;       // Cholesky block edge
 constexpr int CBP = CB + 1;  // padded LDS row
+constexpr int CT = 256;      // threads of the factorisation kernels (16 x 16)
 
 // A (m x m, row-major) = H[idx, idx], b = -(S - N)[idx], d = 0 elsewhere.
 __global__ void reduced_gather_kernel(int K, int m, const int* __restrict__ idx,
@@ -155,215 +167,413 @@ __global__ void reduced_gather_kernel(int K, int m, const int* __restrict__ idx,
   if (e < K) d[e] = 0.0;
 }
 
-__global__ void __launch_bounds__(256)
-    chol_diag_kernel(int m, int p, double* __restrict__ A, int* __restrict__ ok) {
-  __shared__ double T[CB][CBP];
-  __shared__ int bad;
-  const int r0 = p * CB;
-  const int nb = min(CB, m - r0);
-  for (int e = threadIdx.x; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    T[r][c] = (r < nb && c < nb) ? A[(int64_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
-  }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < CB; ++j) {
-    const double piv = T[j][j];
-    if (!(piv > 0.0)) {
-      if (threadIdx.x == 0) bad = 1;
-      break;  // uniform: every thread read the same pivot
+// Factorisation of one 64 x 64 diagonal block held in registers: thread
+// (tx, ty) of 16 x 16 owns t[q][w] = T[ty + 16 q][tx + 16 w] (padding rows and
+// columns hold the identity; only the lower triangle is read). L D L^T first
+// (unit lower L', no square roots): at step j every A_ik, j < k <= i, loses
+// A_ij A_kj / A_jj, and Y = L'^{-1} is built alongside by the same column (row
+// i of Y loses L'_ij times row j). Column j of T and row j of Y are final at
+// step j; their owners publish them to a double-buffered LDS vector, one
+// barrier per column. Then L = L' D^{1/2} and L^{-1} = D^{-1/2} L'^{-1}: on
+// return t holds L (zero above the diagonal) and y holds L^{-1}. Returns
+// false, uniformly, on a pivot that is not positive. lds: 5 * 64 doubles.
+__device__ bool factor_regs(double (&t)[4][4], double (&y)[4][4], double* lds) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double* cb = lds;           // [2][64] column j of T
+  double* yb = lds + 2 * CB;  // [2][64] row j of Y
+  double* sd = lds + 4 * CB;  // sqrt(D)
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) y[q][w] = (ty + 16 * q == tx + 16 * w) ? 1.0 : 0.0;
+#pragma unroll
+  for (int wj = 0; wj < 4; ++wj) {
+#pragma unroll 1
+    for (int tj = 0; tj < 16; ++tj) {
+      const int j = 16 * wj + tj;
+      double* cj = cb + (j & 1) * CB;
+      double* yj = yb + (j & 1) * CB;
+      if (tx == tj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cj[ty + 16 * q] = t[q][wj];
+      }
+      if (ty == tj) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) yj[tx + 16 * w] = y[wj][w];
+      }
+      __syncthreads();
+      const double piv = cj[j];
+      if (!(piv > 0.0)) return false;
+      const double rp = 1.0 / piv;
+      // rows i <= j and the columns each update must not touch take a zero
+      // factor (every operand is finite, so x - 0 * v = x exactly)
+      double li[4], ck[4], yc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) li[q] = ty + 16 * q > j ? -cj[ty + 16 * q] * rp : 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const bool right = tx + 16 * w > j;
+        ck[w] = right ? cj[tx + 16 * w] : 0.0;
+        yc[w] = right ? 0.0 : yj[tx + 16 * w];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          t[q][w] = __builtin_fma(li[q], ck[w], t[q][w]);
+          y[q][w] = __builtin_fma(li[q], yc[w], y[q][w]);
+        }
     }
-    const double l = sqrt(piv);
-    __syncthreads();
-    // column j below the diagonal, then the trailing lower triangle
-    for (int i = j + 1 + threadIdx.x; i < CB; i += 256) T[i][j] /= l;
-    if (threadIdx.x == 0) T[j][j] = l;
-    __syncthreads();
-    for (int e = threadIdx.x; e < (CB - j - 1) * (CB - j - 1); e += 256) {
-      const int i = j + 1 + e / (CB - j - 1), k = j + 1 + e % (CB - j - 1);
-      if (k <= i) T[i][k] -= T[i][j] * T[k][j];
-    }
-    __syncthreads();
+  }
+  if (tx == ty) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sd[tx + 16 * q] = sqrt(t[q][q]);
   }
   __syncthreads();
-  if (bad) {
-    if (threadIdx.x == 0) *ok = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int i = ty + 16 * q, k = tx + 16 * w;
+      t[q][w] = k < i ? t[q][w] / sd[k] : (k == i ? sd[i] : 0.0);
+      y[q][w] = k <= i ? y[q][w] / sd[i] : 0.0;
+    }
+  return true;
+}
+
+// Factor the diagonal block at rows/columns r0 .. r0+nb-1 (t as in
+// factor_regs), store L below and L^T above its diagonal in A, L^{-1}
+// (64 x 64, row-major, zero above the diagonal) in Linv_blk and, for the last
+// block, y = L^{-1} bv. Ls: a 64 x 65 LDS tile (the transpose), lds: 5 * 64
+// doubles.
+__device__ void finish_diag(double (&t)[4][4], double (*Ls)[CBP], double* lds, const double* bv,
+                            int nb, int r0, bool last, int m, double* __restrict__ A,
+                            double* __restrict__ Linv_blk, double* __restrict__ y,
+                            int* __restrict__ ok) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double yi[4][4];
+  if (!factor_regs(t, yi, lds)) {
+    if (tid == 0) *ok = 0;
     return;
   }
-  for (int e = threadIdx.x; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    if (r < nb && c <= r) A[(int64_t)(r0 + r) * m + r0 + c] = T[r][c];
-  }
-}
-
-// Block row i = p + 1 + blockIdx.x: X L_pp^T = A_ip, one row of X per thread
-// (the row lives in registers; L_pp is read from LDS by broadcast).
-__global__ void __launch_bounds__(CB)
-    chol_trsm_kernel(int m, int p, double* __restrict__ A) {
-  __shared__ double L[CB][CBP];
-  const int r0 = p * CB;
-  const int i0 = (p + 1 + blockIdx.x) * CB;
-  const int ni = min(CB, m - i0);
-  const int np = min(CB, m - r0);
-  for (int e = threadIdx.x; e < CB * CB; e += CB) {
-    const int r = e / CB, c = e % CB;
-    L[r][c] = (r < np && c < np) ? A[(int64_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
-  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      Ls[ty + 16 * q][tx + 16 * w] = t[q][w];
+      Linv_blk[(ty + 16 * q) * CB + tx + 16 * w] = yi[q][w];
+    }
   __syncthreads();
-  const int r = threadIdx.x;
-  if (r >= ni) return;
-  double* row = A + (int64_t)(i0 + r) * m + r0;
-  double x[CB];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) x[c] = c < np ? row[c] : 0.0;
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    double v = x[c];
+    for (int w = 0; w < 4; ++w) {
+      const int i = ty + 16 * q, k = tx + 16 * w;
+      if (i < nb && k < nb) A[(int64_t)(r0 + i) * m + r0 + k] = k <= i ? t[q][w] : Ls[k][i];
+    }
+  if (last) {
+    // y_i = sum_c L^{-1}_ic b_c: partial sums over the thread's columns, then
+    // over the 16 threads that share its rows (lanes tx of one wave)
 #pragma unroll
-    for (int t = 0; t < c; ++t) v -= x[t] * L[c][t];
-    x[c] = v / L[c][c];
+    for (int q = 0; q < 4; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v = __builtin_fma(yi[q][w], bv[tx + 16 * w], v);
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+      const int i = ty + 16 * q;
+      if (tx == 0 && i < nb) y[r0 + i] = v;
+    }
   }
-#pragma unroll
-  for (int c = 0; c < CB; ++c)
-    if (c < np) row[c] = x[c];
 }
 
-// Trailing update of block (i, j), p < j <= i, enumerated row by row. Both
-// panels are staged transposed (dynamic LDS, 2 x 64 x 65 doubles) so that
-// the inner loop reads consecutive words; thread (tx, ty) owns rows ty + 16 q
-// and columns tx + 16 w of the block.
-__global__ void __launch_bounds__(256)
-    chol_update_kernel(int m, int p, double* __restrict__ A) {
+// The first diagonal block (one workgroup).
+__global__ void __launch_bounds__(CT)
+    chol_first_kernel(int m, double* __restrict__ A, const double* __restrict__ b,
+                      double* __restrict__ y, double* __restrict__ Linv, int* __restrict__ ok) {
+  __shared__ double Ls[CB][CBP];
+  __shared__ double work[5 * CB];
+  __shared__ double bv[CB];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int nb = min(CB, m);
+  double t[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int i = ty + 16 * q, k = tx + 16 * w;
+      t[q][w] = (i < nb && k < nb) ? A[(int64_t)i * m + k] : (i == k ? 1.0 : 0.0);
+    }
+  if (tid < CB) bv[tid] = tid < nb ? b[tid] : 0.0;
+  __syncthreads();
+  finish_diag(t, Ls, work, bv, nb, 0, m <= CB, m, A, Linv, y, ok);
+}
+
+// Block column p: one workgroup per trailing block (i, j), p < j <= i,
+// enumerated row by row so that workgroup 0 owns block (p+1, p+1). Thread
+// (tx, ty) owns rows ty + 16 q and columns tx + 16 w of each 64 x 64 product;
+// operands sit in LDS transposed (element [t][r]) so the inner loops read
+// consecutive words.
+__global__ void __launch_bounds__(CT)
+    chol_step_kernel(int m, int p, double* __restrict__ A, double* __restrict__ b,
+                     double* __restrict__ y, double* __restrict__ Linv, int* __restrict__ ok) {
+  if (*ok == 0) return;
   extern __shared__ double lds[];
-  double(*LiT)[CBP] = reinterpret_cast<double(*)[CBP]>(lds);
-  double(*LjT)[CBP] = reinterpret_cast<double(*)[CBP]>(lds + CB * CBP);
-  // blockIdx.x -> (ii, jj) with 0 <= jj <= ii over the trailing blocks
+  double(*S0)[CBP] = reinterpret_cast<double(*)[CBP]>(lds);
+  double(*S1)[CBP] = reinterpret_cast<double(*)[CBP]>(lds + CB * CBP);
+  double(*S2)[CBP] = reinterpret_cast<double(*)[CBP]>(lds + 2 * CB * CBP);
+  double* bv = lds + 3 * CB * CBP;
+  double* yv = bv + CB;
   int ii = 0, rem = blockIdx.x;
   while (rem > ii) {
     rem -= ii + 1;
     ++ii;
   }
   const int jj = rem;
-  const int i0 = (p + 1 + ii) * CB, j0 = (p + 1 + jj) * CB, c0 = p * CB;
-  const int ni = min(CB, m - i0), nj = min(CB, m - j0), nc = min(CB, m - c0);
-  for (int e = threadIdx.x; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    LiT[c][r] = (r < ni && c < nc) ? A[(int64_t)(i0 + r) * m + c0 + c] : 0.0;
-    LjT[c][r] = (r < nj && c < nc) ? A[(int64_t)(j0 + r) * m + c0 + c] : 0.0;
+  const bool dg = ii == jj;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int c0 = p * CB, i0 = c0 + (1 + ii) * CB, j0 = c0 + (1 + jj) * CB;
+  const int ni = min(CB, m - i0), nj = min(CB, m - j0);
+  const double* Lp = Linv + (int64_t)p * CB * CB;
+  // S0[t][c] = Linv_p[c][t], S1[t][r] = A_ip[r][t], S2[t][r] = A_jp[r][t]
+  for (int e = tid; e < CB * CB; e += CT) {
+    const int r = e >> 6, c = e & (CB - 1);
+    S0[c][r] = Lp[e];
+    S1[c][r] = r < ni ? A[(int64_t)(i0 + r) * m + c0 + c] : 0.0;
+    if (!dg) S2[c][r] = r < nj ? A[(int64_t)(j0 + r) * m + c0 + c] : 0.0;
   }
+  if (dg && tid < CB) bv[tid] = b[c0 + tid];
   __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4] = {};
+  // L_ip = A_ip Linv_p^T (and L_jp), and y_p = Linv_p b_p
+  double li[4][4] = {}, lj[4][4] = {};
   for (int t = 0; t < CB; ++t) {
-    double a[4], bb[4];
+    double a[4], g[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      a[q] = LiT[t][ty + 16 * q];
-      bb[q] = LjT[t][tx + 16 * q];
+      a[q] = S1[t][ty + 16 * q];
+      g[q] = S0[t][tx + 16 * q];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int w = 0; w < 4; ++w) acc[q][w] = __builtin_fma(a[q], bb[w], acc[q][w]);
+      for (int w = 0; w < 4; ++w) li[q][w] = __builtin_fma(a[q], g[w], li[q][w]);
+    if (!dg) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = S2[t][ty + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) lj[q][w] = __builtin_fma(a[q], g[w], lj[q][w]);
+    }
   }
+  if (dg && tid < CB) {
+    double v = 0.0;
+    for (int t = 0; t <= tid; ++t) v = __builtin_fma(S0[t][tid], bv[t], v);
+    yv[tid] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      S1[tx + 16 * w][ty + 16 * q] = li[q][w];
+      if (!dg) S2[tx + 16 * w][ty + 16 * q] = lj[q][w];
+    }
+  __syncthreads();
+  double(*LjT)[CBP] = dg ? S1 : S2;
+  double acc[4][4] = {};
+  for (int t = 0; t < CB; ++t) {
+    double a[4], g[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = S1[t][ty + 16 * q];
+      g[q] = LjT[t][tx + 16 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[q][w] = __builtin_fma(a[q], g[w], acc[q][w]);
+  }
+  const bool fac = dg && ii == 0;
+  if (dg) {
+    // upper block (p, i) = L_ip^T, and b_i -= L_ip y_p
+    for (int e = tid; e < CB * CB; e += CT) {
+      const int t = e >> 6, r = e & (CB - 1);
+      if (r < ni) A[(int64_t)(c0 + t) * m + i0 + r] = S1[t][r];
+    }
+    if (tid < CB) {
+      double v = 0.0;
+      if (tid < ni) {
+        for (int t = 0; t < CB; ++t) v = __builtin_fma(S1[t][tid], yv[t], v);
+        v = b[i0 + tid] - v;
+        b[i0 + tid] = v;
+      }
+      if (ii == 0) y[c0 + tid] = yv[tid];
+      if (fac) bv[tid] = v;  // b_{p+1} is final now
+    }
+  }
+  if (!fac) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int r = ty + 16 * q, c = tx + 16 * w;
+        if (r < ni && c < nj && (!dg || c <= r)) A[(int64_t)(i0 + r) * m + j0 + c] -= acc[q][w];
+      }
+    return;
+  }
+  // block (p+1, p+1) has received its last update: factor it
+  __syncthreads();
+  double tt[4][4];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       const int r = ty + 16 * q, c = tx + 16 * w;
-      if (r < ni && c < nj && (ii != jj || c <= r)) A[(int64_t)(i0 + r) * m + j0 + c] -= acc[q][w];
+      tt[q][w] = (r < ni && c < ni) ? A[(int64_t)(i0 + r) * m + i0 + c] - acc[q][w]
+                                    : (r == c ? 1.0 : 0.0);
     }
+  finish_diag(tt, S1, S2[0], bv, ni, i0, i0 + CB >= m, m, A, Linv + (int64_t)(p + 1) * CB * CB, y,
+              ok);
 }
 
-// L L^T x = b by blocks of 64 in one workgroup; x scattered to d[idx].
-__global__ void __launch_bounds__(1024)
-    chol_solve_kernel(int m, const double* __restrict__ A, double* __restrict__ b,
-                      const int* __restrict__ idx, double* __restrict__ d,
-                      const int* __restrict__ ok) {
+// After the factorisation the off-diagonal blocks of L sit transposed in the
+// upper triangle; this copies each one, upper block (p, i) = L_ip^T, back to
+// the lower block (i, p) through an LDS tile, so that the backward
+// substitution reads L by rows. One workgroup per block, (i, p) enumerated
+// row by row.
+__global__ void __launch_bounds__(CT)
+    chol_mirror_kernel(int m, double* __restrict__ A, const int* __restrict__ ok) {
   if (*ok == 0) return;
-  __shared__ double y[CB];
-  const int tid = threadIdx.x;
-  const int T = (m + CB - 1) / CB;
-  // forward: L y = b
-  for (int bp = 0; bp < T; ++bp) {
-    const int r0 = bp * CB, nb = min(CB, m - r0);
-    if (tid < 64) {
-      double v = tid < nb ? b[r0 + tid] : 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double yc = __shfl(v, c, 64) / A[(int64_t)(r0 + c) * m + r0 + c];
-        if (tid == c) v = yc;
-        if (tid > c && tid < nb) v -= A[(int64_t)(r0 + tid) * m + r0 + c] * yc;
-      }
-      if (tid < nb) {
-        y[tid] = v;
-        b[r0 + tid] = v;
-      }
-    }
-    __syncthreads();
-    for (int i = r0 + nb + tid; i < m; i += 1024) {
-      double v = b[i];
-      const double* Li = A + (int64_t)i * m + r0;
-      for (int c = 0; c < nb; ++c) v -= Li[c] * y[c];
-      b[i] = v;
-    }
-    __syncthreads();
+  __shared__ double tile[CB][CBP];
+  int ii = 1, rem = blockIdx.x;
+  while (rem >= ii) {
+    rem -= ii;
+    ++ii;
   }
-  // backward: L^T x = y
+  const int i0 = ii * CB, p0 = rem * CB;
+  const int ni = min(CB, m - i0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += CT) {
+    const int t = e >> 6, r = e & (CB - 1);
+    if (r < ni) tile[t][r] = A[(int64_t)(p0 + t) * m + i0 + r];
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += CT) {
+    const int r = e >> 6, t = e & (CB - 1);
+    if (r < ni) A[(int64_t)(i0 + r) * m + p0 + t] = tile[t][r];
+  }
+}
+
+// L^T x = y in one workgroup, block by block from the last: x_p = L_pp^{-T} z_p
+// (L_pp^{-1} staged in LDS, the 64 x 64 product split over all threads), then
+// z_i -= sum_c L[r0 + c][i] x_c for every row i above the block: thread i
+// reads column i of the block's rows of L, so the loads of a wave are
+// consecutive and each thread has its 64 loads in flight together. z starts
+// as y and ends as x, which is scattered to d[idx].
+constexpr int BT = 512;  // threads of the backward substitution (8 waves)
+constexpr int BW = BT / 64;
+
+__global__ void __launch_bounds__(BT)
+    chol_back_kernel(int m, const double* __restrict__ A, const double* __restrict__ y,
+                     const double* __restrict__ Linv, double* __restrict__ z,
+                     const int* __restrict__ idx, double* __restrict__ d,
+                     const int* __restrict__ ok) {
+  if (*ok == 0) return;
+  __shared__ double Lt[CB][CBP];
+  __shared__ double part[BW][CB];
+  __shared__ double zb[CB];
+  __shared__ double xs[CB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int T = (m + CB - 1) / CB;
+  for (int i = tid; i < m; i += BT) z[i] = y[i];
+  __syncthreads();
   for (int bp = T - 1; bp >= 0; --bp) {
     const int r0 = bp * CB, nb = min(CB, m - r0);
-    if (tid < 64) {
-      double v = tid < nb ? b[r0 + tid] : 0.0;
-      for (int c = nb - 1; c >= 0; --c) {
-        const double xc = __shfl(v, c, 64) / A[(int64_t)(r0 + c) * m + r0 + c];
-        if (tid == c) v = xc;
-        if (tid < c) v -= A[(int64_t)(r0 + c) * m + r0 + tid] * xc;
-      }
-      if (tid < nb) {
-        y[tid] = v;
-        b[r0 + tid] = v;
-      }
+    const double* Lb = Linv + (int64_t)bp * CB * CB;
+    for (int e = tid; e < CB * CB; e += BT) Lt[e >> 6][e & (CB - 1)] = Lb[e];
+    if (tid < CB) zb[tid] = tid < nb ? z[r0 + tid] : 0.0;
+    __syncthreads();
+    {
+      // x_c = sum_t Linv[t][c] z_t; wave g takes 8 consecutive t
+      constexpr int TG = CB / BW;
+      double v = 0.0;
+#pragma unroll
+      for (int t = TG * wv; t < TG * wv + TG; ++t) v = __builtin_fma(Lt[t][lane], zb[t], v);
+      part[wv][lane] = v;
     }
     __syncthreads();
-    for (int i = tid; i < r0; i += 1024) {
-      double v = b[i];
-      for (int c = 0; c < nb; ++c) v -= A[(int64_t)(r0 + c) * m + i] * y[c];
-      b[i] = v;
+    if (tid < CB) {
+      double v = 0.0;
+#pragma unroll
+      for (int g = 0; g < BW; ++g) v += part[g][tid];
+      xs[tid] = v;
+      if (tid < nb) z[r0 + tid] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < r0; i += BT) {
+      const double* col = A + (int64_t)r0 * m + i;
+      double v = 0.0;
+      if (nb == CB) {
+#pragma unroll
+        for (int h = 0; h < CB; h += 32) {
+          double a[32];
+#pragma unroll
+          for (int c = 0; c < 32; ++c) a[c] = col[(int64_t)(h + c) * m];
+#pragma unroll
+          for (int c = 0; c < 32; ++c) v = __builtin_fma(a[c], xs[h + c], v);
+        }
+      } else {
+        for (int c = 0; c < nb; ++c) v = __builtin_fma(col[(int64_t)c * m], xs[c], v);
+      }
+      z[i] -= v;
     }
     __syncthreads();
   }
-  for (int a = tid; a < m; a += 1024) d[idx[a]] = b[a];
+  for (int a = tid; a < m; a += BT) d[idx[a]] = z[a];
 }
 
 __global__ void set_ok_kernel(int* ok) { *ok = 1; }
 
+size_t newton_ws_doubles(int K) {
+  return (size_t)K * K + 3 * (size_t)K + (size_t)((K + CB - 1) / CB) * CB * CB;
+}
+
 hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
                                            const double* H, const double* S, double* A,
                                            const int* idx, double* d, int* ok) {
+  if (m <= 0 || m >= K) return hipErrorInvalidValue;
   double* b = A + (int64_t)m * m;
+  double* y = b + m;
+  double* Linv = y + m;
   const int64_t tot = std::max<int64_t>((int64_t)m * m, K);
   hipLaunchKernelGGL(reduced_gather_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                      K, m, idx, H, S, Nk, A, b, d);
   hipLaunchKernelGGL(set_ok_kernel, dim3(1), dim3(1), 0, s, ok);
-  const int T = (m + CB - 1) / CB;
-  const size_t upd_lds = sizeof(double) * 2 * CB * CBP;
-  static const bool attr = [] {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_update_kernel),
+  const size_t step_lds = sizeof(double) * (3 * CB * CBP + 2 * CB);
+  static const bool attr = [&] {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_step_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(sizeof(double) * 2 * CB * CBP)) != hipSuccess)
+                            (int)step_lds) != hipSuccess)
       (void)hipGetLastError();  // clear; a launch that still fails reports it
     return true;
   }();
   (void)attr;
-  for (int p = 0; p < T; ++p) {
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, m, p, A, ok);
+  hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(CT), 0, s, m, A, b, y, Linv, ok);
+  const int T = (m + CB - 1) / CB;
+  for (int p = 0; p + 1 < T; ++p) {
     const int rest = T - p - 1;
-    if (rest > 0) {
-      hipLaunchKernelGGL(chol_trsm_kernel, dim3(rest), dim3(CB), 0, s, m, p, A);
-      hipLaunchKernelGGL(chol_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), upd_lds, s,
-                         m, p, A);
-    }
+    hipLaunchKernelGGL(chol_step_kernel, dim3(rest * (rest + 1) / 2), dim3(CT), step_lds, s, m, p,
+                       A, b, y, Linv, ok);
   }
-  hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), 0, s, m, A, b, idx, d, ok);
+  if (T > 1)
+    hipLaunchKernelGGL(chol_mirror_kernel, dim3(T * (T - 1) / 2), dim3(CT), 0, s, m, A, ok);
+  hipLaunchKernelGGL(chol_back_kernel, dim3(1), dim3(BT), 0, s, m, A, y, Linv, b, idx, d, ok);
   return hipGetLastError();
 }
 

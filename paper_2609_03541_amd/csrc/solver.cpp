@@ -69,7 +69,7 @@ void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
   misc = ar.take<double>(8);
   ok = ar.take<int>(4);
   idx = ar.take<int>(K);
-  A = ar.take<double>((size_t)K * K + 3 * (size_t)K);
+  A = ar.take<double>(newton_ws_doubles(K));
   H = ar.take<double>((size_t)K * K);
   hess_parts = ar.take<double>(hessian_partial_count(K, N, num_cus, &hess_chunks));
   dk = ar.take<double>(K);

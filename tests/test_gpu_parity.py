@@ -141,17 +141,24 @@ def test_plain_solve_matches_oracle(bm, cfg):
     assert info["grad_norm"] < 1e-6
 
 
-@pytest.mark.parametrize("K,Nk,prec", [(140, 40, 0), (300, 30, 0), (300, 30, 1)])
+@pytest.mark.parametrize("K,Nk,prec", [(140, 40, 0), (300, 30, 0), (300, 30, 1), (400, 20, 0),
+                                        (700, 12, 1)])
 def test_solve_large_reduced_system(bm, K, Nk, prec):
     # reduced Newton systems above the LDS solve's size use the blocked
-    # Cholesky path (m = K - 1 > 136; m = 139 leaves a ragged last block)
+    # Cholesky path (m = K - 1 > 136): m = 139, 299, 399, 699 give 3 to 11
+    # blocks of 64, each with a ragged last block
     say(f"large-K solve K={K} Nk={Nk} precision={prec}")
     p = synth.harmonic_1d(K=K, Nk=Nk, seed=K)
     f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
     f, info = bm.solve(dev(p["u"]), p["Nk"], tol=1e-12, precision=prec)
+    say("finisher steps", info["finisher_steps"], "fallbacks", info["sci_fallbacks"],
+        "hessians", info["hessians"])
     assert info["status"] == 0
     assert info["hessians"] >= 1
     assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+    if prec == 0:
+        # an FP64 Newton direction that is wrong shows up as SCI fallbacks
+        assert info["sci_fallbacks"] == 0
 
 
 @pytest.mark.parametrize("d", [1, 2])
