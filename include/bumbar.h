@@ -107,6 +107,10 @@ typedef struct {
   double mixed_tol;    /* PREC_MIXED: Newton on the FP32 matrix until max |delta f| <
                           mixed_tol, then FP64 refinement to tol (default 1e-6)          */
   int represent;       /* bin representatives (BUMBAR_REPRESENT_*); default AUTO         */
+  int graphs;          /* 1 (default): each batch of binned SCI steps queued between two
+                          readbacks is captured once as a HIP graph (per batch shape and
+                          level) and replayed for every later batch of that shape; 0: the
+                          kernels are launched one by one. Same results to the bit.     */
 } bumbar_options;
 
 typedef struct {
@@ -128,6 +132,7 @@ typedef struct {
   int64_t sweep_kernel_launches; /* profile = 1: number of timed sweep kernel launches   */
   bumbar_check* checks;     /* host, caller-owned, may be NULL: schedule of phase 2     */
   int checks_capacity;      /* entries available in checks                              */
+  int64_t graph_batches;    /* batches of binned steps launched as HIP graphs            */
 } bumbar_stats;
 
 /* ---- context ---------------------------------------------------------- */

@@ -51,7 +51,7 @@ class Options(C.Structure):
                 ("max_newton", C.c_int), ("sci_switch", C.c_double),
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
                 ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
-                ("represent", C.c_int)]
+                ("represent", C.c_int), ("graphs", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -64,7 +64,7 @@ class Stats(C.Structure):
                 ("time_binning_ms", C.c_double), ("time_binned_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
-                ("checks_capacity", C.c_int)]
+                ("checks_capacity", C.c_int), ("graph_batches", C.c_int64)]
 
 
 class ServerOptions(C.Structure):

@@ -23,8 +23,12 @@ namespace bumbar {
 
 constexpr int kCountSlots = 8192;
 
+int64_t otf_ubar_cap(int K, int64_t N) {
+  return sweep_fast_supported(K) ? std::min<int64_t>(N, 65536) : 0;
+}
+
 void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,
-                       bool cen_bufs, bool cen_f32) {
+                       bool cen_bufs, bool cen_f32, int64_t otf_cap) {
   (void)num_cus;
   otf = cen_bufs && !ubar_bufs;
   d = d_;
@@ -48,18 +52,22 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
   for (int i = 0; i < 2; ++i) {
     if (cen_bufs) cen[i] = ar.take<double>((size_t)N * d);
     if (cen_bufs && cen_f32) cenf[i] = ar.take<float>((size_t)N * d);
-    if (ubar_bufs) ubar[i] = ar.take<double>((size_t)K * N);
+    if (ubar_bufs)
+      ubar[i] = ar.take<double>((size_t)K * N);
+    else if (otf_cap > 0)
+      ubar[i] = ar.take<double>((size_t)K * otf_cap);
     h[i] = ar.take<double>(N);
   }
+  ubar_cap = ubar_bufs ? N : otf_cap;
   logD_lvl = ar.take<double>(N);
   f_n = ar.take<double>(K);
   f_x = ar.take<double>(K);
 }
 
 void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
-                       bool cen_bufs, bool cen_f32) {
+                       bool cen_bufs, bool cen_f32, int64_t otf_cap) {
   BinnedBufs b;
-  b.carve(ar, K, N, d, num_cus, ubar_bufs, cen_bufs, cen_f32);
+  b.carve(ar, K, N, d, num_cus, ubar_bufs, cen_bufs, cen_f32, otf_cap);
 }
 
 static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
@@ -207,6 +215,93 @@ static int histogram(bumbar_ctx* ctx, BinnedBufs& BB, uint64_t m, int64_t* P) {
   return read_bytes(ctx, BB.counts, P, sizeof(int64_t));
 }
 
+// Batches of binned SCI steps as HIP graphs. A batch (the steps queued
+// between two readbacks) is fixed by its kind, its length and the levels it
+// runs on, since all of its buffers are the stage's own; the first batch of
+// each shape is captured on the context's capture stream (nothing runs
+// there) and that batch and every later one of the shape launch the graph on
+// the working stream. A batch is 40 to 150 kernel launches, so this replaces
+// as many host launches by one. The graphs hold kernel launches only. If
+// capture or instantiation fails, the batch and the rest of the stage are
+// launched kernel by kernel.
+struct BatchKey {
+  int kind;
+  int64_t T;
+  const void* a;
+  int64_t pa;
+  const void* b;
+  int64_t pb;
+  bool operator==(const BatchKey& o) const {
+    return kind == o.kind && T == o.T && a == o.a && pa == o.pa && b == o.b && pb == o.pb;
+  }
+};
+
+class BatchGraphs {
+ public:
+  BatchGraphs(bumbar_ctx* ctx, bool on) : ctx_(ctx), on_(on) {}
+  ~BatchGraphs() {
+    for (auto& x : execs_) (void)hipGraphExecDestroy(x.second);
+  }
+  BatchGraphs(const BatchGraphs&) = delete;
+  BatchGraphs& operator=(const BatchGraphs&) = delete;
+
+  // enqueue(): queues the batch on ctx->stream, returns a BUMBAR_* code
+  template <class F>
+  int run(const BatchKey& k, F&& enqueue) {
+    if (!on_) return enqueue();
+    for (auto& x : execs_)
+      if (x.first == k) return launch(x.second);
+    if (!ctx_->cap_stream &&
+        hipStreamCreateWithFlags(&ctx_->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx_->cap_stream = nullptr;
+      on_ = false;
+      return enqueue();
+    }
+    if (hipStreamBeginCapture(ctx_->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      on_ = false;
+      return enqueue();
+    }
+    hipStream_t work = ctx_->stream;
+    ctx_->stream = ctx_->cap_stream;
+    const int rc = enqueue();
+    ctx_->stream = work;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx_->cap_stream, &g);
+    hipGraphExec_t x = nullptr;
+    if (rc == BUMBAR_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != BUMBAR_OK) return rc;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      on_ = false;
+      return enqueue();
+    }
+    execs_.emplace_back(k, x);
+    return launch(x);
+  }
+  int64_t launched() const { return launched_; }
+
+ private:
+  int launch(hipGraphExec_t x) {
+    const hipError_t e = hipGraphLaunch(x, ctx_->stream);
+    if (e != hipSuccess) return hip_fail(ctx_, e, "graph launch");
+    ++launched_;
+    return BUMBAR_OK;
+  }
+  bumbar_ctx* ctx_;
+  bool on_;
+  int64_t launched_ = 0;
+  std::vector<std::pair<BatchKey, hipGraphExec_t>> execs_;
+};
+
+// Identity of a level's matrix for BatchKey: its representatives or centres
+// (the buffers of its slot) and its bin count.
+static const void* level_id(const Level& L) {
+  return L.ubar ? static_cast<const void*>(L.ubar) : static_cast<const void*>(L.cen);
+}
+
 static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int model,
                        const double* coef, const double* u, int slot, Level* L) {
   uint64_t m = 0;
@@ -227,11 +322,17 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
                          BB.cells, BB.start, BB.perm, u, BB.ubar[slot], BB.h[slot]);
   if (e == hipSuccess && BB.otf && BB.cenf[slot])
     e = launch_pack_coords(ctx->stream, P * BB.d, BB.cen[slot], BB.cenf[slot]);
+  // a small on-the-fly level: the centre representatives once, then the
+  // steps of the level are one-pass sweeps over them
+  const bool mat = BB.otf && BB.ubar[slot] && P <= BB.ubar_cap;
+  if (e == hipSuccess && mat)
+    e = launch_represent(ctx->stream, K, BB.N, BB.d, model, coef, BB.lo, BB.scale, m, P, BB.cells,
+                         BB.start, BB.perm, nullptr, BB.ubar[slot], BB.h[slot]);
   if (e != hipSuccess) return hip_fail(ctx, e, "represent");
   L->n = n;
   L->m = m;
   L->P = P;
-  L->ubar = BB.otf ? nullptr : BB.ubar[slot];
+  L->ubar = (!BB.otf || mat) ? BB.ubar[slot] : nullptr;
   L->cen = BB.otf ? BB.cen[slot] : nullptr;
   L->cenf = BB.otf ? BB.cenf[slot] : nullptr;
   L->h = BB.h[slot];
@@ -242,7 +343,7 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
 // the bin centres when the stage runs on the fly (FP32 when the level has
 // FP32 centres and fp32 is asked for, else FP64).
 static Mat level_mat_of(const Level& L, const Mat* otf_base, bool fp32) {
-  if (otf_base) {
+  if (otf_base && !(L.ubar && !(fp32 && L.cenf))) {
     Mat M = *otf_base;
     M.kind = (fp32 && L.cenf) ? 3 : 4;
     M.otf.xi = L.cen;
@@ -312,6 +413,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   };
   int64_t it1 = 0, it2 = 0, nchk = 0;
   int result = BUMBAR_OK;
+  BatchGraphs graphs(ctx, opt.graphs != 0);
   // ---- phase 1: iterate at n0 until the relative step is below eps ----
   for (bool done = false; !done;) {
     if (it1 + it2 >= opt.max_iter) {
@@ -322,12 +424,17 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     if (opt.replay_refine) T = std::min<int64_t>(T, std::max<int64_t>(1, opt.replay_phase1 - it1));
     int nvalid = 0;  // leading steps that are usable
     if (fast) {
-      for (int i = 0; i < T; ++i) {
-        // each step's finaliser leaves the constants of the next step in B.cst
-        rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, i == 0 ? BB.f_n : fh(i - 1),
-                         fh(i), BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + i, i > 0, B.cst);
-        if (rc) return rc;
-      }
+      rc = graphs.run({1, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+        for (int i = 0; i < T; ++i) {
+          // each step's finaliser leaves the constants of the next step in B.cst
+          const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
+                                    i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
+                                    B.S_t, B.scal_hist + i, i > 0, B.cst);
+          if (r) return r;
+        }
+        return BUMBAR_OK;
+      });
+      if (rc) return rc;
       rc = read_hist((int)T);
       if (rc) return rc;
       while (nvalid < T && !flagged(hs[nvalid])) ++nvalid;
@@ -371,16 +478,20 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       bool fallback = false;
       while (!fallback && nint - done_int > kHistSteps - 2) {
         const int T = kHistSteps - 2;
-        for (int i = 0; i < T && fast; ++i) {
-          rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
-                           i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
-                           B.scal_hist + i, i > 0, B.cst);
-          if (rc) return rc;
-        }
         if (!fast) {
           fallback = true;
           break;
         }
+        rc = graphs.run({2, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+          for (int i = 0; i < T; ++i) {
+            const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
+                                      i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
+                                      B.S_t, B.scal_hist + i, i > 0, B.cst);
+            if (r) return r;
+          }
+          return BUMBAR_OK;
+        });
+        if (rc) return rc;
         rc = read_hist(T);
         if (rc) return rc;
         for (int i = 0; i < T; ++i) fallback = fallback || flagged(hs[i]);
@@ -393,22 +504,25 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
       int in = 0, ix = 0;
       if (!fallback && fast) {
         const int T = nint - done_int;
-        for (int i = 0; i < T; ++i) {
-          rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
-                           i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t, B.S_t,
-                           B.scal_hist + i, i > 0, B.cst);
-          if (rc) return rc;
-        }
-        const double* fin = T == 0 ? BB.f_n : fh(T - 1);
         in = T;
         ix = T + 1;
-        // both probes start from fin: the first reuses the constants the last
-        // intermediate step left (if any), the second those of the first
-        rc = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, fin, fh(in), BB.logD_lvl,
-                         B.lnS_t, B.S_t, B.scal_hist + in, T > 0, nullptr);
-        if (rc) return rc;
-        rc = sweep_queue(ctx, B, level_mat(nxt), nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
-                         B.lnS_t, B.S_t, B.scal_hist + ix, true, nullptr);
+        rc = graphs.run({3, T, level_id(cur), cur.P, level_id(nxt), nxt.P}, [&]() -> int {
+          for (int i = 0; i < T; ++i) {
+            const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
+                                      i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
+                                      B.S_t, B.scal_hist + i, i > 0, B.cst);
+            if (r) return r;
+          }
+          const double* fin = T == 0 ? BB.f_n : fh(T - 1);
+          // both probes start from fin: the first reuses the constants the last
+          // intermediate step left (if any), the second those of the first
+          int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev, fin, fh(in),
+                              BB.logD_lvl, B.lnS_t, B.S_t, B.scal_hist + in, T > 0, nullptr);
+          if (r) return r;
+          r = sweep_queue(ctx, B, level_mat(nxt), nxt.P, nxt.h, Nk_dev, fin, fh(ix), BB.logD_lvl,
+                          B.lnS_t, B.S_t, B.scal_hist + ix, true, nullptr);
+          return r;
+        });
         if (rc) return rc;
         rc = read_hist(T + 2);
         if (rc) return rc;
@@ -472,6 +586,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   st->phase1_iters = it1;
   st->phase2_iters = it2;
   st->n_checks = nchk;
+  st->graph_batches += graphs.launched();
   st->time_binning_ms = t_bin;
   st->time_binned_ms = now_ms() - t_start - t_bin;
   return result;

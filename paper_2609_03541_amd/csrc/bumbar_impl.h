@@ -187,4 +187,7 @@ struct bumbar_ctx {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
+  // private stream on which batches of binned steps are captured as graphs
+  // (created on first use; nothing executes on it)
+  hipStream_t cap_stream = nullptr;
 };

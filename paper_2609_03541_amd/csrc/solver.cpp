@@ -459,6 +459,7 @@ void bumbar_destroy(bumbar_ctx* ctx) {
     (void)hipEventDestroy(p.second);
   }
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -484,6 +485,7 @@ void bumbar_default_options(bumbar_options* o) {
   o->profile = 0;
   o->mixed_tol = 1e-6;
   o->represent = BUMBAR_REPRESENT_AUTO;
+  o->graphs = 1;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
@@ -735,7 +737,7 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
   B.carve(ar, K, N, ctx->num_cus);
   if (opt == nullptr || opt->binning)
     binned_carve_size(ar, K, N, d, ctx->num_cus, false, true,
-                      opt && opt->precision == BUMBAR_PREC_MIXED && K > 256);
+                      opt && opt->precision == BUMBAR_PREC_MIXED && K > 256, otf_ubar_cap(K, N));
   OtfBufs O;
   O.carve(ar, K, N, d);
   *bytes = ar.off + 256;
@@ -800,7 +802,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (opt.binning) {
     // on the fly in mixed precision: FP32 centres for the binned steps
     if (otf)
-      BB.carve(ar, K, N, d, ctx->num_cus, false, true, mixed && K > 256);
+      BB.carve(ar, K, N, d, ctx->num_cus, false, true, mixed && K > 256, otf_ubar_cap(K, N));
     else
       BB.carve(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(opt.represent, K),
                centre_bufs(opt.represent, K));

@@ -130,21 +130,30 @@ struct BinnedBufs {
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   bool otf = false;                      // representatives from the model in the kernels
-  double* ubar[2] = {nullptr, nullptr};  // K x N each (worst case P = N); stored mode
+  // K x N each (worst case P = N) in stored mode; on the fly, K x ubar_cap
+  // each: levels with P <= ubar_cap get their centre representatives
+  // materialised (one model evaluation per level) and step like stored ones
+  double* ubar[2] = {nullptr, nullptr};
+  int64_t ubar_cap = 0;
   double* cen[2] = {nullptr, nullptr};   // N x d each (worst case P = N); otf mode
   float* cenf[2] = {nullptr, nullptr};   // FP32 copies of cen (mixed precision)
   double* h[2] = {nullptr, nullptr};     // N each
   double* logD_lvl = nullptr;            // N
   double *f_n = nullptr, *f_x = nullptr; // K
   // ubar_bufs: K x N representative buffers (MEAN); cen_bufs: N x d centres
-  // (CENTRE), cen_f32 also their FP32 copies. otf is set by the caller to the
-  // representative in use.
+  // (CENTRE), cen_f32 also their FP32 copies; otf_cap > 0: K x otf_cap
+  // representative buffers for the small levels of an on-the-fly stage. otf
+  // is set by the caller to the representative in use.
   void carve(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs, bool cen_bufs,
-             bool cen_f32 = false);
+             bool cen_f32 = false, int64_t otf_cap = 0);
 };
 
 void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool ubar_bufs,
-                       bool cen_bufs, bool cen_f32 = false);
+                       bool cen_bufs, bool cen_f32 = false, int64_t otf_cap = 0);
+
+// On the fly with K states: the largest level (in bins) whose centre
+// representatives are materialised, or 0 (K beyond the register-tiled sweep).
+int64_t otf_ubar_cap(int K, int64_t N);
 
 // otf_base: nullptr for stored representatives, else the FP64 model matrix
 // (kind 4) whose coordinates the stage replaces by the bin centres. With
