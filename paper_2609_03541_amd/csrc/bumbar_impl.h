@@ -76,9 +76,11 @@ hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t l
                                double* logD, double* partM, double* partS, double* part_obj,
                                unsigned* part_flags, int chunks);
 
-// Finaliser. mode 0: partials are S' sums (fast path); mode 1: (M, S) pairs.
+// Finaliser. mode 0: partials are S' sums (fast path), partS a scratch of K
+// doubles for their per-state sums (or null); mode 1: (M, S) pairs in
+// (part, partS).
 hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, const double* part,
-                                 const double* partS, const double* part_obj,
+                                 double* partS, const double* part_obj,
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
                                  SweepScalars* out, double* cst_next = nullptr);

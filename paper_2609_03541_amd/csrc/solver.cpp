@@ -159,7 +159,7 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
   }
   if (ev) (void)hipEventRecord(ev->second, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep");
-  e = launch_sweep_finalize(s, 0, K, grid, B.part, nullptr, B.part_obj, B.part_flags, f, B.lnNp,
+  e = launch_sweep_finalize(s, 0, K, grid, B.part, B.partS, B.part_obj, B.part_flags, f, B.lnNp,
                             Nk, f_out, lnS_out, S_out, dev_scal, cst_next);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep_finalize");
   return BUMBAR_OK;

@@ -648,9 +648,37 @@ __device__ __forceinline__ Red6 block_reduce6(Red6 v, double (*sh)[6]) {
   return r;
 }
 
+// Per-state sums of many state-major partials ahead of the finaliser: one
+// wave per state, lane l adds partials l, l + 64, ... in eight chains (eight
+// loads in flight per round trip), then a fixed xor butterfly, so the order
+// of additions is fixed. S: K sums.
+__global__ void __launch_bounds__(256)
+    part_reduce_kernel(int K, int nparts, const double* __restrict__ part,
+                       double* __restrict__ S) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= K) return;
+  const double* pk = part + (int64_t)k * nparts;
+  double s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = 0.0;
+  int p = lane;
+  for (; p + 7 * 64 < nparts; p += 8 * 64) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += pk[p + 64 * j];
+  }
+  for (; p < nparts; p += 64) s[0] += pk[p];
+  double v = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) S[k] = v;
+}
+
+// nstate: partials per state in part (mode 0: nparts, or 1 after
+// part_reduce_kernel); nparts: entries of part_obj and part_flags.
 template <int FT>
 __global__ void __launch_bounds__(FT)
-    sweep_finalize_kernel(int mode, int K, int nparts, const double* __restrict__ part,
+    sweep_finalize_kernel(int mode, int K, int nstate, int nparts, const double* __restrict__ part,
                           const double* __restrict__ partS, const double* __restrict__ part_obj,
                           const unsigned* __restrict__ part_flags, const double* __restrict__ f,
                           const double* __restrict__ lnNp, const int64_t* __restrict__ Nk,
@@ -670,7 +698,7 @@ __global__ void __launch_bounds__(FT)
   // lanes of one wave) each add every T-th partial, then a fixed xor
   // butterfly combines them, so the order of additions never changes.
   int T = 1;
-  if (mode == 0)
+  if (mode == 0 && nstate > 1)
     while (T < 64 && 2 * T * K <= FT) T *= 2;
   const int kstride = FT / T;
   const int kfirst = tid / T, lane_c = tid % T;
@@ -678,17 +706,17 @@ __global__ void __launch_bounds__(FT)
     const int k = k0 + kfirst;
     double Sp = 0.0;
     if (mode == 0 && k < K) {
-      // fast-path partials are state-major: part[k * nparts + p]
-      const double* pk = part + (int64_t)k * nparts;
+      // fast-path partials are state-major: part[k * nstate + p]
+      const double* pk = part + (int64_t)k * nstate;
       int p = lane_c;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (; p + 3 * T < nparts; p += 4 * T) {
+      for (; p + 3 * T < nstate; p += 4 * T) {
         s0 += pk[p];
         s1 += pk[p + T];
         s2 += pk[p + 2 * T];
         s3 += pk[p + 3 * T];
       }
-      for (; p < nparts; p += T) s0 += pk[p];
+      for (; p < nstate; p += T) s0 += pk[p];
       Sp = (s0 + s1) + (s2 + s3);
     }
     if (mode == 0)
@@ -702,7 +730,7 @@ __global__ void __launch_bounds__(FT)
       if (!(S >= 1e-290 && S <= 1e290)) fl |= FLAG_STATE;
     } else {
       double M = -INFINITY, Ssum = 0.0;
-      for (int p = 0; p < nparts; ++p) lse_merge(M, Ssum, part[(int64_t)p * K + k],
+      for (int p = 0; p < nstate; ++p) lse_merge(M, Ssum, part[(int64_t)p * K + k],
                                                  partS[(int64_t)p * K + k]);
       const double lse = M + log(Ssum);  // ln sum_n h_n exp(-u_kn - ln D_n)
       fn = -lse;
@@ -757,19 +785,29 @@ __global__ void __launch_bounds__(FT)
 }
 
 hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, const double* part,
-                                 const double* partS, const double* part_obj,
+                                 double* partS, const double* part_obj,
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
                                  SweepScalars* out, double* cst_next) {
-  // few partials: one wave-sized block; many: 1024 threads so that several
-  // lanes share each state's partials
-  if (K <= 256 && nparts <= 16)
-    hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts, part,
-                       partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out, cst_next);
-  else
-    hipLaunchKernelGGL(sweep_finalize_kernel<1024>, dim3(1), dim3(1024), 0, s, mode, K, nparts,
-                       part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out, out,
-                       cst_next);
+  // few partials: one wave-sized block; many: the per-state sums first, one
+  // wave per state over all CUs (scratch: partS, which the fast-path mode
+  // does not use otherwise), then 1024 threads for the rest
+  if (K <= 256 && nparts <= 16) {
+    hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts,
+                       nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                       out, cst_next);
+    return hipGetLastError();
+  }
+  int nstate = nparts;
+  if (mode == 0 && partS != nullptr) {
+    hipLaunchKernelGGL(part_reduce_kernel, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, K,
+                       nparts, part, partS);
+    part = partS;
+    nstate = 1;
+  }
+  hipLaunchKernelGGL(sweep_finalize_kernel<1024>, dim3(1), dim3(1024), 0, s, mode, K, nstate,
+                     nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                     out, cst_next);
   return hipGetLastError();
 }
 
