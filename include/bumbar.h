@@ -133,6 +133,8 @@ typedef struct {
   bumbar_check* checks;     /* host, caller-owned, may be NULL: schedule of phase 2     */
   int checks_capacity;      /* entries available in checks                              */
   int64_t graph_batches;    /* batches of binned steps launched as HIP graphs            */
+  int64_t grid_sweeps;      /* FP64 model sweeps done on the product-grid passes (2-D
+                               harmonic windows whose factors form a grid)              */
 } bumbar_stats;
 
 /* ---- context ---------------------------------------------------------- */

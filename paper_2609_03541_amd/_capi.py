@@ -64,7 +64,8 @@ class Stats(C.Structure):
                 ("time_binning_ms", C.c_double), ("time_binned_ms", C.c_double),
                 ("time_final_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
-                ("checks_capacity", C.c_int), ("graph_batches", C.c_int64)]
+                ("checks_capacity", C.c_int), ("graph_batches", C.c_int64),
+                ("grid_sweeps", C.c_int64)]
 
 
 class ServerOptions(C.Structure):

@@ -104,6 +104,25 @@ hipError_t launch_check_finite_f(hipStream_t s, int K, const double* f, unsigned
 
 // ---- Hessian and linear algebra (hessian.hip, linalg.hip) ----------------
 size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out);
+// Windows on a product grid (2-D harmonic): state k takes x-factor ix[k] and
+// y-factor jy[k] among Ix and Jy distinct (kappa/2, centre) pairs, so the
+// FP64 sweeps factor (sweep_otf.hip). Device arrays; cells c = i * Jy + j
+// list their states in cstates[cstart[c] .. cstart[c + 1]).
+constexpr int kSepMax = 64;  // factors per axis
+struct SepGrid {
+  int Ix = 0, Jy = 0, JM = 0;     // JM: Jy rounded up to a multiple of 8
+  const double* fx = nullptr;     // kSepMax x 2: kappa_x / 2, centre x
+  const double* fy = nullptr;     // kSepMax x 2
+  const int* ix = nullptr;        // K
+  const int* jy = nullptr;        // K
+  const int* cstart = nullptr;    // Ix * Jy + 1
+  const int* cstates = nullptr;   // K
+  double* C = nullptr;            // Ix x JM, per sweep
+  double* cmax = nullptr;         // 1, per sweep
+};
+size_t sep_int_count(int K);      // ints of a SepGrid's storage
+size_t sep_double_count();        // doubles of a SepGrid's storage
+
 // Reduced energies from the bias model, evaluated inside the kernels.
 struct OtfModel {
   const double* xi = nullptr;    // N x d FP64 coordinates
@@ -113,6 +132,7 @@ struct OtfModel {
   int model = 0;                 // BUMBAR_MODEL_LINEAR or BUMBAR_MODEL_HARMONIC
   float* cf32 = nullptr;         // K x (2 + 2d) per-sweep FP32 coefficients
   double* cf64 = nullptr;        // K x (2 + 2d) per-sweep FP64 coefficients
+  const SepGrid* sep = nullptr;  // host struct: product-grid factors, or null
 };
 size_t otf_coef_floats(int K, int d);  // entries of cf32 (and of cf64)
 int otf_grid(int64_t N, int num_cus);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "bumbar_impl.h"
@@ -190,7 +191,18 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
     if (rc) return rc;
     // FP32 kinds: flags are the caller's signal to leave FP32
     if (M.kind == 2 || M.kind == 3) return BUMBAR_OK;
-    if ((out->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) return BUMBAR_OK;
+    if ((out->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) {
+      if (cnt && M.kind == 4 && M.otf.sep) cnt->grid++;
+      return BUMBAR_OK;
+    }
+    if (M.kind == 4 && M.otf.sep) {
+      // the product-grid passes shift by per-axis maxima: redo the sweep
+      // with the direct passes
+      Mat M2 = M;
+      M2.otf.sep = nullptr;
+      return sweep_at(ctx, B, M2, N, h, Nk, f, f_out, logD_out, lnS_out, S_out, sc, force_robust,
+                      cnt);
+    }
     if (M.kind == 4) {
       // the model sweep keeps exact maxima per sample; there is no separate
       // robust pass for it
@@ -562,10 +574,85 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   return BUMBAR_OK;
 }
 
+// Product-grid detection for the 2-D harmonic model (host side, once per
+// call): the distinct (kappa_x / 2, x0) and (kappa_y / 2, y0) pairs of the K
+// states. The factored FP64 sweep is used when each axis has at most kSepMax
+// of them and the two together at most K / 4 (below that it saves little).
+// g receives the device arrays in O (filled here); *on says whether to use it.
+static int sep_setup(bumbar_ctx* ctx, int K, int d, int model, const double* coef,
+                     const OtfBufs& O, SepGrid* g, bool* on) {
+  *on = false;
+  if (d != 2 || model != BUMBAR_MODEL_HARMONIC || !O.sep_i || !O.sep_d || K < 16)
+    return BUMBAR_OK;
+  std::vector<double> c((size_t)K * 5);
+  hipError_t e = hipMemcpyAsync(c.data(), coef, sizeof(double) * c.size(),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read model coefficients");
+  std::map<std::pair<double, double>, int> xs, ys;
+  std::vector<int> ibuf(sep_int_count(K), 0);
+  std::vector<double> dbuf(4 * kSepMax, 0.0);
+  int* ix = ibuf.data();
+  int* jy = ix + K;
+  int* cstates = jy + K;
+  int* cstart = cstates + K;
+  for (int k = 0; k < K; ++k) {
+    const double* ck = c.data() + (size_t)k * 5;
+    for (int t = 1; t < 5; ++t)
+      if (!std::isfinite(ck[t])) return BUMBAR_OK;
+    const std::pair<double, double> px{0.5 * ck[1], ck[2]}, py{0.5 * ck[3], ck[4]};
+    auto itx = xs.find(px);
+    if (itx == xs.end()) {
+      if ((int)xs.size() == kSepMax) return BUMBAR_OK;
+      const int i = (int)xs.size();
+      dbuf[2 * i] = px.first;
+      dbuf[2 * i + 1] = px.second;
+      itx = xs.emplace(px, i).first;
+    }
+    auto ity = ys.find(py);
+    if (ity == ys.end()) {
+      if ((int)ys.size() == kSepMax) return BUMBAR_OK;
+      const int j = (int)ys.size();
+      dbuf[2 * kSepMax + 2 * j] = py.first;
+      dbuf[2 * kSepMax + 2 * j + 1] = py.second;
+      ity = ys.emplace(py, j).first;
+    }
+    ix[k] = itx->second;
+    jy[k] = ity->second;
+  }
+  const int Ix = (int)xs.size(), Jy = (int)ys.size();
+  if (4 * (Ix + Jy) > K) return BUMBAR_OK;
+  // cells c = i * Jy + j, their states in increasing k
+  for (int k = 0; k < K; ++k) ++cstart[ix[k] * Jy + jy[k] + 1];
+  for (int q = 0; q < Ix * Jy; ++q) cstart[q + 1] += cstart[q];
+  std::vector<int> cur(cstart, cstart + Ix * Jy);
+  for (int k = 0; k < K; ++k) cstates[cur[ix[k] * Jy + jy[k]]++] = k;
+  e = hipMemcpyAsync(O.sep_i, ibuf.data(), sizeof(int) * ibuf.size(), hipMemcpyHostToDevice,
+                     ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(O.sep_d, dbuf.data(), sizeof(double) * dbuf.size(),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // the host buffers end here
+  if (e != hipSuccess) return hip_fail(ctx, e, "upload product grid");
+  g->Ix = Ix;
+  g->Jy = Jy;
+  g->JM = (Jy + 7) / 8 * 8;
+  g->fx = O.sep_d;
+  g->fy = O.sep_d + 2 * kSepMax;
+  g->C = O.sep_d + 4 * kSepMax;
+  g->cmax = g->C + kSepMax * kSepMax;
+  g->ix = O.sep_i;
+  g->jy = O.sep_i + K;
+  g->cstates = O.sep_i + 2 * K;
+  g->cstart = O.sep_i + 3 * K;
+  *on = true;
+  return BUMBAR_OK;
+}
+
 // Model problem of K states over N coordinates: the on-the-fly kinds.
 static int model_setup(bumbar_ctx* ctx, int K, int64_t N, int d, int model, const double* coef,
                        const double* xi, int precision, void* workspace, size_t ws_bytes,
-                       UnbinnedBufs* B, Mat* M) {
+                       UnbinnedBufs* B, Mat* M, SepGrid* sg = nullptr) {
   int rc = check_common(ctx, coef, BUMBAR_F64, K, N, N);
   if (rc) return rc;
   if ((model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC) || !xi || d < 1 || d > 2)
@@ -590,6 +677,12 @@ static int model_setup(bumbar_ctx* ctx, int K, int64_t N, int d, int model, cons
     const hipError_t e = launch_pack_coords(ctx->stream, N * d, xi, O.xf);
     if (e != hipSuccess) return hip_fail(ctx, e, "pack coordinates");
   }
+  if (sg) {
+    bool on = false;
+    rc = sep_setup(ctx, K, d, model, coef, O, sg, &on);
+    if (rc) return rc;
+    if (on) M->otf.sep = sg;
+  }
   return BUMBAR_OK;
 }
 
@@ -599,7 +692,8 @@ int bumbar_sweep_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, cons
                        double* S, double* sweep_stats) {
   UnbinnedBufs B;
   Mat M;
-  int rc = model_setup(ctx, K, N, d, model, coef, xi, precision, workspace, ws_bytes, &B, &M);
+  SepGrid sg;
+  int rc = model_setup(ctx, K, N, d, model, coef, xi, precision, workspace, ws_bytes, &B, &M, &sg);
   if (rc) return rc;
   if (!N_k || !f || !f_new) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
   SweepScalars sc{};
@@ -823,6 +917,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->checks_capacity = chk_cap;
   hipStream_t s = ctx->stream;
   Mat M = input_mat(u_kn, u_dtype, N);
+  SepGrid sep_grid;  // product-grid factors of the model, when they apply
   hipError_t e;
   if (otf) {
     M.kind = 4;
@@ -837,6 +932,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
       e = launch_pack_coords(s, N * d, xi, O.xf);
       if (e != hipSuccess) return hip_fail(ctx, e, "pack coordinates");
     }
+    bool on = false;
+    rc = sep_setup(ctx, K, d, model, coef, O, &sep_grid, &on);
+    if (rc) return rc;
+    if (on) M.otf.sep = &sep_grid;
   }
   SweepCounters cnt;
   ctx->profiling = opt.profile != 0;
@@ -872,6 +971,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     Mc.otf.model = model;
     Mc.otf.cf32 = O.cf32;
     Mc.otf.cf64 = O.cf64;
+    Mc.otf.sep = M.otf.sep;
     // MEAN ignores a given model: the representatives are the bin means of u
     const int rep_model = rep == BUMBAR_REPRESENT_MEAN ? BUMBAR_MODEL_NONE : model;
     // On the fly in mixed precision with K > 256 (where a binned step is a
@@ -980,6 +1080,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (e != hipSuccess) return hip_fail(ctx, e, "outputs");
   st->unbinned_sweeps = cnt.fast + cnt.robust;
   st->robust_sweeps = cnt.robust;
+  st->grid_sweeps = cnt.grid;
   if (ctx->profiling) st->sweep_kernel_ms = collect_event_ms(ctx, &st->sweep_kernel_launches);
   ctx->profiling = false;
   if (stage_rc == BUMBAR_ENOTCONV || fin_rc == BUMBAR_ENOTCONV)

@@ -21,6 +21,7 @@ constexpr int kHistSteps = 32;
 struct SweepCounters {
   int64_t fast = 0;
   int64_t robust = 0;
+  int64_t grid = 0;  // FP64 model sweeps completed on the product-grid passes
 };
 
 // The matrix a sweep reads: FP64 u, FP32 u (widened to FP64 arithmetic), the
@@ -42,10 +43,16 @@ struct OtfBufs {
   float* xf = nullptr;
   float* cf32 = nullptr;
   double* cf64 = nullptr;
+  int* sep_i = nullptr;     // d = 2: product-grid maps and cells (SepGrid)
+  double* sep_d = nullptr;  // d = 2: product-grid factors, C and cmax
   void carve(Arena& ar, int K, int64_t N, int d) {
     xf = ar.take<float>((size_t)N * d);
     cf32 = ar.take<float>(otf_coef_floats(K, d));
     cf64 = ar.take<double>(otf_coef_floats(K, d));
+    if (d == 2) {
+      sep_i = ar.take<int>(sep_int_count(K));
+      sep_d = ar.take<double>(sep_double_count());
+    }
   }
 };
 

@@ -494,6 +494,266 @@ hipError_t launch_pack_coords(hipStream_t s, int64_t n, const double* xi, float*
   return hipGetLastError();
 }
 
+// ---- FP64 passes for windows on a product grid (2-D harmonic) ----------------
+// State k = (i, j): u_k(x, y) = a_k + hx_i (x - cx_i)^2 + hy_j (y - cy_j)^2, so
+// exp(c_k - u_kn) = exp(c_k - a_k) g_i(x_n) h_j(y_n). Per sample the column
+// sum is the bilinear form g^T C h with C_ij = sum over the states of cell
+// (i, j) of exp(c_k - a_k - cmax); per block the state sums are
+// exp(E_k - cmax) M_ij with M = sum_n g(n) h(n)^T w_n. The factors are shifted
+// per sample so that the largest of each is 1 (mx, my), and the shifts cancel
+// in w_n = h_n exp(cmax - mx - my - ln D_n). Every exponential and product is
+// FP64; the result differs from the direct passes by rounding only. A sample
+// whose shifted column sum falls below 1e-280 (its states all far below the
+// largest c_k - a_k) gets its ln D from the direct sum over the K states.
+
+constexpr int kST = 256;  // threads of the product-grid kernels
+
+__global__ void __launch_bounds__(256)
+    sep_prep_kernel(int K, int Ix, int Jy, int JM, const double* __restrict__ coef,
+                    const double* __restrict__ cst, const double* __restrict__ gk,
+                    const int* __restrict__ cstart, const int* __restrict__ cstates,
+                    double* __restrict__ C, double* __restrict__ cmax) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double m = -INFINITY;
+  for (int k = tid; k < K; k += 256)
+    if (gk[k] != 0.0) m = fmax(m, cst[k] - coef[(int64_t)k * 5]);
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double cm = red[0] == -INFINITY ? 0.0 : red[0];
+  for (int e = tid; e < Ix * JM; e += 256) {
+    const int i = e / JM, j = e % JM;
+    double sum = 0.0;
+    if (j < Jy) {
+      const int c = i * Jy + j;
+      for (int q = cstart[c]; q < cstart[c + 1]; ++q) {
+        const int k = cstates[q];
+        if (gk[k] != 0.0) sum += exp_nonpos(cst[k] - coef[(int64_t)k * 5] - cm);
+      }
+    }
+    C[e] = sum;
+  }
+  if (tid == 0) cmax[0] = cm;
+}
+
+// ln D at (x, y) from the K states directly (the per-sweep FP64 coefficients
+// of otf64_coef_kernel, d = 2): maximum, then the shifted sum.
+__device__ double sep_direct_logD(int K, const double* __restrict__ c64, double x, double y) {
+  double m = -INFINITY;
+  for (int k = 0; k < K; ++k) {
+    const double dx = x - c64[4 * K + k], dy = y - c64[5 * K + k];
+    const double a = c64[k] - __builtin_fma(c64[3 * K + k] * dy, dy, c64[2 * K + k] * dx * dx);
+    m = fmax(m, a);
+  }
+  if (!(m > -INFINITY)) return m;
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double dx = x - c64[4 * K + k], dy = y - c64[5 * K + k];
+    const double a = c64[k] - __builtin_fma(c64[3 * K + k] * dy, dy, c64[2 * K + k] * dx * dx);
+    s += exp_nonpos(a - m);
+  }
+  return m + log(s);
+}
+
+template <int JM>
+__global__ void __launch_bounds__(kST)
+    sep_colpass_kernel(int K, int64_t N, const double* __restrict__ xi,
+                       const double* __restrict__ c64, int Ix, int Jy,
+                       const double* __restrict__ fx, const double* __restrict__ fy,
+                       const double* __restrict__ C, const double* __restrict__ cmax,
+                       const double* __restrict__ h, double* __restrict__ logD,
+                       double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+  __shared__ double wred[kST / 64];
+  __shared__ unsigned fl;
+  if (threadIdx.x == 0) fl = 0u;
+  const double cm = cmax[0];
+  double obj = 0.0;
+  unsigned bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kST;
+  for (int64_t n = (int64_t)blockIdx.x * kST + threadIdx.x; n < N; n += stride) {
+    const double x = xi[2 * n], y = xi[2 * n + 1];
+    if ((x + y) != (x + y)) bad |= FLAG_NAN;
+    // y factors, shifted so that the largest is 1 (padding: 0)
+    double hv[JM];
+    double my = INFINITY;
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      const double dy = y - fy[2 * j + 1];
+      const double q = j < Jy ? fy[2 * j] * dy * dy : INFINITY;
+      hv[j] = q;
+      my = fmin(my, q);
+    }
+#pragma unroll
+    for (int j = 0; j < JM; ++j) hv[j] = exp_nonpos(my - hv[j]);
+    double mx = INFINITY;
+    for (int i = 0; i < Ix; ++i) {
+      const double dx = x - fx[2 * i + 1];
+      mx = fmin(mx, fx[2 * i] * dx * dx);
+    }
+    double Dp = 0.0;
+    for (int i = 0; i < Ix; ++i) {
+      const double dx = x - fx[2 * i + 1];
+      const double g = exp_nonpos(mx - fx[2 * i] * dx * dx);
+      const double* Ci = C + (int64_t)i * JM;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < JM; j += 4) {
+        t0 = __builtin_fma(Ci[j], hv[j], t0);
+        t1 = __builtin_fma(Ci[j + 1], hv[j + 1], t1);
+        t2 = __builtin_fma(Ci[j + 2], hv[j + 2], t2);
+        t3 = __builtin_fma(Ci[j + 3], hv[j + 3], t3);
+      }
+      Dp = __builtin_fma(g, (t0 + t1) + (t2 + t3), Dp);
+    }
+    const double l = Dp >= 1e-280 ? cm - mx - my + log(Dp) : sep_direct_logD(K, c64, x, y);
+    if (!(l > -INFINITY && l < INFINITY)) bad |= FLAG_COL;
+    logD[n] = l;
+    obj = __builtin_fma(h ? h[n] : 1.0, l, obj);
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) obj += __shfl_xor(obj, off, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = obj;
+  if (bad) atomicOr(&fl, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = wred[0];
+    for (int w = 1; w < kST / 64; ++w) o += wred[w];
+    part_obj[blockIdx.x] = o;
+    part_flags[blockIdx.x] = fl;
+  }
+}
+
+// State pass: chunks of 32 samples; eight threads per sample fill the shifted
+// factors (g, and h times w_n) into LDS, then thread (ti, tj) of 16 x 16
+// accumulates M_ij for i = ti + 16 a (a < 4) and j = tj + 16 b (b < JB).
+template <int JB>
+__global__ void __launch_bounds__(kST)
+    sep_statepass_kernel(int K, int64_t N, const double* __restrict__ xi,
+                         const double* __restrict__ c64, int Ix, int Jy,
+                         const double* __restrict__ fx, const double* __restrict__ fy,
+                         const int* __restrict__ ix, const int* __restrict__ jy,
+                         const double* __restrict__ cmax, const double* __restrict__ h,
+                         const double* __restrict__ logD, double* __restrict__ part) {
+  constexpr int NS = 32;            // samples per chunk
+  constexpr int RP = kSepMax + 1;   // padded LDS row
+  __shared__ double buf[2 * NS * RP];
+  double(*Gs)[RP] = reinterpret_cast<double(*)[RP]>(buf);
+  double(*Hs)[RP] = reinterpret_cast<double(*)[RP]>(buf + NS * RP);
+  const int tid = threadIdx.x;
+  const int ti = tid & 15, tj = tid >> 4;
+  const int sl = tid >> 3, r = tid & 7;  // sample of the chunk, and its eighth of the factors
+  const double cm = cmax[0];
+  double acc[4][JB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < JB; ++b) acc[a][b] = 0.0;
+  const int64_t nchunks = (N + NS - 1) / NS;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t n = c * NS + sl;
+    const bool in = n < N;
+    const double x = in ? xi[2 * n] : 0.0, y = in ? xi[2 * n + 1] : 0.0;
+    double mx = INFINITY, my = INFINITY;
+    for (int i = r; i < Ix; i += 8) {
+      const double dx = x - fx[2 * i + 1];
+      mx = fmin(mx, fx[2 * i] * dx * dx);
+    }
+    for (int j = r; j < Jy; j += 8) {
+      const double dy = y - fy[2 * j + 1];
+      my = fmin(my, fy[2 * j] * dy * dy);
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      mx = fmin(mx, __shfl_xor(mx, off, 64));
+      my = fmin(my, __shfl_xor(my, off, 64));
+    }
+    const double w = in ? (h ? h[n] : 1.0) * exp(cm - mx - my - logD[n]) : 0.0;
+    __syncthreads();  // the previous chunk's products are done
+    for (int i = r; i < kSepMax; i += 8) {
+      double g = 0.0;
+      if (i < Ix) {
+        const double dx = x - fx[2 * i + 1];
+        g = exp_nonpos(mx - fx[2 * i] * dx * dx);
+      }
+      Gs[sl][i] = g;
+    }
+    for (int j = r; j < 16 * JB; j += 8) {
+      double v = 0.0;
+      if (j < Jy) {
+        const double dy = y - fy[2 * j + 1];
+        v = w * exp_nonpos(my - fy[2 * j] * dy * dy);
+      }
+      Hs[sl][j] = v;
+    }
+    __syncthreads();
+    for (int t = 0; t < NS; ++t) {
+      double ga[4], hb[JB];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ga[a] = Gs[t][ti + 16 * a];
+#pragma unroll
+      for (int b = 0; b < JB; ++b) hb[b] = Hs[t][tj + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < JB; ++b) acc[a][b] = __builtin_fma(ga[a], hb[b], acc[a][b]);
+    }
+  }
+  // M in LDS (64 x 65 fits in buf), then the per-state partials
+  double(*Ms)[RP] = reinterpret_cast<double(*)[RP]>(buf);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < JB; ++b) Ms[ti + 16 * a][tj + 16 * b] = acc[a][b];
+  __syncthreads();
+  for (int k = tid; k < K; k += kST) {
+    const double M = Ms[ix[k]][jy[k]];
+    const double z = c64[K + k] - cm;
+    double v = 0.0;
+    if (M > 0.0) v = z < 600.0 ? exp(z) * M : exp(z + log(M));
+    part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+size_t sep_int_count(int K) { return 3 * (size_t)K + (size_t)kSepMax * kSepMax + 1; }
+size_t sep_double_count() { return 4 * (size_t)kSepMax + (size_t)kSepMax * kSepMax + 8; }
+
+static hipError_t launch_sweep_sep(hipStream_t s, const OtfModel& m, int K, int64_t N,
+                                   const double* cst, const double* gk, const double* h,
+                                   double* logD, double* part, double* part_obj,
+                                   unsigned* part_flags, int G) {
+  const SepGrid& g = *m.sep;
+  hipLaunchKernelGGL(sep_prep_kernel, dim3(1), dim3(256), 0, s, K, g.Ix, g.Jy, g.JM, m.coef, cst,
+                     gk, g.cstart, g.cstates, g.C, g.cmax);
+#define SEP_COL(JM_)                                                                              \
+  case JM_:                                                                                       \
+    hipLaunchKernelGGL(sep_colpass_kernel<JM_>, dim3(G), dim3(kST), 0, s, K, N, m.xi, m.cf64,      \
+                       g.Ix, g.Jy, g.fx, g.fy, g.C, g.cmax, h, logD, part_obj, part_flags);       \
+    break;
+  switch (g.JM) {
+    SEP_COL(8) SEP_COL(16) SEP_COL(24) SEP_COL(32) SEP_COL(40) SEP_COL(48) SEP_COL(56) SEP_COL(64)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEP_COL
+#define SEP_STATE(JB_)                                                                            \
+  case JB_:                                                                                       \
+    hipLaunchKernelGGL(sep_statepass_kernel<JB_>, dim3(G), dim3(kST), 0, s, K, N, m.xi, m.cf64,    \
+                       g.Ix, g.Jy, g.fx, g.fy, g.ix, g.jy, g.cmax, h, logD, part);                \
+    break;
+  switch ((g.Jy + 15) / 16) {
+    SEP_STATE(1) SEP_STATE(2) SEP_STATE(3) SEP_STATE(4)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEP_STATE
+  return hipGetLastError();
+}
+
 hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, const double* cst,
                             const double* gk) {
   const dim3 cg((K + 255) / 256);
@@ -516,6 +776,8 @@ hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, 
   const dim3 sg(G, (K + kOStates - 1) / kOStates);
   hipError_t e = launch_otf_coefs(s, m, fp32, K, cst, gk);
   if (e != hipSuccess) return e;
+  if (!fp32 && m.sep && m.d == 2 && m.model == BUMBAR_MODEL_HARMONIC)
+    return launch_sweep_sep(s, m, K, N, cst, gk, h, logD, part, part_obj, part_flags, G);
   if (fp32) {
     if (m.d == 1) {
       hipLaunchKernelGGL(otf32_colpass_kernel<1>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,

@@ -58,6 +58,31 @@ def aniso_2d(K, Nk, seed, unsampled=()):
                 N=int(counts.sum()))
 
 
+def grid_2d(nx, ny, Nk, seed, unsampled=(), span=1.5, kappa=(8.0, 30.0), a_far=0.0):
+    """Windows on an nx x ny product grid: per-column kx and centre, per-row ky
+    and centre, a per-state constant a_k (a_far added to every state but the
+    first); u from the model definition."""
+    g = np.random.default_rng(seed)
+    gx, gy = np.linspace(-span, span, nx), np.linspace(-span, span, ny)
+    kxs, kys = g.uniform(*kappa, nx), g.uniform(*kappa, ny)
+    ix, iy = np.tile(np.arange(nx), ny), np.repeat(np.arange(ny), nx)
+    K = nx * ny
+    cx, cy, kx, ky = gx[ix], gy[iy], kxs[ix], kys[iy]
+    a = g.uniform(-1, 1, K)
+    a[1:] += a_far
+    counts = np.full(K, Nk, dtype=np.int64)
+    for k in unsampled:
+        counts[k] = 0
+    owner = np.repeat(np.arange(K), counts)
+    x = g.normal(cx[owner], 1 / np.sqrt(kx[owner]))
+    y = g.normal(cy[owner], 1 / np.sqrt(ky[owner]))
+    coef = np.stack([a, kx, cx, ky, cy], axis=1)
+    u = (a[:, None] + 0.5 * kx[:, None] * (x[None, :] - cx[:, None]) ** 2
+         + 0.5 * ky[:, None] * (y[None, :] - cy[:, None]) ** 2)
+    return dict(u=u, Nk=counts, xi=np.stack([x, y], axis=1), coef=coef,
+                model_type=synth.MODEL_HARMONIC, K=K, N=int(counts.sum()))
+
+
 def cases():
     return {
         "harmonic_1d": lambda: synth.harmonic_1d(K=8, Nk=1000, seed=0),
@@ -66,6 +91,10 @@ def cases():
         "aniso_2d_unsampled": lambda: aniso_2d(K=20, Nk=157, seed=4, unsampled=(0, 7)),
         "linear_2d": lambda: synth.ladder_2d(K=30, Nk=77, seed=2),
         "muller_brown": lambda: synth.muller_brown_grid(G=5, Nk=60, seed=4, materialize=True),
+        # product grids with 4 (Ix + Jy) <= K: the FP64 sweeps take the factored passes
+        "muller_brown_grid12": lambda: synth.muller_brown_grid(G=12, Nk=30, seed=7,
+                                                               materialize=True),
+        "aniso_grid": lambda: grid_2d(10, 12, 25, seed=11, unsampled=(3, 50, 119)),
     }
 
 
@@ -172,3 +201,33 @@ def test_on_the_fly_rejects_missing_model(bm):
         bm.solve(None, p["Nk"], xi=p["xi"])
     with pytest.raises(bm.BumbarError):
         bm.sweep_model(p["xi"], p["coef"], bm.MODEL_NONE, p["Nk"], np.zeros(4))
+
+
+def test_grid_sweep_far_offsets(bm):
+    # every state but one 660 kT up, sweep from f = 0: most samples' factored
+    # column sums fall below 1e-280 and take the direct sum over the states,
+    # and the state pass carries weights near 1e286
+    p = grid_2d(12, 12, 20, seed=13, span=4.0, kappa=(25.0, 30.0), a_far=660.0)
+    say(f"grid sweep, far offsets: K={p['K']} N={p['N']}")
+    f = np.zeros(p["K"])
+    fn_ref, lD_ref = oracle.sci_step(p["u"], p["Nk"], f, return_logD=True)
+    fn, lD, S, st = bm.sweep_model(p["xi"], p["coef"], p["model_type"], p["Nk"], f)
+    fn, lD, S = fn.cpu().numpy(), lD.cpu().numpy(), S.cpu().numpy()
+    assert np.max(np.abs(lD - lD_ref)) < 1e-12 * max(1.0, np.abs(lD_ref).max())
+    assert np.max(np.abs(fn - fn_ref)) < 1e-12 * max(1.0, np.abs(fn_ref).max())
+    W = oracle.weights(p["u"], p["Nk"], f)
+    S_ref = p["Nk"] * W.sum(axis=0)
+    assert np.max(np.abs(S - S_ref) / S_ref) < 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grid_solve_uses_factored_sweeps(bm, precision):
+    p = grid_2d(12, 10, 60, seed=17, unsampled=(7,))
+    say(f"grid solve precision={precision}: K={p['K']} N={p['N']}")
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(None, p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       precision=precision, tol=1e-11)
+    say("  grid sweeps", info["grid_sweeps"], "unbinned sweeps", info["unbinned_sweeps"])
+    assert info["status"] == 0
+    assert info["grid_sweeps"] > 0
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
