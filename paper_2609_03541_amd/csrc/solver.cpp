@@ -232,20 +232,21 @@ static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, 
   // B.cst / B.gk hold the constants at f; the packed matrix needs d = f - f0
   // instead of c, and the model kinds their coefficients rebuilt at f.
   hipStream_t s = ctx->stream;
+  const int hk = M.hess_kind >= 0 ? M.hess_kind : M.kind;
   HessSource hs;
-  hs.kind = M.kind;
+  hs.kind = hk;
   hs.num_cus = ctx->num_cus;
   hs.u = M.u;
   hs.ld = M.ld;
   hs.otf = M.otf;
   const double* cst = B.cst;
   hipError_t e = hipSuccess;
-  if (M.kind == 2) {
+  if (hk == 2) {
     e = launch_delta(s, B.K, f, M.f0, B.dk);
     hs.m0 = M.m0;
     cst = B.dk;
-  } else if (M.kind >= 3) {
-    e = launch_otf_coefs(s, M.otf, M.kind == 3, B.K, B.cst, B.gk);
+  } else if (hk >= 3) {
+    e = launch_otf_coefs(s, M.otf, hk == 3, B.K, B.cst, B.gk);
   }
   if (e != hipSuccess) return e;
   return launch_hessian(s, hs, B.K, B.N, cst, B.gk, B.logD, B.S, B.hess_parts, B.hess_chunks,
@@ -982,7 +983,8 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     // kFp32BinnedSteps steps it is rerun in FP64 from the start. For smaller K
     // the FP32 noise costs more iterations than it saves per step.
     constexpr int64_t kFp32BinnedSteps = 4000;
-    const bool try32 = otf && mixed && K > 256 && BB.cenf[0] != nullptr;
+    // (a product grid of windows steps faster on the factored FP64 sweep)
+    const bool try32 = otf && mixed && K > 256 && BB.cenf[0] != nullptr && !M.otf.sep;
     if (try32) {
       bumbar_options o32 = opt;
       o32.max_iter = std::min<int64_t>(opt.max_iter, kFp32BinnedSteps);
@@ -1012,10 +1014,15 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   const double t1 = now_ms();
   int fin_rc = BUMBAR_OK;
   int64_t steps64 = 0;  // Newton steps on M itself (after any packed stage)
+  // Newton on a product grid in mixed precision: the factored FP64 sweeps
+  // (cheaper than the direct FP32 ones) with the Hessian from the FP32 model
+  Mat Mfin = M;
+  if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
-      if (mixed && otf) {
+      if (mixed && otf && !M.otf.sep) {
         // Newton on the FP32 model sweeps to mixed_tol, then FP64 refinement
+        // (on a product grid the FP64 Newton below takes all the steps)
         Mat R = M;
         R.kind = 3;
         const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
@@ -1024,9 +1031,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
                                 &st->grad_norm);
         if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
         st->mixed_steps = st->finisher_steps - before;
-      } else if (mixed) {
+      } else if (mixed && !otf) {
         // pack at the current f, Newton on the FP32 matrix to mixed_tol, then
         // FP64 refinement on u to tol
+        if (!u_kn || !X.r) return fail(ctx, BUMBAR_EINVAL, "mixed precision needs u_kn or a model");
         e = launch_prepare_consts(s, K, N_k, B.f, B.cst, B.gk, B.lnNp);
         if (e == hipSuccess) e = launch_pack_f32(s, reinterpret_cast<const double*>(u_kn), N, K,
                                                  N, B.cst, X.r, N, X.m0);
@@ -1047,8 +1055,8 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
         st->mixed_steps = st->finisher_steps - before;
       }
       const int64_t before64 = st->finisher_steps;
-      fin_rc = newton_finish(ctx, B, M, N_k, opt.tol, opt.max_newton, st, &cnt, &st->final_step,
-                             &st->grad_norm);
+      fin_rc = newton_finish(ctx, B, Mfin, N_k, opt.tol, opt.max_newton, st, &cnt,
+                             &st->final_step, &st->grad_norm);
       steps64 = st->finisher_steps - before64;
     } else {
       int64_t it = 0;

@@ -35,6 +35,7 @@ struct Mat {
   const double* m0 = nullptr;  // kind 2: per-column shift (N)
   const double* f0 = nullptr;  // kind 2: reference point (K)
   OtfModel otf;                // kinds 3 and 4
+  int hess_kind = -1;          // kind the Newton Hessian reads (-1: kind)
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the

@@ -231,3 +231,18 @@ def test_grid_solve_uses_factored_sweeps(bm, precision):
     assert info["status"] == 0
     assert info["grid_sweeps"] > 0
     assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+
+
+def test_grid_mixed_large_k(bm):
+    # K > 256 on a product grid in mixed precision: binned steps and Newton
+    # sweeps on the factored FP64 passes, Hessian from the FP32 model on the
+    # matrix cores; the result is the FP64 one
+    p = synth.muller_brown_grid(G=17, Nk=12, seed=9, materialize=True)
+    say(f"grid mixed K={p['K']} N={p['N']}")
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(None, p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                       precision=1, tol=1e-11)
+    say("  grid sweeps", info["grid_sweeps"], "hessians", info["hessians"])
+    assert info["status"] == 0
+    assert info["grid_sweeps"] > 0
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
