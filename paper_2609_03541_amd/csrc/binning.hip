@@ -146,15 +146,19 @@ __global__ void iota_kernel(uint32_t* p, int64_t N) {
 }
 
 size_t sort_temp_bytes(int64_t N) {
-  size_t a = 0, b = 0;
+  size_t a = 0, b = 0, k64 = 0, k32 = 0;
   (void)rocprim::radix_sort_pairs((void*)nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                             (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
   (void)rocprim::radix_sort_pairs((void*)nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                             (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
+  (void)rocprim::radix_sort_keys((void*)nullptr, k64, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                 (size_t)N);
+  (void)rocprim::radix_sort_keys((void*)nullptr, k32, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                 (size_t)N);
   size_t c = 0;
   (void)rocprim::inclusive_scan((void*)nullptr, c, (const int32_t*)nullptr, (int32_t*)nullptr,
                           (size_t)N, rocprim::plus<int32_t>());
-  return std::max(std::max(a, b), c) + 1024;
+  return std::max(std::max(std::max(a, b), std::max(k64, k32)), c) + 1024;
 }
 
 hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t* iota,
@@ -186,9 +190,9 @@ __global__ void __launch_bounds__(kBT)
   if (threadIdx.x == 0) counts[1 + blockIdx.x] = sh[0];
 }
 
+template <typename TK>
 __global__ void __launch_bounds__(kBT)
-    count_runs_keys_kernel(const uint64_t* __restrict__ ks, int64_t N,
-                           int64_t* __restrict__ counts) {
+    count_runs_keys_kernel(const TK* __restrict__ ks, int64_t N, int64_t* __restrict__ counts) {
   __shared__ int64_t sh[kBT];
   int64_t c = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBT)
@@ -336,6 +340,14 @@ __global__ void cells_kernel(const uint32_t* __restrict__ q, int64_t N, int d, u
   keys[n] = (d == 1) ? (uint64_t)q[n] / m : cell2(q[2 * n], q[2 * n + 1], m);
 }
 
+// The same 2-D cell ids when every id of this m fits in 32 bits.
+__global__ void cells32_kernel(const uint32_t* __restrict__ q, int64_t N, uint64_t m,
+                               uint32_t* __restrict__ keys) {
+  const int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (n >= N) return;
+  keys[n] = (uint32_t)cell2(q[2 * n], q[2 * n + 1], m);
+}
+
 static unsigned key_bits(int d, uint64_t m) {
   // the largest possible cell id for this m, then its bit length
   uint64_t maxc;
@@ -353,14 +365,29 @@ static unsigned key_bits(int d, uint64_t m) {
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts) {
-  hipLaunchKernelGGL(cells_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q, N, 2,
-                     m, keys);
-  size_t bytes = tmp_bytes;
-  hipError_t e = rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, keys_sorted,
-                                          (size_t)N, 0, key_bits(2, m), s);
-  if (e != hipSuccess) return e;
+  const unsigned bits = key_bits(2, m);
   const int nb = red_blocks(N);
-  hipLaunchKernelGGL(count_runs_keys_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, counts);
+  size_t bytes = tmp_bytes;
+  hipError_t e;
+  if (bits <= 32) {
+    // ids of this width fit in 32 bits: half the bytes through the sort
+    uint32_t* k32 = reinterpret_cast<uint32_t*>(keys);
+    uint32_t* s32 = reinterpret_cast<uint32_t*>(keys_sorted);
+    hipLaunchKernelGGL(cells32_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q,
+                       N, m, k32);
+    e = rocprim::radix_sort_keys(tmp, bytes, (const uint32_t*)k32, s32, (size_t)N, 0, bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_runs_keys_kernel<uint32_t>, dim3(nb), dim3(kBT), 0, s,
+                       (const uint32_t*)s32, N, counts);
+  } else {
+    hipLaunchKernelGGL(cells_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q, N,
+                       2, m, keys);
+    e = rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, keys_sorted, (size_t)N, 0,
+                                 bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_runs_keys_kernel<uint64_t>, dim3(nb), dim3(kBT), 0, s,
+                       (const uint64_t*)keys_sorted, N, counts);
+  }
   hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(kBT), 0, s, nb, counts);
   return hipGetLastError();
 }
