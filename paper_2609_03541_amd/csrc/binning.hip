@@ -238,59 +238,52 @@ __device__ __forceinline__ uint32_t div_by_magic(uint32_t q, uint64_t m, uint64_
   return (uint32_t)(t >> 32);
 }
 
-constexpr int kProbeBlocks = 256;  // workgroups of the multi-probe count
-constexpr int kProbeElems = 16;    // max sorted coordinates per thread per pass
+constexpr int kRunChunk = 256;  // sorted coordinates per wave and pass
 
-// Each thread holds a run of consecutive sorted coordinates in registers and,
-// probe by probe, counts the positions where floor(q / m) changes (one
-// division per element per probe, compared with the previous element's).
-// Per-block totals are added with one integer atomic per probe and block.
+// Lanes are probes: lane j of a wave counts, for width m_j, the positions in
+// a chunk of kRunChunk consecutive sorted coordinates where floor(q / m_j)
+// changes (one division per element and probe, against the previous
+// element's). Every lane reads the same coordinate at a time, so nothing is
+// exchanged between lanes until one sum per block and probe, added with one
+// integer atomic.
 __global__ void __launch_bounds__(kBT)
     count_runs_1d_multi_kernel(const uint32_t* __restrict__ qs, int64_t N,
                                const uint64_t* __restrict__ ms, int M,
                                unsigned long long* __restrict__ counts) {
-  __shared__ uint64_t sm[kMaxProbes], smag[kMaxProbes];
-  __shared__ unsigned sred[kBT / 64][kMaxProbes];
-  for (int j = threadIdx.x; j < M; j += kBT) {
-    sm[j] = ms[2 * j];
-    smag[j] = ms[2 * j + 1];
-  }
-  for (int i = threadIdx.x; i < (kBT / 64) * kMaxProbes; i += kBT) (&sred[0][0])[i] = 0u;
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nthreads = (int64_t)gridDim.x * kBT;
-  const int64_t per = (N + nthreads - 1) / nthreads;
-  const int64_t tid = (int64_t)blockIdx.x * kBT + threadIdx.x;
-  const int64_t first = tid * per;
-  const int64_t last = std::min<int64_t>(N, first + per);
-  // the chunk loop has the same trip count in every lane (shuffles inside)
-  for (int64_t off = 0; off < per; off += kProbeElems) {
-    const int64_t base = first + off;
-    const int cnt = base < last ? (int)std::min<int64_t>(kProbeElems, last - base) : 0;
-    uint32_t v[kProbeElems];
-#pragma unroll
-    for (int e = 0; e < kProbeElems; ++e) v[e] = e < cnt ? qs[base + e] : 0u;
-    const uint32_t prev = (cnt > 0 && base > 0) ? qs[base - 1] : 0u;
-    for (int j = 0; j < M; ++j) {
-      const uint64_t m = sm[j], mg = smag[j];
-      uint32_t dp = div_by_magic(prev, m, mg);
-      unsigned cj = 0;
-#pragma unroll
-      for (int e = 0; e < kProbeElems; ++e) {
-        const uint32_t d = div_by_magic(v[e], m, mg);
-        cj += (e < cnt && (base + e == 0 || d != dp)) ? 1u : 0u;
-        dp = d;
-      }
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) cj += __shfl_xor(cj, o, 64);
-      if (lane == 0) sred[wave][j] += cj;
+  __shared__ unsigned long long sred[kBT / 64][kMaxProbes];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool act = lane < M;
+  const uint64_t m = act ? ms[2 * lane] : 1ull;
+  const uint64_t mg = act ? ms[2 * lane + 1] : 0ull;
+  const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;
+  const int64_t nw = (int64_t)gridDim.x * (kBT / 64);
+  unsigned long long c = 0;
+  for (int64_t ch = (int64_t)blockIdx.x * (kBT / 64) + wave; ch < nchunks; ch += nw) {
+    const int64_t b = ch * kRunChunk;
+    const int64_t e = std::min<int64_t>(N, b + kRunChunk);
+    int64_t i = b;
+    uint32_t dp;
+    if (b == 0) {
+      dp = div_by_magic(qs[0], m, mg);
+      c += 1;  // the first coordinate starts a run
+      i = 1;
+    } else {
+      dp = div_by_magic(qs[b - 1], m, mg);
+    }
+#pragma unroll 8
+    for (; i < e; ++i) {
+      const uint32_t d = div_by_magic(qs[i], m, mg);
+      c += d != dp ? 1ull : 0ull;
+      dp = d;
     }
   }
+  sred[wave][lane] = c;
   __syncthreads();
-  for (int j = threadIdx.x; j < M; j += kBT) {
+  if (threadIdx.x < M) {
     unsigned long long t = 0;
-    for (int w = 0; w < kBT / 64; ++w) t += sred[w][j];
-    if (t) atomicAdd(&counts[j], t);
+    for (int w = 0; w < kBT / 64; ++w) t += sred[w][threadIdx.x];
+    if (t) atomicAdd(&counts[threadIdx.x], t);
   }
 }
 
@@ -319,7 +312,8 @@ uint64_t width_magic(uint64_t m) {
 hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
                                  const uint64_t* ms, int M, unsigned long long* counts) {
   if (M < 1 || M > kMaxProbes) return hipErrorInvalidValue;
-  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(kProbeBlocks, (N + kBT - 1) / kBT));
+  const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(1024, (nchunks + 3) / 4));
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kMaxProbes), 0, s, counts, M);
   hipLaunchKernelGGL(count_runs_1d_multi_kernel, dim3((unsigned)nb), dim3(kBT), 0, s, q_sorted, N,
                      ms, M, counts);
