@@ -343,7 +343,10 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
 // the bin centres when the stage runs on the fly (FP32 when the level has
 // FP32 centres and fp32 is asked for, else FP64).
 static Mat level_mat_of(const Level& L, const Mat* otf_base, bool fp32) {
-  if (otf_base && !(L.ubar && !(fp32 && L.cenf))) {
+  // a small on-the-fly level has its representatives materialised (used
+  // unless FP32 centre steps are asked for)
+  const bool stored = L.ubar != nullptr && !(fp32 && L.cenf);
+  if (otf_base && !stored) {
     Mat M = *otf_base;
     M.kind = (fp32 && L.cenf) ? 3 : 4;
     M.otf.xi = L.cen;
