@@ -789,17 +789,22 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
                                  const unsigned* part_flags, const double* f, const double* lnNp,
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
                                  SweepScalars* out, double* cst_next) {
-  // few partials: one wave-sized block; many: the per-state sums first, one
-  // wave per state over all CUs (scratch: partS, which the fast-path mode
-  // does not use otherwise), then 1024 threads for the rest
+  // few partials: one wave-sized block; more: 1024 threads, with many
+  // partials the per-state sums first, one wave per state over all CUs
+  // (scratch: partS, which the fast-path mode does not use otherwise)
   if (K <= 256 && nparts <= 16) {
     hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts,
                        nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
                        out, cst_next);
     return hipGetLastError();
   }
+  // the single workgroup takes about nparts / (4 T) dependent load rounds
+  // (T lanes per state, as in the kernel); beyond a few rounds one more
+  // launch that spreads the sums over the chip is cheaper
+  int T = 1;
+  while (T < 64 && 2 * T * K <= 1024) T *= 2;
   int nstate = nparts;
-  if (mode == 0 && partS != nullptr) {
+  if (mode == 0 && partS != nullptr && nparts > 16 * T) {
     hipLaunchKernelGGL(part_reduce_kernel, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, K,
                        nparts, part, partS);
     part = partS;
