@@ -140,9 +140,11 @@ hipError_t launch_pack_coords(hipStream_t s, int64_t n, const double* xi, float*
 // Two-pass sweep with u from the model (FP32 or FP64 arithmetic) at the N
 // points of m.xi / m.xf with multiplicities h (NULL: 1); also rebuilds the
 // per-sweep coefficients from cst / gk. Partials state-major.
+// part holds part_cap doubles (it also takes the slices of a split column
+// pass, which the state pass then overwrites).
 hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
                             const double* cst, const double* gk, const double* h, double* logD,
-                            double* part,
+                            double* part, size_t part_cap,
                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out);
 // Rebuilds only the per-sweep coefficients (cf32 or cf64) from cst / gk.
 hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, const double* cst,

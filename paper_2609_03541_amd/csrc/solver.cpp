@@ -148,7 +148,7 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
   } else if (M.kind >= 3) {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, h, logD_out, B.part,
-                         B.part_obj, B.part_flags, ctx->num_cus, &grid);
+                         (size_t)B.nparts_cap * K, B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind == 0 && sweep_fast_supported(K)) {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_fast(s, reinterpret_cast<const double*>(M.u), M.ld, K, N, B.cst, B.gk, h,

@@ -18,6 +18,7 @@
 // quadratic form t = A_k + sum_j (B_kj x_j + C_kj x_j^2) in log2 units with
 // the hardware exp2, from FP32 coordinates; A, B, C are rebuilt in FP64 for
 // every sweep and rounded once.
+#include <algorithm>
 #include <cmath>
 
 #include "bumbar_impl.h"
@@ -293,12 +294,17 @@ __global__ void __launch_bounds__(kOT)
 
 // ---- FP64 passes ----------------------------------------------------------------
 
-template <int D, int MODEL>
+// SPLIT: block (x, y) takes only the states [y kc, (y + 1) kc) and writes, per
+// sample, the pair (max, sum) of its slice to pm[(y N + n) * 2] (the maximum
+// is NaN for non-finite coordinates); otf64_colmerge_kernel combines them.
+// This spreads columns with few samples over more workgroups.
+template <int D, int MODEL, bool SPLIT>
 __global__ void __launch_bounds__(kOT)
     otf64_colpass_kernel(int K, int64_t N, const double* __restrict__ xi,
                          const double* __restrict__ c64, const double* __restrict__ h,
                          double* __restrict__ logD,
-                         double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+                         double* __restrict__ part_obj, unsigned* __restrict__ part_flags,
+                         int kc, double* __restrict__ pm) {
   constexpr int T = kOTile / 2;  // FP64 tile: half the states of the FP32 tile
   __shared__ double sE[T];
   __shared__ double sH[D][T];
@@ -323,8 +329,10 @@ __global__ void __launch_bounds__(kOT)
     }
     if (chk != chk) bad |= FLAG_NAN;
     double m0 = -INFINITY, m1 = -INFINITY, s0 = 0.0, s1 = 0.0;
-    for (int t0 = 0; t0 < K; t0 += T) {
-      const int tl = min(T, K - t0);
+    const int kb = SPLIT ? min(K, (int)blockIdx.y * kc) : 0;
+    const int ke = SPLIT ? min(K, kb + kc) : K;
+    for (int t0 = kb; t0 < ke; t0 += T) {
+      const int tl = min(T, ke - t0);
       __syncthreads();
       for (int i = threadIdx.x; i < tl; i += kOT) {
         sE[i] = c64[t0 + i];
@@ -370,6 +378,19 @@ __global__ void __launch_bounds__(kOT)
         }
       }
     }
+    if constexpr (SPLIT) {
+      const double nan_or = (chk != chk) ? NAN : 0.0;
+      double* q = pm + ((int64_t)blockIdx.y * N + n0) * 2;
+      if (ok0) {
+        q[0] = m0 + nan_or;
+        q[1] = s0;
+      }
+      if (ok1) {
+        q[2] = m1 + nan_or;
+        q[3] = s1;
+      }
+      continue;
+    }
     if (ok0) {
       if (!(m0 > -INFINITY && m0 < INFINITY)) bad |= FLAG_COL;
       const double l0 = m0 + log(s0);
@@ -382,6 +403,54 @@ __global__ void __launch_bounds__(kOT)
       logD[n0 + 1] = l1;
       obj = __builtin_fma(h ? h[n0 + 1] : 1.0, l1, obj);
     }
+  }
+  if constexpr (SPLIT) return;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) obj += __shfl_xor(obj, off, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = obj;
+  if (bad) atomicOr(&fl, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = wred[0];
+    for (int w = 1; w < kOT / 64; ++w) o += wred[w];
+    part_obj[blockIdx.x] = o;
+    part_flags[blockIdx.x] = fl;
+  }
+}
+
+// ln D_n from the Y slices of a split column pass: M = the largest slice
+// maximum, S = sum over the slices (in order) of s_y exp(m_y - M); the
+// objective partial and flags per block as in the column pass.
+__global__ void __launch_bounds__(kOT)
+    otf64_colmerge_kernel(int64_t N, int Y, const double* __restrict__ pm,
+                          const double* __restrict__ h, double* __restrict__ logD,
+                          double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
+  __shared__ double wred[kOT / 64];
+  __shared__ unsigned fl;
+  if (threadIdx.x == 0) fl = 0u;
+  __syncthreads();
+  double obj = 0.0;
+  unsigned bad = 0;
+  for (int64_t n = (int64_t)blockIdx.x * kOT + threadIdx.x; n < N;
+       n += (int64_t)gridDim.x * kOT) {
+    double M = -INFINITY;
+    bool nan = false;
+    for (int y = 0; y < Y; ++y) {
+      const double m = pm[((int64_t)y * N + n) * 2];
+      nan = nan || (m != m);
+      M = fmax(M, m);
+    }
+    double S = 0.0;
+    if (M > -INFINITY && M < INFINITY)
+      for (int y = 0; y < Y; ++y) {
+        const double* q = pm + ((int64_t)y * N + n) * 2;
+        S = __builtin_fma(q[1], exp_nonpos(q[0] - M), S);
+      }
+    if (nan) bad |= FLAG_NAN;
+    if (!(M > -INFINITY && M < INFINITY)) bad |= FLAG_COL;
+    const double l = M + log(S);
+    logD[n] = l;
+    obj = __builtin_fma(h ? h[n] : 1.0, l, obj);
   }
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) obj += __shfl_xor(obj, off, 64);
@@ -768,7 +837,7 @@ hipError_t launch_otf_coefs(hipStream_t s, const OtfModel& m, bool fp32, int K, 
 
 hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, int64_t N,
                             const double* cst, const double* gk, const double* h, double* logD,
-                            double* part,
+                            double* part, size_t part_cap,
                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out) {
   if (m.d != 1 && m.d != 2) return hipErrorInvalidValue;
   const int G = otf_grid(N, num_cus);
@@ -792,9 +861,23 @@ hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, 
     }
     return hipGetLastError();
   }
+  // few column blocks: the states split over Y slices (pairs in part, then merged)
+  int Y = 1;
+  if (G < num_cus) {
+    Y = std::min((K + 63) / 64, (2 * num_cus + G - 1) / G);
+    while (Y > 1 && (size_t)Y * (size_t)N * 2 > part_cap) --Y;
+  }
+  const int kc = (K + Y - 1) / Y;
 #define OTF64_PASSES(D_, M_)                                                                      \
-  hipLaunchKernelGGL((otf64_colpass_kernel<D_, M_>), dim3(G), dim3(kOT), 0, s, K, N, m.xi, m.cf64, \
-                     h, logD, part_obj, part_flags);                                              \
+  if (Y > 1) {                                                                                    \
+    hipLaunchKernelGGL((otf64_colpass_kernel<D_, M_, true>), dim3(G, Y), dim3(kOT), 0, s, K, N,   \
+                       m.xi, m.cf64, h, logD, part_obj, part_flags, kc, part);                     \
+    hipLaunchKernelGGL(otf64_colmerge_kernel, dim3(G), dim3(kOT), 0, s, N, Y, part, h, logD,      \
+                       part_obj, part_flags);                                                     \
+  } else {                                                                                        \
+    hipLaunchKernelGGL((otf64_colpass_kernel<D_, M_, false>), dim3(G), dim3(kOT), 0, s, K, N,     \
+                       m.xi, m.cf64, h, logD, part_obj, part_flags, kc, nullptr);                  \
+  }                                                                                               \
   hipLaunchKernelGGL((otf64_statepass_kernel<D_, M_>), sg, dim3(kOT), 0, s, K, N, m.xi, m.cf64,   \
                      h, logD, part)
   if (m.model == BUMBAR_MODEL_HARMONIC) {
