@@ -452,6 +452,42 @@ struct SrcPacked32 {
   }
 };
 
+// Stored FP64 u: t_kn = log2(e) (c_k - u_kn) + e_n with e_n = -log2(e) ln D_n;
+// the difference is taken in FP64 per element and the product rounded to
+// FP32.
+struct SrcMat64h {
+  const double* u;
+  int64_t ld;
+  struct Row {
+    const double* p;
+    double c;
+  };
+  __device__ Row row(int k, double ck) const { return {u + (int64_t)k * ld, ck}; }
+  __device__ void full(const Row& rw, int64_t n, bool, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+#pragma unroll
+    for (int h = 0; h < 16; h += 8) {
+      double x[8];
+      float cv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        x[q] = rw.p[n + h + q];
+        cv[q] = colv[n + h + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[h + q] = (float)(kLog2eH * (rw.c - x[q])) + cv[q];
+    }
+  }
+  __device__ void tail(const Row& rw, int64_t n, int64_t last, const float* __restrict__ colv,
+                       float (&t)[16]) const {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t m = n + q < last ? n + q : last;
+      t[q] = (float)(kLog2eH * (rw.c - rw.p[m])) + colv[m];
+    }
+  }
+};
+
 // FP32 model (the log2-domain coefficients of the FP32 model sweeps):
 // t_kn = A_k + e_n + sum_j x_nj (B_jk + C_jk x_nj), e_n = -log2(e) ln D_n.
 template <int D>
@@ -767,7 +803,7 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
-  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3)) {
+  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3 || hs.kind == 5)) {
     const int nb16 = h16_nb(K);
     const int nblk16 = nb16 * (nb16 + 1) / 2;
     const int ch16 = h16_chunks(K, N, hs.num_cus);
@@ -783,6 +819,10 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
       hipLaunchKernelGGL(hessian_h16_kernel<SrcPacked32>, g16, dim3(512), 0, s,
                          SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
                          cst, gk, colv, nb16, ch16, len16, vec, p16);
+    } else if (hs.kind == 5) {
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcMat64h>, g16, dim3(512), 0, s,
+                         SrcMat64h{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst, gk,
+                         colv, nb16, ch16, len16, false, p16);
     } else if (hs.otf.d == 1) {
       hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<1>>, g16, dim3(512), 0, s,
                          SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
@@ -798,6 +838,7 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   }
   switch (hs.kind) {
     case 0:
+    case 5:  // FP64 u where the FP16-core path does not apply (K <= kSmallMaxK)
       launch_any(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
                      gk, logD, nb, chunks, chunk_len, partials);
       break;

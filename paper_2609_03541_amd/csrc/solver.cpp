@@ -245,7 +245,8 @@ static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, 
     e = launch_delta(s, B.K, f, M.f0, B.dk);
     hs.m0 = M.m0;
     cst = B.dk;
-  } else if (hk >= 3) {
+  } else if (hk == 3 || hk == 4) {
+    // the model kinds: per-sweep coefficients at f
     e = launch_otf_coefs(s, M.otf, hk == 3, B.K, B.cst, B.gk);
   }
   if (e != hipSuccess) return e;
@@ -1018,6 +1019,9 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   // (cheaper than the direct FP32 ones) with the Hessian from the FP32 model
   Mat Mfin = M;
   if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
+  // FP64 u with K > 256: the Newton Hessian (which only shapes the steps; the
+  // FP64 sweeps decide the fixed point) on the FP16 matrix cores
+  if (!mixed && !otf && M.kind == 0 && K > 256) Mfin.hess_kind = 5;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
       if (mixed && otf && !M.otf.sep) {

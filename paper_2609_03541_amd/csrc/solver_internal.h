@@ -35,7 +35,8 @@ struct Mat {
   const double* m0 = nullptr;  // kind 2: per-column shift (N)
   const double* f0 = nullptr;  // kind 2: reference point (K)
   OtfModel otf;                // kinds 3 and 4
-  int hess_kind = -1;          // kind the Newton Hessian reads (-1: kind)
+  int hess_kind = -1;          // kind the Newton Hessian reads (-1: kind; 5: FP64 u
+                               // on the FP16 matrix cores)
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the
