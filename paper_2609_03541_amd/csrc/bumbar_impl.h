@@ -157,7 +157,8 @@ hipError_t launch_weights_otf(hipStream_t s, const OtfModel& m, int K, int64_t N
 // (otf.cf32 current); 4 model in FP64 (otf.cf64 current). Kinds 2 and 3 with
 // K > 256 run on FP16 matrix cores (FP32 accumulation within a chunk).
 struct HessSource {
-  int kind = 0;  // as Mat::kind; 5: stored FP64 u on the FP16 matrix cores (K > 256)
+  int kind = 0;  // as Mat::kind; 5: stored FP64 u on the FP16 matrix cores (K > 256);
+                 // 6: stored FP64 u with FP32 exponentials (FP64 accumulation)
   int num_cus = 256;  // sizes the sample chunks of the FP16-core path
   const void* u = nullptr;
   int64_t ld = 0;

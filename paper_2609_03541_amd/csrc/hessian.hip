@@ -58,6 +58,23 @@ struct SrcMat {
   }
 };
 
+// FP64 u with the weight's exponential on the FP32 hardware exp2 (relative
+// error about 1e-7): for the Newton Hessian, which only shapes the steps.
+// The exponent c_k - u_kn - ln D_n is taken in FP64 and is <= 0.
+struct SrcMatExp32 {
+  const double* u;
+  int64_t ld;
+  struct Row {
+    const double* p;
+    double c;
+  };
+  __device__ Row row(int k, double c) const { return {u + (int64_t)k * ld, c}; }
+  __device__ double col(int64_t n, const double* logD) const { return logD[n]; }
+  __device__ double p(const Row& r, int64_t n, double lD) const {
+    return (double)__builtin_amdgcn_exp2f((float)(1.4426950408889634 * (r.c - r.p[n] - lD)));
+  }
+};
+
 // Packed mixed-precision matrix r_kn = c0_k - u_kn - m0_n: x = d_k + r_kn -
 // (ln D_n - m0_n) with d_k = c_k - c0_k passed as the row constant.
 struct SrcPacked {
@@ -841,6 +858,10 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
     case 5:  // FP64 u where the FP16-core path does not apply (K <= kSmallMaxK)
       launch_any(s, SrcMat<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
                      gk, logD, nb, chunks, chunk_len, partials);
+      break;
+    case 6:
+      launch_any(s, SrcMatExp32{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst, gk,
+                     logD, nb, chunks, chunk_len, partials);
       break;
     case 1:
       launch_any(s, SrcMat<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst, gk,

@@ -1019,9 +1019,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   // (cheaper than the direct FP32 ones) with the Hessian from the FP32 model
   Mat Mfin = M;
   if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
-  // FP64 u with K > 256: the Newton Hessian (which only shapes the steps; the
-  // FP64 sweeps decide the fixed point) on the FP16 matrix cores
-  if (!mixed && !otf && M.kind == 0 && K > 256) Mfin.hess_kind = 5;
+  // FP64 u: the Newton Hessian (which only shapes the steps; the FP64 sweeps
+  // decide the fixed point) on the FP16 matrix cores for K > 256, else with
+  // FP32 exponentials
+  if (!mixed && !otf && M.kind == 0) Mfin.hess_kind = K > 256 ? 5 : 6;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
       if (mixed && otf && !M.otf.sep) {

@@ -36,7 +36,7 @@ struct Mat {
   const double* f0 = nullptr;  // kind 2: reference point (K)
   OtfModel otf;                // kinds 3 and 4
   int hess_kind = -1;          // kind the Newton Hessian reads (-1: kind; 5: FP64 u
-                               // on the FP16 matrix cores)
+                               // on the FP16 matrix cores; 6: FP64 u, FP32 exponentials)
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the
