@@ -135,6 +135,8 @@ typedef struct {
   int64_t graph_batches;    /* batches of binned steps launched as HIP graphs            */
   int64_t grid_sweeps;      /* FP64 model sweeps done on the product-grid passes (2-D
                                harmonic windows whose factors form a grid)              */
+  int64_t batched_steps;    /* binned SCI steps run inside single-workgroup batches (levels
+                               of at most 512 bins, the matrix held in registers)       */
 } bumbar_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -271,6 +273,25 @@ int bumbar_bin(bumbar_ctx* ctx, const double* xi, int64_t N, int d, int64_t n_ta
  */
 int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const double* log_D_n,
                     void* workspace, size_t ws_bytes, double* p);
+
+/*
+ * Free-energy surface on a regular grid of the coordinates (Section 3: the
+ * surfaces of Fig. 1 from the probabilities of Eqs. (5)-(6)):
+ *   F_b = -ln sum_{n in bin b} p_n,
+ * bin b = b_0 nbins_1 + b_1 (d = 2; b = b_0 for d = 1) with
+ *   b_j = floor((xi_nj - lo_j) * nbins_j / (hi_j - lo_j))   (FP64, this order).
+ * Samples with some b_j outside [0, nbins_j) are left out; empty bins get
+ * +inf. Each bin's p_n are added in increasing n, so F does not depend on the
+ * launch. xi (N x d, FP64, d in {1, 2}) and p (N) in, F (nbins_0 * nbins_1)
+ * out, all device; lo, hi, nbins: host arrays of d entries (finite lo < hi,
+ * nbins >= 1, fewer than 2^32 bins; N < 2^32). The workspace must hold
+ * bumbar_query_workspace_pmf bytes. Synchronises. EINVAL for a bad grid or
+ * argument, ENOMEM for a short workspace.
+ */
+int bumbar_query_workspace_pmf(const bumbar_ctx* ctx, int64_t N, size_t* bytes);
+int bumbar_pmf(bumbar_ctx* ctx, const double* xi, int64_t N, int d, const double* p,
+               const double* lo, const double* hi, const int* nbins, void* workspace,
+               size_t ws_bytes, double* F);
 
 /* ---- batched serving ---------------------------------------------------
  *

@@ -86,6 +86,7 @@ def _load():
                                C.c_int64, C.c_int, C.POINTER(C.c_int), C.c_int, dp, dp,
                                C.POINTER(CheckRecord), C.c_int, ip64]
     lib.orc_reweight.argtypes = [C.c_int64, dp, dp, dp]
+    lib.orc_pmf.argtypes = [C.c_int64, C.c_int, dp, dp, dp, dp, C.POINTER(C.c_int), dp]
     lib.orc_check_record_size.restype = C.c_int
     assert lib.orc_check_record_size() == C.sizeof(CheckRecord)
     _lib = lib
@@ -302,3 +303,18 @@ def reweight(u_target, logD):
     p = np.empty(len(ut))
     _check(_load().orc_reweight(len(ut), _p(ut), _p(ld), _p(p)), "reweight")
     return p
+
+
+def pmf(xi, p, lo, hi, nbins):
+    """Free-energy surface -ln sum_{n in bin} p_n on a regular grid (Section 3, Fig. 1)."""
+    x = _d(xi)
+    if x.ndim == 1:
+        x = x[:, None]
+    x = np.ascontiguousarray(x)
+    N, d = x.shape
+    lo_a, hi_a = _d(np.atleast_1d(lo)), _d(np.atleast_1d(hi))
+    nb = np.ascontiguousarray(np.atleast_1d(nbins), dtype=np.int32)
+    F = np.empty(int(np.prod(nb)))
+    _check(_load().orc_pmf(N, d, _p(x), _p(_d(p)), _p(lo_a), _p(hi_a), _p(nb, C.c_int), _p(F)),
+           "pmf")
+    return F.reshape(tuple(int(v) for v in nb))

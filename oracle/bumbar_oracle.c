@@ -887,5 +887,47 @@ int orc_reweight(int64_t N, const double* u_target, const double* logD, double* 
   return ORC_OK;
 }
 
+/* Free-energy surface on a regular grid (Section 3: the surfaces of Fig. 1,
+ * from the probabilities of Eqs. (5)-(6)): F_b = -ln sum_{n in bin b} p_n with
+ * bin b = b_0 nb_1 + b_1 (b = b_0 for d = 1) and
+ * b_j = floor((xi_nj - lo_j) * nb_j / (hi_j - lo_j)); samples outside the grid
+ * are left out, bins without probability get +inf. The p_n of a bin are added
+ * in increasing n. */
+int orc_pmf(int64_t N, int d, const double* xi, const double* p, const double* lo,
+            const double* hi, const int* nb, double* F) {
+  if (N <= 0 || (d != 1 && d != 2)) return ORC_EINVAL;
+  int64_t total = 1;
+  for (int j = 0; j < d; ++j) {
+    if (nb[j] < 1 || !(hi[j] > lo[j])) return ORC_EINVAL;
+    total *= nb[j];
+  }
+  double* acc = (double*)calloc((size_t)total, sizeof(double));
+  char* hit = (char*)calloc((size_t)total, 1);
+  if (!acc || !hit) {
+    free(acc);
+    free(hit);
+    return ORC_EINVAL;
+  }
+  for (int64_t n = 0; n < N; ++n) {
+    int64_t b = 0;
+    int in = 1;
+    for (int j = 0; j < d; ++j) {
+      const double bj = floor((xi[n * d + j] - lo[j]) * (double)nb[j] / (hi[j] - lo[j]));
+      if (!(bj >= 0.0 && bj < (double)nb[j])) {
+        in = 0;
+        break;
+      }
+      b = b * nb[j] + (int64_t)bj;
+    }
+    if (!in) continue;
+    acc[b] += p[n];
+    hit[b] = 1;
+  }
+  for (int64_t b = 0; b < total; ++b) F[b] = hit[b] ? -log(acc[b]) : INFINITY;
+  free(acc);
+  free(hit);
+  return ORC_OK;
+}
+
 /* Size of the check record, so that a binding can verify its layout. */
 int orc_check_record_size(void) { return (int)sizeof(orc_check_t); }

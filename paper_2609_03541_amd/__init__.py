@@ -16,7 +16,7 @@ from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,
                     FINISH_NEWTON, FINISH_SCI, MODEL_HARMONIC, MODEL_LINEAR, MODEL_NONE, OK,
                     PREC_FP64, PREC_MIXED, REPRESENT_AUTO, REPRESENT_CENTRE, REPRESENT_MEAN)
 
-__all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight",
+__all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight", "pmf",
            "model_energies", "sweep_model", "hessian_model", "Server",
            "BumbarError", "default_options"]
 
@@ -318,6 +318,44 @@ def reweight(u_target, logD, ctx=None):
                                  _ptr(p))
     ctx.check(rc)
     return p
+
+
+def pmf(xi, p, lo, hi, nbins, ctx=None):
+    """Free-energy surface F_b = -ln sum_{n in bin b} p_n on a regular grid.
+
+    xi: N x d coordinates (d in {1, 2}), p: N probabilities (from ``reweight``),
+    lo, hi, nbins: d values each. Returns F as a float64 tensor of shape
+    ``nbins`` (+inf for bins without probability).
+    """
+    torch = _torch()
+    ctx = ctx or context()
+    dev = torch.device(f"cuda:{ctx.device}")
+    xi_t = _dev(xi, torch.float64, dev)
+    if xi_t.dim() == 1:
+        xi_t = xi_t[:, None].contiguous()
+    N, d = xi_t.shape
+    p_t = _dev(p, torch.float64, dev)
+
+    def seq(v):
+        return [v] if not hasattr(v, "__len__") else list(v)
+
+    lo_l, hi_l, nb = [float(v) for v in seq(lo)], [float(v) for v in seq(hi)], \
+        [int(v) for v in seq(nbins)]
+    if not (len(lo_l) == len(hi_l) == len(nb) == d):
+        raise ValueError("lo, hi and nbins need one entry per coordinate")
+    lo_a, hi_a, nb_a = (C.c_double * d)(*lo_l), (C.c_double * d)(*hi_l), (C.c_int * d)(*nb)
+    nbytes = C.c_size_t()
+    ctx.check(ctx.lib.bumbar_query_workspace_pmf(ctx.h, N, C.byref(nbytes)))
+    ws = ctx.workspace(nbytes.value)
+    total = 1
+    for v in nb:
+        total *= v
+    F = torch.empty(total, dtype=torch.float64, device=dev)
+    rc = ctx.lib.bumbar_pmf(ctx.h, _ptr(xi_t), N, d, _ptr(p_t), lo_a, hi_a, nb_a, _ptr(ws),
+                            ws.numel(), _ptr(F))
+    _keep(ctx, xi_t, p_t)
+    ctx.check(rc)
+    return F.reshape(nb)
 
 
 def _model_args(xi, coef, ctx):

@@ -65,7 +65,7 @@ class Stats(C.Structure):
                 ("time_final_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
                 ("checks_capacity", C.c_int), ("graph_batches", C.c_int64),
-                ("grid_sweeps", C.c_int64)]
+                ("grid_sweeps", C.c_int64), ("batched_steps", C.c_int64)]
 
 
 class ServerOptions(C.Structure):
@@ -100,6 +100,9 @@ SIGNATURES = {
     "bumbar_bin": (C.c_int, [vp, vp, C.c_int64, C.c_int, C.c_int64, vp, C.c_size_t, u64p, i64p,
                              vp, vp, vp]),
     "bumbar_reweight": (C.c_int, [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
+    "bumbar_query_workspace_pmf": (C.c_int, [vp, C.c_int64, C.POINTER(C.c_size_t)]),
+    "bumbar_pmf": (C.c_int, [vp, vp, C.c_int64, C.c_int, vp, dp, dp, C.POINTER(C.c_int), vp,
+                             C.c_size_t, vp]),
     "bumbar_query_workspace_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int,
                                                C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "bumbar_sweep_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, C.c_int, vp,

@@ -269,6 +269,14 @@ class BatchGraphs {
     ctx_->stream = work;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx_->cap_stream, &g);
+    // a batch whose work went to another stream captures nothing, and its
+    // replays would do nothing: refuse it
+    size_t nodes = 0;
+    if (rc == BUMBAR_OK && e == hipSuccess && hipGraphGetNodes(g, nullptr, &nodes) == hipSuccess &&
+        nodes == 0) {
+      (void)hipGraphDestroy(g);
+      return fail(ctx_, BUMBAR_EDEVICE, "a captured batch of binned steps holds no work");
+    }
     hipGraphExec_t x = nullptr;
     if (rc == BUMBAR_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
@@ -414,6 +422,22 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     return sweep_at(ctx, B, level_mat64(L), L.P, L.h, Nk_dev, fin, fh(slot), BB.logD_lvl,
                     B.lnS_t, B.S_t, sc, false, nullptr);
   };
+  // a batch of steps on a stored level of at most 512 bins: one workgroup
+  // with the matrix in registers runs them all (same outputs per step);
+  // counted after each batch, since a graph replay does not call the lambda
+  int64_t batched = 0;
+  auto small_level = [&](const Level& L) {
+    const Mat M = level_mat(L);
+    return M.kind == 0 && M.u != nullptr && small_batch_nc(K, L.P) != 0;
+  };
+  auto small_batch = [&](const Level& L, const double* fin, int T) -> int {
+    const Mat M = level_mat(L);
+    // ctx->stream, not s: while a batch is captured it names the capture stream
+    hipError_t e2 = launch_small_batch(ctx->stream, reinterpret_cast<const double*>(M.u), M.ld, K, L.P,
+                                       L.h, Nk_dev, fin, T, fh(0), B.scal_hist, BB.logD_lvl,
+                                       B.lnS_t, B.S_t, B.cst, B.gk, B.lnNp);
+    return e2 == hipSuccess ? BUMBAR_OK : hip_fail(ctx, e2, "small batch");
+  };
   int64_t it1 = 0, it2 = 0, nchk = 0;
   int result = BUMBAR_OK;
   BatchGraphs graphs(ctx, opt.graphs != 0);
@@ -428,6 +452,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     int nvalid = 0;  // leading steps that are usable
     if (fast) {
       rc = graphs.run({1, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+        if (small_level(cur)) return small_batch(cur, BB.f_n, (int)T);
         for (int i = 0; i < T; ++i) {
           // each step's finaliser leaves the constants of the next step in B.cst
           const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
@@ -438,6 +463,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         return BUMBAR_OK;
       });
       if (rc) return rc;
+      if (small_level(cur)) batched += T;
       rc = read_hist((int)T);
       if (rc) return rc;
       while (nvalid < T && !flagged(hs[nvalid])) ++nvalid;
@@ -486,6 +512,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
           break;
         }
         rc = graphs.run({2, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+          if (small_level(cur)) return small_batch(cur, BB.f_n, T);
           for (int i = 0; i < T; ++i) {
             const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                                       i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
@@ -495,6 +522,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
           return BUMBAR_OK;
         });
         if (rc) return rc;
+        if (small_level(cur)) batched += T;
         rc = read_hist(T);
         if (rc) return rc;
         for (int i = 0; i < T; ++i) fallback = fallback || flagged(hs[i]);
@@ -510,11 +538,16 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         in = T;
         ix = T + 1;
         rc = graphs.run({3, T, level_id(cur), cur.P, level_id(nxt), nxt.P}, [&]() -> int {
-          for (int i = 0; i < T; ++i) {
-            const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
-                                      i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
-                                      B.S_t, B.scal_hist + i, i > 0, B.cst);
+          if (T > 0 && small_level(cur)) {
+            const int r = small_batch(cur, BB.f_n, T);
             if (r) return r;
+          } else {
+            for (int i = 0; i < T; ++i) {
+              const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
+                                        i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl,
+                                        B.lnS_t, B.S_t, B.scal_hist + i, i > 0, B.cst);
+              if (r) return r;
+            }
           }
           const double* fin = T == 0 ? BB.f_n : fh(T - 1);
           // both probes start from fin: the first reuses the constants the last
@@ -527,6 +560,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
           return r;
         });
         if (rc) return rc;
+        if (T > 0 && small_level(cur)) batched += T;
         rc = read_hist(T + 2);
         if (rc) return rc;
         for (int i = 0; i < T + 2; ++i) fallback = fallback || flagged(hs[i]);
@@ -590,6 +624,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   st->phase2_iters = it2;
   st->n_checks = nchk;
   st->graph_batches += graphs.launched();
+  st->batched_steps += batched;
   st->time_binning_ms = t_bin;
   st->time_binned_ms = now_ms() - t_start - t_bin;
   return result;

@@ -85,6 +85,18 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
                                  const int64_t* Nk, double* f_new, double* lnS, double* S_out,
                                  SweepScalars* out, double* cst_next = nullptr);
 
+// T consecutive steps (sweep + finaliser, mode 0) of a stored K x P problem
+// with column multiplicities h in one workgroup (sweep_small.hip): step i
+// starts from f_in (i = 0) or f_hist row i - 1 and writes f_hist row i and
+// scal[i]; ln D (P), ln S and S (K) of the last step; after the batch cst,
+// gk and lnNp as launch_prepare_consts would leave them for the last f.
+// small_batch_nc(K, P) is 0 where the batch kernel does not apply.
+int small_batch_nc(int K, int64_t P);
+hipError_t launch_small_batch(hipStream_t s, const double* u, int64_t ld, int K, int64_t P,
+                              const double* h, const int64_t* Nk, const double* f_in, int T,
+                              double* f_hist, SweepScalars* scal, double* logD, double* lnS,
+                              double* S, double* cst, double* gk, double* lnNp);
+
 // cst_k = ln N'_k + f_k, gk, lnNp from N_k and f.
 hipError_t launch_prepare_consts(hipStream_t s, int K, const int64_t* Nk, const double* f,
                                  double* cst, double* gk, double* lnNp);

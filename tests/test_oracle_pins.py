@@ -355,3 +355,78 @@ def test_bumbar_mean_representatives_2d(orc):
     assert np.max(np.abs(f - f_ref)) < 1e-9
     f2, info2 = orc.bumbar(p["u"], p["Nk"], p["xi"], p["model_type"], p["coef"], tol=1e-11)
     assert np.max(np.abs(f2 - f_ref)) < 1e-9
+
+
+def test_pmf_uniform_weights_are_histogram_counts(orc):
+    # With p_n = 1/N the surface is -ln of the normalised histogram. Samples
+    # sit at least 1e-6 of a bin away from every edge, so no rounding of the
+    # bin formula can move one; bins on the sides stay empty (+inf).
+    g = np.random.default_rng(3)
+    nb, lo, hi = 40, -2.0, 3.0
+    w = (hi - lo) / nb
+    cells = g.integers(5, 35, 20000)
+    x = lo + (cells + g.uniform(1e-6, 1 - 1e-6, cells.size)) * w
+    p = np.full(x.size, 1.0 / x.size)
+    F = orc.pmf(x, p, lo, hi, nb)
+    counts = np.bincount(cells, minlength=nb)
+    for b in range(nb):
+        if counts[b]:
+            assert F[b] == pytest.approx(-math.log(counts[b] / x.size), rel=1e-13)
+        else:
+            assert F[b] == math.inf
+    hist, _ = np.histogram(x, bins=nb, range=(lo, hi), weights=p)
+    ok = hist > 0
+    assert np.allclose(np.exp(-F[ok]), hist[ok], rtol=1e-13, atol=0)
+
+
+def test_pmf_2d_row_major_and_weighted(orc):
+    # Unequal bin counts per axis, so a transposed index or swapped axis
+    # fails; weights differ per sample, so a dropped p_n fails.
+    g = np.random.default_rng(4)
+    nb = (7, 5)
+    lo, hi = (0.0, -1.0), (7.0, 4.0)
+    i = g.integers(0, nb[0], 5000)
+    j = g.integers(0, nb[1], 5000)
+    x = np.stack([i + g.uniform(0.01, 0.99, i.size), j - 1.0 + g.uniform(0.01, 0.99, j.size)], 1)
+    p = g.uniform(0.1, 1.0, i.size)
+    F = orc.pmf(x, p, lo, hi, nb)
+    assert F.shape == nb
+    for a in range(nb[0]):
+        for b in range(nb[1]):
+            s = p[(i == a) & (j == b)].sum()
+            assert F[a, b] == pytest.approx(-math.log(s), rel=1e-12)
+    H, _, _ = np.histogram2d(x[:, 0], x[:, 1], bins=nb, range=[[0, 7], [-1, 4]], weights=p)
+    assert np.allclose(np.exp(-F), H, rtol=1e-12, atol=0)
+
+
+def test_pmf_edges_and_outside_samples(orc):
+    # x = lo is in the first bin, x = hi and anything past either end is left
+    # out; a bin whose samples all carry p = 0 has F = +inf.
+    x = np.array([0.0, 0.5, 0.999, 1.0, -0.1, 2.0, 0.25])
+    p = np.array([0.1, 0.2, 0.3, 0.9, 0.9, 0.9, 0.0])
+    F = orc.pmf(x, p, 0.0, 1.0, 4)
+    assert F[0] == pytest.approx(-math.log(0.1))
+    assert F[1] == math.inf  # only the p = 0 sample
+    assert F[2] == pytest.approx(-math.log(0.2))
+    assert F[3] == pytest.approx(-math.log(0.3))
+    with pytest.raises(RuntimeError):
+        orc.pmf(x, p, 1.0, 1.0, 4)
+    with pytest.raises(RuntimeError):
+        orc.pmf(x, p, 0.0, 1.0, 0)
+
+
+def test_pmf_of_reweighted_samples_is_target_potential(orc):
+    # Samples of the state u_0 = x^2 / 2 (standard normal) reweighted to
+    # u_1 = (x - 1/2)^2 / 2 with the one-state solution (logD_n = -u_0,n up to
+    # a constant, removed by the normalisation of Eqs. (5)-(6)); the surface
+    # then approaches u_1 plus a constant where the bins are well sampled.
+    g = np.random.default_rng(11)
+    x = g.normal(0.0, 1.0, 2_000_000)
+    u0, u1 = 0.5 * x ** 2, 0.5 * (x - 0.5) ** 2
+    p = orc.reweight(u1, -u0)
+    nb, lo, hi = 20, -1.0, 1.5
+    F = orc.pmf(x, p, lo, hi, nb)
+    c = lo + (np.arange(nb) + 0.5) * (hi - lo) / nb
+    ref = 0.5 * (c - 0.5) ** 2
+    shift = np.mean(F - ref)
+    assert np.max(np.abs(F - ref - shift)) < 0.02
