@@ -267,6 +267,8 @@ __global__ void __launch_bounds__(NW * 64)
   __shared__ double red1[2][NW][TN];
   __shared__ double red2[2][NW][TN];
   __shared__ double c_sh[ROWS * RG];
+  __shared__ double tr[ROWS * RG * (LPR + 1)];  // per-state lane sums at the end
+  static_assert(LPR % 4 == 0, "lane sums are taken four at a time");
   __shared__ unsigned fl;
 
   const int tid = threadIdx.x;
@@ -315,15 +317,24 @@ __global__ void __launch_bounds__(NW * 64)
                                                  logD, red1[par], red2[par], acc, obj, bad);
   }
 
-  // Reduce each state's accumulator over the LPR lanes of its row group
-  // (contiguous lanes; xor butterfly, identical result in every lane).
+  // Each state's accumulators over the LPR lanes of its row group: through
+  // LDS (rows padded by one against bank conflicts), then one thread per
+  // state adds its LPR values in lane order. A butterfly of shuffles per
+  // state would chain ROWS x log2(LPR) dependent LDS round trips instead.
 #pragma unroll
-  for (int j = 0; j < ROWS; ++j) {
-    double v = acc[j];
+  for (int j = 0; j < ROWS; ++j) tr[(rg + RG * j) * (LPR + 1) + lc] = acc[j];
+  __syncthreads();
+  for (int k = tid; k < K && k < ROWS * RG; k += NT) {
+    const double* row = &tr[k * (LPR + 1)];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-    for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, 64);
-    const int k = rg + RG * j;
-    if (lc == 0 && k < K) part[(int64_t)k * gridDim.x + blockIdx.x] = v;  // state-major
+    for (int l = 0; l < LPR; l += 4) {
+      s0 += row[l];
+      s1 += row[l + 1];
+      s2 += row[l + 2];
+      s3 += row[l + 3];
+    }
+    part[(int64_t)k * gridDim.x + blockIdx.x] = (s0 + s1) + (s2 + s3);  // state-major
   }
   // objective partial: sum over the block (wave butterflies, then waves in order)
   double o = obj;
@@ -674,11 +685,12 @@ __global__ void __launch_bounds__(256)
   if (lane == 0) S[k] = v;
 }
 
+// MODE 0: fast-path partials, 1: (M, S) pairs of the robust sweep.
 // nstate: partials per state in part (mode 0: nparts, or 1 after
 // part_reduce_kernel); nparts: entries of part_obj and part_flags.
-template <int FT>
+template <int FT, int MODE>
 __global__ void __launch_bounds__(FT)
-    sweep_finalize_kernel(int mode, int K, int nstate, int nparts, const double* __restrict__ part,
+    sweep_finalize_kernel(int K, int nstate, int nparts, const double* __restrict__ part,
                           const double* __restrict__ partS, const double* __restrict__ part_obj,
                           const unsigned* __restrict__ part_flags, const double* __restrict__ f,
                           const double* __restrict__ lnNp, const int64_t* __restrict__ Nk,
@@ -688,42 +700,60 @@ __global__ void __launch_bounds__(FT)
   __shared__ double sh[FT / 64][6];
   __shared__ double f0s;
   __shared__ unsigned flags_sh;
+  // unnormalised f_new: in LDS when it fits (no global round trip before
+  // the gauge is applied), else in f_new itself
+  constexpr int kFinLds = 2048;
+  __shared__ double fsh[kFinLds];
+  double* fbuf = (K <= kFinLds) ? fsh : f_new;
   const int tid = threadIdx.x;
   if (tid == 0) flags_sh = 0u;
-  unsigned fl = 0u;
-  for (int i = tid; i < nparts; i += FT) fl |= part_flags[i];
+  // the first flag and objective partial of each thread are loaded up front,
+  // together with the state partials below (one memory round trip, not three)
+  const int t0 = tid < nparts ? tid : nparts - 1;
+  const unsigned fl_first = part_flags[t0];
+  const double ob_first = part_obj[t0];
+  unsigned fl = tid < nparts ? fl_first : 0u;
+  double ob0 = tid < nparts ? ob_first : 0.0;
   Red6 v{0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
-  for (int p = tid; p < nparts; p += FT) v.ob += part_obj[p];
   // Fast-path partials: T lanes per state (T a power of two, consecutive
   // lanes of one wave) each add every T-th partial, then a fixed xor
   // butterfly combines them, so the order of additions never changes.
   int T = 1;
-  if (mode == 0 && nstate > 1)
+  if (MODE == 0 && nstate > 1)
     while (T < 64 && 2 * T * K <= FT) T *= 2;
   const int kstride = FT / T;
   const int kfirst = tid / T, lane_c = tid % T;
   for (int k0 = 0; k0 < K; k0 += kstride) {
     const int k = k0 + kfirst;
     double Sp = 0.0;
-    if (mode == 0 && k < K) {
+    if (MODE == 0 && k < K) {
       // fast-path partials are state-major: part[k * nstate + p]
+      // eight predicated loads in flight per lane, the ragged end included
       const double* pk = part + (int64_t)k * nstate;
-      int p = lane_c;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (; p + 3 * T < nstate; p += 4 * T) {
-        s0 += pk[p];
-        s1 += pk[p + T];
-        s2 += pk[p + 2 * T];
-        s3 += pk[p + 3 * T];
+      double a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = 0.0;
+      // (clamped addresses and a select, not a branch per load: a branch
+      // would wait for each load before the next)
+      for (int p = lane_c; p < nstate; p += 8 * T) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = p + q * T;
+          const double x = pk[i < nstate ? i : nstate - 1];
+          a[q] += i < nstate ? x : 0.0;
+        }
       }
-      for (; p < nstate; p += T) s0 += pk[p];
-      Sp = (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int w = 4; w >= 1; w >>= 1)
+#pragma unroll
+        for (int q = 0; q < w; ++q) a[q] += a[q + w];
+      Sp = a[0];
     }
-    if (mode == 0)
+    if (MODE == 0)
       for (int off = 1; off < T; off <<= 1) Sp += __shfl_xor(Sp, off, 64);
     if (k >= K || lane_c != 0) continue;
     double lnS, fn, S;
-    if (mode == 0) {
+    if (MODE == 0) {
       S = Sp;
       lnS = log(S);
       fn = lnNp[k] + f[k] - lnS;
@@ -740,7 +770,7 @@ __global__ void __launch_bounds__(FT)
     }
     if (lnS_out) lnS_out[k] = lnS;
     if (S_out) S_out[k] = S;
-    f_new[k] = fn;
+    fbuf[k] = fn;
     if (Nk[k] > 0) {
       const double g = S - (double)Nk[k];
       v.gsq += g * g;
@@ -748,13 +778,18 @@ __global__ void __launch_bounds__(FT)
     }
     if (fn != fn) fl |= FLAG_NAN;
   }
+  for (int i = tid + FT; i < nparts; i += FT) {
+    fl |= part_flags[i];
+    ob0 += part_obj[i];
+  }
+  v.ob = ob0;
   __syncthreads();  // flags_sh initialised; f_new complete
   if (fl) atomicOr(&flags_sh, fl);
-  if (tid == 0) f0s = f_new[0];
+  if (tid == 0) f0s = fbuf[0];
   __syncthreads();
   const double f0 = f0s;
   for (int k = tid; k < K; k += FT) {
-    const double fn = f_new[k] - f0;
+    const double fn = fbuf[k] - f0;
     f_new[k] = fn;
     // the constants of a sweep at f_new (what prepare_consts would write)
     if (cst_next) cst_next[k] = lnNp[k] + fn;
@@ -793,26 +828,36 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
   // partials the per-state sums first, one wave per state over all CUs
   // (scratch: partS, which the fast-path mode does not use otherwise)
   if (K <= 256 && nparts <= 16) {
-    hipLaunchKernelGGL(sweep_finalize_kernel<256>, dim3(1), dim3(256), 0, s, mode, K, nparts,
-                       nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
-                       out, cst_next);
+    if (mode == 0)
+      hipLaunchKernelGGL((sweep_finalize_kernel<256, 0>), dim3(1), dim3(256), 0, s, K, nparts,
+                         nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                         out, cst_next);
+    else
+      hipLaunchKernelGGL((sweep_finalize_kernel<256, 1>), dim3(1), dim3(256), 0, s, K, nparts,
+                         nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                         out, cst_next);
     return hipGetLastError();
   }
-  // the single workgroup takes about nparts / (4 T) dependent load rounds
+  // the single workgroup takes about nparts / (8 T) dependent load rounds
   // (T lanes per state, as in the kernel); beyond a few rounds one more
   // launch that spreads the sums over the chip is cheaper
   int T = 1;
   while (T < 64 && 2 * T * K <= 1024) T *= 2;
   int nstate = nparts;
-  if (mode == 0 && partS != nullptr && nparts > 16 * T) {
+  if (mode == 0 && partS != nullptr && nparts > 32 * T) {
     hipLaunchKernelGGL(part_reduce_kernel, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, K,
                        nparts, part, partS);
     part = partS;
     nstate = 1;
   }
-  hipLaunchKernelGGL(sweep_finalize_kernel<1024>, dim3(1), dim3(1024), 0, s, mode, K, nstate,
-                     nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
-                     out, cst_next);
+  if (mode == 0)
+    hipLaunchKernelGGL((sweep_finalize_kernel<1024, 0>), dim3(1), dim3(1024), 0, s, K, nstate,
+                       nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                       out, cst_next);
+  else
+    hipLaunchKernelGGL((sweep_finalize_kernel<1024, 1>), dim3(1), dim3(1024), 0, s, K, nstate,
+                       nparts, part, partS, part_obj, part_flags, f, lnNp, Nk, f_new, lnS, S_out,
+                       out, cst_next);
   return hipGetLastError();
 }
 
