@@ -360,7 +360,8 @@ struct FastCfg {
 };
 static const FastCfg kCfgs[] = {
     {8, 4, 64, 2, 2, 1, 1},    {16, 4, 64, 2, 4, 1, 1},   {32, 4, 64, 2, 8, 1, 1},
-    {64, 4, 32, 2, 8, 1, 1},   {104, 4, 32, 2, 13, 0, 0}, {128, 4, 32, 2, 16, 0, 1},
+    {56, 4, 32, 2, 7, 1, 1},   {64, 4, 32, 2, 8, 1, 1},   {104, 4, 32, 2, 13, 0, 0},
+    {128, 4, 32, 2, 16, 0, 1},
     {256, 8, 32, 2, 16, 0, 1},
 };
 // Extra instantiations reachable through BUMBAR_SWEEP_CFG="nw,lpr,cpl,rows,pf,sg"
@@ -453,6 +454,7 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
   BUMBAR_CFG(4, 64, 2, 2, 1, 1)
   BUMBAR_CFG(4, 64, 2, 4, 1, 1)
   BUMBAR_CFG(4, 64, 2, 8, 1, 1)
+  BUMBAR_CFG(4, 32, 2, 7, 1, 1)
   BUMBAR_CFG(4, 32, 2, 8, 1, 1)
   BUMBAR_CFG(4, 32, 2, 13, 0, 0)
   BUMBAR_CFG(4, 32, 2, 16, 0, 1)

@@ -15,6 +15,10 @@ sample sets of 1e4-1e7 points, Sections 3-4):
 * ``double_well``      1-D umbrella sampling of U(x) = (x^2 - 1)^2 with
                        Metropolis chains.
 * ``ladder_2d``        temperature/alchemical ladder u_kn = beta_k E_n + lambda_k V_n.
+* ``temperature_ladder`` the shape of the paper's parallel-tempering example
+                       (Section 4): K = 50 temperatures spaced geometrically
+                       over a factor of two, u_kn = beta_k E_n, unit-variance
+                       energies at 80% neighbour overlap.
 * ``muller_brown_grid`` 2-D umbrella grid on a scaled Muller-Brown surface.
 * ``serving_stream``   a Poisson stream of independent small problems.
 
@@ -148,6 +152,27 @@ def ladder_2d(K=1000, Nk=2000, seed=2, beta_range=(0.5, 2.0), delta=OVERLAP80_DE
     xi = np.stack([E, V], axis=1)
     return _problem(u, np.full(K, Nk), xi, MODEL_LINEAR, coef, beta=beta, lam=lam,
                     name=f"ladder_2d K={K} Nk={Nk}")
+
+
+def temperature_ladder(K=50, Nk=200000, seed=3, beta_range=(1.0, 2.0), delta=OVERLAP80_DELTA,
+                       materialize=True):
+    """Temperature ladder u_kn = beta_k E_n (1-D, LINEAR model on E).
+
+    beta_k = b0 (b1/b0)^(k/(K-1)): temperatures geometric over a factor of
+    b1/b0 = 2 (as 298 K to 600 K in the paper's replica set). State k draws
+    Nk energies E ~ N(-delta k, 1), delta giving 80% overlap between
+    neighbouring energy histograms.
+    """
+    g = _rng(seed)
+    ks = np.arange(K)
+    t = ks / max(K - 1, 1)
+    beta = beta_range[0] * (beta_range[1] / beta_range[0]) ** t
+    E = np.concatenate([g.normal(-delta * k, 1.0, Nk) for k in range(K)])
+    u = (beta[:, None] * E[None, :]) if materialize else None
+    coef = np.zeros((K, 3))
+    coef[:, 1] = beta
+    return _problem(u, np.full(K, Nk), E[:, None], MODEL_LINEAR, coef, beta=beta,
+                    name=f"temperature_ladder K={K} Nk={Nk}")
 
 
 # Muller-Brown potential (Muller & Brown, Theor. Chim. Acta 53, 75 (1979)).

@@ -43,11 +43,17 @@ def schedule(info):
             for c in info["checks"]]
 
 
-def same_solve(bm, args, kw):
+def same_solve(bm, args, kw, batched=None):
     f1, i1 = bm.solve(*args, graphs=1, **kw)
     f0, i0 = bm.solve(*args, graphs=0, **kw)
     say("  graph batches", i1["graph_batches"], "phase1", i1["phase1_iters"], "phase2",
-        i1["phase2_iters"], "checks", i1["n_checks"])
+        i1["phase2_iters"], "checks", i1["n_checks"], "single-workgroup steps",
+        i1["batched_steps"])
+    # the first level (at most 128 bins here) runs in single-workgroup batches
+    # whenever its matrix is stored in FP64
+    if batched is not None:
+        assert (i1["batched_steps"] > 0) == batched
+        assert i1["batched_steps"] == i0["batched_steps"]
     assert i1["status"] == i0["status"] == 0
     assert i0["graph_batches"] == 0
     # each replay is a batch: a stage of several levels replays some shapes
@@ -62,21 +68,22 @@ def test_graphs_stored_representatives(bm):
     p = synth.double_well(K=30, Nk=700, seed=5)
     say(f"stored u, 1-D: K={p['K']} N={p['N']}")
     same_solve(bm, (dev(p["u"]), p["Nk"]),
-               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11))
+               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11), batched=True)
 
 
 def test_graphs_model_fp64_centres(bm):
     p = synth.double_well(K=40, Nk=800, seed=9)
     say(f"on the fly, FP64 centres: K={p['K']} N={p['N']}")
     same_solve(bm, (None, p["Nk"]),
-               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11))
+               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11), batched=True)
 
 
 def test_graphs_model_fp32_centres(bm):
     p = synth.ladder_2d(K=300, Nk=40, seed=6)
     say(f"on the fly, mixed precision: K={p['K']} N={p['N']}")
     same_solve(bm, (None, p["Nk"]),
-               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], precision=1, tol=1e-11))
+               dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], precision=1, tol=1e-11),
+               batched=False)
 
 
 def test_graphs_on_a_side_stream(bm):

@@ -51,7 +51,8 @@ def random_problem(K, N, seed, unsampled=()):
     return u, Nk, x
 
 
-SHAPES = [(1, 37), (2, 129), (3, 1000), (8, 8000), (13, 515), (64, 3001), (65, 2047),
+SHAPES = [(1, 37), (2, 129), (3, 1000), (8, 8000), (13, 515), (33, 130), (50, 4099), (56, 777),
+          (57, 300), (64, 3001), (65, 2047),
           (100, 12345), (128, 4097), (200, 2500), (256, 1111), (300, 1500), (1000, 700)]
 
 
