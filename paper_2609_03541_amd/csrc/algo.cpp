@@ -100,10 +100,24 @@ static int nonempty(bumbar_ctx* ctx, BinnedBufs& BB, uint64_t m, int64_t* g) {
   return read_bytes(ctx, BB.counts, g, sizeof(int64_t));
 }
 
-// 1-D: the same bisection, with the midpoints of the next kLevels levels of
-// the bisection tree evaluated in one pass and the path then walked on the
-// host, so each round costs one readback instead of one per probe.
-constexpr int kLevels = 6;  // 63 midpoints per round (+ m = 1 in the first)
+// 1-D: the same bisection, with the midpoints of the next k levels of the
+// bisection tree evaluated in one pass and the path then walked on the host,
+// so each round costs one readback instead of one per probe. A pass costs a
+// launch and readback (about 30 us) plus N x 2^k lane steps of the count
+// kernel (about 0.32 ps each on MI355X); k minimises the whole search,
+// ceil(32 / k) passes: 6 levels (63 midpoints) for small N, 3 at N = 1e7.
+static int bisection_levels(int64_t N) {
+  int best = 6;
+  double best_us = 1e300;
+  for (int k = 2; k <= 6; ++k) {
+    const double us = std::ceil(32.0 / k) * (30.0 + (double)N * (double)(1 << k) * 3.2e-7);
+    if (us < best_us) {
+      best_us = us;
+      best = k;
+    }
+  }
+  return best;
+}
 
 static void subtree_mids(uint64_t lo, uint64_t hi, int depth, std::vector<uint64_t>* out) {
   if (depth == 0 || hi - lo <= 1) return;
@@ -135,9 +149,10 @@ static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t*
     gs.resize(ms.size());
     return read_bytes(ctx, dev_g, gs.data(), sizeof(unsigned long long) * ms.size());
   };
+  const int levels = bisection_levels(BB.N);
   uint64_t lo = 1, hi = 4294967296ull;
   ms.push_back(1);
-  subtree_mids(lo, hi, kLevels, &ms);
+  subtree_mids(lo, hi, levels, &ms);
   int rc = eval();
   if (rc) return rc;
   const int64_t g1 = (int64_t)gs[0];
@@ -167,7 +182,7 @@ static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t*
     }
     if (hi - lo <= 1) break;
     ms.clear();
-    subtree_mids(lo, hi, kLevels, &ms);
+    subtree_mids(lo, hi, levels, &ms);
     rc = eval();
     if (rc) return rc;
   }

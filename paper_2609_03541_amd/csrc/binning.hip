@@ -240,28 +240,33 @@ __device__ __forceinline__ uint32_t div_by_magic(uint32_t q, uint64_t m, uint64_
 
 constexpr int kRunChunk = 256;  // sorted coordinates per wave and pass
 
-// Lanes are probes: lane j of a wave counts, for width m_j, the positions in
-// a chunk of kRunChunk consecutive sorted coordinates where floor(q / m_j)
-// changes (one division per element and probe, against the previous
-// element's). Every lane reads the same coordinate at a time, so nothing is
-// exchanged between lanes until one sum per block and probe, added with one
-// integer atomic.
+// Lane (p, s) of a wave counts, for width m_p, the positions where
+// floor(q / m_p) changes (one division per element, against the previous
+// element's) in stream s of a chunk of kRunChunk consecutive sorted
+// coordinates. With MP probe slots (a power of two >= the number of probes)
+// a chunk splits into 64 / MP streams, so a pass costs N x MP lane steps:
+// with all 64 slots every lane reads the same coordinate at a time. Nothing
+// is exchanged between lanes until one sum per block and probe, added with
+// one integer atomic.
 __global__ void __launch_bounds__(kBT)
     count_runs_1d_multi_kernel(const uint32_t* __restrict__ qs, int64_t N,
-                               const uint64_t* __restrict__ ms, int M,
+                               const uint64_t* __restrict__ ms, int M, int MP,
                                unsigned long long* __restrict__ counts) {
   __shared__ unsigned long long sred[kBT / 64][kMaxProbes];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const bool act = lane < M;
-  const uint64_t m = act ? ms[2 * lane] : 1ull;
-  const uint64_t mg = act ? ms[2 * lane + 1] : 0ull;
+  const int p = lane % MP, st = lane / MP;
+  const int len = kRunChunk / (64 / MP);  // coordinates per stream
+  const bool act = p < M;
+  const uint64_t m = act ? ms[2 * p] : 1ull;
+  const uint64_t mg = act ? ms[2 * p + 1] : 0ull;
   const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;
   const int64_t nw = (int64_t)gridDim.x * (kBT / 64);
   unsigned long long c = 0;
   for (int64_t ch = (int64_t)blockIdx.x * (kBT / 64) + wave; ch < nchunks; ch += nw) {
-    const int64_t b = ch * kRunChunk;
-    const int64_t e = std::min<int64_t>(N, b + kRunChunk);
+    const int64_t b = ch * kRunChunk + (int64_t)st * len;
+    const int64_t e = std::min<int64_t>(N, b + len);
+    if (b >= e) continue;
     int64_t i = b;
     uint32_t dp;
     if (b == 0) {
@@ -282,7 +287,8 @@ __global__ void __launch_bounds__(kBT)
   __syncthreads();
   if (threadIdx.x < M) {
     unsigned long long t = 0;
-    for (int w = 0; w < kBT / 64; ++w) t += sred[w][threadIdx.x];
+    for (int w = 0; w < kBT / 64; ++w)
+      for (int q = 0; q < 64 / MP; ++q) t += sred[w][q * MP + threadIdx.x];
     if (t) atomicAdd(&counts[threadIdx.x], t);
   }
 }
@@ -312,11 +318,13 @@ uint64_t width_magic(uint64_t m) {
 hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
                                  const uint64_t* ms, int M, unsigned long long* counts) {
   if (M < 1 || M > kMaxProbes) return hipErrorInvalidValue;
+  int MP = 4;  // probe slots per wave: a power of two, 64 / MP streams of >= 4 coordinates
+  while (MP < M) MP *= 2;
   const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;
   const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(1024, (nchunks + 3) / 4));
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kMaxProbes), 0, s, counts, M);
   hipLaunchKernelGGL(count_runs_1d_multi_kernel, dim3((unsigned)nb), dim3(kBT), 0, s, q_sorted, N,
-                     ms, M, counts);
+                     ms, M, MP, counts);
   return hipGetLastError();
 }
 

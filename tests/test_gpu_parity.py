@@ -181,6 +181,30 @@ def test_binning_bit_exact(bm, d):
         assert np.array_equal(sb.cpu().numpy(), sb_ref)
 
 
+@pytest.mark.parametrize("N", [700001, 3000017, 12000007, 40000003])
+def test_binning_large_1d(bm, N):
+    # Large N evaluates fewer bisection levels per pass (5, 4, 3 and 2 here),
+    # so the count kernel splits its chunks into 2, 4, 8 and 16 streams. At
+    # N = 7e5 the oracle's own search runs; above it (seconds per probe) the
+    # GPU's m is checked by the bisection's end state g(m) >= n > g(m + 1)
+    # with the oracle's g, and the histogram at m against the oracle's.
+    g = np.random.default_rng(N)
+    xi = g.normal(0, 1, size=(N, 1))
+    xi[:1000] = xi[1000:2000]  # duplicate points
+    q, lo, sc = oracle.quantize(xi)
+    for n in ([100, 10000, 1000000] if N < 1000000 else [1000, 1000000]):
+        say(f"binning d=1 N={N} n={n}")
+        m, cells, H, _ = bm.bin_coordinates(xi, n)
+        if N < 1000000:
+            m_ref, _, _ = oracle.width_search(q, n)
+            assert m == m_ref
+        else:
+            assert oracle.nonempty_bins(q, m) >= n > oracle.nonempty_bins(q, m + 1)
+        cells_ref, H_ref, _ = oracle.histogram(q, m)
+        assert np.array_equal(cells.cpu().numpy().view(np.uint64), cells_ref)
+        assert np.array_equal(H.cpu().numpy(), H_ref)
+
+
 def test_bumbar_solve_matches_oracle_1d(bm):
     p = synth.double_well(K=30, Nk=700, seed=5)
     f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
