@@ -43,9 +43,15 @@ overlap, stored as a 4 GB FP64 matrix built on the device. BU-MBAR (bins on
 E, model representatives, Newton finisher) against plain SCI and plain
 Newton (one SCI step, then Newton) on the same GPU, each to the tolerance.
 
+With --workload scaling: the replica-count study of the paper's synthetic
+section in reduced form (one seed, own solver variants): temperature ladders
+of M = 10, 30, 100, 300 states with N_k = N0, N0/M and N0/M^2 samples per
+state (N0 = 1e4, 3e6, 9e8: 1e4 per state at M = 300 in all three), each
+solved by BU-MBAR and plain Newton, and by plain SCI up to M = 100.
+
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
        python bench.py --workload stream [--n-problems 512] [--rate 100]
-       python bench.py --workload ladder|mb2d|tladder [--steps 2]
+       python bench.py --workload ladder|mb2d|tladder|scaling [--steps 2]
 """
 from __future__ import annotations
 
@@ -76,7 +82,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["double_well", "stream", "ladder", "mb2d", "tladder"],
+    ap.add_argument("--workload",
+                    choices=["double_well", "stream", "ladder", "mb2d", "tladder", "scaling"],
                     default="double_well")
     ap.add_argument("--n-problems", type=int, default=512)
     ap.add_argument("--rate", type=float, default=100.0, help="stream arrivals per second")
@@ -111,6 +118,8 @@ def main():
         return run_mb2d(args, bm, synth)
     if args.workload == "tladder":
         return run_tladder(args, bm, synth)
+    if args.workload == "scaling":
+        return run_scaling(args, bm, synth)
     dev = torch.device("cuda:0")
     t = time.time()
     p = synth.double_well(K=100, Nk=10000, seed=1)
@@ -376,6 +385,66 @@ def run_tladder(args, bm, synth):
                                       for k, v in res.items() if k != "bumbar"},
         "sweep_kernel_us": sw * 1e6,
         "grad_norm": res["bumbar"]["info"]["grad_norm"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": None,
+    })
+    print(json.dumps(out), flush=True)
+
+
+def run_scaling(args, bm, synth):
+    import torch
+    ctx = bm.context()
+    scen = {"i": (1e4, 0), "ii": (3e6, 1), "iii": (9e8, 2)}  # N_k = N0 / M^power
+    table = []
+    top = None
+    for M in (10, 30, 100, 300):
+        for sname, (n0, pw) in scen.items():
+            nk = int(round(n0 / M ** pw))
+            p = synth.temperature_ladder(K=M, Nk=nk, seed=11 + M, materialize=False)
+            K, N = p["K"], p["N"]
+            xi = torch.tensor(p["xi"], device="cuda")
+            coef = torch.tensor(p["coef"], device="cuda")
+            u = bm.model_energies(xi, coef, bm.MODEL_LINEAR, K)
+            Nk = torch.tensor(p["Nk"], device="cuda")
+            torch.cuda.synchronize()
+            variants = {
+                "bumbar": dict(xi=xi, model=bm.MODEL_LINEAR, coef=coef),
+                "newton": dict(binning=False, finisher=bm.FINISH_NEWTON, sci_switch=1e300),
+            }
+            if M <= 100:
+                variants["sci"] = dict(binning=False, finisher=bm.FINISH_SCI, max_iter=20000)
+            row = {"M": M, "scenario": sname, "N_k": nk, "N": N}
+            fs = {}
+            for name, kw in variants.items():
+                f, infos, ms = _timed_solves(
+                    bm, args, f"M={M} {sname} {name}",
+                    lambda prof, kw=kw: bm.solve(u, Nk, tol=args.tol, profile=int(prof), ctx=ctx,
+                                                 **kw))
+                fs[name] = f.cpu().numpy()
+                row[name + "_ms"] = ms
+                row[name + "_status"] = infos[-1]["status"]
+                if name == "bumbar":
+                    sw, _ = _avg_sweep_s(infos)
+                    row["sweep_us"] = sw * 1e6
+            row["max_abs_diff_newton_vs_bumbar_kT"] = float(np.max(np.abs(fs["newton"] -
+                                                                          fs["bumbar"])))
+            table.append(row)
+            log(json.dumps(row))
+            if M == 300 and sname == "i":
+                top = (K, N, row)
+            del u, xi, coef, Nk
+            torch.cuda.empty_cache()
+    K, N, row = top
+    sw = row["sweep_us"] / 1e6
+    achieved = 8.0 * K * N / sw / 1e9
+    out = _base_line(args, K * N / sw, "elem/s", row["bumbar_ms"], "f64", {
+        "workload": "replica-count scaling: temperature ladders M = 10, 30, 100, 300, "
+                    "N_k = 1e4, 3e6/M, 9e8/M^2; BU-MBAR vs plain Newton vs plain SCI; "
+                    "value and roofline from M=300, N_k=1e4 (u 300x3e6 FP64)",
+        "tol_kT": args.tol})
+    out.update({
+        "scaling_table": table,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": None,
