@@ -14,6 +14,7 @@
 // the block as 2 x 2 MFMA tiles. Partial blocks are summed over chunks in a
 // fixed order by a second kernel, so the result is deterministic.
 #include <cmath>
+#include <type_traits>
 
 #include "bumbar_impl.h"
 #include "devmath.h"
@@ -53,9 +54,14 @@ struct SrcMat {
   };
   __device__ Row row(int k, double c) const { return {u + (int64_t)k * ld, c}; }
   __device__ double col(int64_t n, const double* logD) const { return logD[n]; }
-  __device__ double p(const Row& r, int64_t n, double lD) const {
-    return exp_nonpos(r.c - (double)r.p[n] - lD);
+  // p in two stages (the load, then the arithmetic), so that a kernel can
+  // issue the next samples' loads before it consumes them
+  using Raw = TI;
+  __device__ Raw load(const Row& r, int64_t n) const { return r.p[n]; }
+  __device__ double fin(const Row& r, Raw x, double lD) const {
+    return exp_nonpos(r.c - (double)x - lD);
   }
+  __device__ double p(const Row& r, int64_t n, double lD) const { return fin(r, load(r, n), lD); }
 };
 
 // FP64 u with the weight's exponential on the FP32 hardware exp2 (relative
@@ -70,9 +76,12 @@ struct SrcMatExp32 {
   };
   __device__ Row row(int k, double c) const { return {u + (int64_t)k * ld, c}; }
   __device__ double col(int64_t n, const double* logD) const { return logD[n]; }
-  __device__ double p(const Row& r, int64_t n, double lD) const {
-    return (double)__builtin_amdgcn_exp2f((float)(1.4426950408889634 * (r.c - r.p[n] - lD)));
+  using Raw = double;
+  __device__ Raw load(const Row& r, int64_t n) const { return r.p[n]; }
+  __device__ double fin(const Row& r, Raw x, double lD) const {
+    return (double)__builtin_amdgcn_exp2f((float)(1.4426950408889634 * (r.c - x - lD)));
   }
+  __device__ double p(const Row& r, int64_t n, double lD) const { return fin(r, load(r, n), lD); }
 };
 
 // Packed mixed-precision matrix r_kn = c0_k - u_kn - m0_n: x = d_k + r_kn -
@@ -252,6 +261,12 @@ __global__ void __launch_bounds__(256)
 // (upper tiles) for the fixed-order reduction.
 constexpr int kSmallMaxK = 256;
 
+// Sources with a two-stage p (load, then fin) take the software-pipelined loop.
+template <class S, class = void>
+struct SplitSource : std::false_type {};
+template <class S>
+struct SplitSource<S, std::void_t<decltype(&S::load)>> : std::true_type {};
+
 template <class Src, int NW, int TPW>
 __global__ void __launch_bounds__(NW * 64)
     hessian_small_kernel(Src src, int K, int Kp, int64_t N, const double* __restrict__ cst,
@@ -298,25 +313,8 @@ __global__ void __launch_bounds__(NW * 64)
   const int64_t n_begin = (int64_t)blockIdx.x * chunk_len;
   int64_t n_end = n_begin + chunk_len;
   if (n_end > N) n_end = N;
-  for (int64_t n0 = n_begin; n0 < n_end; n0 += HS) {
-    double col[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int64_t n = n0 + ls + w;
-      col[w] = n < n_end ? src.col(n, logD) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < MAXP; ++q) {
-      const int r = lr + q * RPP;
-      if (r < Kp) {
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const int64_t n = n0 + ls + w;
-          P[r][ls + w] = (live[q] && n < n_end) ? src.p(rows[q], n, col[w]) : 0.0;
-        }
-      }
-    }
-    __syncthreads();
+  // the MFMAs of one step of HS samples (P in LDS)
+  auto mfma_step = [&]() {
 #pragma unroll
     for (int sidx = 0; sidx < HS / 4; ++sidx) {
       const int c = sidx * 4 + (lane >> 4);
@@ -328,7 +326,69 @@ __global__ void __launch_bounds__(NW * 64)
         acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
       }
     }
-    __syncthreads();
+  };
+  // (the 8-wave shapes of the FP64 / FP32 matrix sources would spill with
+  // the extra registers, so they keep the plain loop)
+  constexpr bool kPipe =
+      SplitSource<Src>::value && (NW == 4 || std::is_same<Src, SrcMatExp32>::value);
+  if constexpr (kPipe) {
+    // software pipeline: the loads of step t + 1 are issued before the MFMAs
+    // of step t and consumed after them (clamped addresses, so every load is
+    // in bounds; rows without samples load row 0 and are zeroed)
+    using Raw = typename Src::Raw;
+    double cv[4];
+    Raw uv[MAXP][4];
+    auto fetch = [&](int64_t n0) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int64_t n = n0 + ls + w < n_end ? n0 + ls + w : n_end - 1;
+        cv[w] = src.col(n, logD);
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+          if (lr + q * RPP < Kp) uv[q][w] = src.load(rows[q], n);
+      }
+    };
+    if (n_begin < n_end) fetch(n_begin);
+    for (int64_t n0 = n_begin; n0 < n_end; n0 += HS) {
+#pragma unroll
+      for (int q = 0; q < MAXP; ++q) {
+        const int r = lr + q * RPP;
+        if (r < Kp) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t n = n0 + ls + w;
+            P[r][ls + w] = (live[q] && n < n_end) ? src.fin(rows[q], uv[q][w], cv[w]) : 0.0;
+          }
+        }
+      }
+      __syncthreads();
+      if (n0 + HS < n_end) fetch(n0 + HS);
+      mfma_step();
+      __syncthreads();
+    }
+  } else {
+    for (int64_t n0 = n_begin; n0 < n_end; n0 += HS) {
+      double col[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int64_t n = n0 + ls + w;
+        col[w] = n < n_end ? src.col(n, logD) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < MAXP; ++q) {
+        const int r = lr + q * RPP;
+        if (r < Kp) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t n = n0 + ls + w;
+            P[r][ls + w] = (live[q] && n < n_end) ? src.p(rows[q], n, col[w]) : 0.0;
+          }
+        }
+      }
+      __syncthreads();
+      mfma_step();
+      __syncthreads();
+    }
   }
   // lane l holds element v at row l/16 + 4 v, column l % 16 of each tile
   double* out = partials + (int64_t)blockIdx.x * Kp * Kp;
