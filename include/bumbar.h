@@ -281,7 +281,8 @@ int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const do
  * bin b = b_0 nbins_1 + b_1 (d = 2; b = b_0 for d = 1) with
  *   b_j = floor((xi_nj - lo_j) * nbins_j / (hi_j - lo_j))   (FP64, this order).
  * Samples with some b_j outside [0, nbins_j) are left out; empty bins get
- * +inf. Each bin's p_n are added in increasing n, so F does not depend on the
+ * +inf. Each bin's p_n are added in increasing n within segments of at most
+ * 1024 samples, then the segment sums in order, so F does not depend on the
  * launch. xi (N x d, FP64, d in {1, 2}) and p (N) in, F (nbins_0 * nbins_1)
  * out, all device; lo, hi, nbins: host arrays of d entries (finite lo < hi,
  * nbins >= 1, fewer than 2^32 bins; N < 2^32). The workspace must hold

@@ -6,11 +6,13 @@
 // (row-major, the first coordinate slowest) with
 //   b_j = floor((xi_nj - lo_j) * nb_j / (hi_j - lo_j)),
 // evaluated in FP64 in exactly that order, and is left out unless
-// 0 <= b_j < nb_j for every j. Every bin's samples are summed in ascending n
-// by one thread: the bin ids are radix-sorted together with the sample index
-// (a stable sort keeps equal ids in index order), and the thread at the start
-// of each run of equal ids adds the run. The sums are therefore those of a
-// plain sequential loop over the samples, and do not depend on the launch.
+// 0 <= b_j < nb_j for every j. The bin ids are radix-sorted together with the
+// sample index (a stable sort keeps equal ids in index order), so each bin is
+// a run of its samples in ascending n. A run is summed in segments of at most
+// kSeg sorted positions (cut at multiples of kSeg), each added in order by
+// one thread, and the thread at the run's start then adds its segments in
+// order. The order of additions depends only on the data, not on the launch,
+// and no thread walks more than kSeg samples plus one sum per segment.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,16 +53,34 @@ __global__ void __launch_bounds__(kPT) pmf_fill_kernel(double* __restrict__ F, i
   if (b < nbins) F[b] = INFINITY;
 }
 
-// The thread at the start of each run of equal (in-grid) ids sums the run.
+constexpr int64_t kSeg = 1024;  // sorted positions per segment
+
+// The thread at the start of each segment (the start of a run, or a multiple
+// of kSeg inside one) adds the segment's probabilities in order.
 __global__ void __launch_bounds__(kPT)
-    pmf_runs_kernel(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ vs, int64_t N,
-                    uint32_t nbins, const double* __restrict__ p, double* __restrict__ F) {
+    pmf_segments_kernel(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ vs,
+                        int64_t N, uint32_t nbins, const double* __restrict__ p,
+                        double* __restrict__ seg) {
+  const int64_t i = (int64_t)blockIdx.x * kPT + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t k = ks[i];
+  if (k >= nbins || (i % kSeg != 0 && ks[i - 1] == k)) return;
+  const int64_t end = (i / kSeg + 1) * kSeg < N ? (i / kSeg + 1) * kSeg : N;
+  double s = 0.0;
+  for (int64_t j = i; j < end && ks[j] == k; ++j) s += p[vs[j]];
+  seg[i] = s;
+}
+
+// The thread at the start of each run adds the run's segment sums in order.
+__global__ void __launch_bounds__(kPT)
+    pmf_runs_kernel(const uint32_t* __restrict__ ks, int64_t N, uint32_t nbins,
+                    const double* __restrict__ seg, double* __restrict__ F) {
   const int64_t i = (int64_t)blockIdx.x * kPT + threadIdx.x;
   if (i >= N) return;
   const uint32_t k = ks[i];
   if (k >= nbins || (i > 0 && ks[i - 1] == k)) return;
-  double s = 0.0;
-  for (int64_t j = i; j < N && ks[j] == k; ++j) s += p[vs[j]];
+  double s = seg[i];
+  for (int64_t c = (i / kSeg + 1) * kSeg; c < N && ks[c] == k; c += kSeg) s += seg[c];
   F[k] = -log(s);
 }
 
@@ -87,7 +107,8 @@ extern "C" {
 
 int bumbar_query_workspace_pmf(const bumbar_ctx* ctx, int64_t N, size_t* bytes) {
   if (!ctx || !bytes || N <= 0 || N > 0xffffffffll) return BUMBAR_EINVAL;
-  *bytes = 4 * pmf_align(sizeof(uint32_t) * (size_t)N) + pmf_align(pmf_sort_bytes(N)) + 256;
+  *bytes = 4 * pmf_align(sizeof(uint32_t) * (size_t)N) + pmf_align(sizeof(double) * (size_t)N) +
+           pmf_align(pmf_sort_bytes(N)) + 256;
   return BUMBAR_OK;
 }
 
@@ -116,7 +137,8 @@ int bumbar_pmf(bumbar_ctx* ctx, const double* xi, int64_t N, int d, const double
   uint32_t* val = reinterpret_cast<uint32_t*>(w + a);
   uint32_t* ks = reinterpret_cast<uint32_t*>(w + 2 * a);
   uint32_t* vs = reinterpret_cast<uint32_t*>(w + 3 * a);
-  void* tmp = w + 4 * a;
+  double* seg = reinterpret_cast<double*>(w + 4 * a);
+  void* tmp = w + 4 * a + pmf_align(sizeof(double) * (size_t)N);
   size_t tmp_bytes = pmf_sort_bytes(N);
   hipStream_t s = ctx->stream;
   const uint32_t nb = (uint32_t)total;
@@ -130,7 +152,8 @@ int bumbar_pmf(bumbar_ctx* ctx, const double* xi, int64_t N, int d, const double
                                            (const uint32_t*)val, vs, (size_t)N, 0,
                                            pmf_key_bits(nb), s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(pmf_runs_kernel, dim3(blocks), dim3(kPT), 0, s, ks, vs, N, nb, p, F);
+    hipLaunchKernelGGL(pmf_segments_kernel, dim3(blocks), dim3(kPT), 0, s, ks, vs, N, nb, p, seg);
+    hipLaunchKernelGGL(pmf_runs_kernel, dim3(blocks), dim3(kPT), 0, s, ks, N, nb, seg, F);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -1,10 +1,10 @@
 """GPU parity of the free-energy surface (Section 3, Fig. 1: F_b = -ln of the
 summed Eq. (5)-(6) probabilities over coordinate bins) against the oracle.
 
-Both sides take the bin of a sample from the same FP64 expression and add a
-bin's probabilities in increasing sample order, so which bins are empty (+inf)
-must agree exactly and the sums bit for bit; only -ln may differ in its last
-place. Cases: 1-D and 2-D grids, sizes spanning many blocks with a ragged
+Both sides take the bin of a sample from the same FP64 expression, so which
+bins are empty (+inf) must agree exactly. The oracle adds a bin's
+probabilities in sample order; the GPU adds segments of at most 1024 of them
+in that order, then the segment sums, so F agrees to rounding (1e-13). Cases: 1-D and 2-D grids, sizes spanning many blocks with a ragged
 tail, samples on and past the edges, zero probabilities, a 10^6-bin grid, a
 solve-then-reweight pipeline, and the argument checks.
 """
@@ -39,7 +39,7 @@ def dev(x):
     return torch.as_tensor(np.ascontiguousarray(x)).cuda()
 
 
-def same_surface(Fg, Fo):
+def same_surface(Fg, Fo, tol=1e-13):
     Fg = Fg.cpu().numpy()
     assert Fg.shape == Fo.shape
     assert np.array_equal(np.isinf(Fg), np.isinf(Fo))
@@ -47,7 +47,7 @@ def same_surface(Fg, Fo):
     assert np.all(np.isfinite(Fg[ok]))
     if ok.any():
         err = np.abs(Fg[ok] - Fo[ok]) / np.maximum(1.0, np.abs(Fo[ok]))
-        assert err.max() <= 4e-16, err.max()
+        assert err.max() <= tol, err.max()
 
 
 def draw(N, d, seed, lo, hi, spill=0.1):
@@ -79,6 +79,22 @@ def test_pmf_2d(bm, N, nb):
     lo, hi = (-1.5, -0.5), (1.0, 2.0)
     x, p = draw(N, 2, seed=N, lo=lo, hi=hi)
     same_surface(bm.pmf(x, p, lo, hi, nb), oracle.pmf(x, p, lo, hi, nb))
+
+
+@pytest.mark.parametrize("N,d,nb", [(2_000_000, 2, (3, 1)), (4_000_000, 1, (1,)),
+                                     (1_500_001, 1, (7,))])
+def test_pmf_coarse_grid(bm, N, d, nb):
+    # hundreds of thousands to millions of samples per bin; two orders of
+    # adding L positive terms differ by about sqrt(L) ulp (2e-13 at L = 4e6),
+    # while a sample dropped or counted twice moves F by about 1/L >= 2.5e-7
+    say(f"pmf coarse grid N={N} d={d} nbins={nb}")
+    lo, hi = [-1.0] * d, [1.0] * d
+    x, p = draw(N, d, seed=N + 1, lo=lo, hi=hi, spill=0.05)
+    xs = x[:, 0] if d == 1 else x
+    same_surface(bm.pmf(xs, p, lo if d > 1 else lo[0], hi if d > 1 else hi[0],
+                        nb if d > 1 else nb[0]),
+                 oracle.pmf(xs, p, lo if d > 1 else lo[0], hi if d > 1 else hi[0],
+                            nb if d > 1 else nb[0]), tol=1e-11)
 
 
 def test_pmf_all_outside_and_single_bin(bm):
