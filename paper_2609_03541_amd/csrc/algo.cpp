@@ -22,6 +22,9 @@
 namespace bumbar {
 
 constexpr int kCountSlots = 8192;
+// the 1-D width search keeps its device state at counts + kCountSlots / 2
+static_assert(sizeof(WidthSearch1D) <= sizeof(int64_t) * (kCountSlots / 2 - 1),
+              "width-search state must fit below the last count slot");
 
 int64_t otf_ubar_cap(int K, int64_t N) {
   return sweep_fast_supported(K) ? std::min<int64_t>(N, 65536) : 0;
@@ -100,17 +103,18 @@ static int nonempty(bumbar_ctx* ctx, BinnedBufs& BB, uint64_t m, int64_t* g) {
   return read_bytes(ctx, BB.counts, g, sizeof(int64_t));
 }
 
-// 1-D: the same bisection, with the midpoints of the next k levels of the
-// bisection tree evaluated in one pass and the path then walked on the host,
-// so each round costs one readback instead of one per probe. A pass costs a
-// launch and readback (about 30 us) plus N x 2^k lane steps of the count
-// kernel (about 0.32 ps each on MI355X); k minimises the whole search,
-// ceil(32 / k) passes: 6 levels (63 midpoints) for small N, 3 at N = 1e7.
+// 1-D: the same bisection, run on the device: each pass counts the midpoints
+// of the next k levels of the bisection tree over the sorted coordinates, and
+// a one-thread kernel walks the path exactly as the bisection would and
+// queues the next pass, so the passes run back to back and the host reads
+// back only the result. A pass costs a few microseconds of launches plus
+// N x 2^k lane steps of the count kernel (about 0.32 ps each on MI355X); k
+// minimises ceil(32 / k) passes of that: 4 levels at N = 1e6, 2 at 1e7.
 static int bisection_levels(int64_t N) {
   int best = 6;
   double best_us = 1e300;
-  for (int k = 2; k <= 6; ++k) {
-    const double us = std::ceil(32.0 / k) * (30.0 + (double)N * (double)(1 << k) * 3.2e-7);
+  for (int k = 1; k <= 6; ++k) {
+    const double us = std::ceil(32.0 / k) * (6.0 + (double)N * (double)(1 << k) * 3.2e-7);
     if (us < best_us) {
       best_us = us;
       best = k;
@@ -119,76 +123,29 @@ static int bisection_levels(int64_t N) {
   return best;
 }
 
-static void subtree_mids(uint64_t lo, uint64_t hi, int depth, std::vector<uint64_t>* out) {
-  if (depth == 0 || hi - lo <= 1) return;
-  const uint64_t mid = lo + (hi - lo) / 2;
-  out->push_back(mid);
-  subtree_mids(mid, hi, depth - 1, out);
-  subtree_mids(lo, mid, depth - 1, out);
-}
-
 static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_out,
                            int64_t* g_out) {
   hipStream_t s = ctx->stream;
-  uint64_t* dev_ms = reinterpret_cast<uint64_t*>(BB.counts + kCountSlots / 2);
-  unsigned long long* dev_g = reinterpret_cast<unsigned long long*>(BB.counts + 8);
-  std::vector<uint64_t> ms;
-  std::vector<unsigned long long> gs;
-  std::vector<uint64_t> pairs;
-  auto eval = [&]() -> int {
-    pairs.clear();
-    for (uint64_t m : ms) {
-      pairs.push_back(m);
-      pairs.push_back(width_magic(m));
-    }
-    hipError_t e = hipMemcpyAsync(dev_ms, pairs.data(), sizeof(uint64_t) * pairs.size(),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = launch_count_1d_multi(s, BB.q1_sorted, BB.N, dev_ms, (int)ms.size(), dev_g);
-    if (e != hipSuccess) return hip_fail(ctx, e, "count");
-    gs.resize(ms.size());
-    return read_bytes(ctx, dev_g, gs.data(), sizeof(unsigned long long) * ms.size());
-  };
+  auto* w = reinterpret_cast<WidthSearch1D*>(BB.counts + kCountSlots / 2);
   const int levels = bisection_levels(BB.N);
-  uint64_t lo = 1, hi = 4294967296ull;
-  ms.push_back(1);
-  subtree_mids(lo, hi, levels, &ms);
-  int rc = eval();
-  if (rc) return rc;
-  const int64_t g1 = (int64_t)gs[0];
-  if (g1 < n) {
-    *m_out = 1;
-    *g_out = g1;
-    return BUMBAR_OK;
-  }
-  int64_t glo = g1;
-  for (;;) {
-    // walk the evaluated part of the tree exactly as the bisection would
-    auto find = [&](uint64_t m) -> int64_t {
-      for (size_t i = 0; i < ms.size(); ++i)
-        if (ms[i] == m) return (int64_t)gs[i];
-      return -1;
-    };
-    while (hi - lo > 1) {
-      const uint64_t mid = lo + (hi - lo) / 2;
-      const int64_t gm = find(mid);
-      if (gm < 0) break;  // outside this round's subtree
-      if (gm >= n) {
-        lo = mid;
-        glo = gm;
-      } else {
-        hi = mid;
-      }
-    }
-    if (hi - lo <= 1) break;
-    ms.clear();
-    subtree_mids(lo, hi, levels, &ms);
-    rc = eval();
+  // 32 levels cover [1, 2^32]; one spare pass
+  int passes = (32 + levels - 1) / levels + 1;
+  bool init = true;
+  WidthSearch1D h;
+  for (int round = 0; round < 4; ++round) {
+    hipError_t e = launch_width_search_1d(s, BB.q1_sorted, BB.N, n, levels, passes, init, w);
+    if (e != hipSuccess) return hip_fail(ctx, e, "width search");
+    const int rc = read_bytes(ctx, w, &h, sizeof(h));
     if (rc) return rc;
+    if (h.done) {
+      *m_out = h.lo;
+      *g_out = h.glo;
+      return BUMBAR_OK;
+    }
+    init = false;
+    passes = 4;
   }
-  *m_out = lo;
-  *g_out = glo;
-  return BUMBAR_OK;
+  return fail(ctx, BUMBAR_EDEVICE, "the width search did not end");
 }
 
 // w*(n) = max{m : g(m) >= n} by the integer bisection of the oracle.

@@ -250,9 +250,12 @@ constexpr int kRunChunk = 256;  // sorted coordinates per wave and pass
 // one integer atomic.
 __global__ void __launch_bounds__(kBT)
     count_runs_1d_multi_kernel(const uint32_t* __restrict__ qs, int64_t N,
-                               const uint64_t* __restrict__ ms, int M, int MP,
-                               unsigned long long* __restrict__ counts) {
+                               const WidthSearch1D* __restrict__ ws, int MP) {
   __shared__ unsigned long long sred[kBT / 64][kMaxProbes];
+  const int M = ws->M;  // 0 once the search has ended: nothing to count
+  if (M == 0) return;
+  const uint64_t* ms = ws->ms;
+  unsigned long long* counts = const_cast<WidthSearch1D*>(ws)->counts;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = lane % MP, st = lane / MP;
@@ -310,21 +313,121 @@ hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, u
   return hipGetLastError();
 }
 
-uint64_t width_magic(uint64_t m) {
+__host__ __device__ static uint64_t magic_of(uint64_t m) {
   if (m < 2 || m > 0xffffffffull) return 0;
   return ~0ull / m + 1ull;  // ceil(2^64 / m)
 }
 
-hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
-                                 const uint64_t* ms, int M, unsigned long long* counts) {
-  if (M < 1 || M > kMaxProbes) return hipErrorInvalidValue;
+// Appends the midpoints of the next `levels` levels of the bisection tree
+// under (lo, hi) to the probe list: the interval at depth d along the path
+// code c (bit i: right half at step i) has its midpoint probed if it is
+// wider than one. Single thread.
+__device__ static void ws_emit(WidthSearch1D* w, uint64_t lo, uint64_t hi) {
+  int M = w->M;
+  for (int d = 0; d < w->levels; ++d) {
+    for (int c = 0; c < (1 << d); ++c) {
+      uint64_t a = lo, b = hi;
+      bool ok = true;
+      for (int i = 0; i < d && ok; ++i) {
+        if (b - a <= 1) {
+          ok = false;
+          break;
+        }
+        const uint64_t mid = a + (b - a) / 2;
+        if ((c >> i) & 1)
+          a = mid;
+        else
+          b = mid;
+      }
+      if (!ok || b - a <= 1) continue;
+      const uint64_t mid = a + (b - a) / 2;
+      w->ms[2 * M] = mid;
+      w->ms[2 * M + 1] = magic_of(mid);
+      w->counts[M] = 0ull;
+      ++M;
+    }
+  }
+  w->M = M;
+}
+
+// First pass: m = 1 and the midpoints of the top `levels` levels.
+__global__ void ws_init_kernel(WidthSearch1D* w, int64_t n, int levels) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  w->lo = 1;
+  w->hi = 4294967296ull;
+  w->glo = 0;
+  w->n = n;
+  w->levels = levels;
+  w->done = 0;
+  w->first = 1;
+  w->ms[0] = 1;
+  w->ms[1] = magic_of(1);
+  w->counts[0] = 0ull;
+  w->M = 1;
+  ws_emit(w, w->lo, w->hi);
+}
+
+// Walks the evaluated part of the tree exactly as the bisection would, then
+// queues the next pass (or ends the search: M = 0, done = 1).
+__global__ void ws_walk_kernel(WidthSearch1D* w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || w->done) return;
+  const int64_t n = w->n;
+  uint64_t lo = w->lo, hi = w->hi;
+  int64_t glo = w->glo;
+  if (w->first) {
+    const int64_t g1 = (int64_t)w->counts[0];
+    w->first = 0;
+    if (g1 < n) {  // even the finest width gives fewer than n bins
+      w->lo = 1;
+      w->glo = g1;
+      w->done = 1;
+      w->M = 0;
+      return;
+    }
+    glo = g1;
+  }
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    int j = -1;
+    for (int q = 0; q < w->M; ++q)
+      if (w->ms[2 * q] == mid) {
+        j = q;
+        break;
+      }
+    if (j < 0) break;  // outside this pass's subtree
+    const int64_t gm = (int64_t)w->counts[j];
+    if (gm >= n) {
+      lo = mid;
+      glo = gm;
+    } else {
+      hi = mid;
+    }
+  }
+  w->lo = lo;
+  w->hi = hi;
+  w->glo = glo;
+  w->M = 0;
+  if (hi - lo <= 1) {
+    w->done = 1;
+    return;
+  }
+  ws_emit(w, lo, hi);
+}
+
+hipError_t launch_width_search_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N,
+                                  int64_t n, int levels, int passes, bool init,
+                                  WidthSearch1D* w) {
+  if (levels < 1 || levels > 6 || passes < 1) return hipErrorInvalidValue;
   int MP = 4;  // probe slots per wave: a power of two, 64 / MP streams of >= 4 coordinates
-  while (MP < M) MP *= 2;
+  while (MP < (1 << levels)) MP *= 2;
   const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;
   const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(1024, (nchunks + 3) / 4));
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kMaxProbes), 0, s, counts, M);
-  hipLaunchKernelGGL(count_runs_1d_multi_kernel, dim3((unsigned)nb), dim3(kBT), 0, s, q_sorted, N,
-                     ms, M, MP, counts);
+  if (init) hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, s, w, n, levels);
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(count_runs_1d_multi_kernel, dim3((unsigned)nb), dim3(kBT), 0, s, q_sorted,
+                       N, w, MP);
+    hipLaunchKernelGGL(ws_walk_kernel, dim3(1), dim3(64), 0, s, w);
+  }
   return hipGetLastError();
 }
 

@@ -185,11 +185,22 @@ hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t*
 // in counts[0] after the call.
 hipError_t launch_count_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N, uint64_t m,
                            int64_t* counts);
-// g(m_j) for M <= 64 widths over sorted 1-D coordinates; ms (device) holds
-// the pairs (m_j, width_magic(m_j)); counts (M, device) are zeroed by the call.
-uint64_t width_magic(uint64_t m);
-hipError_t launch_count_1d_multi(hipStream_t s, const uint32_t* q_sorted, int64_t N,
-                                 const uint64_t* ms, int M, unsigned long long* counts);
+// The 1-D width search on the device: the bisection for max{m : g(m) >= n}
+// on [1, 2^32] with the midpoints of `levels` levels of the tree counted per
+// pass (count kernel) and the path walked between passes (one-thread walk
+// kernel), so the host reads back only the result. init starts a search;
+// `passes` count + walk pairs are queued (passes after the end do nothing).
+// Result: lo (= m), glo (= g(m)), done.
+struct WidthSearch1D {
+  uint64_t lo, hi;
+  int64_t glo, n;
+  int levels, M, done, first;
+  uint64_t ms[2 * 64];              // (m, ceil(2^64 / m)) pairs of this pass
+  unsigned long long counts[64];    // g of each probe
+};
+hipError_t launch_width_search_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N,
+                                  int64_t n, int levels, int passes, bool init,
+                                  WidthSearch1D* w);
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts);

@@ -183,8 +183,8 @@ def test_binning_bit_exact(bm, d):
 
 @pytest.mark.parametrize("N", [700001, 3000017, 12000007, 40000003])
 def test_binning_large_1d(bm, N):
-    # Large N evaluates fewer bisection levels per pass (5, 4, 3 and 2 here),
-    # so the count kernel splits its chunks into 2, 4, 8 and 16 streams. At
+    # Large N evaluates fewer bisection levels per pass (4, 3, 2 and 2 here),
+    # so the count kernel splits its chunks into 4, 8 and 16 streams. At
     # N = 7e5 the oracle's own search runs; above it (seconds per probe) the
     # GPU's m is checked by the bisection's end state g(m) >= n > g(m + 1)
     # with the oracle's g, and the histogram at m against the oracle's.
