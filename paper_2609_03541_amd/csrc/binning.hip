@@ -318,17 +318,16 @@ __host__ __device__ static uint64_t magic_of(uint64_t m) {
   return ~0ull / m + 1ull;  // ceil(2^64 / m)
 }
 
-// Appends the midpoints of the next `levels` levels of the bisection tree
-// under (lo, hi) to the probe list: the interval at depth d along the path
-// code c (bit i: right half at step i) has its midpoint probed if it is
-// wider than one. Single thread.
-__device__ static void ws_emit(WidthSearch1D* w, uint64_t lo, uint64_t hi) {
-  int M = w->M;
-  for (int d = 0; d < w->levels; ++d) {
+// Appends to nm (LDS) the midpoints of the next `levels` levels of the
+// bisection tree under (lo, hi): the interval at depth d along the path code
+// c (bit i: right half at step i) has its midpoint probed if it is wider
+// than one. Single thread; returns the new count.
+__device__ static int ws_emit(uint64_t lo, uint64_t hi, int levels, uint64_t* nm, int M) {
+  for (int d = 0; d < levels; ++d) {
     for (int c = 0; c < (1 << d); ++c) {
       uint64_t a = lo, b = hi;
       bool ok = true;
-      for (int i = 0; i < d && ok; ++i) {
+      for (int i = 0; i < d; ++i) {
         if (b - a <= 1) {
           ok = false;
           break;
@@ -340,78 +339,101 @@ __device__ static void ws_emit(WidthSearch1D* w, uint64_t lo, uint64_t hi) {
           b = mid;
       }
       if (!ok || b - a <= 1) continue;
-      const uint64_t mid = a + (b - a) / 2;
-      w->ms[2 * M] = mid;
-      w->ms[2 * M + 1] = magic_of(mid);
-      w->counts[M] = 0ull;
-      ++M;
+      nm[M++] = a + (b - a) / 2;
     }
   }
-  w->M = M;
+  return M;
+}
+
+// Writes the probes of the next pass (m and its magic number, counts zeroed)
+// with every thread of the block; nm and M in LDS.
+__device__ static void ws_store(WidthSearch1D* w, const uint64_t* nm, int M) {
+  for (int t = threadIdx.x; t < M; t += blockDim.x) {
+    w->ms[2 * t] = nm[t];
+    w->ms[2 * t + 1] = magic_of(nm[t]);
+    w->counts[t] = 0ull;
+  }
 }
 
 // First pass: m = 1 and the midpoints of the top `levels` levels.
-__global__ void ws_init_kernel(WidthSearch1D* w, int64_t n, int levels) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  w->lo = 1;
-  w->hi = 4294967296ull;
-  w->glo = 0;
-  w->n = n;
-  w->levels = levels;
-  w->done = 0;
-  w->first = 1;
-  w->ms[0] = 1;
-  w->ms[1] = magic_of(1);
-  w->counts[0] = 0ull;
-  w->M = 1;
-  ws_emit(w, w->lo, w->hi);
+__global__ void __launch_bounds__(64) ws_init_kernel(WidthSearch1D* w, int64_t n, int levels) {
+  __shared__ uint64_t nm[kMaxProbes];
+  __shared__ int sM;
+  if (threadIdx.x == 0) {
+    nm[0] = 1;
+    sM = ws_emit(1, 4294967296ull, levels, nm, 1);
+    w->lo = 1;
+    w->hi = 4294967296ull;
+    w->glo = 0;
+    w->n = n;
+    w->levels = levels;
+    w->done = 0;
+    w->first = 1;
+    w->M = sM;
+  }
+  __syncthreads();
+  ws_store(w, nm, sM);
 }
 
 // Walks the evaluated part of the tree exactly as the bisection would, then
-// queues the next pass (or ends the search: M = 0, done = 1).
-__global__ void ws_walk_kernel(WidthSearch1D* w) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || w->done) return;
-  const int64_t n = w->n;
-  uint64_t lo = w->lo, hi = w->hi;
-  int64_t glo = w->glo;
-  if (w->first) {
-    const int64_t g1 = (int64_t)w->counts[0];
-    w->first = 0;
-    if (g1 < n) {  // even the finest width gives fewer than n bins
-      w->lo = 1;
-      w->glo = g1;
-      w->done = 1;
-      w->M = 0;
-      return;
-    }
-    glo = g1;
+// queues the next pass (or ends the search: M = 0, done = 1). The probes and
+// their counts are staged in LDS by the whole block; one thread walks.
+__global__ void __launch_bounds__(64) ws_walk_kernel(WidthSearch1D* w) {
+  __shared__ uint64_t sm[kMaxProbes];
+  __shared__ unsigned long long sc[kMaxProbes];
+  __shared__ uint64_t nm[kMaxProbes];
+  __shared__ int sM;
+  if (w->done) return;  // uniform: every thread reads the same flag
+  const int M = w->M;
+  for (int t = threadIdx.x; t < M; t += blockDim.x) {
+    sm[t] = w->ms[2 * t];
+    sc[t] = w->counts[t];
   }
-  while (hi - lo > 1) {
-    const uint64_t mid = lo + (hi - lo) / 2;
-    int j = -1;
-    for (int q = 0; q < w->M; ++q)
-      if (w->ms[2 * q] == mid) {
-        j = q;
-        break;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sM = 0;
+    const int64_t n = w->n;
+    uint64_t lo = w->lo, hi = w->hi;
+    int64_t glo = w->glo;
+    bool finished = false;
+    if (w->first) {
+      const int64_t g1 = (int64_t)sc[0];
+      w->first = 0;
+      if (g1 < n) {  // even the finest width gives fewer than n bins
+        lo = 1;
+        glo = g1;
+        finished = true;
+      } else {
+        glo = g1;
       }
-    if (j < 0) break;  // outside this pass's subtree
-    const int64_t gm = (int64_t)w->counts[j];
-    if (gm >= n) {
-      lo = mid;
-      glo = gm;
-    } else {
-      hi = mid;
     }
+    while (!finished && hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      int j = -1;
+      for (int q = 0; q < M; ++q)
+        if (sm[q] == mid) {
+          j = q;
+          break;
+        }
+      if (j < 0) break;  // outside this pass's subtree
+      const int64_t gm = (int64_t)sc[j];
+      if (gm >= n) {
+        lo = mid;
+        glo = gm;
+      } else {
+        hi = mid;
+      }
+    }
+    if (hi - lo <= 1) finished = true;
+    w->lo = lo;
+    w->hi = hi;
+    w->glo = glo;
+    if (!finished) sM = ws_emit(lo, hi, w->levels, nm, 0);
+    w->M = sM;
+    w->done = finished ? 1 : 0;
   }
-  w->lo = lo;
-  w->hi = hi;
-  w->glo = glo;
-  w->M = 0;
-  if (hi - lo <= 1) {
-    w->done = 1;
-    return;
-  }
-  ws_emit(w, lo, hi);
+  __syncthreads();
+  ws_store(w, nm, sM);
 }
 
 hipError_t launch_width_search_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N,
