@@ -95,7 +95,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
-              "of the sweep is a design note, not part of this build.", file=sys.stderr)
+              "of the sweep is described in the design notes and not implemented.", file=sys.stderr)
         sys.exit(2)
     stream = None
     if args.workload == "stream":
