@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(NW * 64)
       asm volatile("" : "+v"(roff));
       const float* p = base + roff + t * TN;
       if (full && vec) {
-        const f4v v = *reinterpret_cast<const f4v*>(p);
+        // the packed matrix is streamed once per sweep: non-temporal loads
+        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
         a[j][0] = v.x;
         a[j][1] = v.y;
         a[j][2] = v.z;
