@@ -187,6 +187,39 @@ def test_p8_unique_bins_mean_representative(orc):
     assert np.max(np.abs(f_b - f_u)) < 1e-13
 
 
+@pytest.mark.parametrize("d", [1, 2])
+def test_p8_mean_representative_with_populated_bins(orc, d):
+    # MEAN representative of a bin holding several samples: (1 / H_p) sum over
+    # the bin's members of u_kn (the bin value in Eq. (1) for plain u_kn).
+    # The bins are rebuilt here with numpy alone (cell = q // m per dimension,
+    # ascending distinct cells) and the means taken by np.add.reduceat over
+    # the samples sorted by bin, so a missing / H_p, a wrong member set or a
+    # transposed K x P result fails.
+    g = np.random.Generator(np.random.PCG64(40 + d))
+    N, K = 3000, 5
+    xi = g.normal(0.0, 1.0, size=(N, d))
+    u = g.normal(0.0, 2.0, size=(K, N)) + 3.0 * np.arange(K)[:, None]
+    q, lo, sc = orc.quantize(xi)
+    m = 2**27 if d == 1 else 2**28
+    qm = (q.astype(np.uint64) // np.uint64(m))
+    if d == 1:
+        cell = qm[:, 0]
+    else:
+        stride = np.uint64((2**32 - 1) // m + 1)
+        cell = qm[:, 0] + qm[:, 1] * stride
+    ucells, sb_np, H_np = np.unique(cell, return_inverse=True, return_counts=True)
+    assert H_np.max() > 1 and len(ucells) > 10
+    cells, H, sb = orc.histogram(q, m)
+    assert np.array_equal(cells, ucells) and np.array_equal(H, H_np)
+    assert np.array_equal(sb, sb_np.astype(np.int32))
+    order = np.argsort(sb_np, kind="stable")
+    starts = np.concatenate([[0], np.cumsum(H_np)[:-1]])
+    ref = np.add.reduceat(u[:, order], starts, axis=1) / H_np[None, :]
+    ub = orc.represent(K, d, m, lo, sc, cells, H, sample_bin=sb, u=u)
+    assert ub.shape == (K, len(ucells))
+    assert np.max(np.abs(ub - ref)) < 1e-12
+
+
 def test_p8_centre_representative_is_model_at_centre(orc):
     # LINEAR model: the representative of a bin is the model at the bin centre,
     # which for a linear model equals the mean of the bin's lower and upper edge values.
