@@ -294,6 +294,28 @@ int bumbar_pmf(bumbar_ctx* ctx, const double* xi, int64_t N, int d, const double
                const double* lo, const double* hi, const int* nbins, void* workspace,
                size_t ws_bytes, double* F);
 
+/* ---- allocation-free sweep -------------------------------------------- */
+
+/*
+ * bumbar_sweep without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, kernels and results as bumbar_sweep,
+ * except that log_D_n is required (it also carries ln D between the passes
+ * of the FP32-input path). Its scratch (per-state constants, per-workgroup
+ * partial sums, the finaliser's scalars) is a fixed 8 MiB device array of
+ * the library, one per device, resolved when a context is created: the call
+ * performs no device allocation of any kind. Limits: K <= BUMBAR_STATIC_MAX_K
+ * and N <= BUMBAR_STATIC_MAX_N, else BUMBAR_EINVAL. Every call on a device
+ * shares that device's array and leaves its last contents there, so calls
+ * that overlap on one device (two streams, two host threads) race: serialise
+ * them. Synchronises iff sweep_stats != NULL, as bumbar_sweep.
+ */
+#define BUMBAR_STATIC_MAX_K 256
+#define BUMBAR_STATIC_MAX_N ((int64_t)1 << 22)
+int bumbar_sweep_static(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                        int64_t ld, const int64_t* N_k, const double* f, double* f_new,
+                        double* log_D_n, double* S, double* sweep_stats);
+
 /* ---- batched serving ---------------------------------------------------
  *
  * A server keeps up to max_active MBAR problems resident on one device and

@@ -110,6 +110,8 @@ SIGNATURES = {
     "bumbar_hessian_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, C.c_int,
                                        vp, vp, vp, vp, vp, C.c_size_t, vp]),
     "bumbar_model_energies": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, vp]),
+    "bumbar_sweep_static": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,
+                                      vp, vp, dp]),
     "bumbar_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(C.c_void_p)]),
     "bumbar_server_submit": (C.c_int, [vp, C.POINTER(Request), u64p]),
     "bumbar_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int)]),

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbumbar.so")
 SOURCES = ["sweep.hip", "sweep_small.hip", "sweep_wide.hip", "sweep32.hip", "sweep_otf.hip", "hessian.hip", "linalg.hip", "binning.hip",
-           "model.hip", "pmf.hip", "solver.cpp", "algo.cpp", "server.cpp"]
+           "model.hip", "pmf.hip", "solver.cpp", "algo.cpp", "server.cpp",
+           "sweep_static.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -227,4 +227,6 @@ struct bumbar_ctx {
   // private stream on which batches of binned steps are captured as graphs
   // (created on first use; nothing executes on it)
   hipStream_t cap_stream = nullptr;
+  // this device's address of the library's fixed scratch array (bumbar_sweep_static)
+  void* static_scratch = nullptr;
 };

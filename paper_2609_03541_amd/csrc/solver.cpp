@@ -458,7 +458,8 @@ int bumbar_create(bumbar_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) c->num_cus = p.multiProcessorCount;
   }
   if (e == hipSuccess) e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
-  if (e != hipSuccess) {
+  if (e != hipSuccess || static_scratch_init(c) != BUMBAR_OK) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return BUMBAR_EDEVICE;
   }

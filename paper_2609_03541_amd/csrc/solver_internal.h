@@ -104,6 +104,10 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
                   int max_steps, bumbar_stats* st, SweepCounters* cnt, double* final_step,
                   double* final_gnorm);
 
+// Resolves this device's address of the fixed scratch array behind
+// bumbar_sweep_static into ctx->static_scratch (ctx->device current).
+int static_scratch_init(bumbar_ctx* ctx);
+
 int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk, double until,
               int64_t max_steps, int64_t* steps_out, SweepCounters* cnt, double* last_step);
 
