@@ -228,6 +228,39 @@ def test_bumbar_solve_matches_oracle_1d(bm):
         assert abs(a["s_next"] - b["s_next"]) <= 1e-9 * abs(b["s_next"]) + 1e-15
 
 
+@pytest.mark.parametrize("case", ["1d", "2d"])
+def test_mean_representatives_replay_matches_oracle(bm, case):
+    # plain u_kn (no model): the bin values of Eq. (1) are the bin means of u.
+    # Replaying the oracle's schedule must give the oracle's binned trajectory
+    # check by check: the same bins and the same Eq. (2) steps at n and n*inc.
+    if case == "1d":
+        p, n0 = synth.double_well(K=30, Nk=700, seed=6), 100
+    else:
+        p, n0 = synth.ladder_2d(K=16, Nk=1500, seed=3), 10
+    say(f"MEAN replay {case} K={p['u'].shape[0]} N={p['u'].shape[1]}")
+    f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+    fo, info_o = oracle.bumbar(p["u"], p["Nk"], p["xi"], oracle.MODEL_NONE, None, tol=1e-11,
+                               n0=n0)
+    assert len(info_o["checks"]) >= 2
+    flags = [c["refine"] for c in info_o["checks"]]
+    f, info = bm.solve(dev(p["u"]), p["Nk"], xi=p["xi"], model=bm.MODEL_NONE, tol=1e-11, n0=n0,
+                       replay=(info_o["phase1"], flags))
+    assert info["status"] == 0
+    assert info["phase1_iters"] == info_o["phase1"]
+    gc, oc = info["checks"], info_o["checks"]
+    assert len(gc) == len(oc)
+    assert [c["P"] for c in gc] == [c["P"] for c in oc]
+    assert [c["P_next"] for c in gc] == [c["P_next"] for c in oc]
+    # Eq. (2) is a difference quotient of iterates: the bin means are summed
+    # in another order on each side (about 1e-16 relative), which leaves the
+    # iterates about 1e-14 kT apart after hundreds of steps, so a step s of
+    # 1e-5 agrees to about 1e-14 absolute, not to 1e-9 relative
+    for a, b in zip(gc, oc):
+        assert abs(a["s_n"] - b["s_n"]) <= 1e-9 * abs(b["s_n"]) + 1e-12
+        assert abs(a["s_next"] - b["s_next"]) <= 1e-9 * abs(b["s_next"]) + 1e-12
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+
+
 def test_bumbar_solve_mean_representatives_2d(bm):
     p = synth.ladder_2d(K=12, Nk=300, seed=1)
     f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
