@@ -53,6 +53,13 @@ extern "C" {
 /* ---- codes ------------------------------------------------------------ */
 #define BUMBAR_F64 0
 #define BUMBAR_F32 1
+/* The sample-major copy of u_kn (bumbar_sample_major), taken by bumbar_sweep
+ * for 256 < K <= 1024: the same FP64 / FP32 elements transposed to N rows of
+ * Kp = 64 J values (J the smallest of 5, 6, 8, 10, 12, 14, 16 with K <= 64 J;
+ * states past K hold +inf), so that one sample
+ * is one contiguous run of HBM. */
+#define BUMBAR_F64_SMAJOR 2
+#define BUMBAR_F32_SMAJOR 3
 
 #define BUMBAR_PREC_FP64 0  /* every sweep in FP64                                       */
 #define BUMBAR_PREC_MIXED 1 /* FP32 sweeps, FP64 accumulation/solve, FP64 refinement     */
@@ -73,6 +80,19 @@ extern "C" {
 #define BUMBAR_REPRESENT_AUTO 0
 #define BUMBAR_REPRESENT_CENTRE 1
 #define BUMBAR_REPRESENT_MEAN 2
+
+/* Kernels of the FP64 unbinned sweeps (bumbar_plan.sweep). */
+#define BUMBAR_SWEEP_REGISTER 0     /* FP64 u, K <= 256: register-tiled single pass    */
+#define BUMBAR_SWEEP_SAMPLE_MAJOR 1 /* 256 < K <= 1024: single pass over a sample-major
+                                       copy of u in the workspace                       */
+#define BUMBAR_SWEEP_TWO_PASS 2     /* two passes over the state-major u (FP32 u with
+                                       K <= 256, K > 1024, or the copy switched off)    */
+#define BUMBAR_SWEEP_MODEL 3        /* energies from the model inside the kernels       */
+/* The FP32 Newton stage of BUMBAR_PREC_MIXED (bumbar_plan.stage32). */
+#define BUMBAR_STAGE32_NONE 0
+#define BUMBAR_STAGE32_PACKED 1       /* r_kn = fp32(c0_k - u_kn - m0_n), K <= 256          */
+#define BUMBAR_STAGE32_SAMPLE_MAJOR 2 /* FP32 arithmetic over the sample-major copy        */
+#define BUMBAR_STAGE32_MODEL 3        /* the model evaluated in FP32                        */
 
 typedef struct bumbar_ctx bumbar_ctx;
 
@@ -111,6 +131,14 @@ typedef struct {
                           readbacks is captured once as a HIP graph (per batch shape and
                           level) and replayed for every later batch of that shape; 0: the
                           kernels are launched one by one. Same results to the bit.     */
+  int sample_major;    /* 1 (default): for 256 < K <= 1024 a stored u_kn is copied once per
+                          solve to a sample-major layout in the workspace (N Kp elements,
+                          Kp as for BUMBAR_F64_SMAJOR, of the input type) and every unbinned sweep
+                          reads the copy in one pass; 0: no copy, two-pass sweeps over
+                          u_kn (FP64 only: PREC_MIXED with 256 < K needs the copy)         */
+  int u_dtype;         /* element type of the u_kn bumbar_solve will get (BUMBAR_F64,
+                          default, or BUMBAR_F32): the workspace queries size the copy
+                          with it (an FP32 copy with a query for FP64 fits)              */
 } bumbar_options;
 
 typedef struct {
@@ -201,6 +229,30 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
                  size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
                  bumbar_stats* stats);
 
+/*
+ * What bumbar_solve would run for a problem of this shape and options,
+ * decided on the host without touching a device (the solve and the
+ * workspace queries take the same decisions): stored_u = 1 for a stored
+ * u_kn of element type u_dtype, 0 for energies from the model; num_cus the
+ * device's compute units (256 on MI355X; sizes the workspace). Returns
+ * BUMBAR_EINVAL, with the reason in msg (host, may be NULL), for a
+ * combination bumbar_solve refuses, e.g. PREC_MIXED with the SCI finisher,
+ * with a stored u_kn and K > 1024, or with 256 < K <= 1024 and
+ * sample_major = 0: mixed precision is never replaced by FP64 silently.
+ */
+typedef struct {
+  int precision;          /* BUMBAR_PREC_MIXED if an FP32 Newton stage runs, else FP64      */
+  int represent;          /* resolved bin representative (0 without binning)                */
+  int sweep;              /* BUMBAR_SWEEP_*: the FP64 unbinned sweeps                        */
+  int stage32;            /* BUMBAR_STAGE32_*: the FP32 stage                                */
+  int fp32_binned;        /* 1: binned steps first run on the FP32 model sweep               */
+  int hessian_fp16;       /* 1: the Newton Hessian runs on the FP16 matrix cores              */
+  size_t copy_bytes;      /* sample-major copy of u_kn in the workspace (0: none)            */
+  size_t workspace_bytes; /* workspace bumbar_solve needs                                     */
+} bumbar_plan;
+int bumbar_plan_solve(int num_cus, int stored_u, int u_dtype, int K, int64_t N, int d, int model,
+                      const bumbar_options* opt, bumbar_plan* out, char* msg, size_t msg_len);
+
 /* ---- single steps (the kernels of the solve, exposed for testing) ------ */
 
 /*
@@ -248,6 +300,22 @@ int bumbar_hessian_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, co
                          const double* xi, int precision, const int64_t* N_k, const double* f,
                          const double* log_D_n, const double* S, void* workspace,
                          size_t ws_bytes, double* H);
+
+/*
+ * The sample-major copy of a state-major K x N matrix (256 < K <= 1024,
+ * u_dtype BUMBAR_F64 or BUMBAR_F32, row stride ld): element (k, n) is stored
+ * at n Kp + k with Kp = 64 J, J the smallest of 5, 6, 8, 10, 12, 14, 16 with
+ * K <= 64 J; entries k >= K are +inf (a state no
+ * sample can visit). bumbar_sample_major_elems gives N Kp (or -1 where the
+ * layout is not defined); bumbar_sample_major writes the copy to u_nk
+ * (device, caller-allocated, that many elements of the input type).
+ * Stream-ordered, does not synchronise. Pass the copy to bumbar_sweep with
+ * u_dtype BUMBAR_F64_SMAJOR / BUMBAR_F32_SMAJOR. bumbar_solve makes such a
+ * copy in its workspace by itself (bumbar_options.sample_major).
+ */
+int64_t bumbar_sample_major_elems(int K, int64_t N);
+int bumbar_sample_major(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                        int64_t ld, void* u_nk);
 
 /* W_nk = exp(f_k - u_kn - ln D_n), N x K float64 (sample-major). */
 int bumbar_weights(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,

@@ -16,7 +16,7 @@ from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,
                     FINISH_NEWTON, FINISH_SCI, MODEL_HARMONIC, MODEL_LINEAR, MODEL_NONE, OK,
                     PREC_FP64, PREC_MIXED, REPRESENT_AUTO, REPRESENT_CENTRE, REPRESENT_MEAN)
 
-__all__ = ["Context", "solve", "sweep", "hessian", "weights", "bin_coordinates", "reweight", "pmf",
+__all__ = ["Context", "solve", "plan", "sweep", "sample_major", "SampleMajor", "hessian", "weights", "bin_coordinates", "reweight", "pmf",
            "model_energies", "sweep_model", "hessian_model", "Server",
            "BumbarError", "default_options"]
 
@@ -82,6 +82,10 @@ class Context:
         self.check(self.lib.bumbar_query_workspace(self.h, K, N, d, o, C.byref(nb)))
         return nb.value
 
+    def step_workspace(self, K, N):
+        """Workspace of the single-step calls (no binning, no sample-major copy)."""
+        return self.query_workspace(K, N, 0, default_options(sample_major=0))
+
 
 _default_ctx = {}
 
@@ -93,6 +97,21 @@ def context(device=None):
     if key not in _default_ctx:
         _default_ctx[key] = Context(dev)
     return _default_ctx[key]
+
+
+def plan(K, N, d=0, model=MODEL_NONE, u_dtype=F64, stored_u=True, num_cus=256, **options):
+    """What bumbar_solve would run for this shape and options (bumbar_plan_solve, host only).
+
+    Raises BumbarError for a combination the solver refuses."""
+    lib = _capi.load()
+    o = default_options(**options)
+    p = _capi.Plan()
+    msg = C.create_string_buffer(256)
+    rc = lib.bumbar_plan_solve(num_cus, int(bool(stored_u)), u_dtype, K, N, d, model, C.byref(o),
+                               C.byref(p), msg, 256)
+    if rc != 0:
+        raise BumbarError(rc, msg.value.decode())
+    return {f: getattr(p, f) for f, _ in _capi.Plan._fields_}
 
 
 def default_options(**kw):
@@ -178,6 +197,8 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     replay = options.pop("replay", None)
     options.setdefault("represent", _capi.REPRESENT_CENTRE if model != MODEL_NONE
                        else _capi.REPRESENT_MEAN)
+    if u is not None:
+        options.setdefault("u_dtype", _dtype_code(u))
     opts = default_options(binning=int(bool(binning)), **options)
     keep = None
     if replay is not None:
@@ -222,24 +243,52 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     return f, info
 
 
+class SampleMajor:
+    """The sample-major copy of a K x N matrix (``sample_major``): device data plus its shape."""
+
+    def __init__(self, data, K, N, code):
+        self.data, self.K, self.N, self.code = data, K, N, code
+        self.device = data.device
+        self.shape = (K, N)
+
+
+def sample_major(u, ctx=None):
+    """Sample-major copy of u (K x N state-major, 256 < K <= 1024) for ``sweep``."""
+    torch = _torch()
+    ctx = ctx or context()
+    K, N = u.shape
+    code = _dtype_code(u)
+    n = ctx.lib.bumbar_sample_major_elems(K, N)
+    if n < 0:
+        raise BumbarError(EINVAL, "the sample-major layout is defined for 256 < K <= 1024")
+    out = torch.empty(int(n), dtype=u.dtype, device=u.device)
+    ctx.check(ctx.lib.bumbar_sample_major(ctx.h, _ptr(u), code, K, N, u.stride(0), _ptr(out)))
+    _keep(ctx, u)
+    return SampleMajor(out, K, N, _capi.F64_SMAJOR if code == F64 else _capi.F32_SMAJOR)
+
+
 def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True, want_logD=True):
     """One unbinned SCI step (Eq. (1), one sample per bin). Returns f_new, ln D, S, stats.
 
-    With ``want_logD=False`` no ln D is written (the form the SCI iteration
-    uses) and None is returned in its place."""
+    ``u`` is a K x N tensor or the ``SampleMajor`` copy of one. With
+    ``want_logD=False`` no ln D is written (the form the SCI iteration uses)
+    and None is returned in its place."""
     torch = _torch()
     ctx = ctx or context()
     dev = u.device
     K, N = u.shape[0], u.shape[1]
-    ld = u.stride(0) if ld is None else ld
+    if isinstance(u, SampleMajor):
+        code, ld, uptr = u.code, N, _ptr(u.data)
+    else:
+        code, ld, uptr = _dtype_code(u), (u.stride(0) if ld is None else ld), _ptr(u)
     Nk_t = _dev(Nk, torch.int64, dev)
     f_t = _dev(f, torch.float64, dev)
-    ws = ctx.workspace(ctx.query_workspace(K, N, 0))
+    ws = ctx.workspace(ctx.step_workspace(K, N))
     f_new = torch.empty(K, dtype=torch.float64, device=dev)
     lD = torch.empty(N, dtype=torch.float64, device=dev) if want_logD else None
     S = torch.empty(K, dtype=torch.float64, device=dev)
     stats = (C.c_double * 4)() if with_stats else None
-    rc = ctx.lib.bumbar_sweep(ctx.h, _ptr(u), _dtype_code(u), K, N, ld, _ptr(Nk_t), _ptr(f_t),
+    rc = ctx.lib.bumbar_sweep(ctx.h, uptr, code, K, N, ld, _ptr(Nk_t), _ptr(f_t),
                               _ptr(ws), ws.numel(), _ptr(f_new),
                               _ptr(lD), _ptr(S),
                               C.cast(stats, C.POINTER(C.c_double)) if stats else None)
@@ -257,7 +306,7 @@ def hessian(u, Nk, f, logD, S, ctx=None):
     ctx = ctx or context()
     dev = u.device
     K, N = u.shape
-    ws = ctx.workspace(ctx.query_workspace(K, N, 0))
+    ws = ctx.workspace(ctx.step_workspace(K, N))
     H = torch.empty((K, K), dtype=torch.float64, device=dev)
     # keep every marshalled tensor alive until the queued kernels have run
     Nk_t = _dev(Nk, torch.int64, dev)

@@ -22,6 +22,8 @@ EBUSY = -6
 
 F64 = 0
 F32 = 1
+F64_SMAJOR = 2
+F32_SMAJOR = 3
 PREC_FP64 = 0
 PREC_MIXED = 1
 FINISH_NEWTON = 0
@@ -51,7 +53,8 @@ class Options(C.Structure):
                 ("max_newton", C.c_int), ("sci_switch", C.c_double),
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
                 ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
-                ("represent", C.c_int), ("graphs", C.c_int)]
+                ("represent", C.c_int), ("graphs", C.c_int), ("sample_major", C.c_int),
+                ("u_dtype", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -66,6 +69,22 @@ class Stats(C.Structure):
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
                 ("checks_capacity", C.c_int), ("graph_batches", C.c_int64),
                 ("grid_sweeps", C.c_int64), ("batched_steps", C.c_int64)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("precision", C.c_int), ("represent", C.c_int), ("sweep", C.c_int),
+                ("stage32", C.c_int), ("fp32_binned", C.c_int), ("hessian_fp16", C.c_int),
+                ("copy_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t)]
+
+
+SWEEP_REGISTER = 0
+SWEEP_SAMPLE_MAJOR = 1
+SWEEP_TWO_PASS = 2
+SWEEP_MODEL = 3
+STAGE32_NONE = 0
+STAGE32_PACKED = 1
+STAGE32_SAMPLE_MAJOR = 2
+STAGE32_MODEL = 3
 
 
 class ServerOptions(C.Structure):
@@ -89,6 +108,9 @@ SIGNATURES = {
     "bumbar_default_options": (None, [C.POINTER(Options)]),
     "bumbar_query_workspace": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.POINTER(Options),
                                          C.POINTER(C.c_size_t)]),
+    "bumbar_plan_solve": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int,
+                                    C.c_int, C.POINTER(Options), C.POINTER(Plan), C.c_char_p,
+                                    C.c_size_t]),
     "bumbar_solve": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, vp, vp, C.c_int, C.c_int, vp,
                                vp, C.POINTER(Options), vp, C.c_size_t, vp, vp, vp,
                                C.POINTER(Stats)]),
@@ -96,6 +118,8 @@ SIGNATURES = {
                                C.c_size_t, vp, vp, vp, dp]),
     "bumbar_hessian": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp, vp,
                                  vp, C.c_size_t, vp]),
+    "bumbar_sample_major_elems": (C.c_int64, [C.c_int, C.c_int64]),
+    "bumbar_sample_major": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp]),
     "bumbar_weights": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp]),
     "bumbar_bin": (C.c_int, [vp, vp, C.c_int64, C.c_int, C.c_int64, vp, C.c_size_t, u64p, i64p,
                              vp, vp, vp]),

@@ -70,11 +70,29 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
 bool sweep_fast_supported(int K);
 
 // Robust two-pass sweep: exact column max, then per-state online log-sum-exp.
-// u is FP64, or FP32 when f32 (widened on load).
+// u is FP64, or FP32 when f32 (widened on load); state-major with row stride
+// ld, or (sample_major) the sample-major copy with rows of ld values.
 hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                                const double* cst, const double* gk, const double* h,
                                double* logD, double* partM, double* partS, double* part_obj,
-                               unsigned* part_flags, int chunks);
+                               unsigned* part_flags, int chunks, bool sample_major = false);
+
+// Sample-major copy of u for 256 < K <= 1024 (sweep_smaj.hip): N rows of
+// Kp = smaj_row(K) = 64 J values (J in {5, 6, 8, 10, 12, 14, 16}, the smallest
+// with K <= 64 J), states past K = +inf, so that a
+// sample is one contiguous row; smaj_elems = N Kp. launch_sweep_smaj: the
+// single-pass sweep over it, one wavefront per sample, in FP64 arithmetic
+// (FP64 copy, or FP32 copy widened) or, with f32_arith, FP32 arithmetic on
+// an FP32 copy (mixed precision).
+int smaj_row(int K);
+size_t smaj_elems(int K, int64_t N);
+bool sweep_smaj_supported(int K);
+hipError_t launch_smaj_copy(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
+                            void* ut);
+hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_arith, int K,
+                             int64_t N, const double* cst, const double* gk, const double* h,
+                             double* logD, double* part, double* part_obj, unsigned* part_flags,
+                             int num_cus, int* grid_out);
 
 // Finaliser. mode 0: partials are S' sums (fast path), partS a scratch of K
 // doubles for their per-state sums (or null); mode 1: (M, S) pairs in
@@ -170,7 +188,8 @@ hipError_t launch_weights_otf(hipStream_t s, const OtfModel& m, int K, int64_t N
 // K > 256 run on FP16 matrix cores (FP32 accumulation within a chunk).
 struct HessSource {
   int kind = 0;  // as Mat::kind; 5: stored FP64 u on the FP16 matrix cores (K > 256);
-                 // 6: stored FP64 u with FP32 exponentials (FP64 accumulation)
+                 // 6: stored FP64 u with FP32 exponentials (FP64 accumulation);
+                 // 8: stored FP32 u on the FP16 matrix cores (K > 256)
   int num_cus = 256;  // sizes the sample chunks of the FP16-core path
   const void* u = nullptr;
   int64_t ld = 0;
@@ -188,7 +207,7 @@ hipError_t launch_sweep_wide(hipStream_t s, const void* u, bool f32, int64_t ld,
                              int* grid_out);
 // Mixed precision (sweep32.hip).
 bool sweep32_supported(int K);
-hipError_t launch_pack_f32(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+hipError_t launch_pack_f32(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                            const double* c0, float* r, int64_t ldr, double* m0);
 hipError_t launch_delta(hipStream_t s, int K, const double* f, const double* f0, double* d);
 hipError_t launch_sweep32(hipStream_t s, const float* r, int64_t ld, int K, int64_t N,

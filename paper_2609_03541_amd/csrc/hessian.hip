@@ -529,14 +529,15 @@ struct SrcPacked32 {
   }
 };
 
-// Stored FP64 u: t_kn = log2(e) (c_k - u_kn) + e_n with e_n = -log2(e) ln D_n;
-// the difference is taken in FP64 per element and the product rounded to
-// FP32.
-struct SrcMat64h {
-  const double* u;
+// Stored FP64 or FP32 u: t_kn = log2(e) (c_k - u_kn) + e_n with
+// e_n = -log2(e) ln D_n; the difference is taken in FP64 per element and the
+// product rounded to FP32.
+template <typename TI>
+struct SrcMatH {
+  const TI* u;
   int64_t ld;
   struct Row {
-    const double* p;
+    const TI* p;
     double c;
   };
   __device__ Row row(int k, double ck) const { return {u + (int64_t)k * ld, ck}; }
@@ -548,7 +549,7 @@ struct SrcMat64h {
       float cv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        x[q] = rw.p[n + h + q];
+        x[q] = (double)rw.p[n + h + q];
         cv[q] = colv[n + h + q];
       }
 #pragma unroll
@@ -560,7 +561,7 @@ struct SrcMat64h {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int64_t m = n + q < last ? n + q : last;
-      t[q] = (float)(kLog2eH * (rw.c - rw.p[m])) + colv[m];
+      t[q] = (float)(kLog2eH * (rw.c - (double)rw.p[m])) + colv[m];
     }
   }
 };
@@ -880,7 +881,7 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
-  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3 || hs.kind == 5)) {
+  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3 || hs.kind == 5 || hs.kind == 8)) {
     const int nb16 = h16_nb(K);
     const int nblk16 = nb16 * (nb16 + 1) / 2;
     const int ch16 = h16_chunks(K, N, hs.num_cus);
@@ -897,9 +898,13 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                          SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
                          cst, gk, colv, nb16, ch16, len16, vec, p16);
     } else if (hs.kind == 5) {
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcMat64h>, g16, dim3(512), 0, s,
-                         SrcMat64h{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst, gk,
-                         colv, nb16, ch16, len16, false, p16);
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcMatH<double>>, g16, dim3(512), 0, s,
+                         SrcMatH<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
+                         gk, colv, nb16, ch16, len16, false, p16);
+    } else if (hs.kind == 8) {
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcMatH<float>>, g16, dim3(512), 0, s,
+                         SrcMatH<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst,
+                         gk, colv, nb16, ch16, len16, false, p16);
     } else if (hs.otf.d == 1) {
       hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<1>>, g16, dim3(512), 0, s,
                          SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
@@ -924,6 +929,7 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                      logD, nb, chunks, chunk_len, partials);
       break;
     case 1:
+    case 8:  // FP32 u where the FP16-core path does not apply (K <= kSmallMaxK)
       launch_any(s, SrcMat<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst, gk,
                      logD, nb, chunks, chunk_len, partials);
       break;

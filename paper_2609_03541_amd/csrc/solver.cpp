@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -139,7 +140,12 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
   int grid = 0;
   std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
   if (timed && ctx->profiling && h == nullptr) ev = next_event_pair(ctx);
-  if (M.kind == 2) {
+  if (M.ut != nullptr) {
+    // the sample-major copy (FP64 arithmetic, or FP32 for kind 7)
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_smaj(s, M.ut, M.ut_f32, M.kind == 7, K, N, B.cst, B.gk, h, logD_out, B.part,
+                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
+  } else if (M.kind == 2) {
     e = launch_delta(s, K, f, M.f0, B.dk);
     if (e != hipSuccess) return hip_fail(ctx, e, "delta");
     if (ev) (void)hipEventRecord(ev->first, s);
@@ -190,7 +196,7 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
     rc = read_scalars(ctx, B.scal, out);
     if (rc) return rc;
     // FP32 kinds: flags are the caller's signal to leave FP32
-    if (M.kind == 2 || M.kind == 3) return BUMBAR_OK;
+    if (M.kind == 2 || M.kind == 3 || M.kind == 7) return BUMBAR_OK;
     if ((out->flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) == 0) {
       if (cnt && M.kind == 4 && M.otf.sep) cnt->grid++;
       return BUMBAR_OK;
@@ -214,8 +220,10 @@ int sweep_at(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int64_t N, co
   hipError_t e = launch_prepare_consts(s, K, Nk, f, B.cst, B.gk, B.lnNp);
   if (e != hipSuccess) return hip_fail(ctx, e, "prepare_consts");
   const int ch = robust_chunks(N);
-  e = launch_sweep_robust(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
-                          B.partS, B.part_obj, B.part_flags, ch);
+  e = launch_sweep_robust(s, M.ut ? M.ut : M.u, M.ut ? M.ut_f32 : M.kind == 1,
+                          M.ut ? smaj_row(K) : M.ld, K, N,
+                          B.cst, B.gk, h, logD_out, B.part, B.partS, B.part_obj, B.part_flags, ch,
+                          M.ut != nullptr);
   if (e != hipSuccess) return hip_fail(ctx, e, "sweep_robust");
   e = launch_sweep_finalize(s, 1, K, ch, B.part, B.partS, B.part_obj, B.part_flags, f, B.lnNp, Nk,
                             f_out, lnS_out, S_out, B.scal);
@@ -277,7 +285,7 @@ int newton_finish(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t*
   const int K = B.K;
   const int64_t N = B.N;
   SweepScalars sc{};
-  const bool fp32 = M.kind == 2 || M.kind == 3;
+  const bool fp32 = M.kind == 2 || M.kind == 3 || M.kind == 7;
   auto bad32 = [&](const SweepScalars& x) {
     return fp32 && (x.flags & (FLAG_COL | FLAG_STATE | FLAG_NAN)) != 0;
   };
@@ -501,17 +509,26 @@ void bumbar_default_options(bumbar_options* o) {
   o->mixed_tol = 1e-6;
   o->represent = BUMBAR_REPRESENT_AUTO;
   o->graphs = 1;
+  o->sample_major = 1;
+  o->u_dtype = BUMBAR_F64;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
-                        int64_t ld) {
+                        int64_t ld, bool smaj_ok = false) {
   if (!ctx) return BUMBAR_EINVAL;
   ctx->err.clear();
   if (!u) return fail(ctx, BUMBAR_EINVAL, "u_kn is NULL");
   if (K <= 0 || N <= 0) return fail(ctx, BUMBAR_EINVAL, "K and N must be positive");
-  if (ld < N) return fail(ctx, BUMBAR_EINVAL, "row stride ld < N");
-  if (u_dtype != BUMBAR_F64 && u_dtype != BUMBAR_F32)
-    return fail(ctx, BUMBAR_EINVAL, "u_dtype must be BUMBAR_F64 or BUMBAR_F32");
+  const bool smaj = u_dtype == BUMBAR_F64_SMAJOR || u_dtype == BUMBAR_F32_SMAJOR;
+  if (smaj) {
+    if (!smaj_ok) return fail(ctx, BUMBAR_EINVAL, "this call takes state-major u_kn only");
+    if (!sweep_smaj_supported(K))
+      return fail(ctx, BUMBAR_EINVAL, "the sample-major layout is defined for 256 < K <= 1024");
+  } else {
+    if (ld < N) return fail(ctx, BUMBAR_EINVAL, "row stride ld < N");
+    if (u_dtype != BUMBAR_F64 && u_dtype != BUMBAR_F32)
+      return fail(ctx, BUMBAR_EINVAL, "u_dtype must be BUMBAR_F64 or BUMBAR_F32");
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BUMBAR_EDEVICE, "hipSetDevice");
   return BUMBAR_OK;
 }
@@ -519,15 +536,38 @@ static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int6
 static Mat input_mat(const void* u, int u_dtype, int64_t ld) {
   Mat M;
   M.u = u;
-  M.kind = (u_dtype == BUMBAR_F32) ? 1 : 0;
+  M.kind = (u_dtype == BUMBAR_F32 || u_dtype == BUMBAR_F32_SMAJOR) ? 1 : 0;
   M.ld = ld;
+  if (u_dtype == BUMBAR_F64_SMAJOR || u_dtype == BUMBAR_F32_SMAJOR) {
+    M.ut = u;
+    M.ut_f32 = u_dtype == BUMBAR_F32_SMAJOR;
+  }
   return M;
+}
+
+int64_t bumbar_sample_major_elems(int K, int64_t N) {
+  if (!sweep_smaj_supported(K) || N <= 0) return -1;
+  return (int64_t)smaj_elems(K, N);
+}
+
+int bumbar_sample_major(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                        int64_t ld, void* u_nk) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (!sweep_smaj_supported(K))
+    return fail(ctx, BUMBAR_EINVAL, "the sample-major layout is defined for 256 < K <= 1024");
+  if (!u_nk) return fail(ctx, BUMBAR_EINVAL, "NULL output");
+  const hipError_t e = launch_smaj_copy(ctx->stream, u_kn, u_dtype == BUMBAR_F32, ld, K, N, u_nk);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sample-major copy");
+  return BUMBAR_OK;
 }
 
 int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N, int64_t ld,
                  const int64_t* N_k, const double* f, void* workspace, size_t ws_bytes,
                  double* f_new, double* log_D_n, double* S, double* sweep_stats) {
-  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  const bool smaj = u_dtype == BUMBAR_F64_SMAJOR || u_dtype == BUMBAR_F32_SMAJOR;
+  if (smaj) ld = N;
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld, true);
   if (rc) return rc;
   if (!N_k || !f || !f_new || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
@@ -538,7 +578,7 @@ int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   double* Sv = S ? S : B.S;
   SweepScalars sc{};
   const Mat M = input_mat(u_kn, u_dtype, ld);
-  if (sweep_stats == nullptr && M.kind == 0 && sweep_fast_supported(K)) {
+  if (sweep_stats == nullptr && ((M.kind == 0 && sweep_fast_supported(K)) || M.ut)) {
     // asynchronous: queue the sweep without reading anything back (the caller
     // accepts that a far-off f is not rerun on the robust path)
     return sweep_queue(ctx, B, M, N, nullptr, N_k, f, f_new, logD, B.lnS, Sv, B.scal);
@@ -775,53 +815,23 @@ int bumbar_model_energies(bumbar_ctx* ctx, int K, int64_t N, int d, int model,
   return BUMBAR_OK;
 }
 
-// Extra device buffers of the mixed-precision finisher.
-struct MixedBufs {
-  float* r = nullptr;     // K x N packed matrix
-  double* m0 = nullptr;   // N
-  double* f0 = nullptr;   // K
-  void carve(Arena& ar, int K, int64_t N) {
-    r = ar.take<float>((size_t)K * (size_t)N);
-    m0 = ar.take<double>(N);
-    f0 = ar.take<double>(K);
-  }
-};
-
-static bool mixed_enabled(const bumbar_options& opt, int u_dtype, int K) {
-  return opt.precision == BUMBAR_PREC_MIXED && u_dtype == BUMBAR_F64 && sweep32_supported(K) &&
-         opt.finisher == BUMBAR_FINISH_NEWTON;
-}
-
-// With a stored u_kn, bin representatives are materialised (K x P, one
-// represent pass per level) whenever the register-tiled sweep takes K: its
-// binned steps are one launch each. For larger K, bin-centre representatives
-// are evaluated inside the two-pass model sweep instead, which needs only the
-// P x d centres. MEAN always materialises.
-static bool stored_ubar_bufs(int rep, int K) {
-  return rep != BUMBAR_REPRESENT_CENTRE || sweep_fast_supported(K);
-}
-static bool centre_bufs(int rep, int K) {
-  return rep != BUMBAR_REPRESENT_MEAN && !sweep_fast_supported(K);
-}
-
 int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
                            const bumbar_options* opt, size_t* bytes) {
   if (!ctx || !bytes || K <= 0 || N <= 0 || d < 0 || d > 2) return BUMBAR_EINVAL;
+  bumbar_options o;
+  if (opt) {
+    o = *opt;
+    o.binning = o.binning && d > 0;
+  } else {
+    bumbar_default_options(&o);
+    o.binning = d > 0;
+  }
+  Plan p;
+  std::string why;
+  if (make_plan(o, false, o.u_dtype, K, N, d, -1, &p, &why) != BUMBAR_OK) return BUMBAR_EINVAL;
   Arena ar;
-  UnbinnedBufs B;
-  B.carve(ar, K, N, ctx->num_cus);
-  const int rep = opt ? opt->represent : BUMBAR_REPRESENT_AUTO;
-  const bool binned = d > 0 && (opt == nullptr || opt->binning);
-  if (binned)
-    binned_carve_size(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(rep, K), centre_bufs(rep, K));
-  if (opt && opt->precision == BUMBAR_PREC_MIXED && sweep32_supported(K)) {
-    MixedBufs X;
-    X.carve(ar, K, N);
-  }
-  if (binned && centre_bufs(rep, K)) {
-    OtfBufs O;
-    O.carve(ar, K, N, d);
-  }
+  PlanBufs pb;
+  carve_plan(ar, p, ctx->num_cus, &pb);
   *bytes = ar.off + 256;
   return BUMBAR_OK;
 }
@@ -829,14 +839,20 @@ int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
 int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
                                  const bumbar_options* opt, size_t* bytes) {
   if (!ctx || !bytes || K <= 0 || N <= 0 || d < 1 || d > 2) return BUMBAR_EINVAL;
+  bumbar_options o;
+  if (opt) {
+    o = *opt;
+  } else {
+    bumbar_default_options(&o);
+    o.binning = 1;
+  }
+  Plan p;
+  std::string why;
+  if (make_plan(o, true, BUMBAR_F64, K, N, d, BUMBAR_MODEL_HARMONIC, &p, &why) != BUMBAR_OK)
+    return BUMBAR_EINVAL;
   Arena ar;
-  UnbinnedBufs B;
-  B.carve(ar, K, N, ctx->num_cus);
-  if (opt == nullptr || opt->binning)
-    binned_carve_size(ar, K, N, d, ctx->num_cus, false, true,
-                      opt && opt->precision == BUMBAR_PREC_MIXED && K > 256, otf_ubar_cap(K, N));
-  OtfBufs O;
-  O.carve(ar, K, N, d);
+  PlanBufs pb;
+  carve_plan(ar, p, ctx->num_cus, &pb);
   *bytes = ar.off + 256;
   return BUMBAR_OK;
 }
@@ -857,26 +873,16 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   else
     bumbar_default_options(&opt);
   if (!N_k || !f_k || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
-  if (otf && (model == BUMBAR_MODEL_NONE || !xi || d < 1 || d > 2))
-    return fail(ctx, BUMBAR_EINVAL, "u_kn = NULL needs a model, its coefficients and xi (d in {1, 2})");
-  if (!(opt.tol > 0.0)) return fail(ctx, BUMBAR_EINVAL, "tol must be > 0");
-  if (opt.binning && (!xi || d < 1 || d > 2))
-    return fail(ctx, BUMBAR_EINVAL, "binning needs coordinates xi with d in {1, 2}");
-  if (opt.binning && (opt.n0 < 2 || opt.inc < 2 || opt.n_intermediate < 0 || !(opt.eps > 0.0)))
-    return fail(ctx, BUMBAR_EINVAL, "invalid binning settings");
-  if (model != BUMBAR_MODEL_NONE && model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC)
-    return fail(ctx, BUMBAR_EINVAL, "unknown model code");
   if (model != BUMBAR_MODEL_NONE && !coef) return fail(ctx, BUMBAR_EINVAL, "model needs coef");
-  if (opt.represent < BUMBAR_REPRESENT_AUTO || opt.represent > BUMBAR_REPRESENT_MEAN)
-    return fail(ctx, BUMBAR_EINVAL, "unknown bin representative");
-  const int rep = opt.represent != BUMBAR_REPRESENT_AUTO
-                      ? opt.represent
-                      : (model != BUMBAR_MODEL_NONE ? BUMBAR_REPRESENT_CENTRE
-                                                    : BUMBAR_REPRESENT_MEAN);
-  if (opt.binning && rep == BUMBAR_REPRESENT_CENTRE && model == BUMBAR_MODEL_NONE)
-    return fail(ctx, BUMBAR_EINVAL, "bin-centre representatives need a model");
-  if (opt.binning && rep == BUMBAR_REPRESENT_MEAN && (otf || u_dtype != BUMBAR_F64))
-    return fail(ctx, BUMBAR_EINVAL, "mean bin representatives need FP64 u_kn (or give a model)");
+  if ((opt.binning || otf) && !xi) return fail(ctx, BUMBAR_EINVAL, "xi is NULL");
+  Plan plan;
+  {
+    std::string why;
+    rc = make_plan(opt, otf, u_dtype, K, N, opt.binning || otf ? d : 0, model, &plan, &why);
+    if (rc) return fail(ctx, rc, "%s", why.c_str());
+  }
+  const int rep = plan.rep;
+  const bool mixed = plan.mixed;
   // counts: host copy for validation
   std::vector<int64_t> nk(K);
   rc = read_bytes(ctx, N_k, nk.data(), sizeof(int64_t) * K);
@@ -888,29 +894,21 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   }
   if (tot != N) return fail(ctx, BUMBAR_EINVAL, "sum of N_k (%lld) != N (%lld)", (long long)tot,
                             (long long)N);
-  const bool mixed = otf ? (opt.precision == BUMBAR_PREC_MIXED &&
-                            opt.finisher == BUMBAR_FINISH_NEWTON)
-                         : mixed_enabled(opt, u_dtype, K);
-  // carve order mirrors bumbar_query_workspace / bumbar_query_workspace_model
+  // the plan's buffers, in the order of the workspace queries
   Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
-  UnbinnedBufs B;
-  B.carve(ar, K, N, ctx->num_cus);
-  BinnedBufs BB;
-  if (opt.binning) {
-    // on the fly in mixed precision: FP32 centres for the binned steps
-    if (otf)
-      BB.carve(ar, K, N, d, ctx->num_cus, false, true, mixed && K > 256, otf_ubar_cap(K, N));
-    else
-      BB.carve(ar, K, N, d, ctx->num_cus, stored_ubar_bufs(opt.represent, K),
-               centre_bufs(opt.represent, K));
-    BB.otf = rep == BUMBAR_REPRESENT_CENTRE && (otf || !sweep_fast_supported(K));
-  }
-  MixedBufs X;
-  if (mixed && !otf) X.carve(ar, K, N);
-  OtfBufs O;
-  if (otf || (opt.binning && centre_bufs(opt.represent, K))) O.carve(ar, K, N, d);
+  PlanBufs pb;
+  carve_plan(ar, plan, ctx->num_cus, &pb);
   if (ar.overflow)
     return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
+  UnbinnedBufs& B = pb.B;
+  BinnedBufs& BB = pb.BB;
+  MixedBufs& X = pb.X;
+  OtfBufs& O = pb.O;
+  if (opt.binning) BB.otf = rep == BUMBAR_REPRESENT_CENTRE && (otf || !sweep_fast_supported(K));
+  // every buffer a planned path launches with must have been carved
+  if ((plan.x_packed && !X.r) || (plan.copy && !pb.copy) || (plan.o_bufs && !O.cf64) ||
+      (plan.fp32_binned && !BB.cenf[0]))
+    return fail(ctx, BUMBAR_EINVAL, "internal: a planned buffer was not carved");
   bumbar_stats local{};
   bumbar_stats* st = stats ? stats : &local;
   bumbar_check* chk = st->checks;
@@ -939,6 +937,13 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     rc = sep_setup(ctx, K, d, model, coef, O, &sep_grid, &on);
     if (rc) return rc;
     if (on) M.otf.sep = &sep_grid;
+  }
+  if (plan.copy) {
+    // the sample-major copy every unbinned sweep of this solve reads
+    e = launch_smaj_copy(s, u_kn, plan.copy_f32, N, K, N, pb.copy);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sample-major copy");
+    M.ut = pb.copy;
+    M.ut_f32 = plan.copy_f32;
   }
   SweepCounters cnt;
   ctx->profiling = opt.profile != 0;
@@ -977,16 +982,16 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     Mc.otf.sep = M.otf.sep;
     // MEAN ignores a given model: the representatives are the bin means of u
     const int rep_model = rep == BUMBAR_REPRESENT_MEAN ? BUMBAR_MODEL_NONE : model;
-    // On the fly in mixed precision with K > 256 (where a binned step is a
-    // compute-bound model sweep over K x P, not a few launches) the binned
-    // steps first run on the FP32 model sweep. That stage only provides the
+    // In mixed precision with K > 256 and bin-centre representatives (where a
+    // binned step is a compute-bound model sweep over K x P, not a few
+    // launches) the binned steps first run on the FP32 model sweep. That stage only provides the
     // Newton start, but FP32 rounding of large energies can keep its
     // relative-step tests from passing: if it has not converged within
     // kFp32BinnedSteps steps it is rerun in FP64 from the start. For smaller K
     // the FP32 noise costs more iterations than it saves per step.
     constexpr int64_t kFp32BinnedSteps = 4000;
     // (a product grid of windows steps faster on the factored FP64 sweep)
-    const bool try32 = otf && mixed && K > 256 && BB.cenf[0] != nullptr && !M.otf.sep;
+    const bool try32 = plan.fp32_binned && !M.otf.sep;
     if (try32) {
       bumbar_options o32 = opt;
       o32.max_iter = std::min<int64_t>(opt.max_iter, kFp32BinnedSteps);
@@ -1020,10 +1025,9 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   // (cheaper than the direct FP32 ones) with the Hessian from the FP32 model
   Mat Mfin = M;
   if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
-  // FP64 u: the Newton Hessian (which only shapes the steps; the FP64 sweeps
-  // decide the fixed point) on the FP16 matrix cores for K > 256, else with
-  // FP32 exponentials
-  if (!mixed && !otf && M.kind == 0) Mfin.hess_kind = K > 256 ? 5 : 6;
+  // stored u: the planned Newton Hessian source (it only shapes the steps;
+  // the FP64 sweeps decide the fixed point)
+  if (!otf) Mfin.hess_kind = plan.hess_kind;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
       if (mixed && otf && !M.otf.sep) {
@@ -1037,13 +1041,24 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
                                 &st->grad_norm);
         if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
         st->mixed_steps = st->finisher_steps - before;
-      } else if (mixed && !otf) {
+      } else if (mixed && plan.stage32 == BUMBAR_STAGE32_SAMPLE_MAJOR) {
+        // Newton on FP32-arithmetic sweeps of the sample-major copy to
+        // mixed_tol, then FP64 refinement on the same copy to tol
+        Mat R = M;
+        R.kind = 7;
+        R.hess_kind = plan.hess_kind32;
+        const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
+        const int64_t before = st->finisher_steps;
+        int mrc = newton_finish(ctx, B, R, N_k, mtol, opt.max_newton, st, &cnt, &st->final_step,
+                                &st->grad_norm);
+        if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
+        st->mixed_steps = st->finisher_steps - before;
+      } else if (mixed && plan.stage32 == BUMBAR_STAGE32_PACKED) {
         // pack at the current f, Newton on the FP32 matrix to mixed_tol, then
         // FP64 refinement on u to tol
-        if (!u_kn || !X.r) return fail(ctx, BUMBAR_EINVAL, "mixed precision needs u_kn or a model");
         e = launch_prepare_consts(s, K, N_k, B.f, B.cst, B.gk, B.lnNp);
-        if (e == hipSuccess) e = launch_pack_f32(s, reinterpret_cast<const double*>(u_kn), N, K,
-                                                 N, B.cst, X.r, N, X.m0);
+        if (e == hipSuccess) e = launch_pack_f32(s, u_kn, u_dtype == BUMBAR_F32, N, K, N, B.cst,
+                                                 X.r, N, X.m0);
         if (e == hipSuccess)
           e = hipMemcpyAsync(X.f0, B.f, sizeof(double) * K, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(ctx, e, "pack");

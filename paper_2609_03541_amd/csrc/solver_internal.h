@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <string>
 
 #include "bumbar_impl.h"
 
@@ -30,13 +31,16 @@ struct SweepCounters {
 // model evaluated inside the kernels (FP32 or FP64 arithmetic).
 struct Mat {
   const void* u = nullptr;
-  int kind = 0;  // 0: FP64, 1: FP32, 2: packed, 3: model FP32, 4: model FP64
+  int kind = 0;  // 0: FP64, 1: FP32, 2: packed, 3: model FP32, 4: model FP64,
+                 // 7: FP32 arithmetic over the sample-major copy (ut)
   int64_t ld = 0;
   const double* m0 = nullptr;  // kind 2: per-column shift (N)
   const double* f0 = nullptr;  // kind 2: reference point (K)
   OtfModel otf;                // kinds 3 and 4
   int hess_kind = -1;          // kind the Newton Hessian reads (-1: kind; 5: FP64 u
                                // on the FP16 matrix cores; 6: FP64 u, FP32 exponentials)
+  const void* ut = nullptr;    // the sample-major copy the sweeps read (kinds 0, 1, 7), or null
+  bool ut_f32 = false;         // its element type
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the
@@ -83,6 +87,49 @@ struct UnbinnedBufs {
   int m_red = -1;        // reduced Newton size when idx was uploaded by the host, else -1
   void carve(Arena& ar, int K, int64_t N, int num_cus);
 };
+
+// Extra device buffers of the packed mixed-precision stage (K <= 256).
+struct MixedBufs {
+  float* r = nullptr;     // K x N packed matrix
+  double* m0 = nullptr;   // N
+  double* f0 = nullptr;   // K
+  void carve(Arena& ar, int K, int64_t N) {
+    r = ar.take<float>((size_t)K * (size_t)N);
+    m0 = ar.take<double>(N);
+    f0 = ar.take<double>(K);
+  }
+};
+
+// What bumbar_solve runs and which workspace buffers it carves, decided on
+// the host from the call's shapes and options alone (plan.cpp). The solve,
+// the workspace queries and bumbar_plan_solve share it, so the buffers a
+// path launches with are exactly the ones carved for it.
+struct Plan {
+  bool otf = false;        // energies from the model (u_kn = NULL)
+  int u_dtype = BUMBAR_F64;
+  int K = 0;
+  int64_t N = 0;
+  int d = 0;
+  bool binning = false;
+  int rep = 0;             // resolved representative (binning only)
+  bool mixed = false;      // an FP32 Newton stage runs before the FP64 one
+  int sweep = BUMBAR_SWEEP_REGISTER;
+  int stage32 = BUMBAR_STAGE32_NONE;
+  bool fp32_binned = false;  // binned steps first on the FP32 model sweep
+  bool copy = false;         // sample-major copy of u in the workspace
+  bool copy_f32 = false;     // its element type
+  // carve flags
+  bool bb_ubar = false, bb_cen = false, bb_cen_f32 = false;
+  int64_t bb_otf_cap = 0;
+  bool x_packed = false, o_bufs = false;
+  int hess_kind = -1;      // Newton Hessian source of the FP64 stage (-1: the sweep's kind)
+  int hess_kind32 = -1;    // and of the FP32 stage
+  size_t copy_bytes() const;
+};
+
+// Fills *p; returns BUMBAR_OK or BUMBAR_EINVAL with the reason in *msg.
+int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N, int d,
+              int model, Plan* p, std::string* msg);
 
 // One sweep of M at f. With a packed matrix a flagged sweep (weights outside
 // the FP32 range) is reported through sc->flags and not redone.
@@ -225,5 +272,15 @@ hipError_t launch_centres(hipStream_t s, int d, const double* lo, const double* 
 hipError_t launch_sample_bin(hipStream_t s, int64_t N, const uint32_t* perm,
                              const int32_t* bin_of_pos, int32_t* sample_bin);
 hipError_t launch_counts_from_start(hipStream_t s, int64_t P, const int64_t* start, int64_t* H);
+
+// Carves the plan's buffers in a fixed order (the solve and the queries).
+struct PlanBufs {
+  UnbinnedBufs B;
+  BinnedBufs BB;
+  MixedBufs X;
+  OtfBufs O;
+  void* copy = nullptr;
+};
+void carve_plan(Arena& ar, const Plan& p, int num_cus, PlanBufs* pb);
 
 }  // namespace bumbar

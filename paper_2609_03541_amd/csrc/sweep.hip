@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(NW * 64)
   if (tid == 0) part_flags[blockIdx.x] = fl;
 }
 
-// Launch configuration table: (NW, LPR, CPL, ROWS, PF) by number of states.
+// Launch configuration table: (NW, LPR, CPL, ROWS, PF, SG) by number of states.
 struct FastCfg {
   int kmax, nw, lpr, cpl, rows, pf, sg;
 };
@@ -365,43 +365,7 @@ static const FastCfg kCfgs[] = {
     {128, 4, 32, 2, 16, 0, 1},
     {256, 8, 32, 2, 16, 0, 1},
 };
-// Extra instantiations reachable through BUMBAR_SWEEP_CFG="nw,lpr,cpl,rows,pf,sg"
-// (launch-shape tuning; results do not depend on the shape beyond rounding).
-static const FastCfg kTune[] = {
-    {0, 4, 32, 2, 13, 1, 0}, {0, 4, 32, 2, 13, 1, 2}, {0, 4, 32, 2, 13, 1, 1},
-    {0, 8, 32, 2, 7, 1, 0},  {0, 8, 32, 2, 7, 0, 0},  {0, 4, 64, 2, 8, 1, 0},
-};
-
-static FastCfg read_forced_cfg(int* state) {
-  FastCfg forced{};
-  *state = 0;
-  {
-    int& forced_state = *state;
-    if (const char* e = getenv("BUMBAR_SWEEP_CFG")) {
-      FastCfg c{};
-      if (sscanf(e, "%d,%d,%d,%d,%d,%d", &c.nw, &c.lpr, &c.cpl, &c.rows, &c.pf, &c.sg) == 6) {
-        auto same = [&](const FastCfg& t) {
-          return t.nw == c.nw && t.lpr == c.lpr && t.cpl == c.cpl && t.rows == c.rows &&
-                 t.pf == c.pf && t.sg == c.sg;
-        };
-        for (const auto& t : kTune)
-          if (same(t)) forced_state = 1;
-        for (const auto& t : kCfgs)
-          if (same(t)) forced_state = 1;
-        if (*state) {
-          forced = c;
-          forced.kmax = (c.nw * 64 / c.lpr) * c.rows;
-        }
-      }
-    }
-  }
-  return forced;
-}
-
 static const FastCfg* pick_cfg(int K) {
-  static int forced_state = 0;
-  static FastCfg forced = read_forced_cfg(&forced_state);  // thread-safe one-time init
-  if (forced_state == 1) return K <= forced.kmax ? &forced : nullptr;
   for (const auto& c : kCfgs)
     if (K <= c.kmax) return &c;
   return nullptr;
@@ -460,12 +424,6 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
   BUMBAR_CFG(4, 32, 2, 13, 0, 0)
   BUMBAR_CFG(4, 32, 2, 16, 0, 1)
   BUMBAR_CFG(8, 32, 2, 16, 0, 1)
-  BUMBAR_CFG(4, 32, 2, 13, 1, 0)
-  BUMBAR_CFG(4, 32, 2, 13, 1, 2)
-  BUMBAR_CFG(4, 32, 2, 13, 1, 1)
-  BUMBAR_CFG(8, 32, 2, 7, 1, 0)
-  BUMBAR_CFG(8, 32, 2, 7, 0, 0)
-  BUMBAR_CFG(4, 64, 2, 8, 1, 0)
 #undef BUMBAR_CFG
   return hipErrorInvalidValue;
 }
@@ -474,10 +432,12 @@ hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, 
 // Robust two-pass sweep (any K; underflow-safe for arbitrarily poor f).
 // ---------------------------------------------------------------------------
 
-// Pass A: exact ln D_n per column (thread per column, coalesced along n).
+// Element (k, n) of u is at k * sk + n * sn: state-major (sk = ld, sn = 1) or
+// the sample-major copy (sk = 1, sn = its row length).
+// Pass A: exact ln D_n per column (thread per column).
 template <typename TI>
 __global__ void __launch_bounds__(256)
-    robust_logD_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
+    robust_logD_kernel(const TI* __restrict__ u, int64_t sk, int64_t sn, int K, int64_t N,
                        const double* __restrict__ cst, const double* __restrict__ gk,
                        double* __restrict__ logD, unsigned* __restrict__ bad_out) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -485,14 +445,14 @@ __global__ void __launch_bounds__(256)
   if (n < N) {
     double m = -INFINITY;
     for (int k = 0; k < K; ++k) {
-      const double a = cst[k] - (double)u[(int64_t)k * ld + n];
+      const double a = cst[k] - (double)u[(int64_t)k * sk + n * sn];
       if (gk[k] != 0.0) m = fmax(m, a);
       if (a != a || a == INFINITY) bad |= FLAG_NAN;
     }
     double D = 0.0;
     if (m > -INFINITY && m < INFINITY) {
       for (int k = 0; k < K; ++k)
-        if (gk[k] != 0.0) D += exp_nonpos(cst[k] - (double)u[(int64_t)k * ld + n] - m);
+        if (gk[k] != 0.0) D += exp_nonpos(cst[k] - (double)u[(int64_t)k * sk + n * sn] - m);
       logD[n] = m + log(D);
     } else {
       logD[n] = m;
@@ -528,7 +488,7 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
 
 template <typename TI>
 __global__ void __launch_bounds__(kRobustThreads)
-    robust_state_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
+    robust_state_kernel(const TI* __restrict__ u, int64_t sk, int64_t sn, int K, int64_t N,
                         const double* __restrict__ h, const double* __restrict__ logD,
                         double* __restrict__ partM, double* __restrict__ partS,
                         double* __restrict__ part_obj) {
@@ -557,7 +517,7 @@ __global__ void __launch_bounds__(kRobustThreads)
     for (int i = 0; i < kRobustPerThread; ++i) {
       const int64_t n = base + tid + (int64_t)i * kRobustThreads;
       if (n < N) {
-        const double t = lh[i] - (double)u[(int64_t)k * ld + n] - lD[i];
+        const double t = lh[i] - (double)u[(int64_t)k * sk + n * sn] - lD[i];
         lse_merge(m, s, t, 1.0);
       }
     }
@@ -594,29 +554,32 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 }
 
 template <typename TI>
-static hipError_t launch_robust_t(hipStream_t s, const TI* u, int64_t ld, int K, int64_t N,
+static hipError_t launch_robust_t(hipStream_t s, const TI* u, int64_t sk, int64_t sn, int K,
+                                  int64_t N,
                                   const double* cst, const double* gk, const double* h,
                                   double* logD, double* partM, double* partS, double* part_obj,
                                   unsigned* part_flags, int chunks) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3((chunks + 255) / 256), dim3(256), 0, s, part_flags,
                      chunks);
   const int64_t nb = (N + 255) / 256;
-  hipLaunchKernelGGL(robust_logD_kernel<TI>, dim3((unsigned)nb), dim3(256), 0, s, u, ld, K, N, cst,
-                     gk, logD, part_flags);
-  hipLaunchKernelGGL(robust_state_kernel<TI>, dim3(chunks), dim3(kRobustThreads), 0, s, u, ld, K,
-                     N, h, logD, partM, partS, part_obj);
+  hipLaunchKernelGGL(robust_logD_kernel<TI>, dim3((unsigned)nb), dim3(256), 0, s, u, sk, sn, K, N,
+                     cst, gk, logD, part_flags);
+  hipLaunchKernelGGL(robust_state_kernel<TI>, dim3(chunks), dim3(kRobustThreads), 0, s, u, sk, sn,
+                     K, N, h, logD, partM, partS, part_obj);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                                const double* cst, const double* gk, const double* h,
                                double* logD, double* partM, double* partS, double* part_obj,
-                               unsigned* part_flags, int chunks) {
+                               unsigned* part_flags, int chunks, bool sample_major) {
+  // sample-major: ld is the row length of the copy
+  const int64_t sk = sample_major ? 1 : ld, sn = sample_major ? ld : 1;
   if (f32)
-    return launch_robust_t<float>(s, reinterpret_cast<const float*>(u), ld, K, N, cst, gk, h, logD,
-                                  partM, partS, part_obj, part_flags, chunks);
-  return launch_robust_t<double>(s, reinterpret_cast<const double*>(u), ld, K, N, cst, gk, h, logD,
-                                 partM, partS, part_obj, part_flags, chunks);
+    return launch_robust_t<float>(s, reinterpret_cast<const float*>(u), sk, sn, K, N, cst, gk, h,
+                                  logD, partM, partS, part_obj, part_flags, chunks);
+  return launch_robust_t<double>(s, reinterpret_cast<const double*>(u), sk, sn, K, N, cst, gk, h,
+                                 logD, partM, partS, part_obj, part_flags, chunks);
 }
 
 // ---------------------------------------------------------------------------

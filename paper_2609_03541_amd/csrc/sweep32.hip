@@ -30,23 +30,31 @@ __device__ __forceinline__ float exp_f32(float x) {
 // Pack: one thread per column, two passes over the column (the second from
 // cache). Rows past K do not exist here; unsampled states take part in the
 // maximum so every r <= 0.
+// u is FP64, or FP32 (widened: the differences are taken in FP64 either way).
+template <typename TI>
 __global__ void __launch_bounds__(256)
-    pack_f32_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    pack_f32_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                     const double* __restrict__ c0, float* __restrict__ r, int64_t ldr,
                     double* __restrict__ m0) {
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   double m = -INFINITY;
-  for (int k = 0; k < K; ++k) m = fmax(m, c0[k] - u[(int64_t)k * ld + n]);
+  for (int k = 0; k < K; ++k) m = fmax(m, c0[k] - (double)u[(int64_t)k * ld + n]);
   if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
   m0[n] = m;
-  for (int k = 0; k < K; ++k) r[(int64_t)k * ldr + n] = (float)(c0[k] - u[(int64_t)k * ld + n] - m);
+  for (int k = 0; k < K; ++k)
+    r[(int64_t)k * ldr + n] = (float)(c0[k] - (double)u[(int64_t)k * ld + n] - m);
 }
 
-hipError_t launch_pack_f32(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
+hipError_t launch_pack_f32(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
                            const double* c0, float* r, int64_t ldr, double* m0) {
-  hipLaunchKernelGGL(pack_f32_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, u, ld, K,
-                     N, c0, r, ldr, m0);
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (f32)
+    hipLaunchKernelGGL(pack_f32_kernel<float>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(u), ld, K, N, c0, r, ldr, m0);
+  else
+    hipLaunchKernelGGL(pack_f32_kernel<double>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(u), ld, K, N, c0, r, ldr, m0);
   return hipGetLastError();
 }
 

@@ -1,0 +1,84 @@
+"""Host-side planning of bumbar_solve (bumbar_plan_solve): no GPU needed.
+
+Each case fixes which sweep, FP32 stage and workspace copy a problem shape
+and option set gets, and that combinations the kernels do not cover are
+refused (EINVAL) instead of being run in another precision.
+"""
+import pytest
+
+from paper_2609_03541_amd import _capi
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import paper_2609_03541_amd as bm
+    _capi.load()
+    return bm
+
+
+def test_small_k_fp64_register_sweep(bm):
+    p = bm.plan(100, 1_000_000, d=1, model=bm.MODEL_HARMONIC, binning=1, represent=1)
+    assert p["sweep"] == _capi.SWEEP_REGISTER
+    assert p["stage32"] == _capi.STAGE32_NONE and p["precision"] == bm.PREC_FP64
+    assert p["copy_bytes"] == 0 and p["hessian_fp16"] == 0
+
+
+def test_large_k_fp64_sample_major_copy(bm):
+    K, N = 1000, 2_000_000
+    p = bm.plan(K, N, d=2, model=bm.MODEL_LINEAR, binning=1, represent=1)
+    assert p["sweep"] == _capi.SWEEP_SAMPLE_MAJOR
+    assert p["copy_bytes"] == N * 1024 * 8  # rows of 64 J, J = 16
+    assert p["workspace_bytes"] > p["copy_bytes"]
+    assert p["hessian_fp16"] == 1
+    off = bm.plan(K, N, d=2, model=bm.MODEL_LINEAR, binning=1, represent=1, sample_major=0)
+    assert off["sweep"] == _capi.SWEEP_TWO_PASS and off["copy_bytes"] == 0
+    assert off["workspace_bytes"] < p["workspace_bytes"]
+
+
+def test_mixed_fp32_storage(bm):
+    K, N = 1000, 2_000_000
+    p = bm.plan(K, N, d=2, model=bm.MODEL_LINEAR, u_dtype=bm.F32, binning=1, represent=1,
+                precision=bm.PREC_MIXED)
+    assert p["precision"] == bm.PREC_MIXED
+    assert p["stage32"] == _capi.STAGE32_SAMPLE_MAJOR
+    assert p["sweep"] == _capi.SWEEP_SAMPLE_MAJOR
+    assert p["copy_bytes"] == N * 1024 * 4  # FP32 storage: no FP64 copy anywhere
+    assert p["fp32_binned"] == 1 and p["hessian_fp16"] == 1
+
+
+def test_mixed_small_k_packed(bm):
+    for dt in (bm.F64, bm.F32):
+        p = bm.plan(100, 10_000, u_dtype=dt, precision=bm.PREC_MIXED)
+        assert p["stage32"] == _capi.STAGE32_PACKED and p["precision"] == bm.PREC_MIXED
+        assert p["sweep"] == (_capi.SWEEP_REGISTER if dt == bm.F64 else _capi.SWEEP_TWO_PASS)
+
+
+def test_model_energies(bm):
+    p = bm.plan(1600, 8_000_000, d=2, model=bm.MODEL_HARMONIC, stored_u=False, binning=1,
+                represent=1, precision=bm.PREC_MIXED)
+    assert p["sweep"] == _capi.SWEEP_MODEL and p["stage32"] == _capi.STAGE32_MODEL
+    assert p["copy_bytes"] == 0 and p["fp32_binned"] == 1
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(K=500, precision=1, finisher=1), "Newton finisher"),
+    (dict(K=1500, precision=1), "K <= 1024"),
+    (dict(K=500, precision=1, sample_major=0), "sample-major copy"),
+    (dict(K=50, precision=7), "unknown precision"),
+    (dict(K=50, tol=0.0), "tol must be > 0"),
+    (dict(K=50, binning=1, d=1, represent=2, u_dtype=1), "FP64 u_kn"),
+    (dict(K=50, binning=1, d=1, represent=1, model=0), "need a model"),
+    (dict(K=50, binning=1, d=0), "coordinates"),
+])
+def test_refused_combinations(bm, kw, needle):
+    K = kw.pop("K")
+    shape = {k: kw.pop(k) for k in ("d", "model", "u_dtype") if k in kw}
+    with pytest.raises(bm.BumbarError) as ei:
+        bm.plan(K, 10_000, **shape, **kw)
+    assert ei.value.code == bm.EINVAL
+    assert needle in str(ei.value)
+
+
+def test_fp64_beyond_copy_range_two_pass(bm):
+    p = bm.plan(1500, 100_000)
+    assert p["sweep"] == _capi.SWEEP_TWO_PASS and p["copy_bytes"] == 0
