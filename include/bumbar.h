@@ -108,7 +108,8 @@ typedef struct {
 } bumbar_check;
 
 typedef struct {
-  double tol;          /* finisher stops when max_k |applied delta f_k| < tol (kT). Default 1e-10 */
+  double tol;          /* finisher stops when a full Newton step has max_k |delta f_k| < tol
+                          (kT; SCI finisher: the SCI step). Default 1e-10                */
   int precision;       /* BUMBAR_PREC_*                                                  */
   int binning;         /* 1: Algorithm 1 on the coordinates xi, then the finisher;
                           0: plain unbinned SCI then the finisher                        */
@@ -165,6 +166,8 @@ typedef struct {
                                harmonic windows whose factors form a grid)              */
   int64_t batched_steps;    /* binned SCI steps run inside single-workgroup batches (levels
                                of at most 512 bins, the matrix held in registers)       */
+  int64_t damped_steps;     /* Newton steps accepted with alpha < 1 (the finisher stops
+                               only after a full step, or a fresh full step below tol)  */
 } bumbar_stats;
 
 /* ---- context ---------------------------------------------------------- */

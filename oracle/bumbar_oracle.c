@@ -361,8 +361,12 @@ static double norm2(int K, const double* g) {
  * the reduced system; a trial step f + alpha d (alpha = 1, 1/2, ... , 2^-10)
  * is accepted when it lowers the Euclidean norm of the gradient; if no trial
  * step is accepted, or the reduced Hessian is not positive definite, one
- * unbinned SCI step is taken instead. Stops when the applied update satisfies
- * max_k |delta f_k| < tol. Returns the number of steps in *steps_out.
+ * unbinned SCI step is taken instead. Stops on a full Newton step: an
+ * accepted alpha = 1 step with max_k |delta f_k| < tol, or a full step
+ * max_k |d_k| < tol that is not accepted (the gradient norm has reached its
+ * rounding floor). A damped or SCI step never ends the loop: its size does
+ * not bound the distance to the solution. Returns the number of steps in
+ * *steps_out.
  */
 int orc_newton_finish(int K, int64_t N, const double* u, const int64_t* Nk, double* f,
                       double tol, int max_steps, int* steps_out, int* sci_fallbacks_out) {
@@ -377,17 +381,22 @@ int orc_newton_finish(int K, int64_t N, const double* u, const int64_t* Nk, doub
     orc_objective_gradient(K, N, u, Nk, f, NULL, g);
     double gn = norm2(K, g);
     orc_hessian(K, N, u, Nk, f, H);
-    int accepted = 0;
-    double maxstep = 0.0;
+    int accepted = 0, full = 0, have_dir = 0;
+    double maxstep = 0.0, full_step = INFINITY;
     if (orc_newton_direction(K, Nk, H, g, d) == 0) {
+      have_dir = 1;
+      full_step = 0.0;
+      for (int k = 0; k < K; ++k)
+        if (fabs(d[k]) > full_step || d[k] != d[k]) full_step = fabs(d[k]);
       double alpha = 1.0;
       for (int t = 0; t <= 10; ++t, alpha *= 0.5) {
         for (int k = 0; k < K; ++k) ft[k] = f[k] + alpha * d[k];
         fill_unsampled_and_gauge(K, N, u, Nk, ft);
         orc_objective_gradient(K, N, u, Nk, ft, NULL, g2);
-        if (norm2(K, g2) < gn) { accepted = 1; break; }
+        if (norm2(K, g2) < gn) { accepted = 1; full = t == 0; break; }
       }
     }
+    if (!accepted && have_dir && full_step < tol) { rc = ORC_OK; break; }
     if (!accepted) {
       orc_sci_step(K, N, u, NULL, Nk, f, ft, NULL);
       fill_unsampled_and_gauge(K, N, u, Nk, ft);
@@ -399,7 +408,7 @@ int orc_newton_finish(int K, int64_t N, const double* u, const int64_t* Nk, doub
       f[k] = ft[k];
     }
     ++steps;
-    if (maxstep < tol) { rc = ORC_OK; break; }
+    if (full && maxstep < tol) { rc = ORC_OK; break; }
   }
   if (steps_out) *steps_out = steps;
   if (sci_fallbacks_out) *sci_fallbacks_out = fallbacks;

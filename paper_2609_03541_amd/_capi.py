@@ -68,7 +68,8 @@ class Stats(C.Structure):
                 ("time_final_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
                 ("checks_capacity", C.c_int), ("graph_batches", C.c_int64),
-                ("grid_sweeps", C.c_int64), ("batched_steps", C.c_int64)]
+                ("grid_sweeps", C.c_int64), ("batched_steps", C.c_int64),
+                ("damped_steps", C.c_int64)]
 
 
 class Plan(C.Structure):

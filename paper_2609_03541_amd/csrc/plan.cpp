@@ -102,9 +102,12 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
       p->bb_ubar = p->rep != BUMBAR_REPRESENT_CENTRE || sweep_fast_supported(K);
       p->bb_cen = p->rep != BUMBAR_REPRESENT_MEAN && !sweep_fast_supported(K);
     }
-    // with K > 256 a binned step is a model sweep over K x P: the FP32 stage
-    // first runs it in FP32 on FP32 centres
-    p->bb_cen_f32 = p->mixed && K > 256 && p->bb_cen;
+    // on the fly with K > 256 a binned step is a model sweep over K x P: the
+    // FP32 stage first runs it in FP32 on FP32 centres. Not for stored u:
+    // there the binned stage only provides the Newton start, and on ladders
+    // with energies of ~1e3 kT the FP32 relative steps never pass eps (the
+    // c2 ladder spent 4000 FP32 steps, ~0.4 s, before the FP64 rerun).
+    p->bb_cen_f32 = otf && p->mixed && K > 256 && p->bb_cen;
     p->fp32_binned = p->bb_cen_f32;
   }
   p->x_packed = p->stage32 == BUMBAR_STAGE32_PACKED;

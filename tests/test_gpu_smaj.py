@@ -135,3 +135,18 @@ def test_solve_copy_off_equals_copy_on(bm):
     fa, _ = bm.solve(dev(p["u"]), p["Nk"], tol=1e-12)
     fb, _ = bm.solve(dev(p["u"]), p["Nk"], tol=1e-12, sample_major=0)
     assert np.max(np.abs(fa.cpu().numpy() - fb.cpu().numpy())) < 1e-10
+
+
+def test_newton_from_poor_start_weak_overlap(bm):
+    # A weak-overlap ladder with K > 256 (sample-major sweeps, FP16-core
+    # Newton Hessian) from a poor start (one SCI step from f = 0): Newton
+    # needs damped steps there, and the finisher may stop only on a full
+    # step, so the result must still be the oracle's fixed point.
+    p = synth.ladder_2d(K=300, Nk=40, seed=9, delta=1.2)  # neighbour overlap 2 Phi(-0.6) = 0.55
+    f_ref, info_ref = oracle.solve_mbar(p["u"], p["Nk"])
+    f, info = bm.solve(dev(p["u"]), p["Nk"], tol=1e-11, sci_switch=1e9)
+    say("damped", info["damped_steps"], "fallbacks", info["sci_fallbacks"], "newton",
+        info["finisher_steps"], "oracle residual", info_ref["residual"])
+    assert info["status"] == 0
+    assert info["damped_steps"] + info["sci_fallbacks"] >= 1
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9

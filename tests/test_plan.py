@@ -43,7 +43,7 @@ def test_mixed_fp32_storage(bm):
     assert p["stage32"] == _capi.STAGE32_SAMPLE_MAJOR
     assert p["sweep"] == _capi.SWEEP_SAMPLE_MAJOR
     assert p["copy_bytes"] == N * 1024 * 4  # FP32 storage: no FP64 copy anywhere
-    assert p["fp32_binned"] == 1 and p["hessian_fp16"] == 1
+    assert p["fp32_binned"] == 0 and p["hessian_fp16"] == 1
 
 
 def test_mixed_small_k_packed(bm):
