@@ -1,8 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the BU-MBAR hot path on one MI355X.
 
-One step = one full solve (binning, Algorithm 1 binned stage, unbinned Newton
-finisher, outputs) of the umbrella-sampling workload: 1-D double well
+Default (--workload all): every configuration of the metric in one run, the
+K = 1000 ladder (c2) as the headline. One step = one full FP64 solve of the
+ladder u_kn = beta_k E_n + lambda_k V_n (K = 1000, N = 2e6, u 16 GB stored,
+BU-MBAR on (E, V) bins, Newton finisher, tolerance 1e-7 kT) with u resident
+in HBM; value = K N / the average duration of its unbinned sweep kernel (the
+sample-major single pass, HIP events on the library's stream over the timed
+solves); roofline = that kernel against 8 TB/s (8 bytes per element). The
+same line carries, under "configs": c2 in mixed precision from FP32 storage,
+c1 (below), c4 (the Muller-Brown grid, energies in-kernel; its FP16-core
+Hessian against the FP16 peak with the algorithmic K (K + 1) N flops), c4
+with N_k = 500, and c3 (the 512-problem stream served at 0.8 x its measured
+saturation rate, p50/p99, against the sequential FP64 solver); every result
+with its error against the oracle's certified solution in tests/golden.
+
+--workload double_well: one step = one full solve (binning, Algorithm 1
+binned stage, unbinned Newton finisher, outputs) of the umbrella-sampling
+workload: 1-D double well
 U(x) = (x^2 - 1)^2, K = 100 harmonic windows (kappa = 50) on [-1.5, 1.5],
 N_k = 10^4 Metropolis samples each (N = 10^6), u_kn 100 x 10^6 FP64, adaptive
 binning, tolerance 1e-7 kT on the final step. Inputs are resident in HBM
@@ -25,8 +40,8 @@ arrival to result; the largest |f - f_FP64| over all problems in kT.
 
 With --workload ladder: the temperature/alchemical ladder, K = 1000 states,
 N_k = 2000 (N = 2e6), u_kn = beta_k E_n + lambda_k V_n stored as a 16 GB FP64
-matrix (built on the device from E, V); plain MBAR (no binning) solved in
-FP64 and in mixed precision (FP32 packed sweeps, FP64 refinement).
+matrix (built on the device from E, V); BU-MBAR solved in FP64 and in mixed
+precision from an FP32 copy of u (FP32 sweeps, FP64 refinement).
 
 With --workload mb2d: the 2-D umbrella grid on the Muller-Brown surface,
 K = 40 x 40 = 1600 windows (kappa = 20), N_k = 5000 (N = 8e6), FP32 (x, y)
@@ -50,6 +65,7 @@ state (N0 = 1e4, 3e6, 9e8: 1e4 per state at M = 300 in all three), each
 solved by BU-MBAR and plain Newton, and by plain SCI up to M = 100.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
+       python bench.py --workload double_well [--copy-calibration]
        python bench.py --workload stream [--n-problems 512] [--rate 100]
        python bench.py --workload ladder|mb2d|tladder|scaling [--steps 2]
 """
@@ -83,8 +99,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload",
-                    choices=["double_well", "stream", "ladder", "mb2d", "tladder", "scaling"],
-                    default="double_well")
+                    choices=["all", "double_well", "stream", "ladder", "mb2d", "tladder",
+                             "scaling"],
+                    default="all")
     ap.add_argument("--n-problems", type=int, default=512)
     ap.add_argument("--rate", type=float, default=100.0, help="stream arrivals per second")
     ap.add_argument("--max-active", type=int, default=8)
@@ -92,13 +109,15 @@ def main():
     ap.add_argument("--skip-sequential", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--configs", default="c2,c1,c4,c3",
+                    help="default workload: the configurations to run (c2 always runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
               "of the sweep is described in the design notes and not implemented.", file=sys.stderr)
         sys.exit(2)
     stream = None
-    if args.workload == "stream":
+    if args.workload == "stream" or (args.workload == "all" and "c3" in args.configs):
         # host-side generation runs in worker processes before this process touches the GPU
         stream = generate_stream(args)
 
@@ -110,6 +129,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs the GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "all":
+        return run_all(args, bm, synth, stream)
     if args.workload == "stream":
         return run_stream(args, bm, stream)
     if args.workload == "ladder":
@@ -141,13 +162,7 @@ def main():
         log(f"warmup {i}: phase1={info['phase1_iters']} phase2={info['phase2_iters']} "
             f"checks={info['n_checks']} newton={info['finisher_steps']}")
     if args.copy_calibration:
-        # a plain copy of known size: 1 GiB read + 1 GiB written
-        xc = torch.empty(2**27, dtype=torch.float64, device=dev)
-        yc = torch.empty_like(xc)
-        yc.copy_(xc)
-        torch.cuda.synchronize()
-        del xc, yc
-        log("copy calibration: 1 GiB device copy done")
+        _copy_calibration(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sweep_ms, launches = 0.0, 0
@@ -230,6 +245,304 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+METRIC = "sweep K*N elem/s + time-to-solve at 1e-6 kT; batched solves/s, p50/p99"
+
+
+def _golden(name):
+    """Golden f of a workload: the oracle's certified solution (tests/golden)."""
+    try:
+        with open(os.path.join(GOLDEN, name + ".json")) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return None
+
+
+def _err(f, gold):
+    if gold is None:
+        return None
+    f = f.detach().cpu().numpy() if hasattr(f, "detach") else np.asarray(f)
+    return float(np.max(np.abs(f - np.asarray(gold["f"]))))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _side(args, steps=3):
+    """Steps and warm-up for the non-headline configurations (bounded)."""
+    a = argparse.Namespace(**vars(args))
+    a.steps = max(1, min(args.steps, steps))
+    a.warmup = 1
+    return a
+
+
+def _ladder_u(torch, p):
+    """u_kn = beta_k E_n + lambda_k V_n on the device (the generator's arithmetic)."""
+    E = torch.tensor(p["xi"][:, 0], device="cuda")
+    V = torch.tensor(p["xi"][:, 1], device="cuda")
+    beta = torch.tensor(p["beta"], device="cuda")
+    lam = torch.tensor(p["lam"], device="cuda")
+    return beta[:, None] * E[None, :] + lam[:, None] * V[None, :]
+
+
+def run_all(args, bm, synth, stream):
+    """Default run: every configuration of the metric on one GPU, c2 as the headline."""
+    import torch
+
+    import oracle
+    ctx = bm.context()
+    side = _side(args)
+    cfg = {}
+    t_all = time.time()
+
+    # ---- c2: K = 1000 ladder, N = 2e6, u stored FP64 (16 GB); the headline ----
+    p = synth.ladder_2d(K=1000, Nk=2000, seed=2, materialize=False)
+    K, N = p["K"], p["N"]
+    xi = torch.tensor(p["xi"], device="cuda")
+    coef = torch.tensor(p["coef"], device="cuda")
+    Nk = torch.tensor(p["Nk"], device="cuda")
+    u = _ladder_u(torch, p)
+    torch.cuda.synchronize()
+    g2 = _golden("c2_ladder_K1000_N2e6")
+
+    def c2(uu, prec):
+        return lambda prof: bm.solve(uu, Nk, xi=xi, model=bm.MODEL_LINEAR, coef=coef,
+                                     tol=args.tol, precision=prec, profile=int(prof), ctx=ctx)
+
+    f64, inf64, ms64 = _timed_solves(bm, args, "c2 f64", c2(u, bm.PREC_FP64))
+    sw64, nsw = _avg_sweep_s(inf64)
+    elems = K * N
+    value = elems / sw64
+    achieved = 8.0 * elems / sw64 / 1e9
+    cfg["c2_f64"] = dict(time_to_solve_s=ms64 / 1e3, sweep_us=sw64 * 1e6, sweep_launches=nsw,
+                         error_vs_oracle_kT=_err(f64, g2), status=inf64[-1]["status"],
+                         stages_ms=dict(binning=inf64[-1]["time_binning_ms"],
+                                        binned=inf64[-1]["time_binned_ms"],
+                                        finisher=inf64[-1]["time_final_ms"]))
+    # FP32 storage (8 GB, no FP64 copy anywhere): mixed precision, and FP64
+    # arithmetic on the same storage (the oracle's problem is the FP64 one,
+    # so the error against it includes the rounding of u to FP32)
+    u32 = u.float()
+    del u
+    torch.cuda.empty_cache()
+    fm, infm, msm = _timed_solves(bm, side, "c2 mixed fp32 storage", c2(u32, bm.PREC_MIXED))
+    f32s, inf32s, ms32s = _timed_solves(bm, side, "c2 f64 on fp32 storage",
+                                        c2(u32, bm.PREC_FP64))
+    swm, _ = _avg_sweep_s(infm)
+    cfg["c2_mixed_fp32_storage"] = dict(
+        time_to_solve_s=msm / 1e3, sweep_us=swm * 1e6, mixed_steps=infm[-1]["mixed_steps"],
+        error_vs_oracle_kT=_err(fm, g2),
+        error_vs_fp64_on_same_storage_kT=float((fm - f32s).abs().max()),
+        storage_rounding_error_kT=_err(f32s, g2), status=infm[-1]["status"],
+        speedup_vs_f64=ms64 / msm)
+    del u32
+    torch.cuda.empty_cache()
+    log(f"c2 done ({time.time() - t_all:.0f} s)")
+
+    want = set(args.configs.split(","))
+    # ---- c1: K = 100 double-well umbrella windows, N = 1e6, FP64 ----
+    if "c1" in want:
+        cfg["c1_f64"] = _c1(bm, synth, side, ctx)
+        log(f"c1 done ({time.time() - t_all:.0f} s)")
+    # ---- c4: 40 x 40 Muller-Brown umbrella grid, N = 8e6, energies in-kernel ----
+    if "c4" in want:
+        cfg["c4_mixed"] = _c4(bm, synth, side, ctx, Nk_per=5000)
+        cfg["c4r_mixed_Nk500"] = _c4(bm, synth, side, ctx, Nk_per=500,
+                                     gold=_golden("c4r_mullerbrown_K1600_N8e5"), hessian=False)
+        log(f"c4 done ({time.time() - t_all:.0f} s)")
+    # ---- c3: 512-problem stream at 0.8 x the measured saturation rate ----
+    if "c3" in want:
+        cfg["c3_serving"] = _c3(bm, side, stream)
+        log(f"c3 done ({time.time() - t_all:.0f} s)")
+    # ---- the FP64 oracle on this host: per-sweep rate on a bounded sample ----
+    cpu = None
+    if not args.no_cpu:
+        cpu = _cpu_baseline(oracle, synth, args)
+
+    out = _base_line(args, value, "elem/s", ms64, "f64", {
+        "workload": "temperature/alchemical ladder u_kn = beta_k E_n + lambda_k V_n, K=1000, "
+                    "N=2e6 (N_k=2000), u_kn 1000x2e6 FP64 stored (16 GB), BU-MBAR on (E, V) "
+                    "bins + Newton; value = its unbinned sweep (sample-major copy)",
+        "K": K, "N": N, "tol_kT": args.tol})
+    out.update({
+        "time_to_solve_s": ms64 / 1e3,
+        "error_vs_oracle_kT": cfg["c2_f64"]["error_vs_oracle_kT"],
+        "sweep_kernel_us": sw64 * 1e6,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _counter_traffic("sweep_smaj_ladder_K1000_N2e6")},
+        "configs": cfg,
+        "cpu_baseline": cpu,
+        "bench_wall_s": time.time() - t_all,
+    })
+    print(json.dumps(out), flush=True)
+
+
+def _c1(bm, synth, args, ctx):
+    import torch
+    p1 = synth.double_well(K=100, Nk=10000, seed=1)
+    u1 = torch.tensor(p1["u"], device="cuda")
+    Nk1 = torch.tensor(p1["Nk"], device="cuda")
+    xi1 = torch.tensor(p1["xi"], device="cuda")
+    coef1 = torch.tensor(p1["coef"], device="cuda")
+    f1, inf1, ms1 = _timed_solves(
+        bm, args, "c1 f64",
+        lambda prof: bm.solve(u1, Nk1, xi=xi1, model=bm.MODEL_HARMONIC, coef=coef1, tol=args.tol,
+                              profile=int(prof), ctx=ctx))
+    sw1, _ = _avg_sweep_s(inf1)
+    a1 = 8.0 * p1["K"] * p1["N"] / sw1 / 1e9
+    res = dict(time_to_solve_s=ms1 / 1e3, sweep_us=sw1 * 1e6,
+               sweep_elem_s=p1["K"] * p1["N"] / sw1, roofline_frac=a1 / HBM_PEAK_GBS,
+               traffic=_counter_traffic("sweep_fast_double_well_K100_N1e6"),
+               error_vs_oracle_kT=_err(f1, _golden("c1_double_well_K100_N1e6")),
+               status=inf1[-1]["status"])
+    del u1
+    torch.cuda.empty_cache()
+    return res
+
+
+def _c4(bm, synth, args, ctx, Nk_per, gold=None, hessian=True):
+    import torch
+    t = time.time()
+    p = synth.muller_brown_grid(G=40, Nk=Nk_per, seed=4)
+    K, N = p["K"], p["N"]
+    xi = torch.tensor(p["xi"], device="cuda")
+    coef = torch.tensor(p["coef"], device="cuda")
+    Nk = torch.tensor(p["Nk"], device="cuda")
+    log(f"muller-brown grid N_k={Nk_per} generated in {time.time() - t:.1f}s")
+    f, infos, ms = _timed_solves(
+        bm, args, f"c4 N_k={Nk_per} mixed",
+        lambda prof: bm.solve(None, Nk, xi=xi, model=bm.MODEL_HARMONIC, coef=coef, tol=args.tol,
+                              precision=bm.PREC_MIXED, profile=int(prof), ctx=ctx))
+    fn, lD, S, st = bm.sweep_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, precision=bm.PREC_FP64,
+                                   ctx=ctx)
+    res = dict(time_to_solve_s=ms / 1e3, K=K, N=N, status=infos[-1]["status"],
+               fp64_sci_residual_kT=st["max_df"], grad_norm=st["grad_norm"],
+               grid_sweeps=infos[-1]["grid_sweeps"],
+               stages_ms=dict(binning=infos[-1]["time_binning_ms"],
+                              binned=infos[-1]["time_binned_ms"],
+                              finisher=infos[-1]["time_final_ms"]))
+    if gold is not None:
+        res["error_vs_oracle_kT"] = _err(f, gold)
+        f64, _, ms64 = _timed_solves(
+            bm, args, f"c4 N_k={Nk_per} f64",
+            lambda prof: bm.solve(None, Nk, xi=xi, model=bm.MODEL_HARMONIC, coef=coef,
+                                  tol=args.tol, profile=int(prof), ctx=ctx))
+        res["f64_time_to_solve_s"] = ms64 / 1e3
+        res["f64_error_vs_oracle_kT"] = _err(f64, gold)
+    if hessian:
+        # the FP16-core Hessian of the mixed stage, timed on the context's stream;
+        # algorithmic flops K (K + 1) N (the symmetric product, no padding)
+        bm.hessian_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, lD, S, precision=bm.PREC_MIXED,
+                         ctx=ctx)
+        h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        h0.record(ctx.stream)
+        for _ in range(2):
+            bm.hessian_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, lD, S,
+                             precision=bm.PREC_MIXED, ctx=ctx)
+        h1.record(ctx.stream)
+        torch.cuda.synchronize()
+        th = h0.elapsed_time(h1) / 2e3
+        flops = K * (K + 1) * N
+        res["hessian"] = dict(seconds=th, algorithmic_flops=flops, tflop_s=flops / th / 1e12,
+                              peak_tflop_s=2500.0, frac=flops / th / 1e12 / 2500.0,
+                              dtype="fp16 inputs, fp32 accumulation")
+    del xi, coef, Nk
+    torch.cuda.empty_cache()
+    return res
+
+
+def _c3(bm, args, stream):
+    _, probs = stream
+    budget = int(args.hbm_budget_gb * 2**30)
+    mixed = dict(tol=args.tol, precision=bm.PREC_MIXED)
+    n = len(probs)
+    _serve(bm, probs[:2], [0.0, 0.0], 2, budget, mixed)  # warm-up
+    # saturation: the whole stream at t = 0 (closed loop)
+    _, wall_sat, _ = _serve(bm, probs, [0.0] * n, args.max_active, budget, mixed)
+    sat = n / wall_sat
+    rate = 0.8 * sat
+    g = np.random.Generator(np.random.PCG64(33))
+    arrivals = list(np.cumsum(g.exponential(1.0 / rate, size=n)))
+    log(f"c3 saturation {sat:.1f} solves/s; served run at {rate:.1f}/s")
+    res, wall, cnt = _serve(bm, probs, arrivals, args.max_active, budget, mixed)
+    lat = np.array([info["latency_ms"] for _, info in res])
+    log("c3 sequential FP64 run")
+    res64, wall64, _ = _serve(bm, probs, [0.0] * n, 1, budget,
+                              dict(tol=args.tol, precision=bm.PREC_FP64))
+    lat64 = np.array([info["latency_ms"] for _, info in res64])
+    gold = _golden("c3_stream_subset64")
+    err_gold = None
+    if gold is not None:
+        err_gold = max(float(np.max(np.abs(res[it["index"]][0] - np.asarray(it["f"]))))
+                       for it in gold["problems"] if it["index"] < n)
+    return dict(
+        solves_per_s=n / wall, p50_ms=float(np.percentile(lat, 50)),
+        p99_ms=float(np.percentile(lat, 99)), rate_per_s=rate, saturation_solves_per_s=sat,
+        n_problems=n, max_active=args.max_active, precision="mixed",
+        failed=int(sum(1 for _, i in res if i["status"] not in (0, -4))),
+        peak_active=cnt["peak_active"], peak_arena_gb=cnt["peak_bytes"] / 2**30,
+        sequential_fp64=dict(solves_per_s=n / wall64, p50_ms=float(np.percentile(lat64, 50)),
+                             p99_ms=float(np.percentile(lat64, 99))),
+        max_abs_diff_vs_sequential_fp64_kT=max(float(np.max(np.abs(a[0] - b[0])))
+                                               for a, b in zip(res, res64)),
+        error_vs_oracle_subset64_kT=err_gold)
+
+
+def _cpu_baseline(oracle, synth, args):
+    """The FP64 oracle on this host: sweep rate on a bounded slice of c2, c1 in full."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p = synth.ladder_2d(K=1000, Nk=100, seed=2, materialize=False)  # the c2 ladder, 1e5 samples
+    E, V = p["xi"][:, 0], p["xi"][:, 1]
+    u = np.empty((p["K"], p["N"]))
+    for k in range(p["K"]):
+        u[k] = p["beta"][k] * E + p["lam"][k] * V
+    f = np.zeros(p["K"])
+    reps, tc = 0, time.perf_counter()
+    while True:
+        oracle.sci_step(u, p["Nk"], f)
+        reps += 1
+        if time.perf_counter() - tc > args.cpu_seconds or reps >= 20:
+            break
+    per = (time.perf_counter() - tc) / reps
+    rate = u.size / per
+    tts = {}
+    for name, key in (("c1", "c1_double_well_K100_N1e6"), ("c2", "c2_ladder_K1000_N2e6"),
+                      ("c4r", "c4r_mullerbrown_K1600_N8e5")):
+        gd = _golden(key)
+        if gd is not None:
+            c = gd["certificate"]
+            tts[name] = {"seconds": c.get("oracle_seconds"), "threads": gd.get("threads"),
+                         "how": "measured once, Algorithm 1 + Newton polish to the "
+                                "certificate, on the host that wrote tests/golden"}
+    return {"value": rate, "unit": "elem/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} FP64 oracle unbinned SCI sweeps over a 1000 x 1e5 slice of the "
+                      f"c2 ladder ({per:.2f} s each; the full 1000 x 2e6 sweep would take "
+                      f"{per * 20:.1f} s)",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "per_sweep_s_full_c2_extrapolated": per * 20,
+            "time_to_solve": tts}
+
+
+def _copy_calibration(torch):
+    """A plain device copy of known size (1 GiB read + 1 GiB written): the
+    reference kernel that scales the HBM byte counters."""
+    xc = torch.empty(2**27, dtype=torch.float64, device="cuda")
+    yc = torch.empty_like(xc)
+    yc.copy_(xc)
+    torch.cuda.synchronize()
+    del xc, yc
+    log("copy calibration: 1 GiB device copy done")
+
+
 def _counter_traffic(name):
     """HBM bytes per launch of a kernel from its committed counter summary.
 
@@ -297,18 +610,21 @@ def run_ladder(args, bm, synth):
     K, N = p["K"], p["N"]
     xi = torch.tensor(p["xi"], device="cuda")
     coef = torch.tensor(p["coef"], device="cuda")
-    u = bm.model_energies(xi, coef, bm.MODEL_LINEAR, K)  # stored K x N FP64 (16 GB)
+    u = _ladder_u(torch, p)  # stored K x N FP64 (16 GB)
+    u32 = u.float()          # FP32 storage for the mixed-precision solve (8 GB)
     Nk = torch.tensor(p["Nk"], device="cuda")
     torch.cuda.synchronize()
     log(f"ladder generated in {time.time() - t:.1f}s: K={K} N={N}, u {u.numel() * 8 / 1e9:.1f} GB")
+    if args.copy_calibration:
+        _copy_calibration(torch)
     ctx = bm.context()
     res = {}
-    for name, prec in (("f64", bm.PREC_FP64), ("mixed", bm.PREC_MIXED)):
+    for name, prec, uu in (("f64", bm.PREC_FP64, u), ("mixed", bm.PREC_MIXED, u32)):
         f, infos, ms = _timed_solves(
             bm, args, name,
-            lambda prof, prec=prec: bm.solve(u, Nk, xi=xi, model=bm.MODEL_LINEAR, coef=coef,
-                                             tol=args.tol, precision=prec, profile=int(prof),
-                                             ctx=ctx))
+            lambda prof, prec=prec, uu=uu: bm.solve(uu, Nk, xi=xi, model=bm.MODEL_LINEAR,
+                                                    coef=coef, tol=args.tol, precision=prec,
+                                                    profile=int(prof), ctx=ctx))
         sw, n = _avg_sweep_s(infos)
         res[name] = dict(f=f.cpu().numpy(), ms=ms, sweep_s=sw, launches=n, info=infos[-1])
     diff = float(np.max(np.abs(res["mixed"]["f"] - res["f64"]["f"])))
@@ -326,7 +642,8 @@ def run_ladder(args, bm, synth):
     achieved = 8.0 * elems / f64_sweep_s / 1e9
     out = _base_line(args, elems / f64_sweep_s, "elem/s", res["f64"]["ms"], "f64", {
         "workload": "ladder u_kn = beta_k E_n + lambda_k V_n, K=1000, N=2e6 (N_k=2000), "
-                    "u_kn 1000x2e6 FP64 stored, BU-MBAR on (E, V) bins + Newton",
+                    "u_kn 1000x2e6 FP64 stored (mixed: FP32 storage), BU-MBAR on (E, V) bins + "
+                    "Newton",
         "K": K, "N": N, "tol_kT": args.tol})
     out.update({
         "time_to_solve_s": {"f64": res["f64"]["ms"] / 1e3, "mixed": res["mixed"]["ms"] / 1e3},
@@ -548,16 +865,20 @@ def _serve(bm, probs, arrivals, max_active, budget, opts):
 
 
 def generate_stream(args):
+    """Problems of the seeded 512-problem stream (the specs do not depend on the
+    arrival rate) and Poisson arrival times at args.rate from a separate seed."""
     from concurrent.futures import ProcessPoolExecutor
 
     import synth
-    stream = synth.serving_stream(n_problems=args.n_problems, seed=3, rate=args.rate)
+    stream = synth.serving_stream(n_problems=args.n_problems, seed=3)
     t = time.time()
     workers = max(1, min(16, os.cpu_count() or 1))
     with ProcessPoolExecutor(workers) as ex:
         probs = list(ex.map(_gen_problem, [s for _, s in stream], chunksize=4))
     log(f"stream generated in {time.time() - t:.1f}s with {workers} processes")
-    return [t for t, _ in stream], probs
+    g = np.random.Generator(np.random.PCG64(33))
+    arrivals = list(np.cumsum(g.exponential(1.0 / args.rate, size=len(probs))))
+    return arrivals, probs
 
 
 def run_stream(args, bm, stream):

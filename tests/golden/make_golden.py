@@ -14,7 +14,7 @@ with no input from the GPU library:
   3. certification: the full Newton step below 1e-13 kT and the fixed-point
      residual max |SCI(f) - f| below 1e-12 kT, both recorded.
 
-Usage: python tests/golden/make_golden.py {c2,tladder,c4r,c3sub} ...
+Usage: python tests/golden/make_golden.py {c1,c2,tladder,c4r,c3sub} ...
 Inputs are the seeded generators of synth (the same recipes the GPU tests and
 the benchmark use). Output: tests/golden/<name>.json.
 """
@@ -66,6 +66,13 @@ def certify(u, Nk, f, chunk=100_000, max_steps=40):
         if d is None:
             raise RuntimeError("reduced Hessian not positive definite")
         full_step = float(np.max(np.abs(d)))
+        if full_step < 1e-12:
+            # rounding floor of the gradient: the full step itself bounds the
+            # remaining distance; take it and stop
+            f = f + d
+            f -= f[0]
+            say(f"  newton {steps}: |g| {gn:.3e} full step {full_step:.3e} (floor)")
+            break
         alpha, accepted = 1.0, False
         for _ in range(31):
             ft = f + alpha * d
@@ -146,6 +153,14 @@ def run_c4r():
     write("c4r_mullerbrown_K1600_N8e5", "synth.muller_brown_grid(G=40, Nk=500, seed=4)", f, cert)
 
 
+def run_c1():
+    # double-well umbrella sampling, K = 100 windows, N_k = 1e4 (N = 1e6), seed 1
+    p = synth.double_well(K=100, Nk=10000, seed=1)
+    say("c1 double well K=100 N=1e6")
+    f, cert = solve_golden(p["u"], p["Nk"], p["xi"], p["model_type"], p["coef"], chunk=200_000)
+    write("c1_double_well_K100_N1e6", "synth.double_well(K=100, Nk=10000, seed=1)", f, cert)
+
+
 def run_c3sub():
     # every 8th problem of the 512-problem serving stream (seed 3): 64 problems
     stream = synth.serving_stream(n_problems=512, seed=3)
@@ -171,6 +186,6 @@ def run_c3sub():
 
 if __name__ == "__main__":
     oracle.build()
-    jobs = dict(c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub)
+    jobs = dict(c1=run_c1, c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub)
     for name in sys.argv[1:] or list(jobs):
         jobs[name]()
