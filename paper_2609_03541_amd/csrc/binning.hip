@@ -489,9 +489,96 @@ static unsigned key_bits(int d, uint64_t m) {
   return b;
 }
 
+// ---- 2-D g(m) as an occupancy histogram ------------------------------------
+// The cells of width m form an ncx x ncx grid (ncx = floor((2^32 - 1) / m) +
+// 1, row-major ids as cell2). g(m) is the number of occupied cells: each
+// sample sets its cell's bit in a bitmap of the grid with an integer atomic
+// OR, then the set bits are counted. Small grids (the coarse widths at the
+// start of the bisection, where many samples share few cells) are marked in
+// a bitmap private to each workgroup in LDS and merged into the global one
+// word by word; larger grids are marked in the global bitmap directly (few
+// samples per cell, little contention). Integer operations only, so the count
+// is exact and does not depend on the order of the atomics.
+constexpr int kLdsWords = 8192;  // 32 KB of LDS: grids of up to 262144 cells
+
+__global__ void __launch_bounds__(kBT) zero_words_kernel(uint32_t* w, int64_t nw) {
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBT)
+    w[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kBT)
+    mark_cells_kernel(const uint32_t* __restrict__ q, int64_t N, uint64_t m, uint64_t magic,
+                      uint64_t ncx, int64_t nw, uint32_t* __restrict__ words) {
+  __shared__ uint32_t lw[kLdsWords];
+  const bool private_map = nw <= kLdsWords;  // uniform over the grid
+  if (private_map) {
+    for (int i = threadIdx.x; i < nw; i += kBT) lw[i] = 0u;
+    __syncthreads();
+  }
+  for (int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x; n < N; n += (int64_t)gridDim.x * kBT) {
+    const uint64_t c = (uint64_t)div_by_magic(q[2 * n], m, magic) +
+                       (uint64_t)div_by_magic(q[2 * n + 1], m, magic) * ncx;
+    const uint32_t bit = 1u << (uint32_t)(c & 31u);
+    if (private_map)
+      atomicOr(&lw[c >> 5], bit);
+    else
+      atomicOr(&words[c >> 5], bit);
+  }
+  if (private_map) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nw; i += kBT)
+      if (lw[i]) atomicOr(&words[i], lw[i]);
+  }
+}
+
+// counts[0] += number of set bits (per-block sums, one integer atomic each)
+__global__ void __launch_bounds__(kBT)
+    popcount_words_kernel(const uint32_t* __restrict__ w, int64_t nw,
+                          unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long sh[kBT];
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBT)
+    c += (unsigned long long)__builtin_popcount(w[i]);
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int s2 = kBT / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sh[0]) atomicAdd(total, sh[0]);
+}
+
+// Bits of the occupancy bitmap of width m (0 if its grid is beyond 2^62 cells).
+static uint64_t grid_cells_2d(uint64_t m) {
+  const uint64_t ncx = 4294967295ull / m + 1ull;
+  if (ncx > (1ull << 31)) return 0;
+  return ncx * ncx;
+}
+
+static bool count_2d_uses_bitmap(int64_t N, uint64_t m) {
+  const uint64_t g = grid_cells_2d(m);
+  // the bitmap lives in the N x 8 bytes of the key buffer
+  return g != 0 && g <= (uint64_t)N * 64ull;
+}
+
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts) {
+  if (count_2d_uses_bitmap(N, m)) {
+    const uint64_t ncx = 4294967295ull / m + 1ull;
+    const int64_t nw = (int64_t)((grid_cells_2d(m) + 31) / 32);
+    uint32_t* words = reinterpret_cast<uint32_t*>(keys);
+    const unsigned zb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nw + kBT - 1) / kBT));
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(kBT), 0, s, words, nw);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<unsigned long long*>(counts), 1);
+    const unsigned mb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (N + kBT - 1) / kBT));
+    hipLaunchKernelGGL(mark_cells_kernel, dim3(mb), dim3(kBT), 0, s, q, N, m, magic_of(m), ncx,
+                       nw, words);
+    hipLaunchKernelGGL(popcount_words_kernel, dim3(zb), dim3(kBT), 0, s, (const uint32_t*)words,
+                       nw, reinterpret_cast<unsigned long long*>(counts));
+    return hipGetLastError();
+  }
   const unsigned bits = key_bits(2, m);
   const int nb = red_blocks(N);
   size_t bytes = tmp_bytes;

@@ -160,3 +160,26 @@ def test_failed_request_reports_status(bm):
         assert np.max(np.abs(f2 - f_ref)) < 1e-9
     finally:
         srv.close()
+
+
+def test_mixed_precision_served_equals_solo(bm):
+    # mixed precision in the mix: each served result is bitwise the result of
+    # the same mixed solve alone, and within 1e-6 kT of the oracle
+    specs = synth.serving_stream(n_problems=8, seed=21, K_range=(40, 120), Nk_range=(200, 600))
+    probs = [synth.materialize_problem(s) for _, s in specs]
+    srv = bm.Server(hbm_budget_bytes=1 << 30, max_active=4)
+    try:
+        ts = [srv.submit(p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-10,
+                         precision=bm.PREC_MIXED) for p in probs]
+        for i, (p, t) in enumerate(zip(probs, ts)):
+            f, info = srv.result(t)
+            say(f"mixed served problem {i}: K={p['K']} N={p['N']} status={info['status']}")
+            assert info["status"] == 0
+            f_solo, info_solo = bm.solve(None, p["Nk"], xi=p["xi"], model=p["model_type"],
+                                         coef=p["coef"], tol=1e-10, precision=bm.PREC_MIXED)
+            assert np.array_equal(f, f_solo.cpu().numpy()), i
+            f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+            assert np.max(np.abs(f - f_ref)) < 1e-6, i
+        assert srv.counters()["peak_active"] >= 2
+    finally:
+        srv.close()
