@@ -140,6 +140,10 @@ typedef struct {
   int u_dtype;         /* element type of the u_kn bumbar_solve will get (BUMBAR_F64,
                           default, or BUMBAR_F32): the workspace queries size the copy
                           with it (an FP32 copy with a query for FP64 fits)              */
+  int xi_dtype;        /* element type of the xi bumbar_solve will get (BUMBAR_F64,
+                          default, or BUMBAR_F32): FP32 coordinates are widened (exactly)
+                          into N d doubles of the workspace, which the queries then
+                          include; a workspace sized for FP64 is too small for FP32 xi  */
 } bumbar_options;
 
 typedef struct {
@@ -201,7 +205,10 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
 /* ---- solve ------------------------------------------------------------ */
 
 /*
- * Solve the MBAR equations.
+ * Solve the MBAR equations (Eq. 1) by BU-MBAR (Algorithm 1): binned SCI
+ * steps on successively finer bins of the coordinates xi, each level ended
+ * by the relative-step tests of Eqs. (2) and (3), then the unbinned
+ * finisher (Newton on the reduced system, Section 2).
  *  u_kn     K x N (row stride N), dtype u_dtype. With precision MIXED, an
  *           FP64 u_kn is packed to FP32 internally (in the workspace).
  *           NULL: the energies are the model's (HARMONIC or LINEAR, coef
@@ -211,8 +218,11 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
  *           stage then runs on FP32 model sweeps (FP32 coordinates) before
  *           the FP64 refinement.
  *  N_k      K int64.
- *  xi       N x d float64 binning coordinates (row-major), d in {1, 2};
- *           required when opt->binning = 1, else may be NULL.
+ *  xi       N x d binning coordinates (row-major), d in {1, 2}, element
+ *           type xi_dtype (BUMBAR_F64 or BUMBAR_F32; FP32 is widened exactly
+ *           to FP64 in the workspace, and the solve is then that of the
+ *           widened coordinates); required when opt->binning = 1 or u_kn is
+ *           NULL, else may be NULL.
  *  model    BUMBAR_MODEL_*; coef is K x (1 + 2d) float64 (layout in the
  *           model codes above), or NULL for BUMBAR_MODEL_NONE. With a model
  *           the bin representative is the model at the bin centre; without,
@@ -227,10 +237,10 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
  * max_iter or max_newton is reached.
  */
 int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
-                 const int64_t* N_k, const double* xi, int d, int model, const double* coef,
-                 const double* f_init, const bumbar_options* opt, void* workspace,
-                 size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
-                 bumbar_stats* stats);
+                 const int64_t* N_k, const void* xi, int xi_dtype, int d, int model,
+                 const double* coef, const double* f_init, const bumbar_options* opt,
+                 void* workspace, size_t ws_bytes, double* f_k, double* W_nk,
+                 double* log_D_n, bumbar_stats* stats);
 
 /*
  * What bumbar_solve would run for a problem of this shape and options,
@@ -397,6 +407,14 @@ int bumbar_sweep_static(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, i
  * server's memory arena, which is reserved once at creation. Each problem is
  * solved by exactly the kernels and launch shapes of bumbar_solve, so its
  * result is bitwise the same alone and in the mix.
+ *
+ * Two ways of driving the slots: worker threads (caller_driven = 0, one host
+ * thread per slot), or none at all (caller_driven = 1): then every admitted
+ * solve is a fiber (a user-level context on its own stack) that advances
+ * only inside bumbar_server_progress (and bumbar_server_wait, which calls
+ * it), on the calling thread. A fiber runs until its stream is busy with
+ * the kernels it queued, then hands control to the next one, so the
+ * problems' kernels still overlap on the device.
  */
 typedef struct bumbar_server bumbar_server;
 
@@ -404,17 +422,25 @@ typedef struct {
   int device;               /* HIP device                                              */
   size_t hbm_budget_bytes;  /* device memory reserved for resident requests            */
   int max_active;           /* problems solved concurrently (>= 1)                     */
+  int caller_driven;        /* 1: no worker threads; the caller's progress() calls
+                               advance the problems (all server calls but submit, poll,
+                               result and counters from the creating thread)          */
 } bumbar_server_options;
 
 typedef struct {
   int K;
   int64_t N;
-  const double* u_kn;   /* host K x N FP64, or NULL: energies from the model (in-kernel)  */
+  const void* u_kn;     /* host K x N of type u_dtype, or NULL: energies from the model   */
+  int u_dtype;          /* BUMBAR_F64 or BUMBAR_F32: host u_kn, or the materialised u     */
   const int64_t* N_k;   /* host, K entries                                               */
-  const double* xi;     /* host N x d coordinates (binning and/or model), or NULL        */
+  const void* xi;       /* host N x d coordinates (binning and/or model), or NULL        */
+  int xi_dtype;         /* BUMBAR_F64 or BUMBAR_F32                                      */
   int d;                /* coordinate dimension (0 if xi is NULL)                         */
   int model;            /* BUMBAR_MODEL_*                                                */
   const double* coef;   /* host K x (1 + 2d) model coefficients, or NULL                  */
+  int materialize;      /* with u_kn = NULL: 1 evaluates the model once into a resident
+                           device u_kn of type u_dtype (counted in the footprint) and
+                           solves that stored matrix; 0 evaluates it inside the kernels */
   bumbar_options opt;   /* solve options                                                 */
 } bumbar_request;
 
@@ -423,7 +449,8 @@ typedef struct {
 #define BUMBAR_TICKET_DONE 2
 #define BUMBAR_TICKET_FAILED 3
 
-/* Reserve the memory arena and start max_active worker slots. */
+/* Reserve the memory arena and set up max_active slots (with a worker
+ * thread each unless caller_driven). */
 int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out);
 /* Queue a request. The host arrays it points to must stay valid until the
  * ticket is DONE or FAILED. BUMBAR_ETOOBIG if its footprint exceeds the
@@ -431,8 +458,17 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out);
 int bumbar_server_submit(bumbar_server* srv, const bumbar_request* req, uint64_t* ticket);
 /* State of a ticket (BUMBAR_TICKET_*); EINVAL for an unknown ticket. */
 int bumbar_server_poll(bumbar_server* srv, uint64_t ticket, int* state);
-/* Block until the ticket is DONE or FAILED. */
+/* Block until the ticket is DONE or FAILED (caller-driven: calls
+ * bumbar_server_progress until it is). */
 int bumbar_server_wait(bumbar_server* srv, uint64_t ticket);
+/* One tick of a caller-driven server: admit queued requests into free slots
+ * in arrival order while their footprints fit, resume every admitted solve
+ * until it waits on its stream or finishes, and retire the finished ones
+ * (f read back, arena block released). *n_done (may be NULL) receives the
+ * number of tickets that finished in this tick. Does not block on the
+ * device. EINVAL for a threaded server or a call from another thread than
+ * the creating one. */
+int bumbar_server_progress(bumbar_server* srv, int* n_done);
 /* Result of a finished ticket: f_k (host, K entries, or NULL), statistics
  * (host, may be NULL; its checks array is not filled), latency from
  * submission to completion in ms, and the solve's status code. The ticket
@@ -450,12 +486,14 @@ void bumbar_server_destroy(bumbar_server* srv);
 
 /* u_kn = model_k(xi_n) on the device (K x N, row stride N): the reduced
  * energies of the LINEAR / HARMONIC models (layout of coef as in
- * bumbar_solve) for N coordinates xi (N x d, d in {1, 2}); every pointer is
- * device memory owned by the caller. Any potential common to all states is
- * left out, since it cancels in Eq. (1). Stream-ordered on the context's
- * stream (does not synchronise); EINVAL for a bad argument. */
+ * bumbar_solve) for N coordinates xi (N x d float64, d in {1, 2}),
+ * evaluated in FP64 and stored as u_dtype (BUMBAR_F64, or BUMBAR_F32:
+ * rounded once); every pointer is device memory owned by the caller. Any
+ * potential common to all states is left out, since it cancels in Eq. (1).
+ * Stream-ordered on the context's stream (does not synchronise); EINVAL for
+ * a bad argument. */
 int bumbar_model_energies(bumbar_ctx* ctx, int K, int64_t N, int d, int model,
-                          const double* coef, const double* xi, double* u_kn);
+                          const double* coef, const double* xi, int u_dtype, void* u_kn);
 
 #ifdef __cplusplus
 }

@@ -155,7 +155,15 @@ def _dtype_code(u):
         return F64
     if u.dtype == torch.float32:
         return F32
-    raise TypeError("u_kn must be float64 or float32")
+    raise TypeError("u_kn and xi must be float64 or float32")
+
+
+def _is_f32(a):
+    import numpy as np
+    torch = _torch()
+    if torch.is_tensor(a):
+        return a.dtype == torch.float32
+    return getattr(a, "dtype", None) == np.float32
 
 
 def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None,
@@ -183,10 +191,12 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     d = 0
     xi_t = None
     if xi is not None:
-        xi_t = _dev(xi, torch.float64, dev)
+        # FP32 coordinates travel as FP32 (the library widens them exactly)
+        xi_t = _dev(xi, torch.float32 if _is_f32(xi) else torch.float64, dev)
         if xi_t.dim() == 1:
             xi_t = xi_t[:, None].contiguous()
         d = xi_t.shape[1]
+        options.setdefault("xi_dtype", _dtype_code(xi_t))
     if u is None:
         # energies from the model, evaluated inside the kernels
         if xi_t is None or coef is None or model == MODEL_NONE:
@@ -224,9 +234,11 @@ def solve(u, Nk, xi=None, model=MODEL_NONE, coef=None, f_init=None, binning=None
     chk = (_capi.Check * max(1, checks_capacity))()
     st.checks = C.cast(chk, C.POINTER(_capi.Check))
     st.checks_capacity = checks_capacity
-    rc = ctx.lib.bumbar_solve(ctx.h, _ptr(u), _dtype_code(u) if u is not None else F64, K, N, _ptr(Nk_t), _ptr(xi_t), d,
-                              int(model), _ptr(coef_t), _ptr(f_init_t), C.byref(opts),
-                              _ptr(ws), ws.numel(), _ptr(f), _ptr(W), _ptr(lD), C.byref(st))
+    rc = ctx.lib.bumbar_solve(ctx.h, _ptr(u), _dtype_code(u) if u is not None else F64, K, N,
+                              _ptr(Nk_t), _ptr(xi_t),
+                              _dtype_code(xi_t) if xi_t is not None else F64, d, int(model),
+                              _ptr(coef_t), _ptr(f_init_t), C.byref(opts), _ptr(ws), ws.numel(),
+                              _ptr(f), _ptr(W), _ptr(lD), C.byref(st))
     del keep
     _keep(ctx, Nk_t, xi_t, coef_t, f_init_t, u)
     ctx.check(rc, allow=(ENOTCONV,))
@@ -470,9 +482,12 @@ def hessian_model(xi, coef, model, Nk, f, logD, S, precision=PREC_FP64, ctx=None
     return H
 
 
-def model_energies(xi, coef, model, K, ctx=None):
-    """u_kn = model_k(xi_n) (K x N, FP64) built on the device from coordinates xi (N x d)."""
+def model_energies(xi, coef, model, K, ctx=None, dtype=None):
+    """u_kn = model_k(xi_n) (K x N) built on the device from coordinates xi (N x d).
+
+    Evaluated in FP64; ``dtype=torch.float32`` stores it rounded to FP32."""
     torch = _torch()
+    dtype = torch.float64 if dtype is None else dtype
     ctx = ctx or context()
     dev = torch.device(f"cuda:{ctx.device}")
     xi_t = _dev(xi, torch.float64, dev)
@@ -480,9 +495,9 @@ def model_energies(xi, coef, model, K, ctx=None):
         xi_t = xi_t[:, None].contiguous()
     N, d = xi_t.shape
     coef_t = _dev(coef, torch.float64, dev)
-    u = torch.empty((K, N), dtype=torch.float64, device=dev)
+    u = torch.empty((K, N), dtype=dtype, device=dev)
     rc = ctx.lib.bumbar_model_energies(ctx.h, int(K), int(N), int(d), int(model), _ptr(coef_t),
-                                       _ptr(xi_t), _ptr(u))
+                                       _ptr(xi_t), _dtype_code(u), _ptr(u))
     _keep(ctx, xi_t, coef_t)
     ctx.check(rc)
     return u
@@ -497,14 +512,15 @@ class Server:
     The arrays are held here until the ticket's result has been read.
     """
 
-    def __init__(self, hbm_budget_bytes, max_active=4, device=None):
+    def __init__(self, hbm_budget_bytes, max_active=4, device=None, caller_driven=False):
         import numpy  # noqa: F401  (requests are host arrays)
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libbumbar needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = _capi.load()
         dev = torch.cuda.current_device() if device is None else int(device)
-        o = _capi.ServerOptions(dev, int(hbm_budget_bytes), int(max_active))
+        o = _capi.ServerOptions(dev, int(hbm_budget_bytes), int(max_active), int(caller_driven))
+        self.caller_driven = bool(caller_driven)
         h = C.c_void_p()
         rc = self.lib.bumbar_server_create(C.byref(o), C.byref(h))
         if rc != 0:
@@ -513,25 +529,37 @@ class Server:
         self._held = {}
 
     def submit(self, Nk, u=None, xi=None, model=MODEL_NONE, coef=None, K=None, binning=None,
-               **options):
-        """Queue one problem. Give u (K x N float64), or xi + model + coef (u built on device)."""
+               materialize=False, u_dtype=None, **options):
+        """Queue one problem. Give u (K x N host array, float64 or float32), or
+        xi + model + coef: the energies are then evaluated inside the kernels, or,
+        with ``materialize=True``, once into a resident device u of ``u_dtype``
+        (numpy.float32 by default) that the solve reads as a stored matrix.
+        float32 coordinates travel as float32."""
         import numpy as np
         if "replay" in options:
             raise ValueError("replayed schedules are not supported by the server")
         if u is None and (xi is None or coef is None or model == MODEL_NONE):
             raise ValueError("give u, or xi with a model and its coefficients")
         arrs = {}
+        udt = F64
         if u is not None:
-            arrs["u"] = np.ascontiguousarray(u, dtype=np.float64)
+            f32 = getattr(u, "dtype", None) == np.float32
+            arrs["u"] = np.ascontiguousarray(u, dtype=np.float32 if f32 else np.float64)
+            udt = F32 if f32 else F64
             K, N = arrs["u"].shape
+        elif materialize:
+            udt = F64 if u_dtype in (np.float64, F64) else F32
         arrs["Nk"] = np.ascontiguousarray(Nk, dtype=np.int64)
         K = int(K if K is not None else arrs["Nk"].shape[0])
         d = 0
+        xdt = F64
         if xi is not None:
-            x = np.ascontiguousarray(xi, dtype=np.float64)
+            f32 = getattr(xi, "dtype", None) == np.float32
+            x = np.ascontiguousarray(xi, dtype=np.float32 if f32 else np.float64)
             if x.ndim == 1:
                 x = x[:, None]
             arrs["xi"] = x
+            xdt = F32 if f32 else F64
             N, d = x.shape
         if coef is not None:
             arrs["coef"] = np.ascontiguousarray(coef, dtype=np.float64)
@@ -539,6 +567,7 @@ class Server:
             binning = xi is not None
         req = _capi.Request()
         req.K, req.N, req.d, req.model = K, int(N), int(d), int(model)
+        req.u_dtype, req.xi_dtype, req.materialize = udt, xdt, int(bool(materialize))
 
         def p(name):
             a = arrs.get(name)
@@ -547,6 +576,8 @@ class Server:
         req.u_kn, req.N_k, req.xi, req.coef = p("u"), p("Nk"), p("xi"), p("coef")
         options.setdefault("represent", _capi.REPRESENT_CENTRE if model != MODEL_NONE
                            else _capi.REPRESENT_MEAN)
+        options.setdefault("u_dtype", udt)
+        options.setdefault("xi_dtype", xdt)
         req.opt = default_options(binning=int(bool(binning)), **options)
         t = C.c_uint64()
         rc = self.lib.bumbar_server_submit(self.h, C.byref(req), C.byref(t))
@@ -566,6 +597,14 @@ class Server:
         rc = self.lib.bumbar_server_wait(self.h, C.c_uint64(ticket))
         if rc != 0:
             raise BumbarError(rc, "unknown ticket")
+
+    def progress(self):
+        """One tick of a caller-driven server; returns the number of tickets it finished."""
+        n = C.c_int()
+        rc = self.lib.bumbar_server_progress(self.h, C.byref(n))
+        if rc != 0:
+            raise BumbarError(rc, "bumbar_server_progress failed")
+        return n.value
 
     def result(self, ticket, wait=True):
         """(f as numpy float64, info) of a finished ticket; waits for it by default.

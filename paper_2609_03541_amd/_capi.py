@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
                 ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
                 ("represent", C.c_int), ("graphs", C.c_int), ("sample_major", C.c_int),
-                ("u_dtype", C.c_int)]
+                ("u_dtype", C.c_int), ("xi_dtype", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -89,13 +89,15 @@ STAGE32_MODEL = 3
 
 
 class ServerOptions(C.Structure):
-    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int)]
+    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int),
+                ("caller_driven", C.c_int)]
 
 
 class Request(C.Structure):
-    _fields_ = [("K", C.c_int), ("N", C.c_int64), ("u_kn", C.c_void_p), ("N_k", C.c_void_p),
-                ("xi", C.c_void_p), ("d", C.c_int), ("model", C.c_int), ("coef", C.c_void_p),
-                ("opt", Options)]
+    _fields_ = [("K", C.c_int), ("N", C.c_int64), ("u_kn", C.c_void_p), ("u_dtype", C.c_int),
+                ("N_k", C.c_void_p), ("xi", C.c_void_p), ("xi_dtype", C.c_int),
+                ("d", C.c_int), ("model", C.c_int), ("coef", C.c_void_p),
+                ("materialize", C.c_int), ("opt", Options)]
 
 
 # name -> (restype, argtypes); the full exported surface of include/bumbar.h
@@ -112,8 +114,8 @@ SIGNATURES = {
     "bumbar_plan_solve": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int,
                                     C.c_int, C.POINTER(Options), C.POINTER(Plan), C.c_char_p,
                                     C.c_size_t]),
-    "bumbar_solve": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, vp, vp, C.c_int, C.c_int, vp,
-                               vp, C.POINTER(Options), vp, C.c_size_t, vp, vp, vp,
+    "bumbar_solve": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, vp, vp, C.c_int, C.c_int,
+                               C.c_int, vp, vp, C.POINTER(Options), vp, C.c_size_t, vp, vp, vp,
                                C.POINTER(Stats)]),
     "bumbar_sweep": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,
                                C.c_size_t, vp, vp, vp, dp]),
@@ -134,13 +136,15 @@ SIGNATURES = {
                                      vp, vp, C.c_size_t, vp, vp, vp, dp]),
     "bumbar_hessian_model": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, C.c_int,
                                        vp, vp, vp, vp, vp, C.c_size_t, vp]),
-    "bumbar_model_energies": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp, vp]),
+    "bumbar_model_energies": (C.c_int, [vp, C.c_int, C.c_int64, C.c_int, C.c_int, vp, vp,
+                                        C.c_int, vp]),
     "bumbar_sweep_static": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,
                                       vp, vp, dp]),
     "bumbar_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(C.c_void_p)]),
     "bumbar_server_submit": (C.c_int, [vp, C.POINTER(Request), u64p]),
     "bumbar_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int)]),
     "bumbar_server_wait": (C.c_int, [vp, C.c_uint64]),
+    "bumbar_server_progress": (C.c_int, [vp, C.POINTER(C.c_int)]),
     "bumbar_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(Stats), dp,
                                        C.POINTER(C.c_int)]),
     "bumbar_server_counters": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_size_t)]),

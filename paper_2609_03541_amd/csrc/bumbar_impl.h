@@ -227,9 +227,12 @@ size_t newton_ws_doubles(int K);
 hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
                                            const double* H, const double* S, double* A,
                                            const int* idx, double* d, int* ok);
-// u_kn = model_k(xi_n), K x N FP64 with row stride N; d in {1, 2}.
+// u_kn = model_k(xi_n), K x N with row stride N, FP64 or (f32) rounded to
+// FP32; d in {1, 2}.
 hipError_t launch_model_energies(hipStream_t s, int K, int64_t N, int d, int model,
-                                 const double* coef, const double* xi, double* u);
+                                 const double* coef, const double* xi, void* u, bool f32);
+// dst[i] = (double)src[i] for i < n (exact).
+hipError_t launch_widen_f32(hipStream_t s, const float* src, int64_t n, double* dst);
 
 }  // namespace bumbar
 
@@ -248,4 +251,8 @@ struct bumbar_ctx {
   hipStream_t cap_stream = nullptr;
   // this device's address of the library's fixed scratch array (bumbar_sweep_static)
   void* static_scratch = nullptr;
+  // set while a solve runs as a fiber of a caller-driven server: instead of
+  // blocking on a busy stream the solve hands control back to the server
+  void (*yield)(void*) = nullptr;
+  void* yield_arg = nullptr;
 };

@@ -47,12 +47,15 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
     return bad("invalid binning settings");
   if (opt.represent < BUMBAR_REPRESENT_AUTO || opt.represent > BUMBAR_REPRESENT_MEAN)
     return bad("unknown bin representative");
+  if (opt.xi_dtype != BUMBAR_F64 && opt.xi_dtype != BUMBAR_F32)
+    return bad("xi_dtype must be BUMBAR_F64 or BUMBAR_F32");
   p->otf = otf;
   p->u_dtype = otf ? BUMBAR_F64 : u_dtype;
   p->K = K;
   p->N = N;
   p->d = d;
   p->binning = opt.binning != 0;
+  p->xi_wide = d > 0 && opt.xi_dtype == BUMBAR_F32;
   p->rep = opt.represent != BUMBAR_REPRESENT_AUTO || !model_known
                ? opt.represent
                : (model != BUMBAR_MODEL_NONE ? BUMBAR_REPRESENT_CENTRE : BUMBAR_REPRESENT_MEAN);
@@ -129,6 +132,7 @@ void carve_plan(Arena& ar, const Plan& p, int num_cus, PlanBufs* pb) {
   if (p.x_packed) pb->X.carve(ar, p.K, p.N);
   if (p.o_bufs) pb->O.carve(ar, p.K, p.N, p.d);
   if (p.copy) pb->copy = ar.take<char>(p.copy_bytes());
+  if (p.xi_wide) pb->xi64 = ar.take<double>((size_t)p.N * p.d);
 }
 
 }  // namespace bumbar

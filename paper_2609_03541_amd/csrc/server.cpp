@@ -3,16 +3,25 @@
 //
 // Memory: one arena of hbm_budget_bytes is reserved at creation and handed
 // out first-fit (256-byte aligned) to admitted requests; a request's
-// footprint is its resident u_kn (if it carries one; a model request keeps
-// only its coordinates, the energies being evaluated inside the kernels)
-// plus inputs plus the workspace bumbar_solve asks for. Admission is strictly in arrival order: a free slot takes the
+// footprint is its resident u_kn (uploaded, or materialised from the model;
+// a model request without it keeps only its coordinates, the energies being
+// evaluated inside the kernels) plus inputs plus the workspace bumbar_solve
+// asks for. Admission is strictly in arrival order: a free slot takes the
 // oldest queued request as soon as its footprint fits, so a large request is
 // not overtaken indefinitely. Each slot owns a HIP stream (default priority)
-// and a library context; slots run in their own host threads, so the
-// kernels of different problems overlap on the device while every problem is
-// solved by exactly the kernels of bumbar_solve (identical results alone and
-// in the mix). Latency = completion time - submission time (host clock).
+// and a library context, and every problem is solved by exactly the kernels
+// of bumbar_solve (identical results alone and in the mix). Latency =
+// completion time - submission time (host clock).
+//
+// Driving the slots: a host thread per slot, or (caller-driven) fibers: each
+// admitted solve runs on its own stack (ucontext) on the thread that calls
+// bumbar_server_progress, and where bumbar_solve would block on its stream
+// (ctx_wait) it swaps back to the tick, which resumes the next slot. Kernels
+// of all slots stay queued on their streams meanwhile, so they overlap on the
+// device exactly as with threads, but nothing advances between ticks.
 #include <hip/hip_runtime.h>
+#include <sys/mman.h>
+#include <ucontext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -27,6 +36,7 @@
 
 #include "bumbar.h"
 #include "bumbar_impl.h"
+#include "solver_internal.h"
 
 namespace {
 
@@ -82,16 +92,40 @@ class ArenaAllocator {
   std::map<size_t, size_t> free_;  // offset -> size
 };
 
+size_t dtype_bytes(int dt) { return dt == BUMBAR_F32 ? sizeof(float) : sizeof(double); }
+
 struct Job {
   uint64_t ticket = 0;
   bumbar_request req{};
   size_t footprint = 0;
   size_t ws_bytes = 0;
+  bool stored = false;     // the solve reads a resident u_kn (uploaded or materialised)
+  bool xi_wide = false;    // FP32 coordinates widened here for the model evaluation
   Clock::time_point t_submit, t_done;
   int state = BUMBAR_TICKET_QUEUED;
   int status = BUMBAR_OK;
   std::vector<double> f;
   bumbar_stats stats{};
+};
+
+// A solve suspended on its own stack (caller-driven servers).
+struct Fiber {
+  ucontext_t self{}, back{};
+  char* map = nullptr;  // mmap'ed region: a guard page, then the stack
+  size_t map_bytes = 0;
+  bool finished = true;
+};
+
+constexpr size_t kFiberStack = size_t(4) << 20;
+
+struct Slot {
+  bumbar_server* srv = nullptr;
+  hipStream_t stream = nullptr;
+  bumbar_ctx* ctx = nullptr;
+  // caller-driven: the job on this slot and its arena block
+  std::shared_ptr<Job> job;
+  size_t off = 0;
+  Fiber fib;  // ucontext_t points into itself: a Slot never moves (held by pointer)
 };
 
 }  // namespace
@@ -106,8 +140,8 @@ struct bumbar_server {
   std::deque<std::shared_ptr<Job>> queue;
   std::map<uint64_t, std::shared_ptr<Job>> jobs;
   std::vector<std::thread> workers;
-  std::vector<hipStream_t> streams;  // one per slot, default priority
-  std::vector<bumbar_ctx*> ctxs;
+  std::vector<std::unique_ptr<Slot>> slots;
+  std::thread::id owner;  // creating thread (caller-driven calls come from it)
   uint64_t next_ticket = 1;
   bool stop = false;
   int64_t active = 0, peak_active = 0, completed = 0;
@@ -117,18 +151,27 @@ struct bumbar_server {
 
 namespace {
 
-size_t footprint_of(bumbar_server* srv, const bumbar_request& r, size_t* ws_out) {
+size_t footprint_of(bumbar_server* srv, Job& job) {
+  bumbar_request& r = job.req;
+  job.stored = r.u_kn != nullptr || r.materialize;
+  job.xi_wide = r.materialize && r.xi_dtype == BUMBAR_F32;
+  // the solve gets the stored matrix's type, and FP64 coordinates where they
+  // were widened here
+  r.opt.u_dtype = job.stored ? r.u_dtype : BUMBAR_F64;
+  r.opt.xi_dtype = job.xi_wide ? BUMBAR_F64 : r.xi_dtype;
   size_t ws = 0;
-  if (r.u_kn) {
+  if (job.stored) {
     const int dq = (r.opt.binning && r.xi) ? r.d : 0;
     bumbar_query_workspace(srv->sizing_ctx, r.K, r.N, dq, &r.opt, &ws);
   } else {
     bumbar_query_workspace_model(srv->sizing_ctx, r.K, r.N, r.d, &r.opt, &ws);
   }
-  *ws_out = ws;
+  job.ws_bytes = ws;
+  const size_t KN = (size_t)r.K * (size_t)r.N, Nd = (size_t)r.N * (size_t)r.d;
   size_t b = 0;
-  if (r.u_kn) b += align_up(sizeof(double) * (size_t)r.K * (size_t)r.N);  // resident u_kn
-  if (r.xi) b += align_up(sizeof(double) * (size_t)r.N * (size_t)r.d);
+  if (job.stored) b += align_up(dtype_bytes(r.u_dtype) * KN);  // resident u_kn
+  if (r.xi) b += align_up(dtype_bytes(r.xi_dtype) * Nd);
+  if (job.xi_wide) b += align_up(sizeof(double) * Nd);
   b += align_up(sizeof(int64_t) * (size_t)r.K);
   if (r.coef) b += align_up(sizeof(double) * (size_t)r.K * (size_t)(1 + 2 * r.d));
   b += align_up(sizeof(double) * (size_t)r.K);  // f
@@ -136,6 +179,9 @@ size_t footprint_of(bumbar_server* srv, const bumbar_request& r, size_t* ws_out)
   return b;
 }
 
+// Uploads the request into its arena block, solves it and reads f back. On
+// a caller-driven server this runs inside the slot's fiber: every wait on
+// the stream goes through ctx_wait and so yields to the tick.
 void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
   const bumbar_request& r = job.req;
   char* p = base;
@@ -144,9 +190,10 @@ void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
     p += align_up(bytes);
     return q;
   };
-  double* u =
-      r.u_kn ? reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.K * (size_t)r.N)) : nullptr;
-  double* xi = r.xi ? reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.N * r.d)) : nullptr;
+  const size_t KN = (size_t)r.K * (size_t)r.N, Nd = (size_t)r.N * (size_t)r.d;
+  void* u = job.stored ? take(dtype_bytes(r.u_dtype) * KN) : nullptr;
+  void* xi = r.xi ? take(dtype_bytes(r.xi_dtype) * Nd) : nullptr;
+  double* xi64 = job.xi_wide ? reinterpret_cast<double*>(take(sizeof(double) * Nd)) : nullptr;
   int64_t* nk = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (size_t)r.K));
   double* coef =
       r.coef ? reinterpret_cast<double*>(take(sizeof(double) * (size_t)r.K * (1 + 2 * r.d)))
@@ -155,40 +202,68 @@ void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
   void* ws = take(job.ws_bytes);
   hipError_t e = hipSuccess;
   if (r.u_kn)
-    e = hipMemcpyAsync(u, r.u_kn, sizeof(double) * (size_t)r.K * (size_t)r.N,
-                       hipMemcpyHostToDevice, stream);
+    e = hipMemcpyAsync(u, r.u_kn, dtype_bytes(r.u_dtype) * KN, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && r.xi)
-    e = hipMemcpyAsync(xi, r.xi, sizeof(double) * (size_t)r.N * r.d, hipMemcpyHostToDevice,
-                       stream);
+    e = hipMemcpyAsync(xi, r.xi, dtype_bytes(r.xi_dtype) * Nd, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(nk, r.N_k, sizeof(int64_t) * (size_t)r.K, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && r.coef)
     e = hipMemcpyAsync(coef, r.coef, sizeof(double) * (size_t)r.K * (1 + 2 * r.d),
                        hipMemcpyHostToDevice, stream);
+  const void* xs = xi;  // the coordinates the solve reads
+  int xs_dtype = r.xi_dtype;
+  if (e == hipSuccess && job.xi_wide) {
+    e = bumbar::launch_widen_f32(stream, static_cast<const float*>(xi), (int64_t)Nd, xi64);
+    xs = xi64;
+    xs_dtype = BUMBAR_F64;
+  }
+  // a materialised request: the model evaluated once into the resident u_kn
+  if (e == hipSuccess && !r.u_kn && r.materialize)
+    e = bumbar::launch_model_energies(stream, r.K, r.N, r.d, r.model, coef,
+                                      static_cast<const double*>(xs), u,
+                                      r.u_dtype == BUMBAR_F32);
   if (e != hipSuccess) {
     job.status = BUMBAR_EDEVICE;
     return;
   }
-  // a request without u_kn is solved with the energies evaluated from the
-  // model inside the kernels (u_kn = NULL in bumbar_solve)
+  // a request without a stored u_kn is solved with the energies evaluated
+  // from the model inside the kernels (u_kn = NULL in bumbar_solve)
   const int dq = r.xi ? r.d : 0;
   job.stats.checks = nullptr;
   job.stats.checks_capacity = 0;
-  job.status = bumbar_solve(ctx, u, BUMBAR_F64, r.K, r.N, nk, dq ? xi : nullptr, dq, r.model,
-                            coef, nullptr, &r.opt, ws, job.ws_bytes, f, nullptr, nullptr,
-                            &job.stats);
+  job.status = bumbar_solve(ctx, u, r.u_dtype, r.K, r.N, nk, dq ? xs : nullptr, xs_dtype, dq,
+                            r.model, coef, nullptr, &r.opt, ws, job.ws_bytes, f, nullptr,
+                            nullptr, &job.stats);
   job.f.assign(r.K, 0.0);
-  if (hipMemcpyAsync(job.f.data(), f, sizeof(double) * r.K, hipMemcpyDeviceToHost, stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess) {
-    if (job.status == BUMBAR_OK) job.status = BUMBAR_EDEVICE;
-  }
+  // drain before the copy into pageable memory (it would block a fiber's thread)
+  e = bumbar::ctx_wait(ctx, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(job.f.data(), f, sizeof(double) * r.K, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = bumbar::ctx_wait(ctx, stream);
+  if (e != hipSuccess && job.status == BUMBAR_OK) job.status = BUMBAR_EDEVICE;
 }
 
-void worker_main(bumbar_server* srv, int slot) {
+// Marks a job finished and returns its arena block (caller holds srv->mu).
+void finish_locked(bumbar_server* srv, Job& job, size_t off) {
+  srv->alloc->release(off, job.footprint);
+  job.t_done = Clock::now();
+  job.state = (job.status == BUMBAR_OK || job.status == BUMBAR_ENOTCONV) ? BUMBAR_TICKET_DONE
+                                                                         : BUMBAR_TICKET_FAILED;
+  srv->active--;
+  srv->completed++;
+}
+
+// Fails every queued job (shutdown; caller holds srv->mu).
+void fail_queued_locked(bumbar_server* srv) {
+  for (auto& j : srv->queue) {
+    j->state = BUMBAR_TICKET_FAILED;
+    j->status = BUMBAR_EBUSY;
+  }
+  srv->queue.clear();
+}
+
+void worker_main(bumbar_server* srv, Slot* sl) {
   (void)hipSetDevice(srv->opt.device);
-  hipStream_t stream = srv->streams[slot];
-  bumbar_ctx* ctx = srv->ctxs[slot];
   for (;;) {
     std::shared_ptr<Job> job;
     size_t off = 0;
@@ -202,11 +277,7 @@ void worker_main(bumbar_server* srv, int slot) {
       if (srv->stop && srv->queue.empty()) break;
       if (srv->stop) {
         // drain: jobs still queued at shutdown fail without running
-        for (auto& j : srv->queue) {
-          j->state = BUMBAR_TICKET_FAILED;
-          j->status = BUMBAR_EBUSY;
-        }
-        srv->queue.clear();
+        fail_queued_locked(srv);
         srv->cv_done.notify_all();
         break;
       }
@@ -216,30 +287,137 @@ void worker_main(bumbar_server* srv, int slot) {
       srv->active++;
       srv->peak_active = std::max(srv->peak_active, srv->active);
     }
-    run_job(ctx, stream, srv->arena + off, *job);
+    run_job(sl->ctx, sl->stream, srv->arena + off, *job);
     // whatever path run_job left by, no copy or kernel of this job may still
     // touch its arena block once the block is handed to another request
-    if (hipStreamSynchronize(stream) != hipSuccess && job->status == BUMBAR_OK)
+    if (hipStreamSynchronize(sl->stream) != hipSuccess && job->status == BUMBAR_OK)
       job->status = BUMBAR_EDEVICE;
     {
       std::lock_guard<std::mutex> lk(srv->mu);
-      srv->alloc->release(off, job->footprint);
-      job->t_done = Clock::now();
-      job->state = (job->status == BUMBAR_OK || job->status == BUMBAR_ENOTCONV)
-                       ? BUMBAR_TICKET_DONE
-                       : BUMBAR_TICKET_FAILED;
-      srv->active--;
-      srv->completed++;
+      finish_locked(srv, *job, off);
     }
     srv->cv_admit.notify_all();
     srv->cv_done.notify_all();
   }
 }
 
+// ---- fibers (caller-driven servers) --------------------------------------
+
+thread_local Slot* t_entering = nullptr;  // the slot whose fiber starts next
+
+void fiber_yield(void* arg) {
+  Fiber* f = static_cast<Fiber*>(arg);
+  swapcontext(&f->self, &f->back);
+}
+
+void fiber_main() {
+  Slot* sl = t_entering;
+  try {
+    run_job(sl->ctx, sl->stream, sl->srv->arena + sl->off, *sl->job);
+  } catch (...) {
+    sl->job->status = BUMBAR_ENOMEM;  // host allocation failed inside the solve
+  }
+  sl->ctx->yield = nullptr;
+  sl->ctx->yield_arg = nullptr;
+  sl->fib.finished = true;
+  // returning resumes uc_link, the tick that last resumed this fiber
+}
+
+bool fiber_alloc(Fiber& f) {
+  const size_t page = 4096;
+  f.map_bytes = kFiberStack + page;
+  void* m = mmap(nullptr, f.map_bytes, PROT_READ | PROT_WRITE,
+                 MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+  if (m == MAP_FAILED) return false;
+  f.map = static_cast<char*>(m);
+  // the lowest page stays inaccessible: a stack overflow faults on the host
+  // instead of writing over other memory
+  if (mprotect(f.map, page, PROT_NONE) != 0) return false;
+  return true;
+}
+
+void fiber_free(Fiber& f) {
+  if (f.map) munmap(f.map, f.map_bytes);
+  f.map = nullptr;
+}
+
+// Starts the fiber of a slot that has just been given a job.
+bool fiber_start(Slot& sl) {
+  Fiber& f = sl.fib;
+  if (getcontext(&f.self) != 0) return false;
+  f.self.uc_stack.ss_sp = f.map + 4096;
+  f.self.uc_stack.ss_size = kFiberStack;
+  f.self.uc_link = &f.back;
+  makecontext(&f.self, fiber_main, 0);
+  f.finished = false;
+  sl.ctx->yield = fiber_yield;
+  sl.ctx->yield_arg = &f;
+  return true;
+}
+
+// Admission of a caller-driven tick: free slots take queued jobs in arrival
+// order while the oldest one's footprint fits.
+void admit(bumbar_server* srv) {
+  std::lock_guard<std::mutex> lk(srv->mu);
+  for (auto& slp : srv->slots) {
+    Slot& sl = *slp;
+    if (sl.job) continue;
+    if (srv->queue.empty()) break;
+    size_t off = 0;
+    if (!srv->alloc->alloc(srv->queue.front()->footprint, &off)) break;
+    sl.job = srv->queue.front();
+    srv->queue.pop_front();
+    sl.off = off;
+    sl.job->state = BUMBAR_TICKET_RUNNING;
+    srv->active++;
+    srv->peak_active = std::max(srv->peak_active, srv->active);
+    if (!fiber_start(sl)) {
+      sl.job->status = BUMBAR_EDEVICE;
+      finish_locked(srv, *sl.job, off);
+      sl.job.reset();
+      sl.ctx->yield = nullptr;
+    }
+  }
+}
+
+// Resumes every running fiber once and retires the finished ones.
+int tick(bumbar_server* srv) {
+  (void)hipSetDevice(srv->opt.device);
+  admit(srv);
+  int done = 0;
+  for (auto& slp : srv->slots) {
+    Slot& sl = *slp;
+    if (!sl.job) continue;
+    t_entering = &sl;
+    swapcontext(&sl.fib.back, &sl.fib.self);
+    if (!sl.fib.finished) continue;
+    Job& job = *sl.job;
+    if (hipStreamSynchronize(sl.stream) != hipSuccess && job.status == BUMBAR_OK)
+      job.status = BUMBAR_EDEVICE;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      finish_locked(srv, job, sl.off);
+    }
+    sl.job.reset();
+    ++done;
+  }
+  if (done) srv->cv_done.notify_all();
+  return done;
+}
+
+bool any_running(bumbar_server* srv) {
+  for (auto& slp : srv->slots)
+    if (slp->job) return true;
+  return false;
+}
+
 // Frees the slots, the sizing context and the arena, then the server.
 void release_slots(bumbar_server* srv) {
-  for (bumbar_ctx* c : srv->ctxs) bumbar_destroy(c);
-  for (hipStream_t st : srv->streams) (void)hipStreamDestroy(st);
+  for (auto& slp : srv->slots) {
+    if (slp->ctx) bumbar_destroy(slp->ctx);
+    if (slp->stream) (void)hipStreamDestroy(slp->stream);
+    fiber_free(slp->fib);
+  }
   bumbar_destroy(srv->sizing_ctx);
   (void)hipFree(srv->arena);
   delete srv;
@@ -255,6 +433,7 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) 
   auto* srv = new (std::nothrow) bumbar_server();
   if (!srv) return BUMBAR_ENOMEM;
   srv->opt = *opt;
+  srv->owner = std::this_thread::get_id();
   if (hipSetDevice(opt->device) != hipSuccess) {
     delete srv;
     return BUMBAR_EDEVICE;
@@ -271,33 +450,43 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) 
   }
   srv->alloc.reset(new ArenaAllocator(opt->hbm_budget_bytes));
   for (int i = 0; i < opt->max_active; ++i) {
-    hipStream_t st = nullptr;
-    bumbar_ctx* c = nullptr;
-    if (hipStreamCreate(&st) != hipSuccess || bumbar_create(&c, opt->device, st) != BUMBAR_OK) {
-      if (st) (void)hipStreamDestroy(st);
+    std::unique_ptr<Slot> sl(new Slot());
+    sl->srv = srv;
+    if (hipStreamCreate(&sl->stream) != hipSuccess ||
+        bumbar_create(&sl->ctx, opt->device, sl->stream) != BUMBAR_OK) {
       (void)hipGetLastError();
+      srv->slots.push_back(std::move(sl));
       release_slots(srv);
       return BUMBAR_EDEVICE;
     }
-    srv->streams.push_back(st);
-    srv->ctxs.push_back(c);
+    const bool fib_ok = !opt->caller_driven || fiber_alloc(sl->fib);
+    srv->slots.push_back(std::move(sl));
+    if (!fib_ok) {
+      release_slots(srv);
+      return BUMBAR_ENOMEM;
+    }
   }
-  for (int i = 0; i < opt->max_active; ++i) srv->workers.emplace_back(worker_main, srv, i);
+  if (!opt->caller_driven)
+    for (auto& slp : srv->slots) srv->workers.emplace_back(worker_main, srv, slp.get());
   *out = srv;
   return BUMBAR_OK;
 }
 
 int bumbar_server_submit(bumbar_server* srv, const bumbar_request* req, uint64_t* ticket) {
   if (!srv || !req || !ticket || req->K <= 0 || req->N <= 0 || !req->N_k) return BUMBAR_EINVAL;
+  if ((req->u_dtype != BUMBAR_F64 && req->u_dtype != BUMBAR_F32) ||
+      (req->xi_dtype != BUMBAR_F64 && req->xi_dtype != BUMBAR_F32))
+    return BUMBAR_EINVAL;
   if (!req->u_kn && (req->model == BUMBAR_MODEL_NONE || !req->xi || !req->coef))
     return BUMBAR_EINVAL;
+  if (req->u_kn && req->materialize) return BUMBAR_EINVAL;
   auto job = std::make_shared<Job>();
   job->req = *req;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return BUMBAR_EBUSY;
     // the sizing context is shared by submitting threads
-    job->footprint = footprint_of(srv, *req, &job->ws_bytes);
+    job->footprint = footprint_of(srv, *job);
     if (job->footprint > srv->opt.hbm_budget_bytes) return BUMBAR_ETOOBIG;
     job->t_submit = Clock::now();
     job->ticket = srv->next_ticket++;
@@ -318,15 +507,39 @@ int bumbar_server_poll(bumbar_server* srv, uint64_t ticket, int* state) {
   return BUMBAR_OK;
 }
 
+int bumbar_server_progress(bumbar_server* srv, int* n_done) {
+  if (n_done) *n_done = 0;
+  if (!srv || !srv->opt.caller_driven || std::this_thread::get_id() != srv->owner)
+    return BUMBAR_EINVAL;
+  const int done = tick(srv);
+  if (n_done) *n_done = done;
+  return BUMBAR_OK;
+}
+
 int bumbar_server_wait(bumbar_server* srv, uint64_t ticket) {
   if (!srv) return BUMBAR_EINVAL;
-  std::unique_lock<std::mutex> lk(srv->mu);
-  auto it = srv->jobs.find(ticket);
-  if (it == srv->jobs.end()) return BUMBAR_EINVAL;
-  auto job = it->second;
-  srv->cv_done.wait(lk, [&] {
+  std::shared_ptr<Job> job;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end()) return BUMBAR_EINVAL;
+    job = it->second;
+  }
+  auto finished = [&] {
     return job->state == BUMBAR_TICKET_DONE || job->state == BUMBAR_TICKET_FAILED;
-  });
+  };
+  if (srv->opt.caller_driven) {
+    if (std::this_thread::get_id() != srv->owner) return BUMBAR_EINVAL;
+    for (;;) {
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (finished()) return BUMBAR_OK;
+      }
+      if (tick(srv) == 0) std::this_thread::yield();
+    }
+  }
+  std::unique_lock<std::mutex> lk(srv->mu);
+  srv->cv_done.wait(lk, finished);
   return BUMBAR_OK;
 }
 
@@ -368,9 +581,16 @@ void bumbar_server_destroy(bumbar_server* srv) {
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stop = true;
+    if (srv->opt.caller_driven) fail_queued_locked(srv);
   }
-  srv->cv_admit.notify_all();
-  for (auto& t : srv->workers) t.join();
+  if (srv->opt.caller_driven) {
+    // the suspended solves hold live objects on their stacks: run them out
+    while (any_running(srv))
+      if (tick(srv) == 0) std::this_thread::yield();
+  } else {
+    srv->cv_admit.notify_all();
+    for (auto& t : srv->workers) t.join();
+  }
   release_slots(srv);
 }
 

@@ -105,18 +105,30 @@ static double collect_event_ms(bumbar_ctx* ctx, int64_t* count) {
   return tot;
 }
 
+hipError_t ctx_wait(bumbar_ctx* ctx, hipStream_t s) {
+  if (!ctx->yield) return hipStreamSynchronize(s);
+  for (;;) {
+    const hipError_t q = hipStreamQuery(s);
+    if (q != hipErrorNotReady) return q;
+    ctx->yield(ctx->yield_arg);
+  }
+}
+
 int read_scalars(bumbar_ctx* ctx, const SweepScalars* dev, SweepScalars* host) {
   hipError_t e = hipMemcpyAsync(ctx->pinned, dev, sizeof(SweepScalars), hipMemcpyDeviceToHost,
                                 ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = ctx_wait(ctx, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "scalar readback");
   std::memcpy(host, ctx->pinned, sizeof(SweepScalars));
   return BUMBAR_OK;
 }
 
 int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
-  hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  // a copy into pageable memory blocks the host until the stream reaches it:
+  // a fiber first lets the stream drain
+  hipError_t e = ctx->yield ? ctx_wait(ctx, ctx->stream) : hipSuccess;
+  if (e == hipSuccess) e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = ctx_wait(ctx, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "readback");
   return BUMBAR_OK;
 }
@@ -537,6 +549,7 @@ void bumbar_default_options(bumbar_options* o) {
   o->graphs = 1;
   o->sample_major = 1;
   o->u_dtype = BUMBAR_F64;
+  o->xi_dtype = BUMBAR_F64;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,
@@ -654,10 +667,8 @@ static int sep_setup(bumbar_ctx* ctx, int K, int d, int model, const double* coe
   if (d != 2 || model != BUMBAR_MODEL_HARMONIC || !O.sep_i || !O.sep_d || K < 16)
     return BUMBAR_OK;
   std::vector<double> c((size_t)K * 5);
-  hipError_t e = hipMemcpyAsync(c.data(), coef, sizeof(double) * c.size(),
-                                hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "read model coefficients");
+  int rc = read_bytes(ctx, coef, c.data(), sizeof(double) * c.size());
+  if (rc) return rc;
   std::map<std::pair<double, double>, int> xs, ys;
   std::vector<int> ibuf(sep_int_count(K), 0);
   std::vector<double> dbuf(4 * kSepMax, 0.0);
@@ -696,12 +707,12 @@ static int sep_setup(bumbar_ctx* ctx, int K, int d, int model, const double* coe
   for (int q = 0; q < Ix * Jy; ++q) cstart[q + 1] += cstart[q];
   std::vector<int> cur(cstart, cstart + Ix * Jy);
   for (int k = 0; k < K; ++k) cstates[cur[ix[k] * Jy + jy[k]]++] = k;
-  e = hipMemcpyAsync(O.sep_i, ibuf.data(), sizeof(int) * ibuf.size(), hipMemcpyHostToDevice,
-                     ctx->stream);
+  hipError_t e = hipMemcpyAsync(O.sep_i, ibuf.data(), sizeof(int) * ibuf.size(),
+                                hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(O.sep_d, dbuf.data(), sizeof(double) * dbuf.size(),
                        hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // the host buffers end here
+  if (e == hipSuccess) e = ctx_wait(ctx, ctx->stream);  // the host buffers end here
   if (e != hipSuccess) return hip_fail(ctx, e, "upload product grid");
   g->Ix = Ix;
   g->Jy = Jy;
@@ -830,13 +841,15 @@ int bumbar_reweight(bumbar_ctx* ctx, const double* u_target, int64_t N, const do
 }
 
 int bumbar_model_energies(bumbar_ctx* ctx, int K, int64_t N, int d, int model,
-                          const double* coef, const double* xi, double* u_kn) {
+                          const double* coef, const double* xi, int u_dtype, void* u_kn) {
   if (!ctx) return BUMBAR_EINVAL;
   ctx->err.clear();
   if (K <= 0 || N <= 0 || (d != 1 && d != 2) || !coef || !xi || !u_kn ||
-      (model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC))
+      (model != BUMBAR_MODEL_LINEAR && model != BUMBAR_MODEL_HARMONIC) ||
+      (u_dtype != BUMBAR_F64 && u_dtype != BUMBAR_F32))
     return fail(ctx, BUMBAR_EINVAL, "bad argument");
-  const hipError_t e = launch_model_energies(ctx->stream, K, N, d, model, coef, xi, u_kn);
+  const hipError_t e = launch_model_energies(ctx->stream, K, N, d, model, coef, xi, u_kn,
+                                             u_dtype == BUMBAR_F32);
   if (e != hipSuccess) return hip_fail(ctx, e, "model energies");
   return BUMBAR_OK;
 }
@@ -884,10 +897,10 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
 }
 
 int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
-                 const int64_t* N_k, const double* xi, int d, int model, const double* coef,
-                 const double* f_init, const bumbar_options* opt_in, void* workspace,
-                 size_t ws_bytes, double* f_k, double* W_nk, double* log_D_n,
-                 bumbar_stats* stats) {
+                 const int64_t* N_k, const void* xi_in, int xi_dtype, int d, int model,
+                 const double* coef, const double* f_init, const bumbar_options* opt_in,
+                 void* workspace, size_t ws_bytes, double* f_k, double* W_nk,
+                 double* log_D_n, bumbar_stats* stats) {
   // u_kn == NULL: the energies come from the model, evaluated in the kernels
   const bool otf = (u_kn == nullptr);
   int rc = otf ? check_common(ctx, coef, BUMBAR_F64, K, N, N) : check_common(ctx, u_kn, u_dtype, K,
@@ -900,7 +913,8 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     bumbar_default_options(&opt);
   if (!N_k || !f_k || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
   if (model != BUMBAR_MODEL_NONE && !coef) return fail(ctx, BUMBAR_EINVAL, "model needs coef");
-  if ((opt.binning || otf) && !xi) return fail(ctx, BUMBAR_EINVAL, "xi is NULL");
+  if ((opt.binning || otf) && !xi_in) return fail(ctx, BUMBAR_EINVAL, "xi is NULL");
+  opt.xi_dtype = xi_dtype;  // the call's type decides the plan
   Plan plan;
   {
     std::string why;
@@ -933,8 +947,17 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (opt.binning) BB.otf = rep == BUMBAR_REPRESENT_CENTRE && (otf || !sweep_fast_supported(K));
   // every buffer a planned path launches with must have been carved
   if ((plan.x_packed && !X.r) || (plan.copy && !pb.copy) || (plan.o_bufs && !O.cf64) ||
-      (plan.fp32_binned && !BB.cenf[0]))
+      (plan.fp32_binned && !BB.cenf[0]) || (plan.xi_wide && !pb.xi64))
     return fail(ctx, BUMBAR_EINVAL, "internal: a planned buffer was not carved");
+  // the coordinates every kernel reads: the caller's FP64 array, or FP32
+  // coordinates widened (exactly) into the workspace
+  const double* xi = reinterpret_cast<const double*>(xi_in);
+  if (plan.xi_wide) {
+    const hipError_t ew =
+        launch_widen_f32(ctx->stream, reinterpret_cast<const float*>(xi_in), N * d, pb.xi64);
+    if (ew != hipSuccess) return hip_fail(ctx, ew, "widen coordinates");
+    xi = pb.xi64;
+  }
   bumbar_stats local{};
   bumbar_stats* st = stats ? stats : &local;
   bumbar_check* chk = st->checks;
@@ -1131,7 +1154,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (e == hipSuccess && W_nk)
     e = otf ? launch_weights_otf(s, M.otf, K, N, B.f, B.logD, W_nk)
             : launch_weights(s, u_kn, u_dtype == BUMBAR_F32, N, K, N, B.f, B.logD, W_nk);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = ctx_wait(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "outputs");
   st->unbinned_sweeps = cnt.fast + cnt.robust;
   st->robust_sweeps = cnt.robust;

@@ -14,6 +14,10 @@ int fail(bumbar_ctx* ctx, int code, const char* fmt, ...);
 int hip_fail(bumbar_ctx* ctx, hipError_t e, const char* where);
 double now_ms();
 int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes);
+// Waits for the work queued on s: hipStreamSynchronize, or, for a solve
+// running as a fiber of a caller-driven server, yields to the server while
+// the stream is busy.
+hipError_t ctx_wait(bumbar_ctx* ctx, hipStream_t s);
 std::pair<hipEvent_t, hipEvent_t>* next_event_pair(bumbar_ctx* ctx);
 
 // Binned SCI steps queued between two host readbacks.
@@ -118,6 +122,7 @@ struct Plan {
   bool fp32_binned = false;  // binned steps first on the FP32 model sweep
   bool copy = false;         // sample-major copy of u in the workspace
   bool copy_f32 = false;     // its element type
+  bool xi_wide = false;      // FP32 coordinates widened to FP64 in the workspace
   // carve flags
   bool bb_ubar = false, bb_cen = false, bb_cen_f32 = false;
   int64_t bb_otf_cap = 0;
@@ -280,6 +285,7 @@ struct PlanBufs {
   MixedBufs X;
   OtfBufs O;
   void* copy = nullptr;
+  double* xi64 = nullptr;  // N x d widened coordinates (xi_wide)
 };
 void carve_plan(Arena& ar, const Plan& p, int num_cus, PlanBufs* pb);
 

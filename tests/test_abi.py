@@ -53,15 +53,17 @@ def test_version_and_null_context(lib):
     assert lib.bumbar_create(None, 0, None) == -1
     nb = C.c_size_t()
     assert lib.bumbar_query_workspace(None, 4, 10, 0, None, C.byref(nb)) == -1
-    assert lib.bumbar_model_energies(None, 4, 10, 1, 2, None, None, None) == -1
+    assert lib.bumbar_model_energies(None, 4, 10, 1, 2, None, None, 0, None) == -1
     srv = C.c_void_p()
     assert lib.bumbar_server_create(None, C.byref(srv)) == -1
-    bad = _capi.ServerOptions(0, 1 << 20, 0)  # max_active < 1 is rejected before any HIP call
+    bad = _capi.ServerOptions(0, 1 << 20, 0, 1)  # max_active < 1 is rejected before any HIP call
     assert lib.bumbar_server_create(C.byref(bad), C.byref(srv)) == -1
     t = C.c_uint64()
     assert lib.bumbar_server_submit(None, None, C.byref(t)) == -1
     assert lib.bumbar_server_poll(None, 1, None) == -1
     assert lib.bumbar_server_wait(None, 1) == -1
+    n = C.c_int(7)
+    assert lib.bumbar_server_progress(None, C.byref(n)) == -1 and n.value == 0
     assert lib.bumbar_server_counters(None, None, None, None) == -1
     lib.bumbar_server_destroy(None)
 

@@ -4,9 +4,12 @@ A served problem must give bitwise the result of the same problem solved
 alone (same kernels and launch shapes, deterministic reductions), and the
 FP64 oracle's solution to 1e-9 kT. Admission is checked through the
 server's counters: with room for several problems they run concurrently;
-with an arena that holds one at a time they run one after another.
+with an arena that holds one at a time they run one after another. Both
+ways of driving the slots (worker threads, and caller-driven fibers that
+advance only inside progress()) give the same bits.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -183,3 +186,85 @@ def test_mixed_precision_served_equals_solo(bm):
         assert srv.counters()["peak_active"] >= 2
     finally:
         srv.close()
+
+
+def test_caller_driven_server_advances_only_in_progress(bm):
+    # no worker threads: nothing is admitted or run between progress() calls;
+    # driven by progress() alone the results are bitwise those of the solo
+    # solves and of a threaded server
+    probs = small_stream(8, seed=13)
+    kw = [dict(u=p["u"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+               binning=i % 3 != 2, tol=1e-11) for i, p in enumerate(probs)]
+    srv = bm.Server(hbm_budget_bytes=1 << 30, max_active=3, caller_driven=True)
+    try:
+        ts = [srv.submit(p["Nk"], **k) for p, k in zip(probs, kw)]
+        time.sleep(0.3)
+        assert [srv.poll(t) for t in ts] == [0] * len(ts)  # all still QUEUED
+        done = srv.progress()
+        states = [srv.poll(t) for t in ts]
+        say("after one tick", states, "done", done)
+        assert all(s in (1, 2) for s in states[:3]) and states[3:] == [0] * 5
+        ticks, t0 = 1, time.time()
+        while done < len(ts):
+            done += srv.progress()
+            ticks += 1
+            assert time.time() - t0 < 60, "caller-driven server made no progress"
+        say("ticks", ticks)
+        res = [srv.result(t, wait=False) for t in ts]
+        c = srv.counters()
+        assert c["completed"] == len(ts) and c["peak_active"] == 3
+    finally:
+        srv.close()
+    thr = bm.Server(hbm_budget_bytes=1 << 30, max_active=3)
+    try:
+        tt = [thr.submit(p["Nk"], **k) for p, k in zip(probs, kw)]
+        res_thr = [thr.result(t) for t in tt]
+    finally:
+        thr.close()
+    for i, (p, k) in enumerate(zip(probs, kw)):
+        f, info = res[i]
+        assert info["status"] == 0 and info["latency_ms"] > 0
+        assert np.array_equal(f, res_thr[i][0]), i
+        kk = dict(k)
+        f_solo, _ = bm.solve(dev(kk.pop("u")), p["Nk"], **kk)
+        assert np.array_equal(f, f_solo.cpu().numpy()), i
+
+
+def test_caller_driven_wait_and_close_drive_the_fibers(bm):
+    # wait() ticks until its ticket is done; close() runs the admitted solves
+    # to the end and fails the queued ones
+    probs = small_stream(5, seed=17)
+    srv = bm.Server(hbm_budget_bytes=1 << 30, max_active=2, caller_driven=True)
+    ts = [srv.submit(p["Nk"], u=p["u"], tol=1e-11) for p in probs]
+    f, info = srv.result(ts[3])  # waits: tickets 0-2 are admitted and run first
+    assert info["status"] == 0
+    f_solo, _ = bm.solve(dev(probs[3]["u"]), probs[3]["Nk"], tol=1e-11)
+    assert np.array_equal(f, f_solo.cpu().numpy())
+    srv.close()
+
+
+@pytest.mark.parametrize("caller_driven", [False, True])
+def test_materialized_fp32_requests(bm, caller_driven):
+    # u evaluated once on the device from the model and stored in FP32 (4 B
+    # per element in the footprint), solved in mixed precision as a stored
+    # FP32 matrix: bitwise the solo solve of that matrix, and the oracle's
+    # solution of the FP32-rounded problem to 1e-9 kT
+    import torch
+    specs = synth.serving_stream(n_problems=4, seed=23, K_range=(40, 120), Nk_range=(200, 600))
+    probs = [synth.materialize_problem(s) for _, s in specs]
+    srv = bm.Server(hbm_budget_bytes=1 << 30, max_active=3, caller_driven=caller_driven)
+    try:
+        ts = [srv.submit(p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                         materialize=True, tol=1e-10, precision=bm.PREC_MIXED) for p in probs]
+        res = [srv.result(t) for t in ts]
+    finally:
+        srv.close()
+    for i, (p, (f, info)) in enumerate(zip(probs, res)):
+        say(f"materialised FP32 problem {i}: K={p['K']} N={p['N']} status={info['status']}")
+        assert info["status"] == 0 and info["mixed_steps"] >= 1
+        u32 = bm.model_energies(p["xi"], p["coef"], p["model_type"], p["K"], dtype=torch.float32)
+        f_solo, _ = bm.solve(u32, p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
+                             tol=1e-10, precision=bm.PREC_MIXED)
+        assert np.array_equal(f, f_solo.cpu().numpy()), i
+        f_ref, _ = oracle.solve_mbar(u32.double().cpu().numpy(), p["Nk"])
+        assert np.max(np.abs(f - f_ref)) < 1e-9, i

@@ -82,3 +82,17 @@ def test_refused_combinations(bm, kw, needle):
 def test_fp64_beyond_copy_range_two_pass(bm):
     p = bm.plan(1500, 100_000)
     assert p["sweep"] == _capi.SWEEP_TWO_PASS and p["copy_bytes"] == 0
+
+
+def test_fp32_coordinates_widened_in_workspace(bm):
+    # FP32 xi costs exactly N d doubles of workspace (its exact FP64 widening)
+    K, N = 1600, 800_000
+    kw = dict(d=2, model=bm.MODEL_HARMONIC, stored_u=False, binning=1, represent=1)
+    p64 = bm.plan(K, N, **kw)
+    p32 = bm.plan(K, N, xi_dtype=bm.F32, **kw)
+    assert 0 <= p32["workspace_bytes"] - p64["workspace_bytes"] - N * 2 * 8 < 256  # + alignment
+    with pytest.raises(bm.BumbarError):
+        bm.plan(K, N, xi_dtype=7, **kw)
+    # no coordinates: nothing to widen
+    assert bm.plan(100, 1000, xi_dtype=bm.F32)["workspace_bytes"] == \
+        bm.plan(100, 1000)["workspace_bytes"]
