@@ -318,3 +318,31 @@ def pmf(xi, p, lo, hi, nbins):
     _check(_load().orc_pmf(N, d, _p(x), _p(_d(p)), _p(lo_a), _p(hi_a), _p(nb, C.c_int), _p(F)),
            "pmf")
     return F.reshape(tuple(int(v) for v in nb))
+
+
+def covariance(u, Nk, f, null_tol=1e-9):
+    """Asymptotic covariance of the free energies, Cov(f_i, f_j) in the gauge f_0 = 0.
+
+    The paper names uncertainty estimates only as related work (Section 1);
+    the estimator here is the large-sample covariance of the MBAR estimate
+    (Shirts and Chodera, J. Chem. Phys. 129, 124105 (2008)):
+
+        Theta = W^T (I_N - W diag(N_k) W^T)^+ W,   W_nk = exp(f_k - u_kn - ln D_n),
+
+    at the solution f, and Cov(f_i, f_j) = (e_i - e_0)^T Theta (e_j - e_0).
+    The N x N pseudo-inverse is written out through the thin SVD of
+    A = W_S diag(N_S)^(1/2) over the sampled states S: with A = U diag(s) V^T,
+    (I - A A^T)^+ = (I - U U^T) + U diag(h) U^T where h = 1 / (1 - s^2), and
+    h = 0 on the null direction s = 1 (|1 - s^2| < null_tol; at the solution
+    it is the gauge direction, A diag(N_S)^(1/2) 1 = 1_N). Returns K x K.
+    """
+    u, Nk, f = _d(u), _i64(Nk), _d(f)
+    W = weights(u, Nk, f)
+    S = Nk > 0
+    A = W[:, S] * np.sqrt(Nk[S].astype(np.float64))
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    gap = 1.0 - s * s
+    h = np.where(np.abs(gap) < null_tol, 0.0, 1.0 / np.where(np.abs(gap) < null_tol, 1.0, gap))
+    WU = W.T @ U
+    theta = W.T @ W - WU @ WU.T + (WU * h) @ WU.T
+    return theta - theta[:, :1] - theta[:1, :] + theta[0, 0]
