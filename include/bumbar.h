@@ -266,6 +266,29 @@ typedef struct {
 int bumbar_plan_solve(int num_cus, int stored_u, int u_dtype, int K, int64_t N, int d, int model,
                       const bumbar_options* opt, bumbar_plan* out, char* msg, size_t msg_len);
 
+/* ---- uncertainty of f ------------------------------------------------- */
+
+/*
+ * Asymptotic covariance of the free energies at the solution f (gauge
+ * f_0 = 0): cov[i * K + j] = Cov(f_i, f_j), K x K float64 row-major (device),
+ * zero on row and column 0. The estimator is the large-sample covariance of
+ * the MBAR estimate (Shirts and Chodera, J. Chem. Phys. 129, 124105 (2008)),
+ *   Theta = W^T (I_N - W diag(N_k) W^T)^+ W,  W_nk = exp(f_k - u_kn - ln D_n),
+ *   Cov(f_i, f_j) = (e_i - e_0)^T Theta (e_j - e_0);
+ * the paper cites uncertainty estimates as related work (Section 1). It is
+ * evaluated as K x K algebra: W^T W by the FP64 matrix cores (the Newton
+ * Hessian's contraction), then a Cholesky solve with the reduced Hessian of
+ * the sampled states. Unsampled states get their covariances too. u_kn is
+ * state-major (row stride ld, FP64 or FP32), f the converged solution (e.g.
+ * from bumbar_solve; ln D_n is recomputed from it). Workspace:
+ * bumbar_query_workspace_covariance bytes. Synchronises. EINVAL if the
+ * reduced Hessian is not positive definite (sampled states without overlap).
+ */
+int bumbar_query_workspace_covariance(const bumbar_ctx* ctx, int K, int64_t N, size_t* bytes);
+int bumbar_covariance(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                      int64_t ld, const int64_t* N_k, const double* f, void* workspace,
+                      size_t ws_bytes, double* cov);
+
 /* ---- single steps (the kernels of the solve, exposed for testing) ------ */
 
 /*

@@ -17,7 +17,7 @@ from ._capi import (EBUSY, EDEVICE, EINVAL, ENOMEM, ENOTCONV, ETOOBIG, F32, F64,
                     PREC_FP64, PREC_MIXED, REPRESENT_AUTO, REPRESENT_CENTRE, REPRESENT_MEAN)
 
 __all__ = ["Context", "solve", "plan", "sweep", "sample_major", "SampleMajor", "hessian", "weights", "bin_coordinates", "reweight", "pmf",
-           "model_energies", "sweep_model", "hessian_model", "Server",
+           "model_energies", "sweep_model", "hessian_model", "Server", "covariance",
            "BumbarError", "default_options"]
 
 
@@ -328,6 +328,30 @@ def hessian(u, Nk, f, logD, S, ctx=None):
     ctx.check(rc)
     _keep(ctx, Nk_t, f_t)
     return H
+
+
+def covariance(u, Nk, f, ctx=None):
+    """K x K asymptotic covariance of f at the solution f (gauge f_0 = 0), on the device."""
+    torch = _torch()
+    ctx = ctx or context()
+    if not (torch.is_tensor(u) and u.is_cuda):
+        u = torch.as_tensor(u)
+    dev = torch.device(f"cuda:{ctx.device}")
+    u = u.to(dev)
+    if u.stride(1) != 1:
+        u = u.contiguous()
+    K, N = u.shape
+    nb = C.c_size_t()
+    ctx.check(ctx.lib.bumbar_query_workspace_covariance(ctx.h, K, N, C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    cov = torch.empty((K, K), dtype=torch.float64, device=dev)
+    Nk_t = _dev(Nk, torch.int64, dev)
+    f_t = _dev(f, torch.float64, dev)
+    rc = ctx.lib.bumbar_covariance(ctx.h, _ptr(u), _dtype_code(u), K, N, u.stride(0), _ptr(Nk_t),
+                                   _ptr(f_t), _ptr(ws), ws.numel(), _ptr(cov))
+    _keep(ctx, Nk_t, f_t, u)
+    ctx.check(rc)
+    return cov
 
 
 def weights(u, f, logD, ctx=None):

@@ -121,6 +121,10 @@ SIGNATURES = {
                                C.c_size_t, vp, vp, vp, dp]),
     "bumbar_hessian": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp, vp,
                                  vp, C.c_size_t, vp]),
+    "bumbar_query_workspace_covariance": (C.c_int, [vp, C.c_int, C.c_int64,
+                                                    C.POINTER(C.c_size_t)]),
+    "bumbar_covariance": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,
+                                    C.c_size_t, vp]),
     "bumbar_sample_major_elems": (C.c_int64, [C.c_int, C.c_int64]),
     "bumbar_sample_major": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp]),
     "bumbar_weights": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp]),

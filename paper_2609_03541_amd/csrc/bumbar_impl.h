@@ -224,6 +224,20 @@ int newton_lds_max_m();
 // (m entries, the kept states) must be on the device; A holds
 // newton_ws_doubles(K) doubles.
 size_t newton_ws_doubles(int K);
+// Blocked Cholesky A = L L^T of an SPD m x m matrix in place (A then holds L
+// below the diagonal blocks' diagonals, Linv the inverses of the 64 x 64
+// diagonal blocks) and y = L^{-1} b; *ok = 0 on a pivot that is not positive.
+hipError_t launch_chol_factor_blocked(hipStream_t s, int m, double* A, double* b, double* y,
+                                     double* Linv, int* ok);
+// Asymptotic covariance of f (covariance.hip).
+hipError_t launch_cov_consts(hipStream_t s, int K, const double* f, double* cst, double* gk,
+                             double* S);
+hipError_t launch_cov_gather(hipStream_t s, int K, int m, const int* idx, const int64_t* Nk,
+                             const double* Mneg, double* A, double* b, double* Bm);
+hipError_t launch_cov_solve(hipStream_t s, int m, int K, const double* A, const double* Linv,
+                            double* Bm);
+hipError_t launch_cov_theta(hipStream_t s, int m, int K, const double* Z, const double* Mneg,
+                            double* Th, double* cov);
 hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
                                            const double* H, const double* S, double* A,
                                            const int* idx, double* d, int* ok);

@@ -544,16 +544,9 @@ size_t newton_ws_doubles(int K) {
   return (size_t)K * K + 3 * (size_t)K + (size_t)((K + CB - 1) / CB) * CB * CB;
 }
 
-hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
-                                           const double* H, const double* S, double* A,
-                                           const int* idx, double* d, int* ok) {
-  if (m <= 0 || m >= K) return hipErrorInvalidValue;
-  double* b = A + (int64_t)m * m;
-  double* y = b + m;
-  double* Linv = y + m;
-  const int64_t tot = std::max<int64_t>((int64_t)m * m, K);
-  hipLaunchKernelGGL(reduced_gather_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     K, m, idx, H, S, Nk, A, b, d);
+hipError_t launch_chol_factor_blocked(hipStream_t s, int m, double* A, double* b, double* y,
+                                     double* Linv, int* ok) {
+  if (m <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(set_ok_kernel, dim3(1), dim3(1), 0, s, ok);
   const size_t step_lds = sizeof(double) * (3 * CB * CBP + 2 * CB);
   static const bool attr = [&] {
@@ -573,6 +566,21 @@ hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const in
   }
   if (T > 1)
     hipLaunchKernelGGL(chol_mirror_kernel, dim3(T * (T - 1) / 2), dim3(CT), 0, s, m, A, ok);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_direction_blocked(hipStream_t s, int K, int m, const int64_t* Nk,
+                                           const double* H, const double* S, double* A,
+                                           const int* idx, double* d, int* ok) {
+  if (m <= 0 || m >= K) return hipErrorInvalidValue;
+  double* b = A + (int64_t)m * m;
+  double* y = b + m;
+  double* Linv = y + m;
+  const int64_t tot = std::max<int64_t>((int64_t)m * m, K);
+  hipLaunchKernelGGL(reduced_gather_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     K, m, idx, H, S, Nk, A, b, d);
+  const hipError_t e = launch_chol_factor_blocked(s, m, A, b, y, Linv, ok);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(chol_back_kernel, dim3(1), dim3(BT), 0, s, m, A, y, Linv, b, idx, d, ok);
   return hipGetLastError();
 }

@@ -656,6 +656,88 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   return BUMBAR_OK;
 }
 
+static void carve_cov(Arena& ar, UnbinnedBufs& B, int K, int64_t N, int num_cus, double** Th,
+                      double** Bm) {
+  B.carve(ar, K, N, num_cus);
+  *Th = ar.take<double>((size_t)K * K);
+  *Bm = ar.take<double>((size_t)K * K);
+}
+
+int bumbar_query_workspace_covariance(const bumbar_ctx* ctx, int K, int64_t N, size_t* bytes) {
+  if (!ctx || !bytes || K <= 0 || N <= 0) return BUMBAR_EINVAL;
+  Arena ar;
+  UnbinnedBufs B;
+  double *Th, *Bm;
+  carve_cov(ar, B, K, N, ctx->num_cus, &Th, &Bm);
+  *bytes = ar.off + 256;
+  return BUMBAR_OK;
+}
+
+int bumbar_covariance(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                      int64_t ld, const int64_t* N_k, const double* f, void* workspace,
+                      size_t ws_bytes, double* cov) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (!N_k || !f || !cov || !workspace) return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  std::vector<int64_t> nk(K);
+  rc = read_bytes(ctx, N_k, nk.data(), sizeof(int64_t) * K);
+  if (rc) return rc;
+  int64_t tot = 0;
+  std::vector<int> kept;  // sampled states but the first: the reduced system
+  for (int k = 0, first = 1; k < K; ++k) {
+    if (nk[k] < 0) return fail(ctx, BUMBAR_EINVAL, "negative N_k");
+    tot += nk[k];
+    if (nk[k] > 0) {
+      if (!first) kept.push_back(k);
+      first = 0;
+    }
+  }
+  if (tot != N) return fail(ctx, BUMBAR_EINVAL, "sum of N_k (%lld) != N (%lld)", (long long)tot,
+                            (long long)N);
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  UnbinnedBufs B;
+  double *Th, *Bm;
+  carve_cov(ar, B, K, N, ctx->num_cus, &Th, &Bm);
+  if (ar.overflow)
+    return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes, need %zu)", ws_bytes, ar.off);
+  hipStream_t s = ctx->stream;
+  // ln D_n at f by one unbinned sweep
+  Mat M = input_mat(u_kn, u_dtype, ld);
+  SweepScalars sc{};
+  rc = sweep_at(ctx, B, M, N, nullptr, N_k, f, B.f_new, B.logD, B.lnS, B.S, &sc, false, nullptr);
+  if (rc) return rc;
+  // -M = -W^T W from the Hessian contraction with P = W
+  hipError_t e = launch_cov_consts(s, K, f, B.cst, B.gk, B.S);
+  HessSource hs;
+  hs.kind = M.kind;
+  hs.u = u_kn;
+  hs.ld = ld;
+  if (e == hipSuccess)
+    e = launch_hessian(s, hs, K, N, B.cst, B.gk, B.logD, B.S, B.hess_parts, B.hess_chunks, B.H);
+  const int m = (int)kept.size();
+  double* b = B.A + (int64_t)m * m;
+  double* y = b + m;
+  double* Linv = y + m;
+  if (e == hipSuccess && m > 0)
+    e = hipMemcpyAsync(B.idx, kept.data(), sizeof(int) * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m > 0) e = launch_cov_gather(s, K, m, B.idx, N_k, B.H, B.A, b, Bm);
+  if (e == hipSuccess && m > 0) e = launch_chol_factor_blocked(s, m, B.A, b, y, Linv, B.ok);
+  if (e != hipSuccess) return hip_fail(ctx, e, "covariance");
+  if (m > 0) {
+    int ok = 0;
+    rc = read_bytes(ctx, B.ok, &ok, sizeof(int));
+    if (rc) return rc;
+    if (!ok)
+      return fail(ctx, BUMBAR_EINVAL,
+                  "the reduced Hessian is not positive definite (states without overlap)");
+    e = launch_cov_solve(s, m, K, B.A, Linv, Bm);
+  }
+  if (e == hipSuccess) e = launch_cov_theta(s, m, K, Bm, B.H, Th, cov);
+  if (e == hipSuccess) e = ctx_wait(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "covariance");
+  return BUMBAR_OK;
+}
+
 // Product-grid detection for the 2-D harmonic model (host side, once per
 // call): the distinct (kappa_x / 2, x0) and (kappa_y / 2, y0) pairs of the K
 // states. The factored FP64 sweep is used when each axis has at most kSepMax
