@@ -103,6 +103,7 @@ def main():
                              "scaling"],
                     default="all")
     ap.add_argument("--n-problems", type=int, default=512)
+    ap.add_argument("--seeds", type=int, default=12, help="seeds per point of the scaling study")
     ap.add_argument("--rate", type=float, default=100.0, help="stream arrivals per second")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
@@ -594,12 +595,17 @@ def _avg_sweep_s(infos):
     return ms / max(1, n) / 1e3, n
 
 
+def _library_version():
+    from paper_2609_03541_amd import _capi
+    return _capi.load().bumbar_version().decode()
+
+
 def _base_line(args, value, unit, ms, dtype, config):
     return {
         "metric": "sweep K*N elem/s + time-to-solve at 1e-6 kT; batched solves/s, p50/p99",
         "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": dtype, "data": "synthetic", "config": config,
+        "dtype": dtype, "data": "synthetic", "config": config, "library": _library_version(),
     }
 
 
@@ -709,55 +715,82 @@ def run_tladder(args, bm, synth):
     print(json.dumps(out), flush=True)
 
 
+# The replica-count study of Section 4 (Fig. 3): scenario name, N0, power p
+# with N_k = N0 / M^p; seeds 9000 + 100 M + 10 scenario + s (the same recipe
+# tests/golden/make_golden.py gives the oracle).
+FIG3 = (("i", 1e4, 0), ("ii", 3e6, 1), ("iii", 9e8, 2))
+
+
 def run_scaling(args, bm, synth):
     import torch
     ctx = bm.context()
-    scen = {"i": (1e4, 0), "ii": (3e6, 1), "iii": (9e8, 2)}  # N_k = N0 / M^power
+    gold = _golden("fig3_replicas_full_small")
+    gmap = {}
+    if gold is not None:
+        gmap = {(it["scenario"], it["M"], it["seed"]): np.asarray(it["f"])
+                for it in gold["problems"]}
     table = []
     top = None
-    for M in (10, 30, 100, 300):
-        for sname, (n0, pw) in scen.items():
+    for si, (sname, n0, pw) in enumerate(FIG3):
+        for M in (10, 30, 100, 300):
             nk = int(round(n0 / M ** pw))
-            p = synth.temperature_ladder(K=M, Nk=nk, seed=11 + M, materialize=False)
-            K, N = p["K"], p["N"]
-            xi = torch.tensor(p["xi"], device="cuda")
-            coef = torch.tensor(p["coef"], device="cuda")
-            u = bm.model_energies(xi, coef, bm.MODEL_LINEAR, K)
-            Nk = torch.tensor(p["Nk"], device="cuda")
-            torch.cuda.synchronize()
-            variants = {
-                "bumbar": dict(xi=xi, model=bm.MODEL_LINEAR, coef=coef),
-                "newton": dict(binning=False, finisher=bm.FINISH_NEWTON, sci_switch=1e300),
-            }
-            if M <= 100:
-                variants["sci"] = dict(binning=False, finisher=bm.FINISH_SCI, max_iter=20000)
-            row = {"M": M, "scenario": sname, "N_k": nk, "N": N}
-            fs = {}
-            for name, kw in variants.items():
-                f, infos, ms = _timed_solves(
-                    bm, args, f"M={M} {sname} {name}",
-                    lambda prof, kw=kw: bm.solve(u, Nk, tol=args.tol, profile=int(prof), ctx=ctx,
-                                                 **kw))
-                fs[name] = f.cpu().numpy()
-                row[name + "_ms"] = ms
-                row[name + "_status"] = infos[-1]["status"]
-                if name == "bumbar":
-                    sw, _ = _avg_sweep_s(infos)
-                    row["sweep_us"] = sw * 1e6
-            row["max_abs_diff_newton_vs_bumbar_kT"] = float(np.max(np.abs(fs["newton"] -
-                                                                          fs["bumbar"])))
+            times = {"bumbar": [], "newton": [], "sci": []}
+            errs, diffs, sweeps = [], [], []
+            for s in range(args.seeds):
+                seed = 9000 + 100 * M + 10 * si + s
+                p = synth.temperature_ladder(K=M, Nk=nk, seed=seed, materialize=False)
+                K, N = p["K"], p["N"]
+                xi = torch.tensor(p["xi"], device="cuda")
+                coef = torch.tensor(p["coef"], device="cuda")
+                u = bm.model_energies(xi, coef, bm.MODEL_LINEAR, K)
+                Nk = torch.tensor(p["Nk"], device="cuda")
+                torch.cuda.synchronize()
+                variants = {
+                    "bumbar": dict(xi=xi, model=bm.MODEL_LINEAR, coef=coef, profile=1),
+                    "newton": dict(binning=False, finisher=bm.FINISH_NEWTON, sci_switch=1e300),
+                }
+                if s == 0 and M <= 100:
+                    variants["sci"] = dict(binning=False, finisher=bm.FINISH_SCI, max_iter=20000)
+                fs = {}
+                for name, kw in variants.items():
+                    if s == 0:  # untimed first solve of this shape
+                        bm.solve(u, Nk, tol=args.tol, ctx=ctx, **kw)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    f, info = bm.solve(u, Nk, tol=args.tol, ctx=ctx, **kw)
+                    torch.cuda.synchronize()
+                    times[name].append((time.perf_counter() - t0) * 1e3)
+                    fs[name] = f.cpu().numpy()
+                    if name == "bumbar":
+                        sw, _ = _avg_sweep_s([info])
+                        sweeps.append(sw)
+                diffs.append(float(np.max(np.abs(fs["newton"] - fs["bumbar"]))))
+                g = gmap.get((sname, M, seed))
+                if g is not None:
+                    errs.append(max(float(np.max(np.abs(fs[v] - g))) for v in ("bumbar", "newton")))
+                del u, xi, coef, Nk
+            row = {"M": M, "scenario": sname, "N_k": nk, "N": M * nk, "seeds": args.seeds}
+            for name, ts in times.items():
+                if ts:
+                    row[name + "_ms_mean"] = float(np.mean(ts))
+                    row[name + "_ms_sd"] = float(np.std(ts, ddof=1)) if len(ts) > 1 else 0.0
+                    row[name + "_seeds"] = len(ts)
+            row["sweep_us_mean"] = float(np.mean(sweeps)) * 1e6
+            row["max_abs_diff_newton_vs_bumbar_kT"] = max(diffs)
+            row["max_err_vs_oracle_kT"] = max(errs) if errs else None
+            row["oracle_checked_seeds"] = len(errs)
             table.append(row)
             log(json.dumps(row))
             if M == 300 and sname == "i":
-                top = (K, N, row)
-            del u, xi, coef, Nk
+                top = (M, M * nk, row)
             torch.cuda.empty_cache()
     K, N, row = top
-    sw = row["sweep_us"] / 1e6
+    sw = row["sweep_us_mean"] / 1e6
     achieved = 8.0 * K * N / sw / 1e9
-    out = _base_line(args, K * N / sw, "elem/s", row["bumbar_ms"], "f64", {
-        "workload": "replica-count scaling: temperature ladders M = 10, 30, 100, 300, "
-                    "N_k = 1e4, 3e6/M, 9e8/M^2; BU-MBAR vs plain Newton vs plain SCI; "
+    out = _base_line(args, K * N / sw, "elem/s", row["bumbar_ms_mean"], "f64", {
+        "workload": "replica-count study: temperature ladders M = 10, 30, 100, 300 at 80% "
+                    "neighbour overlap, N_k = 1e4, 3e6/M, 9e8/M^2, "
+                    f"{args.seeds} seeds each; BU-MBAR vs plain Newton vs plain SCI (seed 0); "
                     "value and roofline from M=300, N_k=1e4 (u 300x3e6 FP64)",
         "tol_kT": args.tol})
     out.update({

@@ -182,7 +182,9 @@ int bumbar_create(bumbar_ctx** out, int device, void* hip_stream);
 void bumbar_destroy(bumbar_ctx* ctx);
 /* Message of the last failed call on ctx (never NULL; "" if none). */
 const char* bumbar_last_error(const bumbar_ctx* ctx);
-/* Library version string. */
+/* Library version string, "bumbar-gfx950 <version> src:<h>", where h is the
+ * first 16 hex digits of the SHA-256 of the library's sources, this header
+ * and the compiler flags it was built from. */
 const char* bumbar_version(void);
 
 /* Defaults: the paper's settings n0 = 100, eps = 1e-3, inc = 10,

@@ -1,6 +1,7 @@
 """Build libbumbar.so (HIP for gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -22,17 +23,34 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of every source file, the public header and
+    the compiler flags: bumbar_version() of a library built from this tree ends
+    with it, which ties a built libbumbar.so to the sources it came from."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for name in files:
+        h.update(name.encode() + b"\0")
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read() + b"\0")
+    with open(os.path.join(ROOT, "include", "bumbar.h"), "rb") as fh:
+        h.update(fh.read() + b"\0")
+    h.update(" ".join(FLAGS[:6]).encode())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source to an object (in parallel) and link the shared library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
+    stamp = f'-DBUMBAR_SOURCE_HASH="{source_hash()}"'
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        cmd = ["hipcc", "-x", "hip", *FLAGS, "-c", path, "-o", obj]
+        cmd = ["hipcc", "-x", "hip", *FLAGS, stamp, "-c", path, "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:

@@ -488,7 +488,10 @@ int sci_until(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, const int64_t* Nk,
 // ===========================================================================
 extern "C" {
 
-const char* bumbar_version(void) { return "bumbar-gfx950 0.1"; }
+#ifndef BUMBAR_SOURCE_HASH
+#define BUMBAR_SOURCE_HASH "unknown"
+#endif
+const char* bumbar_version(void) { return "bumbar-gfx950 0.2 src:" BUMBAR_SOURCE_HASH; }
 
 int bumbar_create(bumbar_ctx** out, int device, void* hip_stream) {
   if (!out) return BUMBAR_EINVAL;

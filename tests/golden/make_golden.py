@@ -14,7 +14,7 @@ with no input from the GPU library:
   3. certification: the full Newton step below 1e-13 kT and the fixed-point
      residual max |SCI(f) - f| below 1e-12 kT, both recorded.
 
-Usage: python tests/golden/make_golden.py {c1,c2,tladder,c4r,c3sub} ...
+Usage: python tests/golden/make_golden.py {c1,c2,tladder,c4r,c3sub,fig3r,fig3} ...
 Inputs are the seeded generators of synth (the same recipes the GPU tests and
 the benchmark use). Output: tests/golden/<name>.json.
 """
@@ -184,8 +184,55 @@ def run_c3sub():
     say("wrote", path)
 
 
+# The replica-count study of Section 4 (Fig. 3): temperature ladders of M
+# replicas with unit-variance energy histograms at 80% neighbour overlap and
+# N_k = N0 / M^p per replica, scenario i (p = 0, N0 = 1e4), ii (p = 1,
+# N0 = 3e6), iii (p = 2, N0 = 9e8), M in {10, 30, 100, 300}, 12 seeds each.
+FIG3_SCENARIOS = (("i", 1e4, 0), ("ii", 3e6, 1), ("iii", 9e8, 2))
+FIG3_M = (10, 30, 100, 300)
+
+
+def fig3_seed(M, si, s):
+    return 9000 + 100 * M + 10 * si + s
+
+
+def fig3_problems(scale):
+    """(scenario, M, N_k, seed) of the study with every N0 multiplied by scale."""
+    out = []
+    for si, (name, n0, pw) in enumerate(FIG3_SCENARIOS):
+        for M in FIG3_M:
+            nk = int(round(n0 * scale / M ** pw))
+            for s in range(12):
+                out.append((name, M, nk, fig3_seed(M, si, s)))
+    return out
+
+
+def run_fig3(scale, name, max_elems):
+    items = []
+    for scen, M, nk, seed in fig3_problems(scale):
+        if M * M * nk > max_elems:
+            continue
+        p = synth.temperature_ladder(K=M, Nk=nk, seed=seed)
+        say(f"fig3 {scen} M={M} N_k={nk} seed={seed}")
+        f, cert = solve_golden(p["u"], p["Nk"], p["xi"], p["model_type"], p["coef"],
+                               chunk=200_000)
+        items.append(dict(scenario=scen, M=M, Nk=nk, seed=seed, f=[float(v) for v in f],
+                          certificate=cert))
+    path = os.path.join(HERE, name + ".json")
+    with open(path, "w") as fh:
+        json.dump(dict(name=name,
+                       recipe=f"synth.temperature_ladder(K=M, Nk=round(N0 * {scale:g} / M^p), "
+                              f"seed=9000 + 100 M + 10 scenario + s), s = 0..11, "
+                              f"M * M * Nk <= {max_elems:g}",
+                       problems=items, threads=os.cpu_count(),
+                       made_by="tests/golden/make_golden.py (oracle and synth only)"), fh)
+    say("wrote", path)
+
+
 if __name__ == "__main__":
     oracle.build()
-    jobs = dict(c1=run_c1, c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub)
+    jobs = dict(c1=run_c1, c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub,
+                fig3r=lambda: run_fig3(0.01, "fig3_replicas_reduced", 1e12),
+                fig3=lambda: run_fig3(1.0, "fig3_replicas_full_small", 3e7))
     for name in sys.argv[1:] or list(jobs):
         jobs[name]()

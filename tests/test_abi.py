@@ -46,6 +46,13 @@ def test_default_options_are_the_papers_settings(lib):
     assert o.tol > 0 and o.finisher == _capi.FINISH_NEWTON
 
 
+def test_library_was_built_from_this_tree(lib):
+    # bumbar_version ends with the hash of the sources, header and flags
+    from paper_2609_03541_amd.build import source_hash
+    v = lib.bumbar_version().decode()
+    assert v.endswith("src:" + source_hash()), (v, source_hash())
+
+
 def test_version_and_null_context(lib):
     from paper_2609_03541_amd import _capi
     assert lib.bumbar_version().decode().startswith("bumbar")
