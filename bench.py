@@ -874,22 +874,31 @@ def _gen_problem(spec):
     return {k: p[k] for k in ("K", "N", "Nk", "xi", "coef", "model_type")}
 
 
-def _serve(bm, probs, arrivals, max_active, budget, opts):
-    """Submit the problems at their arrival times; returns (results, wall s, counters)."""
-    srv = bm.Server(hbm_budget_bytes=budget, max_active=max_active)
+def _serve(bm, probs, arrivals, max_active, budget, opts, caller_driven=False):
+    """Submit the problems at their arrival times; returns (results, wall s, counters).
+
+    caller_driven: the server has no worker threads; this loop ticks it
+    (progress) between arrivals."""
+    srv = bm.Server(hbm_budget_bytes=budget, max_active=max_active, caller_driven=caller_driven)
     try:
         t0 = time.perf_counter()
         tickets = []
+        done = 0
         for p, ta in zip(probs, arrivals):
-            dt = t0 + ta - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
+            while True:
+                dt = t0 + ta - time.perf_counter()
+                if dt <= 0:
+                    break
+                if caller_driven:
+                    done += srv.progress()
+                else:
+                    time.sleep(dt)
             tickets.append(srv.submit(p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"],
                                       **opts))
         res = []
         for i, t in enumerate(tickets):
             res.append(srv.result(t))
-            if (i + 1) % 16 == 0:
+            if (i + 1) % 64 == 0:
                 log(f"  {i + 1}/{len(tickets)} results")
         wall = time.perf_counter() - t0
         return res, wall, srv.counters()

@@ -82,11 +82,12 @@ extern "C" {
 #define BUMBAR_REPRESENT_MEAN 2
 
 /* Kernels of the FP64 unbinned sweeps (bumbar_plan.sweep). */
-#define BUMBAR_SWEEP_REGISTER 0     /* FP64 u, K <= 256: register-tiled single pass    */
+#define BUMBAR_SWEEP_REGISTER 0     /* K <= 256: register-tiled single pass (FP32 u
+                                       widened on load)                                 */
 #define BUMBAR_SWEEP_SAMPLE_MAJOR 1 /* 256 < K <= 1024: single pass over a sample-major
                                        copy of u in the workspace                       */
-#define BUMBAR_SWEEP_TWO_PASS 2     /* two passes over the state-major u (FP32 u with
-                                       K <= 256, K > 1024, or the copy switched off)    */
+#define BUMBAR_SWEEP_TWO_PASS 2     /* two passes over the state-major u (K > 1024, or
+                                       the copy switched off)                           */
 #define BUMBAR_SWEEP_MODEL 3        /* energies from the model inside the kernels       */
 /* The FP32 Newton stage of BUMBAR_PREC_MIXED (bumbar_plan.stage32). */
 #define BUMBAR_STAGE32_NONE 0
@@ -501,10 +502,12 @@ int bumbar_server_progress(bumbar_server* srv, int* n_done);
  * has not finished (it is then kept). */
 int bumbar_server_result(bumbar_server* srv, uint64_t ticket, double* f_k_host,
                          bumbar_stats* stats, double* latency_ms, int* status);
-/* Counters: completed requests, largest number of problems on the device
- * at once, largest arena use in bytes. */
+/* Counters (each pointer may be NULL): completed requests, largest number
+ * of problems on the device at once, largest arena use in bytes, and the
+ * requests that had to wait at the head of the queue, with a slot free,
+ * until enough of the arena was released (admission bound by memory). */
 int bumbar_server_counters(bumbar_server* srv, int64_t* completed, int64_t* peak_active,
-                           size_t* peak_bytes);
+                           size_t* peak_bytes, int64_t* mem_waits);
 /* Let running requests finish, fail the ones still queued (status
  * BUMBAR_EBUSY), stop the slots and release the arena. */
 void bumbar_server_destroy(bumbar_server* srv);

@@ -654,9 +654,10 @@ class Server:
         return f, info
 
     def counters(self):
-        c, a, b = C.c_int64(), C.c_int64(), C.c_size_t()
-        self.lib.bumbar_server_counters(self.h, C.byref(c), C.byref(a), C.byref(b))
-        return dict(completed=c.value, peak_active=a.value, peak_bytes=b.value)
+        c, a, b, w = C.c_int64(), C.c_int64(), C.c_size_t(), C.c_int64()
+        self.lib.bumbar_server_counters(self.h, C.byref(c), C.byref(a), C.byref(b), C.byref(w))
+        return dict(completed=c.value, peak_active=a.value, peak_bytes=b.value,
+                    mem_waits=w.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -151,7 +151,7 @@ SIGNATURES = {
     "bumbar_server_progress": (C.c_int, [vp, C.POINTER(C.c_int)]),
     "bumbar_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(Stats), dp,
                                        C.POINTER(C.c_int)]),
-    "bumbar_server_counters": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_size_t)]),
+    "bumbar_server_counters": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_size_t), i64p]),
     "bumbar_server_destroy": (None, [vp]),
 }
 

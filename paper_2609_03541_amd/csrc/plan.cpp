@@ -71,7 +71,7 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
   if (otf)
     p->sweep = BUMBAR_SWEEP_MODEL;
   else if (sweep_fast_supported(K))
-    p->sweep = f32 ? BUMBAR_SWEEP_TWO_PASS : BUMBAR_SWEEP_REGISTER;
+    p->sweep = BUMBAR_SWEEP_REGISTER;
   else if (sweep_smaj_supported(K) && opt.sample_major)
     p->sweep = BUMBAR_SWEEP_SAMPLE_MAJOR;
   else

@@ -104,6 +104,7 @@ struct Job {
   Clock::time_point t_submit, t_done;
   int state = BUMBAR_TICKET_QUEUED;
   int status = BUMBAR_OK;
+  bool mem_waited = false;  // was first in line with a slot free but no room in the arena
   std::vector<double> f;
   bumbar_stats stats{};
 };
@@ -145,6 +146,7 @@ struct bumbar_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   int64_t active = 0, peak_active = 0, completed = 0;
+  int64_t mem_waits = 0;  // requests that waited at the head of the queue for arena room
   // workspace sizing uses a context that is never used for work
   bumbar_ctx* sizing_ctx = nullptr;
 };
@@ -243,6 +245,18 @@ void run_job(bumbar_ctx* ctx, hipStream_t stream, char* base, Job& job) {
   if (e != hipSuccess && job.status == BUMBAR_OK) job.status = BUMBAR_EDEVICE;
 }
 
+// Takes an arena block for the request at the head of the queue; a request
+// that finds a free slot but no room is counted once (caller holds srv->mu).
+bool alloc_front_locked(bumbar_server* srv, size_t* off) {
+  Job& front = *srv->queue.front();
+  if (srv->alloc->alloc(front.footprint, off)) return true;
+  if (!front.mem_waited) {
+    front.mem_waited = true;
+    srv->mem_waits++;
+  }
+  return false;
+}
+
 // Marks a job finished and returns its arena block (caller holds srv->mu).
 void finish_locked(bumbar_server* srv, Job& job, size_t off) {
   srv->alloc->release(off, job.footprint);
@@ -272,7 +286,7 @@ void worker_main(bumbar_server* srv, Slot* sl) {
       srv->cv_admit.wait(lk, [&] {
         if (srv->stop) return true;
         if (srv->queue.empty()) return false;
-        return srv->alloc->alloc(srv->queue.front()->footprint, &off);
+        return alloc_front_locked(srv, &off);
       });
       if (srv->stop && srv->queue.empty()) break;
       if (srv->stop) {
@@ -364,7 +378,7 @@ void admit(bumbar_server* srv) {
     if (sl.job) continue;
     if (srv->queue.empty()) break;
     size_t off = 0;
-    if (!srv->alloc->alloc(srv->queue.front()->footprint, &off)) break;
+    if (!alloc_front_locked(srv, &off)) break;
     sl.job = srv->queue.front();
     srv->queue.pop_front();
     sl.off = off;
@@ -567,12 +581,13 @@ int bumbar_server_result(bumbar_server* srv, uint64_t ticket, double* f_k_host,
 }
 
 int bumbar_server_counters(bumbar_server* srv, int64_t* completed, int64_t* peak_active,
-                           size_t* peak_bytes) {
+                           size_t* peak_bytes, int64_t* mem_waits) {
   if (!srv) return BUMBAR_EINVAL;
   std::lock_guard<std::mutex> lk(srv->mu);
   if (completed) *completed = srv->completed;
   if (peak_active) *peak_active = srv->peak_active;
   if (peak_bytes) *peak_bytes = srv->alloc->peak();
+  if (mem_waits) *mem_waits = srv->mem_waits;
   return BUMBAR_OK;
 }
 

@@ -167,10 +167,10 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, h, logD_out, B.part,
                          (size_t)B.nparts_cap * K, B.part_obj, B.part_flags, ctx->num_cus, &grid);
-  } else if (M.kind == 0 && sweep_fast_supported(K)) {
+  } else if ((M.kind == 0 || M.kind == 1) && sweep_fast_supported(K)) {
     if (ev) (void)hipEventRecord(ev->first, s);
-    e = launch_sweep_fast(s, reinterpret_cast<const double*>(M.u), M.ld, K, N, B.cst, B.gk, h,
-                          logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
+    e = launch_sweep_fast(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
+                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_wide(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
@@ -620,7 +620,7 @@ int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   double* Sv = S ? S : B.S;
   SweepScalars sc{};
   const Mat M = input_mat(u_kn, u_dtype, ld);
-  if (sweep_stats == nullptr && ((M.kind == 0 && sweep_fast_supported(K)) || M.ut)) {
+  if (sweep_stats == nullptr && ((M.kind <= 1 && sweep_fast_supported(K)) || M.ut)) {
     // asynchronous: queue the sweep without reading anything back (the caller
     // accepts that a far-off f is not rerun on the robust path)
     return sweep_queue(ctx, B, M, N, nullptr, N_k, f, f_new, logD, B.lnS, Sv, B.scal);

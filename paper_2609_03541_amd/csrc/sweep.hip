@@ -23,6 +23,7 @@
 // robust two-pass path, which keeps an exact per-state log-sum-exp.
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -44,6 +45,7 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl
 // takes a separate guarded path.
 // ---------------------------------------------------------------------------
 typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 template <int NW, int LPR, int CPL, int ROWS>
 struct SweepTile {
@@ -58,8 +60,8 @@ struct SweepTile {
 // zeroed). The row offsets are opaque to the compiler so every load is
 // unconditional: no branch and no reuse of another row's value, hence no wait
 // on an earlier load before the next is issued.
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool TAIL>
-__device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const double* __restrict__ rowp,
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool TAIL, typename TI>
+__device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const TI* __restrict__ rowp,
                                           int64_t rstride, int rows_here, int64_t t, int64_t N,
                                           int lc) {
   constexpr int TN = SweepTile<NW, LPR, CPL, ROWS>::TN;
@@ -68,20 +70,27 @@ __device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const double* 
   for (int j = 0; j < ROWS; ++j) {
     int64_t roff = (int64_t)(j < rows_here ? j : (rows_here > 0 ? rows_here - 1 : 0)) * rstride;
     asm volatile("" : "+v"(roff));
-    const double* p = rowp + roff + t * TN;
+    const TI* p = rowp + roff + t * TN;
     if constexpr (!TAIL && VEC && CPL == 2) {
-      // u is streamed once per sweep: non-temporal loads (c1 sweep 181 -> 171 us)
-      const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
-      a[j][0] = v.x;
-      a[j][1] = v.y;
+      // u is streamed once per sweep: non-temporal loads (c1 sweep 181 -> 171 us);
+      // FP32 storage is widened exactly on load
+      if constexpr (std::is_same<TI, double>::value) {
+        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+        a[j][0] = v.x;
+        a[j][1] = v.y;
+      } else {
+        const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+        a[j][0] = (double)v.x;
+        a[j][1] = (double)v.y;
+      }
     } else if constexpr (!TAIL) {
 #pragma unroll
-      for (int i = 0; i < CPL; ++i) a[j][i] = p[i];
+      for (int i = 0; i < CPL; ++i) a[j][i] = (double)p[i];
     } else {
 #pragma unroll
       for (int i = 0; i < CPL; ++i) {
         const int64_t off = (col0 + i < N) ? (int64_t)i : (N - 1 - col0);
-        a[j][i] = p[off];
+        a[j][i] = (double)p[off];
       }
     }
   }
@@ -215,8 +224,8 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
 // are issued into a second register buffer before the current tile is
 // processed (software prefetch), so HBM traffic overlaps the arithmetic.
 // Successive tiles use alternating copies (par) of the reduction buffers.
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG>
-__device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64_t rstride,
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG, typename TI>
+__device__ __forceinline__ void tile_loop(const TI* __restrict__ base, int64_t rstride,
                                           int rows_here, int64_t nfull, int64_t N, int lc, int rg,
                                           int wave, int rgw, const double* __restrict__ c_sh,
                                           unsigned smask, const double* __restrict__ h,
@@ -229,23 +238,23 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
   if constexpr (!PF) {
     for (; t < nfull; t += G) {
       double a[ROWS][CPL];
-      tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
+      tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(a, base, rstride, rows_here, t, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
     }
   } else {
     double a[ROWS][CPL], b[ROWS][CPL];
-    if (t < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t, N, lc);
+    if (t < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(a, base, rstride, rows_here, t, N, lc);
     while (t < nfull) {
       const int64_t t1 = t + G;
-      if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(b, base, rstride, rows_here, t1, N, lc);
+      if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(b, base, rstride, rows_here, t1, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
       if (t1 >= nfull) break;
       const int64_t t2 = t1 + G;
-      if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false>(a, base, rstride, rows_here, t2, N, lc);
+      if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(a, base, rstride, rows_here, t2, N, lc);
       tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
@@ -254,9 +263,9 @@ __device__ __forceinline__ void tile_loop(const double* __restrict__ base, int64
   }
 }
 
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF, int SG>
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF, int SG, typename TI>
 __global__ void __launch_bounds__(NW * 64)
-    sweep_fast_kernel(const double* __restrict__ u, int64_t ld, int K, int64_t N,
+    sweep_fast_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                       int64_t ntiles, const double* __restrict__ cst,
                       const double* __restrict__ gk, const double* __restrict__ h,
                       double* __restrict__ logD, double* __restrict__ part,
@@ -293,7 +302,7 @@ __global__ void __launch_bounds__(NW * 64)
   // Pointer to this thread's first row (row 0 for a thread with no valid
   // row); its rows are RG apart. rows_here counts its rows below K.
   const int rows_here = (rg < K) ? (K - 1 - rg) / RG + 1 : 0;
-  const double* base = u + (int64_t)((rg < K) ? rg : 0) * ld + (int64_t)lc * CPL;
+  const TI* base = u + (int64_t)((rg < K) ? rg : 0) * ld + (int64_t)lc * CPL;
   const int64_t rstride = (int64_t)RG * ld;
   // any state with N_k = 0 among this block's rows? (uniform over the block)
   const unsigned valid_bits = (rows_here >= 32) ? 0xffffffffu : ((1u << rows_here) - 1u);
@@ -304,16 +313,16 @@ __global__ void __launch_bounds__(NW * 64)
   int par = 0;
   const int64_t nfull = N / TN;
   if (!masked)
-    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG>(base, rstride, rows_here, nfull, N, lc, rg, wave,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG, TI>(base, rstride, rows_here, nfull, N, lc, rg, wave,
                                                   rgw, c_sh, smask, h, logD, red1, red2, par, acc,
                                                   obj, bad);
   else
-    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1>(base, rstride, rows_here, nfull, N, lc, rg,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1, TI>(base, rstride, rows_here, nfull, N, lc, rg,
                                                     wave, rgw, c_sh, smask, h, logD, red1, red2,
                                                     par, acc, obj, bad);
   if (nfull < ntiles && blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     double a[ROWS][CPL];
-    tile_load<NW, LPR, CPL, ROWS, VEC, true>(a, base, rstride, rows_here, nfull, N, lc);
+    tile_load<NW, LPR, CPL, ROWS, VEC, true, TI>(a, base, rstride, rows_here, nfull, N, lc);
     tile_compute<NW, LPR, CPL, ROWS, true, true, 1>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                  logD, red1[par], red2[par], acc, obj, bad);
   }
@@ -375,15 +384,15 @@ bool sweep_fast_supported(int K) { return pick_cfg(K) != nullptr; }
 
 int sweep_max_grid(int num_cus) { return num_cus * 8; }
 
-template <int NW, int LPR, int CPL, int ROWS, int PF, int SG>
-static hipError_t launch_cfg(hipStream_t s, bool vec, const double* u, int64_t ld, int K,
+template <int NW, int LPR, int CPL, int ROWS, int PF, int SG, typename TI>
+static hipError_t launch_cfg(hipStream_t s, bool vec, const TI* u, int64_t ld, int K,
                              int64_t N, const double* cst, const double* gk, const double* h,
                              double* logD, double* part, double* part_obj, unsigned* pf,
                              int num_cus, int* grid_out) {
   constexpr int TN = LPR * CPL;
   const int64_t ntiles = (N + TN - 1) / TN;
-  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG>;
-  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG>;
+  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG, TI>;
+  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG, TI>;
   // resident workgroups per CU of this instantiation (queried once, thread-safe)
   static const int per_cu = [&] {
     int nb = 0;
@@ -405,17 +414,23 @@ static hipError_t launch_cfg(hipStream_t s, bool vec, const double* u, int64_t l
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_fast(hipStream_t s, const double* u, int64_t ld, int K, int64_t N,
-                             const double* cst, const double* gk, const double* h, double* logD,
-                             double* part, double* part_obj, unsigned* part_flags, int num_cus,
-                             int* grid_out) {
+hipError_t launch_sweep_fast(hipStream_t s, const void* u, bool f32, int64_t ld, int K,
+                             int64_t N, const double* cst, const double* gk, const double* h,
+                             double* logD, double* part, double* part_obj, unsigned* part_flags,
+                             int num_cus, int* grid_out) {
   const FastCfg* c = pick_cfg(K);
   if (!c) return hipErrorInvalidValue;
-  const bool vec = ((reinterpret_cast<uintptr_t>(u) & 15) == 0) && ((ld & 1) == 0);
-#define BUMBAR_CFG(a, b, cc, d, e, f)                                                          \
-  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e && c->sg == f)   \
-    return launch_cfg<a, b, cc, d, e, f>(s, vec, u, ld, K, N, cst, gk, h, logD, part, part_obj, \
-                                         part_flags, num_cus, grid_out);
+  // two columns per load: 16 bytes in FP64, 8 bytes in FP32
+  const uintptr_t al = f32 ? 7 : 15;
+  const bool vec = ((reinterpret_cast<uintptr_t>(u) & al) == 0) && ((ld & 1) == 0);
+  const double* ud = static_cast<const double*>(u);
+  const float* uf = static_cast<const float*>(u);
+#define BUMBAR_CFG(a, b, cc, d, e, f)                                                           \
+  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e && c->sg == f)    \
+    return f32 ? launch_cfg<a, b, cc, d, e, f>(s, vec, uf, ld, K, N, cst, gk, h, logD, part,    \
+                                               part_obj, part_flags, num_cus, grid_out)         \
+               : launch_cfg<a, b, cc, d, e, f>(s, vec, ud, ld, K, N, cst, gk, h, logD, part,    \
+                                               part_obj, part_flags, num_cus, grid_out);
   BUMBAR_CFG(4, 64, 2, 2, 1, 1)
   BUMBAR_CFG(4, 64, 2, 4, 1, 1)
   BUMBAR_CFG(4, 64, 2, 8, 1, 1)

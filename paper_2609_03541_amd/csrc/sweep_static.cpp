@@ -93,7 +93,7 @@ extern "C" int bumbar_sweep_static(bumbar_ctx* ctx, const void* u_kn, int u_dtyp
   double* Sv = S ? S : B.S;
   // the same launches as bumbar_sweep: queued only, or with the scalars read
   // back and a flagged sweep redone on the robust path
-  if (sweep_stats == nullptr && M.kind == 0 && sweep_fast_supported(K))
+  if (sweep_stats == nullptr && sweep_fast_supported(K))
     return sweep_queue(ctx, B, M, N, nullptr, N_k, f, f_new, log_D_n, B.lnS, Sv, B.scal);
   SweepScalars sc{};
   const int rc = sweep_at(ctx, B, M, N, nullptr, N_k, f, f_new, log_D_n, B.lnS, Sv, &sc, false,

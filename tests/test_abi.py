@@ -71,7 +71,7 @@ def test_version_and_null_context(lib):
     assert lib.bumbar_server_wait(None, 1) == -1
     n = C.c_int(7)
     assert lib.bumbar_server_progress(None, C.byref(n)) == -1 and n.value == 0
-    assert lib.bumbar_server_counters(None, None, None, None) == -1
+    assert lib.bumbar_server_counters(None, None, None, None, None) == -1
     lib.bumbar_server_destroy(None)
 
 

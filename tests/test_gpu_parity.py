@@ -318,18 +318,39 @@ def test_invalid_inputs_raise(bm):
         bm.solve(dev(bad), Nk)
 
 
-@pytest.mark.parametrize("K,N", [(5, 999), (100, 3001), (300, 2000)])
-def test_fp32_input_sweep_matches_oracle_on_widened_values(bm, K, N):
-    # FP32 u is widened to FP64 on load: the exact reference is the oracle on
-    # the float-rounded values
+@pytest.mark.parametrize("K,N,pad", [(5, 999, 0), (100, 3001, 0), (300, 2000, 0), (64, 1024, 0),
+                                     (256, 4097, 0), (100, 1000, 1), (13, 777, 3)])
+def test_fp32_input_sweep_matches_oracle_on_widened_values(bm, K, N, pad):
+    # FP32 u is widened to FP64 on load (the register-tiled sweep for K <= 256,
+    # with 8-byte loads when rows are aligned, element loads otherwise): the
+    # exact reference is the oracle on the float-rounded values. pad > 0 gives
+    # a row stride N + pad (unaligned rows).
     import torch
     u, Nk, _ = random_problem(K, N, seed=K + 3 * N)
     u32 = u.astype(np.float32)
     f = np.concatenate([[0.0], np.random.default_rng(3).normal(0, 0.2, K - 1)])
     fn_ref, lD_ref = oracle.sci_step(u32.astype(np.float64), Nk, f, return_logD=True)
-    fn, lD, S, st = bm.sweep(torch.as_tensor(u32).cuda(), Nk, f)
+    ut = torch.zeros((K, N + pad), dtype=torch.float32, device="cuda")
+    ut[:, :N] = torch.as_tensor(u32).cuda()
+    fn, lD, S, st = bm.sweep(ut[:, :N], Nk, f)
     assert np.max(np.abs(fn.cpu().numpy() - fn_ref)) < 1e-12
     assert np.max(np.abs(lD.cpu().numpy() - lD_ref)) < 1e-12 * max(1.0, np.abs(lD_ref).max())
+    F_ref, g_ref = oracle.objective_gradient(u32.astype(np.float64), Nk, f)
+    assert abs(st["objective"] - F_ref) < 1e-10 * max(1.0, abs(F_ref))
+
+
+@pytest.mark.parametrize("K,Nk", [(8, 1500), (120, 60), (256, 20)])
+def test_fp32_storage_solve_fp64(bm, K, Nk):
+    # FP64 solve of an FP32-stored matrix (register-tiled sweeps for K <= 256):
+    # the oracle's solution of the rounded problem to 1e-9 kT
+    p = synth.harmonic_1d(K=K, Nk=Nk, seed=K)
+    u32 = p["u"].astype(np.float32)
+    f_ref, _ = oracle.solve_mbar(u32.astype(np.float64), p["Nk"])
+    plan = bm.plan(K, p["N"], u_dtype=bm.F32)
+    assert plan["sweep"] == 0  # BUMBAR_SWEEP_REGISTER
+    f, info = bm.solve(dev(u32), p["Nk"], tol=1e-11)
+    assert info["status"] == 0
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
 
 
 @pytest.mark.parametrize("cfg", ["harmonic", "double_well", "ladder"])

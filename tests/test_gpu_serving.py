@@ -138,6 +138,7 @@ def test_admission_by_footprint(bm):
         say("tight arena counters", c)
         assert c["peak_active"] == 1
         assert c["peak_bytes"] <= fp * 1.5
+        assert c["mem_waits"] >= 1  # slots were free, memory was not
         for f in fs[1:]:
             assert np.array_equal(f, fs[0])
         with pytest.raises(bm.BumbarError) as e:
