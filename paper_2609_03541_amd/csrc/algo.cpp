@@ -26,8 +26,13 @@ constexpr int kCountSlots = 8192;
 static_assert(sizeof(WidthSearch1D) <= sizeof(int64_t) * (kCountSlots / 2 - 1),
               "width-search state must fit below the last count slot");
 
+// Bins per level whose centre representatives are materialised (K <= 256):
+// at least 65536, and N / 8, which covers the levels of nominal size up to
+// N / 10 that Algorithm 1 reaches before it stops refining; larger levels run
+// the model sweep at their centres. Two level slots of K x cap doubles then
+// cost 2 K N bytes at most beyond 65536 bins, not 16 K N.
 int64_t otf_ubar_cap(int K, int64_t N) {
-  return sweep_fast_supported(K) ? std::min<int64_t>(N, 65536) : 0;
+  return sweep_fast_supported(K) ? std::min<int64_t>(N, std::max<int64_t>(65536, N / 8)) : 0;
 }
 
 void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,

@@ -96,14 +96,18 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
   // register-tiled sweep takes K (its binned steps are one launch each) or
   // for MEAN; bin centres for the model sweeps otherwise
   if (p->binning) {
-    if (otf) {
+    if (otf || p->rep == BUMBAR_REPRESENT_CENTRE) {
+      // bin centres: the model at the centres, materialised for levels of up
+      // to otf_ubar_cap bins (K <= 256), else evaluated inside the sweeps
       p->bb_ubar = false;
       p->bb_cen = true;
       p->bb_otf_cap = otf_ubar_cap(K, N);
     } else {
-      // (an unresolved AUTO sizes for both)
-      p->bb_ubar = p->rep != BUMBAR_REPRESENT_CENTRE || sweep_fast_supported(K);
-      p->bb_cen = p->rep != BUMBAR_REPRESENT_MEAN && !sweep_fast_supported(K);
+      // bin means of the stored u: every level materialised (an unresolved
+      // AUTO also carves the centres)
+      p->bb_ubar = true;
+      p->bb_cen = p->rep != BUMBAR_REPRESENT_MEAN;
+      p->bb_otf_cap = 0;
     }
     // on the fly with K > 256 a binned step is a model sweep over K x P: the
     // FP32 stage first runs it in FP32 on FP32 centres. Not for stored u:

@@ -1029,7 +1029,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   BinnedBufs& BB = pb.BB;
   MixedBufs& X = pb.X;
   OtfBufs& O = pb.O;
-  if (opt.binning) BB.otf = rep == BUMBAR_REPRESENT_CENTRE && (otf || !sweep_fast_supported(K));
+  if (opt.binning) BB.otf = rep == BUMBAR_REPRESENT_CENTRE;
   // every buffer a planned path launches with must have been carved
   if ((plan.x_packed && !X.r) || (plan.copy && !pb.copy) || (plan.o_bufs && !O.cf64) ||
       (plan.fp32_binned && !BB.cenf[0]) || (plan.xi_wide && !pb.xi64))

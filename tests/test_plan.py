@@ -96,3 +96,15 @@ def test_fp32_coordinates_widened_in_workspace(bm):
     # no coordinates: nothing to widen
     assert bm.plan(100, 1000, xi_dtype=bm.F32)["workspace_bytes"] == \
         bm.plan(100, 1000)["workspace_bytes"]
+
+
+def test_level_representatives_bounded_by_a_fraction_of_u(bm):
+    # with bin-centre representatives only levels of up to max(65536, N/8)
+    # bins are materialised (two slots of K x cap doubles); bin means keep
+    # every level materialised
+    K, N = 200, 2_000_000
+    kw = dict(d=1, model=bm.MODEL_HARMONIC, binning=1)
+    cen = bm.plan(K, N, u_dtype=bm.F32, represent=bm.REPRESENT_CENTRE, **kw)
+    mean = bm.plan(K, N, represent=bm.REPRESENT_MEAN, **kw)
+    assert cen["workspace_bytes"] < 4 * K * N  # less than the FP32 u itself
+    assert mean["workspace_bytes"] > 16 * K * N
