@@ -319,12 +319,14 @@ def run_all(args, bm, synth, stream):
                                      tol=args.tol, precision=prec, profile=int(prof), ctx=ctx)
 
     f64, inf64, ms64 = _timed_solves(bm, args, "c2 f64", c2(u, bm.PREC_FP64))
+    cov_ms = _covariance_ms(bm, u, Nk, f64, ctx)
     sw64, nsw = _avg_sweep_s(inf64)
     elems = K * N
     value = elems / sw64
     achieved = 8.0 * elems / sw64 / 1e9
     cfg["c2_f64"] = dict(time_to_solve_s=ms64 / 1e3, sweep_us=sw64 * 1e6, sweep_launches=nsw,
                          error_vs_oracle_kT=_err(f64, g2), status=inf64[-1]["status"],
+                         covariance_ms=cov_ms,
                          stages_ms=dict(binning=inf64[-1]["time_binning_ms"],
                                         binned=inf64[-1]["time_binned_ms"],
                                         finisher=inf64[-1]["time_final_ms"]))
@@ -387,6 +389,18 @@ def run_all(args, bm, synth, stream):
     print(json.dumps(out), flush=True)
 
 
+def _covariance_ms(bm, u, Nk, f, ctx, reps=3):
+    """Wall time of bumbar_covariance at the solution (one warm-up call)."""
+    import torch
+    bm.covariance(u, Nk, f, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bm.covariance(u, Nk, f, ctx=ctx)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
 def _c1(bm, synth, args, ctx):
     import torch
     p1 = synth.double_well(K=100, Nk=10000, seed=1)
@@ -399,12 +413,13 @@ def _c1(bm, synth, args, ctx):
         lambda prof: bm.solve(u1, Nk1, xi=xi1, model=bm.MODEL_HARMONIC, coef=coef1, tol=args.tol,
                               profile=int(prof), ctx=ctx))
     sw1, _ = _avg_sweep_s(inf1)
+    cov_ms = _covariance_ms(bm, u1, Nk1, f1, ctx)
     a1 = 8.0 * p1["K"] * p1["N"] / sw1 / 1e9
     res = dict(time_to_solve_s=ms1 / 1e3, sweep_us=sw1 * 1e6,
                sweep_elem_s=p1["K"] * p1["N"] / sw1, roofline_frac=a1 / HBM_PEAK_GBS,
                traffic=_counter_traffic("sweep_fast_double_well_K100_N1e6"),
                error_vs_oracle_kT=_err(f1, _golden("c1_double_well_K100_N1e6")),
-               status=inf1[-1]["status"])
+               status=inf1[-1]["status"], covariance_ms=cov_ms)
     del u1
     torch.cuda.empty_cache()
     return res
@@ -461,41 +476,61 @@ def _c4(bm, synth, args, ctx, Nk_per, gold=None, hessian=True):
     return res
 
 
-def _c3(bm, args, stream):
-    _, probs = stream
-    budget = int(args.hbm_budget_gb * 2**30)
-    mixed = dict(tol=args.tol, precision=bm.PREC_MIXED)
-    n = len(probs)
-    _serve(bm, probs[:2], [0.0, 0.0], 2, budget, mixed)  # warm-up
-    # saturation: the whole stream at t = 0 (closed loop)
-    _, wall_sat, _ = _serve(bm, probs, [0.0] * n, args.max_active, budget, mixed)
+def _served(bm, probs, n, rate_seed, max_active, budget, opts, gold):
+    """Saturation (closed loop), then Poisson arrivals at 0.8x that rate."""
+    _, wall_sat, _ = _serve(bm, probs, [0.0] * n, max_active, budget, opts)
     sat = n / wall_sat
     rate = 0.8 * sat
-    g = np.random.Generator(np.random.PCG64(33))
+    g = np.random.Generator(np.random.PCG64(rate_seed))
     arrivals = list(np.cumsum(g.exponential(1.0 / rate, size=n)))
-    log(f"c3 saturation {sat:.1f} solves/s; served run at {rate:.1f}/s")
-    res, wall, cnt = _serve(bm, probs, arrivals, args.max_active, budget, mixed)
+    log(f"  saturation {sat:.1f} solves/s; served run at {rate:.1f}/s")
+    res, wall, cnt = _serve(bm, probs, arrivals, max_active, budget, opts)
     lat = np.array([info["latency_ms"] for _, info in res])
-    log("c3 sequential FP64 run")
-    res64, wall64, _ = _serve(bm, probs, [0.0] * n, 1, budget,
-                              dict(tol=args.tol, precision=bm.PREC_FP64))
-    lat64 = np.array([info["latency_ms"] for _, info in res64])
-    gold = _golden("c3_stream_subset64")
     err_gold = None
     if gold is not None:
         err_gold = max(float(np.max(np.abs(res[it["index"]][0] - np.asarray(it["f"]))))
                        for it in gold["problems"] if it["index"] < n)
-    return dict(
-        solves_per_s=n / wall, p50_ms=float(np.percentile(lat, 50)),
-        p99_ms=float(np.percentile(lat, 99)), rate_per_s=rate, saturation_solves_per_s=sat,
-        n_problems=n, max_active=args.max_active, precision="mixed",
-        failed=int(sum(1 for _, i in res if i["status"] not in (0, -4))),
-        peak_active=cnt["peak_active"], peak_arena_gb=cnt["peak_bytes"] / 2**30,
+    out = dict(solves_per_s=n / wall, p50_ms=float(np.percentile(lat, 50)),
+               p99_ms=float(np.percentile(lat, 99)), rate_per_s=rate,
+               saturation_solves_per_s=sat, max_active=max_active,
+               hbm_budget_gb=budget / 2**30,
+               failed=int(sum(1 for _, i in res if i["status"] not in (0, -4))),
+               peak_active=cnt["peak_active"], peak_arena_gb=cnt["peak_bytes"] / 2**30,
+               memory_bound_admissions=cnt["mem_waits"],
+               error_vs_oracle_subset64_kT=err_gold)
+    return out, res
+
+
+def _c3(bm, args, stream):
+    _, probs = stream
+    n = len(probs)
+    mixed = dict(tol=args.tol, precision=bm.PREC_MIXED)
+    gold = _golden("c3_stream_subset64")
+    _serve(bm, probs[:2], [0.0, 0.0], 2, 8 << 30, mixed)  # warm-up
+    # the stream's recipe: u materialised on the device in FP32 (K N 4 bytes
+    # resident per problem, counted by admission) and solved in mixed
+    # precision; a 64 GB arena with 16 slots, so that admission is bound by
+    # memory for the large problems
+    log("c3 materialised FP32 u, 16 slots, 64 GB arena")
+    mat, res = _served(bm, probs, n, 33, 16, 64 << 30, dict(mixed, materialize=True), gold)
+    # the same requests with the energies evaluated inside the kernels (no
+    # stored u): the faster mode, in the arena of --hbm-budget-gb
+    log("c3 energies in the kernels, %d slots" % args.max_active)
+    otf, res_otf = _served(bm, probs, n, 34, args.max_active, int(args.hbm_budget_gb * 2**30),
+                           mixed, gold)
+    log("c3 sequential FP64 run")
+    res64, wall64, _ = _serve(bm, probs, [0.0] * n, 1, int(args.hbm_budget_gb * 2**30),
+                              dict(tol=args.tol, precision=bm.PREC_FP64))
+    lat64 = np.array([info["latency_ms"] for _, info in res64])
+    out = dict(mat)
+    out.update(
+        n_problems=n, precision="mixed", storage="u materialised on the device, FP32",
+        energies_in_kernel=otf,
         sequential_fp64=dict(solves_per_s=n / wall64, p50_ms=float(np.percentile(lat64, 50)),
                              p99_ms=float(np.percentile(lat64, 99))),
         max_abs_diff_vs_sequential_fp64_kT=max(float(np.max(np.abs(a[0] - b[0])))
-                                               for a, b in zip(res, res64)),
-        error_vs_oracle_subset64_kT=err_gold)
+                                               for a, b in zip(res_otf, res64)))
+    return out
 
 
 def _cpu_baseline(oracle, synth, args):
