@@ -509,10 +509,10 @@ def _c3(bm, args, stream):
     _serve(bm, probs[:2], [0.0, 0.0], 2, 8 << 30, mixed)  # warm-up
     # the stream's recipe: u materialised on the device in FP32 (K N 4 bytes
     # resident per problem, counted by admission) and solved in mixed
-    # precision; a 64 GB arena with 16 slots, so that admission is bound by
-    # memory for the large problems
-    log("c3 materialised FP32 u, 16 slots, 64 GB arena")
-    mat, res = _served(bm, probs, n, 33, 16, 64 << 30, dict(mixed, materialize=True), gold)
+    # precision; a 32 GB arena with 16 slots, so that admission is bound by
+    # memory whenever several large problems are resident
+    log("c3 materialised FP32 u, 16 slots, 32 GB arena")
+    mat, res = _served(bm, probs, n, 33, 16, 32 << 30, dict(mixed, materialize=True), gold)
     # the same requests with the energies evaluated inside the kernels (no
     # stored u): the faster mode, in the arena of --hbm-budget-gb
     log("c3 energies in the kernels, %d slots" % args.max_active)

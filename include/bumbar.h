@@ -94,6 +94,7 @@ extern "C" {
 #define BUMBAR_STAGE32_PACKED 1       /* r_kn = fp32(c0_k - u_kn - m0_n), K <= 256          */
 #define BUMBAR_STAGE32_SAMPLE_MAJOR 2 /* FP32 arithmetic over the sample-major copy        */
 #define BUMBAR_STAGE32_MODEL 3        /* the model evaluated in FP32                        */
+#define BUMBAR_STAGE32_STORED 4       /* FP32 exponentials over FP32-stored u, K <= 256     */
 
 typedef struct bumbar_ctx bumbar_ctx;
 

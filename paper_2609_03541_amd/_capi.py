@@ -86,6 +86,7 @@ STAGE32_NONE = 0
 STAGE32_PACKED = 1
 STAGE32_SAMPLE_MAJOR = 2
 STAGE32_MODEL = 3
+STAGE32_STORED = 4
 
 
 class ServerOptions(C.Structure):

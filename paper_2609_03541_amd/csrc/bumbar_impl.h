@@ -63,11 +63,13 @@ int robust_chunks(int64_t N);                   // column chunks of the robust p
 // per-block objective partials and flags. h (per-column multiplicity) may be
 // null; logD may be null. Returns 0 or a hipError_t value.
 // The grid (persistent, occupancy-sized) is returned in *grid_out. u is FP64,
-// or FP32 (f32) widened exactly on load; the arithmetic is FP64 either way.
-hipError_t launch_sweep_fast(hipStream_t s, const void* u, bool f32, int64_t ld, int K,
-                             int64_t N, const double* cst, const double* gk, const double* h,
-                             double* logD, double* part, double* part_obj, unsigned* part_flags,
-                             int num_cus, int* grid_out);
+// or FP32 (f32) widened exactly on load; the arithmetic is FP64, except that
+// f32_arith (FP32 storage only: the FP32 stage of mixed precision) takes the
+// exponentials of the FP64-shifted exponents in FP32 (hardware exp2).
+hipError_t launch_sweep_fast(hipStream_t s, const void* u, bool f32, bool f32_arith, int64_t ld,
+                             int K, int64_t N, const double* cst, const double* gk,
+                             const double* h, double* logD, double* part, double* part_obj,
+                             unsigned* part_flags, int num_cus, int* grid_out);
 bool sweep_fast_supported(int K);
 
 // Robust two-pass sweep: exact column max, then per-state online log-sum-exp.

@@ -81,7 +81,9 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
     if (otf)
       p->stage32 = BUMBAR_STAGE32_MODEL;
     else if (sweep_fast_supported(K))
-      p->stage32 = BUMBAR_STAGE32_PACKED;
+      // FP32 storage is read as it is (FP32 exponentials, no copy); FP64
+      // storage is packed once to FP32 differences
+      p->stage32 = f32 ? BUMBAR_STAGE32_STORED : BUMBAR_STAGE32_PACKED;
     else if (p->sweep == BUMBAR_SWEEP_SAMPLE_MAJOR)
       p->stage32 = BUMBAR_STAGE32_SAMPLE_MAJOR;
     else if (sweep_smaj_supported(K))

@@ -163,14 +163,19 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep32(s, reinterpret_cast<const float*>(M.u), M.ld, K, N, B.dk, B.gk, M.m0,
                        logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
+  } else if (M.kind == 7) {
+    // FP32 exponentials over the stored FP32 u (K <= 256), no copy
+    if (ev) (void)hipEventRecord(ev->first, s);
+    e = launch_sweep_fast(s, M.u, true, true, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
+                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind >= 3) {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_otf(s, M.otf, M.kind == 3, K, N, B.cst, B.gk, h, logD_out, B.part,
                          (size_t)B.nparts_cap * K, B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if ((M.kind == 0 || M.kind == 1) && sweep_fast_supported(K)) {
     if (ev) (void)hipEventRecord(ev->first, s);
-    e = launch_sweep_fast(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
-                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
+    e = launch_sweep_fast(s, M.u, M.kind == 1, false, M.ld, K, N, B.cst, B.gk, h, logD_out,
+                          B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else {
     if (ev) (void)hipEventRecord(ev->first, s);
     e = launch_sweep_wide(s, M.u, M.kind == 1, M.ld, K, N, B.cst, B.gk, h, logD_out, B.part,
@@ -1175,9 +1180,11 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
                                 &st->grad_norm);
         if (mrc != BUMBAR_OK && mrc != BUMBAR_ENOTCONV) return mrc;
         st->mixed_steps = st->finisher_steps - before;
-      } else if (mixed && plan.stage32 == BUMBAR_STAGE32_SAMPLE_MAJOR) {
-        // Newton on FP32-arithmetic sweeps of the sample-major copy to
-        // mixed_tol, then FP64 refinement on the same copy to tol
+      } else if (mixed && (plan.stage32 == BUMBAR_STAGE32_SAMPLE_MAJOR ||
+                           plan.stage32 == BUMBAR_STAGE32_STORED)) {
+        // Newton on FP32-exponential sweeps of the sample-major copy (or of
+        // the stored FP32 u, K <= 256) to mixed_tol, then FP64 refinement on
+        // the same data to tol
         Mat R = M;
         R.kind = 7;
         R.hess_kind = plan.hess_kind32;

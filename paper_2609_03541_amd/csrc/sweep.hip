@@ -46,6 +46,7 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl
 // ---------------------------------------------------------------------------
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
+constexpr double kLog2e = 1.4426950408889634;
 
 template <int NW, int LPR, int CPL, int ROWS>
 struct SweepTile {
@@ -101,7 +102,7 @@ __device__ __forceinline__ void tile_load(double (&a)[ROWS][CPL], const TI* __re
 // tiles back to back without a barrier between them alternates two copies of
 // them (a wave may start the next tile's pass 1 while another is still
 // reading this tile's).
-template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED, int SG>
+template <int NW, int LPR, int CPL, int ROWS, bool TAIL, bool MASKED, int SG, bool F32A = false>
 __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, int64_t N, int lc,
                                              int rg, int wave, int rgw,
                                              const double* __restrict__ c_sh, unsigned smask,
@@ -156,7 +157,10 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
   for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
-      a[j][i] = exp_nonpos(a[j][i] - m[i]);
+      if constexpr (F32A)  // FP32 stage of mixed precision: FP32 hardware exp2, FP64 sums
+        a[j][i] = (double)__builtin_amdgcn_exp2f((float)((a[j][i] - m[i]) * kLog2e));
+      else
+        a[j][i] = exp_nonpos(a[j][i] - m[i]);
       if constexpr (MASKED) {
         ds[i] = ((sm >> j) & 1u) ? ds[i] + a[j][i] : ds[i];
       } else {
@@ -224,7 +228,8 @@ __device__ __forceinline__ void tile_compute(double (&a)[ROWS][CPL], int64_t t, 
 // are issued into a second register buffer before the current tile is
 // processed (software prefetch), so HBM traffic overlaps the arithmetic.
 // Successive tiles use alternating copies (par) of the reduction buffers.
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG, typename TI>
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool MASKED, bool PF, int SG, typename TI,
+          bool F32A>
 __device__ __forceinline__ void tile_loop(const TI* __restrict__ base, int64_t rstride,
                                           int rows_here, int64_t nfull, int64_t N, int lc, int rg,
                                           int wave, int rgw, const double* __restrict__ c_sh,
@@ -239,7 +244,7 @@ __device__ __forceinline__ void tile_loop(const TI* __restrict__ base, int64_t r
     for (; t < nfull; t += G) {
       double a[ROWS][CPL];
       tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(a, base, rstride, rows_here, t, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG, F32A>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
     }
@@ -249,13 +254,13 @@ __device__ __forceinline__ void tile_loop(const TI* __restrict__ base, int64_t r
     while (t < nfull) {
       const int64_t t1 = t + G;
       if (t1 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(b, base, rstride, rows_here, t1, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG, F32A>(a, t, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
       if (t1 >= nfull) break;
       const int64_t t2 = t1 + G;
       if (t2 < nfull) tile_load<NW, LPR, CPL, ROWS, VEC, false, TI>(a, base, rstride, rows_here, t2, N, lc);
-      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
+      tile_compute<NW, LPR, CPL, ROWS, false, MASKED, SG, F32A>(b, t1, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                       logD, red1[par], red2[par], acc, obj, bad);
       par ^= 1;
       t = t2;
@@ -263,7 +268,7 @@ __device__ __forceinline__ void tile_loop(const TI* __restrict__ base, int64_t r
   }
 }
 
-template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF, int SG, typename TI>
+template <int NW, int LPR, int CPL, int ROWS, bool VEC, bool PF, int SG, typename TI, bool F32A>
 __global__ void __launch_bounds__(NW * 64)
     sweep_fast_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N,
                       int64_t ntiles, const double* __restrict__ cst,
@@ -313,17 +318,17 @@ __global__ void __launch_bounds__(NW * 64)
   int par = 0;
   const int64_t nfull = N / TN;
   if (!masked)
-    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG, TI>(base, rstride, rows_here, nfull, N, lc, rg, wave,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, false, PF, SG, TI, F32A>(base, rstride, rows_here, nfull, N, lc, rg, wave,
                                                   rgw, c_sh, smask, h, logD, red1, red2, par, acc,
                                                   obj, bad);
   else
-    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1, TI>(base, rstride, rows_here, nfull, N, lc, rg,
+    tile_loop<NW, LPR, CPL, ROWS, VEC, true, false, 1, TI, F32A>(base, rstride, rows_here, nfull, N, lc, rg,
                                                     wave, rgw, c_sh, smask, h, logD, red1, red2,
                                                     par, acc, obj, bad);
   if (nfull < ntiles && blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     double a[ROWS][CPL];
     tile_load<NW, LPR, CPL, ROWS, VEC, true, TI>(a, base, rstride, rows_here, nfull, N, lc);
-    tile_compute<NW, LPR, CPL, ROWS, true, true, 1>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
+    tile_compute<NW, LPR, CPL, ROWS, true, true, 1, F32A>(a, nfull, N, lc, rg, wave, rgw, c_sh, smask, h,
                                                  logD, red1[par], red2[par], acc, obj, bad);
   }
 
@@ -384,15 +389,15 @@ bool sweep_fast_supported(int K) { return pick_cfg(K) != nullptr; }
 
 int sweep_max_grid(int num_cus) { return num_cus * 8; }
 
-template <int NW, int LPR, int CPL, int ROWS, int PF, int SG, typename TI>
+template <int NW, int LPR, int CPL, int ROWS, int PF, int SG, typename TI, bool F32A = false>
 static hipError_t launch_cfg(hipStream_t s, bool vec, const TI* u, int64_t ld, int K,
                              int64_t N, const double* cst, const double* gk, const double* h,
                              double* logD, double* part, double* part_obj, unsigned* pf,
                              int num_cus, int* grid_out) {
   constexpr int TN = LPR * CPL;
   const int64_t ntiles = (N + TN - 1) / TN;
-  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG, TI>;
-  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG, TI>;
+  auto kv = sweep_fast_kernel<NW, LPR, CPL, ROWS, true, PF != 0, SG, TI, F32A>;
+  auto ks = sweep_fast_kernel<NW, LPR, CPL, ROWS, false, PF != 0, SG, TI, F32A>;
   // resident workgroups per CU of this instantiation (queried once, thread-safe)
   static const int per_cu = [&] {
     int nb = 0;
@@ -414,23 +419,29 @@ static hipError_t launch_cfg(hipStream_t s, bool vec, const TI* u, int64_t ld, i
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_fast(hipStream_t s, const void* u, bool f32, int64_t ld, int K,
-                             int64_t N, const double* cst, const double* gk, const double* h,
-                             double* logD, double* part, double* part_obj, unsigned* part_flags,
-                             int num_cus, int* grid_out) {
+hipError_t launch_sweep_fast(hipStream_t s, const void* u, bool f32, bool f32_arith, int64_t ld,
+                             int K, int64_t N, const double* cst, const double* gk,
+                             const double* h, double* logD, double* part, double* part_obj,
+                             unsigned* part_flags, int num_cus, int* grid_out) {
   const FastCfg* c = pick_cfg(K);
   if (!c) return hipErrorInvalidValue;
+  if (f32_arith && !f32) return hipErrorInvalidValue;  // FP32 exponentials only over FP32 storage
   // two columns per load: 16 bytes in FP64, 8 bytes in FP32
   const uintptr_t al = f32 ? 7 : 15;
   const bool vec = ((reinterpret_cast<uintptr_t>(u) & al) == 0) && ((ld & 1) == 0);
   const double* ud = static_cast<const double*>(u);
   const float* uf = static_cast<const float*>(u);
-#define BUMBAR_CFG(a, b, cc, d, e, f)                                                           \
-  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e && c->sg == f)    \
-    return f32 ? launch_cfg<a, b, cc, d, e, f>(s, vec, uf, ld, K, N, cst, gk, h, logD, part,    \
-                                               part_obj, part_flags, num_cus, grid_out)         \
-               : launch_cfg<a, b, cc, d, e, f>(s, vec, ud, ld, K, N, cst, gk, h, logD, part,    \
-                                               part_obj, part_flags, num_cus, grid_out);
+#define BUMBAR_CFG(a, b, cc, d, e, f)                                                            \
+  if (c->nw == a && c->lpr == b && c->cpl == cc && c->rows == d && c->pf == e && c->sg == f) {  \
+    if (f32_arith)                                                                               \
+      return launch_cfg<a, b, cc, d, e, f, float, true>(s, vec, uf, ld, K, N, cst, gk, h, logD,  \
+                                                        part, part_obj, part_flags, num_cus,     \
+                                                        grid_out);                               \
+    return f32 ? launch_cfg<a, b, cc, d, e, f>(s, vec, uf, ld, K, N, cst, gk, h, logD, part,     \
+                                               part_obj, part_flags, num_cus, grid_out)          \
+               : launch_cfg<a, b, cc, d, e, f>(s, vec, ud, ld, K, N, cst, gk, h, logD, part,     \
+                                               part_obj, part_flags, num_cus, grid_out);         \
+  }
   BUMBAR_CFG(4, 64, 2, 2, 1, 1)
   BUMBAR_CFG(4, 64, 2, 4, 1, 1)
   BUMBAR_CFG(4, 64, 2, 8, 1, 1)

@@ -339,6 +339,24 @@ def test_fp32_input_sweep_matches_oracle_on_widened_values(bm, K, N, pad):
     assert abs(st["objective"] - F_ref) < 1e-10 * max(1.0, abs(F_ref))
 
 
+@pytest.mark.parametrize("K,Nk,xi", [(8, 1500, False), (120, 60, True), (256, 20, False)])
+def test_fp32_storage_solve_mixed(bm, K, Nk, xi):
+    # mixed precision on FP32 storage with K <= 256: Newton on FP32-exponential
+    # sweeps of the stored u (no copy), then FP64 refinement: the oracle's
+    # solution of the rounded problem to 1e-9 kT
+    p = synth.harmonic_1d(K=K, Nk=Nk, seed=K + 7)
+    u32 = p["u"].astype(np.float32)
+    f_ref, _ = oracle.solve_mbar(u32.astype(np.float64), p["Nk"])
+    kw = dict(xi=p["xi"], model=p["model_type"], coef=p["coef"]) if xi else {}
+    plan = bm.plan(K, p["N"], u_dtype=bm.F32, precision=bm.PREC_MIXED)
+    assert plan["stage32"] == 4  # BUMBAR_STAGE32_STORED
+    f, info = bm.solve(dev(u32), p["Nk"], tol=1e-11, precision=bm.PREC_MIXED, **kw)
+    say(f"fp32 storage mixed K={K}: mixed steps {info['mixed_steps']}, "
+        f"all {info['finisher_steps']}")
+    assert info["status"] == 0 and info["mixed_steps"] >= 1
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+
+
 @pytest.mark.parametrize("K,Nk", [(8, 1500), (120, 60), (256, 20)])
 def test_fp32_storage_solve_fp64(bm, K, Nk):
     # FP64 solve of an FP32-stored matrix (register-tiled sweeps for K <= 256):

@@ -46,11 +46,16 @@ def test_mixed_fp32_storage(bm):
     assert p["fp32_binned"] == 0 and p["hessian_fp16"] == 1
 
 
-def test_mixed_small_k_packed(bm):
-    for dt in (bm.F64, bm.F32):
-        p = bm.plan(100, 10_000, u_dtype=dt, precision=bm.PREC_MIXED)
-        assert p["stage32"] == _capi.STAGE32_PACKED and p["precision"] == bm.PREC_MIXED
+def test_mixed_small_k_packed_or_stored(bm):
+    # FP64 storage is packed to FP32 differences; FP32 storage is read as it
+    # is by the FP32-exponential sweep, so its workspace holds no copy
+    p64 = bm.plan(100, 10_000, u_dtype=bm.F64, precision=bm.PREC_MIXED)
+    p32 = bm.plan(100, 10_000, u_dtype=bm.F32, precision=bm.PREC_MIXED)
+    assert p64["stage32"] == _capi.STAGE32_PACKED and p64["precision"] == bm.PREC_MIXED
+    assert p32["stage32"] == _capi.STAGE32_STORED and p32["precision"] == bm.PREC_MIXED
+    for p in (p64, p32):
         assert p["sweep"] == _capi.SWEEP_REGISTER  # FP32 storage widened on load
+    assert p64["workspace_bytes"] - p32["workspace_bytes"] >= 100 * 10_000 * 4
 
 
 def test_model_energies(bm):
