@@ -83,19 +83,22 @@ hipError_t launch_sweep_robust(hipStream_t s, const void* u, bool f32, int64_t l
 // Sample-major copy of u for 256 < K <= 1024 (sweep_smaj.hip): N rows of
 // Kp = smaj_row(K) = 64 J values (J in {5, 6, 8, 10, 12, 14, 16}, the smallest
 // with K <= 64 J), states past K = +inf, so that a
-// sample is one contiguous row; smaj_elems = N Kp. launch_sweep_smaj: the
-// single-pass sweep over it, one wavefront per sample, in FP64 arithmetic
-// (FP64 copy, or FP32 copy widened) or, with f32_arith, FP32 arithmetic on
-// an FP32 copy (mixed precision).
+// sample is one contiguous row; smaj_elems = N Kp. launch_smaj_copy sets
+// *nan_flag (if given; the caller zeroes it) when u holds a NaN.
+// launch_sweep_smaj: the single-pass sweep over the copy, one wavefront per
+// sample pair, in FP64 arithmetic (FP64 copy, or FP32 copy widened) or, with
+// f32_arith, FP32 exponentials (mixed precision). nan_check: test every
+// element for NaN (a copy the caller made); the solve's own copy was checked
+// when it was made (f32_arith requires that).
 int smaj_row(int K);
 size_t smaj_elems(int K, int64_t N);
 bool sweep_smaj_supported(int K);
 hipError_t launch_smaj_copy(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
-                            void* ut);
-hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_arith, int K,
-                             int64_t N, const double* cst, const double* gk, const double* h,
-                             double* logD, double* part, double* part_obj, unsigned* part_flags,
-                             int num_cus, int* grid_out);
+                            void* ut, unsigned* nan_flag);
+hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_arith,
+                             bool nan_check, int K, int64_t N, const double* cst,
+                             const double* gk, const double* h, double* logD, double* part,
+                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out);
 
 // Finaliser. mode 0: partials are S' sums (fast path), partS a scratch of K
 // doubles for their per-state sums (or null); mode 1: (M, S) pairs in

@@ -68,8 +68,11 @@ __device__ __forceinline__ double log_ge1(double x) {
 // FP64 operations instead of 18, plus one LDS read.
 __device__ __forceinline__ double exp_nonpos_tab(double x, const double* __restrict__ tab) {
   x = __builtin_fmax(x, -1000.0);
-  const double kf = __builtin_rint(x * 92.33248261689366);
-  const int ki = (int)kf;
+  // round x 64/ln2 to an integer by adding 1.5 2^52 (|x 64/ln2| < 2^17 here):
+  // the sum's low 32 bits are that integer in two's complement
+  const double big = __builtin_fma(x, 92.33248261689366, 6755399441055744.0);
+  const int ki = (int)(uint32_t)__builtin_bit_cast(unsigned long long, big);
+  const double kf = big - 6755399441055744.0;
   double r = __builtin_fma(kf, -0.010830424696905538, x);
   r = __builtin_fma(kf, 6.563929801064195e-13, r);
   double p = __builtin_fma(r, 0.008333333333333333, 0.041666666666666664);

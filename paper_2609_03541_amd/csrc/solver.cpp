@@ -70,6 +70,7 @@ void UnbinnedBufs::carve(Arena& ar, int K_, int64_t N_, int num_cus) {
   f_hist = ar.take<double>((size_t)kHistSteps * K);
   misc = ar.take<double>(8);
   ok = ar.take<int>(4);
+  nan_flag = ar.take<unsigned>(1);
   idx = ar.take<int>(K);
   A = ar.take<double>(newton_ws_doubles(K));
   H = ar.take<double>((size_t)K * K);
@@ -155,8 +156,8 @@ static int queue_sweep(bumbar_ctx* ctx, const UnbinnedBufs& B, const Mat& M, int
   if (M.ut != nullptr) {
     // the sample-major copy (FP64 arithmetic, or FP32 for kind 7)
     if (ev) (void)hipEventRecord(ev->first, s);
-    e = launch_sweep_smaj(s, M.ut, M.ut_f32, M.kind == 7, K, N, B.cst, B.gk, h, logD_out, B.part,
-                          B.part_obj, B.part_flags, ctx->num_cus, &grid);
+    e = launch_sweep_smaj(s, M.ut, M.ut_f32, M.kind == 7, !M.ut_checked, K, N, B.cst, B.gk, h,
+                          logD_out, B.part, B.part_obj, B.part_flags, ctx->num_cus, &grid);
   } else if (M.kind == 2) {
     e = launch_delta(s, K, f, M.f0, B.dk);
     if (e != hipSuccess) return hip_fail(ctx, e, "delta");
@@ -604,7 +605,8 @@ int bumbar_sample_major(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, i
   if (!sweep_smaj_supported(K))
     return fail(ctx, BUMBAR_EINVAL, "the sample-major layout is defined for 256 < K <= 1024");
   if (!u_nk) return fail(ctx, BUMBAR_EINVAL, "NULL output");
-  const hipError_t e = launch_smaj_copy(ctx->stream, u_kn, u_dtype == BUMBAR_F32, ld, K, N, u_nk);
+  const hipError_t e =
+      launch_smaj_copy(ctx->stream, u_kn, u_dtype == BUMBAR_F32, ld, K, N, u_nk, nullptr);
   if (e != hipSuccess) return hip_fail(ctx, e, "sample-major copy");
   return BUMBAR_OK;
 }
@@ -1078,11 +1080,18 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
     if (on) M.otf.sep = &sep_grid;
   }
   if (plan.copy) {
-    // the sample-major copy every unbinned sweep of this solve reads
-    e = launch_smaj_copy(s, u_kn, plan.copy_f32, N, K, N, pb.copy);
+    // the sample-major copy every unbinned sweep of this solve reads; a NaN
+    // in u is caught here once, not in every sweep
+    e = hipMemsetAsync(B.nan_flag, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) e = launch_smaj_copy(s, u_kn, plan.copy_f32, N, K, N, pb.copy, B.nan_flag);
     if (e != hipSuccess) return hip_fail(ctx, e, "sample-major copy");
+    unsigned nan_seen = 0;
+    rc = read_bytes(ctx, B.nan_flag, &nan_seen, sizeof(unsigned));
+    if (rc) return rc;
+    if (nan_seen) return fail(ctx, BUMBAR_EINVAL, "u_kn holds a NaN");
     M.ut = pb.copy;
     M.ut_f32 = plan.copy_f32;
+    M.ut_checked = true;
   }
   SweepCounters cnt;
   ctx->profiling = opt.profile != 0;

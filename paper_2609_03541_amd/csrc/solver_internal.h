@@ -45,6 +45,7 @@ struct Mat {
                                // on the FP16 matrix cores; 6: FP64 u, FP32 exponentials)
   const void* ut = nullptr;    // the sample-major copy the sweeps read (kinds 0, 1, 7), or null
   bool ut_f32 = false;         // its element type
+  bool ut_checked = false;     // made by the solve (NaN checked once by the copy kernel)
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the
@@ -83,6 +84,7 @@ struct UnbinnedBufs {
   double* f_hist = nullptr;           // kHistSteps x K iterates (binned batches)
   double* misc = nullptr;
   int* ok = nullptr;
+  unsigned* nan_flag = nullptr;  // set by the sample-major copy when u holds a NaN
   int* idx = nullptr;
   double *A = nullptr, *H = nullptr, *hess_parts = nullptr;
   double* dk = nullptr;  // f - f0 for the packed matrix

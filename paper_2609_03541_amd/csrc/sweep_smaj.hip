@@ -3,7 +3,8 @@
 // The copy holds u transposed: sample n is one contiguous row of Kp = 64 J
 // values, J the smallest of 5, 6, 8, 10, 12, 14, 16 with K <= 64 J (states
 // past K padded with +inf). One wavefront owns
-// S = 2 samples at a time: lane l holds states k = l + 64 j (j < J), so the
+// S = 2 samples at a time: lane l holds J states, V consecutive ones per
+// 16-byte load (V = 2 in FP64, 4 in FP32 where J allows), so the
 // per-sample log-sum-exp of Eq. (1), ln D_n = LSE_k(c_k - u_kn), is a
 // register loop plus a 64-lane shuffle reduction, with no LDS traffic for the
 // matrix and no barrier in the sample loop; the two samples' reduction chains
@@ -48,9 +49,21 @@ int smaj_row(int K) { return 64 * smaj_slots(K); }
 size_t smaj_elems(int K, int64_t N) { return (size_t)smaj_row(K) * (size_t)N; }
 bool sweep_smaj_supported(int K) { return K > 256 && K <= 1024; }
 
+// Elements of one row a lane loads at once (16 bytes where J allows): slot j
+// of lane l holds state V l + 64 V (j / V) + j % V.
+template <int J, typename TI>
+constexpr int smaj_vec() {
+  return sizeof(TI) == 8 ? (J % 2 == 0 ? 2 : 1) : (J % 4 == 0 ? 4 : (J % 2 == 0 ? 2 : 1));
+}
+template <int J, typename TI>
+__device__ __forceinline__ int smaj_state(int lane, int j) {
+  constexpr int V = smaj_vec<J, TI>();
+  return V * lane + 64 * V * (j / V) + j % V;
+}
+
 // Sample loop of one wave (see the file comment); MASKED: some state has
 // N_k = 0 and is left out of D' (gm holds this lane's sampled slots).
-template <int J, typename TI, bool F32A, bool MASKED>
+template <int J, typename TI, bool F32A, bool MASKED, bool CHK>
 __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, int64_t n0,
                                           int64_t W, int lane, const double* __restrict__ c_sh,
                                           const double* __restrict__ etab, unsigned gm,
@@ -63,28 +76,38 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
   using TA = std::conditional_t<F32A, float, double>;
   for (int64_t nb = n0; nb < N; nb += W) {
     // rows past N re-read row N - 1 (their weight is zeroed below)
+    constexpr int V = smaj_vec<J, TI>();
+    typedef TI vT __attribute__((ext_vector_type(V)));
     TI x[S][J];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const int64_t n = nb + i < N ? nb + i : N - 1;
-      const TI* row = ut + n * Kp + lane;
+      const TI* row = ut + n * Kp + V * lane;
 #pragma unroll
-      for (int j = 0; j < J; ++j) x[i][j] = __builtin_nontemporal_load(row + 64 * j);
+      for (int jb = 0; jb < J / V; ++jb) {
+        if constexpr (V == 1) {
+          x[i][jb] = __builtin_nontemporal_load(row + 64 * jb);
+        } else {
+          const vT v = __builtin_nontemporal_load(reinterpret_cast<const vT*>(row + 64 * V * jb));
+#pragma unroll
+          for (int q = 0; q < V; ++q) x[i][jb * V + q] = v[q];
+        }
+      }
     }
     double m[S], chk = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) m[i] = -INFINITY;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const double cj = c_sh[lane + 64 * j];
+      const double cj = c_sh[smaj_state<J, TI>(lane, j)];
 #pragma unroll
       for (int i = 0; i < S; ++i) {
         const double a = cj - (double)x[i][j];
         m[i] = fmax(m[i], a);
-        chk += a;  // NaN if any u is NaN (padding states give -inf, not NaN)
+        if constexpr (CHK) chk += a;  // NaN if any u is NaN (padding gives -inf, not NaN)
       }
     }
-    if (chk != chk) bad |= FLAG_NAN;
+    if (CHK && chk != chk) bad |= FLAG_NAN;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1)
 #pragma unroll
@@ -97,7 +120,7 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const double cj = c_sh[lane + 64 * j];
+      const double cj = c_sh[smaj_state<J, TI>(lane, j)];
 #pragma unroll
       for (int i = 0; i < S; ++i) {
         const double t = cj - (double)x[i][j] - m[i];
@@ -142,7 +165,9 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
   }
 }
 
-template <int J, typename TI, bool F32A>
+// CHK: look for NaN in every element (a copy made by the caller); a copy made
+// by the solve was checked once by the copy kernel.
+template <int J, typename TI, bool F32A, bool CHK>
 __global__ void __launch_bounds__(kSmajWaves * 64)
     sweep_smaj_kernel(const TI* __restrict__ ut, int K, int64_t N, const double* __restrict__ cst,
                       const double* __restrict__ gk, const double* __restrict__ h,
@@ -164,7 +189,7 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
   unsigned gm = 0u, valid_bits = 0u;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int k = lane + 64 * j;
+    const int k = smaj_state<J, TI>(lane, j);
     if (k < K) valid_bits |= 1u << j;
     if (k < K && gk[k] != 0.0) gm |= 1u << j;
     acc[j] = 0;
@@ -177,12 +202,13 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
   const int64_t W = (int64_t)gridDim.x * kSmajWaves * kSmajS;
   const int64_t n0 = ((int64_t)blockIdx.x * kSmajWaves + wave) * kSmajS;
   if (masked)
-    smaj_loop<J, TI, F32A, true>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj, bad);
+    smaj_loop<J, TI, F32A, true, CHK>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj, bad);
   else
-    smaj_loop<J, TI, F32A, false>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj, bad);
+    smaj_loop<J, TI, F32A, false, CHK>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj,
+                                       bad);
   // per-state sums of the workgroup: waves in order through LDS
 #pragma unroll
-  for (int j = 0; j < J; ++j) red[wave][lane + 64 * j] = (double)acc[j];
+  for (int j = 0; j < J; ++j) red[wave][smaj_state<J, TI>(lane, j)] = (double)acc[j];
   // objective: lanes 0 .. S-1 of each wave hold its parts
   double o = obj;
 #pragma unroll
@@ -205,12 +231,12 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
   }
 }
 
-template <int J, typename TI, bool F32A>
+template <int J, typename TI, bool F32A, bool CHK>
 static hipError_t launch_smaj_t(hipStream_t s, const TI* ut, int K, int64_t N, const double* cst,
                                 const double* gk, const double* h, double* logD, double* part,
                                 double* part_obj, unsigned* part_flags, int num_cus,
                                 int* grid_out) {
-  auto kern = sweep_smaj_kernel<J, TI, F32A>;
+  auto kern = sweep_smaj_kernel<J, TI, F32A, CHK>;
   // resident workgroups per CU of this instantiation (queried once, thread-safe)
   static const int per_cu = [&] {
     int nb = 0;
@@ -231,29 +257,27 @@ static hipError_t launch_smaj_t(hipStream_t s, const TI* ut, int K, int64_t N, c
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_arith, int K,
-                             int64_t N, const double* cst, const double* gk, const double* h,
-                             double* logD, double* part, double* part_obj, unsigned* part_flags,
-                             int num_cus, int* grid_out) {
+hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_arith,
+                             bool nan_check, int K, int64_t N, const double* cst,
+                             const double* gk, const double* h, double* logD, double* part,
+                             double* part_obj, unsigned* part_flags, int num_cus, int* grid_out) {
   if (!sweep_smaj_supported(K)) return hipErrorInvalidValue;
+  // the FP32 stage runs only over the solve's own (checked) copy
+  if (f32_arith && nan_check) return hipErrorInvalidValue;
   const int J = smaj_slots(K);
+  const float* uf = reinterpret_cast<const float*>(ut);
+  const double* ud = reinterpret_cast<const double*>(ut);
+#define BUMBAR_SMAJ_ARGS K, N, cst, gk, h, logD, part, part_obj, part_flags, num_cus, grid_out
 #define BUMBAR_SMAJ(jj)                                                                        \
   if (J == jj) {                                                                               \
-    if (f32_arith && f32)                                                                      \
-      return launch_smaj_t<jj, float, true>(s, reinterpret_cast<const float*>(ut), K, N, cst,   \
-                                            gk, h, logD, part, part_obj, part_flags, num_cus,   \
-                                            grid_out);                                          \
     if (f32_arith)                                                                             \
-      return launch_smaj_t<jj, double, true>(s, reinterpret_cast<const double*>(ut), K, N, cst, \
-                                             gk, h, logD, part, part_obj, part_flags, num_cus,  \
-                                             grid_out);                                         \
-    if (f32)                                                                                   \
-      return launch_smaj_t<jj, float, false>(s, reinterpret_cast<const float*>(ut), K, N, cst,  \
-                                             gk, h, logD, part, part_obj, part_flags, num_cus,  \
-                                             grid_out);                                         \
-    return launch_smaj_t<jj, double, false>(s, reinterpret_cast<const double*>(ut), K, N, cst,  \
-                                            gk, h, logD, part, part_obj, part_flags, num_cus,   \
-                                            grid_out);                                          \
+      return f32 ? launch_smaj_t<jj, float, true, false>(s, uf, BUMBAR_SMAJ_ARGS)              \
+                 : launch_smaj_t<jj, double, true, false>(s, ud, BUMBAR_SMAJ_ARGS);            \
+    if (nan_check)                                                                             \
+      return f32 ? launch_smaj_t<jj, float, false, true>(s, uf, BUMBAR_SMAJ_ARGS)              \
+                 : launch_smaj_t<jj, double, false, true>(s, ud, BUMBAR_SMAJ_ARGS);            \
+    return f32 ? launch_smaj_t<jj, float, false, false>(s, uf, BUMBAR_SMAJ_ARGS)               \
+               : launch_smaj_t<jj, double, false, false>(s, ud, BUMBAR_SMAJ_ARGS);             \
   }
   BUMBAR_SMAJ(5)
   BUMBAR_SMAJ(6)
@@ -263,26 +287,32 @@ hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_a
   BUMBAR_SMAJ(14)
   BUMBAR_SMAJ(16)
 #undef BUMBAR_SMAJ
+#undef BUMBAR_SMAJ_ARGS
   return hipErrorInvalidValue;
 }
 
 // Transpose u (K x N, row stride ld) into the sample-major copy (N x Kp,
 // states past K = +inf) through 64 x 64 LDS tiles: both the reads (along n)
 // and the writes (along k) are coalesced.
+// With nan_flag, a NaN anywhere in u sets *nan_flag (the solve checks its
+// copy once here instead of in every sweep).
 template <typename TI>
 __global__ void __launch_bounds__(256)
     smaj_copy_kernel(const TI* __restrict__ u, int64_t ld, int K, int64_t N, int Kp,
-                     TI* __restrict__ ut) {
+                     TI* __restrict__ ut, unsigned* __restrict__ nan_flag) {
   __shared__ TI tile[64][65];
   const int64_t n0 = (int64_t)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  bool nan_seen = false;
   for (int r = ty; r < 64; r += 4) {
     const int k = k0 + r;
     const int64_t n = n0 + tx;
-    tile[r][tx] = (k < K && n < N) ? u[(int64_t)k * ld + n] : (TI)INFINITY;
+    const TI v = (k < K && n < N) ? u[(int64_t)k * ld + n] : (TI)INFINITY;
+    nan_seen = nan_seen || v != v;
+    tile[r][tx] = v;
   }
-  __syncthreads();
+  if (__syncthreads_or(nan_seen) && nan_flag && threadIdx.x == 0) atomicOr(nan_flag, 1u);
   for (int r = ty; r < 64; r += 4) {
     const int64_t n = n0 + r;
     const int k = k0 + tx;
@@ -291,17 +321,17 @@ __global__ void __launch_bounds__(256)
 }
 
 hipError_t launch_smaj_copy(hipStream_t s, const void* u, bool f32, int64_t ld, int K, int64_t N,
-                            void* ut) {
+                            void* ut, unsigned* nan_flag) {
   const int Kp = smaj_row(K);
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)(Kp / 64));
   if (f32)
     hipLaunchKernelGGL(smaj_copy_kernel<float>, grid, dim3(256), 0, s,
                        reinterpret_cast<const float*>(u), ld, K, N, Kp,
-                       reinterpret_cast<float*>(ut));
+                       reinterpret_cast<float*>(ut), nan_flag);
   else
     hipLaunchKernelGGL(smaj_copy_kernel<double>, grid, dim3(256), 0, s,
                        reinterpret_cast<const double*>(u), ld, K, N, Kp,
-                       reinterpret_cast<double*>(ut));
+                       reinterpret_cast<double*>(ut), nan_flag);
   return hipGetLastError();
 }
 

@@ -150,3 +150,15 @@ def test_newton_from_poor_start_weak_overlap(bm):
     assert info["status"] == 0
     assert info["damped_steps"] + info["sci_fallbacks"] >= 1
     assert np.max(np.abs(f.cpu().numpy() - f_ref)) < 1e-9
+
+
+def test_nan_in_u_is_refused(bm):
+    # the solve's copy is checked for NaN once; a caller's copy in every sweep
+    p = synth.harmonic_1d(K=300, Nk=10, seed=3)
+    u = p["u"].copy()
+    u[123, 456] = np.nan
+    with pytest.raises(bm.BumbarError) as e:
+        bm.solve(dev(u), p["Nk"], tol=1e-10)
+    assert e.value.code == bm.EINVAL
+    with pytest.raises(bm.BumbarError):
+        bm.sweep(bm.sample_major(dev(u)), p["Nk"], np.zeros(300))
