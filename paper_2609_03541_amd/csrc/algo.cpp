@@ -25,6 +25,8 @@ constexpr int kCountSlots = 8192;
 // the 1-D width search keeps its device state at counts + kCountSlots / 2
 static_assert(sizeof(WidthSearch1D) <= sizeof(int64_t) * (kCountSlots / 2 - 1),
               "width-search state must fit below the last count slot");
+static_assert(sizeof(WidthSearch2D) <= sizeof(int64_t) * (kCountSlots / 2 - 1),
+              "width-search state must fit below the last count slot");
 
 // Bins per level whose centre representatives are materialised (K <= 256):
 // at least 65536, and N / 8, which covers the levels of nominal size up to
@@ -80,6 +82,7 @@ void binned_carve_size(Arena& ar, int K, int64_t N, int d, int num_cus, bool uba
 
 static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
   hipStream_t s = ctx->stream;
+  BB.g1 = -1;  // recounted for the new quantisation
   hipError_t e = launch_minmax(s, xi, BB.N, BB.d, BB.mm, BB.counts);
   if (e == hipSuccess)
     e = launch_quantize(s, xi, BB.N, BB.d, BB.mm, BB.lo, BB.scale, BB.q,
@@ -157,9 +160,13 @@ static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t*
 static int width_search(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_out,
                         int64_t* g_out) {
   if (BB.d == 1) return width_search_1d(ctx, BB, n, m_out, g_out);
-  int64_t g1 = 0;
-  int rc = nonempty(ctx, BB, 1, &g1);
-  if (rc) return rc;
+  // g(1) sorts all N cell ids; the coordinates do not change within a solve
+  int rc = BUMBAR_OK;
+  if (BB.g1 < 0) {
+    rc = nonempty(ctx, BB, 1, &BB.g1);
+    if (rc) return rc;
+  }
+  const int64_t g1 = BB.g1;
   if (g1 < n) {
     *m_out = 1;
     *g_out = g1;
@@ -167,6 +174,25 @@ static int width_search(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_
   }
   uint64_t lo = 1, hi = 4294967296ull;
   int64_t glo = g1;
+  // the probes whose grids fit the bitmap run on the device, queued back to
+  // back (32 bisection steps at most); the host takes over where a grid does
+  // not fit, from the same (lo, hi, g(lo))
+  {
+    auto* w = reinterpret_cast<WidthSearch2D*>(BB.counts + kCountSlots / 2);
+    hipError_t e = launch_width_search_2d(ctx->stream, BB.q, BB.N, n, g1, 33, true, BB.keys, w);
+    if (e != hipSuccess) return hip_fail(ctx, e, "width search");
+    WidthSearch2D h;
+    rc = read_bytes(ctx, w, &h, sizeof(h));
+    if (rc) return rc;
+    lo = h.lo;
+    hi = h.hi;
+    glo = h.glo;
+    if (h.done || hi - lo <= 1) {
+      *m_out = lo;
+      *g_out = glo;
+      return BUMBAR_OK;
+    }
+  }
   while (hi - lo > 1) {
     const uint64_t mid = lo + (hi - lo) / 2;
     int64_t gm = 0;

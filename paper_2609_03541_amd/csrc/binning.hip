@@ -5,12 +5,13 @@
 // Everything after quantisation is integer arithmetic, so the bins, counts
 // and the width found by the bisection are bit-identical to any correct
 // implementation of the same definitions. g(m) is computed from sorted keys
-// (distinct values are the run starts of a sorted sequence): in 1-D the
-// quantised coordinates are sorted once, because q -> q / m is monotone, so
+// (distinct values are the run starts of a sorted sequence) in 1-D, where the
+// quantised coordinates are sorted once because q -> q / m is monotone, so
 // every probe is a single pass over N integers; in 2-D the row-major cell id
-// is not monotone in (q_y, q_x) for all m, so each probe sorts the cell ids
-// (radix sort restricted to the bits the ids can occupy). The histogram
-// takes the run starts and run lengths of the same sorted sequence.
+// is not monotone in (q_y, q_x) for all m, so a probe marks the occupied
+// cells in a bitmap (LDS-privatised, integer atomics) and counts its bits,
+// or, for grids too large for the bitmap, sorts the cell ids. The histogram
+// takes the run starts and run lengths of the sorted cell ids.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -519,10 +520,14 @@ __global__ void __launch_bounds__(kBT)
     const uint64_t c = (uint64_t)div_by_magic(q[2 * n], m, magic) +
                        (uint64_t)div_by_magic(q[2 * n + 1], m, magic) * ncx;
     const uint32_t bit = 1u << (uint32_t)(c & 31u);
-    if (private_map)
-      atomicOr(&lw[c >> 5], bit);
-    else
-      atomicOr(&words[c >> 5], bit);
+    // bits are only ever set: a bit seen set is set, so its atomic is
+    // skipped (most samples land in cells already marked); a stale read only
+    // costs a redundant atomic
+    if (private_map) {
+      if (!(lw[c >> 5] & bit)) atomicOr(&lw[c >> 5], bit);
+    } else {
+      if (!(words[c >> 5] & bit)) atomicOr(&words[c >> 5], bit);
+    }
   }
   if (private_map) {
     __syncthreads();
@@ -559,6 +564,127 @@ static bool count_2d_uses_bitmap(int64_t N, uint64_t m) {
   const uint64_t g = grid_cells_2d(m);
   // the bitmap lives in the N x 8 bytes of the key buffer
   return g != 0 && g <= (uint64_t)N * 64ull;
+}
+
+// ---- 2-D width search on the device ------------------------------------
+//
+// The bisection of the host loop, one probe per pass, with every probe whose
+// grid fits the bitmap run on the device: zero the bitmap, mark the cells,
+// count the bits, and a one-thread walk takes the bisection step and prepares
+// the next probe (or ends the search, or hands it back to the host when the
+// next grid is too large for the bitmap). The passes are queued back to back;
+// the host reads the state once at the end.
+__device__ static void ws2_prepare(WidthSearch2D* w) {
+  const uint64_t mid = w->lo + (w->hi - w->lo) / 2;
+  const uint64_t ncx = 4294967295ull / mid + 1ull;
+  const bool fits = ncx <= (1ull << 31) && ncx * ncx <= w->cap_cells;
+  if (!fits) {
+    w->host = 1;
+    return;
+  }
+  w->m = mid;
+  w->magic = magic_of(mid);
+  w->ncx = ncx;
+  w->nw = (int64_t)((ncx * ncx + 31) / 32);
+  w->count = 0ull;
+}
+
+__global__ void ws2_init_kernel(WidthSearch2D* w, int64_t n, int64_t g1, uint64_t cap_cells) {
+  w->lo = 1;
+  w->hi = 4294967296ull;
+  w->glo = g1;
+  w->n = n;
+  w->cap_cells = cap_cells;
+  w->done = 0;
+  w->host = 0;
+  ws2_prepare(w);
+}
+
+__global__ void __launch_bounds__(kBT) ws2_zero_kernel(const WidthSearch2D* w, uint32_t* words) {
+  if (w->done || w->host) return;  // uniform
+  const int64_t nw = w->nw;
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBT)
+    words[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kBT)
+    ws2_mark_kernel(const uint32_t* __restrict__ q, int64_t N, const WidthSearch2D* w,
+                    uint32_t* __restrict__ words) {
+  if (w->done || w->host) return;  // uniform
+  __shared__ uint32_t lw[kLdsWords];
+  const uint64_t m = w->m, magic = w->magic, ncx = w->ncx;
+  const int64_t nw = w->nw;
+  const bool private_map = nw <= kLdsWords;  // uniform over the grid
+  if (private_map) {
+    for (int i = threadIdx.x; i < nw; i += kBT) lw[i] = 0u;
+    __syncthreads();
+  }
+  for (int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x; n < N; n += (int64_t)gridDim.x * kBT) {
+    const uint64_t c = (uint64_t)div_by_magic(q[2 * n], m, magic) +
+                       (uint64_t)div_by_magic(q[2 * n + 1], m, magic) * ncx;
+    const uint32_t bit = 1u << (uint32_t)(c & 31u);
+    if (private_map) {
+      if (!(lw[c >> 5] & bit)) atomicOr(&lw[c >> 5], bit);
+    } else {
+      if (!(words[c >> 5] & bit)) atomicOr(&words[c >> 5], bit);
+    }
+  }
+  if (private_map) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nw; i += kBT)
+      if (lw[i]) atomicOr(&words[i], lw[i]);
+  }
+}
+
+__global__ void __launch_bounds__(kBT)
+    ws2_popcount_kernel(const uint32_t* __restrict__ words, WidthSearch2D* w) {
+  if (w->done || w->host) return;  // uniform
+  __shared__ unsigned long long sh[kBT];
+  const int64_t nw = w->nw;
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBT)
+    c += (unsigned long long)__builtin_popcount(words[i]);
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int s2 = kBT / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sh[0]) atomicAdd(&w->count, sh[0]);
+}
+
+__global__ void ws2_walk_kernel(WidthSearch2D* w) {
+  if (w->done || w->host) return;
+  const int64_t gm = (int64_t)w->count;
+  if (gm >= w->n) {
+    w->lo = w->m;
+    w->glo = gm;
+  } else {
+    w->hi = w->m;
+  }
+  if (w->hi - w->lo <= 1) {
+    w->done = 1;
+    return;
+  }
+  ws2_prepare(w);
+}
+
+hipError_t launch_width_search_2d(hipStream_t s, const uint32_t* q, int64_t N, int64_t n,
+                                  int64_t g1, int passes, bool init, uint64_t* bitmap,
+                                  WidthSearch2D* w) {
+  if (passes < 1) return hipErrorInvalidValue;
+  // the bitmap lives in N x 8 bytes: at most 64 N cells
+  if (init) hipLaunchKernelGGL(ws2_init_kernel, dim3(1), dim3(1), 0, s, w, n, g1, (uint64_t)N * 64ull);
+  uint32_t* words = reinterpret_cast<uint32_t*>(bitmap);
+  const unsigned zb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (2 * N + kBT - 1) / kBT));
+  const unsigned mb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (N + kBT - 1) / kBT));
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(ws2_zero_kernel, dim3(zb), dim3(kBT), 0, s, w, words);
+    hipLaunchKernelGGL(ws2_mark_kernel, dim3(mb), dim3(kBT), 0, s, q, N, w, words);
+    hipLaunchKernelGGL(ws2_popcount_kernel, dim3(zb), dim3(kBT), 0, s, words, w);
+    hipLaunchKernelGGL(ws2_walk_kernel, dim3(1), dim3(1), 0, s, w);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,

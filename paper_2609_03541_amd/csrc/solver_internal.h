@@ -194,6 +194,7 @@ struct BinnedBufs {
   int64_t* start = nullptr;      // N + 1: first sorted position of each bin
   uint64_t* cells = nullptr;     // N: cell id of each bin
   int64_t* counts = nullptr;     // reduction scratch
+  int64_t g1 = -1;               // g(1), the distinct quantised points (once per solve)
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   bool otf = false;                      // representatives from the model in the kernels
@@ -259,6 +260,22 @@ struct WidthSearch1D {
 hipError_t launch_width_search_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N,
                                   int64_t n, int levels, int passes, bool init,
                                   WidthSearch1D* w);
+// The 2-D width search on the device: the same bisection, one probe per
+// pass, each probe an occupancy bitmap of its grid (at most 64 N cells, in
+// the N x 8-byte buffer `bitmap`); the walk ends the search (done) or hands
+// it back (host = 1) when the next grid does not fit. init starts it from
+// lo = 1 with g(1) = g1 given; `passes` passes are queued.
+struct WidthSearch2D {
+  uint64_t lo, hi;
+  int64_t glo, n;
+  uint64_t m, magic, ncx, cap_cells;
+  int64_t nw;
+  unsigned long long count;
+  int done, host;
+};
+hipError_t launch_width_search_2d(hipStream_t s, const uint32_t* q, int64_t N, int64_t n,
+                                  int64_t g1, int passes, bool init, uint64_t* bitmap,
+                                  WidthSearch2D* w);
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts);
