@@ -34,8 +34,14 @@ static_assert(sizeof(WidthSearch2D) <= sizeof(int64_t) * (kCountSlots / 2 - 1),
 // the model sweep at their centres. Two level slots of K x cap doubles then
 // cost 2 K N bytes at most beyond 65536 bins, not 16 K N.
 int64_t otf_ubar_cap(int K, int64_t N) {
-  return sweep_fast_supported(K) ? std::min<int64_t>(N, std::max<int64_t>(65536, N / 8)) : 0;
+  return sweep_fast_supported(K) || sweep_smaj_supported(K)
+             ? std::min<int64_t>(N, std::max<int64_t>(65536, N / 8))
+             : 0;
 }
+
+// Values per bin of a materialised level: K (state-major, K <= 256) or the
+// sample-major row Kp (256 < K <= 1024).
+static int level_row(int K) { return sweep_fast_supported(K) ? K : smaj_row(K); }
 
 void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,
                        bool cen_bufs, bool cen_f32, int64_t otf_cap) {
@@ -65,10 +71,11 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
     if (ubar_bufs)
       ubar[i] = ar.take<double>((size_t)K * N);
     else if (otf_cap > 0)
-      ubar[i] = ar.take<double>((size_t)K * otf_cap);
+      ubar[i] = ar.take<double>((size_t)level_row(K) * otf_cap);
     h[i] = ar.take<double>(N);
   }
   ubar_cap = ubar_bufs ? N : otf_cap;
+  ubar_row = ubar_bufs ? K : level_row(K);
   logD_lvl = ar.take<double>(N);
   f_n = ar.take<double>(K);
   f_x = ar.take<double>(K);
@@ -333,16 +340,22 @@ static int build_level(bumbar_ctx* ctx, BinnedBufs& BB, int K, int64_t n, int mo
                          BB.cells, BB.start, BB.perm, u, BB.ubar[slot], BB.h[slot]);
   if (e == hipSuccess && BB.otf && BB.cenf[slot])
     e = launch_pack_coords(ctx->stream, P * BB.d, BB.cen[slot], BB.cenf[slot]);
-  // a small on-the-fly level: the centre representatives once, then the
-  // steps of the level are one-pass sweeps over them
+  // a level of at most ubar_cap bins with bin-centre representatives: the
+  // representatives once (state-major for K <= 256, sample-major above), then
+  // the steps of the level are one-pass sweeps over them
   const bool mat = BB.otf && BB.ubar[slot] && P <= BB.ubar_cap;
-  if (e == hipSuccess && mat)
+  const bool smaj = mat && BB.ubar_row != K;
+  if (e == hipSuccess && mat && !smaj)
     e = launch_represent(ctx->stream, K, BB.N, BB.d, model, coef, BB.lo, BB.scale, m, P, BB.cells,
                          BB.start, BB.perm, nullptr, BB.ubar[slot], BB.h[slot]);
+  if (e == hipSuccess && smaj)
+    e = launch_represent_smaj(ctx->stream, K, BB.ubar_row, BB.d, model, coef, P, BB.cen[slot],
+                              BB.ubar[slot]);
   if (e != hipSuccess) return hip_fail(ctx, e, "represent");
   L->n = n;
   L->m = m;
   L->P = P;
+  L->smaj = smaj;
   L->ubar = (!BB.otf || mat) ? BB.ubar[slot] : nullptr;
   L->cen = BB.otf ? BB.cen[slot] : nullptr;
   L->cenf = BB.otf ? BB.cenf[slot] : nullptr;
@@ -368,6 +381,12 @@ static Mat level_mat_of(const Level& L, const Mat* otf_base, bool fp32) {
   M.u = L.ubar;
   M.kind = 0;
   M.ld = L.P;
+  if (L.smaj) {
+    // the sample-major sweep over the level's rows (finite model values)
+    M.ut = L.ubar;
+    M.ut_f32 = false;
+    M.ut_checked = true;
+  }
   return M;
 }
 
@@ -431,7 +450,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   int64_t batched = 0;
   auto small_level = [&](const Level& L) {
     const Mat M = level_mat(L);
-    return M.kind == 0 && M.u != nullptr && small_batch_nc(K, L.P) != 0;
+    return M.kind == 0 && M.u != nullptr && M.ut == nullptr && small_batch_nc(K, L.P) != 0;
   };
   auto small_batch = [&](const Level& L, const double* fin, int T) -> int {
     const Mat M = level_mat(L);

@@ -858,6 +858,43 @@ hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, c
   return hipGetLastError();
 }
 
+// The same bin-centre representatives in the sample-major layout of the
+// 256 < K <= 1024 sweeps: row p holds the Kp values model_k(centre_p) (+inf
+// past K), from the centres of centres_kernel and the arithmetic of
+// represent_kernel, so the values are those of the state-major form.
+__global__ void __launch_bounds__(kBT)
+    represent_smaj_kernel(int K, int Kp, int d, int model, const double* __restrict__ coef,
+                          int64_t P, const double* __restrict__ cen, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (e >= (int64_t)Kp * P) return;
+  const int64_t p = e / Kp;
+  const int k = (int)(e % Kp);
+  if (k >= K) {
+    out[e] = INFINITY;
+    return;
+  }
+  const double* ck = coef + (int64_t)k * (1 + 2 * d);
+  double v = ck[0];
+  for (int j = 0; j < d; ++j) {
+    const double x = cen[p * d + j];
+    if (model == BUMBAR_MODEL_LINEAR) {
+      v += ck[1 + j] * x;
+    } else {
+      const double dx = x - ck[2 + 2 * j];
+      v += 0.5 * ck[1 + 2 * j] * dx * dx;
+    }
+  }
+  out[e] = v;
+}
+
+hipError_t launch_represent_smaj(hipStream_t s, int K, int Kp, int d, int model,
+                                 const double* coef, int64_t P, const double* cen, double* out) {
+  const int64_t tot = (int64_t)Kp * P;
+  hipLaunchKernelGGL(represent_smaj_kernel, dim3((unsigned)((tot + kBT - 1) / kBT)), dim3(kBT), 0,
+                     s, K, Kp, d, model, coef, P, cen, out);
+  return hipGetLastError();
+}
+
 // Bin centres (P x d) and multiplicities of the current histogram: the
 // coordinates at which the bias model gives the bin representative (the
 // same centre as in represent_kernel), for sweeps that evaluate the model

@@ -171,7 +171,8 @@ struct Level {
   int64_t n = 0;   // nominal target
   uint64_t m = 0;  // width in quanta
   int64_t P = 0;   // nonempty bins
-  double* ubar = nullptr;  // K x P (row stride P); stored representatives
+  double* ubar = nullptr;  // K x P (row stride P), or P x Kp (smaj); stored representatives
+  bool smaj = false;       // ubar in the sample-major layout (256 < K <= 1024)
   double* cen = nullptr;   // P x d bin centres; representatives from the model
   float* cenf = nullptr;   // the same centres in FP32 (mixed precision), or null
   double* h = nullptr;     // P multiplicities (as double)
@@ -203,6 +204,7 @@ struct BinnedBufs {
   // materialised (one model evaluation per level) and step like stored ones
   double* ubar[2] = {nullptr, nullptr};
   int64_t ubar_cap = 0;
+  int ubar_row = 0;  // values per bin of a materialised level: K, or Kp sample-major
   double* cen[2] = {nullptr, nullptr};   // N x d each (worst case P = N); otf mode
   float* cenf[2] = {nullptr, nullptr};   // FP32 copies of cen (mixed precision)
   double* h[2] = {nullptr, nullptr};     // N each
@@ -293,6 +295,10 @@ hipError_t launch_represent(hipStream_t s, int K, int64_t N, int d, int model, c
 hipError_t launch_centres(hipStream_t s, int d, const double* lo, const double* scale, uint64_t m,
                           int64_t P, const uint64_t* cells, const int64_t* start, double* cen,
                           double* h);
+// out (P x Kp) = model_k(cen_p), +inf past K: bin-centre representatives in
+// the sample-major layout.
+hipError_t launch_represent_smaj(hipStream_t s, int K, int Kp, int d, int model,
+                                 const double* coef, int64_t P, const double* cen, double* out);
 hipError_t launch_sample_bin(hipStream_t s, int64_t N, const uint32_t* perm,
                              const int32_t* bin_of_pos, int32_t* sample_bin);
 hipError_t launch_counts_from_start(hipStream_t s, int64_t P, const int64_t* start, int64_t* H);
