@@ -201,7 +201,9 @@ struct HessSource {
   int64_t ld = 0;
   const double* m0 = nullptr;
   OtfModel otf;
+  void* p16 = nullptr;  // kinds 5, 8: K x p16_row(N) FP16 scratch for P materialised once, or null
 };
+int64_t p16_row(int64_t N);  // halves per row of the materialised P (N rounded up to 8)
 hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
                           const double* S, double* partials, int chunks, double* H);

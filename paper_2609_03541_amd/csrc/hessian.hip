@@ -618,33 +618,106 @@ struct SrcModel32f {
   }
 };
 
+// P materialised once per Hessian (FP16, K rows of ldp samples, ldp a
+// multiple of 8): p16_fill_kernel writes exactly the values the SrcMatH fill
+// would form, so the product reads them instead of recomputing every
+// exponential for each of the block rows a state belongs to.
+struct SrcP16 {
+  const _Float16* p;
+  int64_t ld;
+  struct Row {
+    const _Float16* p;
+  };
+  __device__ Row row(int k, double) const { return {p + (int64_t)k * ld}; }
+};
+template <class Src>
+struct FillDirect {
+  static constexpr bool value = false;
+};
+template <>
+struct FillDirect<SrcP16> {
+  static constexpr bool value = true;
+};
+
+// P_kn = fp16(exp2(fp32(log2(e) (c_k - u_kn)) + e_n)) for sampled states k,
+// 0 otherwise (the arithmetic of SrcMatH and fill16), written as K rows of
+// ldp halves; samples past N are 0. One thread per 8 samples of a row.
+template <typename TI>
+__global__ void __launch_bounds__(256)
+    p16_fill_kernel(int K, int64_t N, const TI* __restrict__ u, int64_t ld,
+                    const double* __restrict__ cst, const double* __restrict__ gk,
+                    const float* __restrict__ colv, int64_t ldp, _Float16* __restrict__ P) {
+  const int64_t per_row = ldp / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)K * per_row) return;
+  const int k = (int)(e / per_row);
+  const int64_t n0 = (e % per_row) * 8;
+  const bool on = gk[k] != 0.0;
+  const double c = on ? cst[k] : 0.0;
+  const TI* row = u + (int64_t)k * ld;
+  h8v v;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t n = n0 + q;
+    float x = 0.f;
+    if (on && n < N)
+      x = __builtin_amdgcn_exp2f((float)(kLog2eH * (c - (double)row[n])) + colv[n]);
+    v[q] = (_Float16)x;
+  }
+  *reinterpret_cast<h8v*>(P + (int64_t)k * ldp + n0) = v;
+}
+
 // 16 FP16 values of P for one row: exp2 of the exponents, zero for an
 // unsampled row or samples past the chunk end.
 template <class Src>
 __device__ __forceinline__ void fill16(const Src& src, const typename Src::Row& rw, bool on,
                                        int64_t n, int64_t n_end, bool vec,
                                        const float* __restrict__ colv, h8v& lo, h8v& hi) {
-  float t[16];
-  if (n + 16 <= n_end) {
-    src.full(rw, n, vec, colv, t);
+  if constexpr (FillDirect<Src>::value) {
+    // materialised P: rows of a multiple of 8 halves, zero past N
+    if (n + 16 <= n_end) {
+      lo = *reinterpret_cast<const h8v*>(rw.p + n);
+      hi = *reinterpret_cast<const h8v*>(rw.p + n + 8);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const _Float16 h = (_Float16)(on ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
-      if (q < 8)
-        lo[q] = h;
-      else
-        hi[q - 8] = h;
+      for (int q = 0; q < 16; ++q) {
+        const _Float16 h = n + q < n_end ? rw.p[n + q] : (_Float16)0.f;
+        if (q < 8)
+          lo[q] = h;
+        else
+          hi[q - 8] = h;
+      }
+    }
+    if (!on) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        lo[q] = (_Float16)0.f;
+        hi[q] = (_Float16)0.f;
+      }
     }
   } else {
-    src.tail(rw, n, n_end - 1, colv, t);
+    float t[16];
+    if (n + 16 <= n_end) {
+      src.full(rw, n, vec, colv, t);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const bool ok = on && n + q < n_end;
-      const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
-      if (q < 8)
-        lo[q] = h;
-      else
-        hi[q - 8] = h;
+      for (int q = 0; q < 16; ++q) {
+        const _Float16 h = (_Float16)(on ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
+        if (q < 8)
+          lo[q] = h;
+        else
+          hi[q - 8] = h;
+      }
+    } else {
+      src.tail(rw, n, n_end - 1, colv, t);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const bool ok = on && n + q < n_end;
+        const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
+        if (q < 8)
+          lo[q] = h;
+        else
+          hi[q - 8] = h;
+      }
     }
   }
 }
@@ -764,6 +837,8 @@ __global__ void __launch_bounds__(256)
 }
 
 static int h16_nb(int K) { return (K + XB - 1) / XB; }
+
+int64_t p16_row(int64_t N) { return (N + 7) / 8 * 8; }
 
 static int h16_chunks(int K, int64_t N, int num_cus) {
   // one workgroup per CU at a time: pick the chunk count in [2, 8] rounds of
@@ -897,6 +972,22 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
       hipLaunchKernelGGL(hessian_h16_kernel<SrcPacked32>, g16, dim3(512), 0, s,
                          SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
                          cst, gk, colv, nb16, ch16, len16, vec, p16);
+    } else if ((hs.kind == 5 || hs.kind == 8) && hs.p16) {
+      // P once (FP16, K x ldp), then the product reads it
+      const int64_t ldp = p16_row(N);
+      const int64_t tot = (int64_t)K * (ldp / 8);
+      const dim3 gf((unsigned)((tot + 255) / 256));
+      if (hs.kind == 5)
+        hipLaunchKernelGGL(p16_fill_kernel<double>, gf, dim3(256), 0, s, K, N,
+                           reinterpret_cast<const double*>(hs.u), hs.ld, cst, gk, colv, ldp,
+                           reinterpret_cast<_Float16*>(hs.p16));
+      else
+        hipLaunchKernelGGL(p16_fill_kernel<float>, gf, dim3(256), 0, s, K, N,
+                           reinterpret_cast<const float*>(hs.u), hs.ld, cst, gk, colv, ldp,
+                           reinterpret_cast<_Float16*>(hs.p16));
+      hipLaunchKernelGGL(hessian_h16_kernel<SrcP16>, g16, dim3(512), 0, s,
+                         SrcP16{reinterpret_cast<const _Float16*>(hs.p16), ldp}, K, N, cst, gk,
+                         colv, nb16, ch16, len16, true, p16);
     } else if (hs.kind == 5) {
       hipLaunchKernelGGL(hessian_h16_kernel<SrcMatH<double>>, g16, dim3(512), 0, s,
                          SrcMatH<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,

@@ -265,6 +265,7 @@ static hipError_t queue_hessian(bumbar_ctx* ctx, UnbinnedBufs& B, const Mat& M, 
   hs.u = M.u;
   hs.ld = M.ld;
   hs.otf = M.otf;
+  hs.p16 = M.p16;
   const double* cst = B.cst;
   hipError_t e = hipSuccess;
   if (hk == 2) {
@@ -1039,7 +1040,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (opt.binning) BB.otf = rep == BUMBAR_REPRESENT_CENTRE;
   // every buffer a planned path launches with must have been carved
   if ((plan.x_packed && !X.r) || (plan.copy && !pb.copy) || (plan.o_bufs && !O.cf64) ||
-      (plan.fp32_binned && !BB.cenf[0]) || (plan.xi_wide && !pb.xi64))
+      (plan.fp32_binned && !BB.cenf[0]) || (plan.xi_wide && !pb.xi64) || (plan.p16 && !pb.p16))
     return fail(ctx, BUMBAR_EINVAL, "internal: a planned buffer was not carved");
   // the coordinates every kernel reads: the caller's FP64 array, or FP32
   // coordinates widened (exactly) into the workspace
@@ -1175,7 +1176,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
   // stored u: the planned Newton Hessian source (it only shapes the steps;
   // the FP64 sweeps decide the fixed point)
-  if (!otf) Mfin.hess_kind = plan.hess_kind;
+  if (!otf) {
+    Mfin.hess_kind = plan.hess_kind;
+    Mfin.p16 = pb.p16;
+  }
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
       if (mixed && otf && !M.otf.sep) {
@@ -1197,6 +1201,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
         Mat R = M;
         R.kind = 7;
         R.hess_kind = plan.hess_kind32;
+        R.p16 = pb.p16;
         const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
         const int64_t before = st->finisher_steps;
         int mrc = newton_finish(ctx, B, R, N_k, mtol, opt.max_newton, st, &cnt, &st->final_step,
