@@ -197,12 +197,18 @@ void bumbar_default_options(bumbar_options* opt);
 /* ---- workspace -------------------------------------------------------- */
 
 /* Bytes of device workspace bumbar_solve needs for a K x N problem with
- * d-dimensional binning coordinates (d = 0 if no binning). */
+ * d-dimensional binning coordinates (d = 0 if no binning). With K > 256 and
+ * the Newton finisher this includes the sample-tiled FP16 copy of P that the
+ * FP16-core Hessian reads: 2 K min(N, 2^31 / K) bytes. */
 int bumbar_query_workspace(const bumbar_ctx* ctx, int K, int64_t N, int d,
                            const bumbar_options* opt, size_t* bytes);
 
 /* Bytes of device workspace bumbar_solve needs when u_kn is NULL (energies
- * from the model, d-dimensional coordinates, d in {1, 2}). */
+ * from the model, d-dimensional coordinates, d in {1, 2}). opt NULL: enough
+ * for a binned Newton solve at either precision, and for bumbar_sweep_model
+ * and bumbar_hessian_model at either. With K > 256 and precision MIXED the
+ * Newton Hessian holds a sample-tiled FP16 copy of P in the workspace:
+ * 2 K min(N, 2^31 / K) bytes (longer problems are taken in super-chunks). */
 int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
                                  const bumbar_options* opt, size_t* bytes);
 
@@ -321,6 +327,19 @@ int bumbar_sweep(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
 int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
                    int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
                    const double* S, void* workspace, size_t ws_bytes, double* H);
+
+/*
+ * The same Hessian as the Newton steps build it for K > 256 (Section 2, the
+ * derivative-based finisher; it only shapes the steps): P rounded to FP16
+ * into a sample-tiled copy in the workspace, G = P P^T on the FP16 matrix
+ * cores with FP32 sums inside a sample chunk and FP64 across chunks. Same
+ * arguments as bumbar_hessian; K > 256 (else BUMBAR_EINVAL), u_dtype
+ * BUMBAR_F64 or BUMBAR_F32. Workspace: bumbar_query_workspace(ctx, K, N, 0,
+ * NULL) bytes. Does not synchronise.
+ */
+int bumbar_hessian_fp16(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                        int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
+                        const double* S, void* workspace, size_t ws_bytes, double* H);
 
 /*
  * The same single sweep and Hessian with u_kn taken from the model (the

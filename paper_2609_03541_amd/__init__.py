@@ -312,8 +312,9 @@ def sweep(u, Nk, f, ld=None, ctx=None, with_stats=True, want_logD=True):
     return f_new, lD, S, st
 
 
-def hessian(u, Nk, f, logD, S, ctx=None):
-    """K x K Hessian of the MBAR objective at f (FP64 MFMA)."""
+def hessian(u, Nk, f, logD, S, ctx=None, fp16=False):
+    """K x K Hessian of the MBAR objective at f (FP64 MFMA; fp16=True: the
+    FP16-core Hessian of the K > 256 Newton steps)."""
     torch = _torch()
     ctx = ctx or context()
     dev = u.device
@@ -323,8 +324,9 @@ def hessian(u, Nk, f, logD, S, ctx=None):
     # keep every marshalled tensor alive until the queued kernels have run
     Nk_t = _dev(Nk, torch.int64, dev)
     f_t = _dev(f, torch.float64, dev)
-    rc = ctx.lib.bumbar_hessian(ctx.h, _ptr(u), _dtype_code(u), K, N, u.stride(0), _ptr(Nk_t),
-                                _ptr(f_t), _ptr(logD), _ptr(S), _ptr(ws), ws.numel(), _ptr(H))
+    fn = ctx.lib.bumbar_hessian_fp16 if fp16 else ctx.lib.bumbar_hessian
+    rc = fn(ctx.h, _ptr(u), _dtype_code(u), K, N, u.stride(0), _ptr(Nk_t), _ptr(f_t),
+            _ptr(logD), _ptr(S), _ptr(ws), ws.numel(), _ptr(H))
     ctx.check(rc)
     _keep(ctx, Nk_t, f_t)
     return H

@@ -122,6 +122,8 @@ SIGNATURES = {
                                C.c_size_t, vp, vp, vp, dp]),
     "bumbar_hessian": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp, vp,
                                  vp, C.c_size_t, vp]),
+    "bumbar_hessian_fp16": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,
+                                      vp, vp, C.c_size_t, vp]),
     "bumbar_query_workspace_covariance": (C.c_int, [vp, C.c_int, C.c_int64,
                                                     C.POINTER(C.c_size_t)]),
     "bumbar_covariance": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int64, C.c_int64, vp, vp, vp,

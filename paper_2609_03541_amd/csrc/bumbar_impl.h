@@ -201,9 +201,12 @@ struct HessSource {
   int64_t ld = 0;
   const double* m0 = nullptr;
   OtfModel otf;
-  void* p16 = nullptr;  // kinds 5, 8: K x p16_row(N) FP16 scratch for P materialised once, or null
+  void* p16 = nullptr;  // kinds 3, 5, 8 with K > 256: the sample-tiled FP16 copy of P,
+                        // K x p16_samples(K, N) halves
 };
-int64_t p16_row(int64_t N);  // halves per row of the materialised P (N rounded up to 8)
+// samples of P held per super-chunk by the FP16-core Hessian: N rounded up to
+// whole 32-sample tiles, capped at 4 GiB of FP16
+int64_t p16_samples(int K, int64_t N);
 hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
                           const double* cst, const double* gk, const double* logD,
                           const double* S, double* partials, int chunks, double* H);

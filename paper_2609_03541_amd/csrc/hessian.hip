@@ -437,134 +437,54 @@ static int small_chunks(int64_t N, int num_cus) {
 // ---- mixed precision, K > 256: FP16 matrix cores ----------------------------
 //
 // The Hessian only shapes the Newton steps (the fixed point is set by the
-// FP64 gradient), so in mixed precision P is formed in FP32 (exp2 of an
-// exponent in log2 units) and rounded to FP16 (P_kn lies in [0, 1]:
-// sum_k P_kn = 1), and G = P P^T runs on v_mfma_f32_16x16x32_f16 with FP32
-// accumulation inside a sample chunk and FP64 across chunks.
+// FP64 gradient), so for K > 256 P is formed in FP32 (exp2 of an exponent in
+// log2 units), rounded to FP16 (P_kn lies in [0, 1]: sum_k P_kn = 1), and
+// G = P P^T runs on v_mfma_f32_16x16x32_f16 with FP32 accumulation inside a
+// sample chunk and FP64 across chunks.
 //
-// A workgroup (8 waves) owns one 256 x 256 output block (bi <= bj) and one
-// sample chunk. Per step of 32 samples it forms the two 256 x 32 slabs of P
-// (rows of block bi and of block bj) in LDS:
-//  * fill: lane l of wave w computes one row of one slab (w / 4 selects the
-//    slab, 64 (w % 4) + l the row) over the step's samples, which are the
-//    same for the whole wave, so the per-sample values (column constant,
-//    coordinates) are wave-uniform scalar loads and each element costs a few
-//    FMAs and one exp2; on a diagonal block the two wave halves split the
-//    samples of the one slab instead;
-//  * product: wave w accumulates the 64 x 128 output tile (rows 64 (w % 4),
-//    columns 128 (w / 4)) as 4 x 8 MFMA tiles.
-// The slabs are double-buffered: the fill of step s + 1 (VALU) is issued
-// between the matrix instructions of step s, one barrier per step.
+// P is materialised once per Hessian: forming it inside the product would
+// recompute every exponential for each 256-row block a state belongs to
+// (7.8 times over at K = 1600), which left the matrix cores idle behind the
+// VALU. The FP16 copy is sample-tiled: tile t holds samples 32 t .. 32 t + 31
+// of every state, state k at (t K + k) 32 halves, so the 256-row slab of a
+// block at one tile is a contiguous 16 KB run. At most 4 GiB of it is held;
+// longer problems are filled and multiplied super-chunk by super-chunk, the
+// product adding into the same partial blocks.
+//
+// Product: a workgroup (8 waves) owns one 256 x 256 output block (bi <= bj)
+// and one chunk of tiles. Per tile it copies the two slabs (one on a diagonal
+// block) into LDS, 1 KB per wave instruction, and wave w accumulates the
+// 64 x 128 output tile (rows 64 (w % 4), columns 128 (w / 4)) as 4 x 8 MFMA
+// tiles; MFMA tiles wholly past K are skipped. LDS is double-buffered (the
+// next tile's loads are in flight during the matrix instructions), one
+// barrier per tile. The hardware deals workgroups to the 8 XCDs round robin;
+// the grid is ordered so that the workgroups one XCD runs together are all
+// block pairs of one sample chunk, which then share the slabs in that XCD's
+// L2 instead of each pulling them from HBM.
 // Operand layout (checked on the hardware): A lane l holds row l % 16,
 // k = 8 (l / 16) .. + 7; B lane l holds column l % 16, the same k; the
 // accumulator lane l holds rows 4 (l / 16) + i, column l % 16.
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef float f4a __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr int XB = 256;      // output block edge
-constexpr int XS = 32;       // samples per step (one MFMA k-extent)
+constexpr int XS = 32;       // samples per tile (one MFMA k-extent)
 constexpr int XP = XS + 8;   // padded LDS row (halves): rows 80 bytes apart
 constexpr double kLog2eH = 1.4426950408889634;
+constexpr int64_t kP16Bytes = int64_t(1) << 32;  // cap of the FP16 copy of P
 
 // Per-sample column constant in log2 units, once per Hessian:
-//   packed FP32 matrix  c_n = log2(e) (ln D_n - m0_n)
-//   FP32 model          c_n = -log2(e) ln D_n       (m0 == nullptr)
+// c_n = -log2(e) ln D_n.
 __global__ void __launch_bounds__(256)
-    h16_colv_kernel(int64_t N, const double* __restrict__ logD, const double* __restrict__ m0,
-                    float* __restrict__ colv) {
+    h16_colv_kernel(int64_t N, const double* __restrict__ logD, float* __restrict__ colv) {
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
-  colv[n] = m0 ? (float)(kLog2eH * (logD[n] - m0[n])) : (float)(-kLog2eH * logD[n]);
+  colv[n] = (float)(-kLog2eH * logD[n]);
 }
 
-// Sources of the exponents t_kn (log2 units) of 16 consecutive samples n ..
-// n + 15 of one row: full() when all 16 lie in the chunk (the per-sample
-// values are contiguous wave-uniform runs, read in batches of 8 by scalar
-// loads), tail() otherwise (indices clamped to the chunk's last sample; the
-// caller zeroes those values).
-
-// Packed FP32 matrix: t_kn = log2(e) r_kn + d_k - c_n.
-struct SrcPacked32 {
-  const float* r;
-  int64_t ld;
-  const double* m0;
-  struct Row {
-    const float* p;
-    float d;
-  };
-  __device__ Row row(int k, double dk) const {
-    return {r + (int64_t)k * ld, (float)(kLog2eH * dk)};
-  }
-  __device__ void full(const Row& rw, int64_t n, bool vec, const float* __restrict__ colv,
-                       float (&t)[16]) const {
-    float x[16];
-    if (vec) {
-#pragma unroll
-      for (int q = 0; q < 16; q += 4) {
-        const f4v v = *reinterpret_cast<const f4v*>(rw.p + n + q);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) x[q + i] = v[i];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] = rw.p[n + q];
-    }
-#pragma unroll
-    for (int h = 0; h < 16; h += 8) {
-      float cv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) cv[q] = colv[n + h + q];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t[h + q] = __builtin_fmaf(x[h + q], 1.44269504f, rw.d - cv[q]);
-    }
-  }
-  __device__ void tail(const Row& rw, int64_t n, int64_t last, const float* __restrict__ colv,
-                       float (&t)[16]) const {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t m = n + q < last ? n + q : last;
-      t[q] = __builtin_fmaf(rw.p[m], 1.44269504f, rw.d - colv[m]);
-    }
-  }
-};
-
-// Stored FP64 or FP32 u: t_kn = log2(e) (c_k - u_kn) + e_n with
-// e_n = -log2(e) ln D_n; the difference is taken in FP64 per element and the
-// product rounded to FP32.
-template <typename TI>
-struct SrcMatH {
-  const TI* u;
-  int64_t ld;
-  struct Row {
-    const TI* p;
-    double c;
-  };
-  __device__ Row row(int k, double ck) const { return {u + (int64_t)k * ld, ck}; }
-  __device__ void full(const Row& rw, int64_t n, bool, const float* __restrict__ colv,
-                       float (&t)[16]) const {
-#pragma unroll
-    for (int h = 0; h < 16; h += 8) {
-      double x[8];
-      float cv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        x[q] = (double)rw.p[n + h + q];
-        cv[q] = colv[n + h + q];
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t[h + q] = (float)(kLog2eH * (rw.c - x[q])) + cv[q];
-    }
-  }
-  __device__ void tail(const Row& rw, int64_t n, int64_t last, const float* __restrict__ colv,
-                       float (&t)[16]) const {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t m = n + q < last ? n + q : last;
-      t[q] = (float)(kLog2eH * (rw.c - (double)rw.p[m])) + colv[m];
-    }
-  }
-};
+// Exponents t_kn (log2 units) of 16 consecutive samples n .. n + 15 of one
+// row: full() when all 16 lie before the end, tail() otherwise (indices
+// clamped to the last sample; the caller zeroes those values).
 
 // FP32 model (the log2-domain coefficients of the FP32 model sweeps):
 // t_kn = A_k + e_n + sum_j x_nj (B_jk + C_jk x_nj), e_n = -log2(e) ln D_n.
@@ -576,7 +496,7 @@ struct SrcModel32f {
   struct Row {
     float a, b[D], c[D];
   };
-  __device__ Row row(int k, double) const {
+  __device__ Row row(int k) const {
     Row rw;
     rw.a = cf[K + k];
 #pragma unroll
@@ -592,7 +512,7 @@ struct SrcModel32f {
     for (int j = 0; j < D; ++j) v = __builtin_fmaf(__builtin_fmaf(rw.c[j], x[j], rw.b[j]), x[j], v);
     return v;
   }
-  __device__ void full(const Row& rw, int64_t n, bool, const float* __restrict__ colv,
+  __device__ void full(const Row& rw, int64_t n, const float* __restrict__ colv,
                        float (&t)[16]) const {
 #pragma unroll
     for (int h = 0; h < 16; h += 8) {
@@ -618,197 +538,210 @@ struct SrcModel32f {
   }
 };
 
-// P materialised once per Hessian (FP16, K rows of ldp samples, ldp a
-// multiple of 8): p16_fill_kernel writes exactly the values the SrcMatH fill
-// would form, so the product reads them instead of recomputing every
-// exponential for each of the block rows a state belongs to.
-struct SrcP16 {
-  const _Float16* p;
-  int64_t ld;
-  struct Row {
-    const _Float16* p;
-  };
-  __device__ Row row(int k, double) const { return {p + (int64_t)k * ld}; }
-};
-template <class Src>
-struct FillDirect {
-  static constexpr bool value = false;
-};
-template <>
-struct FillDirect<SrcP16> {
-  static constexpr bool value = true;
-};
+// Model fill: one thread per 16 samples of one state of one tile, states
+// fastest, so a wave writes 2 KB of the tiled copy in one run (the per-sample
+// coordinates and column constants are shared by the wave's lanes).
+// Samples [n_begin, n_end) as tiles 0 .. nt - 1; past n_end the copy is 0,
+// and so are the rows of unsampled states.
+template <int D>
+__global__ void __launch_bounds__(256)
+    p16t_fill_model_kernel(SrcModel32f<D> src, int K, int64_t n_begin, int64_t n_end, int64_t nt,
+                           const double* __restrict__ gk, const float* __restrict__ colv,
+                           _Float16* __restrict__ P) {
+  const int64_t per_tile = (int64_t)K * (XS / 16);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nt * per_tile) return;
+  const int64_t t = e / per_tile;
+  const int r = (int)(e - t * per_tile);
+  const int k = r / (XS / 16);
+  const int q = r % (XS / 16);
+  const bool on = gk[k] != 0.0;
+  const typename SrcModel32f<D>::Row rw = src.row(k);
+  const int64_t n = n_begin + t * XS + q * 16;
+  float x[16];
+  if (n + 16 <= n_end)
+    src.full(rw, n, colv, x);
+  else
+    src.tail(rw, n, n_end - 1, colv, x);
+  h8v lo, hi;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const bool ok = on && n + j < n_end;
+    const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(x[j]) : 0.f);
+    if (j < 8)
+      lo[j] = h;
+    else
+      hi[j - 8] = h;
+  }
+  _Float16* dst = P + (t * K + k) * XS + q * 16;
+  *reinterpret_cast<h8v*>(dst) = lo;
+  *reinterpret_cast<h8v*>(dst + 8) = hi;
+}
 
-// P_kn = fp16(exp2(fp32(log2(e) (c_k - u_kn)) + e_n)) for sampled states k,
-// 0 otherwise (the arithmetic of SrcMatH and fill16), written as K rows of
-// ldp halves; samples past N are 0. One thread per 8 samples of a row.
+// Stored FP64 or FP32 u: P_kn = fp16(exp2(fp32(log2(e) (c_k - u_kn)) + e_n)),
+// the difference taken in FP64. A workgroup (4 waves) converts 16 states x
+// 256 samples (8 tiles): each wave reads its 4 rows along n (16 bytes per
+// lane, 1 KB of one row per instruction), forms the values in registers,
+// transposes them through LDS, and the workgroup writes each tile's 16 rows
+// as one 1 KB run. vec: rows 16-byte aligned (else element loads).
 template <typename TI>
 __global__ void __launch_bounds__(256)
-    p16_fill_kernel(int K, int64_t N, const TI* __restrict__ u, int64_t ld,
-                    const double* __restrict__ cst, const double* __restrict__ gk,
-                    const float* __restrict__ colv, int64_t ldp, _Float16* __restrict__ P) {
-  const int64_t per_row = ldp / 8;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)K * per_row) return;
-  const int k = (int)(e / per_row);
-  const int64_t n0 = (e % per_row) * 8;
-  const bool on = gk[k] != 0.0;
-  const double c = on ? cst[k] : 0.0;
-  const TI* row = u + (int64_t)k * ld;
-  h8v v;
+    p16t_fill_stored_kernel(const TI* __restrict__ u, int64_t ld, bool vec, int K,
+                            int64_t n_begin, int64_t n_end, int64_t nt,
+                            const double* __restrict__ cst, const double* __restrict__ gk,
+                            const float* __restrict__ colv, _Float16* __restrict__ P) {
+  constexpr int R = 16, C = 256, CP = C + 8;
+  constexpr int V = 16 / (int)sizeof(TI);  // elements per 16-byte load
+  constexpr int NI = C / (64 * V);         // loads per row
+  __shared__ __attribute__((aligned(16))) _Float16 T[R][CP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k0 = blockIdx.y * R;
+  const int64_t s0 = n_begin + (int64_t)blockIdx.x * C;  // first sample of the block
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int64_t n = n0 + q;
-    float x = 0.f;
-    if (on && n < N)
-      x = __builtin_amdgcn_exp2f((float)(kLog2eH * (c - (double)row[n])) + colv[n]);
-    v[q] = (_Float16)x;
-  }
-  *reinterpret_cast<h8v*>(P + (int64_t)k * ldp + n0) = v;
-}
-
-// 16 FP16 values of P for one row: exp2 of the exponents, zero for an
-// unsampled row or samples past the chunk end.
-template <class Src>
-__device__ __forceinline__ void fill16(const Src& src, const typename Src::Row& rw, bool on,
-                                       int64_t n, int64_t n_end, bool vec,
-                                       const float* __restrict__ colv, h8v& lo, h8v& hi) {
-  if constexpr (FillDirect<Src>::value) {
-    // materialised P: rows of a multiple of 8 halves, zero past N
-    if (n + 16 <= n_end) {
-      lo = *reinterpret_cast<const h8v*>(rw.p + n);
-      hi = *reinterpret_cast<const h8v*>(rw.p + n + 8);
-    } else {
+  for (int rr = 0; rr < 4; ++rr) {
+    const int r = wave * 4 + rr;
+    const int k = k0 + r;
+    const bool on = k < K && gk[k] != 0.0;
+    const double c = on ? cst[k] : 0.0;
+    const TI* row = u + (int64_t)(on ? k : 0) * ld;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const _Float16 h = n + q < n_end ? rw.p[n + q] : (_Float16)0.f;
-        if (q < 8)
-          lo[q] = h;
-        else
-          hi[q - 8] = h;
+    for (int i = 0; i < NI; ++i) {
+      const int s = (i * 64 + lane) * V;  // sample within the block
+      const int64_t n = s0 + s;
+      TI x[V];
+      if (on && vec && n + V <= n_end) {
+        if constexpr (V == 2) {
+          const double2 w = *reinterpret_cast<const double2*>(row + n);
+          x[0] = w.x;
+          x[1] = w.y;
+        } else {
+          const float4 w = *reinterpret_cast<const float4*>(row + n);
+          x[0] = w.x;
+          x[1] = w.y;
+          x[2] = w.z;
+          x[3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) x[j] = (on && n + j < n_end) ? row[n + j] : (TI)0;
       }
-    }
-    if (!on) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        lo[q] = (_Float16)0.f;
-        hi[q] = (_Float16)0.f;
-      }
-    }
-  } else {
-    float t[16];
-    if (n + 16 <= n_end) {
-      src.full(rw, n, vec, colv, t);
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const _Float16 h = (_Float16)(on ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
-        if (q < 8)
-          lo[q] = h;
-        else
-          hi[q - 8] = h;
-      }
-    } else {
-      src.tail(rw, n, n_end - 1, colv, t);
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const bool ok = on && n + q < n_end;
-        const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(t[q]) : 0.f);
-        if (q < 8)
-          lo[q] = h;
-        else
-          hi[q - 8] = h;
+      for (int j = 0; j < V; ++j) {
+        const bool ok = on && n + j < n_end;
+        const float cv = ok ? colv[n + j] : 0.f;
+        T[r][s + j] =
+            (_Float16)(ok ? __builtin_amdgcn_exp2f((float)(kLog2eH * (c - (double)x[j])) + cv)
+                          : 0.f);
       }
     }
   }
+  __syncthreads();
+  // tile tl (0..7) of the block, row r, 16-sample half hf: 32 bytes per thread
+  const int tl = threadIdx.x >> 5, r = (threadIdx.x >> 1) & 15, hf = threadIdx.x & 1;
+  const int64_t t = (int64_t)blockIdx.x * (C / XS) + tl;
+  const int k = k0 + r;
+  if (t >= nt || k >= K) return;
+  const h8v lo = *reinterpret_cast<const h8v*>(&T[r][tl * XS + hf * 16]);
+  const h8v hi = *reinterpret_cast<const h8v*>(&T[r][tl * XS + hf * 16 + 8]);
+  _Float16* dst = P + (t * K + k) * XS + hf * 16;
+  *reinterpret_cast<h8v*>(dst) = lo;
+  *reinterpret_cast<h8v*>(dst + 8) = hi;
 }
 
-template <class Src>
-__device__ __forceinline__ void h16_fill(const Src& src, const typename Src::Row& rw, bool on,
-                                         bool diag, int64_t n, int64_t n_end, bool vec,
-                                         const float* __restrict__ colv, h8v& v0, h8v& v1,
-                                         h8v& v2, h8v& v3) {
-  fill16(src, rw, on, n, n_end, vec, colv, v0, v1);
-  if (!diag) fill16(src, rw, on, n + 16, n_end, vec, colv, v2, v3);
-}
-
-__device__ __forceinline__ void h16_store(_Float16* row, bool diag, const h8v& v0, const h8v& v1,
-                                          const h8v& v2, const h8v& v3) {
-  *reinterpret_cast<h8v*>(row) = v0;
-  *reinterpret_cast<h8v*>(row + 8) = v1;
-  if (!diag) {
-    *reinterpret_cast<h8v*>(row + 16) = v2;
-    *reinterpret_cast<h8v*>(row + 24) = v3;
-  }
-}
-
-template <class Src>
+// G over the tiles of one super-chunk; see the section comment. partials:
+// one 256 x 256 FP32 block per (block pair, chunk), written (accumulate
+// false) or added to.
 __global__ void __launch_bounds__(512)
-    hessian_h16_kernel(Src src, int K, int64_t N, const double* __restrict__ cst,
-                       const double* __restrict__ gk, const float* __restrict__ colv, int nb,
-                       int chunks, int64_t chunk_len, bool vec, float* __restrict__ partials) {
-  __shared__ __attribute__((aligned(16))) _Float16 P[2][2][XB][XP];  // [buffer][slab][row][sample]
-  const int blk = blockIdx.x / chunks;
-  const int chunk = blockIdx.x % chunks;
+    hessian_p16t_kernel(const _Float16* __restrict__ P, int K, int64_t nt, int nb, int nblk,
+                        int chunks, int64_t per, bool accumulate, float* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) _Float16 L[2][2][XB][XP];  // [buffer][slab][row][sample]
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, slot = wg >> 3;
+  const int chunk = (slot / nblk) * 8 + xcd;
+  const int blk = slot % nblk;
   int bi, bj;
   block_coords(blk, nb, bi, bj);
   const bool diag = (bi == bj);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // fill role
-  const int slab = diag ? 0 : (wave >> 2);
-  const int frow = (wave & 3) * 64 + lane;
-  const int s0 = diag ? (wave >> 2) * 16 : 0;
-  const int k = (slab ? bj : bi) * XB + frow;
-  const bool on = k < K && gk[k] != 0.0;
-  const typename Src::Row rw = src.row(on ? k : 0, on ? cst[k] : 0.0);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // copy role: 16-byte piece c = tid + 512 j of the tile's slabs (slab j / 2,
+  // row (c % 1024) / 4, quarter c % 4); a diagonal block has one slab
+  const int nj = diag ? 2 : 4;
+  const int crow = (tid & 1023) >> 2, cq = tid & 3;
   // product role: output rows 64 wr + 16 a, columns 128 wc + 16 b
   const int wr = wave & 3, wc = wave >> 2;
   const int kq = (lane >> 4) * 8;
+  const int ra = K - (bi * XB + wr * 64), cb = K - (bj * XB + wc * 128);
+  const int na = ra <= 0 ? 0 : (ra >= 64 ? 4 : (ra + 15) / 16);
+  const int nbv = cb <= 0 ? 0 : (cb >= 128 ? 8 : (cb + 15) / 16);
   f4v acc[4][8];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
 
-  const int64_t n_begin = (int64_t)chunk * chunk_len;
-  const int64_t n_end = n_begin + chunk_len < N ? n_begin + chunk_len : N;
-  h8v v0, v1, v2, v3;
-  if (n_begin < n_end) {
-    h16_fill(src, rw, on, diag, n_begin + s0, n_end, vec, colv, v0, v1, v2, v3);
-    h16_store(&P[0][slab][frow][s0], diag, v0, v1, v2, v3);
+  const int64_t t_begin = (int64_t)chunk * per;
+  const int64_t t_end = t_begin + per < nt ? t_begin + per : nt;
+  h8v v[4];
+  auto load = [&](int64_t t) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < nj) {
+        const int k = ((j >> 1) ? bj : bi) * XB + crow + (j & 1) * 128;
+        v[j] = (h8v){};
+        if (k < K) v[j] = *reinterpret_cast<const h8v*>(P + (t * K + k) * XS + cq * 8);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nj)
+        *reinterpret_cast<h8v*>(&L[buf][j >> 1][crow + (j & 1) * 128][cq * 8]) = v[j];
+  };
+  if (t_begin < t_end) {
+    load(t_begin);
+    store(0);
   }
   __syncthreads();
   int cur = 0;
-  for (int64_t n0 = n_begin; n0 < n_end; n0 += XS) {
-    const bool more = n0 + XS < n_end;
-    if (more) h16_fill(src, rw, on, diag, n0 + XS + s0, n_end, vec, colv, v0, v1, v2, v3);
-    const _Float16(*Pa)[XP] = P[cur][0];
-    const _Float16(*Pb)[XP] = P[cur][diag ? 0 : 1];
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const bool more = t + 1 < t_end;
+    if (more) load(t + 1);
+    const _Float16(*Pa)[XP] = L[cur][0];
+    const _Float16(*Pb)[XP] = L[cur][diag ? 0 : 1];
     h8v av[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       av[a] = *reinterpret_cast<const h8v*>(&Pa[wr * 64 + a * 16 + (lane & 15)][kq]);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const h8v bv = *reinterpret_cast<const h8v*>(&Pb[wc * 128 + b * 16 + (lane & 15)][kq]);
+      if (b < nbv) {
+        const h8v bv = *reinterpret_cast<const h8v*>(&Pb[wc * 128 + b * 16 + (lane & 15)][kq]);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
+        for (int a = 0; a < 4; ++a)
+          if (a < na)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
+      }
     }
-    if (more) h16_store(&P[cur ^ 1][slab][frow][s0], diag, v0, v1, v2, v3);
+    if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
   }
-  float* out = partials + (int64_t)blockIdx.x * XB * XB;
+  float* out = partials + ((int64_t)blk * chunks + chunk) * XB * XB;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wr * 64 + a * 16 + (lane >> 4) * 4 + v;
+      for (int q = 0; q < 4; ++q) {
+        const int r = wr * 64 + a * 16 + (lane >> 4) * 4 + q;
         const int c = wc * 128 + b * 16 + (lane & 15);
-        out[r * XB + c] = acc[a][b][v];
+        if (accumulate)
+          out[r * XB + c] += acc[a][b][q];
+        else
+          out[r * XB + c] = acc[a][b][q];
       }
 }
 
@@ -838,30 +771,38 @@ __global__ void __launch_bounds__(256)
 
 static int h16_nb(int K) { return (K + XB - 1) / XB; }
 
-int64_t p16_row(int64_t N) { return (N + 7) / 8 * 8; }
+int64_t p16_samples(int K, int64_t N) {
+  // whole tiles, at most kP16Bytes of FP16 (K halves per sample)
+  const int64_t all = (N + XS - 1) / XS * XS;
+  int64_t cap = kP16Bytes / (2 * (int64_t)K) / XS * XS;
+  if (cap < XS) cap = XS;
+  return all < cap ? all : cap;
+}
 
 static int h16_chunks(int K, int64_t N, int num_cus) {
-  // one workgroup per CU at a time: pick the chunk count in [2, 8] rounds of
-  // the grid whose last round is fullest (ties: fewer chunks), each chunk at
-  // least 1024 samples
+  // chunks = 8 m (the XCD-ordered grid takes a multiple of 8): per XCD the
+  // nblk m workgroups run on num_cus / 8 CUs, one each at a time; pick the m
+  // in [1, 16] whose last round is fullest (ties: fewer chunks), each chunk at
+  // least 16 tiles of the super-chunk
   const int nb = h16_nb(K);
   const int nblk = nb * (nb + 1) / 2;
-  const int64_t by_n = (N + 1023) / 1024;
-  const int lo = (2 * num_cus + nblk - 1) / nblk, hi = (8 * num_cus + nblk - 1) / nblk;
-  int best = lo;
+  const int per_xcd = num_cus / 8 > 0 ? num_cus / 8 : 1;
+  const int64_t tiles = p16_samples(K, N) / XS;
+  int64_t m_max = tiles / (8 * 16);
+  if (m_max > 16) m_max = 16;
+  if (m_max < 1) m_max = 1;
+  int best = 1;
   double best_eff = 0.0;
-  for (int ch = lo; ch <= hi; ++ch) {
-    const int64_t wgs = (int64_t)nblk * ch;
-    const int64_t rounds = (wgs + num_cus - 1) / num_cus;
-    const double eff = (double)wgs / (double)(rounds * num_cus);
+  for (int m = 1; m <= m_max; ++m) {
+    const int64_t wgs = (int64_t)nblk * m;
+    const int64_t rounds = (wgs + per_xcd - 1) / per_xcd;
+    const double eff = (double)wgs / (double)(rounds * per_xcd);
     if (eff > best_eff + 1e-9) {
       best_eff = eff;
-      best = ch;
+      best = m;
     }
   }
-  int64_t ch = best;
-  if (ch > by_n) ch = by_n;
-  return (int)(ch < 1 ? 1 : ch);
+  return 8 * best;
 }
 
 // H_ij = delta_ij S_i - sum_chunks G_ij, written to both triangles.
@@ -906,8 +847,8 @@ size_t hessian_partial_count(int K, int64_t N, int num_cus, int* chunks_out) {
   if (chunks < 1) chunks = 1;
   if (chunks_out) *chunks_out = chunks;
   // room for the FP16-core path of the mixed-precision sources as well
-  const int nb16 = h16_nb(K);
   // (FP32 partial blocks, then the N per-sample column constants)
+  const int nb16 = h16_nb(K);
   const size_t h16 =
       (size_t)(nb16 * (nb16 + 1) / 2) * h16_chunks(K, N, num_cus) * XB * XB + (size_t)N + 64;
   const size_t fp64 = (size_t)nblk * chunks * HB * HB;
@@ -956,54 +897,49 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
   const int nblk = nb * (nb + 1) / 2;
   int64_t chunk_len = (N + chunks - 1) / chunks;
   chunk_len = (chunk_len + HS - 1) / HS * HS;
-  if (K > kSmallMaxK && (hs.kind == 2 || hs.kind == 3 || hs.kind == 5 || hs.kind == 8)) {
+  if (K > kSmallMaxK && (hs.kind == 3 || hs.kind == 5 || hs.kind == 8)) {
+    // P once into the tiled FP16 copy (per super-chunk), then the product
+    if (!hs.p16) return hipErrorInvalidValue;
     const int nb16 = h16_nb(K);
     const int nblk16 = nb16 * (nb16 + 1) / 2;
     const int ch16 = h16_chunks(K, N, hs.num_cus);
-    int64_t len16 = (N + ch16 - 1) / ch16;
-    len16 = (len16 + XS - 1) / XS * XS;
+    const int64_t len = p16_samples(K, N);
     float* p16 = reinterpret_cast<float*>(partials);
     float* colv = p16 + (size_t)nblk16 * ch16 * XB * XB;
-    const dim3 g16(nblk16 * ch16);
+    _Float16* P = reinterpret_cast<_Float16*>(hs.p16);
     hipLaunchKernelGGL(h16_colv_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N,
-                       logD, hs.kind == 2 ? hs.m0 : nullptr, colv);
-    if (hs.kind == 2) {
-      const bool vec = ((hs.ld & 3) == 0) && ((reinterpret_cast<uintptr_t>(hs.u) & 15) == 0);
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcPacked32>, g16, dim3(512), 0, s,
-                         SrcPacked32{reinterpret_cast<const float*>(hs.u), hs.ld, hs.m0}, K, N,
-                         cst, gk, colv, nb16, ch16, len16, vec, p16);
-    } else if ((hs.kind == 5 || hs.kind == 8) && hs.p16) {
-      // P once (FP16, K x ldp), then the product reads it
-      const int64_t ldp = p16_row(N);
-      const int64_t tot = (int64_t)K * (ldp / 8);
-      const dim3 gf((unsigned)((tot + 255) / 256));
-      if (hs.kind == 5)
-        hipLaunchKernelGGL(p16_fill_kernel<double>, gf, dim3(256), 0, s, K, N,
-                           reinterpret_cast<const double*>(hs.u), hs.ld, cst, gk, colv, ldp,
-                           reinterpret_cast<_Float16*>(hs.p16));
-      else
-        hipLaunchKernelGGL(p16_fill_kernel<float>, gf, dim3(256), 0, s, K, N,
-                           reinterpret_cast<const float*>(hs.u), hs.ld, cst, gk, colv, ldp,
-                           reinterpret_cast<_Float16*>(hs.p16));
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcP16>, g16, dim3(512), 0, s,
-                         SrcP16{reinterpret_cast<const _Float16*>(hs.p16), ldp}, K, N, cst, gk,
-                         colv, nb16, ch16, len16, true, p16);
-    } else if (hs.kind == 5) {
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcMatH<double>>, g16, dim3(512), 0, s,
-                         SrcMatH<double>{reinterpret_cast<const double*>(hs.u), hs.ld}, K, N, cst,
-                         gk, colv, nb16, ch16, len16, false, p16);
-    } else if (hs.kind == 8) {
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcMatH<float>>, g16, dim3(512), 0, s,
-                         SrcMatH<float>{reinterpret_cast<const float*>(hs.u), hs.ld}, K, N, cst,
-                         gk, colv, nb16, ch16, len16, false, p16);
-    } else if (hs.otf.d == 1) {
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<1>>, g16, dim3(512), 0, s,
-                         SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
-                         ch16, len16, false, p16);
-    } else {
-      hipLaunchKernelGGL(hessian_h16_kernel<SrcModel32f<2>>, g16, dim3(512), 0, s,
-                         SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, N, cst, gk, colv, nb16,
-                         ch16, len16, false, p16);
+                       logD, colv);
+    const int esz = hs.kind == 5 ? 8 : 4;
+    const bool vec = hs.kind != 3 && (hs.ld % (16 / esz)) == 0 &&
+                     (reinterpret_cast<uintptr_t>(hs.u) & 15) == 0;
+    for (int64_t n0 = 0; n0 < N; n0 += len) {
+      const int64_t n1 = n0 + len < N ? n0 + len : N;
+      const int64_t nt = (n1 - n0 + XS - 1) / XS;
+      if (hs.kind == 3) {
+        const int64_t tot = nt * K * (XS / 16);
+        const dim3 gf((unsigned)((tot + 255) / 256));
+        if (hs.otf.d == 1)
+          hipLaunchKernelGGL(p16t_fill_model_kernel<1>, gf, dim3(256), 0, s,
+                             SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, n0, n1, nt, gk, colv,
+                             P);
+        else
+          hipLaunchKernelGGL(p16t_fill_model_kernel<2>, gf, dim3(256), 0, s,
+                             SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, n0, n1, nt, gk, colv,
+                             P);
+      } else {
+        const dim3 gf((unsigned)((nt + 7) / 8), (unsigned)((K + 15) / 16));
+        if (hs.kind == 5)
+          hipLaunchKernelGGL(p16t_fill_stored_kernel<double>, gf, dim3(256), 0, s,
+                             reinterpret_cast<const double*>(hs.u), hs.ld, vec, K, n0, n1, nt,
+                             cst, gk, colv, P);
+        else
+          hipLaunchKernelGGL(p16t_fill_stored_kernel<float>, gf, dim3(256), 0, s,
+                             reinterpret_cast<const float*>(hs.u), hs.ld, vec, K, n0, n1, nt,
+                             cst, gk, colv, P);
+      }
+      const int64_t per = (nt + ch16 - 1) / ch16;
+      hipLaunchKernelGGL(hessian_p16t_kernel, dim3(nblk16 * ch16), dim3(512), 0, s, P, K, nt,
+                         nb16, nblk16, ch16, per, n0 > 0, p16);
     }
     hipLaunchKernelGGL(hessian_h16_reduce_kernel, dim3(XB * XB / 256, nblk16), dim3(256), 0, s, K,
                        nb16, ch16, p16, S, gk, H);

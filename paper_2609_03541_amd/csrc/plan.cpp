@@ -127,13 +127,12 @@ int make_plan(const bumbar_options& opt, bool otf, int u_dtype, int K, int64_t N
   if (!otf) {
     p->hess_kind = K > 256 ? (f32 ? 8 : 5) : (f32 ? 1 : 6);
     p->hess_kind32 = p->stage32 == BUMBAR_STAGE32_PACKED ? 2 : p->hess_kind;
-    // FP64 u with 256 < K <= 1024: P is materialised once per Hessian in
-    // FP16 (2 bytes per element of u) instead of being recomputed for every
-    // block row (c2 finisher 50 -> 30 ms). FP32 storage keeps the direct
-    // fill: there the copy did not pay (its fill reads half the bytes).
-    p->p16 = p->hess_kind == 5 && sweep_smaj_supported(K) &&
-             opt.finisher == BUMBAR_FINISH_NEWTON;
   }
+  // the FP16-core Newton Hessian (stored u with K > 256, the FP32 model with
+  // K > 256) reads P from a sample-tiled FP16 copy filled once per Hessian
+  // (at most 4 GiB; longer problems are taken in super-chunks)
+  if (opt.finisher == BUMBAR_FINISH_NEWTON && K > 256)
+    p->p16 = otf ? p->mixed : true;
   return BUMBAR_OK;
 }
 
@@ -145,7 +144,7 @@ void carve_plan(Arena& ar, const Plan& p, int num_cus, PlanBufs* pb) {
   if (p.o_bufs) pb->O.carve(ar, p.K, p.N, p.d);
   if (p.copy) pb->copy = ar.take<char>(p.copy_bytes());
   if (p.xi_wide) pb->xi64 = ar.take<double>((size_t)p.N * p.d);
-  if (p.p16) pb->p16 = ar.take<char>((size_t)p.K * (size_t)p16_row(p.N) * 2);
+  if (p.p16) pb->p16 = ar.take<char>((size_t)p.K * (size_t)p16_samples(p.K, p.N) * 2);
 }
 
 }  // namespace bumbar

@@ -667,6 +667,35 @@ int bumbar_hessian(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_
   return BUMBAR_OK;
 }
 
+int bumbar_hessian_fp16(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
+                        int64_t ld, const int64_t* N_k, const double* f, const double* log_D_n,
+                        const double* S, void* workspace, size_t ws_bytes, double* H) {
+  int rc = check_common(ctx, u_kn, u_dtype, K, N, ld);
+  if (rc) return rc;
+  if (K <= 256) return fail(ctx, BUMBAR_EINVAL, "the FP16-core Hessian takes K > 256");
+  if (u_dtype != BUMBAR_F64 && u_dtype != BUMBAR_F32)
+    return fail(ctx, BUMBAR_EINVAL, "u_dtype must be BUMBAR_F64 or BUMBAR_F32");
+  if (!N_k || !f || !log_D_n || !S || !H || !workspace)
+    return fail(ctx, BUMBAR_EINVAL, "NULL argument");
+  Arena ar{reinterpret_cast<char*>(workspace), ws_bytes};
+  UnbinnedBufs B;
+  B.carve(ar, K, N, ctx->num_cus);
+  char* p16 = ar.take<char>((size_t)K * (size_t)p16_samples(K, N) * 2);
+  if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small");
+  hipError_t e = launch_prepare_consts(ctx->stream, K, N_k, f, B.cst, B.gk, B.lnNp);
+  HessSource hs;
+  hs.kind = u_dtype == BUMBAR_F32 ? 8 : 5;
+  hs.num_cus = ctx->num_cus;
+  hs.u = u_kn;
+  hs.ld = ld;
+  hs.p16 = p16;
+  if (e == hipSuccess)
+    e = launch_hessian(ctx->stream, hs, K, N, B.cst, B.gk, log_D_n, S, B.hess_parts,
+                       B.hess_chunks, H);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hessian");
+  return BUMBAR_OK;
+}
+
 static void carve_cov(Arena& ar, UnbinnedBufs& B, int K, int64_t N, int num_cus, double** Th,
                       double** Bm) {
   B.carve(ar, K, N, num_cus);
@@ -837,6 +866,9 @@ static int model_setup(bumbar_ctx* ctx, int K, int64_t N, int d, int model, cons
   B->carve(ar, K, N, ctx->num_cus);
   OtfBufs O;
   O.carve(ar, K, N, d);
+  // the FP32 model's Hessian on the FP16 matrix cores reads a tiled FP16 copy of P
+  if (precision == BUMBAR_PREC_MIXED && K > 256)
+    M->p16 = ar.take<char>((size_t)K * (size_t)p16_samples(K, N) * 2);
   if (ar.overflow) return fail(ctx, BUMBAR_ENOMEM, "workspace too small (%zu bytes)", ws_bytes);
   M->kind = precision == BUMBAR_PREC_MIXED ? 3 : 4;
   M->otf.xi = xi;
@@ -898,6 +930,7 @@ int bumbar_hessian_model(bumbar_ctx* ctx, int K, int64_t N, int d, int model, co
   hs.kind = M.kind;
   hs.num_cus = ctx->num_cus;
   hs.otf = M.otf;
+  hs.p16 = M.p16;
   if (e == hipSuccess) e = launch_otf_coefs(ctx->stream, M.otf, M.kind == 3, K, B.cst, B.gk);
   if (e == hipSuccess)
     e = launch_hessian(ctx->stream, hs, K, N, B.cst, B.gk, log_D_n, S, B.hess_parts,
@@ -978,14 +1011,24 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
     bumbar_default_options(&o);
     o.binning = 1;
   }
-  Plan p;
-  std::string why;
-  if (make_plan(o, true, BUMBAR_F64, K, N, d, BUMBAR_MODEL_HARMONIC, &p, &why) != BUMBAR_OK)
-    return BUMBAR_EINVAL;
-  Arena ar;
-  PlanBufs pb;
-  carve_plan(ar, p, ctx->num_cus, &pb);
-  *bytes = ar.off + 256;
+  // without options: enough for the solve at either precision (and so for
+  // bumbar_sweep_model / bumbar_hessian_model at either)
+  size_t most = 0;
+  for (int pass = 0; pass < (opt ? 1 : 2); ++pass) {
+    if (!opt) {
+      o.precision = pass ? BUMBAR_PREC_MIXED : BUMBAR_PREC_FP64;
+      o.finisher = BUMBAR_FINISH_NEWTON;
+    }
+    Plan p;
+    std::string why;
+    if (make_plan(o, true, BUMBAR_F64, K, N, d, BUMBAR_MODEL_HARMONIC, &p, &why) != BUMBAR_OK)
+      return BUMBAR_EINVAL;
+    Arena ar;
+    PlanBufs pb;
+    carve_plan(ar, p, ctx->num_cus, &pb);
+    most = std::max(most, ar.off);
+  }
+  *bytes = most + 256;
   return BUMBAR_OK;
 }
 
@@ -1060,6 +1103,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->checks_capacity = chk_cap;
   hipStream_t s = ctx->stream;
   Mat M = input_mat(u_kn, u_dtype, N);
+  M.p16 = pb.p16;    // the FP16 copy of P for the Newton Hessian (K > 256), or null
   SepGrid sep_grid;  // product-grid factors of the model, when they apply
   hipError_t e;
   if (otf) {
@@ -1176,10 +1220,7 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   if (mixed && otf && M.otf.sep) Mfin.hess_kind = 3;
   // stored u: the planned Newton Hessian source (it only shapes the steps;
   // the FP64 sweeps decide the fixed point)
-  if (!otf) {
-    Mfin.hess_kind = plan.hess_kind;
-    Mfin.p16 = pb.p16;
-  }
+  if (!otf) Mfin.hess_kind = plan.hess_kind;
   if (stage_rc == BUMBAR_OK) {
     if (opt.finisher == BUMBAR_FINISH_NEWTON) {
       if (mixed && otf && !M.otf.sep) {
@@ -1201,7 +1242,6 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
         Mat R = M;
         R.kind = 7;
         R.hess_kind = plan.hess_kind32;
-        R.p16 = pb.p16;
         const double mtol = opt.mixed_tol > opt.tol ? opt.mixed_tol : opt.tol;
         const int64_t before = st->finisher_steps;
         int mrc = newton_finish(ctx, B, R, N_k, mtol, opt.max_newton, st, &cnt, &st->final_step,

@@ -46,7 +46,7 @@ struct Mat {
   const void* ut = nullptr;    // the sample-major copy the sweeps read (kinds 0, 1, 7), or null
   bool ut_f32 = false;         // its element type
   bool ut_checked = false;     // made by the solve (NaN checked once by the copy kernel)
-  void* p16 = nullptr;         // FP16 scratch for P of the FP16-core Hessian (kinds 5, 8), or null
+  void* p16 = nullptr;         // FP16 copy of P for the FP16-core Hessian (K > 256), or null
 };
 
 // Coordinates in FP32 and the per-sweep model coefficients of the
@@ -126,7 +126,7 @@ struct Plan {
   bool copy = false;         // sample-major copy of u in the workspace
   bool copy_f32 = false;     // its element type
   bool xi_wide = false;      // FP32 coordinates widened to FP64 in the workspace
-  bool p16 = false;          // FP16 P scratch (K x p16_row(N)) for the stored-u Newton Hessian
+  bool p16 = false;          // FP16 copy of P (K x p16_samples(K, N)) for the Newton Hessian
   // carve flags
   bool bb_ubar = false, bb_cen = false, bb_cen_f32 = false;
   int64_t bb_otf_cap = 0;
@@ -313,7 +313,7 @@ struct PlanBufs {
   OtfBufs O;
   void* copy = nullptr;
   double* xi64 = nullptr;  // N x d widened coordinates (xi_wide)
-  void* p16 = nullptr;     // K x p16_row(N) halves (Plan::p16)
+  void* p16 = nullptr;     // K x p16_samples(K, N) halves (Plan::p16)
 };
 void carve_plan(Arena& ar, const Plan& p, int num_cus, PlanBufs* pb);
 

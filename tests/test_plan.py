@@ -113,3 +113,28 @@ def test_level_representatives_bounded_by_a_fraction_of_u(bm):
     mean = bm.plan(K, N, represent=bm.REPRESENT_MEAN, **kw)
     assert cen["workspace_bytes"] < 4 * K * N  # less than the FP32 u itself
     assert mean["workspace_bytes"] > 16 * K * N
+
+
+def test_fp16_hessian_reads_a_tiled_copy_of_p(bm):
+    # K > 256 with the Newton finisher: the workspace holds the sample-tiled
+    # FP16 copy of P (2 K bytes per sample, N rounded up to 32-sample tiles,
+    # at most 2^31 / K samples: longer problems are taken in super-chunks);
+    # the SCI finisher builds no Hessian and carves none
+    K, N = 1000, 2_000_000
+    newton = bm.plan(K, N, sample_major=0, finisher=bm.FINISH_NEWTON)
+    sci = bm.plan(K, N, sample_major=0, finisher=bm.FINISH_SCI)
+    assert newton["hessian_fp16"] == 1
+    assert 0 <= newton["workspace_bytes"] - sci["workspace_bytes"] - 2 * K * N < 256
+    # a ragged N rounds up to whole tiles
+    r = bm.plan(K, 1001, finisher=bm.FINISH_NEWTON)
+    rs = bm.plan(K, 1001, finisher=bm.FINISH_SCI)
+    assert 0 <= r["workspace_bytes"] - rs["workspace_bytes"] - 2 * K * 1024 < 256
+    # the on-the-fly K = 1600 grid at N = 8e6: capped at 4 GiB
+    K, N = 1600, 8_000_000
+    cap = 2 * K * ((2 ** 31 // K) // 32 * 32)
+    mixed = bm.plan(K, N, d=2, model=bm.MODEL_HARMONIC, stored_u=False, binning=1,
+                    precision=bm.PREC_MIXED)
+    assert mixed["hessian_fp16"] == 1 and cap <= 2 ** 32
+    fp64 = bm.plan(K, N, d=2, model=bm.MODEL_HARMONIC, stored_u=False, binning=1)
+    assert mixed["workspace_bytes"] - fp64["workspace_bytes"] >= cap
+    assert mixed["workspace_bytes"] < fp64["workspace_bytes"] + cap + 2 * K * N
