@@ -538,44 +538,42 @@ struct SrcModel32f {
   }
 };
 
-// Model fill: one thread per 16 samples of one state of one tile, states
-// fastest, so a wave writes 2 KB of the tiled copy in one run (the per-sample
-// coordinates and column constants are shared by the wave's lanes).
-// Samples [n_begin, n_end) as tiles 0 .. nt - 1; past n_end the copy is 0,
-// and so are the rows of unsampled states.
+// Model fill: a wave takes 64 states of one tile (32 samples per lane), so
+// the per-sample coordinates and column constants are wave-uniform scalar
+// loads and each element costs the expanded quadratic, one exp2 and a
+// conversion. Kr = K rounded up to 64. Samples [n_begin, n_end) as tiles
+// 0 .. nt - 1; past n_end the copy is 0, and so are the rows of unsampled
+// states.
 template <int D>
 __global__ void __launch_bounds__(256)
-    p16t_fill_model_kernel(SrcModel32f<D> src, int K, int64_t n_begin, int64_t n_end, int64_t nt,
-                           const double* __restrict__ gk, const float* __restrict__ colv,
-                           _Float16* __restrict__ P) {
-  const int64_t per_tile = (int64_t)K * (XS / 16);
+    p16t_fill_model_kernel(SrcModel32f<D> src, int K, int Kr, int64_t n_begin, int64_t n_end,
+                           int64_t nt, const double* __restrict__ gk,
+                           const float* __restrict__ colv, _Float16* __restrict__ P) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nt * per_tile) return;
-  const int64_t t = e / per_tile;
-  const int r = (int)(e - t * per_tile);
-  const int k = r / (XS / 16);
-  const int q = r % (XS / 16);
+  const int64_t t = __builtin_amdgcn_readfirstlane((int)(e / Kr));
+  if (t >= nt) return;
+  const int k = (int)(e - t * Kr);
+  if (k >= K) return;
   const bool on = gk[k] != 0.0;
   const typename SrcModel32f<D>::Row rw = src.row(k);
-  const int64_t n = n_begin + t * XS + q * 16;
-  float x[16];
-  if (n + 16 <= n_end)
-    src.full(rw, n, colv, x);
-  else
-    src.tail(rw, n, n_end - 1, colv, x);
-  h8v lo, hi;
+  const int64_t n0 = n_begin + t * XS;
+  const bool whole = n0 + XS <= n_end;
+  _Float16* dst = P + (t * K + k) * XS;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const bool ok = on && n + j < n_end;
-    const _Float16 h = (_Float16)(ok ? __builtin_amdgcn_exp2f(x[j]) : 0.f);
-    if (j < 8)
-      lo[j] = h;
-    else
-      hi[j - 8] = h;
+  for (int h = 0; h < XS; h += 8) {
+    h8v v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t n = n0 + h + j;
+      const int64_t m = whole || n < n_end ? n : n_end - 1;
+      float x[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) x[i] = src.xf[m * D + i];
+      const float y = src.eval(rw, colv[m], x);
+      v[j] = (_Float16)((on && (whole || n < n_end)) ? __builtin_amdgcn_exp2f(y) : 0.f);
+    }
+    *reinterpret_cast<h8v*>(dst + h) = v;
   }
-  _Float16* dst = P + (t * K + k) * XS + q * 16;
-  *reinterpret_cast<h8v*>(dst) = lo;
-  *reinterpret_cast<h8v*>(dst + 8) = hi;
 }
 
 // Stored FP64 or FP32 u: P_kn = fp16(exp2(fp32(log2(e) (c_k - u_kn)) + e_n)),
@@ -597,41 +595,51 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k0 = blockIdx.y * R;
   const int64_t s0 = n_begin + (int64_t)blockIdx.x * C;  // first sample of the block
+  // all loads of the wave's 4 rows first (they are in flight together), then
+  // the arithmetic
+  TI x[4][NI][V];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int k = k0 + wave * 4 + rr;
+    const bool on = k < K;
+    const TI* row = u + (int64_t)(on ? k : 0) * ld;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int64_t n = s0 + (i * 64 + lane) * V;
+      if (on && vec && n + V <= n_end) {
+        if constexpr (V == 2) {
+          const double2 w = *reinterpret_cast<const double2*>(row + n);
+          x[rr][i][0] = w.x;
+          x[rr][i][1] = w.y;
+        } else {
+          const float4 w = *reinterpret_cast<const float4*>(row + n);
+          x[rr][i][0] = w.x;
+          x[rr][i][1] = w.y;
+          x[rr][i][2] = w.z;
+          x[rr][i][3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) x[rr][i][j] = (on && n + j < n_end) ? row[n + j] : (TI)0;
+      }
+    }
+  }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int r = wave * 4 + rr;
     const int k = k0 + r;
     const bool on = k < K && gk[k] != 0.0;
     const double c = on ? cst[k] : 0.0;
-    const TI* row = u + (int64_t)(on ? k : 0) * ld;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int s = (i * 64 + lane) * V;  // sample within the block
       const int64_t n = s0 + s;
-      TI x[V];
-      if (on && vec && n + V <= n_end) {
-        if constexpr (V == 2) {
-          const double2 w = *reinterpret_cast<const double2*>(row + n);
-          x[0] = w.x;
-          x[1] = w.y;
-        } else {
-          const float4 w = *reinterpret_cast<const float4*>(row + n);
-          x[0] = w.x;
-          x[1] = w.y;
-          x[2] = w.z;
-          x[3] = w.w;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) x[j] = (on && n + j < n_end) ? row[n + j] : (TI)0;
-      }
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const bool ok = on && n + j < n_end;
         const float cv = ok ? colv[n + j] : 0.f;
-        T[r][s + j] =
-            (_Float16)(ok ? __builtin_amdgcn_exp2f((float)(kLog2eH * (c - (double)x[j])) + cv)
-                          : 0.f);
+        T[r][s + j] = (_Float16)(
+            ok ? __builtin_amdgcn_exp2f((float)(kLog2eH * (c - (double)x[rr][i][j])) + cv) : 0.f);
       }
     }
   }
@@ -916,15 +924,16 @@ hipError_t launch_hessian(hipStream_t s, const HessSource& hs, int K, int64_t N,
       const int64_t n1 = n0 + len < N ? n0 + len : N;
       const int64_t nt = (n1 - n0 + XS - 1) / XS;
       if (hs.kind == 3) {
-        const int64_t tot = nt * K * (XS / 16);
+        const int Kr = (K + 63) / 64 * 64;
+        const int64_t tot = nt * Kr;
         const dim3 gf((unsigned)((tot + 255) / 256));
         if (hs.otf.d == 1)
           hipLaunchKernelGGL(p16t_fill_model_kernel<1>, gf, dim3(256), 0, s,
-                             SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, n0, n1, nt, gk, colv,
+                             SrcModel32f<1>{hs.otf.xf, hs.otf.cf32, K}, K, Kr, n0, n1, nt, gk, colv,
                              P);
         else
           hipLaunchKernelGGL(p16t_fill_model_kernel<2>, gf, dim3(256), 0, s,
-                             SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, n0, n1, nt, gk, colv,
+                             SrcModel32f<2>{hs.otf.xf, hs.otf.cf32, K}, K, Kr, n0, n1, nt, gk, colv,
                              P);
       } else {
         const dim3 gf((unsigned)((nt + 7) / 8), (unsigned)((K + 15) / 16));
