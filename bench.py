@@ -847,6 +847,8 @@ def run_mb2d(args, bm, synth):
     Nk = torch.tensor(p["Nk"], device="cuda")
     torch.cuda.synchronize()
     log(f"muller-brown grid generated in {time.time() - t:.1f}s: K={K} N={N}")
+    if args.copy_calibration:
+        _copy_calibration(torch)
     ctx = bm.context()
     f, infos, ms = _timed_solves(
         bm, args, "mixed",
@@ -869,8 +871,8 @@ def run_mb2d(args, bm, synth):
             gnorm = st["grad_norm"]
     elems = K * N
     # the dominant kernel of the solve: the FP16-core Hessian of the mixed
-    # stage (upper 256 x 256 blocks of K padded to a multiple of 256, 2 flops
-    # per product), timed on the context's stream
+    # stage, algorithmic flops K (K + 1) N (the symmetric product, no
+    # padding), timed on the context's stream
     bm.hessian_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, lD, S, precision=bm.PREC_MIXED, ctx=ctx)
     torch.cuda.synchronize()
     h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -882,8 +884,7 @@ def run_mb2d(args, bm, synth):
     h1.record()
     torch.cuda.synchronize()
     t_hess = h0.elapsed_time(h1) / reps / 1e3
-    nb = (K + 255) // 256
-    hflops = nb * (nb + 1) // 2 * 256 * 256 * N * 2
+    hflops = K * (K + 1) * N
     hrate = hflops / t_hess / 1e12
     # the solve's sweeps on this grid are the factored FP64 passes
     out = _base_line(args, elems / rates["f64"], "elem/s", ms, "f32+f64", {

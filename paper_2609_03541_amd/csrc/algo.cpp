@@ -57,8 +57,12 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
   keys_sorted = ar.take<uint64_t>(N);
   iota = ar.take<uint32_t>(N);
   perm = ar.take<uint32_t>(N);
-  q1_sorted = ar.take<uint32_t>(N);
-  perm1 = ar.take<uint32_t>(N);
+  if (d == 1) {
+    q1_sorted = ar.take<uint32_t>(N);
+    perm1 = ar.take<uint32_t>(N);
+  } else {
+    q2_sorted = ar.take<uint64_t>(N);
+  }
   bin_of_pos = ar.take<int32_t>(N);
   start = ar.take<int64_t>(N + 1);
   cells = ar.take<uint64_t>(N);
@@ -99,11 +103,12 @@ static int quantize_all(bumbar_ctx* ctx, BinnedBufs& BB, const double* xi) {
   int rc = read_bytes(ctx, BB.counts + kCountSlots - 1, &bad, sizeof(unsigned));
   if (rc) return rc;
   if (bad) return fail(ctx, BUMBAR_EINVAL, "non-finite binning coordinates");
-  if (BB.d == 1) {
+  if (BB.d == 1)
     e = launch_sort_1d(s, BB.q, BB.N, BB.iota, BB.q1_sorted, BB.perm1, BB.sort_tmp,
                        BB.sort_tmp_bytes);
-    if (e != hipSuccess) return hip_fail(ctx, e, "sort");
-  }
+  else
+    e = launch_sort_2d(s, BB.q, BB.N, BB.keys, BB.q2_sorted, BB.sort_tmp, BB.sort_tmp_bytes);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sort");
   return BUMBAR_OK;
 }
 
@@ -167,10 +172,13 @@ static int width_search_1d(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t*
 static int width_search(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_out,
                         int64_t* g_out) {
   if (BB.d == 1) return width_search_1d(ctx, BB, n, m_out, g_out);
-  // g(1) sorts all N cell ids; the coordinates do not change within a solve
+  // g(1): the runs of the sorted pairs; the coordinates do not change within
+  // a solve
   int rc = BUMBAR_OK;
   if (BB.g1 < 0) {
-    rc = nonempty(ctx, BB, 1, &BB.g1);
+    const hipError_t e = launch_count_sorted_2d(ctx->stream, BB.q2_sorted, BB.N, BB.counts);
+    if (e != hipSuccess) return hip_fail(ctx, e, "count");
+    rc = read_bytes(ctx, BB.counts, &BB.g1, sizeof(int64_t));
     if (rc) return rc;
   }
   const int64_t g1 = BB.g1;
@@ -186,7 +194,8 @@ static int width_search(bumbar_ctx* ctx, BinnedBufs& BB, int64_t n, uint64_t* m_
   // not fit, from the same (lo, hi, g(lo))
   {
     auto* w = reinterpret_cast<WidthSearch2D*>(BB.counts + kCountSlots / 2);
-    hipError_t e = launch_width_search_2d(ctx->stream, BB.q, BB.N, n, g1, 33, true, BB.keys, w);
+    hipError_t e =
+        launch_width_search_2d(ctx->stream, BB.q2_sorted, BB.N, n, g1, 33, true, BB.keys, w);
     if (e != hipSuccess) return hip_fail(ctx, e, "width search");
     WidthSearch2D h;
     rc = read_bytes(ctx, w, &h, sizeof(h));

@@ -607,50 +607,65 @@ __global__ void __launch_bounds__(kBT) ws2_zero_kernel(const WidthSearch2D* w, u
     words[i] = 0u;
 }
 
+// One probe over the samples sorted by (q_y, q_x) (key q_y 2^32 + q_x):
+// workgroup b takes the run [b L, (b + 1) L). Sorted by q_y, its cells lie in
+// the rows q_y / m of its first to its last sample, one contiguous range of
+// ids, which is marked in an LDS window when it fits (the whole grid at
+// coarse widths, a band of a few rows at fine ones) and OR-ed into the global
+// bitmap word by word; otherwise the global bitmap is marked directly. Each
+// workgroup counts the bits it is the first to set (the word an atomic OR
+// returns shows which were set before), so w->count ends as the number of
+// occupied cells whatever the order of the atomics.
 __global__ void __launch_bounds__(kBT)
-    ws2_mark_kernel(const uint32_t* __restrict__ q, int64_t N, const WidthSearch2D* w,
-                    uint32_t* __restrict__ words) {
+    ws2_mark_kernel(const uint64_t* __restrict__ qs, int64_t N, int64_t L,
+                    WidthSearch2D* w, uint32_t* __restrict__ words) {
   if (w->done || w->host) return;  // uniform
   __shared__ uint32_t lw[kLdsWords];
+  __shared__ unsigned long long sh[kBT / 64];
   const uint64_t m = w->m, magic = w->magic, ncx = w->ncx;
-  const int64_t nw = w->nw;
-  const bool private_map = nw <= kLdsWords;  // uniform over the grid
-  if (private_map) {
-    for (int i = threadIdx.x; i < nw; i += kBT) lw[i] = 0u;
+  const int64_t n0 = (int64_t)blockIdx.x * L;
+  const int64_t n1 = n0 + L < N ? n0 + L : N;
+  if (n0 >= n1) return;  // uniform
+  const uint64_t w_lo = (uint64_t)div_by_magic((uint32_t)(qs[n0] >> 32), m, magic) * ncx >> 5;
+  const uint64_t w_hi =
+      ((uint64_t)div_by_magic((uint32_t)(qs[n1 - 1] >> 32), m, magic) * ncx + ncx - 1) >> 5;
+  const int64_t nwin = (int64_t)(w_hi - w_lo) + 1;
+  const bool window = nwin <= kLdsWords;  // uniform over the workgroup
+  unsigned long long fresh = 0;
+  if (window) {
+    for (int i = threadIdx.x; i < nwin; i += kBT) lw[i] = 0u;
     __syncthreads();
   }
-  for (int64_t n = (int64_t)blockIdx.x * kBT + threadIdx.x; n < N; n += (int64_t)gridDim.x * kBT) {
-    const uint64_t c = (uint64_t)div_by_magic(q[2 * n], m, magic) +
-                       (uint64_t)div_by_magic(q[2 * n + 1], m, magic) * ncx;
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += kBT) {
+    const uint64_t key = qs[n];
+    const uint64_t c = (uint64_t)div_by_magic((uint32_t)key, m, magic) +
+                       (uint64_t)div_by_magic((uint32_t)(key >> 32), m, magic) * ncx;
     const uint32_t bit = 1u << (uint32_t)(c & 31u);
-    if (private_map) {
-      if (!(lw[c >> 5] & bit)) atomicOr(&lw[c >> 5], bit);
+    // bits are only ever set: a bit seen set is set, so its atomic is
+    // skipped (most samples land in cells already marked)
+    if (window) {
+      uint32_t* wp = &lw[(c >> 5) - w_lo];
+      if (!(*wp & bit)) atomicOr(wp, bit);
     } else {
-      if (!(words[c >> 5] & bit)) atomicOr(&words[c >> 5], bit);
+      uint32_t* wp = &words[c >> 5];
+      if (!(*wp & bit) && !(atomicOr(wp, bit) & bit)) ++fresh;
     }
   }
-  if (private_map) {
+  if (window) {
     __syncthreads();
-    for (int i = threadIdx.x; i < nw; i += kBT)
-      if (lw[i]) atomicOr(&words[i], lw[i]);
+    for (int64_t i = threadIdx.x; i < nwin; i += kBT) {
+      const uint32_t v = lw[i];
+      if (v) fresh += (unsigned long long)__builtin_popcount(v & ~atomicOr(&words[w_lo + i], v));
+    }
   }
-}
-
-__global__ void __launch_bounds__(kBT)
-    ws2_popcount_kernel(const uint32_t* __restrict__ words, WidthSearch2D* w) {
-  if (w->done || w->host) return;  // uniform
-  __shared__ unsigned long long sh[kBT];
-  const int64_t nw = w->nw;
-  unsigned long long c = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBT)
-    c += (unsigned long long)__builtin_popcount(words[i]);
-  sh[threadIdx.x] = c;
+  for (int off = 32; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = fresh;
   __syncthreads();
-  for (int s2 = kBT / 2; s2 > 0; s2 >>= 1) {
-    if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kBT / 64; ++i) t += sh[i];
+    if (t) atomicAdd(&w->count, t);
   }
-  if (threadIdx.x == 0 && sh[0]) atomicAdd(&w->count, sh[0]);
 }
 
 __global__ void ws2_walk_kernel(WidthSearch2D* w) {
@@ -669,7 +684,14 @@ __global__ void ws2_walk_kernel(WidthSearch2D* w) {
   ws2_prepare(w);
 }
 
-hipError_t launch_width_search_2d(hipStream_t s, const uint32_t* q, int64_t N, int64_t n,
+// samples per workgroup of the sorted probe: at least 8 per thread, at most
+// 2048 workgroups
+static int64_t ws2_run(int64_t N) {
+  const int64_t by_grid = (N + 2047) / 2048;
+  return by_grid > 8 * kBT ? by_grid : 8 * kBT;
+}
+
+hipError_t launch_width_search_2d(hipStream_t s, const uint64_t* qs, int64_t N, int64_t n,
                                   int64_t g1, int passes, bool init, uint64_t* bitmap,
                                   WidthSearch2D* w) {
   if (passes < 1) return hipErrorInvalidValue;
@@ -677,13 +699,40 @@ hipError_t launch_width_search_2d(hipStream_t s, const uint32_t* q, int64_t N, i
   if (init) hipLaunchKernelGGL(ws2_init_kernel, dim3(1), dim3(1), 0, s, w, n, g1, (uint64_t)N * 64ull);
   uint32_t* words = reinterpret_cast<uint32_t*>(bitmap);
   const unsigned zb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (2 * N + kBT - 1) / kBT));
-  const unsigned mb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (N + kBT - 1) / kBT));
+  const int64_t L = ws2_run(N);
+  const unsigned mb = (unsigned)((N + L - 1) / L);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(ws2_zero_kernel, dim3(zb), dim3(kBT), 0, s, w, words);
-    hipLaunchKernelGGL(ws2_mark_kernel, dim3(mb), dim3(kBT), 0, s, q, N, w, words);
-    hipLaunchKernelGGL(ws2_popcount_kernel, dim3(zb), dim3(kBT), 0, s, words, w);
+    hipLaunchKernelGGL(ws2_mark_kernel, dim3(mb), dim3(kBT), 0, s, qs, N, L, w, words);
     hipLaunchKernelGGL(ws2_walk_kernel, dim3(1), dim3(1), 0, s, w);
   }
+  return hipGetLastError();
+}
+
+// The quantised 2-D coordinates sorted once per solve as keys q_y 2^32 + q_x
+// (the order the sorted probe needs); keys is scratch of N entries.
+__global__ void pair_keys_kernel(const uint32_t* __restrict__ q, int64_t N,
+                                 uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x;
+  if (i < N) keys[i] = ((uint64_t)q[2 * i + 1] << 32) | (uint64_t)q[2 * i];
+}
+
+hipError_t launch_sort_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t* keys,
+                          uint64_t* q2_sorted, void* tmp, size_t tmp_bytes) {
+  hipLaunchKernelGGL(pair_keys_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q,
+                     N, keys);
+  size_t bytes = tmp_bytes;
+  return rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, q2_sorted, (size_t)N, 0, 64,
+                                  s);
+}
+
+// counts[0] = the distinct points of the sorted pairs, g(1).
+hipError_t launch_count_sorted_2d(hipStream_t s, const uint64_t* q2_sorted, int64_t N,
+                                  int64_t* counts) {
+  const int nb = red_blocks(N);
+  hipLaunchKernelGGL(count_runs_keys_kernel<uint64_t>, dim3(nb), dim3(kBT), 0, s, q2_sorted, N,
+                     counts);
+  hipLaunchKernelGGL(sum_counts_kernel, dim3(1), dim3(kBT), 0, s, nb, counts);
   return hipGetLastError();
 }
 

@@ -193,6 +193,7 @@ struct BinnedBufs {
   uint32_t* perm = nullptr;      // N: sample index of each sorted position
   uint32_t* q1_sorted = nullptr; // 1-D: sorted q (sorted once)
   uint32_t* perm1 = nullptr;     // 1-D: permutation of the one-time sort
+  uint64_t* q2_sorted = nullptr; // 2-D: the pairs sorted by (q_y, q_x) (sorted once)
   int32_t* bin_of_pos = nullptr; // N: bin index of each sorted position
   int64_t* start = nullptr;      // N + 1: first sorted position of each bin
   uint64_t* cells = nullptr;     // N: cell id of each bin
@@ -277,9 +278,16 @@ struct WidthSearch2D {
   unsigned long long count;
   int done, host;
 };
-hipError_t launch_width_search_2d(hipStream_t s, const uint32_t* q, int64_t N, int64_t n,
+// Probes over q2_sorted (the 2-D coordinates sorted by launch_sort_2d).
+hipError_t launch_width_search_2d(hipStream_t s, const uint64_t* q2_sorted, int64_t N, int64_t n,
                                   int64_t g1, int passes, bool init, uint64_t* bitmap,
                                   WidthSearch2D* w);
+// q2_sorted = the N quantised pairs as keys q_y 2^32 + q_x in ascending order
+// (keys: N entries of scratch); counts[0] = their distinct values, g(1).
+hipError_t launch_sort_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t* keys,
+                          uint64_t* q2_sorted, void* tmp, size_t tmp_bytes);
+hipError_t launch_count_sorted_2d(hipStream_t s, const uint64_t* q2_sorted, int64_t N,
+                                  int64_t* counts);
 hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t m,
                            uint64_t* keys, uint64_t* keys_sorted, void* tmp, size_t tmp_bytes,
                            int64_t* counts);

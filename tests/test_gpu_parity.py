@@ -181,6 +181,28 @@ def test_binning_bit_exact(bm, d):
         assert np.array_equal(sb.cpu().numpy(), sb_ref)
 
 
+def test_binning_2d_heavy_tail(bm):
+    # The 2-D probes visit the samples sorted by (q_y, q_x), a workgroup per
+    # run of 2048: its cells lie in a band of grid rows, marked in LDS when
+    # the band fits 8192 words, else in the global bitmap. A heavy-tailed y
+    # makes the tail runs span many rows at fine widths (global marking)
+    # while the bulk stays in LDS bands; every width must match the oracle.
+    g = np.random.default_rng(77)
+    N = 300007
+    xi = np.stack([g.normal(0, 1, N), g.standard_cauchy(N)], axis=1)
+    xi[:500] = xi[500:1000]  # duplicate points
+    q, lo, sc = oracle.quantize(xi)
+    for n in [100, 5000, 100000, 250000]:
+        say(f"binning 2-D heavy tail n={n}")
+        m_ref, g_ref, _ = oracle.width_search(q, n)
+        cells_ref, H_ref, sb_ref = oracle.histogram(q, m_ref)
+        m, cells, H, sb = bm.bin_coordinates(xi, n)
+        assert m == m_ref
+        assert np.array_equal(cells.cpu().numpy().view(np.uint64), cells_ref)
+        assert np.array_equal(H.cpu().numpy(), H_ref)
+        assert np.array_equal(sb.cpu().numpy(), sb_ref)
+
+
 @pytest.mark.parametrize("N", [700001, 3000017, 12000007, 40000003])
 def test_binning_large_1d(bm, N):
     # Large N evaluates fewer bisection levels per pass (4, 3, 2 and 2 here),
