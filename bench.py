@@ -326,10 +326,7 @@ def run_all(args, bm, synth, stream):
     achieved = 8.0 * elems / sw64 / 1e9
     cfg["c2_f64"] = dict(time_to_solve_s=ms64 / 1e3, sweep_us=sw64 * 1e6, sweep_launches=nsw,
                          error_vs_oracle_kT=_err(f64, g2), status=inf64[-1]["status"],
-                         covariance_ms=cov_ms,
-                         stages_ms=dict(binning=inf64[-1]["time_binning_ms"],
-                                        binned=inf64[-1]["time_binned_ms"],
-                                        finisher=inf64[-1]["time_final_ms"]))
+                         covariance_ms=cov_ms, **_stages(inf64[-1]))
     # FP32 storage (8 GB, no FP64 copy anywhere): mixed precision, and FP64
     # arithmetic on the same storage (the oracle's problem is the FP64 one,
     # so the error against it includes the rounding of u to FP32)
@@ -419,7 +416,7 @@ def _c1(bm, synth, args, ctx):
                sweep_elem_s=p1["K"] * p1["N"] / sw1, roofline_frac=a1 / HBM_PEAK_GBS,
                traffic=_counter_traffic("sweep_fast_double_well_K100_N1e6"),
                error_vs_oracle_kT=_err(f1, _golden("c1_double_well_K100_N1e6")),
-               status=inf1[-1]["status"], covariance_ms=cov_ms)
+               status=inf1[-1]["status"], covariance_ms=cov_ms, **_stages(inf1[-1]))
     del u1
     torch.cuda.empty_cache()
     return res
@@ -442,10 +439,7 @@ def _c4(bm, synth, args, ctx, Nk_per, gold=None, hessian=True):
                                    ctx=ctx)
     res = dict(time_to_solve_s=ms / 1e3, K=K, N=N, status=infos[-1]["status"],
                fp64_sci_residual_kT=st["max_df"], grad_norm=st["grad_norm"],
-               grid_sweeps=infos[-1]["grid_sweeps"],
-               stages_ms=dict(binning=infos[-1]["time_binning_ms"],
-                              binned=infos[-1]["time_binned_ms"],
-                              finisher=infos[-1]["time_final_ms"]))
+               grid_sweeps=infos[-1]["grid_sweeps"], **_stages(infos[-1]))
     if gold is not None:
         res["error_vs_oracle_kT"] = _err(f, gold)
         f64, _, ms64 = _timed_solves(
@@ -628,6 +622,16 @@ def _avg_sweep_s(infos):
     ms = sum(i["sweep_kernel_ms"] for i in infos)
     n = sum(i["sweep_kernel_launches"] for i in infos)
     return ms / max(1, n) / 1e3, n
+
+
+def _stages(info):
+    """Stage times of a timed solve, and the binned stage per binned SCI step
+    (phase 1 and phase 2 of Algorithm 1, one sweep and its finaliser each)."""
+    steps = info["phase1_iters"] + info["phase2_iters"]
+    return dict(stages_ms=dict(binning=info["time_binning_ms"], binned=info["time_binned_ms"],
+                               finisher=info["time_final_ms"]),
+                binned_steps=dict(phase1=info["phase1_iters"], phase2=info["phase2_iters"],
+                                  us_per_step=1e3 * info["time_binned_ms"] / max(1, steps)))
 
 
 def _library_version():
