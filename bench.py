@@ -324,9 +324,12 @@ def run_all(args, bm, synth, stream):
     elems = K * N
     value = elems / sw64
     achieved = 8.0 * elems / sw64 / 1e9
+    up_ms, up_gbs = _upload_solve_ms(torch, u, c2(u, bm.PREC_FP64))
     cfg["c2_f64"] = dict(time_to_solve_s=ms64 / 1e3, sweep_us=sw64 * 1e6, sweep_launches=nsw,
                          error_vs_oracle_kT=_err(f64, g2), status=inf64[-1]["status"],
-                         covariance_ms=cov_ms, **_stages(inf64[-1]))
+                         covariance_ms=cov_ms,
+                         with_upload=dict(time_to_solve_s=up_ms / 1e3, upload_gb_s=up_gbs),
+                         **_stages(inf64[-1]))
     # FP32 storage (8 GB, no FP64 copy anywhere): mixed precision, and FP64
     # arithmetic on the same storage (the oracle's problem is the FP64 one,
     # so the error against it includes the rounding of u to FP32)
@@ -411,12 +414,17 @@ def _c1(bm, synth, args, ctx):
                               profile=int(prof), ctx=ctx))
     sw1, _ = _avg_sweep_s(inf1)
     cov_ms = _covariance_ms(bm, u1, Nk1, f1, ctx)
+    up_ms, up_gbs = _upload_solve_ms(
+        torch, u1, lambda prof: bm.solve(u1, Nk1, xi=xi1, model=bm.MODEL_HARMONIC, coef=coef1,
+                                         tol=args.tol, profile=int(prof), ctx=ctx))
     a1 = 8.0 * p1["K"] * p1["N"] / sw1 / 1e9
     res = dict(time_to_solve_s=ms1 / 1e3, sweep_us=sw1 * 1e6,
                sweep_elem_s=p1["K"] * p1["N"] / sw1, roofline_frac=a1 / HBM_PEAK_GBS,
                traffic=_counter_traffic("sweep_fast_double_well_K100_N1e6"),
                error_vs_oracle_kT=_err(f1, _golden("c1_double_well_K100_N1e6")),
-               status=inf1[-1]["status"], covariance_ms=cov_ms, **_stages(inf1[-1]))
+               status=inf1[-1]["status"], covariance_ms=cov_ms,
+               with_upload=dict(time_to_solve_s=up_ms / 1e3, upload_gb_s=up_gbs),
+               **_stages(inf1[-1]))
     del u1
     torch.cuda.empty_cache()
     return res
@@ -440,6 +448,23 @@ def _c4(bm, synth, args, ctx, Nk_per, gold=None, hessian=True):
     res = dict(time_to_solve_s=ms / 1e3, K=K, N=N, status=infos[-1]["status"],
                fp64_sci_residual_kT=st["max_df"], grad_norm=st["grad_norm"],
                grid_sweeps=infos[-1]["grid_sweeps"], **_stages(infos[-1]))
+    # one unbinned model sweep of each kind at the solution: the FP32 model
+    # (two passes, one hardware exp2 per element each: bound by the
+    # transcendental rate, 256 CUs x 16 per clock x 2.4 GHz = 9.83e12/s) and
+    # the solve's FP64 sweep (the factored product-grid passes on this grid)
+    sw = {}
+    for name, prec in (("fp32_model", bm.PREC_MIXED), ("fp64", bm.PREC_FP64)):
+        bm.sweep_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, precision=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            bm.sweep_model(xi, coef, bm.MODEL_HARMONIC, Nk, f, precision=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        sw[name] = (time.perf_counter() - t0) / 3
+    res["sweeps"] = dict(
+        fp32_model_ms=1e3 * sw["fp32_model"], fp64_ms=1e3 * sw["fp64"],
+        fp32_elem_s=K * N / sw["fp32_model"],
+        fp32_exp_roofline_frac=2.0 * K * N / sw["fp32_model"] / 9.83e12)
     if gold is not None:
         res["error_vs_oracle_kT"] = _err(f, gold)
         f64, _, ms64 = _timed_solves(
@@ -632,6 +657,29 @@ def _stages(info):
                                finisher=info["time_final_ms"]),
                 binned_steps=dict(phase1=info["phase1_iters"], phase2=info["phase2_iters"],
                                   us_per_step=1e3 * info["time_binned_ms"] / max(1, steps)))
+
+
+def _upload_solve_ms(torch, u, solve, reps=2):
+    """Time-to-solve with u first copied from pinned host memory (PCIe included).
+
+    The copy is synchronous, so it ends before the solve starts on the
+    library's stream; returns (ms per upload + solve, upload GB/s)."""
+    host = torch.empty(u.shape, dtype=u.dtype, pin_memory=True)
+    host.copy_(u)
+    solve(False)
+    torch.cuda.synchronize()
+    tot, up = 0.0, 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        u.copy_(host)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solve(False)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t0
+        up += t1 - t0
+    del host
+    return 1e3 * tot / reps, u.numel() * u.element_size() * reps / up / 1e9
 
 
 def _library_version():
