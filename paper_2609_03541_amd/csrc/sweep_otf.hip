@@ -845,8 +845,17 @@ hipError_t launch_sweep_otf(hipStream_t s, const OtfModel& m, bool fp32, int K, 
   const dim3 sg(G, (K + kOStates - 1) / kOStates);
   hipError_t e = launch_otf_coefs(s, m, fp32, K, cst, gk);
   if (e != hipSuccess) return e;
-  if (!fp32 && m.sep && m.d == 2 && m.model == BUMBAR_MODEL_HARMONIC)
-    return launch_sweep_sep(s, m, K, N, cst, gk, h, logD, part, part_obj, part_flags, G);
+  if (!fp32 && m.sep && m.d == 2 && m.model == BUMBAR_MODEL_HARMONIC) {
+    // a workgroup per 64 samples (two state-pass chunks), up to the partial
+    // buffers' capacity: a workgroup's chunks run one after another, each a
+    // chain of dependent loads and FP64 exponentials, so on a binned level
+    // the pass takes as long as one workgroup's share (512 samples per
+    // workgroup cost about 90 us whatever the level size)
+    int64_t gs = (N + 63) / 64;
+    if (gs > sweep_max_grid(num_cus)) gs = sweep_max_grid(num_cus);
+    *grid_out = (int)gs;
+    return launch_sweep_sep(s, m, K, N, cst, gk, h, logD, part, part_obj, part_flags, (int)gs);
+  }
   if (fp32) {
     if (m.d == 1) {
       hipLaunchKernelGGL(otf32_colpass_kernel<1>, dim3(G), dim3(kOT), 0, s, K, N, m.xf, m.cf32,
