@@ -698,8 +698,8 @@ __global__ void __launch_bounds__(kST)
 
 // State pass: chunks of 32 samples; eight threads per sample fill the shifted
 // factors (g, and h times w_n) into LDS, then thread (ti, tj) of 16 x 16
-// accumulates M_ij for i = ti + 16 a (a < 4) and j = tj + 16 b (b < JB).
-template <int JB>
+// accumulates M_ij for i = ti + 16 a (a < IA) and j = tj + 16 b (b < JB).
+template <int IA, int JB>
 __global__ void __launch_bounds__(kST)
     sep_statepass_kernel(int K, int64_t N, const double* __restrict__ xi,
                          const double* __restrict__ c64, int Ix, int Jy,
@@ -716,9 +716,9 @@ __global__ void __launch_bounds__(kST)
   const int ti = tid & 15, tj = tid >> 4;
   const int sl = tid >> 3, r = tid & 7;  // sample of the chunk, and its eighth of the factors
   const double cm = cmax[0];
-  double acc[4][JB];
+  double acc[IA][JB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < IA; ++a)
 #pragma unroll
     for (int b = 0; b < JB; ++b) acc[a][b] = 0.0;
   const int64_t nchunks = (N + NS - 1) / NS;
@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(kST)
     }
     const double w = in ? (h ? h[n] : 1.0) * exp(cm - mx - my - logD[n]) : 0.0;
     __syncthreads();  // the previous chunk's products are done
-    for (int i = r; i < kSepMax; i += 8) {
+    for (int i = r; i < 16 * IA; i += 8) {
       double g = 0.0;
       if (i < Ix) {
         const double dx = x - fx[2 * i + 1];
@@ -760,13 +760,13 @@ __global__ void __launch_bounds__(kST)
     }
     __syncthreads();
     for (int t = 0; t < NS; ++t) {
-      double ga[4], hb[JB];
+      double ga[IA], hb[JB];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) ga[a] = Gs[t][ti + 16 * a];
+      for (int a = 0; a < IA; ++a) ga[a] = Gs[t][ti + 16 * a];
 #pragma unroll
       for (int b = 0; b < JB; ++b) hb[b] = Hs[t][tj + 16 * b];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < IA; ++a)
 #pragma unroll
         for (int b = 0; b < JB; ++b) acc[a][b] = __builtin_fma(ga[a], hb[b], acc[a][b]);
     }
@@ -775,7 +775,7 @@ __global__ void __launch_bounds__(kST)
   double(*Ms)[RP] = reinterpret_cast<double(*)[RP]>(buf);
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < IA; ++a)
 #pragma unroll
     for (int b = 0; b < JB; ++b) Ms[ti + 16 * a][tj + 16 * b] = acc[a][b];
   __syncthreads();
@@ -809,13 +809,17 @@ static hipError_t launch_sweep_sep(hipStream_t s, const OtfModel& m, int K, int6
       return hipErrorInvalidValue;
   }
 #undef SEP_COL
-#define SEP_STATE(JB_)                                                                            \
-  case JB_:                                                                                       \
-    hipLaunchKernelGGL(sep_statepass_kernel<JB_>, dim3(G), dim3(kST), 0, s, K, N, m.xi, m.cf64,    \
-                       g.Ix, g.Jy, g.fx, g.fy, g.ix, g.jy, g.cmax, h, logD, part);                \
+#define SEP_STATE(IA_, JB_)                                                                       \
+  case 4 * (IA_ - 1) + JB_ - 1:                                                                   \
+    hipLaunchKernelGGL((sep_statepass_kernel<IA_, JB_>), dim3(G), dim3(kST), 0, s, K, N, m.xi,     \
+                       m.cf64, g.Ix, g.Jy, g.fx, g.fy, g.ix, g.jy, g.cmax, h, logD, part);        \
     break;
-  switch ((g.Jy + 15) / 16) {
-    SEP_STATE(1) SEP_STATE(2) SEP_STATE(3) SEP_STATE(4)
+  // 16-row groups of the x and y factors (Ix, Jy <= 64)
+  switch (4 * ((g.Ix + 15) / 16 - 1) + (g.Jy + 15) / 16 - 1) {
+    SEP_STATE(1, 1) SEP_STATE(1, 2) SEP_STATE(1, 3) SEP_STATE(1, 4)
+    SEP_STATE(2, 1) SEP_STATE(2, 2) SEP_STATE(2, 3) SEP_STATE(2, 4)
+    SEP_STATE(3, 1) SEP_STATE(3, 2) SEP_STATE(3, 3) SEP_STATE(3, 4)
+    SEP_STATE(4, 1) SEP_STATE(4, 2) SEP_STATE(4, 3) SEP_STATE(4, 4)
     default:
       return hipErrorInvalidValue;
   }
