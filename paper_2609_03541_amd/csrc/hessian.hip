@@ -452,15 +452,15 @@ static int small_chunks(int64_t N, int num_cus) {
 // product adding into the same partial blocks.
 //
 // Product: a workgroup (8 waves) owns one 256 x 256 output block (bi <= bj)
-// and one chunk of tiles. Per tile it copies the two slabs (one on a diagonal
-// block) into LDS, 1 KB per wave instruction, and wave w accumulates the
-// 64 x 128 output tile (rows 64 (w % 4), columns 128 (w / 4)) as 4 x 8 MFMA
-// tiles; MFMA tiles wholly past K are skipped. LDS is double-buffered (the
-// next tile's loads are in flight during the matrix instructions), one
-// barrier per tile. The hardware deals workgroups to the 8 XCDs round robin;
-// the grid is ordered so that the workgroups one XCD runs together are all
-// block pairs of one sample chunk, which then share the slabs in that XCD's
-// L2 instead of each pulling them from HBM.
+// and one chunk of tiles. Per tile it copies the two slabs into LDS, 1 KB
+// per wave instruction, and wave w accumulates the 64 x 128 output tile (rows
+// 64 (w % 4), columns 128 (w / 4)) as 4 x 8 MFMA tiles. LDS is
+// double-buffered (the next tile's loads are in flight during the matrix
+// instructions), one barrier per tile. The hardware deals workgroups to the
+// 8 XCDs round robin; the grid is ordered so that the workgroups one XCD
+// runs together are all block pairs of one sample chunk, which share the
+// slabs in that XCD's L2 instead of each pulling them from HBM, and every
+// block pair does the same work so that they stay in step.
 // Operand layout (checked on the hardware): A lane l holds row l % 16,
 // k = 8 (l / 16) .. + 7; B lane l holds column l % 16, the same k; the
 // accumulator lane l holds rows 4 (l / 16) + i, column l % 16.
@@ -669,20 +669,20 @@ __global__ void __launch_bounds__(512)
   const int blk = slot % nblk;
   int bi, bj;
   block_coords(blk, nb, bi, bj);
-  const bool diag = (bi == bj);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // copy role: 16-byte piece c = tid + 512 j of the tile's slabs (slab j / 2,
-  // row (c % 1024) / 4, quarter c % 4); a diagonal block has one slab
-  const int nj = diag ? 2 : 4;
+  // row (c % 1024) / 4, quarter c % 4). Every block pair does the same work:
+  // a diagonal block copies its slab twice and the tiles past K are
+  // multiplied (as zeros). Workgroups of one chunk then stay in step and
+  // share each slab in their XCD's L2; with the shortcuts the faster ones ran
+  // ahead and the slabs were fetched again from HBM (9% slower at K = 1600
+  // despite 20% fewer MFMAs, the same at K = 1000).
   const int crow = (tid & 1023) >> 2, cq = tid & 3;
   // product role: output rows 64 wr + 16 a, columns 128 wc + 16 b
   const int wr = wave & 3, wc = wave >> 2;
   const int kq = (lane >> 4) * 8;
-  const int ra = K - (bi * XB + wr * 64), cb = K - (bj * XB + wc * 128);
-  const int na = ra <= 0 ? 0 : (ra >= 64 ? 4 : (ra + 15) / 16);
-  const int nbv = cb <= 0 ? 0 : (cb >= 128 ? 8 : (cb + 15) / 16);
   f4v acc[4][8];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -695,18 +695,15 @@ __global__ void __launch_bounds__(512)
   auto load = [&](int64_t t) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (j < nj) {
-        const int k = ((j >> 1) ? bj : bi) * XB + crow + (j & 1) * 128;
-        v[j] = (h8v){};
-        if (k < K) v[j] = *reinterpret_cast<const h8v*>(P + (t * K + k) * XS + cq * 8);
-      }
+      const int k = ((j >> 1) ? bj : bi) * XB + crow + (j & 1) * 128;
+      v[j] = (h8v){};
+      if (k < K) v[j] = *reinterpret_cast<const h8v*>(P + (t * K + k) * XS + cq * 8);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < nj)
-        *reinterpret_cast<h8v*>(&L[buf][j >> 1][crow + (j & 1) * 128][cq * 8]) = v[j];
+      *reinterpret_cast<h8v*>(&L[buf][j >> 1][crow + (j & 1) * 128][cq * 8]) = v[j];
   };
   if (t_begin < t_end) {
     load(t_begin);
@@ -718,20 +715,17 @@ __global__ void __launch_bounds__(512)
     const bool more = t + 1 < t_end;
     if (more) load(t + 1);
     const _Float16(*Pa)[XP] = L[cur][0];
-    const _Float16(*Pb)[XP] = L[cur][diag ? 0 : 1];
+    const _Float16(*Pb)[XP] = L[cur][1];
     h8v av[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       av[a] = *reinterpret_cast<const h8v*>(&Pa[wr * 64 + a * 16 + (lane & 15)][kq]);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      if (b < nbv) {
-        const h8v bv = *reinterpret_cast<const h8v*>(&Pb[wc * 128 + b * 16 + (lane & 15)][kq]);
+      const h8v bv = *reinterpret_cast<const h8v*>(&Pb[wc * 128 + b * 16 + (lane & 15)][kq]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-          if (a < na)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
-      }
+      for (int a = 0; a < 4; ++a)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv, acc[a][b], 0, 0, 0);
     }
     if (more) store(cur ^ 1);
     __syncthreads();
