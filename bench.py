@@ -495,15 +495,19 @@ def _c4(bm, synth, args, ctx, Nk_per, gold=None, hessian=True):
     return res
 
 
-def _served(bm, probs, n, rate_seed, max_active, budget, opts, gold):
-    """Saturation (closed loop), then Poisson arrivals at 0.8x that rate."""
-    _, wall_sat, _ = _serve(bm, probs, [0.0] * n, max_active, budget, opts)
+def _served(bm, probs, n, rate_seed, max_active, budget, opts, gold, fuse=False):
+    """Saturation (closed loop), then Poisson arrivals at 0.8x that rate.
+
+    fuse: a caller-driven server that fuses the small binned batches of its
+    problems into one launch per tick."""
+    drive = dict(caller_driven=fuse, fuse=fuse)
+    _, wall_sat, _ = _serve(bm, probs, [0.0] * n, max_active, budget, opts, **drive)
     sat = n / wall_sat
     rate = 0.8 * sat
     g = np.random.Generator(np.random.PCG64(rate_seed))
     arrivals = list(np.cumsum(g.exponential(1.0 / rate, size=n)))
     log(f"  saturation {sat:.1f} solves/s; served run at {rate:.1f}/s")
-    res, wall, cnt = _serve(bm, probs, arrivals, max_active, budget, opts)
+    res, wall, cnt = _serve(bm, probs, arrivals, max_active, budget, opts, **drive)
     lat = np.array([info["latency_ms"] for _, info in res])
     err_gold = None
     if gold is not None:
@@ -517,6 +521,8 @@ def _served(bm, probs, n, rate_seed, max_active, budget, opts, gold):
                peak_active=cnt["peak_active"], peak_arena_gb=cnt["peak_bytes"] / 2**30,
                memory_bound_admissions=cnt["mem_waits"],
                error_vs_oracle_subset64_kT=err_gold)
+    if fuse:
+        out.update(fused_launches=cnt["fused_launches"], fused_batches=cnt["fused_items"])
     return out, res
 
 
@@ -532,6 +538,13 @@ def _c3(bm, args, stream):
     # memory whenever several large problems are resident
     log("c3 materialised FP32 u, 16 slots, 32 GB arena")
     mat, res = _served(bm, probs, n, 33, 16, 32 << 30, dict(mixed, materialize=True), gold)
+    # the same, driven by progress() ticks with the small binned batches of
+    # all resident problems fused into one graph-replayed launch per tick
+    log("c3 materialised FP32 u, 16 slots, 32 GB arena, fused launches")
+    fused, res_f = _served(bm, probs, n, 33, 16, 32 << 30, dict(mixed, materialize=True), gold,
+                           fuse=True)
+    fused["max_abs_diff_vs_unfused_kT"] = max(float(np.max(np.abs(a[0] - b[0])))
+                                              for a, b in zip(res, res_f))
     # the same requests with the energies evaluated inside the kernels (no
     # stored u): the faster mode, in the arena of --hbm-budget-gb
     log("c3 energies in the kernels, %d slots" % args.max_active)
@@ -544,7 +557,7 @@ def _c3(bm, args, stream):
     out = dict(mat)
     out.update(
         n_problems=n, precision="mixed", storage="u materialised on the device, FP32",
-        energies_in_kernel=otf,
+        fused=fused, energies_in_kernel=otf,
         sequential_fp64=dict(solves_per_s=n / wall64, p50_ms=float(np.percentile(lat64, 50)),
                              p99_ms=float(np.percentile(lat64, 99))),
         max_abs_diff_vs_sequential_fp64_kT=max(float(np.max(np.abs(a[0] - b[0])))
@@ -962,12 +975,13 @@ def _gen_problem(spec):
     return {k: p[k] for k in ("K", "N", "Nk", "xi", "coef", "model_type")}
 
 
-def _serve(bm, probs, arrivals, max_active, budget, opts, caller_driven=False):
+def _serve(bm, probs, arrivals, max_active, budget, opts, caller_driven=False, fuse=False):
     """Submit the problems at their arrival times; returns (results, wall s, counters).
 
     caller_driven: the server has no worker threads; this loop ticks it
-    (progress) between arrivals."""
-    srv = bm.Server(hbm_budget_bytes=budget, max_active=max_active, caller_driven=caller_driven)
+    (progress) between arrivals. fuse: fused small batches (caller-driven)."""
+    srv = bm.Server(hbm_budget_bytes=budget, max_active=max_active, caller_driven=caller_driven,
+                    fuse=fuse)
     try:
         t0 = time.perf_counter()
         tickets = []

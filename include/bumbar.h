@@ -461,6 +461,15 @@ int bumbar_sweep_static(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, i
  * it), on the calling thread. A fiber runs until its stream is busy with
  * the kernels it queued, then hands control to the next one, so the
  * problems' kernels still overlap on the device.
+ *
+ * A caller-driven server may also fuse (fuse = 1): the batches of binned
+ * self-consistent steps (Eq. (1) with the bin counts, Algorithm 1) that
+ * its problems reach on levels small enough for one workgroup are not
+ * launched per problem; each tick gathers them into a device work list and
+ * replays one captured HIP graph (the list's upload, then one kernel whose
+ * fixed grid walks the list), so a single launch advances every resident
+ * problem that is in such a batch. Each item runs the same code as its own
+ * launch would: results stay bitwise the same alone and in the mix.
  */
 typedef struct bumbar_server bumbar_server;
 
@@ -471,6 +480,8 @@ typedef struct {
   int caller_driven;        /* 1: no worker threads; the caller's progress() calls
                                advance the problems (all server calls but submit, poll,
                                result and counters from the creating thread)          */
+  int fuse;                 /* 1: fused launches of the small binned batches (needs
+                               caller_driven = 1; EINVAL otherwise); 0: off           */
 } bumbar_server_options;
 
 typedef struct {
@@ -528,6 +539,10 @@ int bumbar_server_result(bumbar_server* srv, uint64_t ticket, double* f_k_host,
  * until enough of the arena was released (admission bound by memory). */
 int bumbar_server_counters(bumbar_server* srv, int64_t* completed, int64_t* peak_active,
                            size_t* peak_bytes, int64_t* mem_waits);
+/* Fused launches of a fusing server so far, and the batches they ran
+ * (items / launches is the mean number of problems advanced per launch);
+ * both 0 for a server without fuse. */
+int bumbar_server_fused_counters(bumbar_server* srv, int64_t* launches, int64_t* items);
 /* Let running requests finish, fail the ones still queued (status
  * BUMBAR_EBUSY), stop the slots and release the arena. */
 void bumbar_server_destroy(bumbar_server* srv);

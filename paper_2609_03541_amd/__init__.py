@@ -538,14 +538,16 @@ class Server:
     The arrays are held here until the ticket's result has been read.
     """
 
-    def __init__(self, hbm_budget_bytes, max_active=4, device=None, caller_driven=False):
+    def __init__(self, hbm_budget_bytes, max_active=4, device=None, caller_driven=False,
+                 fuse=False):
         import numpy  # noqa: F401  (requests are host arrays)
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libbumbar needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = _capi.load()
         dev = torch.cuda.current_device() if device is None else int(device)
-        o = _capi.ServerOptions(dev, int(hbm_budget_bytes), int(max_active), int(caller_driven))
+        o = _capi.ServerOptions(dev, int(hbm_budget_bytes), int(max_active), int(caller_driven),
+                                int(bool(fuse)))
         self.caller_driven = bool(caller_driven)
         h = C.c_void_p()
         rc = self.lib.bumbar_server_create(C.byref(o), C.byref(h))
@@ -658,8 +660,10 @@ class Server:
     def counters(self):
         c, a, b, w = C.c_int64(), C.c_int64(), C.c_size_t(), C.c_int64()
         self.lib.bumbar_server_counters(self.h, C.byref(c), C.byref(a), C.byref(b), C.byref(w))
+        fl, fi = C.c_int64(), C.c_int64()
+        self.lib.bumbar_server_fused_counters(self.h, C.byref(fl), C.byref(fi))
         return dict(completed=c.value, peak_active=a.value, peak_bytes=b.value,
-                    mem_waits=w.value)
+                    mem_waits=w.value, fused_launches=fl.value, fused_items=fi.value)
 
     def close(self):
         if getattr(self, "h", None):

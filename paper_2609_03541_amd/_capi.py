@@ -91,7 +91,7 @@ STAGE32_STORED = 4
 
 class ServerOptions(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int),
-                ("caller_driven", C.c_int)]
+                ("caller_driven", C.c_int), ("fuse", C.c_int)]
 
 
 class Request(C.Structure):
@@ -155,6 +155,7 @@ SIGNATURES = {
     "bumbar_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(Stats), dp,
                                        C.POINTER(C.c_int)]),
     "bumbar_server_counters": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_size_t), i64p]),
+    "bumbar_server_fused_counters": (C.c_int, [vp, i64p, i64p]),
     "bumbar_server_destroy": (None, [vp]),
 }
 

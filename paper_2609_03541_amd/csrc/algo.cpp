@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <utility>
 #include <vector>
 
@@ -463,16 +464,41 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   };
   auto small_batch = [&](const Level& L, const double* fin, int T) -> int {
     const Mat M = level_mat(L);
+    SmallBatch a;
+    a.u = reinterpret_cast<const double*>(M.u);
+    a.ld = M.ld;
+    a.h = L.h;
+    a.Nk = Nk_dev;
+    a.f_in = fin;
+    a.f_hist = fh(0);
+    a.scal = B.scal_hist;
+    a.logD = BB.logD_lvl;
+    a.lnS = B.lnS_t;
+    a.S = B.S_t;
+    a.cst = B.cst;
+    a.gk = B.gk;
+    a.lnNp = B.lnNp;
+    a.K = K;
+    a.P = (int)L.P;
+    a.T = T;
+    a.nc = small_batch_nc(K, L.P);
+    // a fusing server takes the batch into its next fused launch
+    if (ctx->post_small) return ctx->post_small(ctx->post_arg, a);
     // ctx->stream, not s: while a batch is captured it names the capture stream
-    hipError_t e2 = launch_small_batch(ctx->stream, reinterpret_cast<const double*>(M.u), M.ld, K, L.P,
-                                       L.h, Nk_dev, fin, T, fh(0), B.scal_hist, BB.logD_lvl,
-                                       B.lnS_t, B.S_t, B.cst, B.gk, B.lnNp);
+    hipError_t e2 = launch_small_batch(ctx->stream, a);
     return e2 == hipSuccess ? BUMBAR_OK : hip_fail(ctx, e2, "small batch");
   };
+
   int64_t it1 = 0, it2 = 0, nchk = 0;
   int result = BUMBAR_OK;
   BatchGraphs graphs(ctx, opt.graphs != 0);
-  // ---- phase 1: iterate at n0 until the relative step is below eps ----
+  // batches handed to a fusing server are not captured here (the server
+  // launches them); every other batch goes through the graphs
+  auto run_batch = [&](const BatchKey& key, const Level& L, bool small_part,
+                       const std::function<int()>& enqueue) -> int {
+    if (ctx->post_small && small_part && small_level(L)) return enqueue();
+    return graphs.run(key, enqueue);
+  };  // ---- phase 1: iterate at n0 until the relative step is below eps ----
   for (bool done = false; !done;) {
     if (it1 + it2 >= opt.max_iter) {
       result = BUMBAR_ENOTCONV;
@@ -482,7 +508,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     if (opt.replay_refine) T = std::min<int64_t>(T, std::max<int64_t>(1, opt.replay_phase1 - it1));
     int nvalid = 0;  // leading steps that are usable
     if (fast) {
-      rc = graphs.run({1, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+      rc = run_batch({1, T, level_id(cur), cur.P, nullptr, 0}, cur, true, [&]() -> int {
         if (small_level(cur)) return small_batch(cur, BB.f_n, (int)T);
         for (int i = 0; i < T; ++i) {
           // each step's finaliser leaves the constants of the next step in B.cst
@@ -542,7 +568,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
           fallback = true;
           break;
         }
-        rc = graphs.run({2, T, level_id(cur), cur.P, nullptr, 0}, [&]() -> int {
+        rc = run_batch({2, T, level_id(cur), cur.P, nullptr, 0}, cur, true, [&]() -> int {
           if (small_level(cur)) return small_batch(cur, BB.f_n, T);
           for (int i = 0; i < T; ++i) {
             const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
@@ -568,7 +594,8 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         const int T = nint - done_int;
         in = T;
         ix = T + 1;
-        rc = graphs.run({3, T, level_id(cur), cur.P, level_id(nxt), nxt.P}, [&]() -> int {
+        rc = run_batch({3, T, level_id(cur), cur.P, level_id(nxt), nxt.P}, cur, T > 0,
+                       [&]() -> int {
           if (T > 0 && small_level(cur)) {
             const int r = small_batch(cur, BB.f_n, T);
             if (r) return r;

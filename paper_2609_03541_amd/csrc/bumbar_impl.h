@@ -116,10 +116,43 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
 // gk and lnNp as launch_prepare_consts would leave them for the last f.
 // small_batch_nc(K, P) is 0 where the batch kernel does not apply.
 int small_batch_nc(int K, int64_t P);
-hipError_t launch_small_batch(hipStream_t s, const double* u, int64_t ld, int K, int64_t P,
-                              const double* h, const int64_t* Nk, const double* f_in, int T,
-                              double* f_hist, SweepScalars* scal, double* logD, double* lnS,
-                              double* S, double* cst, double* gk, double* lnNp);
+// The arguments of one such batch (nc = small_batch_nc(K, P)).
+struct SmallBatch {
+  const double* u;
+  int64_t ld;
+  const double* h;
+  const int64_t* Nk;
+  const double* f_in;
+  double* f_hist;
+  SweepScalars* scal;
+  double* logD;
+  double* lnS;
+  double* S;
+  double* cst;
+  double* gk;
+  double* lnNp;
+  int K, P, T, nc;
+};
+hipError_t launch_small_batch(hipStream_t s, const SmallBatch& a);
+// Batches of several independent problems in one launch per column layout:
+// a fixed grid of workgroups walks the items of its layout in the device
+// work list (workgroup b takes items b, b + grid, ...); each item runs
+// exactly the code of launch_small_batch, so its outputs are bitwise those
+// of its own launch. Layout classes 0..3 are nc = 64, 128, 256, 512; the
+// items of class c are items[first[c] .. first[c] + count[c]).
+constexpr int kFusedGrid = 256;
+struct SmallWorkHeader {
+  int64_t count[4];
+  int64_t first[4];
+};
+inline size_t small_work_bytes(int64_t count) {
+  return sizeof(SmallWorkHeader) + (size_t)count * sizeof(SmallBatch);
+}
+int small_class(int nc);  // 0..3, -1 for an nc that is not a layout
+// wl: device work list (header, then the items); a kernel of grid
+// workgroups for each class whose bit is set in cls_mask.
+hipError_t launch_small_fused(hipStream_t s, const SmallWorkHeader* wl, unsigned cls_mask,
+                              int grid);
 
 // cst_k = ln N'_k + f_k, gk, lnNp from N_k and f.
 hipError_t launch_prepare_consts(hipStream_t s, int K, const int64_t* Nk, const double* f,
@@ -280,4 +313,9 @@ struct bumbar_ctx {
   // blocking on a busy stream the solve hands control back to the server
   void (*yield)(void*) = nullptr;
   void* yield_arg = nullptr;
+  // set by a server that fuses the small batches of its problems into one
+  // launch: the batch is handed over instead of launched; the call returns
+  // once the fused launch is queued and ctx->stream waits for it
+  int (*post_small)(void* arg, const bumbar::SmallBatch& a) = nullptr;
+  void* post_arg = nullptr;
 };

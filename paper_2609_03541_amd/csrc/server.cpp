@@ -19,6 +19,17 @@
 // (ctx_wait) it swaps back to the tick, which resumes the next slot. Kernels
 // of all slots stay queued on their streams meanwhile, so they overlap on the
 // device exactly as with threads, but nothing advances between ticks.
+//
+// Fused launches (caller-driven servers with fuse = 1): a solve that reaches
+// a batch of binned steps on a level small enough for one workgroup posts
+// the batch's arguments instead of launching it and yields. After resuming
+// every slot the tick writes all posts of the tick into a pinned work list,
+// makes the fused stream wait for each posting slot's stream (an event
+// recorded at the post), and replays a captured graph (copy of the work list
+// to the device, then one fused kernel over all items); each posting slot's
+// stream then waits for the graph's completion event before its readback.
+// Two work-list buffers alternate; a buffer is rewritten only once the
+// replay that last read it has completed (else the posts wait a tick).
 #include <hip/hip_runtime.h>
 #include <sys/mman.h>
 #include <ucontext.h>
@@ -122,11 +133,32 @@ constexpr size_t kFiberStack = size_t(4) << 20;
 struct Slot {
   bumbar_server* srv = nullptr;
   hipStream_t stream = nullptr;
+  hipEvent_t ev_post = nullptr;  // fused servers: recorded on the stream at a post
   bumbar_ctx* ctx = nullptr;
   // caller-driven: the job on this slot and its arena block
   std::shared_ptr<Job> job;
   size_t off = 0;
   Fiber fib;  // ucontext_t points into itself: a Slot never moves (held by pointer)
+};
+
+// A batch handed to the next fused launch; lives on the posting fiber's
+// stack until the launch is queued.
+struct Post {
+  Slot* slot = nullptr;
+  bumbar::SmallBatch a{};
+  hipEvent_t done = nullptr;
+  hipError_t status = hipSuccess;
+  bool launched = false;
+};
+
+// One work-list buffer of the fused launches and the graphs that replay it
+// (one per item count).
+struct FusedBuf {
+  bumbar::SmallWorkHeader* host = nullptr;  // pinned
+  bumbar::SmallWorkHeader* dev = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+  std::map<int64_t, hipGraphExec_t> graphs;
 };
 
 }  // namespace
@@ -149,6 +181,16 @@ struct bumbar_server {
   int64_t mem_waits = 0;  // requests that waited at the head of the queue for arena room
   // workspace sizing uses a context that is never used for work
   bumbar_ctx* sizing_ctx = nullptr;
+  // fused launches
+  hipStream_t fstream = nullptr;  // the fused launches run here
+  hipStream_t fcap = nullptr;     // graphs are captured here (nothing executes on it)
+  FusedBuf fbuf[2];
+  size_t fbytes = 0;  // a work-list buffer: header and max_active items
+  int fgrid = 1;      // workgroups per fused kernel: min(max_active, kFusedGrid)
+  int fnext = 0;
+  bool fgraphs = true;  // false once capture or instantiation failed
+  std::vector<Post*> posts;
+  int64_t fused_launches = 0, fused_items = 0;
 };
 
 namespace {
@@ -333,6 +375,8 @@ void fiber_main() {
   }
   sl->ctx->yield = nullptr;
   sl->ctx->yield_arg = nullptr;
+  sl->ctx->post_small = nullptr;
+  sl->ctx->post_arg = nullptr;
   sl->fib.finished = true;
   // returning resumes uc_link, the tick that last resumed this fiber
 }
@@ -355,6 +399,100 @@ void fiber_free(Fiber& f) {
   f.map = nullptr;
 }
 
+// ctx->post_small of a fused server's fibers: queue the batch for the tick's
+// fused launch, yield until it is queued, then order the slot's stream
+// after it.
+int post_small(void* arg, const bumbar::SmallBatch& a) {
+  Slot& sl = *static_cast<Slot*>(arg);
+  hipError_t e = hipEventRecord(sl.ev_post, sl.stream);
+  if (e != hipSuccess) return bumbar::hip_fail(sl.ctx, e, "post event");
+  Post p;
+  p.slot = &sl;
+  p.a = a;
+  sl.srv->posts.push_back(&p);
+  while (!p.launched) sl.ctx->yield(sl.ctx->yield_arg);
+  if (p.status != hipSuccess) return bumbar::hip_fail(sl.ctx, p.status, "fused launch");
+  e = hipStreamWaitEvent(sl.stream, p.done, 0);
+  if (e != hipSuccess) return bumbar::hip_fail(sl.ctx, e, "wait for the fused launch");
+  return BUMBAR_OK;
+}
+
+// The graph of buffer fb for the column-layout classes in mask: the work
+// list's copy, then a fused kernel per class (nullptr if capture is off or
+// fails). The copy is of the whole buffer, so the graph serves any counts.
+hipGraphExec_t fused_graph(bumbar_server* srv, FusedBuf& fb, unsigned mask) {
+  auto it = fb.graphs.find(mask);
+  if (it != fb.graphs.end()) return it->second;
+  if (!srv->fgraphs) return nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipError_t e = hipStreamBeginCapture(srv->fcap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t e1 = hipMemcpyAsync(fb.dev, fb.host, srv->fbytes, hipMemcpyHostToDevice, srv->fcap);
+    if (e1 == hipSuccess) e1 = bumbar::launch_small_fused(srv->fcap, fb.dev, mask, srv->fgrid);
+    e = hipStreamEndCapture(srv->fcap, &g);
+    if (e == hipSuccess) e = e1;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    srv->fgraphs = false;  // launched directly from now on
+    return nullptr;
+  }
+  fb.graphs[mask] = x;
+  return x;
+}
+
+// Queues one fused launch over every post of this tick (after the slot
+// resumptions); posts stay pending for a tick if the next buffer is still
+// being read by an earlier launch.
+void launch_fused(bumbar_server* srv) {
+  if (srv->posts.empty()) return;
+  FusedBuf& fb = srv->fbuf[srv->fnext];
+  if (fb.used && hipEventQuery(fb.done) == hipErrorNotReady) return;
+  (void)hipGetLastError();
+  srv->fnext ^= 1;
+  // the items grouped by column layout, in posting order within a layout
+  bumbar::SmallWorkHeader& hd = *fb.host;
+  bumbar::SmallBatch* items = reinterpret_cast<bumbar::SmallBatch*>(fb.host + 1);
+  unsigned mask = 0u;
+  int64_t n = 0;
+  for (int c = 0; c < 4; ++c) {
+    hd.first[c] = n;
+    hd.count[c] = 0;
+    for (Post* p : srv->posts)
+      if (bumbar::small_class(p->a.nc) == c) {
+        items[n++] = p->a;
+        hd.count[c]++;
+      }
+    if (hd.count[c]) mask |= 1u << c;
+  }
+  hipError_t e = n == (int64_t)srv->posts.size() ? hipSuccess : hipErrorInvalidValue;
+  for (Post* p : srv->posts)
+    if (e == hipSuccess) e = hipStreamWaitEvent(srv->fstream, p->slot->ev_post, 0);
+  if (e == hipSuccess) {
+    hipGraphExec_t x = fused_graph(srv, fb, mask);
+    if (x) {
+      e = hipGraphLaunch(x, srv->fstream);
+    } else {
+      e = hipMemcpyAsync(fb.dev, fb.host, bumbar::small_work_bytes(n), hipMemcpyHostToDevice,
+                         srv->fstream);
+      if (e == hipSuccess) e = bumbar::launch_small_fused(srv->fstream, fb.dev, mask, srv->fgrid);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(fb.done, srv->fstream);
+  fb.used = true;
+  for (Post* p : srv->posts) {
+    p->done = fb.done;
+    p->status = e;
+    p->launched = true;
+  }
+  srv->posts.clear();
+  srv->fused_launches++;
+  srv->fused_items += n;
+}
+
 // Starts the fiber of a slot that has just been given a job.
 bool fiber_start(Slot& sl) {
   Fiber& f = sl.fib;
@@ -366,6 +504,10 @@ bool fiber_start(Slot& sl) {
   f.finished = false;
   sl.ctx->yield = fiber_yield;
   sl.ctx->yield_arg = &f;
+  if (sl.srv->opt.fuse) {
+    sl.ctx->post_small = post_small;
+    sl.ctx->post_arg = &sl;
+  }
   return true;
 }
 
@@ -415,6 +557,7 @@ int tick(bumbar_server* srv) {
     sl.job.reset();
     ++done;
   }
+  launch_fused(srv);
   if (done) srv->cv_done.notify_all();
   return done;
 }
@@ -429,9 +572,19 @@ bool any_running(bumbar_server* srv) {
 void release_slots(bumbar_server* srv) {
   for (auto& slp : srv->slots) {
     if (slp->ctx) bumbar_destroy(slp->ctx);
+    if (slp->ev_post) (void)hipEventDestroy(slp->ev_post);
     if (slp->stream) (void)hipStreamDestroy(slp->stream);
     fiber_free(slp->fib);
   }
+  if (srv->fstream) (void)hipStreamSynchronize(srv->fstream);
+  for (FusedBuf& fb : srv->fbuf) {
+    for (auto& g : fb.graphs) (void)hipGraphExecDestroy(g.second);
+    if (fb.done) (void)hipEventDestroy(fb.done);
+    if (fb.host) (void)hipHostFree(fb.host);
+    if (fb.dev) (void)hipFree(fb.dev);
+  }
+  if (srv->fstream) (void)hipStreamDestroy(srv->fstream);
+  if (srv->fcap) (void)hipStreamDestroy(srv->fcap);
   bumbar_destroy(srv->sizing_ctx);
   (void)hipFree(srv->arena);
   delete srv;
@@ -443,6 +596,7 @@ extern "C" {
 
 int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) {
   if (!opt || !out || opt->max_active < 1 || opt->hbm_budget_bytes < kAlign) return BUMBAR_EINVAL;
+  if (opt->fuse != 0 && (opt->fuse != 1 || !opt->caller_driven)) return BUMBAR_EINVAL;
   *out = nullptr;
   auto* srv = new (std::nothrow) bumbar_server();
   if (!srv) return BUMBAR_ENOMEM;
@@ -467,6 +621,7 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) 
     std::unique_ptr<Slot> sl(new Slot());
     sl->srv = srv;
     if (hipStreamCreate(&sl->stream) != hipSuccess ||
+        (opt->fuse && hipEventCreateWithFlags(&sl->ev_post, hipEventDisableTiming) != hipSuccess) ||
         bumbar_create(&sl->ctx, opt->device, sl->stream) != BUMBAR_OK) {
       (void)hipGetLastError();
       srv->slots.push_back(std::move(sl));
@@ -478,6 +633,23 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) 
     if (!fib_ok) {
       release_slots(srv);
       return BUMBAR_ENOMEM;
+    }
+  }
+  if (opt->fuse) {
+    // one work-list buffer holds a post of every slot
+    const size_t wl = bumbar::small_work_bytes(opt->max_active);
+    srv->fbytes = wl;
+    srv->fgrid = std::min(opt->max_active, bumbar::kFusedGrid);
+    bool ok = hipStreamCreate(&srv->fstream) == hipSuccess &&
+              hipStreamCreateWithFlags(&srv->fcap, hipStreamNonBlocking) == hipSuccess;
+    for (FusedBuf& fb : srv->fbuf)
+      ok = ok && hipHostMalloc(reinterpret_cast<void**>(&fb.host), wl, hipHostMallocDefault) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void**>(&fb.dev), wl) == hipSuccess &&
+           hipEventCreateWithFlags(&fb.done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      release_slots(srv);
+      return BUMBAR_EDEVICE;
     }
   }
   if (!opt->caller_driven)
@@ -588,6 +760,14 @@ int bumbar_server_counters(bumbar_server* srv, int64_t* completed, int64_t* peak
   if (peak_active) *peak_active = srv->peak_active;
   if (peak_bytes) *peak_bytes = srv->alloc->peak();
   if (mem_waits) *mem_waits = srv->mem_waits;
+  return BUMBAR_OK;
+}
+
+int bumbar_server_fused_counters(bumbar_server* srv, int64_t* launches, int64_t* items) {
+  if (!srv) return BUMBAR_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (launches) *launches = srv->fused_launches;
+  if (items) *items = srv->fused_items;
   return BUMBAR_OK;
 }
 

@@ -15,6 +15,11 @@
 // the batch the constants c_k = ln N'_k + f_k, the sampled flags and ln N'_k
 // are left as the next sweep expects them. All sums run in a fixed order, so
 // the results do not depend on timing.
+//
+// The fused kernels run the batches of several independent problems (a
+// serving mix) together: a fixed grid walks a device work list, each
+// workgroup running whole items with the same inlined code; one kernel per
+// column layout present in the list.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -48,18 +53,24 @@ struct SmallShared {
   unsigned flags[2];
 };
 
+// The batch of one problem on the workgroup's LDS block L (every thread of
+// the workgroup calls it).
 template <int NC>
-__global__ void __launch_bounds__(kSB)
-    sci_small_kernel(const double* __restrict__ u, int64_t ld, int K, int P,
-                     const double* __restrict__ h, const int64_t* __restrict__ Nk,
-                     const double* __restrict__ f_in, int T, double* __restrict__ f_hist,
-                     SweepScalars* __restrict__ scal, double* __restrict__ logD,
-                     double* __restrict__ lnS_out, double* __restrict__ S_out,
-                     double* __restrict__ cst, double* __restrict__ gk_out,
-                     double* __restrict__ lnNp_out) {
+__device__ __forceinline__ void small_steps(SmallShared<NC>& L, const double* __restrict__ u,
+                                            int64_t ld, int K, int P,
+                                            const double* __restrict__ h,
+                                            const int64_t* __restrict__ Nk,
+                                            const double* __restrict__ f_in, int T,
+                                            double* __restrict__ f_hist,
+                                            SweepScalars* __restrict__ scal,
+                                            double* __restrict__ logD,
+                                            double* __restrict__ lnS_out,
+                                            double* __restrict__ S_out,
+                                            double* __restrict__ cst,
+                                            double* __restrict__ gk_out,
+                                            double* __restrict__ lnNp_out) {
   using SS = SmallShared<NC>;
   constexpr int KR = SS::KR;
-  __shared__ SS L;
   const int tid = threadIdx.x;
   const int nc = tid % NC, kr = tid / NC;
   const bool colv = nc < P;
@@ -252,6 +263,34 @@ __global__ void __launch_bounds__(kSB)
 }
 
 template <int NC>
+__device__ __forceinline__ void small_steps(SmallShared<NC>& L, const SmallBatch& a) {
+  small_steps<NC>(L, a.u, a.ld, a.K, a.P, a.h, a.Nk, a.f_in, a.T, a.f_hist, a.scal, a.logD,
+                  a.lnS, a.S, a.cst, a.gk, a.lnNp);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kSB) sci_small_kernel(SmallBatch a) {
+  __shared__ SmallShared<NC> L;
+  small_steps<NC>(L, a);
+}
+
+// The items of column layout NC in a work list (a launch per layout: one
+// kernel holding all four bodies would spill registers).
+template <int NC>
+__global__ void __launch_bounds__(kSB)
+    sci_small_fused_kernel(const SmallWorkHeader* __restrict__ wl, int cls) {
+  __shared__ SmallShared<NC> L;
+  const int64_t count = wl->count[cls];
+  const SmallBatch* items = reinterpret_cast<const SmallBatch*>(wl + 1) + wl->first[cls];
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const SmallBatch a = items[i];
+    small_steps<NC>(L, a);
+    // the next item reuses the LDS block
+    __syncthreads();
+  }
+}
+
+template <int NC>
 constexpr int small_kcap() {
   return (kSB / NC) * kSR;
 }
@@ -267,17 +306,13 @@ int small_batch_nc(int K, int64_t P) {
   return 0;
 }
 
-hipError_t launch_small_batch(hipStream_t s, const double* u, int64_t ld, int K, int64_t P,
-                              const double* h, const int64_t* Nk, const double* f_in, int T,
-                              double* f_hist, SweepScalars* scal, double* logD, double* lnS,
-                              double* S, double* cst, double* gk, double* lnNp) {
-  const int nc = small_batch_nc(K, P);
-  if (nc == 0 || T < 1 || ld < P) return hipErrorInvalidValue;
-#define BUMBAR_SMALL(NCV)                                                                       \
-  if (nc == NCV) {                                                                              \
-    hipLaunchKernelGGL(sci_small_kernel<NCV>, dim3(1), dim3(kSB), 0, s, u, ld, K, (int)P, h, Nk, \
-                       f_in, T, f_hist, scal, logD, lnS, S, cst, gk, lnNp);                     \
-    return hipGetLastError();                                                                   \
+hipError_t launch_small_batch(hipStream_t s, const SmallBatch& a) {
+  const int nc = small_batch_nc(a.K, a.P);
+  if (nc == 0 || nc != a.nc || a.T < 1 || a.ld < a.P) return hipErrorInvalidValue;
+#define BUMBAR_SMALL(NCV)                                                     \
+  if (nc == NCV) {                                                            \
+    hipLaunchKernelGGL(sci_small_kernel<NCV>, dim3(1), dim3(kSB), 0, s, a);   \
+    return hipGetLastError();                                                 \
   }
   BUMBAR_SMALL(64)
   BUMBAR_SMALL(128)
@@ -285,6 +320,28 @@ hipError_t launch_small_batch(hipStream_t s, const double* u, int64_t ld, int K,
   BUMBAR_SMALL(512)
 #undef BUMBAR_SMALL
   return hipErrorInvalidValue;
+}
+
+int small_class(int nc) {
+  return nc == 64 ? 0 : nc == 128 ? 1 : nc == 256 ? 2 : nc == 512 ? 3 : -1;
+}
+
+hipError_t launch_small_fused(hipStream_t s, const SmallWorkHeader* wl, unsigned cls_mask,
+                              int grid) {
+  if (!wl || grid < 1 || grid > kFusedGrid || cls_mask == 0u || cls_mask > 15u)
+    return hipErrorInvalidValue;
+#define BUMBAR_FUSED(NCV, C)                                                              \
+  if (cls_mask & (1u << C)) {                                                             \
+    hipLaunchKernelGGL(sci_small_fused_kernel<NCV>, dim3(grid), dim3(kSB), 0, s, wl, C);  \
+    const hipError_t e = hipGetLastError();                                               \
+    if (e != hipSuccess) return e;                                                        \
+  }
+  BUMBAR_FUSED(64, 0)
+  BUMBAR_FUSED(128, 1)
+  BUMBAR_FUSED(256, 2)
+  BUMBAR_FUSED(512, 3)
+#undef BUMBAR_FUSED
+  return hipSuccess;
 }
 
 }  // namespace bumbar

@@ -88,3 +88,14 @@ def test_struct_layouts_match_header():
         body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
         fields = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*;", body)
         assert fields == [f for f, _ in cls._fields_], struct
+
+
+def test_fused_server_needs_caller_driven(lib):
+    # fuse = 1 is refused for a threaded server and for values other than
+    # 0/1, before any device call
+    from paper_2609_03541_amd import _capi
+    h = C.c_void_p()
+    for caller_driven, fuse in ((0, 1), (1, 2), (1, -1)):
+        o = _capi.ServerOptions(0, 1 << 20, 2, caller_driven, fuse)
+        assert lib.bumbar_server_create(C.byref(o), C.byref(h)) == -1
+        assert not h.value

@@ -269,3 +269,46 @@ def test_materialized_fp32_requests(bm, caller_driven):
         assert np.array_equal(f, f_solo.cpu().numpy()), i
         f_ref, _ = oracle.solve_mbar(u32.double().cpu().numpy(), p["Nk"])
         assert np.max(np.abs(f - f_ref)) < 1e-9, i
+
+
+@pytest.mark.parametrize("kind", ["fp64_stored", "fp32_materialized"])
+def test_fused_server_equals_solo_and_oracle(bm, kind):
+    # a fusing server gathers the small binned batches of all its problems
+    # into one graph-replayed launch per tick; every result is bitwise the
+    # solo solve's (same code per item) and the oracle's to the tolerance
+    import torch
+    if kind == "fp64_stored":
+        probs = small_stream(12, seed=31)
+        kw = [dict(u=p["u"], xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11)
+              for p in probs]
+    else:
+        specs = synth.serving_stream(n_problems=8, seed=37, K_range=(20, 120),
+                                     Nk_range=(200, 600))
+        probs = [synth.materialize_problem(s) for _, s in specs]
+        kw = [dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], materialize=True,
+                   tol=1e-10, precision=bm.PREC_MIXED) for p in probs]
+    srv = bm.Server(hbm_budget_bytes=1 << 30, max_active=6, caller_driven=True, fuse=True)
+    try:
+        ts = [srv.submit(p["Nk"], **k) for p, k in zip(probs, kw)]
+        res = [srv.result(t) for t in ts]
+        c = srv.counters()
+    finally:
+        srv.close()
+    say(f"fused {kind}: {c['fused_launches']} launches, {c['fused_items']} batches")
+    assert c["fused_launches"] >= 1 and c["fused_items"] > c["fused_launches"]
+    for i, (p, k, (f, info)) in enumerate(zip(probs, kw, res)):
+        say(f"fused {kind} problem {i}: K={p['K']} N={p['N']} status={info['status']} "
+            f"batched={info['batched_steps']}")
+        assert info["status"] == 0
+        kk = dict(k)
+        if kind == "fp64_stored":
+            f_solo, _ = bm.solve(dev(kk.pop("u")), p["Nk"], **kk)
+            f_ref, _ = oracle.solve_mbar(p["u"], p["Nk"])
+        else:
+            kk.pop("materialize")
+            u32 = bm.model_energies(p["xi"], p["coef"], p["model_type"], p["K"],
+                                    dtype=torch.float32)
+            f_solo, _ = bm.solve(u32, p["Nk"], **kk)
+            f_ref, _ = oracle.solve_mbar(u32.double().cpu().numpy(), p["Nk"])
+        assert np.array_equal(f, f_solo.cpu().numpy()), i
+        assert np.max(np.abs(f - f_ref)) < 1e-9, i
