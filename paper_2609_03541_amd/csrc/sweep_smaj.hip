@@ -66,6 +66,7 @@ __device__ __forceinline__ int smaj_state(int lane, int j) {
 template <int J, typename TI, bool F32A, bool MASKED, bool CHK>
 __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, int64_t n0,
                                           int64_t W, int lane, const double* __restrict__ c_sh,
+                                          const float* __restrict__ c32_sh,
                                           const double* __restrict__ etab, unsigned gm,
                                           const double* __restrict__ h,
                                           double* __restrict__ logD,
@@ -94,30 +95,51 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
         }
       }
     }
-    double m[S], chk = 0.0;
+    double m[S];
+    if constexpr (F32A) {
+      // the shift only has to be near the maximum: taken in FP32 (nothing
+      // is held for the second pass, which recomputes the FP64 difference)
+      float m32[S];
 #pragma unroll
-    for (int i = 0; i < S; ++i) m[i] = -INFINITY;
+      for (int i = 0; i < S; ++i) m32[i] = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const double cj = c_sh[smaj_state<J, TI>(lane, j)];
+      for (int j = 0; j < J; ++j) {
+        const float cj = c32_sh[smaj_state<J, TI>(lane, j)];
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const double a = cj - (double)x[i][j];
-        m[i] = fmax(m[i], a);
-        if constexpr (CHK) chk += a;  // NaN if any u is NaN (padding gives -inf, not NaN)
+        for (int i = 0; i < S; ++i) m32[i] = fmaxf(m32[i], cj - (float)x[i][j]);
       }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < S; ++i) m32[i] = fmaxf(m32[i], __shfl_xor(m32[i], off, 64));
+#pragma unroll
+      for (int i = 0; i < S; ++i) m[i] = m32[i] == -INFINITY ? 0.0 : (double)m32[i];
+    } else {
+      double chk = 0.0;
+#pragma unroll
+      for (int i = 0; i < S; ++i) m[i] = -INFINITY;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const double cj = c_sh[smaj_state<J, TI>(lane, j)];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double a = cj - (double)x[i][j];
+          m[i] = fmax(m[i], a);
+          if constexpr (CHK) chk += a;  // NaN if any u is NaN (padding gives -inf, not NaN)
+        }
+      }
+      if (CHK && chk != chk) bad |= FLAG_NAN;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < S; ++i) m[i] = fmax(m[i], __shfl_xor(m[i], off, 64));
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+        if (m[i] == -INFINITY) m[i] = 0.0;
     }
-    if (CHK && chk != chk) bad |= FLAG_NAN;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1)
-#pragma unroll
-      for (int i = 0; i < S; ++i) m[i] = fmax(m[i], __shfl_xor(m[i], off, 64));
     TA e[S][J], d[S];
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      if (m[i] == -INFINITY) m[i] = 0.0;
-      d[i] = 0;
-    }
+    for (int i = 0; i < S; ++i) d[i] = 0;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const double cj = c_sh[smaj_state<J, TI>(lane, j)];
@@ -139,6 +161,7 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
 #pragma unroll
       for (int i = 0; i < S; ++i) d[i] += __shfl_xor(d[i], off, 64);
     TA w[S];
+    double hl = 1.0, ml = m[0], dl = (double)d[0];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const int64_t n = nb + i;
@@ -152,16 +175,27 @@ __device__ __forceinline__ void smaj_loop(const TI* __restrict__ ut, int64_t N, 
         if (valid && !(dd >= 1e-300 && dd <= 1e300)) bad |= FLAG_COL;
         w[i] = valid ? hn * rcp_nr(dd) : 0.0;
       }
-      if (lane == i && valid) {
-        const double l = m[i] + log_ge1(dd);
-        if (logD) logD[n] = l;
-        obj = __builtin_fma(hn, l, obj);
+      if (lane == i) {
+        hl = hn;
+        ml = m[i];
+        dl = dd;
       }
+    }
+    // ln D_n of the S samples in one masked pass: lane i takes sample i
+    if (lane < S && nb + lane < N) {
+      const double l = ml + log_ge1(dl);
+      if (logD) logD[nb + lane] = l;
+      obj = __builtin_fma(hl, l, obj);
     }
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int i = 0; i < S; ++i) acc[j] = __builtin_fma(e[i][j], w[i], acc[j]);
+      for (int i = 0; i < S; ++i) {
+        if constexpr (F32A)
+          acc[j] = __builtin_fmaf(e[i][j], w[i], acc[j]);
+        else
+          acc[j] = __builtin_fma(e[i][j], w[i], acc[j]);
+      }
   }
 }
 
@@ -175,15 +209,20 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
                       double* __restrict__ part_obj, unsigned* __restrict__ part_flags) {
   constexpr int Kp = 64 * J;
   using TA = std::conditional_t<F32A, float, double>;
-  __shared__ double red[kSmajWaves][Kp];
+  __shared__ double red[kSmajWaves / 2][Kp];
   __shared__ double c_sh[Kp];
+  __shared__ float c32_sh[F32A ? Kp : 1];
   __shared__ double etab[64];
   __shared__ double ored[kSmajWaves];
   __shared__ unsigned fl;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) fl = 0u;
-  for (int k = threadIdx.x; k < Kp; k += kSmajWaves * 64) c_sh[k] = k < K ? cst[k] : -INFINITY;
+  for (int k = threadIdx.x; k < Kp; k += kSmajWaves * 64) {
+    const double c = k < K ? cst[k] : -INFINITY;
+    c_sh[k] = c;
+    if constexpr (F32A) c32_sh[k] = (float)c;
+  }
   if (threadIdx.x < 64) etab[threadIdx.x] = kExp2Frac64[threadIdx.x];
   TA acc[J];
   unsigned gm = 0u, valid_bits = 0u;
@@ -202,13 +241,20 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
   const int64_t W = (int64_t)gridDim.x * kSmajWaves * kSmajS;
   const int64_t n0 = ((int64_t)blockIdx.x * kSmajWaves + wave) * kSmajS;
   if (masked)
-    smaj_loop<J, TI, F32A, true, CHK>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj, bad);
+    smaj_loop<J, TI, F32A, true, CHK>(ut, N, n0, W, lane, c_sh, c32_sh, etab, gm, h, logD, acc,
+                                      obj, bad);
   else
-    smaj_loop<J, TI, F32A, false, CHK>(ut, N, n0, W, lane, c_sh, etab, gm, h, logD, acc, obj,
-                                       bad);
-  // per-state sums of the workgroup: waves in order through LDS
+    smaj_loop<J, TI, F32A, false, CHK>(ut, N, n0, W, lane, c_sh, c32_sh, etab, gm, h, logD, acc,
+                                       obj, bad);
+  // per-state sums of the workgroup, waves in order through LDS in two
+  // halves (half the LDS, so more workgroups fit a CU):
+  // v_k = ((a0 + a1) + a2) + a3
+  constexpr int kHalf = kSmajWaves / 2;
+  constexpr int kPer = (Kp + kSmajWaves * 64 - 1) / (kSmajWaves * 64);
+  if (wave < kHalf) {
 #pragma unroll
-  for (int j = 0; j < J; ++j) red[wave][smaj_state<J, TI>(lane, j)] = (double)acc[j];
+    for (int j = 0; j < J; ++j) red[wave][smaj_state<J, TI>(lane, j)] = (double)acc[j];
+  }
   // objective: lanes 0 .. S-1 of each wave hold its parts
   double o = obj;
 #pragma unroll
@@ -216,11 +262,32 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
   if (lane == 0) ored[wave] = o;
   if (bad) atomicOr(&fl, bad);
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += kSmajWaves * 64) {
-    double v = red[0][k];
+  double t[kPer];
 #pragma unroll
-    for (int wv = 1; wv < kSmajWaves; ++wv) v += red[wv][k];
-    part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+  for (int q = 0; q < kPer; ++q) {
+    const int k = threadIdx.x + q * kSmajWaves * 64;
+    t[q] = 0.0;
+    if (k < K) {
+      t[q] = red[0][k];
+#pragma unroll
+      for (int wv = 1; wv < kHalf; ++wv) t[q] += red[wv][k];
+    }
+  }
+  __syncthreads();
+  if (wave >= kHalf) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) red[wave - kHalf][smaj_state<J, TI>(lane, j)] = (double)acc[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int k = threadIdx.x + q * kSmajWaves * 64;
+    if (k < K) {
+      double v = t[q];
+#pragma unroll
+      for (int wv = 0; wv < kHalf; ++wv) v += red[wv][k];
+      part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+    }
   }
   if (threadIdx.x == 0) {
     double ob = ored[0];
