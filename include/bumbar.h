@@ -146,6 +146,12 @@ typedef struct {
                           default, or BUMBAR_F32): FP32 coordinates are widened (exactly)
                           into N d doubles of the workspace, which the queries then
                           include; a workspace sized for FP64 is too small for FP32 xi  */
+  int grid_batches;    /* 1: a batch of binned SCI steps on a level held in the
+                          sample-major layout (256 < K <= 1024) runs as one cooperative
+                          launch, with grid barriers between each step's sweep and its
+                          per-state sums (the device must then run no other cooperative
+                          kernel at the same time; server slots do not use it); 0
+                          (default): per-step kernels, which are faster on MI355X    */
 } bumbar_options;
 
 typedef struct {
@@ -174,6 +180,8 @@ typedef struct {
                                of at most 512 bins, the matrix held in registers)       */
   int64_t damped_steps;     /* Newton steps accepted with alpha < 1 (the finisher stops
                                only after a full step, or a fresh full step below tol)  */
+  int64_t coop_steps;       /* binned SCI steps run inside cooperative batches (levels
+                               materialised sample-major, 256 < K <= 1024)              */
 } bumbar_stats;
 
 /* ---- context ---------------------------------------------------------- */

@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
                 ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
                 ("represent", C.c_int), ("graphs", C.c_int), ("sample_major", C.c_int),
-                ("u_dtype", C.c_int), ("xi_dtype", C.c_int)]
+                ("u_dtype", C.c_int), ("xi_dtype", C.c_int), ("grid_batches", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -69,7 +69,7 @@ class Stats(C.Structure):
                 ("sweep_kernel_launches", C.c_int64), ("checks", C.POINTER(Check)),
                 ("checks_capacity", C.c_int), ("graph_batches", C.c_int64),
                 ("grid_sweeps", C.c_int64), ("batched_steps", C.c_int64),
-                ("damped_steps", C.c_int64)]
+                ("damped_steps", C.c_int64), ("coop_steps", C.c_int64)]
 
 
 class Plan(C.Structure):

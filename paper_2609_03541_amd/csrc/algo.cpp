@@ -46,7 +46,6 @@ static int level_row(int K) { return sweep_fast_supported(K) ? K : smaj_row(K); 
 
 void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool ubar_bufs,
                        bool cen_bufs, bool cen_f32, int64_t otf_cap) {
-  (void)num_cus;
   otf = cen_bufs && !ubar_bufs;
   d = d_;
   N = N_;
@@ -82,6 +81,7 @@ void BinnedBufs::carve(Arena& ar, int K, int64_t N_, int d_, int num_cus, bool u
   ubar_cap = ubar_bufs ? N : otf_cap;
   ubar_row = ubar_bufs ? K : level_row(K);
   logD_lvl = ar.take<double>(N);
+  if (smaj_batch_supported(K)) coop = ar.take<double>(smaj_batch_scratch(num_cus, kHistSteps));
   f_n = ar.take<double>(K);
   f_x = ar.take<double>(K);
 }
@@ -457,10 +457,32 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   // a batch of steps on a stored level of at most 512 bins: one workgroup
   // with the matrix in registers runs them all (same outputs per step);
   // counted after each batch, since a graph replay does not call the lambda
-  int64_t batched = 0;
+  int64_t batched = 0, coop_steps = 0;
   auto small_level = [&](const Level& L) {
     const Mat M = level_mat(L);
     return M.kind == 0 && M.u != nullptr && M.ut == nullptr && small_batch_nc(K, L.P) != 0;
+  };
+  // a batch of steps on a level materialised sample-major (256 < K <= 1024):
+  // one cooperative launch (same outputs per step as sweep and finaliser)
+  auto coop_level = [&](const Level& L) {
+    if (!opt.grid_batches || !ctx->coop_ok || BB.coop == nullptr) return false;
+    const Mat M = level_mat(L);
+    return M.kind == 0 && M.ut != nullptr && !M.ut_f32 && smaj_batch_supported(K);
+  };
+  auto coop_batch = [&](const Level& L, const double* fin, int T) -> int {
+    const Mat M = level_mat(L);
+    hipError_t e2 = launch_smaj_batch(ctx->stream, static_cast<const double*>(M.ut), K, L.P, L.h,
+                                      Nk_dev, fin, T, fh(0), B.scal_hist, BB.logD_lvl, B.lnS_t,
+                                      B.S_t, B.cst, B.gk, B.lnNp, B.part, B.nparts_cap, BB.coop,
+                                      kHistSteps, ctx->num_cus);
+    if (e2 != hipSuccess) {
+      // no co-resident grid for it on this device: the per-step kernels from now on
+      (void)hipGetLastError();
+      ctx->coop_ok = false;
+      return -1;
+    }
+    coop_steps += T;
+    return BUMBAR_OK;
   };
   auto small_batch = [&](const Level& L, const double* fin, int T) -> int {
     const Mat M = level_mat(L);
@@ -493,10 +515,11 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   int result = BUMBAR_OK;
   BatchGraphs graphs(ctx, opt.graphs != 0);
   // batches handed to a fusing server are not captured here (the server
-  // launches them); every other batch goes through the graphs
+  // launches them), nor are cooperative batches; every other batch goes
+  // through the graphs
   auto run_batch = [&](const BatchKey& key, const Level& L, bool small_part,
                        const std::function<int()>& enqueue) -> int {
-    if (ctx->post_small && small_part && small_level(L)) return enqueue();
+    if (small_part && ((ctx->post_small && small_level(L)) || coop_level(L))) return enqueue();
     return graphs.run(key, enqueue);
   };  // ---- phase 1: iterate at n0 until the relative step is below eps ----
   for (bool done = false; !done;) {
@@ -510,6 +533,10 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
     if (fast) {
       rc = run_batch({1, T, level_id(cur), cur.P, nullptr, 0}, cur, true, [&]() -> int {
         if (small_level(cur)) return small_batch(cur, BB.f_n, (int)T);
+        if (coop_level(cur)) {
+          const int r = coop_batch(cur, BB.f_n, (int)T);
+          if (r != -1) return r;
+        }
         for (int i = 0; i < T; ++i) {
           // each step's finaliser leaves the constants of the next step in B.cst
           const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
@@ -570,6 +597,10 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         }
         rc = run_batch({2, T, level_id(cur), cur.P, nullptr, 0}, cur, true, [&]() -> int {
           if (small_level(cur)) return small_batch(cur, BB.f_n, T);
+          if (coop_level(cur)) {
+            const int r = coop_batch(cur, BB.f_n, T);
+            if (r != -1) return r;
+          }
           for (int i = 0; i < T; ++i) {
             const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                                       i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl, B.lnS_t,
@@ -596,10 +627,13 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
         ix = T + 1;
         rc = run_batch({3, T, level_id(cur), cur.P, level_id(nxt), nxt.P}, cur, T > 0,
                        [&]() -> int {
+          int rc_coop = -1;
+          if (T > 0 && !small_level(cur) && coop_level(cur)) rc_coop = coop_batch(cur, BB.f_n, T);
+          if (rc_coop != -1 && rc_coop != BUMBAR_OK) return rc_coop;
           if (T > 0 && small_level(cur)) {
             const int r = small_batch(cur, BB.f_n, T);
             if (r) return r;
-          } else {
+          } else if (rc_coop != BUMBAR_OK) {
             for (int i = 0; i < T; ++i) {
               const int r = sweep_queue(ctx, B, level_mat(cur), cur.P, cur.h, Nk_dev,
                                         i == 0 ? BB.f_n : fh(i - 1), fh(i), BB.logD_lvl,
@@ -683,6 +717,7 @@ int binned_stage(bumbar_ctx* ctx, UnbinnedBufs& B, BinnedBufs& BB, const double*
   st->n_checks = nchk;
   st->graph_batches += graphs.launched();
   st->batched_steps += batched;
+  st->coop_steps += coop_steps;
   st->time_binning_ms = t_bin;
   st->time_binned_ms = now_ms() - t_start - t_bin;
   return result;

@@ -116,6 +116,19 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
 // gk and lnNp as launch_prepare_consts would leave them for the last f.
 // small_batch_nc(K, P) is 0 where the batch kernel does not apply.
 int small_batch_nc(int K, int64_t P);
+// The same batch on a level materialised in the sample-major layout (FP64,
+// 256 < K <= 1024) as one cooperative launch (sweep_smaj.hip): grid
+// barriers between each step's sweep, its per-state sums and its scalars.
+// part: K x part_cap partials; wsc: smaj_batch_scratch(num_cus, T_max)
+// doubles for batches of at most T_max steps. Also leaves ln S and S of
+// the last step.
+bool smaj_batch_supported(int K);
+int64_t smaj_batch_scratch(int num_cus, int max_steps);
+hipError_t launch_smaj_batch(hipStream_t s, const double* ut, int K, int64_t P, const double* h,
+                             const int64_t* Nk, const double* f_in, int T, double* f_hist,
+                             SweepScalars* scal, double* logD, double* lnS, double* S,
+                             double* cst, double* gk, double* lnNp, double* part, int part_cap,
+                             double* wsc, int wsc_steps, int num_cus);
 // The arguments of one such batch (nc = small_batch_nc(K, P)).
 struct SmallBatch {
   const double* u;
@@ -318,4 +331,7 @@ struct bumbar_ctx {
   // once the fused launch is queued and ctx->stream waits for it
   int (*post_small)(void* arg, const bumbar::SmallBatch& a) = nullptr;
   void* post_arg = nullptr;
+  // cooperative batches allowed (cleared for server slots, whose streams run
+  // concurrently, and after a cooperative launch failed)
+  bool coop_ok = true;
 };

@@ -628,6 +628,9 @@ int bumbar_server_create(const bumbar_server_options* opt, bumbar_server** out) 
       release_slots(srv);
       return BUMBAR_EDEVICE;
     }
+    // the slots' streams run concurrently: no cooperative launches (two of
+    // them could each hold part of the device and wait for the rest)
+    sl->ctx->coop_ok = false;
     const bool fib_ok = !opt->caller_driven || fiber_alloc(sl->fib);
     srv->slots.push_back(std::move(sl));
     if (!fib_ok) {

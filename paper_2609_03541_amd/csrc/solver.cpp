@@ -560,6 +560,7 @@ void bumbar_default_options(bumbar_options* o) {
   o->sample_major = 1;
   o->u_dtype = BUMBAR_F64;
   o->xi_dtype = BUMBAR_F64;
+  o->grid_batches = 0;
 }
 
 static int check_common(bumbar_ctx* ctx, const void* u, int u_dtype, int K, int64_t N,

@@ -212,6 +212,7 @@ struct BinnedBufs {
   float* cenf[2] = {nullptr, nullptr};   // FP32 copies of cen (mixed precision)
   double* h[2] = {nullptr, nullptr};     // N each
   double* logD_lvl = nullptr;            // N
+  double* coop = nullptr;                // scratch of the cooperative batches (256 < K <= 1024)
   double *f_n = nullptr, *f_x = nullptr; // K
   // ubar_bufs: K x N representative buffers (MEAN); cen_bufs: N x d centres
   // (CENTRE), cen_f32 also their FP32 copies; otf_cap > 0: K x otf_cap

@@ -26,6 +26,9 @@
 //    sample maximum are taken in FP64, the shifted exponent is rounded to
 //    FP32 and exponentiated with the hardware exp2; the column sums and the
 //    per-lane state accumulators are FP32, the workgroup partials FP64.
+#include <hip/hip_cooperative_groups.h>
+
+
 #include <cmath>
 #include <type_traits>
 
@@ -355,6 +358,384 @@ hipError_t launch_sweep_smaj(hipStream_t s, const void* ut, bool f32, bool f32_a
   BUMBAR_SMAJ(16)
 #undef BUMBAR_SMAJ
 #undef BUMBAR_SMAJ_ARGS
+  return hipErrorInvalidValue;
+}
+
+// ---- batches of binned steps in one cooperative launch --------------------
+//
+// A batch of T self-consistent steps (Eq. (1) with the bin counts h_n,
+// Algorithm 1) on a level materialised in the sample-major layout (FP64),
+// 256 < K <= 1024. As separate launches each step is a sweep, a reduction of
+// the per-state partials and a single-workgroup finaliser: three dependent
+// launches whose fixed costs, not the level's few hundred kilobytes, set the
+// step time. Here the grid is co-resident (cooperative launch) and a step is
+//   sweep (as sweep_smaj_kernel: workgroup partials of every state)
+//   -- grid barrier --
+//   per-state sums S_k over the workgroup partials (T lanes per state, a
+//   fixed xor butterfly), f_un_k = ln N'_k + f_k - ln S_k; every workgroup
+//   also sums state 0 itself (the same lanes' order, so the same bits) for
+//   the gauge f_new = f_un - f_un_0; iterate and per-workgroup scalars out
+//   -- grid barrier --
+// and after the last step the per-workgroup scalars of every step are added
+// in workgroup order (Eq. (2) relative step, max |delta f|, objective,
+// gradient norm, flags), a wave per value, the steps spread over the
+// workgroups: off the steps' critical path, since the host reads the
+// scalars only after the batch.
+// Outputs per step are those of a sweep and its finaliser (f_hist row i,
+// scal[i], ln D of the level); after the batch cst, gk and lnNp as the
+// constants of a sweep at the last iterate, ln S and S of the last step.
+// Measured on one MI355X it does not beat the per-step kernels (c2 ladder:
+// 97 against 54 us per binned step; K = 1000, N = 4e4: 27 against 24): a
+// grid barrier across the eight XCDs costs about as much as a kernel
+// boundary, so the solve uses it only when asked (grid_batches = 1).
+namespace {
+constexpr int kBatchVals = 8;  // per-workgroup scalars: obj, flags, gsq, minS, mdf, rs, nf, pad
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v |= __shfl_xor(v, off, 64);
+  return v;
+}
+
+// S_k summed by the T consecutive lanes starting at a multiple of T: lane c
+// adds partials c, c + T, ... in order, then a fixed butterfly over the T
+// lanes (every lane of the group gets the sum).
+__device__ __forceinline__ double state_sum(const double* __restrict__ pk, int G, int T, int c) {
+  // eight loads in flight per round trip
+  double a[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = 0.0;
+  int p = c;
+  for (; p + 7 * T < G; p += 8 * T) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += pk[p + q * T];
+  }
+  for (; p < G; p += T) a[0] += pk[p];
+  double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int off = 1; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace
+
+template <int J>
+__global__ void __launch_bounds__(kSmajWaves * 64)
+    smaj_batch_kernel(const double* __restrict__ ut, int K, int64_t P,
+                      const double* __restrict__ h, const int64_t* __restrict__ Nk,
+                      const double* __restrict__ f_in, int T, int TL,
+                      double* __restrict__ f_hist, SweepScalars* __restrict__ scal,
+                      double* __restrict__ logD, double* __restrict__ lnS_out,
+                      double* __restrict__ S_out, double* __restrict__ cst,
+                      double* __restrict__ gk_out, double* __restrict__ lnNp_out,
+                      double* __restrict__ part, double* __restrict__ wsc) {
+  using TI = double;
+  constexpr int Kp = 64 * J;
+  constexpr int NT = kSmajWaves * 64;
+  __shared__ double red[kSmajWaves / 2][Kp];
+  __shared__ double c_sh[Kp];
+  __shared__ double lnNp_sh[Kp];
+  __shared__ double etab[64];
+  __shared__ double wred[kSmajWaves][7];
+  __shared__ double g0_sh;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int G = gridDim.x, b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = tid; k < Kp; k += NT) {
+    const int64_t n = k < K ? Nk[k] : 0;
+    lnNp_sh[k] = n > 0 ? log((double)n) : 0.0;
+  }
+  if (tid < 64) etab[tid] = kExp2Frac64[tid];
+  unsigned gm = 0u, valid_bits = 0u;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int k = smaj_state<J, TI>(lane, j);
+    if (k < K) valid_bits |= 1u << j;
+    if (k < K && Nk[k] > 0) gm |= 1u << j;
+  }
+  const bool masked = __syncthreads_or(gm != valid_bits) != 0;
+  const int64_t W = (int64_t)G * kSmajWaves * kSmajS;
+  const int64_t n0 = ((int64_t)b * kSmajWaves + wave) * kSmajS;
+  constexpr int kHalf = kSmajWaves / 2;
+  constexpr int kPer = (Kp + NT - 1) / NT;
+  for (int it = 0; it < T; ++it) {
+    const double* fp = it == 0 ? f_in : f_hist + (int64_t)(it - 1) * K;
+    double* ws = wsc + (int64_t)it * G * kBatchVals;
+    // ---- sweep at fp ----
+    for (int k = tid; k < Kp; k += NT) c_sh[k] = k < K ? lnNp_sh[k] + fp[k] : -INFINITY;
+    __syncthreads();
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+    double obj = 0.0;
+    unsigned bad = 0u;
+    if (masked)
+      smaj_loop<J, TI, false, true, false>(ut, P, n0, W, lane, c_sh, nullptr, etab, gm, h, logD,
+                                           acc, obj, bad);
+    else
+      smaj_loop<J, TI, false, false, false>(ut, P, n0, W, lane, c_sh, nullptr, etab, gm, h, logD,
+                                            acc, obj, bad);
+    if (wave < kHalf) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) red[wave][smaj_state<J, TI>(lane, j)] = acc[j];
+    }
+    const double o = wave_sum(obj);
+    const unsigned fw = wave_or(bad);
+    if (lane == 0) {
+      wred[wave][0] = o;
+      wred[wave][1] = (double)fw;
+    }
+    __syncthreads();
+    double t[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = tid + q * NT;
+      t[q] = 0.0;
+      if (k < K) {
+        t[q] = red[0][k];
+#pragma unroll
+        for (int wv = 1; wv < kHalf; ++wv) t[q] += red[wv][k];
+      }
+    }
+    __syncthreads();
+    if (wave >= kHalf) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) red[wave - kHalf][smaj_state<J, TI>(lane, j)] = acc[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = tid + q * NT;
+      if (k < K) {
+        double v = t[q];
+#pragma unroll
+        for (int wv = 0; wv < kHalf; ++wv) v += red[wv][k];
+        part[(int64_t)k * G + b] = v;
+      }
+    }
+    if (tid == 0) {
+      double ob = wred[0][0];
+      unsigned fl = (unsigned)wred[0][1];
+      for (int wv = 1; wv < kSmajWaves; ++wv) {
+        ob += wred[wv][0];
+        fl |= (unsigned)wred[wv][1];
+      }
+      ws[(int64_t)b * kBatchVals + 0] = ob;
+      ws[(int64_t)b * kBatchVals + 1] = (double)fl;
+    }
+    grid.sync();
+    // ---- per-state sums, new f, gauge ----
+    if (wave == 0) {
+      const double S0 = lane < TL ? state_sum(part, G, TL, lane) : 0.0;
+      if (lane == 0) g0_sh = lnNp_sh[0] + fp[0] - log(S0);
+    }
+    __syncthreads();
+    const double fu0 = g0_sh;
+    double gsq = 0.0, minS = INFINITY, mdf = 0.0, rs = 0.0, nf = 0.0;
+    unsigned fl = 0u;
+    const int64_t gl = (int64_t)b * NT + tid;
+    const int64_t stride = (int64_t)G * NT / TL;
+    for (int64_t k = gl / TL; k < K; k += stride) {
+      const double S = state_sum(part + k * G, G, TL, (int)(gl % TL));
+      if (gl % TL != 0) continue;
+      const double lnS = log(S);
+      const double fo = fp[k];
+      const double fun = lnNp_sh[k] + fo - lnS;
+      if (!(S >= 1e-290 && S <= 1e290)) fl |= FLAG_STATE;
+      if (fun != fun) fl |= FLAG_NAN;
+      const double fn = fun - fu0;
+      f_hist[(int64_t)it * K + k] = fn;
+      const int64_t nk = Nk[k];
+      if (nk > 0) {
+        const double g = S - (double)nk;
+        gsq += g * g;
+        minS = fmin(minS, S);
+      }
+      double df = fabs(fn - fo);
+      if (df != df) df = INFINITY;
+      mdf = fmax(mdf, df);
+      if (k >= 1) {
+        double r;
+        if (fo != 0.0)
+          r = fabs(fn / fo - 1.0);
+        else
+          r = (fn == 0.0) ? 0.0 : INFINITY;
+        if (r != r) r = INFINITY;
+        rs = fmax(rs, r);
+      }
+      nf = __builtin_fma(-(double)nk, fo, nf);
+      if (it == T - 1) {
+        lnS_out[k] = lnS;
+        S_out[k] = S;
+        cst[k] = lnNp_sh[k] + fn;
+        gk_out[k] = nk > 0 ? 1.0 : 0.0;
+        lnNp_out[k] = lnNp_sh[k];
+      }
+    }
+    // workgroup scalars: waves in order
+    gsq = wave_sum(gsq);
+    minS = wave_min(minS);
+    mdf = wave_max(mdf);
+    rs = wave_max(rs);
+    nf = wave_sum(nf);
+    fl = wave_or(fl);
+    if (lane == 0) {
+      wred[wave][0] = gsq;
+      wred[wave][1] = minS;
+      wred[wave][2] = mdf;
+      wred[wave][3] = rs;
+      wred[wave][4] = nf;
+      wred[wave][5] = (double)fl;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) v[q] = wred[0][q];
+      unsigned f2 = (unsigned)v[5];
+      for (int wv = 1; wv < kSmajWaves; ++wv) {
+        v[0] += wred[wv][0];
+        v[1] = fmin(v[1], wred[wv][1]);
+        v[2] = fmax(v[2], wred[wv][2]);
+        v[3] = fmax(v[3], wred[wv][3]);
+        v[4] += wred[wv][4];
+        f2 |= (unsigned)wred[wv][5];
+      }
+      double* o = ws + (int64_t)b * kBatchVals;
+      o[2] = v[0];
+      o[3] = v[1];
+      o[4] = v[2];
+      o[5] = v[3];
+      o[6] = v[4];
+      o[7] = (double)f2;
+    }
+    grid.sync();
+  }
+  // ---- the scalars of every step: step s on workgroup s mod G, value q on
+  // wave q mod 4, lane l adding workgroups l, l + 64, ... then a butterfly ----
+  __shared__ double sv[kBatchVals];
+  for (int st = b; st < T; st += G) {
+    const double* ws = wsc + (int64_t)st * G * kBatchVals;
+    for (int q = wave; q < kBatchVals - 1; q += kSmajWaves) {
+      // q: 0 obj (sum), 1 sweep flags (or), 2 gsq (sum), 3 minS (min),
+      // 4 mdf (max), 5 rs (max), 6 nf (sum); the state flags (slot 7) go
+      // with q = 1
+      double v = (q == 3) ? INFINITY : 0.0;
+      unsigned fo = 0u;
+      for (int w = lane; w < G; w += 64) {
+        const double x = ws[(int64_t)w * kBatchVals + q];
+        if (q == 1)
+          fo |= (unsigned)x | (unsigned)ws[(int64_t)w * kBatchVals + 7];
+        else if (q == 3)
+          v = fmin(v, x);
+        else if (q == 4 || q == 5)
+          v = fmax(v, x);
+        else
+          v += x;
+      }
+      if (q == 1)
+        v = (double)wave_or(fo);
+      else if (q == 3)
+        v = wave_min(v);
+      else if (q == 4 || q == 5)
+        v = wave_max(v);
+      else
+        v = wave_sum(v);
+      if (lane == 0) sv[q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      SweepScalars sc;
+      sc.max_df = sv[4];
+      sc.rel_step = sv[5];
+      sc.objective = sv[0] + sv[6];
+      sc.grad_norm = sqrt(sv[2]);
+      sc.min_S = sv[3];
+      sc.flags = (unsigned)sv[1];
+      sc.pad = 0u;
+      scal[st] = sc;
+    }
+    __syncthreads();
+  }
+}
+
+bool smaj_batch_supported(int K) { return sweep_smaj_supported(K); }
+
+int64_t smaj_batch_scratch(int num_cus, int max_steps) {
+  return (int64_t)max_steps * sweep_max_grid(num_cus) * kBatchVals;
+}
+
+template <int J>
+static hipError_t launch_batch_t(hipStream_t s, const double* ut, int K, int64_t P,
+                                 const double* h, const int64_t* Nk, const double* f_in, int T,
+                                 double* f_hist, SweepScalars* scal, double* logD, double* lnS,
+                                 double* S, double* cst, double* gk, double* lnNp, double* part,
+                                 int part_cap, double* wsc, int num_cus) {
+  auto kern = smaj_batch_kernel<J>;
+  static const int per_cu = [&] {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kSmajWaves * 64, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 0;
+    return nb;
+  }();
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  // co-resident grid (at most the occupancy limit), at least one wave's
+  // sample pair per wave, within the partials' and the scalars' capacity
+  int64_t g = (int64_t)num_cus * per_cu;
+  const int64_t need = (P + kSmajWaves * kSmajS - 1) / (kSmajWaves * kSmajS);
+  if (g > need) g = need;
+  if (g > part_cap) g = part_cap;
+  if (g > sweep_max_grid(num_cus)) g = sweep_max_grid(num_cus);
+  if (g < 1) g = 1;
+  int G = (int)g;
+  // lanes per state in the per-state sums: a power of two up to 64, as many
+  // as the grid's threads allow for K states
+  int TL = 1;
+  while (TL < 64 && (int64_t)2 * TL * K <= (int64_t)G * kSmajWaves * 64) TL *= 2;
+  void* args[] = {&ut, &K, &P, &h, &Nk, &f_in, &T, &TL, &f_hist, &scal, &logD, &lnS, &S,
+                  &cst, &gk, &lnNp, &part, &wsc};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)G),
+                                    dim3(kSmajWaves * 64), args, 0, s);
+}
+
+hipError_t launch_smaj_batch(hipStream_t s, const double* ut, int K, int64_t P, const double* h,
+                             const int64_t* Nk, const double* f_in, int T, double* f_hist,
+                             SweepScalars* scal, double* logD, double* lnS, double* S,
+                             double* cst, double* gk, double* lnNp, double* part, int part_cap,
+                             double* wsc, int wsc_steps, int num_cus) {
+  if (!smaj_batch_supported(K) || T < 1 || T > wsc_steps || P < 1 || !ut || !Nk || !f_in ||
+      !f_hist || !scal ||
+      !logD || !lnS || !S || !cst || !gk || !lnNp || !part || part_cap < 1 || !wsc)
+    return hipErrorInvalidValue;
+  const int J = smaj_slots(K);
+#define BUMBAR_BATCH(jj)                                                                      \
+  if (J == jj)                                                                                \
+    return launch_batch_t<jj>(s, ut, K, P, h, Nk, f_in, T, f_hist, scal, logD, lnS, S, cst, gk, \
+                              lnNp, part, part_cap, wsc, num_cus);
+  BUMBAR_BATCH(5)
+  BUMBAR_BATCH(6)
+  BUMBAR_BATCH(8)
+  BUMBAR_BATCH(10)
+  BUMBAR_BATCH(12)
+  BUMBAR_BATCH(14)
+  BUMBAR_BATCH(16)
+#undef BUMBAR_BATCH
   return hipErrorInvalidValue;
 }
 
