@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbumbar.so")
 SOURCES = ["sweep.hip", "sweep_small.hip", "sweep_wide.hip", "sweep_smaj.hip", "sweep32.hip", "sweep_otf.hip", "hessian.hip", "linalg.hip", "covariance.hip", "binning.hip",
-           "model.hip", "pmf.hip", "solver.cpp", "algo.cpp", "server.cpp",
+           "model.hip", "pmf.hip", "radix.hip", "solver.cpp", "algo.cpp", "server.cpp",
            "sweep_static.cpp", "plan.cpp"]
 
 FLAGS = [

@@ -16,8 +16,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "bumbar_impl.h"
 #include "solver_internal.h"
@@ -147,28 +145,14 @@ __global__ void iota_kernel(uint32_t* p, int64_t N) {
 }
 
 size_t sort_temp_bytes(int64_t N) {
-  size_t a = 0, b = 0, k64 = 0, k32 = 0;
-  (void)rocprim::radix_sort_pairs((void*)nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
-  (void)rocprim::radix_sort_pairs((void*)nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
-  (void)rocprim::radix_sort_keys((void*)nullptr, k64, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                 (size_t)N);
-  (void)rocprim::radix_sort_keys((void*)nullptr, k32, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                 (size_t)N);
-  size_t c = 0;
-  (void)rocprim::inclusive_scan((void*)nullptr, c, (const int32_t*)nullptr, (int32_t*)nullptr,
-                          (size_t)N, rocprim::plus<int32_t>());
-  return std::max(std::max(std::max(a, b), std::max(k64, k32)), c) + 1024;
+  return std::max(radix_temp_bytes(N), scan_temp_bytes(N)) + 1024;
 }
 
 hipError_t launch_sort_1d(hipStream_t s, const uint32_t* q, int64_t N, uint32_t* iota,
                           uint32_t* q_sorted, uint32_t* perm, void* tmp, size_t tmp_bytes) {
   hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, iota,
                      N);
-  size_t bytes = tmp_bytes;
-  return rocprim::radix_sort_pairs(tmp, bytes, q, q_sorted, (const uint32_t*)iota, perm, (size_t)N,
-                                   0, 32, s);
+  return radix_sort_u32(s, q, q_sorted, iota, perm, N, 32, tmp, tmp_bytes);
 }
 
 // ---- distinct counting -----------------------------------------------------
@@ -721,9 +705,7 @@ hipError_t launch_sort_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t*
                           uint64_t* q2_sorted, void* tmp, size_t tmp_bytes) {
   hipLaunchKernelGGL(pair_keys_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q,
                      N, keys);
-  size_t bytes = tmp_bytes;
-  return rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, q2_sorted, (size_t)N, 0, 64,
-                                  s);
+  return radix_sort_u64(s, keys, q2_sorted, nullptr, nullptr, N, 64, tmp, tmp_bytes);
 }
 
 // counts[0] = the distinct points of the sorted pairs, g(1).
@@ -756,7 +738,6 @@ hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t
   }
   const unsigned bits = key_bits(2, m);
   const int nb = red_blocks(N);
-  size_t bytes = tmp_bytes;
   hipError_t e;
   if (bits <= 32) {
     // ids of this width fit in 32 bits: half the bytes through the sort
@@ -764,15 +745,14 @@ hipError_t launch_count_2d(hipStream_t s, const uint32_t* q, int64_t N, uint64_t
     uint32_t* s32 = reinterpret_cast<uint32_t*>(keys_sorted);
     hipLaunchKernelGGL(cells32_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q,
                        N, m, k32);
-    e = rocprim::radix_sort_keys(tmp, bytes, (const uint32_t*)k32, s32, (size_t)N, 0, bits, s);
+    e = radix_sort_u32(s, k32, s32, nullptr, nullptr, N, (int)bits, tmp, tmp_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(count_runs_keys_kernel<uint32_t>, dim3(nb), dim3(kBT), 0, s,
                        (const uint32_t*)s32, N, counts);
   } else {
     hipLaunchKernelGGL(cells_kernel, dim3((unsigned)((N + kBT - 1) / kBT)), dim3(kBT), 0, s, q, N,
                        2, m, keys);
-    e = rocprim::radix_sort_keys(tmp, bytes, (const uint64_t*)keys, keys_sorted, (size_t)N, 0,
-                                 bits, s);
+    e = radix_sort_u64(s, keys, keys_sorted, nullptr, nullptr, N, (int)bits, tmp, tmp_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(count_runs_keys_kernel<uint64_t>, dim3(nb), dim3(kBT), 0, s,
                        (const uint64_t*)keys_sorted, N, counts);
@@ -832,17 +812,13 @@ hipError_t launch_histogram(hipStream_t s, const uint32_t* q, int64_t N, int d, 
   } else {
     hipLaunchKernelGGL(cells_kernel, dim3(nb), dim3(kBT), 0, s, q, N, 2, m, keys);
     hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(kBT), 0, s, iota, N);
-    size_t bytes = tmp_bytes;
-    e = rocprim::radix_sort_pairs(tmp, bytes, (const uint64_t*)keys, keys_sorted,
-                                  (const uint32_t*)iota, perm, (size_t)N, 0, key_bits(2, m), s);
+    e = radix_sort_u64(s, keys, keys_sorted, iota, perm, N, (int)key_bits(2, m), tmp, tmp_bytes);
     if (e != hipSuccess) return e;
   }
   // run flags -> inclusive scan -> bin index per sorted position
   int32_t* flags = reinterpret_cast<int32_t*>(keys);  // keys no longer needed
   hipLaunchKernelGGL(run_flags_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, flags);
-  size_t bytes = tmp_bytes;
-  e = rocprim::inclusive_scan(tmp, bytes, (const int32_t*)flags, bin_of_pos, (size_t)N,
-                              rocprim::plus<int32_t>(), s);
+  e = scan_inclusive_i32(s, flags, bin_of_pos, N, tmp, tmp_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(run_starts_kernel, dim3(nb), dim3(kBT), 0, s, keys_sorted, N, bin_of_pos,
                      start, cells, counts);

@@ -115,6 +115,22 @@ hipError_t launch_sweep_finalize(hipStream_t s, int mode, int K, int nparts, con
 // scal[i]; ln D (P), ln S and S (K) of the last step; after the batch cst,
 // gk and lnNp as launch_prepare_consts would leave them for the last f.
 // small_batch_nc(K, P) is 0 where the batch kernel does not apply.
+// Stable LSD radix sort (8-bit digits) of N < 2^32 keys over their low
+// `bits` bits, with an optional 32-bit value per key (both value pointers
+// set, or neither), and an inclusive scan of int32 (radix.hip). tmp:
+// radix_temp_bytes(N) / scan_temp_bytes(N) bytes of device scratch. Inputs
+// are not modified; outputs must not alias them.
+size_t radix_temp_bytes(int64_t N);
+size_t scan_temp_bytes(int64_t N);
+hipError_t radix_sort_u32(hipStream_t s, const uint32_t* keys_in, uint32_t* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, int64_t N, int bits,
+                          void* tmp, size_t tmp_bytes);
+hipError_t radix_sort_u64(hipStream_t s, const uint64_t* keys_in, uint64_t* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, int64_t N, int bits,
+                          void* tmp, size_t tmp_bytes);
+hipError_t scan_inclusive_i32(hipStream_t s, const int32_t* in, int32_t* out, int64_t N,
+                              void* tmp, size_t tmp_bytes);
+
 int small_batch_nc(int K, int64_t P);
 // The same batch on a level materialised in the sample-major layout (FP64,
 // 256 < K <= 1024) as one cooperative launch (sweep_smaj.hip): grid

@@ -17,7 +17,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "bumbar_impl.h"
 #include "solver_internal.h"
@@ -90,12 +89,7 @@ static unsigned pmf_key_bits(uint32_t nbins) {
   return b;
 }
 
-static size_t pmf_sort_bytes(int64_t N) {
-  size_t t = 0;
-  (void)rocprim::radix_sort_pairs((void*)nullptr, t, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                  (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N);
-  return t;
-}
+static size_t pmf_sort_bytes(int64_t N) { return radix_temp_bytes(N); }
 
 static size_t pmf_align(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -148,9 +142,7 @@ int bumbar_pmf(bumbar_ctx* ctx, const double* xi, int64_t N, int d, const double
                      nb, key, val);
   hipLaunchKernelGGL(pmf_fill_kernel, dim3((unsigned)((total + kPT - 1) / kPT)), dim3(kPT), 0, s,
                      F, total);
-  hipError_t e = rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t*)key, ks,
-                                           (const uint32_t*)val, vs, (size_t)N, 0,
-                                           pmf_key_bits(nb), s);
+  hipError_t e = radix_sort_u32(s, key, ks, val, vs, N, (int)pmf_key_bits(nb), tmp, tmp_bytes);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(pmf_segments_kernel, dim3(blocks), dim3(kPT), 0, s, ks, vs, N, nb, p, seg);
     hipLaunchKernelGGL(pmf_runs_kernel, dim3(blocks), dim3(kPT), 0, s, ks, N, nb, seg, F);

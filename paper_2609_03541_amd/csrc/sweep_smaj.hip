@@ -615,13 +615,13 @@ __global__ void __launch_bounds__(kSmajWaves * 64)
         v[4] += wred[wv][4];
         f2 |= (unsigned)wred[wv][5];
       }
-      double* o = ws + (int64_t)b * kBatchVals;
-      o[2] = v[0];
-      o[3] = v[1];
-      o[4] = v[2];
-      o[5] = v[3];
-      o[6] = v[4];
-      o[7] = (double)f2;
+      double* slot = ws + (int64_t)b * kBatchVals;
+      slot[2] = v[0];
+      slot[3] = v[1];
+      slot[4] = v[2];
+      slot[5] = v[3];
+      slot[6] = v[4];
+      slot[7] = (double)f2;
     }
     grid.sync();
   }
