@@ -323,12 +323,14 @@ hipError_t launch_widen_f32(hipStream_t s, const float* src, int64_t n, double* 
 
 }  // namespace bumbar
 
+constexpr size_t kPinnedBytes = 16384;  // a context's pinned readback buffer
+
 struct bumbar_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 256;
   std::string err;
-  void* pinned = nullptr;  // small pinned host buffer for scalar readbacks
+  void* pinned = nullptr;  // pinned host buffer of kPinnedBytes for small readbacks
   // optional timing of the unbinned sweep kernel (HIP events on ctx->stream)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -125,6 +125,16 @@ int read_scalars(bumbar_ctx* ctx, const SweepScalars* dev, SweepScalars* host) {
 }
 
 int read_bytes(bumbar_ctx* ctx, const void* dev, void* host, size_t bytes) {
+  // small readbacks go through the context's pinned buffer: an asynchronous
+  // DMA, with no staging through the runtime's shared pageable-copy buffers
+  // (which serialise the readbacks of concurrent solves)
+  if (bytes <= kPinnedBytes) {
+    hipError_t e = hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = ctx_wait(ctx, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "readback");
+    std::memcpy(host, ctx->pinned, bytes);
+    return BUMBAR_OK;
+  }
   // a copy into pageable memory blocks the host until the stream reaches it:
   // a fiber first lets the stream drain
   hipError_t e = ctx->yield ? ctx_wait(ctx, ctx->stream) : hipSuccess;
@@ -513,7 +523,7 @@ int bumbar_create(bumbar_ctx** out, int device, void* hip_stream) {
     e = hipGetDeviceProperties(&p, device);
     if (e == hipSuccess) c->num_cus = p.multiProcessorCount;
   }
-  if (e == hipSuccess) e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault);
   if (e != hipSuccess || static_scratch_init(c) != BUMBAR_OK) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
