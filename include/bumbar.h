@@ -146,6 +146,11 @@ typedef struct {
                           default, or BUMBAR_F32): FP32 coordinates are widened (exactly)
                           into N d doubles of the workspace, which the queries then
                           include; a workspace sized for FP64 is too small for FP32 xi  */
+  const char* trace_path; /* host string or NULL: append the solve's trace to this text
+                          file (one line per phase-2 check of Algorithm 1: nominal n, bins
+                          at n and n inc, the relative steps of Eq. (2), refine and stop;
+                          then a summary line of stage lengths, finisher steps and stage
+                          times); EINVAL if it cannot be written                      */
   int grid_batches;    /* 1: a batch of binned SCI steps on a level held in the
                           sample-major layout (256 < K <= 1024) runs as one cooperative
                           launch, with grid barriers between each step's sweep and its

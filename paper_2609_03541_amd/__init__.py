@@ -120,6 +120,8 @@ def default_options(**kw):
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "trace_path" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
 

@@ -54,7 +54,8 @@ class Options(C.Structure):
                 ("replay_phase1", C.c_int), ("replay_refine", C.POINTER(C.c_int)),
                 ("n_replay", C.c_int), ("profile", C.c_int), ("mixed_tol", C.c_double),
                 ("represent", C.c_int), ("graphs", C.c_int), ("sample_major", C.c_int),
-                ("u_dtype", C.c_int), ("xi_dtype", C.c_int), ("grid_batches", C.c_int)]
+                ("u_dtype", C.c_int), ("xi_dtype", C.c_int), ("trace_path", C.c_char_p),
+                ("grid_batches", C.c_int)]
 
 
 class Stats(C.Structure):

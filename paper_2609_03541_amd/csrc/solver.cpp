@@ -1043,6 +1043,36 @@ int bumbar_query_workspace_model(const bumbar_ctx* ctx, int K, int64_t N, int d,
   return BUMBAR_OK;
 }
 
+// The solve's trace: one line per phase-2 check of Algorithm 1 (nominal n,
+// the bins at n and n inc, the relative steps of Eq. (2), the decision), then
+// a summary line (stage lengths, finisher steps, last step, gradient norm,
+// stage times). Text, appended to path; EINVAL if it cannot be written.
+constexpr int kTraceChecks = 4096;
+static int write_trace(bumbar_ctx* ctx, const char* path, int K, int64_t N, const bumbar_stats& st) {
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return fail(ctx, BUMBAR_EINVAL, "cannot open the trace file %s", path);
+  std::fprintf(fp, "# bumbar trace K=%d N=%lld\n", K, (long long)N);
+  std::fprintf(fp, "# check n P P_next s_n s_next refine stop\n");
+  const int64_t n = std::min<int64_t>(st.n_checks, st.checks ? st.checks_capacity : 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const bumbar_check& c = st.checks[i];
+    std::fprintf(fp, "check %lld %lld %lld %lld %.17g %.17g %d %d\n", (long long)i, (long long)c.n,
+                 (long long)c.P, (long long)c.P_next, c.s_n, c.s_next, c.refine, c.stop);
+  }
+  std::fprintf(fp,
+               "summary phase1_iters=%lld phase2_iters=%lld n_checks=%lld finisher_steps=%lld "
+               "sci_fallbacks=%lld unbinned_sweeps=%lld hessians=%lld mixed_steps=%lld "
+               "final_step=%.17g grad_norm=%.17g time_binning_ms=%.6f time_binned_ms=%.6f "
+               "time_final_ms=%.6f\n",
+               (long long)st.phase1_iters, (long long)st.phase2_iters, (long long)st.n_checks,
+               (long long)st.finisher_steps, (long long)st.sci_fallbacks,
+               (long long)st.unbinned_sweeps, (long long)st.hessians, (long long)st.mixed_steps,
+               st.final_step, st.grad_norm, st.time_binning_ms, st.time_binned_ms,
+               st.time_final_ms);
+  const bool ok = std::fclose(fp) == 0;
+  return ok ? BUMBAR_OK : fail(ctx, BUMBAR_EINVAL, "cannot write the trace file %s", path);
+}
+
 int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t N,
                  const int64_t* N_k, const void* xi_in, int xi_dtype, int d, int model,
                  const double* coef, const double* f_init, const bumbar_options* opt_in,
@@ -1109,6 +1139,27 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   bumbar_stats* st = stats ? stats : &local;
   bumbar_check* chk = st->checks;
   int chk_cap = st->checks_capacity;
+  // a trace file needs the schedule even if the caller keeps none: then the
+  // solve records it in its own buffer, and on every return path the
+  // caller's buffer gets back its place in the statistics, with what fits
+  struct TraceChecks {
+    bumbar_stats* st;
+    bumbar_check* caller;
+    int cap;
+    std::vector<bumbar_check> buf;
+    ~TraceChecks() {
+      if (buf.empty()) return;
+      const int64_t n = std::min<int64_t>(st->n_checks, caller ? cap : 0);
+      if (n > 0) std::memcpy(caller, buf.data(), sizeof(bumbar_check) * (size_t)n);
+      st->checks = caller;
+      st->checks_capacity = cap;
+    }
+  } trace_checks{st, chk, chk_cap, {}};
+  if (opt.trace_path && (!chk || chk_cap < kTraceChecks)) {
+    trace_checks.buf.resize(kTraceChecks);
+    chk = trace_checks.buf.data();
+    chk_cap = kTraceChecks;
+  }
   std::memset(st, 0, sizeof(*st));
   st->checks = chk;
   st->checks_capacity = chk_cap;
@@ -1318,6 +1369,10 @@ int bumbar_solve(bumbar_ctx* ctx, const void* u_kn, int u_dtype, int K, int64_t 
   st->grid_sweeps = cnt.grid;
   if (ctx->profiling) st->sweep_kernel_ms = collect_event_ms(ctx, &st->sweep_kernel_launches);
   ctx->profiling = false;
+  if (opt.trace_path) {
+    rc = write_trace(ctx, opt.trace_path, K, N, *st);
+    if (rc) return rc;
+  }
   if (stage_rc == BUMBAR_ENOTCONV || fin_rc == BUMBAR_ENOTCONV)
     return fail(ctx, BUMBAR_ENOTCONV, "iteration cap reached before convergence");
   return BUMBAR_OK;

@@ -433,3 +433,27 @@ def test_hessian_fp32_input(bm):
     fn, lD, S, _ = bm.sweep(ud, Nk, f)
     H = bm.hessian(ud, Nk, f, lD, S).cpu().numpy()
     assert np.max(np.abs(H - H_ref)) < 1e-12 * np.abs(H_ref).max()
+
+
+def test_trace_file_records_the_schedule(bm, tmp_path):
+    # trace_path: one line per phase-2 check (the same values as the checks
+    # in the statistics) and a summary line; appended on every solve
+    p = synth.double_well(K=20, Nk=2000, seed=5)
+    path = str(tmp_path / "trace.txt")
+    u = dev(p["u"])
+    kw = dict(xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-10)
+    f, info = bm.solve(u, p["Nk"], trace_path=path, **kw)
+    assert info["status"] == 0 and info["n_checks"] >= 1
+    lines = open(path).read().splitlines()
+    checks = [l.split() for l in lines if l.startswith("check ")]
+    assert len(checks) == info["n_checks"] == len(info["checks"])
+    for row, c in zip(checks, info["checks"]):
+        assert (int(row[2]), int(row[3]), int(row[4])) == (c["n"], c["P"], c["P_next"])
+        assert float(row[5]) == c["s_n"] and float(row[6]) == c["s_next"]
+        assert (int(row[7]), int(row[8])) == (c["refine"], c["stop"])
+    summ = [l for l in lines if l.startswith("summary ")]
+    assert len(summ) == 1 and f"phase1_iters={info['phase1_iters']}" in summ[0]
+    # a second solve appends; a solve without a trace leaves the file alone
+    bm.solve(u, p["Nk"], trace_path=path, checks_capacity=1, **kw)
+    bm.solve(u, p["Nk"], **kw)
+    assert sum(1 for l in open(path) if l.startswith("summary ")) == 2
