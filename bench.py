@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--skip-sequential", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (reference kernel for HBM counters)")
-    ap.add_argument("--configs", default="c2,c1,c4,c3",
+    ap.add_argument("--configs", default="c0,c2,c1,c4,c3",
                     help="default workload: the configurations to run (c2 always runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -351,6 +351,10 @@ def run_all(args, bm, synth, stream):
     log(f"c2 done ({time.time() - t_all:.0f} s)")
 
     want = set(args.configs.split(","))
+    # ---- c0: K = 8 harmonic wells, N = 8000, FP64: latency-bound ----
+    if "c0" in want:
+        cfg["c0_f64"] = _c0(bm, synth, ctx, args.tol)
+        log(f"c0 done ({time.time() - t_all:.0f} s)")
     # ---- c1: K = 100 double-well umbrella windows, N = 1e6, FP64 ----
     if "c1" in want:
         cfg["c1_f64"] = _c1(bm, synth, side, ctx)
@@ -399,6 +403,38 @@ def _covariance_ms(bm, u, Nk, f, ctx, reps=3):
         bm.covariance(u, Nk, f, ctx=ctx)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def _c0(bm, synth, ctx, tol, reps=25):
+    """K = 8 harmonic wells (N_k = 1000): time-to-solve in microseconds (median of
+    the timed solves), BU-MBAR and plain Newton, errors against the oracle's
+    golden f and the analytic free energies."""
+    import torch
+    p = synth.harmonic_1d(K=8, Nk=1000, seed=0)
+    u = torch.tensor(p["u"], device="cuda")
+    Nk = torch.tensor(p["Nk"], device="cuda")
+    xi = torch.tensor(p["xi"], device="cuda")
+    coef = torch.tensor(p["coef"], device="cuda")
+    gold = _golden("c0_harmonic_K8_N8e3")
+    out = {}
+    for name, kw in (("bu_mbar", dict(xi=xi, model=bm.MODEL_HARMONIC, coef=coef)),
+                     ("plain_newton", dict(binning=False))):
+        times = []
+        for i in range(reps + 5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f, info = bm.solve(u, Nk, tol=tol, ctx=ctx, **kw)
+            torch.cuda.synchronize()
+            if i >= 5:
+                times.append(time.perf_counter() - t0)
+        fa = f.cpu().numpy()
+        stages = _stages(bm.solve(u, Nk, tol=tol, ctx=ctx, profile=1, **kw)[1])
+        out[name] = dict(time_to_solve_us=1e6 * float(np.median(times)), status=info["status"],
+                         **stages,
+                         error_vs_oracle_kT=_err(f, gold),
+                         error_vs_analytic_kT=(float(np.max(np.abs(fa - np.asarray(gold["analytic"]))))
+                                               if gold else None))
+    return out
 
 
 def _c1(bm, synth, args, ctx):

@@ -14,7 +14,7 @@ with no input from the GPU library:
   3. certification: the full Newton step below 1e-13 kT and the fixed-point
      residual max |SCI(f) - f| below 1e-12 kT, both recorded.
 
-Usage: python tests/golden/make_golden.py {c1,c2,tladder,c4r,c3sub,fig3r,fig3} ...
+Usage: python tests/golden/make_golden.py {c0,c1,c2,tladder,c4r,c3sub,fig3r,fig3} ...
 Inputs are the seeded generators of synth (the same recipes the GPU tests and
 the benchmark use). Output: tests/golden/<name>.json.
 """
@@ -153,6 +153,15 @@ def run_c4r():
     write("c4r_mullerbrown_K1600_N8e5", "synth.muller_brown_grid(G=40, Nk=500, seed=4)", f, cert)
 
 
+def run_c0():
+    p = synth.harmonic_1d(K=8, Nk=1000, seed=0)
+    f, cert = solve_golden(p["u"], p["Nk"], p["xi"], p["model_type"], p["coef"])
+    # the analytic free energies of the wells (beta = 1): f_k - f_0 = ln(kappa_k / kappa_0) / 2
+    analytic = 0.5 * np.log(p["kappa"] / p["kappa"][0])
+    write("c0_harmonic_K8_N8e3", "synth.harmonic_1d(K=8, Nk=1000, seed=0)", f, cert,
+          extra=dict(analytic=[float(v) for v in analytic]))
+
+
 def run_c1():
     # double-well umbrella sampling, K = 100 windows, N_k = 1e4 (N = 1e6), seed 1
     p = synth.double_well(K=100, Nk=10000, seed=1)
@@ -231,7 +240,7 @@ def run_fig3(scale, name, max_elems):
 
 if __name__ == "__main__":
     oracle.build()
-    jobs = dict(c1=run_c1, c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub,
+    jobs = dict(c0=run_c0, c1=run_c1, c2=run_c2, tladder=run_tladder, c4r=run_c4r, c3sub=run_c3sub,
                 fig3r=lambda: run_fig3(0.01, "fig3_replicas_reduced", 1e12),
                 fig3=lambda: run_fig3(1.0, "fig3_replicas_full_small", 3e7))
     for name in sys.argv[1:] or list(jobs):

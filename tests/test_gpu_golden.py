@@ -129,3 +129,19 @@ def test_stream_subset_served_against_oracle(bm):
         worst[name] = e
         say(f"c3 subset {name}: max error {e:.3e} kT")
         assert e < tol_ok
+
+
+def test_c0_harmonic_wells(bm):
+    # K = 8 harmonic wells, N = 8000: BU-MBAR and plain Newton against the
+    # oracle's certified f; the analytic free energies within the sampling
+    # error of N_k = 1000 draws per well
+    import torch
+    g = golden("c0_harmonic_K8_N8e3")
+    p = synth.harmonic_1d(K=8, Nk=1000, seed=0)
+    u = torch.tensor(p["u"], device="cuda")
+    f, info = bm.solve(u, p["Nk"], xi=p["xi"], model=p["model_type"], coef=p["coef"], tol=1e-11)
+    f0, info0 = bm.solve(u, p["Nk"], binning=False, tol=1e-11)
+    say("c0", err(f, g), err(f0, g))
+    assert info["status"] == 0 and info0["status"] == 0
+    assert err(f, g) < 1e-9 and err(f0, g) < 1e-9
+    assert np.max(np.abs(f.cpu().numpy() - np.asarray(g["analytic"]))) < 0.2
