@@ -421,10 +421,85 @@ __global__ void __launch_bounds__(64) ws_walk_kernel(WidthSearch1D* w) {
   ws_store(w, nm, sM);
 }
 
+// The whole bisection in one workgroup, for N <= kWsSmallN: thread t keeps
+// the kWsL sorted coordinates from t kWsL on in registers (and the one
+// before them), and each probe is a count of run starts over them plus a
+// workgroup sum. g(1) first; if g(1) < n the width is 1, else the interval
+// [1, 2^32] is halved until hi - lo = 1, keeping g(lo) >= n, as the
+// multi-pass search does. Ends the search (done = 1) in w.
+constexpr int kWsT = 1024;
+constexpr int kWsL = 16;
+constexpr int64_t kWsSmallN = (int64_t)kWsT * kWsL;
+
+__global__ void __launch_bounds__(kWsT)
+    ws_small_kernel(const uint32_t* __restrict__ qs, int64_t N, int64_t n, WidthSearch1D* w) {
+  __shared__ unsigned part[kWsT / 64];
+  __shared__ unsigned total;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int64_t b = (int64_t)t * kWsL;
+  uint32_t q[kWsL];
+#pragma unroll
+  for (int j = 0; j < kWsL; ++j) q[j] = b + j < N ? qs[b + j] : 0u;
+  const uint32_t before = (b > 0 && b < N) ? qs[b - 1] : 0u;
+  auto count = [&](uint64_t m) -> int64_t {
+    const uint64_t mg = magic_of(m);
+    uint32_t dp = div_by_magic(before, m, mg);
+    unsigned c = 0u;
+#pragma unroll
+    for (int j = 0; j < kWsL; ++j) {
+      if (b + j < N) {
+        const uint32_t d = div_by_magic(q[j], m, mg);
+        c += (b + j == 0) ? 1u : (d != dp ? 1u : 0u);
+        dp = d;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) part[wave] = c;
+    __syncthreads();
+    if (t == 0) {
+      unsigned a = 0u;
+      for (int v = 0; v < kWsT / 64; ++v) a += part[v];
+      total = a;
+    }
+    __syncthreads();
+    return (int64_t)total;
+  };
+  uint64_t lo = 1, hi = 4294967296ull;
+  int64_t glo = count(1);
+  if (glo >= n) {
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      const int64_t gm = count(mid);
+      if (gm >= n) {
+        lo = mid;
+        glo = gm;
+      } else {
+        hi = mid;
+      }
+    }
+  }
+  if (t == 0) {
+    w->lo = lo;
+    w->hi = hi;
+    w->glo = glo;
+    w->n = n;
+    w->levels = 0;
+    w->M = 0;
+    w->done = 1;
+    w->first = 0;
+  }
+}
+
 hipError_t launch_width_search_1d(hipStream_t s, const uint32_t* q_sorted, int64_t N,
                                   int64_t n, int levels, int passes, bool init,
                                   WidthSearch1D* w) {
   if (levels < 1 || levels > 6 || passes < 1) return hipErrorInvalidValue;
+  if (init && N <= kWsSmallN) {
+    hipLaunchKernelGGL(ws_small_kernel, dim3(1), dim3(kWsT), 0, s, q_sorted, N, n, w);
+    return hipGetLastError();
+  }
   int MP = 4;  // probe slots per wave: a power of two, 64 / MP streams of >= 4 coordinates
   while (MP < (1 << levels)) MP *= 2;
   const int64_t nchunks = (N + kRunChunk - 1) / kRunChunk;

@@ -19,6 +19,12 @@
 //      sort, is stable.
 // Scan: three launches (per-block sums, a one-workgroup scan of the block
 // sums, per-block scans plus their offsets); integer, so exact.
+//
+// Small inputs (at most kSmallTiles tiles, or kSmallScan scan chunks) run the
+// same steps in one workgroup and one launch: every pass keeps all tile
+// histograms in LDS, and the workgroup barrier between passes orders each
+// pass's scattered stores before the next pass reads them. A sort of 8000
+// keys is then one launch instead of five per pass.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -36,9 +42,12 @@ constexpr int kST = 256;             // threads of a scan workgroup
 constexpr int kSItems = 8;           // items per scan thread
 constexpr int kSChunk = kST * kSItems;
 
+constexpr int kSmallTiles = 16;      // one-workgroup sorts: up to 16 tiles (65536 keys)
+constexpr int kSmallScan = 4;        // one-workgroup scans: up to 4 chunks (8192 items)
+
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-int64_t radix_tiles(int64_t N) { return (N + kTile - 1) / kTile; }
+__host__ __device__ int64_t radix_tiles(int64_t N) { return (N + kTile - 1) / kTile; }
 int64_t scan_blocks(int64_t n) { return (n + kSChunk - 1) / kSChunk; }
 
 template <typename K>
@@ -109,6 +118,96 @@ __global__ void __launch_bounds__(kRT)
     }
     running[t] += add;
     __syncthreads();
+  }
+}
+
+// All passes of a sort of at most kSmallTiles tiles in one workgroup: the
+// digit histograms of every tile in LDS, their digit-major exclusive scan,
+// and the scatter of each tile in turn, exactly as the three kernels above
+// compute them. Pass p reads what pass p - 1 wrote; the barrier at the end of
+// a pass orders those stores (all within this workgroup) before the loads.
+template <typename K, bool VALS>
+__global__ void __launch_bounds__(kRT)
+    radix_small_kernel(const K* keys_in, const uint32_t* vals_in, K* keys_out,
+                       uint32_t* vals_out, K* kalt, uint32_t* valt, int64_t N, int passes) {
+  __shared__ uint32_t h[kSmallTiles][256];
+  __shared__ uint32_t dsum[256];
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t cnt[kRT / 64][256];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int nb = (int)radix_tiles(N);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const K* ks = keys_in;
+  const uint32_t* vs = vals_in;
+  for (int p = 0; p < passes; ++p) {
+    // the last pass writes keys_out
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    K* kd = to_out ? keys_out : kalt;
+    uint32_t* vd = to_out ? vals_out : valt;
+    const int shift = 8 * p;
+    for (int b = 0; b < nb; ++b) h[b][t] = 0u;
+    __syncthreads();
+    for (int64_t i = t; i < N; i += kRT) atomicAdd(&h[i / kTile][digit_of(ks[i], shift)], 1u);
+    __syncthreads();
+    // first output position of digit t in tile b: the keys of smaller digits,
+    // then those of digit t in earlier tiles
+    uint32_t tot = 0u;
+    for (int b = 0; b < nb; ++b) tot += h[b][t];
+    dsum[t] = tot;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t a = t >= off ? dsum[t - off] : 0u;
+      __syncthreads();
+      dsum[t] += a;
+      __syncthreads();
+    }
+    uint32_t run = dsum[t] - tot;
+    for (int b = 0; b < nb; ++b) {
+      const uint32_t c = h[b][t];
+      h[b][t] = run;
+      run += c;
+    }
+    for (int b = 0; b < nb; ++b) {
+      running[t] = h[b][t];
+#pragma unroll
+      for (int w = 0; w < kRT / 64; ++w) cnt[w][t] = 0u;
+      __syncthreads();
+      const int64_t base = (int64_t)b * kTile;
+      for (int j = 0; j < kRounds; ++j) {
+        const int64_t i = base + (int64_t)j * kRT + t;
+        const bool valid = i < N;
+        const K key = valid ? ks[i] : (K)0;
+        const unsigned d = digit_of(key, shift);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+          const uint64_t bb = __ballot(valid && ((d >> bit) & 1u));
+          peers &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        const unsigned rank = (unsigned)__popcll(peers & below);
+        if (valid && rank == 0u) cnt[wave][d] = (unsigned)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+          uint32_t pos = running[d] + rank;
+          for (int w = 0; w < wave; ++w) pos += cnt[w][d];
+          kd[pos] = key;
+          if constexpr (VALS) vd[pos] = vs[i];
+        }
+        __syncthreads();
+        uint32_t add = 0u;
+#pragma unroll
+        for (int w = 0; w < kRT / 64; ++w) {
+          add += cnt[w][t];
+          cnt[w][t] = 0u;
+        }
+        running[t] += add;
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    ks = kd;
+    vs = vd;
   }
 }
 
@@ -189,10 +288,43 @@ __global__ void __launch_bounds__(kST)
   }
 }
 
+// One workgroup over at most kSmallScan chunks, each scanned as by
+// scan_apply_kernel with the running total of the chunks before it. In place
+// as well: a thread reads its items of a chunk before the chunk's workgroup
+// scan and writes them after it.
+template <typename T, bool INCLUSIVE>
+__global__ void __launch_bounds__(kST) scan_small_kernel(const T* in, int64_t n, T* out) {
+  __shared__ T sh[kST];
+  T carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kSChunk) {
+    const int64_t base = c0 + (int64_t)threadIdx.x * kSItems;
+    T x[kSItems];
+    T v = 0;
+#pragma unroll
+    for (int q = 0; q < kSItems; ++q) {
+      x[q] = base + q < n ? in[base + q] : (T)0;
+      v += x[q];
+    }
+    T tot;
+    T run = block_exclusive_scan<T>(v, sh, &tot) + carry;
+#pragma unroll
+    for (int q = 0; q < kSItems; ++q) {
+      if (INCLUSIVE) run += x[q];
+      if (base + q < n) out[base + q] = run;
+      if (!INCLUSIVE) run += x[q];
+    }
+    carry += tot;
+  }
+}
+
 template <typename T, bool INCLUSIVE>
 hipError_t scan_t(hipStream_t s, const T* in, T* out, int64_t n, T* sums) {
   if (n <= 0) return hipSuccess;
   const int64_t nbk = scan_blocks(n);
+  if (nbk <= kSmallScan) {
+    hipLaunchKernelGGL((scan_small_kernel<T, INCLUSIVE>), dim3(1), dim3(kST), 0, s, in, n, out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(scan_sums_kernel<T>, dim3((unsigned)nbk), dim3(kST), 0, s, in, n, sums);
   hipLaunchKernelGGL(scan_top_kernel<T>, dim3(1), dim3(kST), 0, s, sums, nbk);
   hipLaunchKernelGGL((scan_apply_kernel<T, INCLUSIVE>), dim3((unsigned)nbk), dim3(kST), 0, s, in,
@@ -225,6 +357,16 @@ hipError_t radix_sort_t(hipStream_t s, const K* keys_in, K* keys_out, const uint
       e = hipMemcpyAsync(vals_out, vals_in, sizeof(uint32_t) * (size_t)N,
                          hipMemcpyDeviceToDevice, s);
     return e;
+  }
+  if (nb <= kSmallTiles) {
+    if (vals)
+      hipLaunchKernelGGL((radix_small_kernel<K, true>), dim3(1), dim3(kRT), 0, s, keys_in, vals_in,
+                         keys_out, vals_out, kalt, valt, N, passes);
+    else
+      hipLaunchKernelGGL((radix_small_kernel<K, false>), dim3(1), dim3(kRT), 0, s, keys_in,
+                         (const uint32_t*)nullptr, keys_out, (uint32_t*)nullptr, kalt,
+                         (uint32_t*)nullptr, N, passes);
+    return hipGetLastError();
   }
   // the last pass writes keys_out: an odd count starts there
   const K* ks = keys_in;

@@ -181,6 +181,46 @@ def test_binning_bit_exact(bm, d):
         assert np.array_equal(sb.cpu().numpy(), sb_ref)
 
 
+@pytest.mark.parametrize("N", [1, 2, 7, 300, 4097, 8000, 16383, 16384, 16385, 65536, 65537])
+def test_binning_small_1d(bm, N):
+    # Up to 16384 samples the width search runs in one workgroup, and up to
+    # 65536 keys the radix sort does (both one launch); 16385 and 65537 take
+    # the multi-pass forms. Targets above N make g(1) < n (width 1).
+    g = np.random.default_rng(1000 + N)
+    xi = g.normal(0, 1, size=(N, 1))
+    if N > 10:
+        xi[: N // 10] = xi[N // 10: 2 * (N // 10)]  # duplicate points
+    q, lo, sc = oracle.quantize(xi)
+    for n in sorted({2, max(2, N // 3), max(2, N), N + 5}):
+        say(f"binning small d=1 N={N} n={n}")
+        m_ref, g_ref, _ = oracle.width_search(q, n)
+        cells_ref, H_ref, sb_ref = oracle.histogram(q, m_ref)
+        m, cells, H, sb = bm.bin_coordinates(xi, n)
+        assert m == m_ref
+        assert np.array_equal(cells.cpu().numpy().view(np.uint64), cells_ref)
+        assert np.array_equal(H.cpu().numpy(), H_ref)
+        assert np.array_equal(sb.cpu().numpy(), sb_ref)
+
+
+@pytest.mark.parametrize("N", [5, 4096, 9000, 65536])
+def test_binning_small_2d(bm, N):
+    # 2-D cell keys sorted by the one-workgroup radix sort (64-bit keys)
+    g = np.random.default_rng(2000 + N)
+    xi = g.normal(0, 1, size=(N, 2))
+    if N > 10:
+        xi[: N // 10] = xi[N // 10: 2 * (N // 10)]
+    q, lo, sc = oracle.quantize(xi)
+    for n in sorted({2, max(2, N // 4), N + 1}):
+        say(f"binning small d=2 N={N} n={n}")
+        m_ref, g_ref, _ = oracle.width_search(q, n)
+        cells_ref, H_ref, sb_ref = oracle.histogram(q, m_ref)
+        m, cells, H, sb = bm.bin_coordinates(xi, n)
+        assert m == m_ref
+        assert np.array_equal(cells.cpu().numpy().view(np.uint64), cells_ref)
+        assert np.array_equal(H.cpu().numpy(), H_ref)
+        assert np.array_equal(sb.cpu().numpy(), sb_ref)
+
+
 def test_binning_2d_heavy_tail(bm):
     # The 2-D probes visit the samples sorted by (q_y, q_x), a workgroup per
     # run of 2048: its cells lie in a band of grid rows, marked in LDS when
