@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(kRT)
     const int shift = 8 * p;
     for (int b = 0; b < nb; ++b) h[b][t] = 0u;
     __syncthreads();
+#pragma unroll 8
     for (int64_t i = t; i < N; i += kRT) atomicAdd(&h[i / kTile][digit_of(ks[i], shift)], 1u);
     __syncthreads();
     // first output position of digit t in tile b: the keys of smaller digits,
@@ -172,12 +173,23 @@ __global__ void __launch_bounds__(kRT)
       running[t] = h[b][t];
 #pragma unroll
       for (int w = 0; w < kRT / 64; ++w) cnt[w][t] = 0u;
-      __syncthreads();
+      // the tile's keys (and values) of this thread, loaded together: the
+      // rounds below then wait on no memory
       const int64_t base = (int64_t)b * kTile;
+      K kr[kRounds];
+      uint32_t vr[kRounds];
+#pragma unroll
+      for (int j = 0; j < kRounds; ++j) {
+        const int64_t i = base + (int64_t)j * kRT + t;
+        kr[j] = i < N ? ks[i] : (K)0;
+        if constexpr (VALS) vr[j] = i < N ? vs[i] : 0u;
+      }
+      __syncthreads();
+#pragma unroll
       for (int j = 0; j < kRounds; ++j) {
         const int64_t i = base + (int64_t)j * kRT + t;
         const bool valid = i < N;
-        const K key = valid ? ks[i] : (K)0;
+        const K key = kr[j];
         const unsigned d = digit_of(key, shift);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -192,7 +204,7 @@ __global__ void __launch_bounds__(kRT)
           uint32_t pos = running[d] + rank;
           for (int w = 0; w < wave; ++w) pos += cnt[w][d];
           kd[pos] = key;
-          if constexpr (VALS) vd[pos] = vs[i];
+          if constexpr (VALS) vd[pos] = vr[j];
         }
         __syncthreads();
         uint32_t add = 0u;
@@ -290,28 +302,33 @@ __global__ void __launch_bounds__(kST)
 
 // One workgroup over at most kSmallScan chunks, each scanned as by
 // scan_apply_kernel with the running total of the chunks before it. In place
-// as well: a thread reads its items of a chunk before the chunk's workgroup
-// scan and writes them after it.
+// as well: every item is read before the first one is written.
 template <typename T, bool INCLUSIVE>
 __global__ void __launch_bounds__(kST) scan_small_kernel(const T* in, int64_t n, T* out) {
   __shared__ T sh[kST];
+  // every item of this thread, all chunks, loaded before the first scan
+  T x[kSmallScan][kSItems];
+#pragma unroll
+  for (int c = 0; c < kSmallScan; ++c) {
+    const int64_t base = (int64_t)c * kSChunk + (int64_t)threadIdx.x * kSItems;
+#pragma unroll
+    for (int q = 0; q < kSItems; ++q) x[c][q] = base + q < n ? in[base + q] : (T)0;
+  }
   T carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += kSChunk) {
-    const int64_t base = c0 + (int64_t)threadIdx.x * kSItems;
-    T x[kSItems];
+#pragma unroll
+  for (int c = 0; c < kSmallScan; ++c) {
+    if ((int64_t)c * kSChunk >= n) break;  // uniform
+    const int64_t base = (int64_t)c * kSChunk + (int64_t)threadIdx.x * kSItems;
     T v = 0;
 #pragma unroll
-    for (int q = 0; q < kSItems; ++q) {
-      x[q] = base + q < n ? in[base + q] : (T)0;
-      v += x[q];
-    }
+    for (int q = 0; q < kSItems; ++q) v += x[c][q];
     T tot;
     T run = block_exclusive_scan<T>(v, sh, &tot) + carry;
 #pragma unroll
     for (int q = 0; q < kSItems; ++q) {
-      if (INCLUSIVE) run += x[q];
+      if (INCLUSIVE) run += x[c][q];
       if (base + q < n) out[base + q] = run;
-      if (!INCLUSIVE) run += x[q];
+      if (!INCLUSIVE) run += x[c][q];
     }
     carry += tot;
   }
