@@ -88,10 +88,20 @@ __global__ void __launch_bounds__(kRT)
   __syncthreads();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = (int64_t)blockIdx.x * kTile;
+  // the thread's keys (and values) of the tile, loaded together
+  K kr[kRounds];
+  uint32_t vr[kRounds];
+#pragma unroll
+  for (int j = 0; j < kRounds; ++j) {
+    const int64_t i = base + (int64_t)j * kRT + t;
+    kr[j] = i < N ? src[i] : (K)0;
+    if constexpr (VALS) vr[j] = i < N ? vsrc[i] : 0u;
+  }
+#pragma unroll
   for (int j = 0; j < kRounds; ++j) {
     const int64_t i = base + (int64_t)j * kRT + t;
     const bool valid = i < N;
-    const K key = valid ? src[i] : (K)0;
+    const K key = kr[j];
     const unsigned d = digit_of(key, shift);
     // lanes of this wave holding a valid key with the same digit
     uint64_t peers = __ballot(valid);
@@ -107,7 +117,7 @@ __global__ void __launch_bounds__(kRT)
       uint32_t pos = running[d] + rank;
       for (int w = 0; w < wave; ++w) pos += cnt[w][d];
       dst[pos] = key;
-      if constexpr (VALS) vdst[pos] = vsrc[i];
+      if constexpr (VALS) vdst[pos] = vr[j];
     }
     __syncthreads();
     uint32_t add = 0u;
